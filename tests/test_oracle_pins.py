@@ -1,0 +1,384 @@
+"""Pins of the CPU oracle to facts outside itself (closed forms, brute force, invariants,
+the paper's worked example).  None of these re-types an oracle formula: each checks
+the oracle's output against something the mathematics or the paper fixes."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2009_09767_amd import gen
+from tests import helpers as H
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+METHODS = ["whole", "whole_qr", "merge", "gram"]
+
+
+def run(orc, A, k=None, method="whole", D=None, tol=0.0, **kw):
+    k = A.M if k is None else k
+    D = A.meta.get("D", 1) if D is None else D
+    D = max(1, min(D, A.N))
+    return orc.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=k, tol=tol, method=method, D=D, **kw)
+
+
+# --------------------------------------------------------------------------------------
+# closed forms
+# --------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("D", [1, 3, 8])
+def test_diagonal_closed_form(orc, method, D):
+    """One nonzero per row in distinct columns: sigma = sorted |d|, u_i = e_row (sign +),
+    v_i = sign(d) e_col.  Most blocks hold a single row -> deeply rank-deficient blocks."""
+    rng = np.random.default_rng(5)
+    M, N = 12, 97
+    d = rng.uniform(0.5, 4.0, M) * rng.choice([-1.0, 1.0], M)
+    A = gen.diagonal(d, N, seed=3)
+    r = run(orc, A, method=method, D=D)
+    order = np.argsort(-np.abs(d), kind="stable")
+    np.testing.assert_allclose(r.sigma, np.abs(d)[order], rtol=4e-15, atol=0)
+    assert r.rank == M
+    for i, m in enumerate(order):
+        e = np.zeros(M)
+        e[m] = 1.0
+        np.testing.assert_allclose(r.U[:, i], e, atol=1e-15)
+        ev = np.zeros(N)
+        ev[A.meta["cols"][m]] = np.sign(d[m])
+        np.testing.assert_allclose(r.V[:, i], ev, atol=1e-15)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_diagonal_with_empty_rows_exact_rank(orc, method):
+    """Zero entries of d are structurally empty rows: rank = M - |E| exactly, sigma = 0 exactly,
+    U columns e_row for the empty rows in ascending row order, V columns zero."""
+    d = np.array([0.0, 3.0, 0.0, -1.5, 2.0, 0.0, 0.25, 5.0])
+    A = gen.diagonal(d, 40, seed=9)
+    r = run(orc, A, method=method, D=4)
+    nz = np.flatnonzero(d)
+    empty = np.flatnonzero(d == 0)
+    assert r.rank == nz.size
+    assert np.all(r.sigma[nz.size:] == 0.0)
+    for j, m in enumerate(empty):
+        e = np.zeros(d.size)
+        e[m] = 1.0
+        assert np.array_equal(r.U[:, nz.size + j], e)
+        assert np.all(r.V[:, nz.size + j] == 0.0)
+    np.testing.assert_allclose(r.sigma[:nz.size], np.sort(np.abs(d[nz]))[::-1], rtol=4e-15)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_single_row(orc, method):
+    """M = 1: sigma = ||row||_2, u = [1], v = row / ||row||."""
+    A = gen.random_sparse(1, 300, 0.3, seed=4)
+    r = run(orc, A, k=1, method=method, D=5)
+    row = A.dense()[0]
+    assert r.sigma[0] == pytest.approx(np.sqrt(np.sum(row ** 2)), rel=2e-15)
+    assert r.U[0, 0] == 1.0
+    np.testing.assert_allclose(r.V[:, 0], row / np.linalg.norm(row), atol=1e-15)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_two_rows_closed_form(orc, method):
+    """M = 2: sigma^2 are the roots of the 2x2 Gram's characteristic polynomial,
+    (a+c)/2 +- sqrt(((a-c)/2)^2 + b^2), evaluated here from the dense rows."""
+    A = gen.random_sparse(2, 500, 0.2, seed=12)
+    X = A.dense()
+    a, c, b = X[0] @ X[0], X[1] @ X[1], X[0] @ X[1]
+    mid, rad = 0.5 * (a + c), np.hypot(0.5 * (a - c), b)
+    lam = np.array([mid + rad, (a * c - b * b) / (mid + rad)])  # product form for the small root
+    r = run(orc, A, k=2, method=method, D=7)
+    np.testing.assert_allclose(r.sigma, np.sqrt(lam), rtol=1e-14)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_known_factors(orc, method):
+    """A = U diag(s) V^T with exactly orthonormal V (disjoint supports): sigma = s, u_i = +-U e_i,
+    v_i = +-V e_i.  Two zero entries of s give an exact rank deficiency that is not structural."""
+    s = np.array([9.0, 7.5, 6.0, 4.0, 3.0, 2.0, 1.0, 0.5, 0.0, 0.0])
+    A, U, s_true, V = gen.known_factors(s, 600, seed=21)
+    r = run(orc, A, method=method, D=6)
+    assert r.rank == 8
+    np.testing.assert_allclose(r.sigma[:8], s[:8], rtol=1e-13)
+    assert np.all(r.sigma[8:] == 0.0)
+    assert np.max(H.sin_angles(r.U[:, :8], U[:, :8])) < 1e-13
+    assert np.max(H.sin_angles(r.V[:, :8], V[:, :8])) < 1e-13
+    assert np.all(r.V[:, 8:] == 0.0)
+
+
+# --------------------------------------------------------------------------------------
+# brute force against an independent dense SVD (LAPACK through numpy; test-only)
+# --------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("method", METHODS)
+def test_brute_force_tiny(orc, seed, method):
+    rng = np.random.default_rng(100 + seed)
+    M = int(rng.integers(2, 17))
+    N = int(rng.integers(M, 257))
+    A = gen.random_sparse(M, N, float(rng.uniform(0.05, 0.5)), seed=200 + seed)
+    X = A.dense()
+    s_ref = np.linalg.svd(X, compute_uv=False)
+    r = run(orc, A, method=method, D=int(rng.integers(1, 9)))
+    rk = r.rank
+    np.testing.assert_allclose(r.sigma[:rk], s_ref[:rk], rtol=1e-12)
+    Ur, _, Vt = np.linalg.svd(X)
+    gaps = H.relgaps(s_ref, rk)
+    sin_u = H.sin_angles(r.U[:, :rk], Ur[:, :rk])
+    assert np.all(sin_u <= np.minimum(1.0, 1e-12 / gaps) + 1e-14)
+
+
+# --------------------------------------------------------------------------------------
+# the paper's merge identity (Sec. III, Eq. 2-3): any D, any block rank
+# --------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("D", [1, 2, 3, 8, 64, 128])
+def test_merge_equals_whole(orc, D):
+    A = gen.cfg1()
+    whole = run(orc, A, method="whole_qr", tol=1e-12)
+    merged = run(orc, A, method="merge", D=D, tol=1e-12)
+    assert merged.rank == whole.rank == A.M
+    assert H.rel_sigma_err(merged.sigma, whole.sigma, whole.rank) < 1e-12
+    scaled, _ = H.vector_errors(merged.U, whole.U, whole.sigma, whole.rank)
+    assert scaled < 1e-12
+
+
+def test_merge_rank_deficient_blocks(orc):
+    """Blocks narrower than the number of rows (rank < M in every block) still merge exactly."""
+    A = gen.random_sparse(40, 400, 0.1, seed=77)
+    whole = run(orc, A, method="whole")
+    merged = run(orc, A, method="merge", D=20)  # 20 columns per block < 40 rows
+    assert merged.rank == whole.rank
+    assert H.rel_sigma_err(merged.sigma, whole.sigma, whole.rank) < 1e-12
+
+
+# --------------------------------------------------------------------------------------
+# invariants
+# --------------------------------------------------------------------------------------
+
+def test_invariants_full_spectrum(orc):
+    A = gen.cfg1()
+    r = run(orc, A, method="whole", tol=1e-12)
+    X = A.dense()
+    fro2 = float(np.sum(X * X))
+    assert abs(np.sum(r.sigma ** 2) - fro2) <= 1e-12 * fro2
+    resid = np.linalg.norm(X - (r.U * r.sigma) @ r.V.T) / np.sqrt(fro2)
+    assert resid <= 1e-10
+    assert np.linalg.norm(r.U.T @ r.U - np.eye(A.M)) <= 1e-10
+    Vr = r.V[:, : r.rank]
+    assert np.linalg.norm(Vr.T @ Vr - np.eye(r.rank)) <= 1e-10
+    assert H.canonical_sign_ok(r.U)
+
+
+def test_eckart_young_topk(orc):
+    A = gen.cfg2_small()
+    k = 24
+    r = run(orc, A, k=k, method="whole_qr")
+    X = A.dense()
+    approx = (r.U * r.sigma) @ r.V.T
+    lhs = np.sum((X - approx) ** 2)
+    rhs = np.sum(X * X) - np.sum(r.sigma ** 2)
+    assert abs(lhs - rhs) <= 1e-10 * np.sum(X * X)
+
+
+def test_scaling_and_permutations(orc):
+    A = gen.random_sparse(10, 120, 0.15, seed=31)
+    X = A.dense()
+    r = run(orc, A, method="whole")
+    c = -2.5
+    rs = run(orc, gen.from_dense(c * X), method="whole")
+    np.testing.assert_allclose(rs.sigma, abs(c) * r.sigma, rtol=1e-13)
+    pr = np.random.default_rng(1).permutation(10)
+    pc = np.random.default_rng(2).permutation(120)
+    rp = run(orc, gen.from_dense(X[pr][:, pc]), method="whole")
+    np.testing.assert_allclose(rp.sigma, r.sigma, rtol=1e-13)
+    assert np.max(H.sin_angles(rp.U, r.U[pr])) < 1e-12
+    assert np.max(H.sin_angles(rp.V[:, : r.rank], r.V[pc][:, : r.rank])) < 1e-12
+
+
+def test_block_local_zeros_keep_rank(orc):
+    """cfg1: rows 24..63 are empty inside block 3 only; the rank stays M."""
+    A = gen.cfg1()
+    occ = orc.occupancy(A.M, A.N, A.colptr, A.rowidx, 8)
+    assert np.all(occ.cnt[3, 24:] == 0)
+    assert np.all(occ.rownnz > 0)
+    r = run(orc, A, method="merge", D=8, tol=1e-12)
+    assert r.rank == A.M
+
+
+def test_global_zero_rows_exact_rank(orc):
+    """Zeroed rows (the cfg3 recipe): rank = M - |E| exactly, e_row columns, sigma = 0."""
+    rng = np.random.default_rng(3)
+    A = gen.cfg3_matrix(rng, 48, 3000, density=0.02, zero_half=True)
+    E = A.meta["zeroed_rows"]
+    for method in METHODS:
+        r = run(orc, A, method=method, D=4)
+        assert r.rank == A.M - E.size
+        for j, m in enumerate(E):
+            col = r.U[:, A.M - E.size + j]
+            assert col[m] == 1.0 and np.count_nonzero(col) == 1
+        assert np.all(r.sigma[A.M - E.size:] == 0.0)
+
+
+# --------------------------------------------------------------------------------------
+# Alg. 1 scan and Eq. 4-5
+# --------------------------------------------------------------------------------------
+
+def test_occupancy_brute_force(orc):
+    A = gen.cfg1()
+    X = A.dense() != 0
+    D = 8
+    occ = orc.occupancy(A.M, A.N, A.colptr, A.rowidx, D)
+    bs = gen.block_starts(A.N, D)
+    for b in range(D):
+        cnt = X[:, bs[b]:bs[b + 1]].sum(axis=1)
+        assert np.array_equal(occ.cnt[b], cnt)
+        assert occ.lonely[b] == int(np.sum(cnt == 0))
+        assert occ.single[b] == int(np.sum(cnt == 1))
+    assert np.array_equal(occ.rownnz, X.sum(axis=1))
+    assert occ.lonely[3] >= 40
+
+
+def test_block_bounds_cover_all_columns(orc):
+    for N, D in [(170897, 2), (170897, 3), (170897, 128), (10, 10), (4096, 8)]:
+        bs = orc.block_bounds(N, D)
+        assert bs[0] == 0 and bs[-1] == N
+        w = np.diff(bs)
+        assert w.min() >= N // D and w.max() <= N // D + 1
+
+
+def test_eq5_worked_example(orc):
+    """Sec. III, Eq. 5: the printed 5 x 500 block has NO = 3 and Pr = 0.994."""
+    fx = {}
+    entries = []
+    for line in open(os.path.join(GOLDEN, "eq5_rank_prob.txt")):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        key, *vals = line.split()
+        if key == "entry":
+            entries.append((int(vals[0]) - 1, int(vals[1]) - 1))
+        else:
+            fx[key] = float(vals[0])
+    M, N = int(fx["rows"]), int(fx["cols"])
+    rows = [e[0] for e in entries]
+    cols = [e[1] for e in entries]
+    A = gen.from_coo(M, N, rows, cols, np.ones(len(rows)))
+    occ = orc.occupancy(M, N, A.colptr, A.rowidx, 1)
+    assert occ.single[0] == int(fx["NO"])
+    assert occ.lonely[0] == 1
+    assert orc.rank_prob(int(fx["NC"]), int(occ.single[0])) == pytest.approx(fx["Pr"], abs=1e-12)
+
+
+# --------------------------------------------------------------------------------------
+# building blocks
+# --------------------------------------------------------------------------------------
+
+def test_gram_matches_dense_and_is_block_additive(orc):
+    A = gen.cfg1()
+    X = A.dense()
+    G = orc.gram(A.M, A.N, A.colptr, A.rowidx, A.values)
+    np.testing.assert_allclose(G, X @ X.T, rtol=1e-13, atol=1e-13)
+    bs = gen.block_starts(A.N, 8)
+    Gsum = np.zeros_like(G)
+    for b in range(8):
+        Xb = X[:, bs[b]:bs[b + 1]]
+        Ab = gen.from_dense(Xb)
+        Gb = orc.gram(A.M, Ab.N, Ab.colptr, Ab.rowidx, Ab.values)
+        assert np.trace(Gb) == pytest.approx(np.sum(Xb * Xb), rel=1e-14)
+        Gsum += Gb
+    np.testing.assert_allclose(Gsum, G, rtol=1e-13, atol=1e-13)
+
+
+def test_eig_jacobi_against_eigh(orc):
+    rng = np.random.default_rng(8)
+    B = rng.standard_normal((30, 80))
+    G = B @ B.T
+    lam, V, _ = orc.eig_jacobi(G)
+    ref = np.linalg.eigvalsh(G)
+    np.testing.assert_allclose(np.sort(lam), ref, rtol=1e-13)
+    assert np.linalg.norm(V @ np.diag(lam) @ V.T - G) <= 1e-13 * np.linalg.norm(G)
+    assert np.linalg.norm(V.T @ V - np.eye(30)) <= 1e-13
+
+
+def test_eig_jacobi_graded_relative_accuracy(orc):
+    """A graded diagonally dominant matrix: Jacobi keeps relative accuracy in the tiny eigenvalues
+    (they equal the diagonal to first order, a fact independent of any solver)."""
+    d = 10.0 ** -np.arange(0, 12, dtype=np.float64)
+    G = np.diag(d)
+    rng = np.random.default_rng(2)
+    for i in range(11):
+        e = 1e-9 * np.sqrt(d[i] * d[i + 1]) * rng.uniform(-1, 1)
+        G[i, i + 1] = G[i + 1, i] = e
+    lam, _, _ = orc.eig_jacobi(G)
+    np.testing.assert_allclose(np.sort(lam)[::-1], d, rtol=1e-12)
+
+
+def test_hestenes_and_qr(orc):
+    rng = np.random.default_rng(13)
+    B = rng.standard_normal((9, 50))
+    U, s, Bo, _ = orc.hestenes(B)
+    np.testing.assert_allclose(U @ Bo, B, atol=1e-13)
+    Gb = Bo @ Bo.T
+    assert np.max(np.abs(Gb - np.diag(np.diag(Gb)))) < 1e-12
+    np.testing.assert_allclose(np.sort(s)[::-1], np.linalg.svd(B, compute_uv=False), rtol=1e-13)
+    X = rng.standard_normal((70, 12))
+    R = orc.qr_r(X)
+    assert np.allclose(np.tril(R, -1), 0.0)
+    np.testing.assert_allclose(R.T @ R, X.T @ X, rtol=1e-12, atol=1e-12)
+
+
+def test_backproject_never_divides_by_vanishing_sigma(orc):
+    A = gen.random_sparse(6, 40, 0.3, seed=44)
+    U = np.linalg.qr(np.random.default_rng(1).standard_normal((6, 6)))[0]
+    sigma = np.array([3.0, 2.0, 1.0, 1e-300, 0.0, 0.0])
+    V = orc.backproject(A.M, A.N, A.colptr, A.rowidx, A.values, U, sigma, 3)
+    X = A.dense()
+    np.testing.assert_allclose(V[:, :3], (X.T @ U[:, :3]) / sigma[:3], rtol=1e-13, atol=1e-15)
+    assert np.all(V[:, 3:] == 0.0) and np.all(np.isfinite(V))
+
+
+def test_check_csc_error_codes(orc):
+    A = gen.random_sparse(5, 8, 0.5, seed=1)
+    cp, ri, v = A.colptr.copy(), A.rowidx.copy(), A.values.copy()
+    assert orc.check_csc(5, 8, cp, ri, v) == orc.OK
+    bad = ri.copy()
+    bad[0] = 5
+    assert orc.check_csc(5, 8, cp, bad, v) == orc.E_CSC
+    bad = ri.copy()
+    bad[0] = -1
+    assert orc.check_csc(5, 8, cp, bad, v) == orc.E_CSC
+    j = int(np.argmax(np.diff(cp) >= 2))
+    bad = ri.copy()
+    bad[cp[j] + 1] = bad[cp[j]]
+    assert orc.check_csc(5, 8, cp, bad, v) == orc.E_CSC           # duplicate
+    bad = ri.copy()
+    bad[cp[j]], bad[cp[j] + 1] = bad[cp[j] + 1], bad[cp[j]]
+    assert orc.check_csc(5, 8, cp, bad, v) == orc.E_CSC           # unsorted
+    bcp = cp.copy()
+    bcp[3], bcp[4] = bcp[4], bcp[3]
+    if bcp[3] != bcp[4]:
+        assert orc.check_csc(5, 8, bcp, ri, v) == orc.E_CSC       # non-monotone colptr
+    for x in (np.nan, np.inf, -np.inf):
+        bv = v.copy()
+        bv[2] = x
+        assert orc.check_csc(5, 8, cp, ri, bv) == orc.E_NONFINITE
+    bv = v.copy()
+    bv[2] = np.nan
+    bad = ri.copy()
+    bad[0] = 9
+    assert orc.check_csc(5, 8, cp, bad, bv) == orc.E_CSC           # structure wins
+
+
+def test_fp32_values_promote_exactly(orc):
+    A = gen.cfg2_small(dtype=np.float32)
+    r32 = run(orc, A, k=16, method="gram")
+    r64 = run(orc, A.astype(np.float64), k=16, method="gram")
+    assert np.array_equal(r32.sigma, r64.sigma)
+
+
+def test_paper_metrics_reading():
+    """e_sigma and e_u as read from Sec. IV: zero for identical results, sign-free for vectors."""
+    U = np.linalg.qr(np.random.default_rng(0).standard_normal((7, 7)))[0]
+    s = np.arange(7, 0, -1.0)
+    assert H.paper_e_sigma(s, s, 7) == 0.0
+    assert H.paper_e_u(-U, U, 7) == 0.0
+    assert H.paper_e_u(U + 1e-3, U, 7) > 0.0
