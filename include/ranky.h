@@ -1,0 +1,218 @@
+/*
+ * ranky.h -- C-ABI of the MI355X-native rank-safe column-block SVD of a
+ * short-and-fat sparse matrix (Tugay & Gunduz Oguducu, "Ranky: An Approach to
+ * Solve Distributed SVD on Large Sparse Matrices", arXiv 2009.09767).
+ *
+ * The method (Sec. III): split A (M x N, N >> M) column-wise into D blocks
+ * A = [A^1 | ... | A^D]; each block has a reduced SVD A^i = U^i S^i V^i^T (Eq. 1);
+ * the proxy matrix P = [U^1 S^1 | ... | U^D S^D] has the same singular values and
+ * left singular vectors as A because A A^T = sum_i U^i S^i S^i^T U^i^T = P P^T
+ * (Eq. 2, Eq. 3).  This library evaluates that merge in Gram form:
+ * G = sum_i A^i A^i^T (which is P P^T), an FP64 eigensolve of G gives Sigma^2 and U,
+ * and the right vectors come from the back-projection V = A^T U Sigma^{-1}, which
+ * the paper leaves as future work (Sec. V).  Blocks whose rank falls below M need
+ * no repair: an empty row inside a block only drops a zero singular value from
+ * that block's factor, which adds nothing to P P^T.  No entry of A is altered and
+ * no vanishing sigma is ever divided by (see the rank rule under ranky_svd).
+ *
+ * Conventions for every entry point:
+ *   - Pointers are DEVICE pointers unless the comment says "host".
+ *   - Matrices are dense row-major unless stated; "M x k row-major" means element
+ *     (m, i) at index m * k + i.
+ *   - The caller owns every buffer (inputs, outputs, workspace); the library never
+ *     frees caller memory and never allocates device memory inside these calls.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the legacy default
+ *     stream).  Calls documented as "blocking" synchronise that stream before
+ *     returning; the others are stream-ordered and return after enqueueing.
+ *   - Errors are status codes; nothing throws across the ABI.  On an error the
+ *     outputs are undefined.  ranky_last_error() returns a thread-local message.
+ *   - Results are bitwise deterministic: every floating-point reduction runs in
+ *     a fixed order, so the same inputs give the same bits on every run.
+ */
+#ifndef RANKY_H
+#define RANKY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Same type as hipStream_t (declared here so that callers need no HIP header). */
+typedef struct ihipStream_t *ranky_stream_t;
+
+typedef enum {
+    RANKY_OK = 0,
+    RANKY_E_INVALID = 1,       /* a size, pointer or option is out of range (host-checked) */
+    RANKY_E_CSC = 2,           /* colptr not monotone / not spanning [0, nnz], row index out of
+                                  range, or rows not strictly increasing inside a column (device-checked) */
+    RANKY_E_NONFINITE = 3,     /* a value is NaN or +-Inf (device-checked; E_CSC takes precedence) */
+    RANKY_E_NOMEM = 4,         /* the workspace is smaller than ranky_workspace_bytes() */
+    RANKY_E_DEVICE = 5,        /* a HIP runtime call failed */
+    RANKY_E_BUSY = 6,          /* serving: no slot or memory free (back-pressure) */
+    RANKY_E_CANCELLED = 7,     /* serving: the request was cancelled */
+    RANKY_E_NOT_CONVERGED = 8, /* the Jacobi eigensolver hit max_sweeps */
+    RANKY_PENDING = 9          /* serving: the request has not finished */
+} ranky_status;
+
+typedef enum { RANKY_F32 = 0, RANKY_F64 = 1 } ranky_dtype;
+
+/* Precision of the Gram accumulation (step 2 of the path).  The eigensolve, the
+ * rank decision and the Rayleigh-Ritz refinement are FP64 in every mode. */
+typedef enum {
+    RANKY_PREC_FP64 = 0, /* products and sums in FP64 (FP32 inputs are promoted exactly) */
+    RANKY_PREC_FP32 = 1  /* products and sums in FP32, merged into the FP64 Gram per row */
+} ranky_prec;
+
+/* Compressed sparse columns.  colptr[0] = 0, colptr non-decreasing,
+ * colptr[N] = nnz; rowidx strictly increasing inside a column, in [0, M);
+ * values finite.  int32 indices (nnz <= 2^31 - 1). */
+typedef struct {
+    int64_t nnz;
+    const int32_t *colptr; /* device, N + 1 */
+    const int32_t *rowidx; /* device, nnz */
+    const void *values;    /* device, nnz elements of `dtype` */
+    int32_t dtype;         /* ranky_dtype */
+} ranky_csc;
+
+typedef struct {
+    int32_t n_blocks;   /* D; block b = columns [floor(b N / D), floor((b+1) N / D)).
+                           0 selects ceil(N / 16384).  1 <= D <= N. */
+    int32_t gram_prec;  /* ranky_prec (default FP64) */
+    int32_t refine;     /* Rayleigh-Ritz steps after the eigensolve (0 or 1); default 1 when
+                           gram_prec != FP64, else 0 */
+    int32_t max_sweeps; /* Jacobi sweep cap (0 = 40) */
+    int32_t validate;   /* 1 = check the CSC contract and finiteness on the device (default 1) */
+    int32_t v_dtype;    /* ranky_dtype of the output V (default F64) */
+    int32_t timing;     /* 1 = fill ranky_info.ms with per-phase times (adds event records) */
+    int32_t reserved;
+} ranky_opts;
+
+typedef struct {
+    int32_t status;        /* ranky_status of the call */
+    int32_t rank;          /* r = #{sigma_i > tau}, at most k */
+    int32_t n_nonempty;    /* M' = rows with at least one nonzero */
+    int32_t empty_rows;    /* |E| = M - M' */
+    int32_t sweeps;        /* Jacobi sweeps used */
+    int32_t n_blocks;      /* D actually used */
+    int32_t lonely_max;    /* largest number of rows empty inside one block (Alg. 1 scan) */
+    int32_t lonely_blocks; /* number of blocks with at least one empty row */
+    double tau;            /* effective threshold tau */
+    double sigma_max;      /* sigma_1 */
+    float ms[8];           /* with opts.timing: [0] occupancy+plan, [1] transpose, [2] Gram,
+                              [3] eigensolve, [4] select, [5] refine, [6] back-projection, [7] total */
+} ranky_info;
+
+typedef struct ranky_ctx ranky_ctx;
+
+/* ------------------------------------------------------------------------- */
+/* Context                                                                    */
+/* ------------------------------------------------------------------------- */
+
+/* Binds the calling thread's work to `device` and caches its properties.
+ * *out receives a handle owned by the caller (ranky_ctx_destroy).  Returns
+ * E_INVALID for a bad device, E_DEVICE if HIP fails. */
+ranky_status ranky_ctx_create(int device, ranky_ctx **out);
+ranky_status ranky_ctx_destroy(ranky_ctx *ctx);
+
+/* Fills *opts (host) with the defaults listed in ranky_opts. */
+ranky_status ranky_default_opts(ranky_opts *opts);
+
+/* Thread-local text of the last error (never NULL). */
+const char *ranky_last_error(void);
+const char *ranky_version(void);
+
+/* ------------------------------------------------------------------------- */
+/* The whole path                                                             */
+/* ------------------------------------------------------------------------- */
+
+/* Bytes of device workspace ranky_svd needs for these sizes and options
+ * (0 if they are invalid).  Depends on M, N, nnz, k and opts only. */
+size_t ranky_workspace_bytes(int32_t M, int64_t N, int64_t nnz, int32_t k, const ranky_opts *opts);
+
+/* Top-k singular triplets of A (M x N) by the block merge of Sec. III in Gram
+ * form (Eq. 2-3), with the right vectors back-projected.  Blocking.
+ *
+ * Steps (all on the device): the Alg. 1 scan of every block (per-block row
+ * occupancy: lonely rows are counted, not repaired); the block Grams
+ * A^i A^i^T reduced in block order into G restricted to the M' non-empty rows;
+ * a two-sided Jacobi FP64 eigensolve of G (the SVD of the proxy P, Sec. III);
+ * the rank-safe threshold; with gram_prec != FP64 and refine = 1 one FP64
+ * Rayleigh-Ritz step with the exact operator; V = A^T U Sigma^{-1}.
+ *
+ * Rank rule: sigma_i = sqrt(max(lambda_i, 0)); sigma_i counts as zero iff
+ * sigma_i <= tau = max(tol, sqrt(M' u_G)) sigma_1, u_G = 2^-53 for the FP64 Gram
+ * (2^-24 for the FP32 Gram without refinement).  rank = #{sigma_i > tau}.
+ *
+ * Outputs (device, caller-allocated):
+ *   sigma [k]            descending; sigma_i = 0 exactly for i >= rank
+ *   U     [M x k]        row-major; column i < min(k, M') is the eigenvector of
+ *                        G scattered to the non-empty rows (zero on empty rows),
+ *                        sign fixed so its entry of largest magnitude is positive
+ *                        (lowest row on an exact tie); columns i >= M' are e_row for
+ *                        the empty rows in ascending row order
+ *   V     [N x k]        row-major, v_dtype; V[:, i] = A^T u_i / sigma_i for i < rank,
+ *                        exactly 0 for i >= rank (no division by a vanishing sigma)
+ *   info  (host, may be NULL)
+ * Errors: E_INVALID (M < 1, N < 1, k < 1 or k > M, tol < 0 or NaN, nnz outside
+ * [0, 2^31), D outside [1, N], M > 8192, a NULL pointer), E_NOMEM (ws_bytes too
+ * small), E_CSC / E_NONFINITE (device validation), E_NOT_CONVERGED, E_DEVICE. */
+ranky_status ranky_svd(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N, int32_t k, double tol,
+                       const ranky_opts *opts, void *workspace, size_t ws_bytes, double *sigma, double *U,
+                       void *V, ranky_info *info, ranky_stream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* Individual steps (the same kernels ranky_svd runs), for composition and    */
+/* per-step checking.  Stream-ordered unless marked blocking.                 */
+/* ------------------------------------------------------------------------- */
+
+/* Bytes of workspace the step calls below need for these sizes. */
+size_t ranky_step_workspace_bytes(int32_t M, int64_t N, int64_t nnz, int32_t D);
+
+/* Alg. 1 scan (the lonely-node test of every block and row) plus the CSC
+ * contract check.  Blocking.
+ *   cnt    [D x M] int32   nonzeros of row m inside block b (row-major by block)
+ *   rownnz [M]     int32   nonzeros of row m
+ *   lonely [D]     int32   rows with no entry inside block b
+ *   single [D]     int32   rows with exactly one entry inside block b (NO of Eq. 4)
+ * Returns E_CSC / E_NONFINITE for an input that breaks the contract. */
+ranky_status ranky_occupancy(const ranky_csc *A, int32_t M, int64_t N, int32_t D, int32_t *cnt, int32_t *rownnz,
+                             int32_t *lonely, int32_t *single, void *workspace, size_t ws_bytes,
+                             ranky_stream_t stream);
+
+/* The Gram matrix G = sum_i A^i A^i^T (Eq. 2), full M x M row-major FP64 in the
+ * original row order (rows and columns of empty rows are zero), accumulated
+ * in `prec`.  Blocking (it reads back the validation status). */
+ranky_status ranky_gram(const ranky_csc *A, int32_t M, int64_t N, int32_t prec, double *G, void *workspace,
+                        size_t ws_bytes, ranky_stream_t stream);
+
+/* Bytes of workspace ranky_eigh needs for an n x n problem. */
+size_t ranky_eigh_workspace_bytes(int32_t n);
+
+/* Two-sided blocked Jacobi eigensolve of a dense symmetric n x n FP64 matrix
+ * (the proxy SVD of Sec. III / Alg. 1 in Gram form).  Blocking.
+ *   G      [n x n]  input, row-major; read only (copied into the workspace)
+ *   lambda [n]      eigenvalues, unsorted (pairing with the columns of Q)
+ *   Q      [n x n]  row-major, column j is the unit eigenvector of lambda[j]
+ *   sweeps (host, may be NULL) receives the number of sweeps.
+ * Convergence: every |g_pq| <= max(1e-15, sqrt(n) eps) sqrt(|g_pp g_qq|) or below
+ * (n eps)^2 max|g_ii|.  Returns E_NOT_CONVERGED after max_sweeps (0 = 40). */
+ranky_status ranky_eigh(int32_t n, const double *G, double *lambda, double *Q, int32_t max_sweeps, int32_t *sweeps,
+                        void *workspace, size_t ws_bytes, ranky_stream_t stream);
+
+/* Back-projection V = A^T U Sigma^{-1} on the retained triplets (Sec. V asks for
+ * V; the rank rule forbids dividing by a vanishing sigma):
+ *   V[j][i] = (sum_m a_mj U[m][i]) / sigma[i]   for i < *rank
+ *   V[j][i] = 0                                 for i >= *rank
+ *   U [M x k] FP64 row-major, sigma [k] FP64, rank: device int32 scalar,
+ *   V [N x k] row-major of v_dtype.  Stream-ordered; no workspace. */
+ranky_status ranky_backproject(const ranky_csc *A, int32_t M, int64_t N, int32_t k, const double *U,
+                               const double *sigma, const int32_t *rank, void *V, int32_t v_dtype,
+                               ranky_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RANKY_H */

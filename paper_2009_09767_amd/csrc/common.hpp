@@ -1,0 +1,49 @@
+// common.hpp -- shared constants and small device helpers of the HIP path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ranky {
+
+// Columns handled by one workgroup of the occupancy and transpose passes.
+constexpr int kChunkCols = 4096;
+// Blocked Jacobi: the matrix is cut into blocks of kJB indices; a round pairs two
+// blocks, so every subproblem is kJP = 2 kJB wide.  kJS pads LDS rows.
+constexpr int kJB = 32;
+constexpr int kJP = 64;
+constexpr int kJS = 65;
+
+// Bits of the device status word.
+enum : int32_t { kStCsc = 1, kStNonfinite = 2 };
+
+// Integer slots and double slots of the device scalar block (in the workspace).
+enum : int32_t {
+    kScStatus = 0,     // status bits
+    kScNonempty = 1,   // M' (rows with a nonzero)
+    kScRank = 2,       // rank after the threshold
+    kScNotConv = 3,    // 1 if some off-diagonal entry still fails the Jacobi test
+    kScCount = 16
+};
+enum : int32_t { kSdTau = 0, kSdSigmaMax = 1, kSdFloor = 2, kSdCount = 8 };
+
+// Column range of chunk c: block b = c / cpb owns columns [floor(bN/D), floor((b+1)N/D)),
+// and its t-th chunk (t = c % cpb) is the t-th run of kChunkCols columns of it.
+__device__ __forceinline__ void chunk_columns(int64_t c, int32_t cpb, int64_t N, int32_t D, int64_t &c0,
+                                              int64_t &c1) {
+    const int64_t b = c / cpb, t = c % cpb;
+    const int64_t bs = (b * N) / D, be = ((b + 1) * N) / D;
+    c0 = bs + t * kChunkCols;
+    c1 = c0 + kChunkCols < be ? c0 + kChunkCols : be;
+    if (c0 > c1) c0 = c1;
+}
+
+template <typename T>
+__device__ __forceinline__ double as_double(T v) {
+    return static_cast<double>(v);
+}
+
+__device__ __forceinline__ bool finite_value(double v) { return __builtin_isfinite(v); }
+__device__ __forceinline__ bool finite_value(float v) { return __builtin_isfinite(v); }
+
+}  // namespace ranky

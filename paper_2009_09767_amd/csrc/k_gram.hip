@@ -1,0 +1,172 @@
+// k_gram.hip -- the block Grams A^i A^i^T reduced into G (Eq. 2-3).
+//
+// G = sum_i A^i A^i^T = sum_j a_j a_j^T over all columns j.  Owner computes: the
+// workgroup of compacted row i (original row p) produces row i of G, entries
+// G[p][q] for q > p, by walking row p's nonzeros (j, a_pj) in column order (hence
+// block by block) and, for each, the later entries (q, a_qj) of column j.  Its waves
+// split row p's nonzeros into contiguous runs (so runs of blocks), each wave summing
+// into a private LDS row; the runs are then added in wave order: a fixed-order
+// segmented reduction over the blocks, with no floating-point atomics.
+//
+// Inside a wave the 64 lanes hold 64 different columns, and two of them may reach
+// the same q at the same step.  Each such collision is resolved by electing the
+// lowest lane through an integer min in LDS; the winner adds its product, the others
+// retry, so the sum per address runs in lane order.  Integer min commutes, so the
+// election -- and therefore every floating-point result -- is independent of timing.
+//
+// The diagonal a_pj^2 terms are summed per lane and reduced by a fixed shuffle tree.
+// G is written in compacted coordinates (empty rows removed), symmetric, padded
+// with zeros up to npad; every entry is written exactly once.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace ranky {
+
+template <typename Acc>
+__device__ __forceinline__ Acc wave_sum(Acc v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename TV, typename Acc>
+__global__ __launch_bounds__(512) void k_gram_rows(const int32_t *__restrict__ rowidx, const TV *__restrict__ vals,
+                                                   int32_t M, int32_t n, int32_t npad, int64_t ld,
+                                                   const int32_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ r2m,
+                                                   const int32_t *__restrict__ csr_k,
+                                                   const int32_t *__restrict__ csr_end, double *__restrict__ G) {
+    extern __shared__ double lds_raw[];
+    const int32_t i = blockIdx.x;
+    const int nw = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    if (i >= n) {  // padding row and column of the Jacobi layout
+        for (int32_t j = i + threadIdx.x; j < npad; j += blockDim.x) {
+            G[(int64_t)i * ld + j] = 0.0;
+            G[(int64_t)j * ld + i] = 0.0;
+        }
+        return;
+    }
+    Acc *acc = reinterpret_cast<Acc *>(lds_raw);                  // nw x M
+    int32_t *tag = reinterpret_cast<int32_t *>(acc + (size_t)nw * M);  // nw x M
+    __shared__ Acc dsum[16];
+    for (int32_t t = threadIdx.x; t < nw * M; t += blockDim.x) {
+        acc[t] = Acc(0);
+        tag[t] = 64;
+    }
+    __syncthreads();
+
+    const int32_t p = r2m[i];
+    const int32_t e_begin = rowptr[p], e_end = rowptr[p + 1];
+    const int32_t deg = e_end - e_begin;
+    const int32_t seg = (deg + nw - 1) / nw;
+    const int32_t wb = e_begin + wave * seg;
+    const int32_t we = (wb + seg < e_end) ? wb + seg : e_end;
+    Acc *my = acc + (size_t)wave * M;
+    int32_t *mytag = tag + (size_t)wave * M;
+    Acc dg = Acc(0);
+
+    for (int32_t base = wb; base < we; base += 64) {
+        const int32_t e = base + lane;
+        const bool has = e < we;
+        int32_t kk = 0, kend = 0;
+        Acc a = Acc(0);
+        if (has) {
+            kk = csr_k[e];
+            kend = csr_end[e];
+            a = static_cast<Acc>(vals[kk]);
+            dg += a * a;
+        }
+        for (int32_t s = 1;; ++s) {
+            const bool act = has && (kk + s < kend);
+            if (__ballot(act) == 0) break;
+            int32_t q = 0;
+            Acc v = Acc(0);
+            if (act) {
+                q = rowidx[kk + s];
+                v = a * static_cast<Acc>(vals[kk + s]);
+            }
+            bool pend = act;
+            while (__ballot(pend) != 0) {
+                if (pend) atomicMin(&mytag[q], lane);
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                const bool win = pend && (__hip_atomic_load(&mytag[q], __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_WAVEFRONT) == lane);
+                if (win) {
+                    my[q] += v;
+                    mytag[q] = 64;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                pend = pend && !win;
+            }
+        }
+    }
+    dg = wave_sum(dg);
+    if (lane == 0) dsum[wave] = dg;
+    __syncthreads();
+
+    // row part G[i][j] and column part G[j][i] for j > i, summing the waves in order
+    for (int32_t j = i + 1 + threadIdx.x; j < npad; j += blockDim.x) {
+        double v = 0.0;
+        if (j < n) {
+            const int32_t q = r2m[j];
+            for (int w = 0; w < nw; ++w) v += static_cast<double>(acc[(size_t)w * M + q]);
+        }
+        G[(int64_t)i * ld + j] = v;
+        G[(int64_t)j * ld + i] = v;
+    }
+    if (threadIdx.x == 0) {
+        double d = 0.0;
+        for (int w = 0; w < nw; ++w) d += static_cast<double>(dsum[w]);
+        G[(int64_t)i * ld + i] = d;
+    }
+}
+
+int gram_waves(int32_t M, int32_t acc_bytes, size_t lds_limit) {
+    // LDS per wave: one accumulator row and one tag row.
+    const size_t per_wave = (size_t)M * (acc_bytes + sizeof(int32_t));
+    int w = (int)(lds_limit / per_wave);
+    if (w > 8) w = 8;
+    if (w < 1) w = 1;
+    return w;
+}
+
+void launch_gram(const CscView &A, int32_t M, int32_t n, int32_t npad, int64_t ld, const int32_t *rowptr,
+                 const int32_t *r2m, const int32_t *csr_k, const int32_t *csr_end, double *G, int32_t prec,
+                 size_t lds_limit, hipStream_t s) {
+    const int acc_bytes = prec == 0 ? 8 : 4;
+    const int nw = gram_waves(M, acc_bytes, lds_limit);
+    const size_t lds = (size_t)nw * M * (acc_bytes + sizeof(int32_t));
+    const dim3 grid((unsigned)npad), block((unsigned)(64 * nw));
+    if (A.dtype == 1) {
+        const double *v = static_cast<const double *>(A.values);
+        if (prec == 0)
+            hipLaunchKernelGGL((k_gram_rows<double, double>), grid, block, lds, s, A.rowidx, v, M, n, npad, ld, rowptr,
+                               r2m, csr_k, csr_end, G);
+        else
+            hipLaunchKernelGGL((k_gram_rows<double, float>), grid, block, lds, s, A.rowidx, v, M, n, npad, ld, rowptr,
+                               r2m, csr_k, csr_end, G);
+    } else {
+        const float *v = static_cast<const float *>(A.values);
+        if (prec == 0)
+            hipLaunchKernelGGL((k_gram_rows<float, double>), grid, block, lds, s, A.rowidx, v, M, n, npad, ld, rowptr,
+                               r2m, csr_k, csr_end, G);
+        else
+            hipLaunchKernelGGL((k_gram_rows<float, float>), grid, block, lds, s, A.rowidx, v, M, n, npad, ld, rowptr,
+                               r2m, csr_k, csr_end, G);
+    }
+}
+
+hipError_t gram_set_attributes(size_t lds_limit) {
+    const void *fns[] = {reinterpret_cast<const void *>(k_gram_rows<double, double>),
+                         reinterpret_cast<const void *>(k_gram_rows<double, float>),
+                         reinterpret_cast<const void *>(k_gram_rows<float, double>),
+                         reinterpret_cast<const void *>(k_gram_rows<float, float>)};
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace ranky

@@ -1,0 +1,212 @@
+// k_select.hip -- rank-safe threshold, ordering and sign convention of the merged
+// singular triplets, and the back-projection of the right singular vectors.
+//
+// After the eigensolve, lambda_i = G_ii.  sigma_i = sqrt(max(lambda_i, 0)); the rank
+// is r = #{sigma_i > tau}, tau = max(tol, sqrt(M' u_G)) sigma_1 (squaring in the Gram
+// halves the exponent, so below sqrt(M' u_G) sigma_1 a singular value cannot be told
+// from zero).  Returned sigma_i for i >= r are exactly 0, and the back-projection
+// V = A^T U Sigma^{-1} (Sec. V) fills those columns with zeros instead of dividing.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace ranky {
+
+// One workgroup of 1024 threads: bitonic sort of (lambda desc, index asc) over the
+// n eigenvalues, then sigma, tau and the rank.  LDS holds npow2 keys and indices.
+__global__ __launch_bounds__(1024) void k_select_sort(const double *__restrict__ lam, int32_t n, int32_t npow2,
+                                                      int32_t k, double tol, double u_gram,
+                                                      int32_t *__restrict__ perm, double *__restrict__ sigma,
+                                                      int32_t *__restrict__ scal, double *__restrict__ sdbl) {
+    extern __shared__ double lds_key[];
+    int32_t *idx = reinterpret_cast<int32_t *>(lds_key + npow2);
+    for (int32_t i = threadIdx.x; i < npow2; i += blockDim.x) {
+        lds_key[i] = i < n ? lam[i] : -__builtin_inf();
+        idx[i] = i;
+    }
+    __syncthreads();
+    // "a before b" = larger lambda, or equal lambda and smaller index
+    for (int32_t size = 2; size <= npow2; size <<= 1) {
+        for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int32_t i = threadIdx.x; i < npow2; i += blockDim.x) {
+                const int32_t j = i ^ stride;
+                if (j > i) {
+                    const bool up = (i & size) == 0;
+                    const double ki = lds_key[i], kj = lds_key[j];
+                    const int32_t ii = idx[i], ij = idx[j];
+                    const bool j_first = (kj > ki) || (kj == ki && ij < ii);
+                    if (j_first == up) {
+                        lds_key[i] = kj;
+                        lds_key[j] = ki;
+                        idx[i] = ij;
+                        idx[j] = ii;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const double s1 = n > 0 ? sqrt(fmax(lds_key[0], 0.0)) : 0.0;
+    const double tau = fmax(tol, sqrt((double)n * u_gram)) * s1;
+    __shared__ int32_t cnt[1024];
+    int32_t c = 0;
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) c += sqrt(fmax(lds_key[i], 0.0)) > tau;
+    cnt[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) cnt[threadIdx.x] += cnt[threadIdx.x + off];
+        __syncthreads();
+    }
+    int32_t rank = cnt[0];
+    if (rank > k) rank = k;
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) perm[i] = idx[i];
+    for (int32_t i = threadIdx.x; i < k; i += blockDim.x)
+        sigma[i] = (i < rank) ? sqrt(fmax(lds_key[i], 0.0)) : 0.0;
+    if (threadIdx.x == 0) {
+        scal[kScRank] = rank;
+        sdbl[kSdTau] = tau;
+        sdbl[kSdSigmaMax] = s1;
+    }
+}
+
+// One workgroup per output column i: the eigenvector W[:, perm[i]] scattered to the
+// non-empty rows with its largest-magnitude entry made positive (lowest row on a
+// tie); columns i >= M' are e_row of the empty rows in ascending order.
+__global__ __launch_bounds__(256) void k_gather_u(const double *__restrict__ W, int64_t ld, int32_t n, int32_t M,
+                                                  int32_t k, const int32_t *__restrict__ perm,
+                                                  const int32_t *__restrict__ m2r,
+                                                  const int32_t *__restrict__ empty, double *__restrict__ U) {
+    const int32_t i = blockIdx.x;
+    if (i >= n) {
+        const int32_t e = empty[i - n];
+        for (int32_t m = threadIdx.x; m < M; m += blockDim.x) U[(int64_t)m * k + i] = (m == e) ? 1.0 : 0.0;
+        return;
+    }
+    const int32_t col = perm[i];
+    __shared__ double best_abs[256];
+    __shared__ int32_t best_row[256];
+    double ba = -1.0;
+    int32_t br = 0x7fffffff;
+    for (int32_t p = threadIdx.x; p < n; p += blockDim.x) {
+        const double a = fabs(W[(int64_t)p * ld + col]);
+        if (a > ba) {  // rows visited in increasing order per thread: strict > keeps the lowest
+            ba = a;
+            br = p;
+        }
+    }
+    best_abs[threadIdx.x] = ba;
+    best_row[threadIdx.x] = br;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            const double oa = best_abs[threadIdx.x + off];
+            const int32_t orow = best_row[threadIdx.x + off];
+            if (oa > best_abs[threadIdx.x] || (oa == best_abs[threadIdx.x] && orow < best_row[threadIdx.x])) {
+                best_abs[threadIdx.x] = oa;
+                best_row[threadIdx.x] = orow;
+            }
+        }
+        __syncthreads();
+    }
+    const double sgn = W[(int64_t)best_row[0] * ld + col] < 0.0 ? -1.0 : 1.0;
+    for (int32_t m = threadIdx.x; m < M; m += blockDim.x) {
+        const int32_t p = m2r[m];
+        U[(int64_t)m * k + i] = p >= 0 ? sgn * W[(int64_t)p * ld + col] : 0.0;
+    }
+}
+
+// V[j][i] = (sum over the nonzeros a_mj of column j of a_mj U[m][i]) / sigma[i] for
+// i < rank, else 0.  One wave per column (grid-stride); a lane owns two consecutive
+// outputs i, so a wave covers 128 outputs per pass with 16-byte U loads.  The
+// column's nonzeros are read once per pass; U rows come from L2.
+template <typename TV, typename TO>
+__global__ __launch_bounds__(256) void k_backproject(const int32_t *__restrict__ colptr,
+                                                     const int32_t *__restrict__ rowidx,
+                                                     const TV *__restrict__ vals, int64_t N, int32_t k,
+                                                     const double *__restrict__ U, const double *__restrict__ sigma,
+                                                     const int32_t *__restrict__ rank_ptr, TO *__restrict__ V) {
+    const int32_t rank = *rank_ptr;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int32_t i0 = 0; i0 < k; i0 += 128) {
+        const int32_t i = i0 + 2 * lane;
+        const bool ok0 = i < k, ok1 = i + 1 < k;
+        const double s0 = (ok0 && i < rank) ? sigma[i] : 0.0;
+        const double s1 = (ok1 && i + 1 < rank) ? sigma[i + 1] : 0.0;
+        const bool live0 = ok0 && i < rank, live1 = ok1 && i + 1 < rank;
+        for (int64_t j = wave; j < N; j += nwaves) {
+            const int32_t e0 = colptr[j], e1 = colptr[j + 1];
+            double a0 = 0.0, a1 = 0.0;
+            for (int32_t e = e0; e < e1; ++e) {
+                const int32_t m = rowidx[e];
+                const double a = static_cast<double>(vals[e]);
+                const double *Um = U + (int64_t)m * k + i;
+                if (ok1) {
+                    a0 = fma(a, Um[0], a0);
+                    a1 = fma(a, Um[1], a1);
+                } else if (ok0) {
+                    a0 = fma(a, Um[0], a0);
+                }
+            }
+            const double v0 = live0 ? a0 / s0 : 0.0;
+            const double v1 = live1 ? a1 / s1 : 0.0;
+            TO *out = V + j * (int64_t)k + i;
+            if (ok1) {
+                __builtin_nontemporal_store(static_cast<TO>(v0), out);
+                __builtin_nontemporal_store(static_cast<TO>(v1), out + 1);
+            } else if (ok0) {
+                __builtin_nontemporal_store(static_cast<TO>(v0), out);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+
+void launch_select(const double *lam, int32_t n, int32_t k, double tol, double u_gram, int32_t *perm, double *sigma,
+                   int32_t *scal, double *sdbl, hipStream_t s) {
+    int32_t npow2 = 1;
+    while (npow2 < n) npow2 <<= 1;
+    const size_t lds = (sizeof(double) + sizeof(int32_t)) * (size_t)npow2;
+    hipLaunchKernelGGL(k_select_sort, dim3(1), dim3(1024), lds, s, lam, n, npow2, k, tol, u_gram, perm, sigma, scal,
+                       sdbl);
+}
+
+void launch_gather_u(const double *W, int64_t ld, int32_t n, int32_t M, int32_t k, const int32_t *perm,
+                     const int32_t *m2r, const int32_t *empty, double *U, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_u, dim3((unsigned)k), dim3(256), 0, s, W, ld, n, M, k, perm, m2r, empty, U);
+}
+
+void launch_backproject(const CscView &A, int64_t N, int32_t k, const double *U, const double *sigma,
+                        const int32_t *rank, void *V, int32_t v_dtype, int32_t cu_count, hipStream_t s) {
+    int64_t blocks = (N + 3) / 4;
+    const int64_t cap = (int64_t)cu_count * 32;
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    const dim3 grid((unsigned)blocks), block(256);
+    if (A.dtype == 1) {
+        const double *v = static_cast<const double *>(A.values);
+        if (v_dtype == 1)
+            hipLaunchKernelGGL((k_backproject<double, double>), grid, block, 0, s, A.colptr, A.rowidx, v, N, k, U,
+                               sigma, rank, static_cast<double *>(V));
+        else
+            hipLaunchKernelGGL((k_backproject<double, float>), grid, block, 0, s, A.colptr, A.rowidx, v, N, k, U,
+                               sigma, rank, static_cast<float *>(V));
+    } else {
+        const float *v = static_cast<const float *>(A.values);
+        if (v_dtype == 1)
+            hipLaunchKernelGGL((k_backproject<float, double>), grid, block, 0, s, A.colptr, A.rowidx, v, N, k, U,
+                               sigma, rank, static_cast<double *>(V));
+        else
+            hipLaunchKernelGGL((k_backproject<float, float>), grid, block, 0, s, A.colptr, A.rowidx, v, N, k, U,
+                               sigma, rank, static_cast<float *>(V));
+    }
+}
+
+hipError_t select_set_attributes() {
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_select_sort),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)((sizeof(double) + sizeof(int32_t)) * 8192));
+}
+
+}  // namespace ranky

@@ -1,0 +1,275 @@
+"""Python binding of libranky.so (the C-ABI in include/ranky.h).
+
+Argument marshalling only: torch tensors supply device memory and the current
+HIP stream; every step of the computation runs in the library's HIP kernels.
+There is no fallback: if the library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libranky.so")
+
+OK, E_INVALID, E_CSC, E_NONFINITE, E_NOMEM, E_DEVICE, E_BUSY, E_CANCELLED, E_NOT_CONVERGED, PENDING = range(10)
+STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_CSC", 3: "E_NONFINITE", 4: "E_NOMEM", 5: "E_DEVICE", 6: "E_BUSY",
+                7: "E_CANCELLED", 8: "E_NOT_CONVERGED", 9: "PENDING"}
+F32, F64 = 0, 1
+PREC = {"fp64": 0, "fp32": 1}
+
+
+class RankyError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Csc(ctypes.Structure):
+    _fields_ = [("nnz", ctypes.c_int64), ("colptr", ctypes.c_void_p), ("rowidx", ctypes.c_void_p),
+                ("values", ctypes.c_void_p), ("dtype", ctypes.c_int32)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("n_blocks", "gram_prec", "refine", "max_sweeps", "validate", "v_dtype", "timing", "reserved")]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("status", "rank", "n_nonempty", "empty_rows", "sweeps", "n_blocks", "lonely_max", "lonely_blocks")]
+    _fields_ += [("tau", ctypes.c_double), ("sigma_max", ctypes.c_double), ("ms", ctypes.c_float * 8)]
+
+    def as_dict(self):
+        d = {n: getattr(self, n) for n, _ in self._fields_ if n != "ms"}
+        d["ms"] = list(self.ms)
+        return d
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RankyError(E_DEVICE, f"{LIB_PATH} is not built (python -m paper_2009_09767_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    P = ctypes.POINTER
+    sig = {
+        "ranky_ctx_create": ([ctypes.c_int, P(vp)], i32),
+        "ranky_ctx_destroy": ([vp], i32),
+        "ranky_default_opts": ([P(Opts)], i32),
+        "ranky_last_error": ([], ctypes.c_char_p),
+        "ranky_version": ([], ctypes.c_char_p),
+        "ranky_workspace_bytes": ([i32, i64, i64, i32, P(Opts)], sz),
+        "ranky_svd": ([vp, P(Csc), i32, i64, i32, dbl, P(Opts), vp, sz, vp, vp, vp, P(Info), vp], i32),
+        "ranky_step_workspace_bytes": ([i32, i64, i64, i32], sz),
+        "ranky_occupancy": ([P(Csc), i32, i64, i32, vp, vp, vp, vp, vp, sz, vp], i32),
+        "ranky_gram": ([P(Csc), i32, i64, i32, vp, vp, sz, vp], i32),
+        "ranky_eigh_workspace_bytes": ([i32], sz),
+        "ranky_eigh": ([i32, vp, vp, vp, i32, P(i32), vp, sz, vp], i32),
+        "ranky_backproject": ([P(Csc), i32, i64, i32, vp, vp, vp, vp, i32, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().ranky_last_error().decode()
+
+
+def _check(st: int):
+    if st != OK:
+        raise RankyError(st, last_error())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+@dataclass
+class DeviceCSC:
+    """Device-resident CSC (int32 colptr/rowidx, FP32 or FP64 values)."""
+    M: int
+    N: int
+    colptr: torch.Tensor
+    rowidx: torch.Tensor
+    values: torch.Tensor
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowidx.numel())
+
+    def struct(self) -> Csc:
+        for t in (self.colptr, self.rowidx, self.values):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("CSC arrays must be contiguous device tensors")
+        if self.colptr.dtype != torch.int32 or self.rowidx.dtype != torch.int32:
+            raise TypeError("colptr and rowidx must be int32")
+        if self.values.dtype not in (torch.float32, torch.float64):
+            raise TypeError("values must be float32 or float64")
+        return Csc(self.nnz, self.colptr.data_ptr(), self.rowidx.data_ptr() if self.nnz else 0,
+                   self.values.data_ptr() if self.nnz else 0, F64 if self.values.dtype == torch.float64 else F32)
+
+
+def to_device(A, device="cuda") -> DeviceCSC:
+    """Copy a host CSC (anything with M, N, colptr, rowidx, values numpy arrays) to the device."""
+    return DeviceCSC(A.M, A.N, torch.from_numpy(A.colptr).to(device), torch.from_numpy(A.rowidx).to(device),
+                     torch.from_numpy(A.values).to(device))
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().ranky_ctx_create(device, ctypes.byref(h)))
+        self.handle = h
+        self.device = device
+        self._ws = None
+
+    def close(self):
+        if self.handle:
+            lib().ranky_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+
+_default_ctx: dict[int, Context] = {}
+
+
+def context(device: int = 0) -> Context:
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+def make_opts(n_blocks=0, gram_prec="fp64", refine=None, max_sweeps=0, validate=True, v_dtype=torch.float64,
+              timing=False) -> Opts:
+    o = Opts()
+    _check(lib().ranky_default_opts(ctypes.byref(o)))
+    o.n_blocks = n_blocks
+    o.gram_prec = PREC[gram_prec]
+    o.refine = (0 if gram_prec == "fp64" else 1) if refine is None else int(refine)
+    o.max_sweeps = max_sweeps
+    o.validate = int(validate)
+    o.v_dtype = F64 if v_dtype == torch.float64 else F32
+    o.timing = int(timing)
+    return o
+
+
+def workspace_bytes(M, N, nnz, k, opts: Opts) -> int:
+    return int(lib().ranky_workspace_bytes(M, N, nnz, k, ctypes.byref(opts)))
+
+
+@dataclass
+class SVDResult:
+    sigma: torch.Tensor
+    U: torch.Tensor
+    V: torch.Tensor
+    info: dict
+
+
+def svd(A: DeviceCSC, k: int, tol: float = 0.0, ctx: Context | None = None, out: SVDResult | None = None,
+        workspace: torch.Tensor | None = None, stream=None, **opt_kw) -> SVDResult:
+    """Top-k singular triplets of A by ranky_svd (blocking)."""
+    ctx = ctx or context(A.colptr.device.index or 0)
+    opts = make_opts(**opt_kw)
+    vdt = torch.float64 if opts.v_dtype == F64 else torch.float32
+    dev = A.colptr.device
+    if out is None:
+        out = SVDResult(torch.empty(k, dtype=torch.float64, device=dev),
+                        torch.empty((A.M, k), dtype=torch.float64, device=dev),
+                        torch.empty((A.N, k), dtype=vdt, device=dev), {})
+    nbytes = workspace_bytes(A.M, A.N, A.nnz, k, opts)
+    if nbytes == 0:
+        raise RankyError(E_INVALID, "invalid sizes for the workspace")
+    ws = workspace if workspace is not None else ctx.workspace(nbytes)
+    info = Info()
+    csc = A.struct()
+    st = lib().ranky_svd(ctx.handle, ctypes.byref(csc), A.M, A.N, k, float(tol), ctypes.byref(opts), _ptr(ws),
+                         ws.numel(), _ptr(out.sigma), _ptr(out.U), _ptr(out.V), ctypes.byref(info), _stream(stream))
+    _check(st)
+    out.info = info.as_dict()
+    return out
+
+
+def occupancy(A: DeviceCSC, D: int, stream=None):
+    """Alg. 1 scan: (cnt [D, M], rownnz [M], lonely [D], single [D]) as int32 device tensors."""
+    dev = A.colptr.device
+    cnt = torch.empty((D, A.M), dtype=torch.int32, device=dev)
+    rownnz = torch.empty(A.M, dtype=torch.int32, device=dev)
+    lonely = torch.empty(D, dtype=torch.int32, device=dev)
+    single = torch.empty(D, dtype=torch.int32, device=dev)
+    nbytes = int(lib().ranky_step_workspace_bytes(A.M, A.N, A.nnz, D))
+    if nbytes == 0:
+        raise RankyError(E_INVALID, "invalid sizes")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    csc = A.struct()
+    _check(lib().ranky_occupancy(ctypes.byref(csc), A.M, A.N, D, _ptr(cnt), _ptr(rownnz), _ptr(lonely),
+                                 _ptr(single), _ptr(ws), nbytes, _stream(stream)))
+    return cnt, rownnz, lonely, single
+
+
+def gram(A: DeviceCSC, prec: str = "fp64", stream=None) -> torch.Tensor:
+    dev = A.colptr.device
+    G = torch.empty((A.M, A.M), dtype=torch.float64, device=dev)
+    D = max(1, min(A.N, (A.N + 16383) // 16384))
+    nbytes = int(lib().ranky_step_workspace_bytes(A.M, A.N, A.nnz, D))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    csc = A.struct()
+    _check(lib().ranky_gram(ctypes.byref(csc), A.M, A.N, PREC[prec], _ptr(G), _ptr(ws), nbytes, _stream(stream)))
+    return G
+
+
+def eigh(G: torch.Tensor, max_sweeps: int = 0, stream=None):
+    """Blocked Jacobi eigensolve of a dense symmetric FP64 matrix: (lambda unsorted, Q, sweeps)."""
+    if G.dtype != torch.float64 or not G.is_cuda or G.dim() != 2 or G.shape[0] != G.shape[1]:
+        raise TypeError("G must be a square float64 device tensor")
+    G = G.contiguous()
+    n = G.shape[0]
+    lam = torch.empty(n, dtype=torch.float64, device=G.device)
+    Q = torch.empty((n, n), dtype=torch.float64, device=G.device)
+    nbytes = int(lib().ranky_eigh_workspace_bytes(n))
+    ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=G.device)
+    sw = ctypes.c_int32(0)
+    _check(lib().ranky_eigh(n, _ptr(G), _ptr(lam), _ptr(Q), max_sweeps, ctypes.byref(sw), _ptr(ws), nbytes,
+                            _stream(stream)))
+    return lam, Q, int(sw.value)
+
+
+def backproject(A: DeviceCSC, U: torch.Tensor, sigma: torch.Tensor, rank: int, v_dtype=torch.float64, stream=None):
+    """V = A^T U Sigma^{-1} on the first `rank` columns, zero beyond (stream-ordered)."""
+    k = U.shape[1]
+    dev = A.colptr.device
+    V = torch.empty((A.N, k), dtype=v_dtype, device=dev)
+    r = torch.tensor([rank], dtype=torch.int32, device=dev)
+    Uc, sc = U.contiguous(), sigma.contiguous()
+    csc = A.struct()
+    _check(lib().ranky_backproject(ctypes.byref(csc), A.M, A.N, k, _ptr(Uc), _ptr(sc), _ptr(r), _ptr(V),
+                                   F64 if v_dtype == torch.float64 else F32, _stream(stream)))
+    torch.cuda.current_stream().synchronize()
+    return V
