@@ -8,11 +8,6 @@ namespace ranky {
 
 // Columns handled by one workgroup of the occupancy and transpose passes.
 constexpr int kChunkCols = 4096;
-// Blocked Jacobi: the matrix is cut into blocks of kJB indices; a round pairs two
-// blocks, so every subproblem is kJP = 2 kJB wide.  kJS pads LDS rows.
-constexpr int kJB = 32;
-constexpr int kJP = 64;
-constexpr int kJS = 65;
 
 // Bits of the device status word.
 enum : int32_t { kStCsc = 1, kStNonfinite = 2 };

@@ -4,35 +4,41 @@
 // the eigendecomposition G = W Lambda W^T of G = P P^T.  Jacobi keeps relative
 // accuracy in the small eigenvalues, which the rank decision relies on.
 //
-// Layout: G and W are npad x npad row-major (npad a multiple of 64; indices >= n
-// are zero padding that no rotation ever touches, since their couplings stay
-// exactly zero).  The index range is cut into nb = npad / 32 blocks.  One sweep is
-// nb - 1 rounds of a round-robin tournament on the blocks; in a round the nb / 2
-// block pairs are disjoint, so their subproblems are independent:
-//   k_jsolve   one workgroup per pair (P, Q): the 64 x 64 subproblem S = G[s, s],
-//              s = P u Q, is diagonalised in LDS by cyclic Jacobi (a round-robin
-//              over its 64 indices, 32 rotations at a time); the accumulated
-//              rotation J (64 x 64) and the rotated S are written back.
-//   k_jupdate  one workgroup per 64 x 64 tile: G[s_a, s_b] <- J_a^T G[s_a, s_b] J_b
-//              for a < b (mirrored into (b, a)), and W[rows, s_b] <- W[rows, s_b] J_b.
-//              Tiles whose J are both the identity are skipped.
-//   k_jcheck   after a sweep: does any off-diagonal entry still fail the test
-//              |g_pq| > max(tol sqrt|g_pp g_qq|, floor)?  (tol = max(1e-15, sqrt(n) eps),
-//              floor = (n eps)^2 max|g_ii|.)  The host stops when none does.
+// Layout: G (two ping-pong copies) and W are npad x npad row-major, npad a multiple
+// of 32; indices >= n are zero padding that no rotation touches (their couplings
+// stay exactly zero).  The index range is cut into nb = npad / 16 blocks; one sweep
+// is nb - 1 rounds of a round-robin tournament on the blocks, and in a round the
+// nb / 2 block pairs are disjoint.  Every round is ONE launch of k_jround:
+//   * workgroups [0, npairs) solve the round's 32 x 32 subproblems S = M_r[s, s]
+//     (s = the pair's two blocks) by cyclic Jacobi in LDS and write the rotation J
+//     (32 x 32) and the rotated S.  M_r is the matrix after the previous rounds; its
+//     diagonal subproblem blocks are built directly from M_{r-1} and the previous
+//     round's J (J_a^T M_{r-1}[s_a, s_b] J_b), so no workgroup waits for the update.
+//   * the other workgroups apply the previous round: M_r = Jp^T M_{r-1} Jp tile by
+//     tile (32 x 32 tiles of the previous pairing; the diagonal tiles are the rotated
+//     subproblems themselves) into the other G buffer, and W <- W Jp in place.
+// A flush launch (update only) ends every sweep; k_jcheck then tests every
+// off-diagonal entry against |g_pq| > max(tol sqrt|g_pp g_qq|, floor) with
+// tol = max(1e-15, sqrt(n) eps), floor = (n eps)^2 max|g_ii|.
 // Rotation (Rutishauser): zeta = (g_qq - g_pp) / (2 g_pq), t = sign(zeta) / (|zeta| +
-// sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = c t; g_pp -= t g_pq, g_qq += t g_pq.
+// sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = c t; then g_pp -= t g_pq, g_qq += t g_pq.
+// Rows: r_p <- c r_p - s r_q, r_q <- s r_p + c r_q; columns likewise.
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace ranky {
 
-// Round r of the round-robin tournament on `players` (even) seats: seat 0 stays,
-// the others turn one place per round; pair i joins seat i and seat players-1-i.
+constexpr int kB = 16;       // block of indices
+constexpr int kP = 32;       // subproblem = two blocks
+constexpr int kPS = 33;      // LDS row stride of 32-wide tiles
+
+// Round r of the round-robin tournament on `players` (even) seats: seat 0 stays, the
+// others turn one place per round; pair i joins seat i and seat players-1-i.
 __device__ __forceinline__ void tournament_pair(int players, int r, int i, int &a, int &b) {
     const int ring = players - 1;
-    auto seat = [&](int k) { return k == 0 ? 0 : 1 + (k - 1 + r) % ring; };
-    a = seat(i);
-    b = seat(players - 1 - i);
+    const int sa = i, sb = players - 1 - i;
+    a = sa == 0 ? 0 : 1 + (sa - 1 + r) % ring;
+    b = sb == 0 ? 0 : 1 + (sb - 1 + r) % ring;
     if (a > b) {
         const int t = a;
         a = b;
@@ -40,7 +46,8 @@ __device__ __forceinline__ void tournament_pair(int players, int r, int i, int &
     }
 }
 
-__device__ __forceinline__ int sub_index(int l, int P, int Q) { return l < kJB ? P * kJB + l : Q * kJB + (l - kJB); }
+// global index of position l (0..31) of the super-block made of blocks (P, Q)
+__device__ __forceinline__ int gidx(int l, int P, int Q) { return l < kB ? P * kB + l : Q * kB + (l - kB); }
 
 __device__ __forceinline__ void rotation(double app, double aqq, double apq, double &c, double &s, double &t) {
     const double zeta = (aqq - app) / (2.0 * apq);
@@ -60,7 +67,7 @@ __global__ __launch_bounds__(256) void k_jeye(double *__restrict__ W, int32_t np
         W[e] = (e / npad == e % npad) ? 1.0 : 0.0;
 }
 
-// max |g_ii| -> floor = (n eps)^2 max|g_ii| (one workgroup).
+// floor = (n eps)^2 max|g_ii| (one workgroup).
 __global__ __launch_bounds__(256) void k_jprep(const double *__restrict__ G, int64_t ld, int32_t n,
                                                double *__restrict__ sdbl) {
     __shared__ double red[256];
@@ -78,226 +85,314 @@ __global__ __launch_bounds__(256) void k_jprep(const double *__restrict__ G, int
     }
 }
 
-__global__ __launch_bounds__(256) void k_jsolve(double *__restrict__ G, int64_t ld, int32_t nb, int32_t round,
-                                                double tol, const double *__restrict__ sdbl,
-                                                double *__restrict__ Jbuf, int32_t *__restrict__ jflag,
-                                                int32_t inner_sweeps) {
-    __shared__ double S[kJP * kJS];
-    __shared__ double J[kJP * kJS];
-    __shared__ double rc[kJP / 2], rs[kJP / 2], rpp[kJP / 2], rqq[kJP / 2];
-    __shared__ int32_t ra[kJP / 2], rb[kJP / 2], ract[kJP / 2];
-    __shared__ int32_t s_rot;
-    const int pair = blockIdx.x;
-    int P, Q;
-    tournament_pair(nb, round, pair, P, Q);
-    const double floor_abs = sdbl[kSdFloor];
-    const int tid = threadIdx.x;
+struct RoundArgs {
+    const double *Gin;     // M_{r-1} (or M_r itself when there is no previous round)
+    double *Gout;          // receives M_r = Jp^T M_{r-1} Jp (update part)
+    double *W;             // eigenvectors, updated in place by Jp
+    int64_t ld;
+    int32_t nb;            // blocks
+    int32_t round_cur;     // pairing of the subproblems solved now (if do_solve)
+    int32_t round_prev;    // pairing of the previous round (if has_prev)
+    int32_t has_prev, do_solve;
+    const double *Jprev;   // [npairs][32][32]
+    const int32_t *fprev;  // [npairs] 1 if Jprev[i] is not the identity
+    const double *Sprev;   // [npairs][32][32] rotated subproblems of the previous round
+    double *Jcur;
+    int32_t *fcur;
+    double *Scur;
+    const double *sdbl;
+    double tol;
+    int32_t inner_sweeps;
+    int32_t ntiles_g;      // npairs (npairs + 1) / 2
+    int32_t nrowtiles;     // npad / 32
+};
 
-    for (int e = tid; e < kJP * kJP; e += 256) {
-        const int a = e >> 6, b = e & 63;
-        S[a * kJS + b] = G[(int64_t)sub_index(a, P, Q) * ld + sub_index(b, P, Q)];
-        J[a * kJS + b] = (a == b) ? 1.0 : 0.0;
+// ---- subproblem solve -------------------------------------------------------
+
+__device__ void solve_pair(const RoundArgs &a, int pair, double *S, double *J, double *T, double *JA, double *JB,
+                           int *pos) {
+    const int tid = threadIdx.x;
+    const int npairs = a.nb / 2;
+    int P, Q;
+    tournament_pair(a.nb, a.round_cur, pair, P, Q);
+    if (!a.has_prev) {
+        for (int e = tid; e < kP * kP; e += 256) {
+            const int x = e >> 5, y = e & 31;
+            S[x * kPS + y] = a.Gin[(int64_t)gidx(x, P, Q) * a.ld + gidx(y, P, Q)];
+        }
+    } else {
+        // where blocks P and Q sat in the previous round: pos[block] = pair * 2 + half
+        for (int j = tid; j < npairs; j += 256) {
+            int x, y;
+            tournament_pair(a.nb, a.round_prev, j, x, y);
+            pos[x] = 2 * j;
+            pos[y] = 2 * j + 1;
+        }
+        __syncthreads();
+        const int pp = pos[P] >> 1, hp = pos[P] & 1, pq = pos[Q] >> 1, hq = pos[Q] & 1;
+        // diagonal blocks: the previous round's rotated subproblems
+        for (int e = tid; e < kB * kB; e += 256) {
+            const int x = e >> 4, y = e & 15;
+            S[x * kPS + y] = a.Sprev[(int64_t)pp * kP * kP + (hp * kB + x) * kP + hp * kB + y];
+            S[(kB + x) * kPS + kB + y] = a.Sprev[(int64_t)pq * kP * kP + (hq * kB + x) * kP + hq * kB + y];
+        }
+        // off-diagonal block: J_pp[:, hp]^T  M_{r-1}[s_pp, s_pq]  J_pq[:, hq]
+        int Pa, Qa, Pb, Qb;
+        tournament_pair(a.nb, a.round_prev, pp, Pa, Qa);
+        tournament_pair(a.nb, a.round_prev, pq, Pb, Qb);
+        const bool fa = a.fprev[pp] != 0, fb = a.fprev[pq] != 0;
+        for (int e = tid; e < kP * kP; e += 256) {
+            const int x = e >> 5, y = e & 31;
+            T[x * kPS + y] = a.Gin[(int64_t)gidx(x, Pa, Qa) * a.ld + gidx(y, Pb, Qb)];
+        }
+        for (int e = tid; e < kP * kB; e += 256) {
+            const int x = e >> 4, y = e & 15;
+            JA[x * kB + y] = fa ? a.Jprev[(int64_t)pp * kP * kP + x * kP + hp * kB + y] : (x == hp * kB + y ? 1.0 : 0.0);
+            JB[x * kB + y] = fb ? a.Jprev[(int64_t)pq * kP * kP + x * kP + hq * kB + y] : (x == hq * kB + y ? 1.0 : 0.0);
+        }
+        __syncthreads();
+        // U1 = T JB (32 x 16): two outputs per thread, kept in registers
+        double u0 = 0.0, u1 = 0.0;
+        {
+            const int x = tid >> 3, y = (tid & 7) * 2;
+            for (int z = 0; z < kP; ++z) {
+                const double t = T[x * kPS + z];
+                u0 = fma(t, JB[z * kB + y], u0);
+                u1 = fma(t, JB[z * kB + y + 1], u1);
+            }
+        }
+        __syncthreads();
+        {
+            const int x = tid >> 3, y = (tid & 7) * 2;
+            T[x * kPS + y] = u0;
+            T[x * kPS + y + 1] = u1;
+        }
+        __syncthreads();
+        // S_PQ = JA^T U1 (16 x 16): one output per thread
+        {
+            const int x = tid >> 4, y = tid & 15;
+            double v = 0.0;
+            for (int z = 0; z < kP; ++z) v = fma(JA[z * kB + x], T[z * kPS + y], v);
+            S[x * kPS + kB + y] = v;
+            S[(kB + y) * kPS + x] = v;
+        }
     }
-    if (tid == 0) s_rot = 0;
+    for (int e = tid; e < kP * kP; e += 256) {
+        const int x = e >> 5, y = e & 31;
+        J[x * kPS + y] = (x == y) ? 1.0 : 0.0;
+    }
     __syncthreads();
 
-    int total_rot = 0;
-    for (int sw = 0; sw < inner_sweeps; ++sw) {
+    __shared__ double rc[kP / 2], rs[kP / 2], rpp[kP / 2], rqq[kP / 2];
+    __shared__ int ra[kP / 2], rb[kP / 2], ract[kP / 2];
+    const double floor_abs = a.sdbl[kSdFloor];
+    int rotated = 0;
+    const int bi = tid >> 4, bj = tid & 15;   // this thread's 2x2 block of pair slots
+    for (int sw = 0; sw < a.inner_sweeps; ++sw) {
         int sweep_rot = 0;
-        for (int step = 0; step < kJP - 1; ++step) {
-            if (tid < kJP / 2) {
-                int a, b;
-                tournament_pair(kJP, step, tid, a, b);
-                const double app = S[a * kJS + a], aqq = S[b * kJS + b], apq = S[a * kJS + b];
-                int act = 0;
+        for (int step = 0; step < kP - 1; ++step) {
+            int act = 0;
+            if (tid < kP / 2) {
+                int x, y;
+                tournament_pair(kP, step, tid, x, y);
+                const double app = S[x * kPS + x], aqq = S[y * kPS + y], apq = S[x * kPS + y];
                 double c = 1.0, s = 0.0;
-                if (fabs(apq) > floor_abs && fabs(apq) > tol * sqrt(fabs(app * aqq))) {
+                if (fabs(apq) > floor_abs && fabs(apq) > a.tol * sqrt(fabs(app * aqq))) {
                     double t;
                     rotation(app, aqq, apq, c, s, t);
                     rpp[tid] = app - t * apq;
                     rqq[tid] = aqq + t * apq;
                     act = 1;
                 }
-                ra[tid] = a;
-                rb[tid] = b;
+                ra[tid] = x;
+                rb[tid] = y;
                 rc[tid] = c;
                 rs[tid] = s;
                 ract[tid] = act;
             }
-            __syncthreads();
-            int any = 0;
-            for (int k = 0; k < kJP / 2; ++k) any |= ract[k];
-            if (any) {
-                // rows a, b of S
-                for (int w = tid; w < (kJP / 2) * kJP; w += 256) {
-                    const int pr = w >> 6, x = w & 63;
-                    if (!ract[pr]) continue;
-                    const int a = ra[pr], b = rb[pr];
-                    const double c = rc[pr], s = rs[pr];
-                    const double xa = S[a * kJS + x], xb = S[b * kJS + x];
-                    S[a * kJS + x] = c * xa - s * xb;
-                    S[b * kJS + x] = s * xa + c * xb;
+            if (__syncthreads_or(act) == 0) continue;
+            sweep_rot += 1;
+            // two-sided update of this thread's 2x2 block: R_i^T X R_j
+            {
+                const int ai = ra[bi], bi2 = rb[bi], aj = ra[bj], bj2 = rb[bj];
+                const int acti = ract[bi], actj = ract[bj];
+                if (bi == bj) {
+                    if (acti) {
+                        S[ai * kPS + ai] = rpp[bi];
+                        S[bi2 * kPS + bi2] = rqq[bi];
+                        S[ai * kPS + bi2] = 0.0;
+                        S[bi2 * kPS + ai] = 0.0;
+                    }
+                } else if (acti || actj) {
+                    double x00 = S[ai * kPS + aj], x01 = S[ai * kPS + bj2];
+                    double x10 = S[bi2 * kPS + aj], x11 = S[bi2 * kPS + bj2];
+                    if (acti) {
+                        const double c = rc[bi], s = rs[bi];
+                        const double y00 = c * x00 - s * x10, y01 = c * x01 - s * x11;
+                        const double y10 = s * x00 + c * x10, y11 = s * x01 + c * x11;
+                        x00 = y00;
+                        x01 = y01;
+                        x10 = y10;
+                        x11 = y11;
+                    }
+                    if (actj) {
+                        const double c = rc[bj], s = rs[bj];
+                        const double y00 = c * x00 - s * x01, y01 = s * x00 + c * x01;
+                        const double y10 = c * x10 - s * x11, y11 = s * x10 + c * x11;
+                        x00 = y00;
+                        x01 = y01;
+                        x10 = y10;
+                        x11 = y11;
+                    }
+                    S[ai * kPS + aj] = x00;
+                    S[ai * kPS + bj2] = x01;
+                    S[bi2 * kPS + aj] = x10;
+                    S[bi2 * kPS + bj2] = x11;
                 }
-                __syncthreads();
-                // columns a, b of S and of J
-                for (int w = tid; w < (kJP / 2) * kJP; w += 256) {
-                    const int pr = w >> 6, x = w & 63;
-                    if (!ract[pr]) continue;
-                    const int a = ra[pr], b = rb[pr];
-                    const double c = rc[pr], s = rs[pr];
-                    double xa = S[x * kJS + a], xb = S[x * kJS + b];
-                    S[x * kJS + a] = c * xa - s * xb;
-                    S[x * kJS + b] = s * xa + c * xb;
-                    xa = J[x * kJS + a];
-                    xb = J[x * kJS + b];
-                    J[x * kJS + a] = c * xa - s * xb;
-                    J[x * kJS + b] = s * xa + c * xb;
+            }
+            // J <- J R: columns of the pair, two rows per thread
+            {
+                const int p = tid & 15;
+                if (ract[p]) {
+                    const int x0 = ra[p], y0 = rb[p];
+                    const double c = rc[p], s = rs[p];
+                    for (int row = tid >> 4; row < kP; row += 16) {
+                        const double u = J[row * kPS + x0], v = J[row * kPS + y0];
+                        J[row * kPS + x0] = c * u - s * v;
+                        J[row * kPS + y0] = s * u + c * v;
+                    }
                 }
-                __syncthreads();
-                if (tid < kJP / 2 && ract[tid]) {
-                    const int a = ra[tid], b = rb[tid];
-                    S[a * kJS + a] = rpp[tid];
-                    S[b * kJS + b] = rqq[tid];
-                    S[a * kJS + b] = 0.0;
-                    S[b * kJS + a] = 0.0;
-                }
-                sweep_rot += 1;
             }
             __syncthreads();
         }
-        total_rot += sweep_rot;
+        rotated += sweep_rot;
         if (sweep_rot == 0) break;
     }
-    // write back S (rotated diagonal block) and J
-    for (int e = tid; e < kJP * kJP; e += 256) {
-        const int a = e >> 6, b = e & 63;
-        G[(int64_t)sub_index(a, P, Q) * ld + sub_index(b, P, Q)] = S[a * kJS + b];
-        Jbuf[(int64_t)pair * kJP * kJP + e] = J[a * kJS + b];
+    for (int e = tid; e < kP * kP; e += 256) {
+        const int x = e >> 5, y = e & 31;
+        a.Jcur[(int64_t)pair * kP * kP + e] = J[x * kPS + y];
+        a.Scur[(int64_t)pair * kP * kP + e] = S[x * kPS + y];
     }
-    if (tid == 0) jflag[pair] = total_rot > 0;
+    if (tid == 0) a.fcur[pair] = rotated > 0;
 }
 
-// C (4x4 per thread) = A (64 x 64, LDS) * B (64 x 64, LDS); transA reads A^T.
+// ---- update of the previous round ------------------------------------------
+
+// C (2x2 per thread... 4 outputs) = A (32x32) * B (32x32); transA reads A^T.
 template <bool transA>
-__device__ __forceinline__ void tile_gemm(const double *__restrict__ A, const double *__restrict__ B, double c[4][4],
-                                          int ty, int tx) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) c[u][v] = 0.0;
-    for (int x = 0; x < kJP; ++x) {
-        double a[4], b[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) a[u] = transA ? A[x * kJS + 4 * ty + u] : A[(4 * ty + u) * kJS + x];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) b[v] = B[x * kJS + 4 * tx + v];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) c[u][v] = fma(a[u], b[v], c[u][v]);
+__device__ __forceinline__ void gemm32(const double *__restrict__ A, const double *__restrict__ B, double c[4],
+                                       int row, int col0) {
+    c[0] = c[1] = c[2] = c[3] = 0.0;
+    for (int z = 0; z < kP; ++z) {
+        const double av = transA ? A[z * kPS + row] : A[row * kPS + z];
+        const double *b = B + z * kPS + col0;
+        c[0] = fma(av, b[0], c[0]);
+        c[1] = fma(av, b[1], c[1]);
+        c[2] = fma(av, b[2], c[2]);
+        c[3] = fma(av, b[3], c[3]);
     }
 }
 
-__global__ __launch_bounds__(256) void k_jupdate(double *__restrict__ G, double *__restrict__ W, int64_t ld,
-                                                 int32_t nb, int32_t round, const double *__restrict__ Jbuf,
-                                                 const int32_t *__restrict__ jflag, int32_t ntiles_g,
-                                                 int32_t nrowtiles) {
-    __shared__ double A[kJP * kJS];
-    __shared__ double B[kJP * kJS];
-    const int npairs = nb / 2;
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    int t = blockIdx.x;
-    double c[4][4];
-    if (t < ntiles_g) {
-        // tile (ia, ib), ia < ib, from the row-major upper-triangular enumeration
-        int ia = 0, rem = t;
-        while (rem >= npairs - 1 - ia) {
-            rem -= npairs - 1 - ia;
+__device__ void update_tile(const RoundArgs &a, int u, double *A, double *B) {
+    const int tid = threadIdx.x;
+    const int npairs = a.nb / 2;
+    const int row = tid >> 3, col0 = (tid & 7) * 4;
+    double c[4];
+    if (u < a.ntiles_g) {
+        int ia = 0, rem = u;
+        while (rem >= npairs - ia) {
+            rem -= npairs - ia;
             ++ia;
         }
-        const int ib = ia + 1 + rem;
-        const int fa = jflag[ia], fb = jflag[ib];
-        if (!fa && !fb) return;
+        const int ib = ia + rem;
         int Pa, Qa, Pb, Qb;
-        tournament_pair(nb, round, ia, Pa, Qa);
-        tournament_pair(nb, round, ib, Pb, Qb);
-        for (int e = tid; e < kJP * kJP; e += 256) {
-            const int r = e >> 6, q = e & 63;
-            A[r * kJS + q] = G[(int64_t)sub_index(r, Pa, Qa) * ld + sub_index(q, Pb, Qb)];
+        tournament_pair(a.nb, a.round_prev, ia, Pa, Qa);
+        tournament_pair(a.nb, a.round_prev, ib, Pb, Qb);
+        if (ia == ib) {
+            const double *s = a.Sprev + (int64_t)ia * kP * kP;
+            for (int e = tid; e < kP * kP; e += 256)
+                a.Gout[(int64_t)gidx(e >> 5, Pa, Qa) * a.ld + gidx(e & 31, Pa, Qa)] = s[e];
+            return;
+        }
+        const bool fa = a.fprev[ia] != 0, fb = a.fprev[ib] != 0;
+        for (int e = tid; e < kP * kP; e += 256) {
+            const int x = e >> 5, y = e & 31;
+            A[x * kPS + y] = a.Gin[(int64_t)gidx(x, Pa, Qa) * a.ld + gidx(y, Pb, Qb)];
         }
         if (fb) {
-            const double *Jb = Jbuf + (int64_t)ib * kJP * kJP;
-            for (int e = tid; e < kJP * kJP; e += 256) B[(e >> 6) * kJS + (e & 63)] = Jb[e];
+            const double *jb = a.Jprev + (int64_t)ib * kP * kP;
+            for (int e = tid; e < kP * kP; e += 256) B[(e >> 5) * kPS + (e & 31)] = jb[e];
             __syncthreads();
-            tile_gemm<false>(A, B, c, ty, tx);
+            gemm32<false>(A, B, c, row, col0);
             __syncthreads();
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) A[(4 * ty + u) * kJS + 4 * tx + v] = c[u][v];
+            for (int v = 0; v < 4; ++v) A[row * kPS + col0 + v] = c[v];
         }
         if (fa) {
-            const double *Ja = Jbuf + (int64_t)ia * kJP * kJP;
+            const double *ja = a.Jprev + (int64_t)ia * kP * kP;
             __syncthreads();
-            for (int e = tid; e < kJP * kJP; e += 256) B[(e >> 6) * kJS + (e & 63)] = Ja[e];
+            for (int e = tid; e < kP * kP; e += 256) B[(e >> 5) * kPS + (e & 31)] = ja[e];
             __syncthreads();
-            tile_gemm<true>(B, A, c, ty, tx);
+            gemm32<true>(B, A, c, row, col0);
             __syncthreads();
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) A[(4 * ty + u) * kJS + 4 * tx + v] = c[u][v];
+            for (int v = 0; v < 4; ++v) A[row * kPS + col0 + v] = c[v];
         }
         __syncthreads();
-        for (int e = tid; e < kJP * kJP; e += 256) {
-            const int r = e >> 6, q = e & 63;
-            const double v = A[r * kJS + q];
-            G[(int64_t)sub_index(r, Pa, Qa) * ld + sub_index(q, Pb, Qb)] = v;
-            G[(int64_t)sub_index(q, Pb, Qb) * ld + sub_index(r, Pa, Qa)] = v;
+        for (int e = tid; e < kP * kP; e += 256) {
+            const int x = e >> 5, y = e & 31;
+            const double v = A[x * kPS + y];
+            a.Gout[(int64_t)gidx(x, Pa, Qa) * a.ld + gidx(y, Pb, Qb)] = v;
+            a.Gout[(int64_t)gidx(y, Pb, Qb) * a.ld + gidx(x, Pa, Qa)] = v;
         }
         return;
     }
-    t -= ntiles_g;
-    const int rt = t / npairs, ib = t % npairs;
-    if (rt >= nrowtiles || !jflag[ib]) return;
+    u -= a.ntiles_g;
+    const int rt = u / npairs, ib = u % npairs;
+    if (rt >= a.nrowtiles || !a.fprev[ib]) return;
     int Pb, Qb;
-    tournament_pair(nb, round, ib, Pb, Qb);
-    const double *Jb = Jbuf + (int64_t)ib * kJP * kJP;
-    for (int e = tid; e < kJP * kJP; e += 256) {
-        const int r = e >> 6, q = e & 63;
-        A[r * kJS + q] = W[(int64_t)(rt * kJP + r) * ld + sub_index(q, Pb, Qb)];
-        B[r * kJS + q] = Jb[e];
+    tournament_pair(a.nb, a.round_prev, ib, Pb, Qb);
+    const double *jb = a.Jprev + (int64_t)ib * kP * kP;
+    for (int e = tid; e < kP * kP; e += 256) {
+        const int x = e >> 5, y = e & 31;
+        A[x * kPS + y] = a.W[(int64_t)(rt * kP + x) * a.ld + gidx(y, Pb, Qb)];
+        B[x * kPS + y] = jb[e];
     }
     __syncthreads();
-    tile_gemm<false>(A, B, c, ty, tx);
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-            W[(int64_t)(rt * kJP + 4 * ty + u) * ld + sub_index(4 * tx + v, Pb, Qb)] = c[u][v];
+    gemm32<false>(A, B, c, row, col0);
+    for (int v = 0; v < 4; ++v) a.W[(int64_t)(rt * kP + row) * a.ld + gidx(col0 + v, Pb, Qb)] = c[v];
+}
+
+__global__ __launch_bounds__(256) void k_jround(RoundArgs a) {
+    __shared__ double L0[kP * kPS], L1[kP * kPS], L2[kP * kPS];
+    __shared__ double L3[kP * kB], L4[kP * kB];
+    __shared__ int pos[512];
+    const int npairs = a.nb / 2;
+    int b = blockIdx.x;
+    if (a.do_solve) {
+        if (b < npairs) {
+            solve_pair(a, b, L0, L1, L2, L3, L4, pos);
+            return;
+        }
+        b -= npairs;
+    }
+    update_tile(a, b, L0, L1);
 }
 
 // Sets scal[kScNotConv] = 1 if an off-diagonal entry of the leading n x n part still
-// fails the rotation test.  Grid: one thread per (row, 64-column strip), upper part only.
+// fails the rotation test (one thread per entry of the upper triangle, coalesced).
 __global__ __launch_bounds__(256) void k_jcheck(const double *__restrict__ G, int64_t ld, int32_t n, double tol,
                                                 const double *__restrict__ sdbl, int32_t *__restrict__ scal) {
     const double floor_abs = sdbl[kSdFloor];
-    const int64_t strips = (n + 63) / 64;
     int bad = 0;
-    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < (int64_t)n * strips;
-         w += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = w / strips, st = w % strips;
-        const double gpp = G[p * ld + p];
-        for (int64_t q = st * 64; q < st * 64 + 64 && q < n; ++q) {
-            if (q <= p) continue;
-            const double g = G[p * ld + q];
-            if (fabs(g) > floor_abs && fabs(g) > tol * sqrt(fabs(gpp * G[q * ld + q]))) bad = 1;
-        }
+    const int64_t total = (int64_t)n * n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e / n, q = e % n;
+        if (q <= p) continue;
+        const double g = G[p * ld + q];
+        if (fabs(g) > floor_abs && fabs(g) > tol * sqrt(fabs(G[p * ld + p] * G[q * ld + q]))) bad = 1;
     }
     if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(&scal[kScNotConv], 1);
 }
 
-// eigenvalues = diag(G)
 __global__ __launch_bounds__(256) void k_jdiag(const double *__restrict__ G, int64_t ld, int32_t n,
                                                double *__restrict__ lam) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -305,6 +400,8 @@ __global__ __launch_bounds__(256) void k_jdiag(const double *__restrict__ G, int
 }
 
 // ---------------------------------------------------------------------------
+
+int32_t jacobi_npad(int32_t n) { return ((n + kP - 1) / kP) * kP; }
 
 void launch_jacobi_init(double *W, int32_t npad, const double *G, int64_t ld, int32_t n, double *sdbl,
                         hipStream_t s) {
@@ -314,25 +411,41 @@ void launch_jacobi_init(double *W, int32_t npad, const double *G, int64_t ld, in
     hipLaunchKernelGGL(k_jprep, dim3(1), dim3(256), 0, s, G, ld, n, sdbl);
 }
 
-void launch_jacobi_round(double *G, double *W, int64_t ld, int32_t npad, int32_t round, double tol,
-                         const double *sdbl, double *Jbuf, int32_t *jflag, int32_t inner_sweeps, hipStream_t s) {
-    const int32_t nb = npad / kJB;
-    const int32_t npairs = nb / 2;
-    hipLaunchKernelGGL(k_jsolve, dim3((unsigned)npairs), dim3(256), 0, s, G, ld, nb, round, tol, sdbl, Jbuf, jflag,
-                       inner_sweeps);
-    const int32_t ntiles_g = npairs * (npairs - 1) / 2;
-    const int32_t nrowtiles = npad / kJP;
-    const int32_t total = ntiles_g + nrowtiles * npairs;
-    hipLaunchKernelGGL(k_jupdate, dim3((unsigned)total), dim3(256), 0, s, G, W, ld, nb, round, Jbuf, jflag, ntiles_g,
-                       nrowtiles);
+void launch_jacobi_round(const JacobiRound &r, hipStream_t s) {
+    RoundArgs a;
+    a.Gin = r.Gin;
+    a.Gout = r.Gout;
+    a.W = r.W;
+    a.ld = r.ld;
+    a.nb = r.npad / kB;
+    a.round_cur = r.round_cur;
+    a.round_prev = r.round_prev;
+    a.has_prev = r.has_prev;
+    a.do_solve = r.do_solve;
+    a.Jprev = r.Jprev;
+    a.fprev = r.fprev;
+    a.Sprev = r.Sprev;
+    a.Jcur = r.Jcur;
+    a.fcur = r.fcur;
+    a.Scur = r.Scur;
+    a.sdbl = r.sdbl;
+    a.tol = r.tol;
+    a.inner_sweeps = r.inner_sweeps;
+    const int32_t npairs = a.nb / 2;
+    a.ntiles_g = npairs * (npairs + 1) / 2;
+    a.nrowtiles = r.npad / kP;
+    int64_t grid = 0;
+    if (a.do_solve) grid += npairs;
+    if (a.has_prev) grid += a.ntiles_g + (int64_t)a.nrowtiles * npairs;
+    if (grid == 0) return;
+    hipLaunchKernelGGL(k_jround, dim3((unsigned)grid), dim3(256), 0, s, a);
 }
 
 void launch_jacobi_check(const double *G, int64_t ld, int32_t n, double tol, const double *sdbl, int32_t *scal,
                          hipStream_t s) {
-    const int64_t work = (int64_t)n * ((n + 63) / 64);
-    int64_t blocks = (work + 255) / 256;
+    int64_t blocks = ((int64_t)n * n + 255) / 256;
     if (blocks < 1) blocks = 1;
-    if (blocks > 2048) blocks = 2048;
+    if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_jcheck, dim3((unsigned)blocks), dim3(256), 0, s, G, ld, n, tol, sdbl, scal);
 }
 

@@ -37,10 +37,28 @@ void launch_gram(const CscView &A, int32_t M, int32_t n, int32_t npad, int64_t l
 hipError_t gram_set_attributes(size_t lds_limit);
 
 // Jacobi eigensolver (k_jacobi.hip)
+struct JacobiRound {
+    const double *Gin;
+    double *Gout;
+    double *W;
+    int64_t ld;
+    int32_t npad;
+    int32_t round_cur, round_prev, has_prev, do_solve;
+    const double *Jprev;
+    const int32_t *fprev;
+    const double *Sprev;
+    double *Jcur;
+    int32_t *fcur;
+    double *Scur;
+    const double *sdbl;
+    double tol;
+    int32_t inner_sweeps;
+};
+int32_t jacobi_npad(int32_t n);  // multiple of the 32-wide subproblem
+constexpr int32_t kJacobiPair = 32;
 void launch_jacobi_init(double *W, int32_t npad, const double *G, int64_t ld, int32_t n, double *sdbl,
                         hipStream_t s);
-void launch_jacobi_round(double *G, double *W, int64_t ld, int32_t npad, int32_t round, double tol,
-                         const double *sdbl, double *Jbuf, int32_t *jflag, int32_t inner_sweeps, hipStream_t s);
+void launch_jacobi_round(const JacobiRound &r, hipStream_t s);
 void launch_jacobi_check(const double *G, int64_t ld, int32_t n, double tol, const double *sdbl, int32_t *scal,
                          hipStream_t s);
 void launch_jacobi_diag(const double *G, int64_t ld, int32_t n, double *lam, hipStream_t s);

@@ -47,14 +47,15 @@ ranky_status fail(ranky_status st, const char *fmt, ...) {
     } while (0)
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
-int32_t round_up64(int32_t x) { return ((x + 63) / 64) * 64; }
+int32_t round_up64(int32_t x) { return jacobi_npad(x); }  // padded order of the eigensolver
 
 // Workspace plan: offsets of every device array for the given sizes.
 struct Plan {
     int32_t M = 0, k = 0, D = 0, cpb = 0, npad = 0;
     int64_t N = 0, nnz = 0, nchunks = 0;
     size_t o_scal = 0, o_sdbl = 0, o_hist = 0, o_rownnz = 0, o_rowptr = 0, o_m2r = 0, o_r2m = 0, o_empty = 0;
-    size_t o_lonely = 0, o_single = 0, o_csrk = 0, o_csrend = 0, o_G = 0, o_W = 0, o_J = 0, o_jflag = 0;
+    size_t o_lonely = 0, o_single = 0, o_csrk = 0, o_csrend = 0, o_G = 0, o_G2 = 0, o_W = 0, o_J = 0, o_S = 0,
+           o_jflag = 0;
     size_t o_lam = 0, o_perm = 0, total = 0;
 };
 
@@ -90,9 +91,12 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool wit
     p.o_csrend = take(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
     p.o_G = take(sizeof(double) * (size_t)p.npad * p.npad);
     if (with_solver) {
+        const size_t npairs = (size_t)(p.npad / kJacobiPair);
+        p.o_G2 = take(sizeof(double) * (size_t)p.npad * p.npad);
         p.o_W = take(sizeof(double) * (size_t)p.npad * p.npad);
-        p.o_J = take(sizeof(double) * (size_t)(p.npad / kJP) * kJP * kJP);
-        p.o_jflag = take(sizeof(int32_t) * (size_t)(p.npad / kJP));
+        p.o_J = take(sizeof(double) * 2 * npairs * kJacobiPair * kJacobiPair);
+        p.o_S = take(sizeof(double) * 2 * npairs * kJacobiPair * kJacobiPair);
+        p.o_jflag = take(sizeof(int32_t) * 2 * npairs);
         p.o_lam = take(sizeof(double) * p.npad);
         p.o_perm = take(sizeof(int32_t) * p.npad);
     }
@@ -102,7 +106,7 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool wit
 
 struct Ptrs {
     int32_t *scal, *hist, *rownnz, *rowptr, *m2r, *r2m, *empty, *lonely, *single, *csrk, *csrend, *jflag, *perm;
-    double *sdbl, *G, *W, *J, *lam;
+    double *sdbl, *G, *G2, *W, *J, *S, *lam;
 };
 
 Ptrs carve(const Plan &p, void *ws) {
@@ -121,8 +125,10 @@ Ptrs carve(const Plan &p, void *ws) {
     q.csrk = reinterpret_cast<int32_t *>(b + p.o_csrk);
     q.csrend = reinterpret_cast<int32_t *>(b + p.o_csrend);
     q.G = reinterpret_cast<double *>(b + p.o_G);
+    q.G2 = reinterpret_cast<double *>(b + p.o_G2);
     q.W = reinterpret_cast<double *>(b + p.o_W);
     q.J = reinterpret_cast<double *>(b + p.o_J);
+    q.S = reinterpret_cast<double *>(b + p.o_S);
     q.jflag = reinterpret_cast<int32_t *>(b + p.o_jflag);
     q.lam = reinterpret_cast<double *>(b + p.o_lam);
     q.perm = reinterpret_cast<int32_t *>(b + p.o_perm);
@@ -186,20 +192,25 @@ ranky_status run_occupancy(ranky_ctx *ctx, const Plan &p, const Ptrs &w, const C
     return RANKY_OK;
 }
 
-// Blocked Jacobi on G (leading n x n of an npad x npad array, ld = npad); W receives
-// the eigenvectors, lam the eigenvalues.
+// Blocked Jacobi on G (leading n x n of an npad x npad array in w.G, ld = npad); on
+// return *Gcur points at the buffer (w.G or w.G2) that holds the rotated matrix, W
+// holds the eigenvectors and lam the eigenvalues.
 ranky_status run_jacobi(ranky_ctx *ctx, const Ptrs &w, int32_t n, int32_t max_sweeps, hipStream_t s,
                         int32_t *sweeps_out) {
     const int32_t npad = round_up64(n);
     const int64_t ld = npad;
+    const int32_t nb = npad / (kJacobiPair / 2);
+    const int32_t npairs = nb / 2;
+    const size_t jsz = (size_t)npairs * kJacobiPair * kJacobiPair;
     const double tol = std::fmax(1e-15, std::sqrt((double)n) * kEps);
     launch_jacobi_init(w.W, npad, w.G, ld, n, w.sdbl, s);
-    const int32_t nb = npad / kJB;
+    double *buf[2] = {w.G, w.G2};
+    int cur = 0;
     int32_t sweeps = 0;
     bool converged = false;
     for (;;) {
         launch_fill_i32(w.scal + kScNotConv, 1, 0, s);
-        launch_jacobi_check(w.G, ld, n, tol, w.sdbl, w.scal, s);
+        launch_jacobi_check(buf[cur], ld, n, tol, w.sdbl, w.scal, s);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(ctx->pinned + kScNotConv, w.scal + kScNotConv, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
@@ -208,11 +219,33 @@ ranky_status run_jacobi(ranky_ctx *ctx, const Ptrs &w, int32_t n, int32_t max_sw
             break;
         }
         if (sweeps >= max_sweeps) break;
-        for (int32_t r = 0; r < nb - 1; ++r)
-            launch_jacobi_round(w.G, w.W, ld, npad, r, tol, w.sdbl, w.J, w.jflag, kInnerSweeps, s);
+        for (int32_t r = 0; r <= nb - 1; ++r) {  // r = nb - 1 is the flush of the last round
+            JacobiRound jr;
+            jr.Gin = buf[cur];
+            jr.Gout = buf[cur ^ 1];
+            jr.W = w.W;
+            jr.ld = ld;
+            jr.npad = npad;
+            jr.round_cur = r;
+            jr.round_prev = r - 1;
+            jr.has_prev = r > 0;
+            jr.do_solve = r < nb - 1;
+            jr.Jprev = w.J + ((r + 1) & 1) * jsz;
+            jr.Sprev = w.S + ((r + 1) & 1) * jsz;
+            jr.fprev = w.jflag + ((r + 1) & 1) * npairs;
+            jr.Jcur = w.J + (r & 1) * jsz;
+            jr.Scur = w.S + (r & 1) * jsz;
+            jr.fcur = w.jflag + (r & 1) * npairs;
+            jr.sdbl = w.sdbl;
+            jr.tol = tol;
+            jr.inner_sweeps = npairs == 1 ? 40 : 1;
+            launch_jacobi_round(jr, s);
+            if (jr.has_prev) cur ^= 1;
+        }
+        HIP_TRY(hipGetLastError());
         sweeps += 1;
     }
-    launch_jacobi_diag(w.G, ld, n, w.lam, s);
+    launch_jacobi_diag(buf[cur], ld, n, w.lam, s);
     HIP_TRY(hipGetLastError());
     if (sweeps_out) *sweeps_out = sweeps;
     if (!converged) return fail(RANKY_E_NOT_CONVERGED, "Jacobi did not converge in %d sweeps", max_sweeps);
@@ -452,8 +485,10 @@ size_t ranky_eigh_workspace_bytes(int32_t n) {
     const int32_t npad = round_up64(n);
     size_t b = 0;
     b += align_up(sizeof(int32_t) * kScCount) + align_up(sizeof(double) * kSdCount);
-    b += 2 * align_up(sizeof(double) * (size_t)npad * npad);
-    b += align_up(sizeof(double) * (size_t)(npad / kJP) * kJP * kJP) + align_up(sizeof(int32_t) * (npad / kJP));
+    const size_t npairs = (size_t)(npad / kJacobiPair);
+    b += 3 * align_up(sizeof(double) * (size_t)npad * npad);
+    b += 2 * align_up(sizeof(double) * 2 * npairs * kJacobiPair * kJacobiPair);
+    b += align_up(sizeof(int32_t) * 2 * npairs);
     b += align_up(sizeof(double) * npad);
     return b;
 }
@@ -476,10 +511,13 @@ ranky_status ranky_eigh(int32_t n, const double *G, double *lambda, double *Q, i
     };
     w.scal = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * kScCount));
     w.sdbl = reinterpret_cast<double *>(take(sizeof(double) * kSdCount));
+    const size_t npairs = (size_t)(npad / kJacobiPair);
     w.G = reinterpret_cast<double *>(take(sizeof(double) * (size_t)npad * npad));
+    w.G2 = reinterpret_cast<double *>(take(sizeof(double) * (size_t)npad * npad));
     w.W = reinterpret_cast<double *>(take(sizeof(double) * (size_t)npad * npad));
-    w.J = reinterpret_cast<double *>(take(sizeof(double) * (size_t)(npad / kJP) * kJP * kJP));
-    w.jflag = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (npad / kJP)));
+    w.J = reinterpret_cast<double *>(take(sizeof(double) * 2 * npairs * kJacobiPair * kJacobiPair));
+    w.S = reinterpret_cast<double *>(take(sizeof(double) * 2 * npairs * kJacobiPair * kJacobiPair));
+    w.jflag = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * 2 * npairs));
     w.lam = reinterpret_cast<double *>(take(sizeof(double) * npad));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     ranky_ctx tmp;
