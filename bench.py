@@ -35,6 +35,34 @@ def spmm_bytes(nnz, N, k, M, val_bytes, out_bytes):
     return nnz * (4 + val_bytes) + 4 * (N + 1) + N * k * out_bytes + M * k * 8
 
 
+def time_path(ranky, torch, np, dA, A, k, D, prec, steps, warmup):
+    """Wall time per ranky_svd call (host clock around synchronised calls) and the
+    per-phase times from the library's HIP events on the same stream."""
+    vdt = torch.float64 if prec == "fp64" else torch.float32
+    kw = dict(n_blocks=D, gram_prec=prec, v_dtype=vdt)
+    opts = ranky.make_opts(**kw)
+    ws = torch.empty(ranky.workspace_bytes(A.M, A.N, A.nnz, k, opts), dtype=torch.uint8, device="cuda:0")
+    out = ranky.SVDResult(torch.empty(k, dtype=torch.float64, device="cuda:0"),
+                          torch.empty((A.M, k), dtype=torch.float64, device="cuda:0"),
+                          torch.empty((A.N, k), dtype=vdt, device="cuda:0"), {})
+    ctx = ranky.context(0)
+    for _ in range(warmup):
+        ranky.svd(dA, k, 0.0, ctx=ctx, out=out, workspace=ws, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ranky.svd(dA, k, 0.0, ctx=ctx, out=out, workspace=ws, **kw)
+    torch.cuda.synchronize()
+    ms_step = 1e3 * (time.perf_counter() - t0) / steps
+    phases = np.zeros(8)
+    for _ in range(steps):
+        r = ranky.svd(dA, k, 0.0, ctx=ctx, out=out, workspace=ws, timing=True, **kw)
+        phases += np.array(r.info["ms"])
+    phases /= steps
+    names = ["occupancy", "transpose", "gram", "eigensolve", "select", "refine", "backproject", "total"]
+    return ms_step, dict(zip(names, phases.tolist())), r.info, out.sigma.cpu().numpy(), vdt
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -48,35 +76,14 @@ def main():
     A = gen.cfg2(seed=args.seed)
     k, D = 128, 64
     dA = ranky.to_device(A, "cuda:0")
-    ctx = ranky.context(0)
-    vdt = torch.float64 if args.prec == "fp64" else torch.float32
-    kw = dict(n_blocks=D, gram_prec=args.prec, v_dtype=vdt)
-    opts = ranky.make_opts(**kw)
-    ws = torch.empty(ranky.workspace_bytes(A.M, A.N, A.nnz, k, opts), dtype=torch.uint8, device="cuda:0")
-    out = ranky.SVDResult(torch.empty(k, dtype=torch.float64, device="cuda:0"),
-                          torch.empty((A.M, k), dtype=torch.float64, device="cuda:0"),
-                          torch.empty((A.N, k), dtype=vdt, device="cuda:0"), {})
-    for _ in range(args.warmup):
-        ranky.svd(dA, k, 0.0, ctx=ctx, out=out, workspace=ws, **kw)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ranky.svd(dA, k, 0.0, ctx=ctx, out=out, workspace=ws, **kw)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_step = 1e3 * elapsed / args.steps
+    ms_step, phases, info, sig64, vdt = time_path(ranky, torch, np, dA, A, k, D, args.prec, args.steps, args.warmup)
+    other = "fp32" if args.prec == "fp64" else "fp64"
+    ms2, phases2, info2, sig2, vdt2 = time_path(ranky, torch, np, dA, A, k, D, other, args.steps, args.warmup)
 
-    # per-phase times from HIP events recorded by the library on the same stream
-    phases = np.zeros(8)
-    for _ in range(args.steps):
-        r = ranky.svd(dA, k, 0.0, ctx=ctx, out=out, workspace=ws, timing=True, **kw)
-        phases += np.array(r.info["ms"])
-    phases /= args.steps
-    info = r.info
     val_bytes = 8 if A.values.dtype == np.float64 else 4
     out_bytes = 8 if vdt == torch.float64 else 4
     sb = spmm_bytes(A.nnz, A.N, k, A.M, val_bytes, out_bytes)
-    spmm_ms = float(phases[6])
+    spmm_ms = float(phases["backproject"])
     achieved = sb / (spmm_ms * 1e-3) / 1e9
 
     line = {
@@ -96,10 +103,12 @@ def main():
                                f"gram={args.prec}", "M": A.M, "N": A.N, "nnz": A.nnz, "n_blocks": D, "k": k},
         "rank": info["rank"],
         "sweeps": info["sweeps"],
-        "phase_ms": {"occupancy": phases[0], "transpose": phases[1], "gram": phases[2], "eigensolve": phases[3],
-                     "select": phases[4], "refine": phases[5], "backproject": phases[6], "total": phases[7]},
+        "phase_ms": phases,
         "roofline": {"kernel": "k_backproject (V = A^T U Sigma^-1)", "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": sb},
+        other + "_path": {"value": A.nnz / (ms2 * 1e-3), "ms_per_step": ms2, "phase_ms": phases2,
+                          "rank": info2["rank"], "sweeps": info2["sweeps"]},
     }
 
     if not args.no_cpu_baseline:
@@ -109,12 +118,12 @@ def main():
         t0 = time.perf_counter()
         ref = oracle.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=k, method="gram", want_v=True)
         t_cpu = time.perf_counter() - t0
-        s = out.sigma.cpu().numpy()
-        err = float(np.max(np.abs(s[:ref.rank] - ref.sigma[:ref.rank]) / ref.sigma[:ref.rank]))
+        r = ref.rank
         line["cpu_baseline"] = {"value": A.nnz / t_cpu, "unit": "nnz/s", "cores": cores, "kind": "oracle",
                                 "sample": "the whole workload once: FP64 sparse Gram + cyclic Jacobi + V (Gram route)",
                                 "seconds": t_cpu}
-        line["sigma_rel_err_vs_oracle"] = err
+        line["sigma_rel_err_vs_oracle"] = float(np.max(np.abs(sig64[:r] - ref.sigma[:r]) / ref.sigma[:r]))
+        line[other + "_path"]["sigma_rel_err_vs_oracle"] = float(np.max(np.abs(sig2[:r] - ref.sigma[:r]) / ref.sigma[:r]))
     print(json.dumps(line), flush=True)
 
 

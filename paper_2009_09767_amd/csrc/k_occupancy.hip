@@ -169,11 +169,13 @@ __global__ __launch_bounds__(256) void k_occ_offsets(int32_t *__restrict__ hist,
 // lanes publish themselves in a per-row 64-bit mask (bitwise OR commutes, so the
 // mask does not depend on timing), read it back and count.  The entry's slot is
 // the row's running offset plus that rank; the lowest lane then advances the offset.
-// csr_k[slot] = CSC position of the entry, csr_end[slot] = end of its column.
+// csr_k[slot] = CSC position of the entry, csr_end[slot] = end of its column,
+// csr_col[slot] = its column.
 __global__ __launch_bounds__(64) void k_transpose(const int32_t *__restrict__ colptr,
                                                   const int32_t *__restrict__ rowidx, int32_t M, int64_t N,
                                                   int32_t D, int32_t cpb, const int32_t *__restrict__ offs,
-                                                  int32_t *__restrict__ csr_k, int32_t *__restrict__ csr_end) {
+                                                  int32_t *__restrict__ csr_k, int32_t *__restrict__ csr_end,
+                                                  int32_t *__restrict__ csr_col) {
     extern __shared__ uint64_t lds_mask[];
     int32_t *ctr = reinterpret_cast<int32_t *>(lds_mask + M);
     const int64_t c = blockIdx.x;
@@ -202,6 +204,7 @@ __global__ __launch_bounds__(64) void k_transpose(const int32_t *__restrict__ co
             const int32_t slot = ctr[r] + __popcll(lds_mask[r] & lower);
             csr_k[slot] = e;
             csr_end[slot] = e1;
+            csr_col[slot] = (int32_t)j;
         }
         __syncthreads();
         for (int32_t e = e0; e < e1; ++e) {
@@ -254,10 +257,10 @@ void launch_row_offsets(int32_t *hist, const int32_t *rowptr, int32_t M, int64_t
 }
 
 void launch_transpose(const CscView &A, int32_t M, int64_t N, int32_t D, int32_t cpb, int64_t nchunks,
-                      const int32_t *offs, int32_t *csr_k, int32_t *csr_end, hipStream_t s) {
+                      const int32_t *offs, int32_t *csr_k, int32_t *csr_end, int32_t *csr_col, hipStream_t s) {
     const size_t lds = (sizeof(uint64_t) + sizeof(int32_t)) * (size_t)M;
     hipLaunchKernelGGL(k_transpose, dim3((unsigned)nchunks), dim3(64), lds, s, A.colptr, A.rowidx, M, N, D, cpb, offs,
-                       csr_k, csr_end);
+                       csr_k, csr_end, csr_col);
 }
 
 size_t transpose_lds_bytes(int32_t M) { return (sizeof(uint64_t) + sizeof(int32_t)) * (size_t)M; }

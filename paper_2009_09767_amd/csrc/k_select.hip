@@ -14,7 +14,7 @@ namespace ranky {
 // One workgroup of 1024 threads: bitonic sort of (lambda desc, index asc) over the
 // n eigenvalues, then sigma, tau and the rank.  LDS holds npow2 keys and indices.
 __global__ __launch_bounds__(1024) void k_select_sort(const double *__restrict__ lam, int32_t n, int32_t npow2,
-                                                      int32_t k, double tol, double u_gram,
+                                                      int32_t k, int32_t n_tau, double tol, double u_gram,
                                                       int32_t *__restrict__ perm, double *__restrict__ sigma,
                                                       int32_t *__restrict__ scal, double *__restrict__ sdbl) {
     extern __shared__ double lds_key[];
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(1024) void k_select_sort(const double *__restrict__
         }
     }
     const double s1 = n > 0 ? sqrt(fmax(lds_key[0], 0.0)) : 0.0;
-    const double tau = fmax(tol, sqrt((double)n * u_gram)) * s1;
+    const double tau = fmax(tol, sqrt((double)n_tau * u_gram)) * s1;
     __shared__ int32_t cnt[1024];
     int32_t c = 0;
     for (int32_t i = threadIdx.x; i < n; i += blockDim.x) c += sqrt(fmax(lds_key[i], 0.0)) > tau;
@@ -163,13 +163,13 @@ __global__ __launch_bounds__(256) void k_backproject(const int32_t *__restrict__
 
 // ---------------------------------------------------------------------------
 
-void launch_select(const double *lam, int32_t n, int32_t k, double tol, double u_gram, int32_t *perm, double *sigma,
-                   int32_t *scal, double *sdbl, hipStream_t s) {
+void launch_select(const double *lam, int32_t n, int32_t k, int32_t n_tau, double tol, double u_gram, int32_t *perm,
+                   double *sigma, int32_t *scal, double *sdbl, hipStream_t s) {
     int32_t npow2 = 1;
     while (npow2 < n) npow2 <<= 1;
     const size_t lds = (sizeof(double) + sizeof(int32_t)) * (size_t)npow2;
-    hipLaunchKernelGGL(k_select_sort, dim3(1), dim3(1024), lds, s, lam, n, npow2, k, tol, u_gram, perm, sigma, scal,
-                       sdbl);
+    hipLaunchKernelGGL(k_select_sort, dim3(1), dim3(1024), lds, s, lam, n, npow2, k, n_tau, tol, u_gram, perm, sigma,
+                       scal, sdbl);
 }
 
 void launch_gather_u(const double *W, int64_t ld, int32_t n, int32_t M, int32_t k, const int32_t *perm,

@@ -25,7 +25,7 @@ void launch_occupancy(const CscView &A, int32_t M, int64_t N, int32_t D, int32_t
                       int32_t *scal, hipStream_t s);
 void launch_row_offsets(int32_t *hist, const int32_t *rowptr, int32_t M, int64_t nchunks, hipStream_t s);
 void launch_transpose(const CscView &A, int32_t M, int64_t N, int32_t D, int32_t cpb, int64_t nchunks,
-                      const int32_t *offs, int32_t *csr_k, int32_t *csr_end, hipStream_t s);
+                      const int32_t *offs, int32_t *csr_k, int32_t *csr_end, int32_t *csr_col, hipStream_t s);
 size_t transpose_lds_bytes(int32_t M);
 hipError_t occupancy_set_attributes(int32_t maxM);
 
@@ -64,12 +64,22 @@ void launch_jacobi_check(const double *G, int64_t ld, int32_t n, double tol, con
 void launch_jacobi_diag(const double *G, int64_t ld, int32_t n, double *lam, hipStream_t s);
 
 // select / gather / back-projection (k_select.hip)
-void launch_select(const double *lam, int32_t n, int32_t k, double tol, double u_gram, int32_t *perm, double *sigma,
-                   int32_t *scal, double *sdbl, hipStream_t s);
+void launch_select(const double *lam, int32_t n, int32_t k, int32_t n_tau, double tol, double u_gram, int32_t *perm,
+                   double *sigma, int32_t *scal, double *sdbl, hipStream_t s);
 void launch_gather_u(const double *W, int64_t ld, int32_t n, int32_t M, int32_t k, const int32_t *perm,
                      const int32_t *m2r, const int32_t *empty, double *U, hipStream_t s);
 void launch_backproject(const CscView &A, int64_t N, int32_t k, const double *U, const double *sigma,
                         const int32_t *rank, void *V, int32_t v_dtype, int32_t cu_count, hipStream_t s);
 hipError_t select_set_attributes();
+
+// Rayleigh-Ritz refinement with the exact operator (k_refine.hip)
+void launch_rr_z(const CscView &A, int64_t N, int32_t k, const double *U0, double *Z, int32_t cu_count, hipStream_t s);
+int64_t rr_max_segments(int32_t M, int64_t nnz);
+void launch_rr_rows(const CscView &A, const int32_t *rownnz, const int32_t *rowptr, int32_t M, int64_t nnz, int32_t k,
+                    const int32_t *csr_k, const int32_t *csr_col, const double *Z, int32_t *seg_ptr, double *part,
+                    double *Y, hipStream_t s);
+void launch_rr_h(const double *U0, const double *Y, int32_t M, int32_t k, int32_t npad, double *H, hipStream_t s);
+void launch_rr_apply(const double *U0, const double *Q, int64_t ldq, const int32_t *perm, int32_t M, int32_t k,
+                     double *U, hipStream_t s);
 
 }  // namespace ranky

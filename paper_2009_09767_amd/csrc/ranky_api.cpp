@@ -56,10 +56,11 @@ struct Plan {
     size_t o_scal = 0, o_sdbl = 0, o_hist = 0, o_rownnz = 0, o_rowptr = 0, o_m2r = 0, o_r2m = 0, o_empty = 0;
     size_t o_lonely = 0, o_single = 0, o_csrk = 0, o_csrend = 0, o_G = 0, o_G2 = 0, o_W = 0, o_J = 0, o_S = 0,
            o_jflag = 0;
-    size_t o_lam = 0, o_perm = 0, total = 0;
+    size_t o_lam = 0, o_perm = 0, o_csrcol = 0, o_U0 = 0, o_Z = 0, o_part = 0, o_Y = 0, o_seg = 0, total = 0;
+    bool refine = false;
 };
 
-Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool with_solver) {
+Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool with_solver, bool refine = false) {
     Plan p;
     p.M = M;
     p.N = N;
@@ -89,6 +90,7 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool wit
     p.o_single = take(sizeof(int32_t) * D);
     p.o_csrk = take(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
     p.o_csrend = take(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    p.o_csrcol = take(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
     p.o_G = take(sizeof(double) * (size_t)p.npad * p.npad);
     if (with_solver) {
         const size_t npairs = (size_t)(p.npad / kJacobiPair);
@@ -99,14 +101,23 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool wit
         p.o_jflag = take(sizeof(int32_t) * 2 * npairs);
         p.o_lam = take(sizeof(double) * p.npad);
         p.o_perm = take(sizeof(int32_t) * p.npad);
+        if (refine) {
+            p.refine = true;
+            p.o_U0 = take(sizeof(double) * (size_t)M * k);
+            p.o_Z = take(sizeof(double) * (size_t)N * k);
+            p.o_part = take(sizeof(double) * (size_t)rr_max_segments(M, nnz) * k);
+            p.o_Y = take(sizeof(double) * (size_t)M * k);
+            p.o_seg = take(sizeof(int32_t) * (size_t)(M + 1));
+        }
     }
     p.total = off;
     return p;
 }
 
 struct Ptrs {
-    int32_t *scal, *hist, *rownnz, *rowptr, *m2r, *r2m, *empty, *lonely, *single, *csrk, *csrend, *jflag, *perm;
-    double *sdbl, *G, *G2, *W, *J, *S, *lam;
+    int32_t *scal, *hist, *rownnz, *rowptr, *m2r, *r2m, *empty, *lonely, *single, *csrk, *csrend, *csrcol, *jflag,
+        *perm, *seg;
+    double *sdbl, *G, *G2, *W, *J, *S, *lam, *U0, *Z, *part, *Y;
 };
 
 Ptrs carve(const Plan &p, void *ws) {
@@ -124,6 +135,12 @@ Ptrs carve(const Plan &p, void *ws) {
     q.single = reinterpret_cast<int32_t *>(b + p.o_single);
     q.csrk = reinterpret_cast<int32_t *>(b + p.o_csrk);
     q.csrend = reinterpret_cast<int32_t *>(b + p.o_csrend);
+    q.csrcol = reinterpret_cast<int32_t *>(b + p.o_csrcol);
+    q.U0 = p.refine ? reinterpret_cast<double *>(b + p.o_U0) : nullptr;
+    q.Z = p.refine ? reinterpret_cast<double *>(b + p.o_Z) : nullptr;
+    q.part = p.refine ? reinterpret_cast<double *>(b + p.o_part) : nullptr;
+    q.Y = p.refine ? reinterpret_cast<double *>(b + p.o_Y) : nullptr;
+    q.seg = p.refine ? reinterpret_cast<int32_t *>(b + p.o_seg) : nullptr;
     q.G = reinterpret_cast<double *>(b + p.o_G);
     q.G2 = reinterpret_cast<double *>(b + p.o_G2);
     q.W = reinterpret_cast<double *>(b + p.o_W);
@@ -142,6 +159,8 @@ int32_t default_blocks(int64_t N) {
     return (int32_t)d;
 }
 
+constexpr int32_t kMaxRefineK = 1024;
+
 ranky_opts resolved(const ranky_opts *in, int64_t N) {
     ranky_opts o;
     ranky_default_opts(&o);
@@ -150,6 +169,8 @@ ranky_opts resolved(const ranky_opts *in, int64_t N) {
     if (o.max_sweeps <= 0) o.max_sweeps = kDefaultSweeps;
     return o;
 }
+
+bool wants_refine(const ranky_opts &o, int32_t k) { return o.refine > 0 && k <= kMaxRefineK; }
 
 ranky_status check_csc_args(const ranky_csc *A, int32_t M, int64_t N) {
     if (!A) return fail(RANKY_E_INVALID, "A is NULL");
@@ -317,7 +338,7 @@ size_t ranky_workspace_bytes(int32_t M, int64_t N, int64_t nnz, int32_t k, const
     if (M < 1 || N < 1 || k < 1 || k > M || M > kMaxM || nnz < 0) return 0;
     const ranky_opts o = resolved(opts, N);
     if (o.n_blocks < 1 || o.n_blocks > N) return 0;
-    return make_plan(M, N, nnz, k, o.n_blocks, true).total;
+    return make_plan(M, N, nnz, k, o.n_blocks, true, wants_refine(o, k)).total;
 }
 
 size_t ranky_step_workspace_bytes(int32_t M, int64_t N, int64_t nnz, int32_t D) {
@@ -344,7 +365,10 @@ ranky_status ranky_svd(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N,
     if (o.gram_prec != RANKY_PREC_FP64 && o.gram_prec != RANKY_PREC_FP32)
         return finish(fail(RANKY_E_INVALID, "gram_prec=%d", o.gram_prec));
     if (o.v_dtype != RANKY_F32 && o.v_dtype != RANKY_F64) return finish(fail(RANKY_E_INVALID, "v_dtype=%d", o.v_dtype));
-    const Plan p = make_plan(M, N, A->nnz, k, o.n_blocks, true);
+    if (o.refine < 0 || o.refine > 1) return finish(fail(RANKY_E_INVALID, "refine=%d (0 or 1)", o.refine));
+    if (o.refine && k > kMaxRefineK) return finish(fail(RANKY_E_INVALID, "refine needs k <= %d", kMaxRefineK));
+    const bool refine = wants_refine(o, k);
+    const Plan p = make_plan(M, N, A->nnz, k, o.n_blocks, true, refine);
     if (!workspace || ws_bytes < p.total)
         return finish(fail(RANKY_E_NOMEM, "workspace %zu bytes < %zu needed", ws_bytes, p.total));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -362,7 +386,7 @@ ranky_status ranky_svd(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N,
     const int32_t npad = round_up64(n > 0 ? n : 1);
     if (n > 0) {
         launch_row_offsets(w.hist, w.rowptr, M, p.nchunks, s);
-        launch_transpose(Av, M, N, p.D, p.cpb, p.nchunks, w.hist, w.csrk, w.csrend, s);
+        launch_transpose(Av, M, N, p.D, p.cpb, p.nchunks, w.hist, w.csrk, w.csrend, w.csrcol, s);
         if (timing) hipEventRecord(ctx->ev[2], s);
         launch_gram(Av, M, n, npad, npad, w.rowptr, w.r2m, w.csrk, w.csrend, w.G, o.gram_prec, ctx->lds_limit, s);
         if (hipGetLastError() != hipSuccess) return finish(fail(RANKY_E_DEVICE, "Gram launch failed"));
@@ -374,10 +398,29 @@ ranky_status ranky_svd(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N,
         hipEventRecord(ctx->ev[3], s);
     }
     if (timing) hipEventRecord(ctx->ev[4], s);
-    const double u_gram = (o.gram_prec == RANKY_PREC_FP64) ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
-    launch_select(w.lam, n, k, tol, u_gram, w.perm, sigma, w.scal, w.sdbl, s);
-    launch_gather_u(w.W, npad, n, M, k, w.perm, w.m2r, w.empty, U, s);
+    const double u64 = std::ldexp(1.0, -53);
+    const double u_gram = (o.gram_prec == RANKY_PREC_FP64 || refine) ? u64 : std::ldexp(1.0, -24);
+    launch_select(w.lam, n, k, n, tol, u_gram, w.perm, sigma, w.scal, w.sdbl, s);
+    launch_gather_u(w.W, npad, n, M, k, w.perm, w.m2r, w.empty, refine ? w.U0 : U, s);
     if (timing) hipEventRecord(ctx->ev[5], s);
+    if (refine) {
+        // Rayleigh-Ritz with the exact operator: H = U0^T (A A^T) U0 in FP64
+        if (n > 0) {
+            launch_rr_z(Av, N, k, w.U0, w.Z, ctx->cu_count, s);
+            launch_rr_rows(Av, w.rownnz, w.rowptr, M, A->nnz, k, w.csrk, w.csrcol, w.Z, w.seg, w.part, w.Y, s);
+        } else {
+            launch_fill_f64(w.Y, (int64_t)M * k, 0.0, s);
+        }
+        const int32_t kpad = round_up64(k);
+        launch_rr_h(w.U0, w.Y, M, k, kpad, w.G, s);
+        if (hipGetLastError() != hipSuccess) return finish(fail(RANKY_E_DEVICE, "refine launch failed"));
+        int32_t sw2 = 0;
+        st = run_jacobi(ctx, w, k, o.max_sweeps, s, &sw2);
+        if (st) return finish(st);
+        sweeps += sw2;
+        launch_select(w.lam, k, k, n, tol, u64, w.perm, sigma, w.scal, w.sdbl, s);
+        launch_rr_apply(w.U0, w.W, kpad, w.perm, M, k, U, s);
+    }
     if (timing) hipEventRecord(ctx->ev[6], s);
     launch_backproject(Av, N, k, U, sigma, w.scal + kScRank, V, o.v_dtype, ctx->cu_count, s);
     if (timing) hipEventRecord(ctx->ev[7], s);
@@ -469,7 +512,7 @@ ranky_status ranky_gram(const ranky_csc *A, int32_t M, int64_t N, int32_t prec, 
     const int32_t npad = round_up64(n > 0 ? n : 1);
     if (n > 0) {
         launch_row_offsets(w.hist, w.rowptr, M, p.nchunks, s);
-        launch_transpose(Av, M, N, p.D, p.cpb, p.nchunks, w.hist, w.csrk, w.csrend, s);
+        launch_transpose(Av, M, N, p.D, p.cpb, p.nchunks, w.hist, w.csrk, w.csrend, w.csrcol, s);
         launch_gram(Av, M, n, npad, npad, w.rowptr, w.r2m, w.csrk, w.csrend, w.G, prec, lds, s);
         launch_scatter_gram(w.G, npad, w.m2r, M, G, s);
     } else {

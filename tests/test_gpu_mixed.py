@@ -1,0 +1,98 @@
+"""Mixed-precision path (FP32 Gram accumulation, FP64 eigensolve, one FP64 Rayleigh-Ritz step
+with the exact operator, FP32 V) against the FP64 CPU oracle.  Bar: relative sigma error
+<= 1e-6; vectors sin(angle) <= min(1, 1e-6 / relgap); exact rank; zeros beyond the rank."""
+import numpy as np
+import pytest
+
+from paper_2009_09767_amd import gen
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_09767_amd import ranky
+
+    ranky.lib()
+    return ranky
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+
+    oracle._load()
+    return oracle
+
+
+CASES = {
+    "cfg2_small_f32": lambda: gen.cfg2_small(dtype=np.float32),
+    "cfg3_full_rank": lambda: [A for A in gen.cfg3(count=6, deficient_frac=0.5) if not A.meta["zeroed_rows"].size][0],
+    "cfg3_half_rows_zero": lambda: [A for A in gen.cfg3(count=6, deficient_frac=0.5) if A.meta["zeroed_rows"].size][0],
+    "cfg1_f64": lambda: gen.cfg1(),
+}
+
+
+def check(A, got, ref, bar):
+    import torch
+
+    sg, Ug = got.sigma.cpu().numpy(), got.U.cpu().numpy()
+    Vg = got.V.to(torch.float64).cpu().numpy()
+    r = ref.rank
+    assert got.info["rank"] == r
+    err = H.rel_sigma_err(sg, ref.sigma, r)
+    assert err <= bar, err
+    assert np.all(sg[r:] == 0.0)
+    scaled, _ = H.vector_errors(Ug[:, :r], ref.U[:, :r], ref.sigma, r)
+    assert scaled <= bar
+    scaled_v, _ = H.vector_errors(Vg[:, :r], ref.V[:, :r], ref.sigma, r)
+    assert scaled_v <= max(bar, 2.0 ** -22)   # V is stored in FP32
+    assert np.all(Vg[:, r:] == 0.0)
+    assert H.canonical_sign_ok(Ug)
+    return err
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_mixed_refined_against_fp64_oracle(R, orc, name):
+    import torch
+
+    A = CASES[name]()
+    k = min(A.meta.get("k", A.M), A.M, 64)
+    ref = orc.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=k, method="whole_qr" if A.M > 64 else "whole")
+    got = R.svd(R.to_device(A), k, 0.0, n_blocks=min(A.meta.get("D", 8), A.N), gram_prec="fp32", refine=1,
+                v_dtype=torch.float32)
+    err = check(A, got, ref, 1e-6)
+    # the Ritz values come from the exact operator in FP64: far inside the mixed bar
+    assert err <= 1e-10
+
+
+def test_mixed_without_refinement_meets_the_mixed_bar(R, orc):
+    import torch
+
+    A = CASES["cfg3_full_rank"]()
+    k = 32
+    ref = orc.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=k, method="whole_qr")
+    got = R.svd(R.to_device(A), k, 0.0, n_blocks=8, gram_prec="fp32", refine=0, v_dtype=torch.float32)
+    check(A, got, ref, 1e-6)
+
+
+def test_mixed_is_deterministic(R):
+    import torch
+
+    A = gen.cfg2_small(dtype=np.float32)
+    dA = R.to_device(A)
+    a = R.svd(dA, 32, 0.0, n_blocks=8, gram_prec="fp32", refine=1, v_dtype=torch.float32)
+    b = R.svd(dA, 32, 0.0, n_blocks=8, gram_prec="fp32", refine=1, v_dtype=torch.float32)
+    assert torch.equal(a.sigma, b.sigma) and torch.equal(a.U, b.U) and torch.equal(a.V, b.V)
+
+
+def test_refine_rejects_large_k(R):
+    A = gen.random_sparse(1100, 3000, 0.002, seed=5, dtype=np.float32)
+    with pytest.raises(R.RankyError) as e:
+        R.svd(R.to_device(A), 1100, 0.0, gram_prec="fp32", refine=1)
+    assert e.value.status == R.E_INVALID
