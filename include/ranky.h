@@ -86,7 +86,7 @@ typedef struct {
     int32_t validate;   /* 1 = check the CSC contract and finiteness on the device (default 1) */
     int32_t v_dtype;    /* ranky_dtype of the output V (default F64) */
     int32_t timing;     /* 1 = fill ranky_info.ms with per-phase times (adds event records) */
-    int32_t reserved;
+    int32_t reserved;   /* ranky_batch: 1 = replay the Jacobi sweep as a captured HIP graph */
 } ranky_opts;
 
 typedef struct {
@@ -161,6 +161,41 @@ size_t ranky_workspace_bytes(int32_t M, int64_t N, int64_t nnz, int32_t k, const
 ranky_status ranky_svd(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N, int32_t k, double tol,
                        const ranky_opts *opts, void *workspace, size_t ws_bytes, double *sigma, double *U,
                        void *V, ranky_info *info, ranky_stream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* Batches of independent matrices                                            */
+/* ------------------------------------------------------------------------- */
+
+/* One matrix of a batch: its CSC, sizes and caller-allocated outputs (device),
+ * laid out exactly as for ranky_svd. */
+typedef struct {
+    ranky_csc A;
+    int64_t N;
+    int32_t M;
+    int32_t k;        /* 1 <= k <= M */
+    int32_t n_blocks; /* D for this matrix; 0 selects ceil(N / 16384) */
+    int32_t reserved;
+    double *sigma;    /* [k] */
+    double *U;        /* [M x k] row-major */
+    void *V;          /* [N x k] row-major, opts->v_dtype */
+} ranky_batch_item;
+
+/* Bytes of workspace ranky_batch needs (0 if an item is invalid).  items: host. */
+size_t ranky_batch_workspace_bytes(int32_t count, const ranky_batch_item *items, const ranky_opts *opts);
+
+/* The whole path of ranky_svd for `count` independent matrices of different sizes,
+ * run together: every phase is one launch whose workgroups are spread over all
+ * matrices (a per-matrix descriptor table maps workgroups to matrices), and the
+ * Jacobi sweeps of all matrices advance in lock-step, each matrix dropping out when
+ * its own convergence test passes.  With opts->reserved = 1 the sweep is captured
+ * once as a HIP graph and replayed.  Blocking.
+ *   items [count] host; infos [count] host (may be NULL): per-matrix ranky_info.
+ * The return value is RANKY_OK only if every matrix succeeded; a matrix whose CSC
+ * breaks the contract gets its own status in infos[i].status and does not stop the
+ * others.  opts->refine must be 0 (Rayleigh-Ritz is per matrix: use ranky_svd). */
+ranky_status ranky_batch(ranky_ctx *ctx, int32_t count, const ranky_batch_item *items, double tol,
+                         const ranky_opts *opts, void *workspace, size_t ws_bytes, ranky_info *infos,
+                         ranky_stream_t stream);
 
 /* ------------------------------------------------------------------------- */
 /* Individual steps (the same kernels ranky_svd runs), for composition and    */

@@ -1,0 +1,53 @@
+// batch.hpp -- per-matrix descriptors and the workgroup -> matrix mapping shared by
+// every kernel.  A launch covers a batch of independent matrices: workgroups
+// [wp[i], wp[i+1]) belong to matrix i, so uneven matrices share one grid.  The
+// single-matrix entry point is the same code with a batch of one.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ranky {
+
+struct MatDesc {
+    // input (caller-owned)
+    const int32_t *colptr;
+    const int32_t *rowidx;
+    const void *values;
+    int64_t nnz;
+    int64_t N;
+    int64_t nchunks;
+    int32_t M, k, D, cpb;
+    int32_t dtype, v_dtype;
+    int32_t n, npad;          // non-empty rows and the eigensolver order (set after the scan)
+    int32_t prec;             // Gram accumulation: 0 FP64, 1 FP32
+    int32_t validate;
+    int32_t n_tau;            // row count entering the threshold sqrt(n_tau u_gram)
+    int32_t pad0;
+    double tol;               // rank threshold option
+    double u_gram;            // unit roundoff of the Gram entries for the threshold
+    // workspace (library-carved from caller memory)
+    int32_t *scal, *hist, *rownnz, *rowptr, *m2r, *r2m, *empty, *lonely, *single;
+    int32_t *csrk, *csrend, *csrcol, *jflag, *perm;
+    int32_t *cnt;             // optional [D x M] occupancy output (step call only)
+    int32_t *jstate;          // Jacobi state: [0] sweeps done, [1] active this sweep, [2] not converged
+    double *sdbl, *G, *G2, *W, *J, *S, *lam;
+    // outputs (caller-owned)
+    double *sigma, *U;
+    void *V;
+};
+
+enum : int32_t { kJsSweeps = 0, kJsActive = 1, kJsNotConv = 2, kJsCount = 4 };
+
+// Matrix owning workgroup b: the last i with wp[i] <= b (wp has count + 1 entries).
+__device__ __forceinline__ int find_mat(const int32_t *__restrict__ wp, int count, int b) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (wp[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+}  // namespace ranky

@@ -17,6 +17,7 @@
 // The diagonal a_pj^2 terms are summed per lane and reduced by a fixed shuffle tree.
 // G is written in compacted coordinates (empty rows removed), symmetric, padded
 // with zeros up to npad; every entry is written exactly once.
+#include "batch.hpp"
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -29,14 +30,15 @@ __device__ __forceinline__ Acc wave_sum(Acc v) {
 }
 
 template <typename TV, typename Acc>
-__global__ __launch_bounds__(512) void k_gram_rows(const int32_t *__restrict__ rowidx, const TV *__restrict__ vals,
-                                                   int32_t M, int32_t n, int32_t npad, int64_t ld,
-                                                   const int32_t *__restrict__ rowptr,
-                                                   const int32_t *__restrict__ r2m,
-                                                   const int32_t *__restrict__ csr_k,
-                                                   const int32_t *__restrict__ csr_end, double *__restrict__ G) {
-    extern __shared__ double lds_raw[];
-    const int32_t i = blockIdx.x;
+__device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals, int32_t i, double *lds_raw) {
+    const int32_t M = dsc.M, n = dsc.n, npad = dsc.npad;
+    const int64_t ld = npad;
+    const int32_t *__restrict__ rowidx = dsc.rowidx;
+    const int32_t *__restrict__ rowptr = dsc.rowptr;
+    const int32_t *__restrict__ r2m = dsc.r2m;
+    const int32_t *__restrict__ csr_k = dsc.csrk;
+    const int32_t *__restrict__ csr_end = dsc.csrend;
+    double *__restrict__ G = dsc.G;
     const int nw = blockDim.x >> 6;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -50,6 +52,7 @@ __global__ __launch_bounds__(512) void k_gram_rows(const int32_t *__restrict__ r
     Acc *acc = reinterpret_cast<Acc *>(lds_raw);                  // nw x M
     int32_t *tag = reinterpret_cast<int32_t *>(acc + (size_t)nw * M);  // nw x M
     __shared__ Acc dsum[16];
+    __syncthreads();
     for (int32_t t = threadIdx.x; t < nw * M; t += blockDim.x) {
         acc[t] = Acc(0);
         tag[t] = 64;
@@ -122,6 +125,24 @@ __global__ __launch_bounds__(512) void k_gram_rows(const int32_t *__restrict__ r
     }
 }
 
+
+__global__ __launch_bounds__(512) void k_gram_rows(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
+                                                   int count) {
+    extern __shared__ double lds_raw[];
+    const int mat = find_mat(wp, count, blockIdx.x);
+    const MatDesc &d = descs[mat];
+    const int32_t i = blockIdx.x - wp[mat];
+    if (d.dtype == 1) {
+        const double *v = static_cast<const double *>(d.values);
+        if (d.prec == 0) gram_row<double, double>(d, v, i, lds_raw);
+        else gram_row<double, float>(d, v, i, lds_raw);
+    } else {
+        const float *v = static_cast<const float *>(d.values);
+        if (d.prec == 0) gram_row<float, double>(d, v, i, lds_raw);
+        else gram_row<float, float>(d, v, i, lds_raw);
+    }
+}
+
 int gram_waves(int32_t M, int32_t acc_bytes, size_t lds_limit) {
     // LDS per wave: one accumulator row and one tag row.
     const size_t per_wave = (size_t)M * (acc_bytes + sizeof(int32_t));
@@ -131,42 +152,21 @@ int gram_waves(int32_t M, int32_t acc_bytes, size_t lds_limit) {
     return w;
 }
 
-void launch_gram(const CscView &A, int32_t M, int32_t n, int32_t npad, int64_t ld, const int32_t *rowptr,
-                 const int32_t *r2m, const int32_t *csr_k, const int32_t *csr_end, double *G, int32_t prec,
-                 size_t lds_limit, hipStream_t s) {
-    const int acc_bytes = prec == 0 ? 8 : 4;
-    const int nw = gram_waves(M, acc_bytes, lds_limit);
-    const size_t lds = (size_t)nw * M * (acc_bytes + sizeof(int32_t));
-    const dim3 grid((unsigned)npad), block((unsigned)(64 * nw));
-    if (A.dtype == 1) {
-        const double *v = static_cast<const double *>(A.values);
-        if (prec == 0)
-            hipLaunchKernelGGL((k_gram_rows<double, double>), grid, block, lds, s, A.rowidx, v, M, n, npad, ld, rowptr,
-                               r2m, csr_k, csr_end, G);
-        else
-            hipLaunchKernelGGL((k_gram_rows<double, float>), grid, block, lds, s, A.rowidx, v, M, n, npad, ld, rowptr,
-                               r2m, csr_k, csr_end, G);
-    } else {
-        const float *v = static_cast<const float *>(A.values);
-        if (prec == 0)
-            hipLaunchKernelGGL((k_gram_rows<float, double>), grid, block, lds, s, A.rowidx, v, M, n, npad, ld, rowptr,
-                               r2m, csr_k, csr_end, G);
-        else
-            hipLaunchKernelGGL((k_gram_rows<float, float>), grid, block, lds, s, A.rowidx, v, M, n, npad, ld, rowptr,
-                               r2m, csr_k, csr_end, G);
-    }
+size_t gram_lds_bytes(int32_t maxM, size_t lds_limit) {
+    const int nw = gram_waves(maxM, 8, lds_limit);
+    return (size_t)nw * maxM * (8 + sizeof(int32_t));
+}
+
+void launch_gram(const MatDesc *descs, const int32_t *wp, int64_t nblocks, int count, int32_t maxM, size_t lds_limit,
+                 hipStream_t s) {
+    const int nw = gram_waves(maxM, 8, lds_limit);
+    hipLaunchKernelGGL(k_gram_rows, dim3((unsigned)nblocks), dim3((unsigned)(64 * nw)), gram_lds_bytes(maxM, lds_limit),
+                       s, descs, wp, count);
 }
 
 hipError_t gram_set_attributes(size_t lds_limit) {
-    const void *fns[] = {reinterpret_cast<const void *>(k_gram_rows<double, double>),
-                         reinterpret_cast<const void *>(k_gram_rows<double, float>),
-                         reinterpret_cast<const void *>(k_gram_rows<float, double>),
-                         reinterpret_cast<const void *>(k_gram_rows<float, float>)};
-    for (const void *f : fns) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_gram_rows), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds_limit);
 }
 
 }  // namespace ranky

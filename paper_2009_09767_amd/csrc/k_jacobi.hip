@@ -23,6 +23,7 @@
 // Rotation (Rutishauser): zeta = (g_qq - g_pp) / (2 g_pq), t = sign(zeta) / (|zeta| +
 // sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = c t; then g_pp -= t g_pq, g_qq += t g_pq.
 // Rows: r_p <- c r_p - s r_q, r_q <- s r_p + c r_q; columns likewise.
+#include "batch.hpp"
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -61,33 +62,11 @@ __device__ __forceinline__ void rotation(double app, double aqq, double apq, dou
     t = tt;
 }
 
-__global__ __launch_bounds__(256) void k_jeye(double *__restrict__ W, int32_t npad) {
-    const int64_t total = (int64_t)npad * npad;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
-        W[e] = (e / npad == e % npad) ? 1.0 : 0.0;
-}
-
-// floor = (n eps)^2 max|g_ii| (one workgroup).
-__global__ __launch_bounds__(256) void k_jprep(const double *__restrict__ G, int64_t ld, int32_t n,
-                                               double *__restrict__ sdbl) {
-    __shared__ double red[256];
-    double m = 0.0;
-    for (int32_t i = threadIdx.x; i < n; i += 256) m = fmax(m, fabs(G[(int64_t)i * ld + i]));
-    red[threadIdx.x] = m;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const double ne = (double)n * 2.220446049250313e-16;
-        sdbl[kSdFloor] = ne * ne * red[0];
-    }
-}
-
+// Per-matrix arguments of one round launch (a table of these covers a batch).
 struct RoundArgs {
-    const double *Gin;     // M_{r-1} (or M_r itself when there is no previous round)
-    double *Gout;          // receives M_r = Jp^T M_{r-1} Jp (update part)
+    const double *Gin;     // M_{r-1} (or M_r itself when there is no previous round); set in-kernel
+    double *Gout;          // receives M_r = Jp^T M_{r-1} Jp (update part); set in-kernel
+    double *G0, *G1;       // the two G buffers
     double *W;             // eigenvectors, updated in place by Jp
     int64_t ld;
     int32_t nb;            // blocks
@@ -101,6 +80,7 @@ struct RoundArgs {
     int32_t *fcur;
     double *Scur;
     const double *sdbl;
+    const int32_t *jstate; // sweeps done / active (device state of this matrix)
     double tol;
     int32_t inner_sweeps;
     int32_t ntiles_g;      // npairs (npairs + 1) / 2
@@ -361,12 +341,20 @@ __device__ void update_tile(const RoundArgs &a, int u, double *A, double *B) {
     for (int v = 0; v < 4; ++v) a.W[(int64_t)(rt * kP + row) * a.ld + gidx(col0 + v, Pb, Qb)] = c[v];
 }
 
-__global__ __launch_bounds__(256) void k_jround(RoundArgs a) {
+__global__ __launch_bounds__(256) void k_jround(const RoundArgs *__restrict__ table, const int32_t *__restrict__ wp,
+                                                int count, int32_t launch_r) {
     __shared__ double L0[kP * kPS], L1[kP * kPS], L2[kP * kPS];
     __shared__ double L3[kP * kB], L4[kP * kB];
     __shared__ int pos[512];
+    const int mat = find_mat(wp, count, blockIdx.x);
+    RoundArgs a = table[mat];
+    if (a.jstate[kJsActive] == 0) return;
+    // G buffer holding M_{r-1}: one flip per launch with a previous round, nb - 1 per sweep
+    const int32_t flips = a.jstate[kJsSweeps] * (a.nb - 1) + (launch_r > 0 ? launch_r - 1 : 0);
+    a.Gin = (flips & 1) ? a.G1 : a.G0;
+    a.Gout = (flips & 1) ? a.G0 : a.G1;
     const int npairs = a.nb / 2;
-    int b = blockIdx.x;
+    int b = blockIdx.x - wp[mat];
     if (a.do_solve) {
         if (b < npairs) {
             solve_pair(a, b, L0, L1, L2, L3, L4, pos);
@@ -377,80 +365,164 @@ __global__ __launch_bounds__(256) void k_jround(RoundArgs a) {
     update_tile(a, b, L0, L1);
 }
 
-// Sets scal[kScNotConv] = 1 if an off-diagonal entry of the leading n x n part still
-// fails the rotation test (one thread per entry of the upper triangle, coalesced).
-__global__ __launch_bounds__(256) void k_jcheck(const double *__restrict__ G, int64_t ld, int32_t n, double tol,
-                                                const double *__restrict__ sdbl, int32_t *__restrict__ scal) {
-    const double floor_abs = sdbl[kSdFloor];
-    int bad = 0;
-    const int64_t total = (int64_t)n * n;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = e / n, q = e % n;
-        if (q <= p) continue;
-        const double g = G[p * ld + q];
-        if (fabs(g) > floor_abs && fabs(g) > tol * sqrt(fabs(G[p * ld + p] * G[q * ld + q]))) bad = 1;
-    }
-    if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(&scal[kScNotConv], 1);
+// The G buffer holding the matrix after `sweeps` complete sweeps.
+__device__ __forceinline__ const double *current_g(const MatDesc &d) {
+    const int32_t nb = d.npad / kB;
+    return ((d.jstate[kJsSweeps] * (nb - 1)) & 1) ? d.G2 : d.G;
 }
 
-__global__ __launch_bounds__(256) void k_jdiag(const double *__restrict__ G, int64_t ld, int32_t n,
-                                               double *__restrict__ lam) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) lam[i] = G[(int64_t)i * ld + i];
+// Sets jstate[kJsNotConv] = 1 if an off-diagonal entry of the leading n x n part
+// still fails the rotation test (one thread per entry of the upper triangle).
+__global__ __launch_bounds__(256) void k_jcheck(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
+                                                int count) {
+    const int mat = find_mat(wp, count, blockIdx.x);
+    const MatDesc &d = descs[mat];
+    const int32_t n = d.n;
+    const int64_t ld = d.npad;
+    const double *__restrict__ G = current_g(d);
+    const double floor_abs = d.sdbl[kSdFloor];
+    const double tol = fmax(1e-15, sqrt((double)n) * 2.220446049250313e-16);
+    const int64_t nblk = wp[mat + 1] - wp[mat];
+    int bad = 0;
+    for (int64_t p = blockIdx.x - wp[mat]; p < n; p += nblk) {
+        const double gpp = G[p * ld + p];
+        for (int64_t q = p + 1 + threadIdx.x; q < n; q += blockDim.x) {
+            const double g = G[p * ld + q];
+            if (fabs(g) > floor_abs && fabs(g) > tol * sqrt(fabs(gpp * G[q * ld + q]))) bad = 1;
+        }
+    }
+    if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(&d.jstate[kJsNotConv], 1);
+}
+
+// Per matrix: start of a sweep (active = not converged and under the cap, clear the
+// flag) or end of a sweep (count it).
+__global__ __launch_bounds__(256) void k_jstate(const MatDesc *__restrict__ descs, int count, int32_t phase,
+                                                int32_t max_sweeps) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    int32_t *js = descs[i].jstate;
+    if (descs[i].n <= 0) {
+        js[kJsActive] = 0;
+        return;
+    }
+    if (phase == 0) {
+        js[kJsActive] = (js[kJsNotConv] != 0 && js[kJsSweeps] < max_sweeps) ? 1 : 0;
+    } else if (phase == 1) {
+        if (js[kJsActive]) js[kJsSweeps] += 1;
+        js[kJsNotConv] = 0;
+    }
+}
+
+// Per matrix: W = I, floor = (n eps)^2 max|g_ii|, state cleared.  One workgroup per
+// (matrix, slice) for the identity; slice 0 also does the floor.
+__global__ __launch_bounds__(256) void k_jinit(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
+                                               int count) {
+    __shared__ double red[256];
+    const int mat = find_mat(wp, count, blockIdx.x);
+    const MatDesc &d = descs[mat];
+    const int64_t npad = d.npad;
+    const int64_t nblk = wp[mat + 1] - wp[mat];
+    const int64_t b = blockIdx.x - wp[mat];
+    for (int64_t e = b * blockDim.x + threadIdx.x; e < npad * npad; e += nblk * blockDim.x)
+        d.W[e] = (e / npad == e % npad) ? 1.0 : 0.0;
+    if (b != 0) return;
+    double m = 0.0;
+    for (int32_t i = threadIdx.x; i < d.n; i += 256) m = fmax(m, fabs(d.G[(int64_t)i * npad + i]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double ne = (double)d.n * 2.220446049250313e-16;
+        d.sdbl[kSdFloor] = ne * ne * red[0];
+        d.jstate[kJsSweeps] = 0;
+        d.jstate[kJsActive] = 0;
+        d.jstate[kJsNotConv] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_jdiag(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
+                                               int count) {
+    const int mat = find_mat(wp, count, blockIdx.x);
+    const MatDesc &d = descs[mat];
+    const int32_t i = (blockIdx.x - wp[mat]) * blockDim.x + threadIdx.x;
+    if (i < d.n) d.lam[i] = current_g(d)[(int64_t)i * d.npad + i];
 }
 
 // ---------------------------------------------------------------------------
 
 int32_t jacobi_npad(int32_t n) { return ((n + kP - 1) / kP) * kP; }
 
-void launch_jacobi_init(double *W, int32_t npad, const double *G, int64_t ld, int32_t n, double *sdbl,
-                        hipStream_t s) {
-    int64_t blocks = ((int64_t)npad * npad + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_jeye, dim3((unsigned)blocks), dim3(256), 0, s, W, npad);
-    hipLaunchKernelGGL(k_jprep, dim3(1), dim3(256), 0, s, G, ld, n, sdbl);
+void launch_jacobi_init(const MatDesc *descs, const int32_t *wp, int64_t nblocks, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_jinit, dim3((unsigned)nblocks), dim3(256), 0, s, descs, wp, count);
 }
 
-void launch_jacobi_round(const JacobiRound &r, hipStream_t s) {
-    RoundArgs a;
-    a.Gin = r.Gin;
-    a.Gout = r.Gout;
-    a.W = r.W;
-    a.ld = r.ld;
-    a.nb = r.npad / kB;
-    a.round_cur = r.round_cur;
-    a.round_prev = r.round_prev;
-    a.has_prev = r.has_prev;
-    a.do_solve = r.do_solve;
-    a.Jprev = r.Jprev;
-    a.fprev = r.fprev;
-    a.Sprev = r.Sprev;
-    a.Jcur = r.Jcur;
-    a.fcur = r.fcur;
-    a.Scur = r.Scur;
-    a.sdbl = r.sdbl;
-    a.tol = r.tol;
-    a.inner_sweeps = r.inner_sweeps;
-    const int32_t npairs = a.nb / 2;
-    a.ntiles_g = npairs * (npairs + 1) / 2;
-    a.nrowtiles = r.npad / kP;
-    int64_t grid = 0;
-    if (a.do_solve) grid += npairs;
-    if (a.has_prev) grid += a.ntiles_g + (int64_t)a.nrowtiles * npairs;
-    if (grid == 0) return;
-    hipLaunchKernelGGL(k_jround, dim3((unsigned)grid), dim3(256), 0, s, a);
+void launch_jacobi_state(const MatDesc *descs, int count, int32_t phase, int32_t max_sweeps, hipStream_t s) {
+    hipLaunchKernelGGL(k_jstate, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, descs, count, phase,
+                       max_sweeps);
 }
 
-void launch_jacobi_check(const double *G, int64_t ld, int32_t n, double tol, const double *sdbl, int32_t *scal,
+void launch_jacobi_round(const void *table, const int32_t *wp, int64_t nblocks, int count, int32_t launch_r,
                          hipStream_t s) {
-    int64_t blocks = ((int64_t)n * n + 255) / 256;
-    if (blocks < 1) blocks = 1;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_jcheck, dim3((unsigned)blocks), dim3(256), 0, s, G, ld, n, tol, sdbl, scal);
+    if (nblocks <= 0) return;
+    hipLaunchKernelGGL(k_jround, dim3((unsigned)nblocks), dim3(256), 0, s, static_cast<const RoundArgs *>(table), wp,
+                       count, launch_r);
 }
 
-void launch_jacobi_diag(const double *G, int64_t ld, int32_t n, double *lam, hipStream_t s) {
-    hipLaunchKernelGGL(k_jdiag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, G, ld, n, lam);
+void launch_jacobi_check(const MatDesc *descs, const int32_t *wp, int64_t nblocks, int count, hipStream_t s) {
+    if (nblocks <= 0) return;
+    hipLaunchKernelGGL(k_jcheck, dim3((unsigned)nblocks), dim3(256), 0, s, descs, wp, count);
+}
+
+void launch_jacobi_diag(const MatDesc *descs, const int32_t *wp, int64_t nblocks, int count, hipStream_t s) {
+    if (nblocks <= 0) return;
+    hipLaunchKernelGGL(k_jdiag, dim3((unsigned)nblocks), dim3(256), 0, s, descs, wp, count);
+}
+
+size_t round_args_bytes() { return sizeof(RoundArgs); }
+
+void fill_round_args(void *dst, const MatDesc &d, int32_t r, int32_t inner_sweeps) {
+    RoundArgs a;
+    const int32_t nb = d.npad / kB;
+    const int32_t npairs = nb / 2;
+    const size_t jsz = (size_t)npairs * kP * kP;
+    a.Gin = nullptr;
+    a.Gout = nullptr;
+    a.G0 = d.G;
+    a.G1 = d.G2;
+    a.W = d.W;
+    a.ld = d.npad;
+    a.nb = nb;
+    a.round_cur = r;
+    a.round_prev = r - 1;
+    a.has_prev = r > 0 && r <= nb - 1;
+    a.do_solve = r < nb - 1;
+    a.Jprev = d.J + ((r + 1) & 1) * jsz;
+    a.Sprev = d.S + ((r + 1) & 1) * jsz;
+    a.fprev = d.jflag + ((r + 1) & 1) * npairs;
+    a.Jcur = d.J + (r & 1) * jsz;
+    a.Scur = d.S + (r & 1) * jsz;
+    a.fcur = d.jflag + (r & 1) * npairs;
+    a.sdbl = d.sdbl;
+    a.jstate = d.jstate;
+    a.tol = fmax(1e-15, sqrt((double)d.n) * 2.220446049250313e-16);
+    a.inner_sweeps = npairs == 1 ? 40 : inner_sweeps;
+    a.ntiles_g = npairs * (npairs + 1) / 2;
+    a.nrowtiles = d.npad / kP;
+    *static_cast<RoundArgs *>(dst) = a;
+}
+
+// workgroups matrix d needs in launch r of a sweep (0 when it has no work there)
+int64_t round_blocks(const MatDesc &d, int32_t r) {
+    if (d.n <= 0) return 0;
+    const int32_t nb = d.npad / kB;
+    const int32_t npairs = nb / 2;
+    int64_t b = 0;
+    if (r < nb - 1) b += npairs;
+    if (r > 0 && r <= nb - 1) b += (int64_t)npairs * (npairs + 1) / 2 + (int64_t)(d.npad / kP) * npairs;
+    return b;
 }
 
 }  // namespace ranky

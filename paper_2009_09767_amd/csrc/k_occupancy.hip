@@ -10,6 +10,7 @@
 //
 // The same counts give the offsets of a stable counting sort of the nonzeros by
 // row (column order kept inside a row), used by the Gram pass.
+#include "batch.hpp"
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -29,27 +30,23 @@ __global__ void k_fill_f64(double *__restrict__ p, int64_t n, double v) {
 // its nonzeros per row in LDS; write the chunk's row histogram.  Reads are
 // bounded by the colptr checks, so a malformed CSC only sets status bits.
 template <typename TV>
-__global__ __launch_bounds__(256) void k_occ_chunks(const int32_t *__restrict__ colptr,
-                                                    const int32_t *__restrict__ rowidx,
-                                                    const TV *__restrict__ vals, int32_t M, int64_t N, int64_t nnz,
-                                                    int32_t D, int32_t cpb, int32_t validate,
-                                                    int32_t *__restrict__ hist, int32_t *__restrict__ scal) {
-    extern __shared__ int32_t lds_hist[];
-    const int64_t c = blockIdx.x;
+__device__ void occ_chunk(const MatDesc &d, const TV *__restrict__ vals, int64_t c, int32_t *lds_hist) {
+    const int32_t M = d.M;
+    const int64_t N = d.N, nnz = d.nnz;
     int64_t c0, c1;
-    chunk_columns(c, cpb, N, D, c0, c1);
+    chunk_columns(c, d.cpb, N, d.D, c0, c1);
     for (int32_t m = threadIdx.x; m < M; m += blockDim.x) lds_hist[m] = 0;
     __syncthreads();
     int32_t err = 0;
     for (int64_t j = c0 + threadIdx.x; j < c1; j += blockDim.x) {
-        const int64_t e0 = colptr[j], e1 = colptr[j + 1];
+        const int64_t e0 = d.colptr[j], e1 = d.colptr[j + 1];
         if (e0 < 0 || e1 < e0 || e1 > nnz) {
             err |= kStCsc;
             continue;
         }
         int32_t prev = -1;
         for (int64_t e = e0; e < e1; ++e) {
-            const int32_t r = rowidx[e];
+            const int32_t r = d.rowidx[e];
             if (r < 0 || r >= M) {
                 err |= kStCsc;
                 continue;
@@ -57,52 +54,71 @@ __global__ __launch_bounds__(256) void k_occ_chunks(const int32_t *__restrict__ 
             if (r <= prev) err |= kStCsc;
             prev = r;
             atomicAdd(&lds_hist[r], 1);
-            if (validate && !finite_value(vals[e])) err |= kStNonfinite;
+            if (d.validate && !finite_value(vals[e])) err |= kStNonfinite;
         }
     }
     if (threadIdx.x == 0) {
-        if (c0 == 0 && c1 > 0 && colptr[0] != 0) err |= kStCsc;
-        if (c1 == N && c0 < c1 && (int64_t)colptr[N] != nnz) err |= kStCsc;
+        if (c0 == 0 && c1 > 0 && d.colptr[0] != 0) err |= kStCsc;
+        if (c1 == N && c0 < c1 && (int64_t)d.colptr[N] != nnz) err |= kStCsc;
     }
-    if (err) atomicOr(&scal[kScStatus], err);
+    if (err) atomicOr(&d.scal[kScStatus], err);
     __syncthreads();
-    int32_t *out = hist + c * (int64_t)M;
+    int32_t *out = d.hist + c * (int64_t)M;
     for (int32_t m = threadIdx.x; m < M; m += blockDim.x) out[m] = lds_hist[m];
+}
+
+__global__ __launch_bounds__(256) void k_occ_chunks(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
+                                                    int count) {
+    extern __shared__ int32_t lds_hist[];
+    const int mat = find_mat(wp, count, blockIdx.x);
+    const MatDesc &d = descs[mat];
+    const int64_t c = blockIdx.x - wp[mat];
+    if (d.dtype == 1)
+        occ_chunk<double>(d, static_cast<const double *>(d.values), c, lds_hist);
+    else
+        occ_chunk<float>(d, static_cast<const float *>(d.values), c, lds_hist);
 }
 
 // One thread per row: per-block occupancy (sum of the block's chunk histograms),
 // lonely / single-entry row counts per block, and the row's total.
-__global__ __launch_bounds__(256) void k_occ_rows(const int32_t *__restrict__ hist, int32_t M, int32_t D, int32_t cpb,
-                                                  int32_t *__restrict__ rownnz, int32_t *__restrict__ cnt,
-                                                  int32_t *__restrict__ lonely, int32_t *__restrict__ single) {
-    const int32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_occ_rows(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
+                                                  int count) {
+    const int mat = find_mat(wp, count, blockIdx.x);
+    const MatDesc &d = descs[mat];
+    const int32_t M = d.M, D = d.D, cpb = d.cpb;
+    const int32_t m = (blockIdx.x - wp[mat]) * blockDim.x + threadIdx.x;
     const bool valid = m < M;
     const int lane = threadIdx.x & 63;
     int32_t total = 0;
     for (int32_t b = 0; b < D; ++b) {
         int32_t cb = 0;
         if (valid)
-            for (int32_t t = 0; t < cpb; ++t) cb += hist[((int64_t)b * cpb + t) * M + m];
-        if (valid && cnt) cnt[(int64_t)b * M + m] = cb;
+            for (int32_t t = 0; t < cpb; ++t) cb += d.hist[((int64_t)b * cpb + t) * M + m];
+        if (valid && d.cnt) d.cnt[(int64_t)b * M + m] = cb;
         total += cb;
         const uint64_t z = __ballot(valid && cb == 0);
         const uint64_t s = __ballot(valid && cb == 1);
         if (lane == 0) {
-            if (z) atomicAdd(&lonely[b], __popcll(z));
-            if (s) atomicAdd(&single[b], __popcll(s));
+            if (z) atomicAdd(&d.lonely[b], __popcll(z));
+            if (s) atomicAdd(&d.single[b], __popcll(s));
         }
     }
-    if (valid) rownnz[m] = total;
+    if (valid) d.rownnz[m] = total;
 }
 
 // One workgroup of 1024 threads: exclusive scan of the row counts (row pointers of
 // the row-major copy) and the compaction maps of the non-empty rows.
 //   m2r[m] = position of row m among the non-empty rows, or -1
 //   r2m[i] = the i-th non-empty row;  empty[e] = the e-th empty row (ascending)
-__global__ __launch_bounds__(1024) void k_occ_scan(const int32_t *__restrict__ rownnz, int32_t M,
-                                                   int32_t *__restrict__ rowptr, int32_t *__restrict__ m2r,
-                                                   int32_t *__restrict__ r2m, int32_t *__restrict__ empty,
-                                                   int32_t *__restrict__ scal) {
+__global__ __launch_bounds__(1024) void k_occ_scan(const MatDesc *__restrict__ descs) {
+    const MatDesc &d = descs[blockIdx.x];
+    const int32_t M = d.M;
+    const int32_t *__restrict__ rownnz = d.rownnz;
+    int32_t *__restrict__ rowptr = d.rowptr;
+    int32_t *__restrict__ m2r = d.m2r;
+    int32_t *__restrict__ r2m = d.r2m;
+    int32_t *__restrict__ empty = d.empty;
+    int32_t *__restrict__ scal = d.scal;
     __shared__ int64_t s_nnz[1024];
     __shared__ int32_t s_ne[1024];
     const int32_t per = (M + 1023) / 1024;
@@ -151,14 +167,17 @@ __global__ __launch_bounds__(1024) void k_occ_scan(const int32_t *__restrict__ r
 
 // One thread per row: turn the chunk histograms into the start offset of every
 // (chunk, row) run in the row-major copy (row pointer + earlier chunks), in place.
-__global__ __launch_bounds__(256) void k_occ_offsets(int32_t *__restrict__ hist, const int32_t *__restrict__ rowptr,
-                                                     int32_t M, int64_t nchunks) {
-    const int32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_occ_offsets(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
+                                                     int count) {
+    const int mat = find_mat(wp, count, blockIdx.x);
+    const MatDesc &d = descs[mat];
+    const int32_t M = d.M;
+    const int32_t m = (blockIdx.x - wp[mat]) * blockDim.x + threadIdx.x;
     if (m >= M) return;
-    int32_t run = rowptr[m];
-    for (int64_t c = 0; c < nchunks; ++c) {
-        const int32_t h = hist[c * M + m];
-        hist[c * M + m] = run;
+    int32_t run = d.rowptr[m];
+    for (int64_t c = 0; c < d.nchunks; ++c) {
+        const int32_t h = d.hist[c * M + m];
+        d.hist[c * M + m] = run;
         run += h;
     }
 }
@@ -171,17 +190,22 @@ __global__ __launch_bounds__(256) void k_occ_offsets(int32_t *__restrict__ hist,
 // the row's running offset plus that rank; the lowest lane then advances the offset.
 // csr_k[slot] = CSC position of the entry, csr_end[slot] = end of its column,
 // csr_col[slot] = its column.
-__global__ __launch_bounds__(64) void k_transpose(const int32_t *__restrict__ colptr,
-                                                  const int32_t *__restrict__ rowidx, int32_t M, int64_t N,
-                                                  int32_t D, int32_t cpb, const int32_t *__restrict__ offs,
-                                                  int32_t *__restrict__ csr_k, int32_t *__restrict__ csr_end,
-                                                  int32_t *__restrict__ csr_col) {
+__global__ __launch_bounds__(64) void k_transpose(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
+                                                  int count) {
+    const int mat = find_mat(wp, count, blockIdx.x);
+    const MatDesc &d = descs[mat];
+    const int32_t M = d.M;
+    const int32_t *__restrict__ colptr = d.colptr;
+    const int32_t *__restrict__ rowidx = d.rowidx;
+    int32_t *__restrict__ csr_k = d.csrk;
+    int32_t *__restrict__ csr_end = d.csrend;
+    int32_t *__restrict__ csr_col = d.csrcol;
     extern __shared__ uint64_t lds_mask[];
     int32_t *ctr = reinterpret_cast<int32_t *>(lds_mask + M);
-    const int64_t c = blockIdx.x;
+    const int64_t c = blockIdx.x - wp[mat];
     int64_t c0, c1;
-    chunk_columns(c, cpb, N, D, c0, c1);
-    const int32_t *off = offs + c * (int64_t)M;
+    chunk_columns(c, d.cpb, d.N, d.D, c0, c1);
+    const int32_t *off = d.hist + c * (int64_t)M;
     for (int32_t m = threadIdx.x; m < M; m += 64) {
         lds_mask[m] = 0;
         ctr[m] = off[m];
@@ -218,6 +242,62 @@ __global__ __launch_bounds__(64) void k_transpose(const int32_t *__restrict__ co
     }
 }
 
+// Per matrix: clear the scalar block and the per-block counters (one workgroup each).
+__global__ __launch_bounds__(256) void k_batch_prep(const MatDesc *__restrict__ descs) {
+    const MatDesc &d = descs[blockIdx.x];
+    for (int32_t i = threadIdx.x; i < kScCount; i += blockDim.x) d.scal[i] = 0;
+    for (int32_t b = threadIdx.x; b < d.D; b += blockDim.x) {
+        d.lonely[b] = 0;
+        d.single[b] = 0;
+    }
+}
+
+// Gather every matrix's scalars into one compact array for a single read-back:
+// out_i32[8i..8i+7] = status, M', rank, sweeps, not-converged, lonely max, blocks with
+// lonely rows, 0;  out_f64[2i..2i+1] = tau, sigma_1.
+__global__ __launch_bounds__(256) void k_batch_collect(const MatDesc *__restrict__ descs, int count,
+                                                       int32_t *__restrict__ out_i32, double *__restrict__ out_f64) {
+    const int i = blockIdx.x;
+    if (i >= count) return;
+    const MatDesc &d = descs[i];
+    __shared__ int32_t mx[256], nz[256];
+    int32_t m = 0, z = 0;
+    for (int32_t b = threadIdx.x; b < d.D; b += blockDim.x) {
+        m = max(m, d.lonely[b]);
+        z += d.lonely[b] > 0;
+    }
+    mx[threadIdx.x] = m;
+    nz[threadIdx.x] = z;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            mx[threadIdx.x] = max(mx[threadIdx.x], mx[threadIdx.x + off]);
+            nz[threadIdx.x] += nz[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out_i32[8 * i + 0] = d.scal[kScStatus];
+        out_i32[8 * i + 1] = d.scal[kScNonempty];
+        out_i32[8 * i + 2] = d.scal[kScRank];
+        out_i32[8 * i + 3] = d.jstate ? d.jstate[kJsSweeps] : 0;
+        out_i32[8 * i + 4] = d.jstate ? d.jstate[kJsNotConv] : 0;
+        out_i32[8 * i + 5] = mx[0];
+        out_i32[8 * i + 6] = nz[0];
+        out_i32[8 * i + 7] = d.jstate ? d.jstate[kJsActive] : 0;
+        out_f64[2 * i + 0] = d.sdbl[kSdTau];
+        out_f64[2 * i + 1] = d.sdbl[kSdSigmaMax];
+    }
+}
+
+void launch_batch_prep(const MatDesc *descs, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)count), dim3(256), 0, s, descs);
+}
+
+void launch_batch_collect(const MatDesc *descs, int count, int32_t *out_i32, double *out_f64, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_collect, dim3((unsigned)count), dim3(256), 0, s, descs, count, out_i32, out_f64);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -236,31 +316,22 @@ void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
 }
 
-void launch_occupancy(const CscView &A, int32_t M, int64_t N, int32_t D, int32_t cpb, int64_t nchunks,
-                      int32_t validate, int32_t *hist, int32_t *rownnz, int32_t *cnt, int32_t *lonely,
-                      int32_t *single, int32_t *rowptr, int32_t *m2r, int32_t *r2m, int32_t *empty,
-                      int32_t *scal, hipStream_t s) {
-    const size_t lds = sizeof(int32_t) * (size_t)M;
-    if (A.dtype == 1)
-        hipLaunchKernelGGL(k_occ_chunks<double>, dim3((unsigned)nchunks), dim3(256), lds, s, A.colptr, A.rowidx,
-                           static_cast<const double *>(A.values), M, N, A.nnz, D, cpb, validate, hist, scal);
-    else
-        hipLaunchKernelGGL(k_occ_chunks<float>, dim3((unsigned)nchunks), dim3(256), lds, s, A.colptr, A.rowidx,
-                           static_cast<const float *>(A.values), M, N, A.nnz, D, cpb, validate, hist, scal);
-    hipLaunchKernelGGL(k_occ_rows, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, hist, M, D, cpb, rownnz, cnt,
-                       lonely, single);
-    hipLaunchKernelGGL(k_occ_scan, dim3(1), dim3(1024), 0, s, rownnz, M, rowptr, m2r, r2m, empty, scal);
+void launch_occupancy(const MatDesc *descs, const int32_t *wp_chunks, int64_t n_chunk_blocks,
+                      const int32_t *wp_rows, int64_t n_row_blocks, int count, int32_t maxM, hipStream_t s) {
+    hipLaunchKernelGGL(k_occ_chunks, dim3((unsigned)n_chunk_blocks), dim3(256), sizeof(int32_t) * (size_t)maxM, s,
+                       descs, wp_chunks, count);
+    hipLaunchKernelGGL(k_occ_rows, dim3((unsigned)n_row_blocks), dim3(256), 0, s, descs, wp_rows, count);
+    hipLaunchKernelGGL(k_occ_scan, dim3((unsigned)count), dim3(1024), 0, s, descs);
 }
 
-void launch_row_offsets(int32_t *hist, const int32_t *rowptr, int32_t M, int64_t nchunks, hipStream_t s) {
-    hipLaunchKernelGGL(k_occ_offsets, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, hist, rowptr, M, nchunks);
+void launch_row_offsets(const MatDesc *descs, const int32_t *wp_rows, int64_t n_row_blocks, int count, hipStream_t s) {
+    hipLaunchKernelGGL(k_occ_offsets, dim3((unsigned)n_row_blocks), dim3(256), 0, s, descs, wp_rows, count);
 }
 
-void launch_transpose(const CscView &A, int32_t M, int64_t N, int32_t D, int32_t cpb, int64_t nchunks,
-                      const int32_t *offs, int32_t *csr_k, int32_t *csr_end, int32_t *csr_col, hipStream_t s) {
-    const size_t lds = (sizeof(uint64_t) + sizeof(int32_t)) * (size_t)M;
-    hipLaunchKernelGGL(k_transpose, dim3((unsigned)nchunks), dim3(64), lds, s, A.colptr, A.rowidx, M, N, D, cpb, offs,
-                       csr_k, csr_end, csr_col);
+void launch_transpose(const MatDesc *descs, const int32_t *wp_chunks, int64_t n_chunk_blocks, int count, int32_t maxM,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_transpose, dim3((unsigned)n_chunk_blocks), dim3(64), transpose_lds_bytes(maxM), s, descs,
+                       wp_chunks, count);
 }
 
 size_t transpose_lds_bytes(int32_t M) { return (sizeof(uint64_t) + sizeof(int32_t)) * (size_t)M; }

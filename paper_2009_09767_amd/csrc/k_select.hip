@@ -6,6 +6,7 @@
 // halves the exponent, so below sqrt(M' u_G) sigma_1 a singular value cannot be told
 // from zero).  Returned sigma_i for i >= r are exactly 0, and the back-projection
 // V = A^T U Sigma^{-1} (Sec. V) fills those columns with zeros instead of dividing.
+#include "batch.hpp"
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -13,11 +14,18 @@ namespace ranky {
 
 // One workgroup of 1024 threads: bitonic sort of (lambda desc, index asc) over the
 // n eigenvalues, then sigma, tau and the rank.  LDS holds npow2 keys and indices.
-__global__ __launch_bounds__(1024) void k_select_sort(const double *__restrict__ lam, int32_t n, int32_t npow2,
-                                                      int32_t k, int32_t n_tau, double tol, double u_gram,
-                                                      int32_t *__restrict__ perm, double *__restrict__ sigma,
-                                                      int32_t *__restrict__ scal, double *__restrict__ sdbl) {
+__global__ __launch_bounds__(1024) void k_select_sort(const MatDesc *__restrict__ descs) {
     extern __shared__ double lds_key[];
+    const MatDesc &d = descs[blockIdx.x];
+    const double *__restrict__ lam = d.lam;
+    const int32_t n = d.n, k = d.k, n_tau = d.n_tau;
+    const double tol = d.tol, u_gram = d.u_gram;
+    int32_t *__restrict__ perm = d.perm;
+    double *__restrict__ sigma = d.sigma;
+    int32_t *__restrict__ scal = d.scal;
+    double *__restrict__ sdbl = d.sdbl;
+    int32_t npow2 = 1;
+    while (npow2 < n) npow2 <<= 1;
     int32_t *idx = reinterpret_cast<int32_t *>(lds_key + npow2);
     for (int32_t i = threadIdx.x; i < npow2; i += blockDim.x) {
         lds_key[i] = i < n ? lam[i] : -__builtin_inf();
@@ -71,11 +79,18 @@ __global__ __launch_bounds__(1024) void k_select_sort(const double *__restrict__
 // One workgroup per output column i: the eigenvector W[:, perm[i]] scattered to the
 // non-empty rows with its largest-magnitude entry made positive (lowest row on a
 // tie); columns i >= M' are e_row of the empty rows in ascending order.
-__global__ __launch_bounds__(256) void k_gather_u(const double *__restrict__ W, int64_t ld, int32_t n, int32_t M,
-                                                  int32_t k, const int32_t *__restrict__ perm,
-                                                  const int32_t *__restrict__ m2r,
-                                                  const int32_t *__restrict__ empty, double *__restrict__ U) {
-    const int32_t i = blockIdx.x;
+__global__ __launch_bounds__(256) void k_gather_u(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
+                                                  int count) {
+    const int mat = find_mat(wp, count, blockIdx.x);
+    const MatDesc &d = descs[mat];
+    const double *__restrict__ W = d.W;
+    const int64_t ld = d.npad;
+    const int32_t n = d.n, M = d.M, k = d.k;
+    const int32_t *__restrict__ perm = d.perm;
+    const int32_t *__restrict__ m2r = d.m2r;
+    const int32_t *__restrict__ empty = d.empty;
+    double *__restrict__ U = d.U;
+    const int32_t i = blockIdx.x - wp[mat];
     if (i >= n) {
         const int32_t e = empty[i - n];
         for (int32_t m = threadIdx.x; m < M; m += blockDim.x) U[(int64_t)m * k + i] = (m == e) ? 1.0 : 0.0;
@@ -119,15 +134,11 @@ __global__ __launch_bounds__(256) void k_gather_u(const double *__restrict__ W, 
 // outputs i, so a wave covers 128 outputs per pass with 16-byte U loads.  The
 // column's nonzeros are read once per pass; U rows come from L2.
 template <typename TV, typename TO>
-__global__ __launch_bounds__(256) void k_backproject(const int32_t *__restrict__ colptr,
-                                                     const int32_t *__restrict__ rowidx,
-                                                     const TV *__restrict__ vals, int64_t N, int32_t k,
-                                                     const double *__restrict__ U, const double *__restrict__ sigma,
-                                                     const int32_t *__restrict__ rank_ptr, TO *__restrict__ V) {
-    const int32_t rank = *rank_ptr;
+__device__ void backproject_cols(const int32_t *__restrict__ colptr, const int32_t *__restrict__ rowidx,
+                                 const TV *__restrict__ vals, int64_t N, int32_t k, const double *__restrict__ U,
+                                 const double *__restrict__ sigma, int32_t rank, TO *__restrict__ V, int64_t wave,
+                                 int64_t nwaves) {
     const int lane = threadIdx.x & 63;
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int32_t i0 = 0; i0 < k; i0 += 128) {
         const int32_t i = i0 + 2 * lane;
         const bool ok0 = i < k, ok1 = i + 1 < k;
@@ -161,44 +172,92 @@ __global__ __launch_bounds__(256) void k_backproject(const int32_t *__restrict__
     }
 }
 
+// Batched back-projection: matrix `mat` owns workgroups [wp[mat], wp[mat+1]) and its
+// waves stride over its columns.
+__global__ __launch_bounds__(256) void k_backproject(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
+                                                     int count) {
+    const int mat = find_mat(wp, count, blockIdx.x);
+    const MatDesc &d = descs[mat];
+    const int64_t wave = (((int64_t)blockIdx.x - wp[mat]) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)(wp[mat + 1] - wp[mat]) * blockDim.x) >> 6;
+    const int32_t rank = d.scal[kScRank];
+    if (d.dtype == 1) {
+        const double *v = static_cast<const double *>(d.values);
+        if (d.v_dtype == 1)
+            backproject_cols<double, double>(d.colptr, d.rowidx, v, d.N, d.k, d.U, d.sigma, rank,
+                                             static_cast<double *>(d.V), wave, nwaves);
+        else
+            backproject_cols<double, float>(d.colptr, d.rowidx, v, d.N, d.k, d.U, d.sigma, rank,
+                                            static_cast<float *>(d.V), wave, nwaves);
+    } else {
+        const float *v = static_cast<const float *>(d.values);
+        if (d.v_dtype == 1)
+            backproject_cols<float, double>(d.colptr, d.rowidx, v, d.N, d.k, d.U, d.sigma, rank,
+                                            static_cast<double *>(d.V), wave, nwaves);
+        else
+            backproject_cols<float, float>(d.colptr, d.rowidx, v, d.N, d.k, d.U, d.sigma, rank,
+                                           static_cast<float *>(d.V), wave, nwaves);
+    }
+}
+
+// Stand-alone back-projection with an explicit device rank (step call).
+template <typename TV, typename TO>
+__global__ __launch_bounds__(256) void k_backproject_one(const int32_t *__restrict__ colptr,
+                                                         const int32_t *__restrict__ rowidx,
+                                                         const TV *__restrict__ vals, int64_t N, int32_t k,
+                                                         const double *__restrict__ U,
+                                                         const double *__restrict__ sigma,
+                                                         const int32_t *__restrict__ rank_ptr, TO *__restrict__ V) {
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    backproject_cols<TV, TO>(colptr, rowidx, vals, N, k, U, sigma, *rank_ptr, V, wave, nwaves);
+}
+
 // ---------------------------------------------------------------------------
 
-void launch_select(const double *lam, int32_t n, int32_t k, int32_t n_tau, double tol, double u_gram, int32_t *perm,
-                   double *sigma, int32_t *scal, double *sdbl, hipStream_t s) {
+void launch_select(const MatDesc *descs, int count, int32_t max_n, hipStream_t s) {
     int32_t npow2 = 1;
-    while (npow2 < n) npow2 <<= 1;
+    while (npow2 < max_n) npow2 <<= 1;
     const size_t lds = (sizeof(double) + sizeof(int32_t)) * (size_t)npow2;
-    hipLaunchKernelGGL(k_select_sort, dim3(1), dim3(1024), lds, s, lam, n, npow2, k, n_tau, tol, u_gram, perm, sigma,
-                       scal, sdbl);
+    hipLaunchKernelGGL(k_select_sort, dim3((unsigned)count), dim3(1024), lds, s, descs);
 }
 
-void launch_gather_u(const double *W, int64_t ld, int32_t n, int32_t M, int32_t k, const int32_t *perm,
-                     const int32_t *m2r, const int32_t *empty, double *U, hipStream_t s) {
-    hipLaunchKernelGGL(k_gather_u, dim3((unsigned)k), dim3(256), 0, s, W, ld, n, M, k, perm, m2r, empty, U);
+void launch_gather_u(const MatDesc *descs, const int32_t *wp, int64_t nblocks, int count, hipStream_t s) {
+    if (nblocks <= 0) return;
+    hipLaunchKernelGGL(k_gather_u, dim3((unsigned)nblocks), dim3(256), 0, s, descs, wp, count);
 }
 
-void launch_backproject(const CscView &A, int64_t N, int32_t k, const double *U, const double *sigma,
-                        const int32_t *rank, void *V, int32_t v_dtype, int32_t cu_count, hipStream_t s) {
+int64_t backproject_blocks(int64_t N, int32_t cu_count) {
     int64_t blocks = (N + 3) / 4;
     const int64_t cap = (int64_t)cu_count * 32;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
-    const dim3 grid((unsigned)blocks), block(256);
+    return blocks;
+}
+
+void launch_backproject_batch(const MatDesc *descs, const int32_t *wp, int64_t nblocks, int count, hipStream_t s) {
+    if (nblocks <= 0) return;
+    hipLaunchKernelGGL(k_backproject, dim3((unsigned)nblocks), dim3(256), 0, s, descs, wp, count);
+}
+
+void launch_backproject(const CscView &A, int64_t N, int32_t k, const double *U, const double *sigma,
+                        const int32_t *rank, void *V, int32_t v_dtype, int32_t cu_count, hipStream_t s) {
+    const dim3 grid((unsigned)backproject_blocks(N, cu_count)), block(256);
     if (A.dtype == 1) {
         const double *v = static_cast<const double *>(A.values);
         if (v_dtype == 1)
-            hipLaunchKernelGGL((k_backproject<double, double>), grid, block, 0, s, A.colptr, A.rowidx, v, N, k, U,
+            hipLaunchKernelGGL((k_backproject_one<double, double>), grid, block, 0, s, A.colptr, A.rowidx, v, N, k, U,
                                sigma, rank, static_cast<double *>(V));
         else
-            hipLaunchKernelGGL((k_backproject<double, float>), grid, block, 0, s, A.colptr, A.rowidx, v, N, k, U,
+            hipLaunchKernelGGL((k_backproject_one<double, float>), grid, block, 0, s, A.colptr, A.rowidx, v, N, k, U,
                                sigma, rank, static_cast<float *>(V));
     } else {
         const float *v = static_cast<const float *>(A.values);
         if (v_dtype == 1)
-            hipLaunchKernelGGL((k_backproject<float, double>), grid, block, 0, s, A.colptr, A.rowidx, v, N, k, U,
+            hipLaunchKernelGGL((k_backproject_one<float, double>), grid, block, 0, s, A.colptr, A.rowidx, v, N, k, U,
                                sigma, rank, static_cast<double *>(V));
         else
-            hipLaunchKernelGGL((k_backproject<float, float>), grid, block, 0, s, A.colptr, A.rowidx, v, N, k, U,
+            hipLaunchKernelGGL((k_backproject_one<float, float>), grid, block, 0, s, A.colptr, A.rowidx, v, N, k, U,
                                sigma, rank, static_cast<float *>(V));
     }
 }

@@ -1,25 +1,32 @@
 // ranky_api.cpp -- host runtime behind include/ranky.h: argument checks, the
-// workspace plan, stream-ordered enqueue of the kernels and status read-back.
+// workspace plan, a batch engine that drives every kernel over a table of
+// per-matrix descriptors (a single matrix is a batch of one), and status read-back.
 #include "ranky.h"
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <vector>
 
+#include "batch.hpp"
 #include "common.hpp"
 #include "launch.hpp"
 #include "launch_util.hpp"
 
 struct ranky_ctx {
-    int device;
-    int cu_count;
-    size_t lds_limit;   // dynamic LDS the Gram kernel may use per workgroup
-    int32_t *pinned;    // host pinned read-back of the device scalars
-    hipEvent_t ev[9];
+    int device = 0;
+    int cu_count = 0;
+    size_t lds_limit = 0;      // dynamic LDS the Gram kernel may use per workgroup
+    void *pinned = nullptr;    // host staging for descriptor uploads and scalar read-back
+    size_t pinned_bytes = 0;
+    hipEvent_t ev[9] = {};
+    hipGraphExec_t sweep_graph = nullptr;  // captured Jacobi sweep of the last graph batch
+    const void *sweep_graph_key = nullptr;
+    size_t sweep_graph_sig = 0;
 };
 
 namespace {
@@ -30,7 +37,7 @@ thread_local char g_err[512] = "";
 constexpr int32_t kMaxM = 8192;
 constexpr int32_t kDefaultSweeps = 40;
 constexpr int32_t kInnerSweeps = 1;
-constexpr double kEps = 2.220446049250313e-16;
+constexpr int32_t kMaxRefineK = 1024;
 
 ranky_status fail(ranky_status st, const char *fmt, ...) {
     va_list ap;
@@ -40,27 +47,29 @@ ranky_status fail(ranky_status st, const char *fmt, ...) {
     return st;
 }
 
-#define HIP_TRY(expr)                                                                        \
-    do {                                                                                     \
-        hipError_t e_ = (expr);                                                              \
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
         if (e_ != hipSuccess) return fail(RANKY_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
-int32_t round_up64(int32_t x) { return jacobi_npad(x); }  // padded order of the eigensolver
 
-// Workspace plan: offsets of every device array for the given sizes.
+// ---------------------------------------------------------------------------
+// per-matrix workspace plan
+// ---------------------------------------------------------------------------
+
 struct Plan {
     int32_t M = 0, k = 0, D = 0, cpb = 0, npad = 0;
     int64_t N = 0, nnz = 0, nchunks = 0;
-    size_t o_scal = 0, o_sdbl = 0, o_hist = 0, o_rownnz = 0, o_rowptr = 0, o_m2r = 0, o_r2m = 0, o_empty = 0;
-    size_t o_lonely = 0, o_single = 0, o_csrk = 0, o_csrend = 0, o_G = 0, o_G2 = 0, o_W = 0, o_J = 0, o_S = 0,
-           o_jflag = 0;
-    size_t o_lam = 0, o_perm = 0, o_csrcol = 0, o_U0 = 0, o_Z = 0, o_part = 0, o_Y = 0, o_seg = 0, total = 0;
-    bool refine = false;
+    size_t o_scal = 0, o_sdbl = 0, o_jstate = 0, o_hist = 0, o_rownnz = 0, o_rowptr = 0, o_m2r = 0, o_r2m = 0;
+    size_t o_empty = 0, o_lonely = 0, o_single = 0, o_csrk = 0, o_csrend = 0, o_csrcol = 0;
+    size_t o_G = 0, o_G2 = 0, o_W = 0, o_J = 0, o_S = 0, o_jflag = 0, o_lam = 0, o_perm = 0;
+    size_t o_U0 = 0, o_Z = 0, o_part = 0, o_Y = 0, o_seg = 0, total = 0;
+    bool solver = false, refine = false;
 };
 
-Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool with_solver, bool refine = false) {
+Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool solver, bool refine) {
     Plan p;
     p.M = M;
     p.N = N;
@@ -71,15 +80,17 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool wit
     p.cpb = (int32_t)((maxw + kChunkCols - 1) / kChunkCols);
     if (p.cpb < 1) p.cpb = 1;
     p.nchunks = (int64_t)D * p.cpb;
-    p.npad = round_up64(M);
+    p.npad = jacobi_npad(M);
     size_t off = 0;
     auto take = [&](size_t bytes) {
-        size_t o = off;
+        const size_t o = off;
         off = align_up(off + bytes);
         return o;
     };
+    const size_t nz = (size_t)(nnz > 0 ? nnz : 1);
     p.o_scal = take(sizeof(int32_t) * kScCount);
     p.o_sdbl = take(sizeof(double) * kSdCount);
+    p.o_jstate = take(sizeof(int32_t) * kJsCount);
     p.o_hist = take(sizeof(int32_t) * (size_t)p.nchunks * M);
     p.o_rownnz = take(sizeof(int32_t) * M);
     p.o_rowptr = take(sizeof(int32_t) * (M + 1));
@@ -88,11 +99,12 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool wit
     p.o_empty = take(sizeof(int32_t) * M);
     p.o_lonely = take(sizeof(int32_t) * D);
     p.o_single = take(sizeof(int32_t) * D);
-    p.o_csrk = take(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
-    p.o_csrend = take(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
-    p.o_csrcol = take(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    p.o_csrk = take(sizeof(int32_t) * nz);
+    p.o_csrend = take(sizeof(int32_t) * nz);
+    p.o_csrcol = take(sizeof(int32_t) * nz);
     p.o_G = take(sizeof(double) * (size_t)p.npad * p.npad);
-    if (with_solver) {
+    if (solver) {
+        p.solver = true;
         const size_t npairs = (size_t)(p.npad / kJacobiPair);
         p.o_G2 = take(sizeof(double) * (size_t)p.npad * p.npad);
         p.o_W = take(sizeof(double) * (size_t)p.npad * p.npad);
@@ -114,42 +126,89 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool wit
     return p;
 }
 
-struct Ptrs {
-    int32_t *scal, *hist, *rownnz, *rowptr, *m2r, *r2m, *empty, *lonely, *single, *csrk, *csrend, *csrcol, *jflag,
-        *perm, *seg;
-    double *sdbl, *G, *G2, *W, *J, *S, *lam, *U0, *Z, *part, *Y;
+struct Refine {
+    double *U0 = nullptr, *Z = nullptr, *part = nullptr, *Y = nullptr;
+    int32_t *seg = nullptr;
 };
 
-Ptrs carve(const Plan &p, void *ws) {
-    char *b = static_cast<char *>(ws);
-    Ptrs q;
-    q.scal = reinterpret_cast<int32_t *>(b + p.o_scal);
-    q.sdbl = reinterpret_cast<double *>(b + p.o_sdbl);
-    q.hist = reinterpret_cast<int32_t *>(b + p.o_hist);
-    q.rownnz = reinterpret_cast<int32_t *>(b + p.o_rownnz);
-    q.rowptr = reinterpret_cast<int32_t *>(b + p.o_rowptr);
-    q.m2r = reinterpret_cast<int32_t *>(b + p.o_m2r);
-    q.r2m = reinterpret_cast<int32_t *>(b + p.o_r2m);
-    q.empty = reinterpret_cast<int32_t *>(b + p.o_empty);
-    q.lonely = reinterpret_cast<int32_t *>(b + p.o_lonely);
-    q.single = reinterpret_cast<int32_t *>(b + p.o_single);
-    q.csrk = reinterpret_cast<int32_t *>(b + p.o_csrk);
-    q.csrend = reinterpret_cast<int32_t *>(b + p.o_csrend);
-    q.csrcol = reinterpret_cast<int32_t *>(b + p.o_csrcol);
-    q.U0 = p.refine ? reinterpret_cast<double *>(b + p.o_U0) : nullptr;
-    q.Z = p.refine ? reinterpret_cast<double *>(b + p.o_Z) : nullptr;
-    q.part = p.refine ? reinterpret_cast<double *>(b + p.o_part) : nullptr;
-    q.Y = p.refine ? reinterpret_cast<double *>(b + p.o_Y) : nullptr;
-    q.seg = p.refine ? reinterpret_cast<int32_t *>(b + p.o_seg) : nullptr;
-    q.G = reinterpret_cast<double *>(b + p.o_G);
-    q.G2 = reinterpret_cast<double *>(b + p.o_G2);
-    q.W = reinterpret_cast<double *>(b + p.o_W);
-    q.J = reinterpret_cast<double *>(b + p.o_J);
-    q.S = reinterpret_cast<double *>(b + p.o_S);
-    q.jflag = reinterpret_cast<int32_t *>(b + p.o_jflag);
-    q.lam = reinterpret_cast<double *>(b + p.o_lam);
-    q.perm = reinterpret_cast<int32_t *>(b + p.o_perm);
-    return q;
+// Descriptor of one matrix with its workspace carved at `base`.
+MatDesc carve(const Plan &p, char *base, Refine *rf) {
+    MatDesc d;
+    std::memset(&d, 0, sizeof(d));
+    auto i32 = [&](size_t o) { return reinterpret_cast<int32_t *>(base + o); };
+    auto f64 = [&](size_t o) { return reinterpret_cast<double *>(base + o); };
+    d.M = p.M;
+    d.N = p.N;
+    d.nnz = p.nnz;
+    d.k = p.k;
+    d.D = p.D;
+    d.cpb = p.cpb;
+    d.nchunks = p.nchunks;
+    d.npad = kJacobiPair;
+    d.scal = i32(p.o_scal);
+    d.sdbl = f64(p.o_sdbl);
+    d.jstate = i32(p.o_jstate);
+    d.hist = i32(p.o_hist);
+    d.rownnz = i32(p.o_rownnz);
+    d.rowptr = i32(p.o_rowptr);
+    d.m2r = i32(p.o_m2r);
+    d.r2m = i32(p.o_r2m);
+    d.empty = i32(p.o_empty);
+    d.lonely = i32(p.o_lonely);
+    d.single = i32(p.o_single);
+    d.csrk = i32(p.o_csrk);
+    d.csrend = i32(p.o_csrend);
+    d.csrcol = i32(p.o_csrcol);
+    d.G = f64(p.o_G);
+    if (p.solver) {
+        d.G2 = f64(p.o_G2);
+        d.W = f64(p.o_W);
+        d.J = f64(p.o_J);
+        d.S = f64(p.o_S);
+        d.jflag = i32(p.o_jflag);
+        d.lam = f64(p.o_lam);
+        d.perm = i32(p.o_perm);
+    }
+    if (rf && p.refine) {
+        rf->U0 = f64(p.o_U0);
+        rf->Z = f64(p.o_Z);
+        rf->part = f64(p.o_part);
+        rf->Y = f64(p.o_Y);
+        rf->seg = i32(p.o_seg);
+    }
+    return d;
+}
+
+// ---------------------------------------------------------------------------
+// batch header: device descriptor table, workgroup maps, round tables, read-back
+// ---------------------------------------------------------------------------
+
+enum Phase { kPhChunks, kPhRows, kPhGram, kPhJinit, kPhJcheck, kPhJdiag, kPhGather, kPhBack, kPhCount };
+
+struct Header {
+    size_t o_desc = 0, o_wp = 0, o_rwp = 0, o_rtab = 0, o_col_i = 0, o_col_f = 0, total = 0;
+    int32_t count = 0, slots = 0, nb_max = 0;
+};
+
+Header make_header(int32_t count, int32_t slots, int32_t nb_max) {
+    Header h;
+    h.count = count;
+    h.slots = slots;
+    h.nb_max = nb_max;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    h.o_desc = take(sizeof(MatDesc) * slots);
+    h.o_wp = take(sizeof(int32_t) * (size_t)kPhCount * (slots + 1));
+    h.o_rwp = take(sizeof(int32_t) * (size_t)nb_max * (slots + 1));
+    h.o_rtab = take(round_args_bytes() * (size_t)nb_max * slots);
+    h.o_col_i = take(sizeof(int32_t) * 8 * slots);
+    h.o_col_f = take(sizeof(double) * 2 * slots);
+    h.total = off;
+    return h;
 }
 
 int32_t default_blocks(int64_t N) {
@@ -159,13 +218,10 @@ int32_t default_blocks(int64_t N) {
     return (int32_t)d;
 }
 
-constexpr int32_t kMaxRefineK = 1024;
-
-ranky_opts resolved(const ranky_opts *in, int64_t N) {
+ranky_opts resolved(const ranky_opts *in) {
     ranky_opts o;
     ranky_default_opts(&o);
     if (in) o = *in;
-    if (o.n_blocks == 0) o.n_blocks = default_blocks(N);
     if (o.max_sweeps <= 0) o.max_sweeps = kDefaultSweeps;
     return o;
 }
@@ -177,99 +233,472 @@ ranky_status check_csc_args(const ranky_csc *A, int32_t M, int64_t N) {
     if (M < 1 || N < 1) return fail(RANKY_E_INVALID, "M=%d N=%lld must be >= 1", M, (long long)N);
     if (M > kMaxM) return fail(RANKY_E_INVALID, "M=%d exceeds %d", M, kMaxM);
     if (N > (int64_t)0x7ffffffe) return fail(RANKY_E_INVALID, "N=%lld exceeds int32 column pointers", (long long)N);
-    if (A->nnz < 0 || A->nnz > (int64_t)0x7fffffff) return fail(RANKY_E_INVALID, "nnz=%lld out of range", (long long)A->nnz);
-    if (!A->colptr || (A->nnz > 0 && (!A->rowidx || !A->values)))
-        return fail(RANKY_E_INVALID, "NULL CSC array");
+    if (A->nnz < 0 || A->nnz > (int64_t)0x7fffffff)
+        return fail(RANKY_E_INVALID, "nnz=%lld out of range", (long long)A->nnz);
+    if (!A->colptr || (A->nnz > 0 && (!A->rowidx || !A->values))) return fail(RANKY_E_INVALID, "NULL CSC array");
     if (A->dtype != RANKY_F32 && A->dtype != RANKY_F64) return fail(RANKY_E_INVALID, "bad dtype %d", A->dtype);
     return RANKY_OK;
 }
 
-CscView view(const ranky_csc *A) {
-    CscView v;
-    v.nnz = A->nnz;
-    v.colptr = A->colptr;
-    v.rowidx = A->rowidx;
-    v.values = A->values;
-    v.dtype = A->dtype;
-    return v;
-}
-
-// Runs the occupancy pass and reads back the status word and M'.
-ranky_status run_occupancy(ranky_ctx *ctx, const Plan &p, const Ptrs &w, const CscView &A, int32_t validate,
-                           int32_t *cnt, int32_t *lonely, int32_t *single, int32_t *rownnz, hipStream_t s,
-                           int32_t *n_out) {
-    launch_fill_i32(w.scal, kScCount, 0, s);
-    launch_fill_i32(lonely, p.D, 0, s);
-    launch_fill_i32(single, p.D, 0, s);
-    launch_occupancy(A, p.M, p.N, p.D, p.cpb, p.nchunks, validate, w.hist, rownnz, cnt, lonely, single, w.rowptr,
-                     w.m2r, w.r2m, w.empty, w.scal, s);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(ctx->pinned, w.scal, sizeof(int32_t) * kScCount, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    const int32_t st = ctx->pinned[kScStatus];
-    if (st & kStCsc) return fail(RANKY_E_CSC, "CSC contract violated (colptr, row range or row order)");
-    if (st & kStNonfinite) return fail(RANKY_E_NONFINITE, "non-finite value in A");
-    *n_out = ctx->pinned[kScNonempty];
+ranky_status check_opts(const ranky_opts &o) {
+    if (o.gram_prec != RANKY_PREC_FP64 && o.gram_prec != RANKY_PREC_FP32)
+        return fail(RANKY_E_INVALID, "gram_prec=%d", o.gram_prec);
+    if (o.v_dtype != RANKY_F32 && o.v_dtype != RANKY_F64) return fail(RANKY_E_INVALID, "v_dtype=%d", o.v_dtype);
+    if (o.refine < 0 || o.refine > 1) return fail(RANKY_E_INVALID, "refine=%d (0 or 1)", o.refine);
     return RANKY_OK;
 }
 
-// Blocked Jacobi on G (leading n x n of an npad x npad array in w.G, ld = npad); on
-// return *Gcur points at the buffer (w.G or w.G2) that holds the rotated matrix, W
-// holds the eigenvectors and lam the eigenvalues.
-ranky_status run_jacobi(ranky_ctx *ctx, const Ptrs &w, int32_t n, int32_t max_sweeps, hipStream_t s,
-                        int32_t *sweeps_out) {
-    const int32_t npad = round_up64(n);
-    const int64_t ld = npad;
-    const int32_t nb = npad / (kJacobiPair / 2);
-    const int32_t npairs = nb / 2;
-    const size_t jsz = (size_t)npairs * kJacobiPair * kJacobiPair;
-    const double tol = std::fmax(1e-15, std::sqrt((double)n) * kEps);
-    launch_jacobi_init(w.W, npad, w.G, ld, n, w.sdbl, s);
-    double *buf[2] = {w.G, w.G2};
-    int cur = 0;
-    int32_t sweeps = 0;
-    bool converged = false;
-    for (;;) {
-        launch_fill_i32(w.scal + kScNotConv, 1, 0, s);
-        launch_jacobi_check(buf[cur], ld, n, tol, w.sdbl, w.scal, s);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(ctx->pinned + kScNotConv, w.scal + kScNotConv, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (ctx->pinned[kScNotConv] == 0) {
-            converged = true;
-            break;
-        }
-        if (sweeps >= max_sweeps) break;
-        for (int32_t r = 0; r <= nb - 1; ++r) {  // r = nb - 1 is the flush of the last round
-            JacobiRound jr;
-            jr.Gin = buf[cur];
-            jr.Gout = buf[cur ^ 1];
-            jr.W = w.W;
-            jr.ld = ld;
-            jr.npad = npad;
-            jr.round_cur = r;
-            jr.round_prev = r - 1;
-            jr.has_prev = r > 0;
-            jr.do_solve = r < nb - 1;
-            jr.Jprev = w.J + ((r + 1) & 1) * jsz;
-            jr.Sprev = w.S + ((r + 1) & 1) * jsz;
-            jr.fprev = w.jflag + ((r + 1) & 1) * npairs;
-            jr.Jcur = w.J + (r & 1) * jsz;
-            jr.Scur = w.S + (r & 1) * jsz;
-            jr.fcur = w.jflag + (r & 1) * npairs;
-            jr.sdbl = w.sdbl;
-            jr.tol = tol;
-            jr.inner_sweeps = npairs == 1 ? 40 : 1;
-            launch_jacobi_round(jr, s);
-            if (jr.has_prev) cur ^= 1;
-        }
-        HIP_TRY(hipGetLastError());
-        sweeps += 1;
+// One matrix of a job (host view).
+struct Job {
+    ranky_csc A;
+    int64_t N;
+    int32_t M, k, D;
+    double *sigma, *U;
+    void *V;
+};
+
+ranky_status ensure_pinned(ranky_ctx *ctx, size_t bytes) {
+    if (ctx->pinned_bytes >= bytes) return RANKY_OK;
+    if (ctx->pinned) hipHostFree(ctx->pinned);
+    ctx->pinned = nullptr;
+    ctx->pinned_bytes = 0;
+    const size_t want = std::max<size_t>(bytes, 1 << 16);
+    HIP_TRY(hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault));
+    ctx->pinned_bytes = want;
+    return RANKY_OK;
+}
+
+// Fills the workgroup prefix for one phase: wp[i+1] = wp[i] + blocks(i).
+template <typename F>
+int64_t fill_wp(int32_t *wp, int count, F blocks) {
+    wp[0] = 0;
+    for (int i = 0; i < count; ++i) wp[i + 1] = wp[i] + (int32_t)blocks(i);
+    return wp[count];
+}
+
+// Drives the kernels for `count` matrices whose descriptors live in a device header.
+// Every staging write is followed by its upload and, before the staging area is
+// reused, by a read-back that synchronises the stream.
+struct Engine {
+    ranky_ctx *ctx = nullptr;
+    hipStream_t s = nullptr;
+    int count = 0;
+    std::vector<MatDesc> d;          // host copies
+    std::vector<int32_t> status;     // per matrix ranky_status so far
+    std::vector<int32_t> sweeps, notconv;
+    Header h;
+    char *hdr = nullptr;             // device header base
+    int64_t nblk[kPhCount] = {};
+    std::vector<int64_t> rblk;
+    int32_t maxM = 1, maxn = 1, nb_max = 0;
+    int32_t sweeps_cap = kDefaultSweeps;
+
+    char *stage() { return static_cast<char *>(ctx->pinned); }
+    MatDesc *ddesc() { return reinterpret_cast<MatDesc *>(hdr + h.o_desc); }
+    int32_t *dwp(int ph) { return reinterpret_cast<int32_t *>(hdr + h.o_wp) + (size_t)ph * (h.slots + 1); }
+    int32_t *drwp(int r) { return reinterpret_cast<int32_t *>(hdr + h.o_rwp) + (size_t)r * (h.slots + 1); }
+    void *drtab(int r) { return hdr + h.o_rtab + round_args_bytes() * (size_t)r * h.slots; }
+    int32_t *hwp(int ph) { return reinterpret_cast<int32_t *>(stage() + h.o_wp) + (size_t)ph * (h.slots + 1); }
+    int32_t *hrwp(int r) { return reinterpret_cast<int32_t *>(stage() + h.o_rwp) + (size_t)r * (h.slots + 1); }
+    char *hrtab(int r) { return stage() + h.o_rtab + round_args_bytes() * (size_t)r * h.slots; }
+
+    ranky_status upload(size_t from, size_t bytes) {
+        HIP_TRY(hipMemcpyAsync(hdr + from, stage() + from, bytes, hipMemcpyHostToDevice, s));
+        return RANKY_OK;
     }
-    launch_jacobi_diag(buf[cur], ld, n, w.lam, s);
+    ranky_status upload_desc() {
+        std::memcpy(stage() + h.o_desc, d.data(), sizeof(MatDesc) * count);
+        return upload(h.o_desc, sizeof(MatDesc) * count);
+    }
+    // compact per-matrix scalars (blocking)
+    ranky_status collect(std::vector<int32_t> &iv, std::vector<double> &fv) {
+        int32_t *ci = reinterpret_cast<int32_t *>(hdr + h.o_col_i);
+        double *cf = reinterpret_cast<double *>(hdr + h.o_col_f);
+        launch_batch_collect(ddesc(), count, ci, cf, s);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(stage() + h.o_col_i, ci, sizeof(int32_t) * 8 * count, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(stage() + h.o_col_f, cf, sizeof(double) * 2 * count, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const int32_t *pi = reinterpret_cast<const int32_t *>(stage() + h.o_col_i);
+        const double *pf = reinterpret_cast<const double *>(stage() + h.o_col_f);
+        iv.assign(pi, pi + 8 * count);
+        fv.assign(pf, pf + 2 * count);
+        return RANKY_OK;
+    }
+
+    // Alg. 1 scan, validation and structural rank of every matrix; sets n / npad.
+    ranky_status scan() {
+        for (const MatDesc &x : d) maxM = std::max(maxM, x.M);
+        nblk[kPhChunks] = fill_wp(hwp(kPhChunks), count, [&](int i) { return d[i].nchunks; });
+        nblk[kPhRows] = fill_wp(hwp(kPhRows), count, [&](int i) { return (int64_t)(d[i].M + 255) / 256; });
+        ranky_status st = upload_desc();
+        if (!st) st = upload(h.o_wp, sizeof(int32_t) * (size_t)kPhCount * (h.slots + 1));
+        if (st) return st;
+        launch_batch_prep(ddesc(), count, s);
+        launch_occupancy(ddesc(), dwp(kPhChunks), nblk[kPhChunks], dwp(kPhRows), nblk[kPhRows], count, maxM, s);
+        HIP_TRY(hipGetLastError());
+        std::vector<int32_t> iv;
+        std::vector<double> fv;
+        st = collect(iv, fv);
+        if (st) return st;
+        for (int i = 0; i < count; ++i) {
+            const int32_t bits = iv[8 * i];
+            if (bits & kStCsc) status[i] = RANKY_E_CSC;
+            else if (bits & kStNonfinite) status[i] = RANKY_E_NONFINITE;
+            d[i].n = status[i] == RANKY_OK ? iv[8 * i + 1] : 0;
+            d[i].n_tau = d[i].n;
+            d[i].npad = jacobi_npad(d[i].n > 0 ? d[i].n : 1);
+            maxn = std::max(maxn, d[i].n);
+        }
+        return RANKY_OK;
+    }
+
+    bool live(int i) const { return status[i] == RANKY_OK && d[i].n > 0; }
+
+    // Maps of every later phase and the round tables; one upload.
+    ranky_status plan_rest() {
+        nblk[kPhGram] = fill_wp(hwp(kPhGram), count, [&](int i) { return live(i) ? (int64_t)d[i].npad : 0; });
+        nblk[kPhJinit] = fill_wp(hwp(kPhJinit), count, [&](int i) -> int64_t {
+            if (!live(i)) return 0;
+            const int64_t sl = ((int64_t)d[i].npad * d[i].npad + 8191) / 8192;
+            return std::min<int64_t>(std::max<int64_t>(sl, 1), 64);
+        });
+        nblk[kPhJcheck] = fill_wp(hwp(kPhJcheck), count, [&](int i) { return live(i) ? (int64_t)std::min(d[i].n, 512) : 0; });
+        nblk[kPhJdiag] = fill_wp(hwp(kPhJdiag), count, [&](int i) { return live(i) ? (int64_t)(d[i].n + 255) / 256 : 0; });
+        nblk[kPhGather] = fill_wp(hwp(kPhGather), count, [&](int i) { return status[i] == RANKY_OK ? (int64_t)d[i].k : 0; });
+        nblk[kPhBack] = fill_wp(hwp(kPhBack), count, [&](int i) {
+            return status[i] == RANKY_OK ? backproject_blocks(d[i].N, ctx->cu_count) : (int64_t)0;
+        });
+        nb_max = 0;
+        for (int i = 0; i < count; ++i)
+            if (live(i)) nb_max = std::max(nb_max, d[i].npad / kJacobiBlock);
+        rblk.assign(nb_max, 0);
+        for (int r = 0; r < nb_max; ++r) {
+            rblk[r] = fill_wp(hrwp(r), count, [&](int i) { return live(i) ? round_blocks(d[i], r) : (int64_t)0; });
+            for (int i = 0; i < count; ++i) fill_round_args(hrtab(r) + round_args_bytes() * i, d[i], r, kInnerSweeps);
+        }
+        ranky_status st = upload_desc();
+        if (!st) st = upload(h.o_wp, sizeof(int32_t) * (size_t)kPhCount * (h.slots + 1));
+        if (!st && nb_max > 0) st = upload(h.o_rwp, sizeof(int32_t) * (size_t)nb_max * (h.slots + 1));
+        if (!st && nb_max > 0) st = upload(h.o_rtab, round_args_bytes() * (size_t)nb_max * h.slots);
+        return st;
+    }
+
+    void enqueue_transpose() {
+        launch_row_offsets(ddesc(), dwp(kPhRows), nblk[kPhRows], count, s);
+        launch_transpose(ddesc(), dwp(kPhChunks), nblk[kPhChunks], count, maxM, s);
+    }
+
+    void enqueue_sweep() {
+        launch_jacobi_check(ddesc(), dwp(kPhJcheck), nblk[kPhJcheck], count, s);
+        launch_jacobi_state(ddesc(), count, 0, sweeps_cap, s);
+        for (int r = 0; r < nb_max; ++r) launch_jacobi_round(drtab(r), drwp(r), rblk[r], count, r, s);
+        launch_jacobi_state(ddesc(), count, 1, sweeps_cap, s);
+    }
+
+    // Jacobi on every live matrix.  Each sweep = convergence test, activity update,
+    // nb_max round launches, sweep count; one read-back per sweep decides whether
+    // any matrix is still active.  With use_graph the sweep is a replayed HIP graph.
+    ranky_status eigensolve(bool use_graph) {
+        launch_jacobi_init(ddesc(), dwp(kPhJinit), nblk[kPhJinit], count, s);
+        HIP_TRY(hipGetLastError());
+        sweeps.assign(count, 0);
+        notconv.assign(count, 0);
+        if (nb_max == 0) return RANKY_OK;
+        hipGraphExec_t exec = nullptr;
+        if (use_graph && s != nullptr) {
+            size_t sig = (size_t)count * 1315423911u ^ (size_t)nb_max;
+            for (int r = 0; r < nb_max; ++r) sig = sig * 31 + (size_t)rblk[r];
+            for (int ph = 0; ph < kPhCount; ++ph) sig = sig * 31 + (size_t)nblk[ph];
+            if (ctx->sweep_graph && ctx->sweep_graph_key == hdr && ctx->sweep_graph_sig == sig) {
+                exec = ctx->sweep_graph;
+            } else {
+                if (ctx->sweep_graph) hipGraphExecDestroy(ctx->sweep_graph);
+                ctx->sweep_graph = nullptr;
+                hipGraph_t g = nullptr;
+                HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                enqueue_sweep();
+                HIP_TRY(hipStreamEndCapture(s, &g));
+                const hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+                hipGraphDestroy(g);
+                if (ie != hipSuccess) return fail(RANKY_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+                ctx->sweep_graph = exec;
+                ctx->sweep_graph_key = hdr;
+                ctx->sweep_graph_sig = sig;
+            }
+        }
+        std::vector<int32_t> iv;
+        std::vector<double> fv;
+        for (int32_t sw = 0; sw <= sweeps_cap; ++sw) {
+            if (exec) {
+                HIP_TRY(hipGraphLaunch(exec, s));
+            } else {
+                enqueue_sweep();
+                HIP_TRY(hipGetLastError());
+            }
+            ranky_status st = collect(iv, fv);
+            if (st) return st;
+            bool still = false;
+            for (int i = 0; i < count; ++i) still |= iv[8 * i + 7] != 0;
+            if (!still) break;
+        }
+        // convergence test of the final matrices, for the report
+        launch_jacobi_check(ddesc(), dwp(kPhJcheck), nblk[kPhJcheck], count, s);
+        ranky_status st = collect(iv, fv);
+        if (st) return st;
+        for (int i = 0; i < count; ++i) {
+            sweeps[i] = iv[8 * i + 3];
+            notconv[i] = iv[8 * i + 4];
+        }
+        launch_jacobi_diag(ddesc(), dwp(kPhJdiag), nblk[kPhJdiag], count, s);
+        HIP_TRY(hipGetLastError());
+        return RANKY_OK;
+    }
+};
+
+ranky_status make_engine(ranky_ctx *ctx, hipStream_t s, const Header &h, char *hdr, int count, Engine &e) {
+    ranky_status st = ensure_pinned(ctx, h.total);
+    if (st) return st;
+    e.ctx = ctx;
+    e.s = s;
+    e.count = count;
+    e.h = h;
+    e.hdr = hdr;
+    e.status.assign(count, RANKY_OK);
+    return RANKY_OK;
+}
+
+size_t path_bytes(const std::vector<Job> &jobs, const ranky_opts &o) {
+    const int count = (int)jobs.size();
+    const bool refine = count == 1 && wants_refine(o, jobs[0].k);
+    int32_t maxM = 1;
+    size_t total = 0;
+    for (const Job &j : jobs) {
+        total += make_plan(j.M, j.N, j.A.nnz, j.k, j.D, true, refine).total;
+        maxM = std::max(maxM, j.M);
+    }
+    return total + make_header(count, count, jacobi_npad(maxM) / kJacobiBlock).total;
+}
+
+// The whole path for a batch (Rayleigh-Ritz refinement only for a batch of one).
+ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, const ranky_opts &o, void *workspace,
+                      size_t ws_bytes, ranky_info *infos, hipStream_t s, bool use_graph) {
+    const int count = (int)jobs.size();
+    const bool refine = count == 1 && wants_refine(o, jobs[0].k);
+    std::vector<Plan> plans(count);
+    int32_t maxM = 1;
+    for (int i = 0; i < count; ++i) {
+        plans[i] = make_plan(jobs[i].M, jobs[i].N, jobs[i].A.nnz, jobs[i].k, jobs[i].D, true, refine);
+        maxM = std::max(maxM, jobs[i].M);
+    }
+    const Header h = make_header(count, count, jacobi_npad(maxM) / kJacobiBlock);
+    size_t need = h.total;
+    std::vector<size_t> base(count);
+    for (int i = 0; i < count; ++i) {
+        base[i] = need;
+        need += plans[i].total;
+    }
+    if (!workspace || ws_bytes < need) return fail(RANKY_E_NOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
+    char *ws = static_cast<char *>(workspace);
+    Engine e;
+    ranky_status st = make_engine(ctx, s, h, ws, count, e);
+    if (st) return st;
+    e.sweeps_cap = o.max_sweeps;
+    e.d.resize(count);
+    Refine rf;
+    for (int i = 0; i < count; ++i) {
+        const Job &j = jobs[i];
+        MatDesc &x = e.d[i];
+        x = carve(plans[i], ws + base[i], i == 0 ? &rf : nullptr);
+        x.colptr = j.A.colptr;
+        x.rowidx = j.A.rowidx;
+        x.values = j.A.values;
+        x.dtype = j.A.dtype;
+        x.v_dtype = o.v_dtype;
+        x.prec = o.gram_prec;
+        x.validate = o.validate;
+        x.tol = tol;
+        x.u_gram = (o.gram_prec == RANKY_PREC_FP64) ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
+        x.sigma = j.sigma;
+        x.U = refine ? rf.U0 : j.U;
+        x.V = j.V;
+    }
+    const bool timing = o.timing != 0 && count == 1;
+    if (timing) hipEventRecord(ctx->ev[0], s);
+    st = e.scan();
+    if (st) return st;
+    if (timing) hipEventRecord(ctx->ev[1], s);
+    st = e.plan_rest();
+    if (st) return st;
+    e.enqueue_transpose();
+    if (timing) hipEventRecord(ctx->ev[2], s);
+    launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], count, maxM, ctx->lds_limit, s);
     HIP_TRY(hipGetLastError());
-    if (sweeps_out) *sweeps_out = sweeps;
-    if (!converged) return fail(RANKY_E_NOT_CONVERGED, "Jacobi did not converge in %d sweeps", max_sweeps);
+    if (timing) hipEventRecord(ctx->ev[3], s);
+    st = e.eigensolve(use_graph);
+    if (st) return st;
+    if (timing) hipEventRecord(ctx->ev[4], s);
+    launch_select(e.ddesc(), count, e.maxn, s);
+    launch_gather_u(e.ddesc(), e.dwp(kPhGather), e.nblk[kPhGather], count, s);
+    HIP_TRY(hipGetLastError());
+    if (timing) hipEventRecord(ctx->ev[5], s);
+    std::vector<int32_t> iv;
+    std::vector<double> fv;
+    int32_t refine_sweeps = 0, refine_notconv = 0;
+    if (refine && e.status[0] == RANKY_OK) {
+        // Rayleigh-Ritz with the exact operator: H = U0^T (A A^T) U0 in FP64, eigensolved
+        // by the same engine on a descriptor for H, then U = U0 Q, sigma = sqrt(theta).
+        const MatDesc x = e.d[0];
+        const Job &j = jobs[0];
+        const CscView Av{j.A.nnz, j.A.colptr, j.A.rowidx, j.A.values, j.A.dtype};
+        const int32_t k = j.k;
+        if (x.n > 0) {
+            launch_rr_z(Av, j.N, k, rf.U0, rf.Z, ctx->cu_count, s);
+            launch_rr_rows(Av, x.rownnz, x.rowptr, j.M, j.A.nnz, k, x.csrk, x.csrcol, rf.Z, rf.seg, rf.part, rf.Y, s);
+        } else {
+            launch_fill_f64(rf.Y, (int64_t)j.M * k, 0.0, s);
+        }
+        const int32_t kpad = jacobi_npad(k);
+        launch_rr_h(rf.U0, rf.Y, j.M, k, kpad, x.G, s);
+        HIP_TRY(hipGetLastError());
+        // the main matrix's header entries are no longer read: reuse them for H
+        Engine eh;
+        st = make_engine(ctx, s, h, ws, 1, eh);
+        if (st) return st;
+        eh.sweeps_cap = o.max_sweeps;
+        eh.d.assign(1, x);
+        MatDesc &y = eh.d[0];
+        y.n = k;
+        y.npad = kpad;
+        y.n_tau = x.n;
+        y.k = k;
+        y.u_gram = std::ldexp(1.0, -53);
+        y.U = j.U;
+        eh.maxn = k;
+        st = eh.plan_rest();
+        if (st) return st;
+        st = eh.eigensolve(false);
+        if (st) return st;
+        refine_sweeps = eh.sweeps[0];
+        refine_notconv = eh.notconv[0];
+        launch_select(eh.ddesc(), 1, k, s);
+        launch_rr_apply(rf.U0, y.W, kpad, y.perm, j.M, k, j.U, s);
+        launch_backproject(Av, j.N, k, j.U, j.sigma, y.scal + kScRank, j.V, o.v_dtype, ctx->cu_count, s);
+        HIP_TRY(hipGetLastError());
+        e.d[0].U = j.U;
+        st = e.upload_desc();
+        if (st) return st;
+    }
+    if (timing) hipEventRecord(ctx->ev[6], s);
+    if (!refine) launch_backproject_batch(e.ddesc(), e.dwp(kPhBack), e.nblk[kPhBack], count, s);
+    HIP_TRY(hipGetLastError());
+    if (timing) hipEventRecord(ctx->ev[7], s);
+    st = e.collect(iv, fv);
+    if (st) return st;
+    ranky_status overall = RANKY_OK;
+    for (int i = 0; i < count; ++i) {
+        ranky_status si = static_cast<ranky_status>(e.status[i]);
+        if (si == RANKY_OK && (e.notconv[i] != 0 || refine_notconv != 0)) si = RANKY_E_NOT_CONVERGED;
+        if (si != RANKY_OK && overall == RANKY_OK) overall = si;
+        if (infos) {
+            ranky_info &in = infos[i];
+            std::memset(&in, 0, sizeof(in));
+            in.status = si;
+            in.rank = iv[8 * i + 2];
+            in.n_nonempty = e.d[i].n;
+            in.empty_rows = jobs[i].M - e.d[i].n;
+            in.sweeps = e.sweeps[i] + refine_sweeps;
+            in.n_blocks = jobs[i].D;
+            in.lonely_max = iv[8 * i + 5];
+            in.lonely_blocks = iv[8 * i + 6];
+            in.tau = fv[2 * i];
+            in.sigma_max = fv[2 * i + 1];
+            if (timing) {
+                float t = 0.f;
+                for (int q = 0; q < 7; ++q) {
+                    hipEventElapsedTime(&t, ctx->ev[q], ctx->ev[q + 1]);
+                    in.ms[q] = t;
+                }
+                hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[7]);
+                in.ms[7] = t;
+            }
+        }
+    }
+    if (overall == RANKY_E_CSC) return fail(RANKY_E_CSC, "CSC contract violated (colptr, row range or row order)");
+    if (overall == RANKY_E_NONFINITE) return fail(RANKY_E_NONFINITE, "non-finite value in A");
+    if (overall == RANKY_E_NOT_CONVERGED)
+        return fail(RANKY_E_NOT_CONVERGED, "Jacobi did not converge in %d sweeps", o.max_sweeps);
+    return overall;
+}
+
+ranky_status make_job(const ranky_csc *A, int32_t M, int64_t N, int32_t k, int32_t D, double *sigma, double *U,
+                      void *V, Job *out) {
+    ranky_status st = check_csc_args(A, M, N);
+    if (st) return st;
+    if (k < 1 || k > M) return fail(RANKY_E_INVALID, "k=%d must be in [1, M=%d]", k, M);
+    if (D == 0) D = default_blocks(N);
+    if (D < 1 || D > N) return fail(RANKY_E_INVALID, "n_blocks=%d outside [1, N]", D);
+    out->A = *A;
+    out->N = N;
+    out->M = M;
+    out->k = k;
+    out->D = D;
+    out->sigma = sigma;
+    out->U = U;
+    out->V = V;
+    return RANKY_OK;
+}
+
+// Context-free pieces for the step calls.
+struct StepCtx {
+    ranky_ctx c;
+    ~StepCtx() {
+        if (c.pinned) hipHostFree(c.pinned);
+    }
+};
+
+ranky_status step_device(StepCtx &sc) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    size_t lds = prop.sharedMemPerBlock;
+    if (lds > 160 * 1024) lds = 160 * 1024;
+    sc.c.lds_limit = lds > 4096 ? lds - 4096 : lds;
+    sc.c.cu_count = prop.multiProcessorCount;
+    HIP_TRY(occupancy_set_attributes(kMaxM));
+    HIP_TRY(gram_set_attributes(sc.c.lds_limit));
+    HIP_TRY(select_set_attributes());
+    return RANKY_OK;
+}
+
+ranky_status step_scan(StepCtx &sc, const ranky_csc *A, int32_t M, int64_t N, int32_t D, void *workspace,
+                       size_t ws_bytes, hipStream_t s, Engine &e, int32_t *cnt, int32_t *rownnz, int32_t *lonely,
+                       int32_t *single) {
+    const Plan p = make_plan(M, N, A->nnz, 1, D, false, false);
+    const Header h = make_header(1, 1, 1);
+    if (!workspace || ws_bytes < h.total + p.total)
+        return fail(RANKY_E_NOMEM, "workspace %zu < %zu", ws_bytes, h.total + p.total);
+    ranky_status st = step_device(sc);
+    if (st) return st;
+    char *ws = static_cast<char *>(workspace);
+    st = make_engine(&sc.c, s, h, ws, 1, e);
+    if (st) return st;
+    e.d.assign(1, carve(p, ws + h.total, nullptr));
+    MatDesc &x = e.d[0];
+    x.colptr = A->colptr;
+    x.rowidx = A->rowidx;
+    x.values = A->values;
+    x.dtype = A->dtype;
+    x.validate = 1;
+    if (cnt) x.cnt = cnt;
+    if (rownnz) x.rownnz = rownnz;
+    if (lonely) x.lonely = lonely;
+    if (single) x.single = single;
+    st = e.scan();
+    if (st) return st;
+    if (e.status[0] == RANKY_E_CSC) return fail(RANKY_E_CSC, "CSC contract violated (colptr, row range or row order)");
+    if (e.status[0] == RANKY_E_NONFINITE) return fail(RANKY_E_NONFINITE, "non-finite value in A");
     return RANKY_OK;
 }
 
@@ -278,7 +707,7 @@ ranky_status run_jacobi(ranky_ctx *ctx, const Ptrs &w, int32_t n, int32_t max_sw
 extern "C" {
 
 const char *ranky_last_error(void) { return g_err; }
-const char *ranky_version(void) { return "ranky-mi355x 0.1 (gfx950)"; }
+const char *ranky_version(void) { return "ranky-mi355x 0.2 (gfx950)"; }
 
 ranky_status ranky_default_opts(ranky_opts *o) {
     if (!o) return fail(RANKY_E_INVALID, "opts is NULL");
@@ -307,154 +736,122 @@ ranky_status ranky_ctx_create(int device, ranky_ctx **out) {
     size_t lds = prop.sharedMemPerBlock;
     if (lds > 160 * 1024) lds = 160 * 1024;
     c->lds_limit = lds > 4096 ? lds - 4096 : lds;  // room for the kernels' static LDS
-    void *pin = nullptr;
-    hipError_t e = hipHostMalloc(&pin, 4096, hipHostMallocDefault);
-    if (e != hipSuccess) {
-        delete c;
-        return fail(RANKY_E_DEVICE, "hipHostMalloc: %s", hipGetErrorString(e));
-    }
-    c->pinned = static_cast<int32_t *>(pin);
     for (auto &ev : c->ev) {
-        e = hipEventCreate(&ev);
-        if (e != hipSuccess) return fail(RANKY_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+        const hipError_t e = hipEventCreate(&ev);
+        if (e != hipSuccess) {
+            ranky_ctx_destroy(c);
+            return fail(RANKY_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+        }
     }
-    e = occupancy_set_attributes(kMaxM);
+    hipError_t e = occupancy_set_attributes(kMaxM);
     if (e == hipSuccess) e = gram_set_attributes(c->lds_limit);
     if (e == hipSuccess) e = select_set_attributes();
-    if (e != hipSuccess) return fail(RANKY_E_DEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(e));
+    if (e != hipSuccess) {
+        ranky_ctx_destroy(c);
+        return fail(RANKY_E_DEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(e));
+    }
     *out = c;
     return RANKY_OK;
 }
 
 ranky_status ranky_ctx_destroy(ranky_ctx *ctx) {
     if (!ctx) return RANKY_OK;
-    for (auto &ev : ctx->ev) hipEventDestroy(ev);
-    hipHostFree(ctx->pinned);
+    for (auto &ev : ctx->ev)
+        if (ev) hipEventDestroy(ev);
+    if (ctx->sweep_graph) hipGraphExecDestroy(ctx->sweep_graph);
+    if (ctx->pinned) hipHostFree(ctx->pinned);
     delete ctx;
     return RANKY_OK;
 }
 
 size_t ranky_workspace_bytes(int32_t M, int64_t N, int64_t nnz, int32_t k, const ranky_opts *opts) {
     if (M < 1 || N < 1 || k < 1 || k > M || M > kMaxM || nnz < 0) return 0;
-    const ranky_opts o = resolved(opts, N);
-    if (o.n_blocks < 1 || o.n_blocks > N) return 0;
-    return make_plan(M, N, nnz, k, o.n_blocks, true, wants_refine(o, k)).total;
-}
-
-size_t ranky_step_workspace_bytes(int32_t M, int64_t N, int64_t nnz, int32_t D) {
-    if (M < 1 || N < 1 || M > kMaxM || nnz < 0 || D < 1 || D > N) return 0;
-    return make_plan(M, N, nnz, 1, D, false).total;
+    const ranky_opts o = resolved(opts);
+    const int32_t D = o.n_blocks == 0 ? default_blocks(N) : o.n_blocks;
+    if (D < 1 || D > N) return 0;
+    Job j;
+    std::memset(&j, 0, sizeof(j));
+    j.A.nnz = nnz;
+    j.M = M;
+    j.N = N;
+    j.k = k;
+    j.D = D;
+    return path_bytes({j}, o);
 }
 
 ranky_status ranky_svd(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N, int32_t k, double tol,
                        const ranky_opts *opts, void *workspace, size_t ws_bytes, double *sigma, double *U, void *V,
                        ranky_info *info, ranky_stream_t stream) {
-    if (info) std::memset(info, 0, sizeof(*info));
+    ranky_info local;
+    ranky_info *inf = info ? info : &local;
+    std::memset(inf, 0, sizeof(*inf));
     auto finish = [&](ranky_status st) {
-        if (info) info->status = st;
+        if (inf->status == RANKY_OK) inf->status = st;
         return st;
     };
     if (!ctx) return finish(fail(RANKY_E_INVALID, "ctx is NULL"));
-    ranky_status st = check_csc_args(A, M, N);
-    if (st) return finish(st);
-    if (k < 1 || k > M) return finish(fail(RANKY_E_INVALID, "k=%d must be in [1, M=%d]", k, M));
     if (!(tol >= 0.0)) return finish(fail(RANKY_E_INVALID, "tol must be >= 0"));
     if (!sigma || !U || !V) return finish(fail(RANKY_E_INVALID, "NULL output"));
-    const ranky_opts o = resolved(opts, N);
-    if (o.n_blocks < 1 || o.n_blocks > N) return finish(fail(RANKY_E_INVALID, "n_blocks=%d outside [1, N]", o.n_blocks));
-    if (o.gram_prec != RANKY_PREC_FP64 && o.gram_prec != RANKY_PREC_FP32)
-        return finish(fail(RANKY_E_INVALID, "gram_prec=%d", o.gram_prec));
-    if (o.v_dtype != RANKY_F32 && o.v_dtype != RANKY_F64) return finish(fail(RANKY_E_INVALID, "v_dtype=%d", o.v_dtype));
-    if (o.refine < 0 || o.refine > 1) return finish(fail(RANKY_E_INVALID, "refine=%d (0 or 1)", o.refine));
-    if (o.refine && k > kMaxRefineK) return finish(fail(RANKY_E_INVALID, "refine needs k <= %d", kMaxRefineK));
-    const bool refine = wants_refine(o, k);
-    const Plan p = make_plan(M, N, A->nnz, k, o.n_blocks, true, refine);
-    if (!workspace || ws_bytes < p.total)
-        return finish(fail(RANKY_E_NOMEM, "workspace %zu bytes < %zu needed", ws_bytes, p.total));
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if (hipSetDevice(ctx->device) != hipSuccess) return finish(fail(RANKY_E_DEVICE, "hipSetDevice"));
-    const Ptrs w = carve(p, workspace);
-    const CscView Av = view(A);
-    const bool timing = o.timing != 0;
-    if (timing) hipEventRecord(ctx->ev[0], s);
-
-    int32_t n = 0;
-    st = run_occupancy(ctx, p, w, Av, o.validate, nullptr, w.lonely, w.single, w.rownnz, s, &n);
+    const ranky_opts o = resolved(opts);
+    ranky_status st = check_opts(o);
     if (st) return finish(st);
-    if (timing) hipEventRecord(ctx->ev[1], s);
-    int32_t sweeps = 0;
-    const int32_t npad = round_up64(n > 0 ? n : 1);
-    if (n > 0) {
-        launch_row_offsets(w.hist, w.rowptr, M, p.nchunks, s);
-        launch_transpose(Av, M, N, p.D, p.cpb, p.nchunks, w.hist, w.csrk, w.csrend, w.csrcol, s);
-        if (timing) hipEventRecord(ctx->ev[2], s);
-        launch_gram(Av, M, n, npad, npad, w.rowptr, w.r2m, w.csrk, w.csrend, w.G, o.gram_prec, ctx->lds_limit, s);
-        if (hipGetLastError() != hipSuccess) return finish(fail(RANKY_E_DEVICE, "Gram launch failed"));
-        if (timing) hipEventRecord(ctx->ev[3], s);
-        st = run_jacobi(ctx, w, n, o.max_sweeps, s, &sweeps);
-        if (st) return finish(st);
-    } else if (timing) {
-        hipEventRecord(ctx->ev[2], s);
-        hipEventRecord(ctx->ev[3], s);
+    Job j;
+    st = make_job(A, M, N, k, o.n_blocks, sigma, U, V, &j);
+    if (st) return finish(st);
+    if (o.refine && k > kMaxRefineK) return finish(fail(RANKY_E_INVALID, "refine needs k <= %d", kMaxRefineK));
+    if (hipSetDevice(ctx->device) != hipSuccess) return finish(fail(RANKY_E_DEVICE, "hipSetDevice"));
+    return finish(run_path(ctx, {j}, tol, o, workspace, ws_bytes, inf, reinterpret_cast<hipStream_t>(stream), false));
+}
+
+size_t ranky_batch_workspace_bytes(int32_t count, const ranky_batch_item *items, const ranky_opts *opts) {
+    if (count < 1 || !items) return 0;
+    ranky_opts o = resolved(opts);
+    o.refine = 0;
+    std::vector<Job> jobs(count);
+    for (int i = 0; i < count; ++i) {
+        const ranky_batch_item &it = items[i];
+        if (it.M < 1 || it.N < 1 || it.k < 1 || it.k > it.M || it.M > kMaxM || it.A.nnz < 0) return 0;
+        const int32_t D = it.n_blocks == 0 ? default_blocks(it.N) : it.n_blocks;
+        if (D < 1 || D > it.N) return 0;
+        std::memset(&jobs[i], 0, sizeof(Job));
+        jobs[i].A.nnz = it.A.nnz;
+        jobs[i].M = it.M;
+        jobs[i].N = it.N;
+        jobs[i].k = it.k;
+        jobs[i].D = D;
     }
-    if (timing) hipEventRecord(ctx->ev[4], s);
-    const double u64 = std::ldexp(1.0, -53);
-    const double u_gram = (o.gram_prec == RANKY_PREC_FP64 || refine) ? u64 : std::ldexp(1.0, -24);
-    launch_select(w.lam, n, k, n, tol, u_gram, w.perm, sigma, w.scal, w.sdbl, s);
-    launch_gather_u(w.W, npad, n, M, k, w.perm, w.m2r, w.empty, refine ? w.U0 : U, s);
-    if (timing) hipEventRecord(ctx->ev[5], s);
-    if (refine) {
-        // Rayleigh-Ritz with the exact operator: H = U0^T (A A^T) U0 in FP64
-        if (n > 0) {
-            launch_rr_z(Av, N, k, w.U0, w.Z, ctx->cu_count, s);
-            launch_rr_rows(Av, w.rownnz, w.rowptr, M, A->nnz, k, w.csrk, w.csrcol, w.Z, w.seg, w.part, w.Y, s);
-        } else {
-            launch_fill_f64(w.Y, (int64_t)M * k, 0.0, s);
-        }
-        const int32_t kpad = round_up64(k);
-        launch_rr_h(w.U0, w.Y, M, k, kpad, w.G, s);
-        if (hipGetLastError() != hipSuccess) return finish(fail(RANKY_E_DEVICE, "refine launch failed"));
-        int32_t sw2 = 0;
-        st = run_jacobi(ctx, w, k, o.max_sweeps, s, &sw2);
-        if (st) return finish(st);
-        sweeps += sw2;
-        launch_select(w.lam, k, k, n, tol, u64, w.perm, sigma, w.scal, w.sdbl, s);
-        launch_rr_apply(w.U0, w.W, kpad, w.perm, M, k, U, s);
+    return path_bytes(jobs, o);
+}
+
+ranky_status ranky_batch(ranky_ctx *ctx, int32_t count, const ranky_batch_item *items, double tol,
+                         const ranky_opts *opts, void *workspace, size_t ws_bytes, ranky_info *infos,
+                         ranky_stream_t stream) {
+    if (!ctx) return fail(RANKY_E_INVALID, "ctx is NULL");
+    if (count < 1 || !items) return fail(RANKY_E_INVALID, "empty batch");
+    if (!(tol >= 0.0)) return fail(RANKY_E_INVALID, "tol must be >= 0");
+    const ranky_opts o = resolved(opts);
+    ranky_status st = check_opts(o);
+    if (st) return st;
+    if (o.refine) return fail(RANKY_E_INVALID, "ranky_batch runs without refinement (use ranky_svd per matrix)");
+    std::vector<Job> jobs(count);
+    for (int i = 0; i < count; ++i) {
+        const ranky_batch_item &it = items[i];
+        if (!it.sigma || !it.U || !it.V) return fail(RANKY_E_INVALID, "item %d: NULL output", i);
+        st = make_job(&it.A, it.M, it.N, it.k, it.n_blocks, it.sigma, it.U, it.V, &jobs[i]);
+        if (st) return st;
     }
-    if (timing) hipEventRecord(ctx->ev[6], s);
-    launch_backproject(Av, N, k, U, sigma, w.scal + kScRank, V, o.v_dtype, ctx->cu_count, s);
-    if (timing) hipEventRecord(ctx->ev[7], s);
-    if (hipGetLastError() != hipSuccess) return finish(fail(RANKY_E_DEVICE, "kernel launch failed"));
-    HIP_TRY(hipMemcpyAsync(ctx->pinned, w.scal, sizeof(int32_t) * kScCount, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(ctx->pinned + kScCount, w.sdbl, sizeof(double) * kSdCount, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (info) {
-        const double *sd = reinterpret_cast<const double *>(ctx->pinned + kScCount);
-        info->rank = ctx->pinned[kScRank];
-        info->n_nonempty = n;
-        info->empty_rows = M - n;
-        info->sweeps = sweeps;
-        info->n_blocks = p.D;
-        info->tau = sd[kSdTau];
-        info->sigma_max = sd[kSdSigmaMax];
-        std::vector<int32_t> lon(p.D);
-        HIP_TRY(hipMemcpy(lon.data(), w.lonely, sizeof(int32_t) * p.D, hipMemcpyDeviceToHost));
-        for (int32_t b = 0; b < p.D; ++b) {
-            if (lon[b] > info->lonely_max) info->lonely_max = lon[b];
-            info->lonely_blocks += lon[b] > 0;
-        }
-        if (timing) {
-            float t = 0.f;
-            const int pairs[7][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {5, 6}, {6, 7}};
-            for (int i = 0; i < 7; ++i) {
-                hipEventElapsedTime(&t, ctx->ev[pairs[i][0]], ctx->ev[pairs[i][1]]);
-                info->ms[i] = t;
-            }
-            hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[7]);
-            info->ms[7] = t;
-        }
-    }
-    return finish(RANKY_OK);
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(RANKY_E_DEVICE, "hipSetDevice");
+    return run_path(ctx, jobs, tol, o, workspace, ws_bytes, infos, reinterpret_cast<hipStream_t>(stream),
+                    o.reserved == 1);
+}
+
+// ---------------------------------------------------------------------------
+// step calls
+// ---------------------------------------------------------------------------
+
+size_t ranky_step_workspace_bytes(int32_t M, int64_t N, int64_t nnz, int32_t D) {
+    if (M < 1 || N < 1 || M > kMaxM || nnz < 0 || D < 1 || D > N) return 0;
+    return make_header(1, 1, 1).total + make_plan(M, N, nnz, 1, D, false, false).total;
 }
 
 ranky_status ranky_occupancy(const ranky_csc *A, int32_t M, int64_t N, int32_t D, int32_t *cnt, int32_t *rownnz,
@@ -464,20 +861,10 @@ ranky_status ranky_occupancy(const ranky_csc *A, int32_t M, int64_t N, int32_t D
     if (st) return st;
     if (D < 1 || D > N) return fail(RANKY_E_INVALID, "D=%d outside [1, N]", D);
     if (!cnt || !rownnz || !lonely || !single) return fail(RANKY_E_INVALID, "NULL output");
-    const Plan p = make_plan(M, N, A->nnz, 1, D, false);
-    if (!workspace || ws_bytes < p.total) return fail(RANKY_E_NOMEM, "workspace %zu < %zu", ws_bytes, p.total);
-    // the occupancy pass needs only a context-free pinned read-back; use a local one
-    ranky_ctx tmp;
-    int32_t pin_local[kScCount];
-    void *pin = nullptr;
-    HIP_TRY(hipHostMalloc(&pin, sizeof(pin_local), hipHostMallocDefault));
-    tmp.pinned = static_cast<int32_t *>(pin);
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const Ptrs w = carve(p, workspace);
-    int32_t n = 0;
-    st = run_occupancy(&tmp, p, w, view(A), 1, cnt, lonely, single, rownnz, s, &n);
-    hipHostFree(pin);
-    return st;
+    StepCtx sc;
+    Engine e;
+    return step_scan(sc, A, M, N, D, workspace, ws_bytes, reinterpret_cast<hipStream_t>(stream), e, cnt, rownnz,
+                     lonely, single);
 }
 
 ranky_status ranky_gram(const ranky_csc *A, int32_t M, int64_t N, int32_t prec, double *G, void *workspace,
@@ -486,35 +873,21 @@ ranky_status ranky_gram(const ranky_csc *A, int32_t M, int64_t N, int32_t prec, 
     if (st) return st;
     if (!G) return fail(RANKY_E_INVALID, "G is NULL");
     if (prec != RANKY_PREC_FP64 && prec != RANKY_PREC_FP32) return fail(RANKY_E_INVALID, "prec=%d", prec);
-    const int32_t D = default_blocks(N);
-    const Plan p = make_plan(M, N, A->nnz, 1, D, false);
-    if (!workspace || ws_bytes < p.total) return fail(RANKY_E_NOMEM, "workspace %zu < %zu", ws_bytes, p.total);
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    hipDeviceProp_t prop;
-    HIP_TRY(hipGetDeviceProperties(&prop, dev));
-    size_t lds = prop.sharedMemPerBlock;
-    if (lds > 160 * 1024) lds = 160 * 1024;
-    lds = lds > 4096 ? lds - 4096 : lds;
-    HIP_TRY(occupancy_set_attributes(kMaxM));
-    HIP_TRY(gram_set_attributes(lds));
-    ranky_ctx tmp;
-    void *pin = nullptr;
-    HIP_TRY(hipHostMalloc(&pin, sizeof(int32_t) * kScCount, hipHostMallocDefault));
-    tmp.pinned = static_cast<int32_t *>(pin);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const Ptrs w = carve(p, workspace);
-    const CscView Av = view(A);
-    int32_t n = 0;
-    st = run_occupancy(&tmp, p, w, Av, 1, nullptr, w.lonely, w.single, w.rownnz, s, &n);
-    hipHostFree(pin);
+    StepCtx sc;
+    Engine e;
+    st = step_scan(sc, A, M, N, default_blocks(N), workspace, ws_bytes, s, e, nullptr, nullptr, nullptr, nullptr);
     if (st) return st;
-    const int32_t npad = round_up64(n > 0 ? n : 1);
-    if (n > 0) {
-        launch_row_offsets(w.hist, w.rowptr, M, p.nchunks, s);
-        launch_transpose(Av, M, N, p.D, p.cpb, p.nchunks, w.hist, w.csrk, w.csrend, w.csrcol, s);
-        launch_gram(Av, M, n, npad, npad, w.rowptr, w.r2m, w.csrk, w.csrend, w.G, prec, lds, s);
-        launch_scatter_gram(w.G, npad, w.m2r, M, G, s);
+    MatDesc &x = e.d[0];
+    x.prec = prec;
+    if (x.n > 0) {
+        e.nblk[kPhGram] = fill_wp(e.hwp(kPhGram), 1, [&](int) { return (int64_t)x.npad; });
+        st = e.upload_desc();
+        if (!st) st = e.upload(e.h.o_wp, sizeof(int32_t) * (size_t)kPhCount * (e.h.slots + 1));
+        if (st) return st;
+        e.enqueue_transpose();
+        launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], 1, M, sc.c.lds_limit, s);
+        launch_scatter_gram(x.G, x.npad, x.m2r, M, G, s);
     } else {
         launch_fill_f64(G, (int64_t)M * M, 0.0, s);
     }
@@ -525,10 +898,11 @@ ranky_status ranky_gram(const ranky_csc *A, int32_t M, int64_t N, int32_t prec, 
 
 size_t ranky_eigh_workspace_bytes(int32_t n) {
     if (n < 1 || n > kMaxM) return 0;
-    const int32_t npad = round_up64(n);
-    size_t b = 0;
-    b += align_up(sizeof(int32_t) * kScCount) + align_up(sizeof(double) * kSdCount);
+    const int32_t npad = jacobi_npad(n);
     const size_t npairs = (size_t)(npad / kJacobiPair);
+    size_t b = make_header(1, 1, npad / kJacobiBlock).total;
+    b += align_up(sizeof(int32_t) * kScCount) + align_up(sizeof(double) * kSdCount) +
+         align_up(sizeof(int32_t) * kJsCount);
     b += 3 * align_up(sizeof(double) * (size_t)npad * npad);
     b += 2 * align_up(sizeof(double) * 2 * npairs * kJacobiPair * kJacobiPair);
     b += align_up(sizeof(int32_t) * 2 * npairs);
@@ -542,42 +916,56 @@ ranky_status ranky_eigh(int32_t n, const double *G, double *lambda, double *Q, i
     if (!G || !lambda || !Q) return fail(RANKY_E_INVALID, "NULL argument");
     const size_t need = ranky_eigh_workspace_bytes(n);
     if (!workspace || ws_bytes < need) return fail(RANKY_E_NOMEM, "workspace %zu < %zu", ws_bytes, need);
-    const int32_t npad = round_up64(n);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int32_t npad = jacobi_npad(n);
+    const size_t npairs = (size_t)(npad / kJacobiPair);
+    const Header h = make_header(1, 1, npad / kJacobiBlock);
     char *b = static_cast<char *>(workspace);
-    Ptrs w;
-    std::memset(&w, 0, sizeof(w));
-    size_t off = 0;
+    size_t off = h.total;
     auto take = [&](size_t bytes) {
         char *ptr = b + off;
         off += align_up(bytes);
         return ptr;
     };
-    w.scal = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * kScCount));
-    w.sdbl = reinterpret_cast<double *>(take(sizeof(double) * kSdCount));
-    const size_t npairs = (size_t)(npad / kJacobiPair);
-    w.G = reinterpret_cast<double *>(take(sizeof(double) * (size_t)npad * npad));
-    w.G2 = reinterpret_cast<double *>(take(sizeof(double) * (size_t)npad * npad));
-    w.W = reinterpret_cast<double *>(take(sizeof(double) * (size_t)npad * npad));
-    w.J = reinterpret_cast<double *>(take(sizeof(double) * 2 * npairs * kJacobiPair * kJacobiPair));
-    w.S = reinterpret_cast<double *>(take(sizeof(double) * 2 * npairs * kJacobiPair * kJacobiPair));
-    w.jflag = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * 2 * npairs));
-    w.lam = reinterpret_cast<double *>(take(sizeof(double) * npad));
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    ranky_ctx tmp;
-    void *pin = nullptr;
-    HIP_TRY(hipHostMalloc(&pin, sizeof(int32_t) * kScCount, hipHostMallocDefault));
-    tmp.pinned = static_cast<int32_t *>(pin);
-    launch_fill_i32(w.scal, kScCount, 0, s);
-    launch_pad_copy(G, n, w.G, npad, npad, s);
-    int32_t sw = 0;
-    ranky_status st = run_jacobi(&tmp, w, n, max_sweeps > 0 ? max_sweeps : kDefaultSweeps, s, &sw);
-    hipHostFree(pin);
-    if (sweeps) *sweeps = sw;
-    hipMemcpyAsync(lambda, w.lam, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
-    launch_unpad_copy(w.W, npad, n, Q, s);
+    MatDesc x;
+    std::memset(&x, 0, sizeof(x));
+    x.scal = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * kScCount));
+    x.sdbl = reinterpret_cast<double *>(take(sizeof(double) * kSdCount));
+    x.jstate = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * kJsCount));
+    x.G = reinterpret_cast<double *>(take(sizeof(double) * (size_t)npad * npad));
+    x.G2 = reinterpret_cast<double *>(take(sizeof(double) * (size_t)npad * npad));
+    x.W = reinterpret_cast<double *>(take(sizeof(double) * (size_t)npad * npad));
+    x.J = reinterpret_cast<double *>(take(sizeof(double) * 2 * npairs * kJacobiPair * kJacobiPair));
+    x.S = reinterpret_cast<double *>(take(sizeof(double) * 2 * npairs * kJacobiPair * kJacobiPair));
+    x.jflag = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * 2 * npairs));
+    x.lam = reinterpret_cast<double *>(take(sizeof(double) * npad));
+    x.M = n;
+    x.k = n;
+    x.D = 0;  // no column blocks: no per-block counters to read back
+    x.n = n;
+    x.n_tau = n;
+    x.npad = npad;
+    StepCtx sc;
+    ranky_status st = step_device(sc);
+    if (st) return st;
+    Engine e;
+    st = make_engine(&sc.c, s, h, b, 1, e);
+    if (st) return st;
+    e.d.assign(1, x);
+    e.sweeps_cap = max_sweeps > 0 ? max_sweeps : kDefaultSweeps;
+    launch_fill_i32(x.scal, kScCount, 0, s);
+    launch_pad_copy(G, n, x.G, npad, npad, s);
+    st = e.plan_rest();
+    if (st) return st;
+    st = e.eigensolve(false);
+    if (st) return st;
+    if (sweeps) *sweeps = e.sweeps[0];
+    HIP_TRY(hipMemcpyAsync(lambda, x.lam, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    launch_unpad_copy(x.W, npad, n, Q, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
-    return st;
+    if (e.notconv[0] != 0) return fail(RANKY_E_NOT_CONVERGED, "Jacobi did not converge in %d sweeps", e.sweeps_cap);
+    return RANKY_OK;
 }
 
 ranky_status ranky_backproject(const ranky_csc *A, int32_t M, int64_t N, int32_t k, const double *U,
@@ -592,7 +980,8 @@ ranky_status ranky_backproject(const ranky_csc *A, int32_t M, int64_t N, int32_t
     HIP_TRY(hipGetDevice(&dev));
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    launch_backproject(view(A), N, k, U, sigma, rank, V, v_dtype, cus, reinterpret_cast<hipStream_t>(stream));
+    const CscView Av{A->nnz, A->colptr, A->rowidx, A->values, A->dtype};
+    launch_backproject(Av, N, k, U, sigma, rank, V, v_dtype, cus, reinterpret_cast<hipStream_t>(stream));
     HIP_TRY(hipGetLastError());
     return RANKY_OK;
 }

@@ -38,6 +38,12 @@ class Opts(ctypes.Structure):
                 ("n_blocks", "gram_prec", "refine", "max_sweeps", "validate", "v_dtype", "timing", "reserved")]
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("A", Csc), ("N", ctypes.c_int64), ("M", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("n_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32), ("sigma", ctypes.c_void_p),
+                ("U", ctypes.c_void_p), ("V", ctypes.c_void_p)]
+
+
 class Info(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
                 ("status", "rank", "n_nonempty", "empty_rows", "sweeps", "n_blocks", "lonely_max", "lonely_blocks")]
@@ -69,6 +75,8 @@ def lib():
         "ranky_version": ([], ctypes.c_char_p),
         "ranky_workspace_bytes": ([i32, i64, i64, i32, P(Opts)], sz),
         "ranky_svd": ([vp, P(Csc), i32, i64, i32, dbl, P(Opts), vp, sz, vp, vp, vp, P(Info), vp], i32),
+        "ranky_batch_workspace_bytes": ([i32, P(BatchItem), P(Opts)], sz),
+        "ranky_batch": ([vp, i32, P(BatchItem), dbl, P(Opts), vp, sz, P(Info), vp], i32),
         "ranky_step_workspace_bytes": ([i32, i64, i64, i32], sz),
         "ranky_occupancy": ([P(Csc), i32, i64, i32, vp, vp, vp, vp, vp, sz, vp], i32),
         "ranky_gram": ([P(Csc), i32, i64, i32, vp, vp, sz, vp], i32),
@@ -168,7 +176,7 @@ def context(device: int = 0) -> Context:
 
 
 def make_opts(n_blocks=0, gram_prec="fp64", refine=None, max_sweeps=0, validate=True, v_dtype=torch.float64,
-              timing=False) -> Opts:
+              timing=False, graph=False) -> Opts:
     o = Opts()
     _check(lib().ranky_default_opts(ctypes.byref(o)))
     o.n_blocks = n_blocks
@@ -178,6 +186,7 @@ def make_opts(n_blocks=0, gram_prec="fp64", refine=None, max_sweeps=0, validate=
     o.validate = int(validate)
     o.v_dtype = F64 if v_dtype == torch.float64 else F32
     o.timing = int(timing)
+    o.reserved = int(graph)
     return o
 
 
@@ -273,3 +282,57 @@ def backproject(A: DeviceCSC, U: torch.Tensor, sigma: torch.Tensor, rank: int, v
                                    F64 if v_dtype == torch.float64 else F32, _stream(stream)))
     torch.cuda.current_stream().synchronize()
     return V
+
+
+def batch(mats: list[DeviceCSC], ks: list[int], tol: float = 0.0, n_blocks: list[int] | None = None,
+          ctx: Context | None = None, outs: list[SVDResult] | None = None, workspace: torch.Tensor | None = None,
+          stream=None, gram_prec="fp64", v_dtype=torch.float64, graph=False, max_sweeps=0,
+          check=True) -> list[SVDResult]:
+    """All matrices through ranky_batch (one launch per phase for the whole batch; blocking).
+    Returns one SVDResult per matrix; info["status"] carries each matrix's own status."""
+    if not mats:
+        raise ValueError("empty batch")
+    ctx = ctx or context(mats[0].colptr.device.index or 0)
+    opts = make_opts(gram_prec=gram_prec, refine=0, v_dtype=v_dtype, graph=graph, max_sweeps=max_sweeps)
+    n = len(mats)
+    items = (BatchItem * n)()
+    if outs is None:
+        outs = []
+        for A, k in zip(mats, ks):
+            dev = A.colptr.device
+            outs.append(SVDResult(torch.empty(k, dtype=torch.float64, device=dev),
+                                  torch.empty((A.M, k), dtype=torch.float64, device=dev),
+                                  torch.empty((A.N, k), dtype=v_dtype, device=dev), {}))
+    for i, (A, k, o) in enumerate(zip(mats, ks, outs)):
+        items[i].A = A.struct()
+        items[i].N = A.N
+        items[i].M = A.M
+        items[i].k = k
+        items[i].n_blocks = 0 if n_blocks is None else n_blocks[i]
+        items[i].sigma = o.sigma.data_ptr()
+        items[i].U = o.U.data_ptr()
+        items[i].V = o.V.data_ptr()
+    nbytes = int(lib().ranky_batch_workspace_bytes(n, items, ctypes.byref(opts)))
+    if nbytes == 0:
+        raise RankyError(E_INVALID, "invalid batch sizes")
+    ws = workspace if workspace is not None else ctx.workspace(nbytes)
+    infos = (Info * n)()
+    st = lib().ranky_batch(ctx.handle, n, items, float(tol), ctypes.byref(opts), _ptr(ws), ws.numel(), infos,
+                           _stream(stream))
+    for o, inf in zip(outs, infos):
+        o.info = inf.as_dict()
+    if check:
+        _check(st)
+    return outs
+
+
+def batch_workspace_bytes(mats, ks, gram_prec="fp64", v_dtype=torch.float64) -> int:
+    opts = make_opts(gram_prec=gram_prec, refine=0, v_dtype=v_dtype)
+    n = len(mats)
+    items = (BatchItem * n)()
+    for i, (A, k) in enumerate(zip(mats, ks)):
+        items[i].A.nnz = A.nnz
+        items[i].N = A.N
+        items[i].M = A.M
+        items[i].k = k
+    return int(lib().ranky_batch_workspace_bytes(n, items, ctypes.byref(opts)))
