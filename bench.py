@@ -26,6 +26,7 @@ def parse():
     ap.add_argument("--prec", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=None)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-matrix leg")
     return ap.parse_args()
 
 
@@ -61,6 +62,41 @@ def time_path(ranky, torch, np, dA, A, k, D, prec, steps, warmup):
     phases /= steps
     names = ["occupancy", "transpose", "gram", "eigensolve", "select", "refine", "backproject", "total"]
     return ms_step, dict(zip(names, phases.tolist())), r.info, out.sigma.cpu().numpy(), vdt
+
+
+def time_batch(ranky, torch, gen, steps, warmup):
+    """Batched leg: 256 independent matrices (M ~ U{32..512}, N ~ U{1e4..1e5}, density 0.5%,
+    FP32 values, 20% with half their rows zeroed), full spectrum each, through ranky_batch
+    with the Jacobi sweep replayed as a captured graph.  FP64 Gram and FP32 Gram."""
+    mats = gen.cfg3()
+    dms = [ranky.to_device(A, "cuda:0") for A in mats]
+    ks = [A.M for A in mats]
+    Ds = [int(A.meta["D"]) for A in mats]
+    nnz = sum(A.nnz for A in mats)
+    stream = torch.cuda.Stream()
+    out = {"workload": "cfg3: 256 matrices, M~U{32..512}, N~U{1e4..1e5}, density 0.5%, 20% half-rank, full spectrum",
+           "matrices": len(mats), "nnz": nnz}
+    for prec, vdt in (("fp64", torch.float64), ("fp32", torch.float32)):
+        outs = [ranky.SVDResult(torch.empty(k, dtype=torch.float64, device="cuda:0"),
+                                torch.empty((A.M, k), dtype=torch.float64, device="cuda:0"),
+                                torch.empty((A.N, k), dtype=vdt, device="cuda:0"), {}) for A, k in zip(mats, ks)]
+        ws = torch.empty(ranky.batch_workspace_bytes(dms, ks, gram_prec=prec, v_dtype=vdt), dtype=torch.uint8,
+                         device="cuda:0")
+        with torch.cuda.stream(stream):
+            for _ in range(warmup):
+                ranky.batch(dms, ks, 0.0, n_blocks=Ds, outs=outs, workspace=ws, gram_prec=prec, v_dtype=vdt, graph=True)
+            stream.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                ranky.batch(dms, ks, 0.0, n_blocks=Ds, outs=outs, workspace=ws, gram_prec=prec, v_dtype=vdt, graph=True)
+            stream.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        out[prec + "_gram"] = {"ms_per_batch": ms, "value": nnz / (ms * 1e-3), "unit": "nnz/s",
+                               "max_sweeps": max(o.info["sweeps"] for o in outs),
+                               "ranks_ok": all(o.info["status"] == 0 for o in outs)}
+        del outs, ws
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -110,6 +146,9 @@ def main():
         other + "_path": {"value": A.nnz / (ms2 * 1e-3), "ms_per_step": ms2, "phase_ms": phases2,
                           "rank": info2["rank"], "sweeps": info2["sweeps"]},
     }
+
+    if not args.no_batch:
+        line["batch"] = time_batch(ranky, torch, gen, max(2, args.steps // 3), 1)
 
     if not args.no_cpu_baseline:
         import oracle

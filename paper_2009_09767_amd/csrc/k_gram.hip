@@ -159,6 +159,7 @@ size_t gram_lds_bytes(int32_t maxM, size_t lds_limit) {
 
 void launch_gram(const MatDesc *descs, const int32_t *wp, int64_t nblocks, int count, int32_t maxM, size_t lds_limit,
                  hipStream_t s) {
+    if (nblocks <= 0) return;
     const int nw = gram_waves(maxM, 8, lds_limit);
     hipLaunchKernelGGL(k_gram_rows, dim3((unsigned)nblocks), dim3((unsigned)(64 * nw)), gram_lds_bytes(maxM, lds_limit),
                        s, descs, wp, count);

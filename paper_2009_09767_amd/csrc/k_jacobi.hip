@@ -456,6 +456,7 @@ __global__ __launch_bounds__(256) void k_jdiag(const MatDesc *__restrict__ descs
 int32_t jacobi_npad(int32_t n) { return ((n + kP - 1) / kP) * kP; }
 
 void launch_jacobi_init(const MatDesc *descs, const int32_t *wp, int64_t nblocks, int count, hipStream_t s) {
+    if (nblocks <= 0) return;
     hipLaunchKernelGGL(k_jinit, dim3((unsigned)nblocks), dim3(256), 0, s, descs, wp, count);
 }
 

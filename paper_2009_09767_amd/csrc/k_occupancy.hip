@@ -325,11 +325,13 @@ void launch_occupancy(const MatDesc *descs, const int32_t *wp_chunks, int64_t n_
 }
 
 void launch_row_offsets(const MatDesc *descs, const int32_t *wp_rows, int64_t n_row_blocks, int count, hipStream_t s) {
+    if (n_row_blocks <= 0) return;
     hipLaunchKernelGGL(k_occ_offsets, dim3((unsigned)n_row_blocks), dim3(256), 0, s, descs, wp_rows, count);
 }
 
 void launch_transpose(const MatDesc *descs, const int32_t *wp_chunks, int64_t n_chunk_blocks, int count, int32_t maxM,
                       hipStream_t s) {
+    if (n_chunk_blocks <= 0) return;
     hipLaunchKernelGGL(k_transpose, dim3((unsigned)n_chunk_blocks), dim3(64), transpose_lds_bytes(maxM), s, descs,
                        wp_chunks, count);
 }

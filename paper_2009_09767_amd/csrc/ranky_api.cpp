@@ -355,8 +355,13 @@ struct Engine {
 
     bool live(int i) const { return status[i] == RANKY_OK && d[i].n > 0; }
 
-    // Maps of every later phase and the round tables; one upload.
+    // Maps of every later phase and the round tables; one upload.  A matrix whose
+    // scan reported a contract violation gets no workgroup in any later phase (the
+    // transpose and the Gram index LDS and the row-major copy by its row indices).
     ranky_status plan_rest() {
+        nblk[kPhChunks] = fill_wp(hwp(kPhChunks), count, [&](int i) { return status[i] == RANKY_OK ? d[i].nchunks : 0; });
+        nblk[kPhRows] = fill_wp(hwp(kPhRows), count,
+                                [&](int i) { return status[i] == RANKY_OK ? (int64_t)(d[i].M + 255) / 256 : 0; });
         nblk[kPhGram] = fill_wp(hwp(kPhGram), count, [&](int i) { return live(i) ? (int64_t)d[i].npad : 0; });
         nblk[kPhJinit] = fill_wp(hwp(kPhJinit), count, [&](int i) -> int64_t {
             if (!live(i)) return 0;
@@ -527,6 +532,14 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
     if (timing) hipEventRecord(ctx->ev[0], s);
     st = e.scan();
     if (st) return st;
+    if (count == 1 && e.status[0] != RANKY_OK) {
+        if (infos) {
+            std::memset(infos, 0, sizeof(ranky_info));
+            infos[0].status = e.status[0];
+        }
+        return e.status[0] == RANKY_E_CSC ? fail(RANKY_E_CSC, "CSC contract violated (colptr, row range or row order)")
+                                          : fail(RANKY_E_NONFINITE, "non-finite value in A");
+    }
     if (timing) hipEventRecord(ctx->ev[1], s);
     st = e.plan_rest();
     if (st) return st;
