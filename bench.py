@@ -80,8 +80,8 @@ def time_batch(ranky, torch, gen, steps, warmup):
         outs = [ranky.SVDResult(torch.empty(k, dtype=torch.float64, device="cuda:0"),
                                 torch.empty((A.M, k), dtype=torch.float64, device="cuda:0"),
                                 torch.empty((A.N, k), dtype=vdt, device="cuda:0"), {}) for A, k in zip(mats, ks)]
-        ws = torch.empty(ranky.batch_workspace_bytes(dms, ks, gram_prec=prec, v_dtype=vdt), dtype=torch.uint8,
-                         device="cuda:0")
+        ws = torch.empty(ranky.batch_workspace_bytes(dms, ks, gram_prec=prec, v_dtype=vdt, n_blocks=Ds),
+                         dtype=torch.uint8, device="cuda:0")
         with torch.cuda.stream(stream):
             for _ in range(warmup):
                 ranky.batch(dms, ks, 0.0, n_blocks=Ds, outs=outs, workspace=ws, gram_prec=prec, v_dtype=vdt, graph=True)

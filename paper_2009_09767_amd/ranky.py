@@ -326,7 +326,7 @@ def batch(mats: list[DeviceCSC], ks: list[int], tol: float = 0.0, n_blocks: list
     return outs
 
 
-def batch_workspace_bytes(mats, ks, gram_prec="fp64", v_dtype=torch.float64) -> int:
+def batch_workspace_bytes(mats, ks, gram_prec="fp64", v_dtype=torch.float64, n_blocks=None) -> int:
     opts = make_opts(gram_prec=gram_prec, refine=0, v_dtype=v_dtype)
     n = len(mats)
     items = (BatchItem * n)()
@@ -335,4 +335,5 @@ def batch_workspace_bytes(mats, ks, gram_prec="fp64", v_dtype=torch.float64) -> 
         items[i].N = A.N
         items[i].M = A.M
         items[i].k = k
+        items[i].n_blocks = 0 if n_blocks is None else n_blocks[i]
     return int(lib().ranky_batch_workspace_bytes(n, items, ctypes.byref(opts)))
