@@ -27,6 +27,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-matrix leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
     return ap.parse_args()
 
 
@@ -99,6 +101,58 @@ def time_batch(ranky, torch, gen, steps, warmup):
     return out
 
 
+def time_serving(ranky, torch, gen, seconds, pool_size=48, slots=8):
+    """Serving leg: cfg4's open-loop Poisson arrivals (200 req/s) replayed for `seconds`, each
+    arrival drawing the next matrix of a seeded pool of cfg4 requests (M in {128..1024},
+    N = 2^U{14..20}, LogUniform nnz up to 20M, Zipf(1.1) rows, FP32 values, k = min(M, 64)).
+    Latency = completion - submit through ranky_serve_*.  Requests that share a pool entry
+    share its output buffers (identical results)."""
+    reqs = gen.cfg4_requests()
+    pool = [gen.cfg4_matrix(r) for r in reqs[:pool_size]]
+    dpool = [ranky.to_device(A, "cuda:0") for A in pool]
+    arrivals = [r.arrival_s for r in reqs if r.arrival_s < seconds]
+    res = {"workload": f"cfg4: Poisson 200 req/s for {seconds:g} s over a pool of {pool_size} requests",
+           "requests": len(arrivals), "slots": slots}
+    for prec in ("fp64", "fp32"):
+        vdt = torch.float64 if prec == "fp64" else torch.float32
+        outs = [ranky.SVDResult(torch.empty(min(A.M, 64), dtype=torch.float64, device="cuda:0"),
+                                torch.empty((A.M, min(A.M, 64)), dtype=torch.float64, device="cuda:0"),
+                                torch.empty((A.N, min(A.M, 64)), dtype=vdt, device="cuda:0"), {}) for A in pool]
+        srv = ranky.Server(arena_bytes=16 << 30, max_slots=slots, max_queue=4096, gram_prec=prec, v_dtype=vdt,
+                           refine=0 if prec == "fp64" else 1)
+        # warm every pool entry once (kernel loading, allocator)
+        for i in range(0, pool_size, 8):
+            ts = [srv.submit(dpool[j], min(pool[j].M, 64), outs[j])[1] for j in range(i, min(i + 8, pool_size))]
+            for t in ts:
+                srv.wait(t)
+        srv.close()
+        srv = ranky.Server(arena_bytes=16 << 30, max_slots=slots, max_queue=4096, gram_prec=prec, v_dtype=vdt,
+                           refine=0 if prec == "fp64" else 1)
+        t0 = time.perf_counter()
+        tickets, busy = [], 0
+        for i, ta in enumerate(arrivals):
+            now = time.perf_counter() - t0
+            if ta > now:
+                time.sleep(ta - now)
+            j = i % pool_size
+            st, t = srv.submit(dpool[j], min(pool[j].M, 64), outs[j])
+            if st == ranky.OK:
+                tickets.append(t)
+            else:
+                busy += 1
+        bad = sum(1 for t in tickets if srv.wait(t)[0] != ranky.OK)
+        st = srv.stats()
+        srv.close()
+        res[prec + "_gram"] = {"p50_ms": st["p50_us"] / 1e3, "p99_ms": st["p99_us"] / 1e3,
+                               "mean_ms": st["mean_us"] / 1e3, "req_per_s": st["req_per_s"],
+                               "nnz_per_s": st["nnz_per_s"], "completed": st["completed"], "failed": bad,
+                               "rejected": busy, "peak_running": st["peak_running"],
+                               "arena_peak_gb": st["arena_peak_bytes"] / 2**30}
+        del outs
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -149,6 +203,8 @@ def main():
 
     if not args.no_batch:
         line["batch"] = time_batch(ranky, torch, gen, max(2, args.steps // 3), 1)
+    if not args.no_serve:
+        line["serving"] = time_serving(ranky, torch, gen, args.serve_seconds)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -198,6 +198,65 @@ ranky_status ranky_batch(ranky_ctx *ctx, int32_t count, const ranky_batch_item *
                          ranky_stream_t stream);
 
 /* ------------------------------------------------------------------------- */
+/* Serving: continuous admission of requests into a device arena              */
+/* ------------------------------------------------------------------------- */
+
+typedef struct ranky_server ranky_server;
+
+typedef struct {
+    void *arena;          /* device memory the server carves for admitted requests (caller-owned) */
+    size_t arena_bytes;
+    int32_t max_slots;    /* requests on the device at once (each has its own stream), >= 1 */
+    int32_t max_queue;    /* waiting requests before submit answers RANKY_E_BUSY, >= 1 */
+    int device;
+    int32_t reserved;
+    ranky_opts opts;      /* path options used for every request */
+} ranky_serve_cfg;
+
+/* One request.  A and the outputs are device pointers; A must stay valid until the
+ * request completes (the server copies it into the arena when it is admitted and
+ * computes from that copy); the outputs are written once, at completion. */
+typedef struct {
+    ranky_csc A;
+    int64_t N;
+    int32_t M;
+    int32_t k;
+    double tol;
+    double *sigma;   /* [k] */
+    double *U;       /* [M x k] row-major */
+    void *V;         /* [N x k] row-major, opts.v_dtype */
+} ranky_request;
+
+typedef struct {
+    double p50_us, p99_us, mean_us, max_us; /* latency = completion - submit, completed requests */
+    double span_s;                           /* first submit to last completion */
+    double req_per_s, nnz_per_s;             /* completed requests (nnz) / span */
+    int64_t submitted, admitted, completed, failed, cancelled, rejected;
+    int64_t queued_now, running_now, peak_running;
+    size_t arena_peak_bytes;
+} ranky_serve_summary;
+
+/* Starts max_slots worker threads, each with its own context and stream.  The arena
+ * is used as a first-fit heap: a request is admitted (FIFO) when a slot is free and
+ * its footprint (CSC copy + ranky_workspace_bytes) fits; requests that arrive while
+ * others run join as soon as memory and a slot free up, and their kernels overlap
+ * on the device.  Results are bitwise those of ranky_svd alone (no shared state). */
+ranky_status ranky_serve_create(const ranky_serve_cfg *cfg, ranky_server **out);
+/* E_BUSY when the queue is full (back-pressure); E_NOMEM when the request could never
+ * fit in the arena; E_INVALID for bad sizes.  *ticket receives the request's id. */
+ranky_status ranky_serve_submit(ranky_server *srv, const ranky_request *req, uint64_t *ticket);
+/* RANKY_PENDING while queued or running; else the request's final status (info filled). */
+ranky_status ranky_serve_poll(ranky_server *srv, uint64_t ticket, ranky_info *info);
+/* Waits up to timeout_us (< 0: forever); returns as ranky_serve_poll. */
+ranky_status ranky_serve_wait(ranky_server *srv, uint64_t ticket, int64_t timeout_us, ranky_info *info);
+/* A queued request is dropped (status E_CANCELLED); a running one completes but
+ * reports E_CANCELLED. */
+ranky_status ranky_serve_cancel(ranky_server *srv, uint64_t ticket);
+ranky_status ranky_serve_stats(ranky_server *srv, ranky_serve_summary *stats);
+/* Stops admission, drains queued and running requests, joins the workers. */
+ranky_status ranky_serve_destroy(ranky_server *srv);
+
+/* ------------------------------------------------------------------------- */
 /* Individual steps (the same kernels ranky_svd runs), for composition and    */
 /* per-step checking.  Stream-ordered unless marked blocking.                 */
 /* ------------------------------------------------------------------------- */

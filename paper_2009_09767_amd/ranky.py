@@ -44,6 +44,28 @@ class BatchItem(ctypes.Structure):
                 ("U", ctypes.c_void_p), ("V", ctypes.c_void_p)]
 
 
+class ServeCfg(ctypes.Structure):
+    _fields_ = [("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
+                ("max_queue", ctypes.c_int32), ("device", ctypes.c_int), ("reserved", ctypes.c_int32),
+                ("opts", Opts)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("A", Csc), ("N", ctypes.c_int64), ("M", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("sigma", ctypes.c_void_p), ("U", ctypes.c_void_p), ("V", ctypes.c_void_p)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("p50_us", "p99_us", "mean_us", "max_us", "span_s", "req_per_s",
+                                               "nnz_per_s")]
+    _fields_ += [(n, ctypes.c_int64) for n in ("submitted", "admitted", "completed", "failed", "cancelled",
+                                               "rejected", "queued_now", "running_now", "peak_running")]
+    _fields_ += [("arena_peak_bytes", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 class Info(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
                 ("status", "rank", "n_nonempty", "empty_rows", "sweeps", "n_blocks", "lonely_max", "lonely_blocks")]
@@ -77,6 +99,13 @@ def lib():
         "ranky_svd": ([vp, P(Csc), i32, i64, i32, dbl, P(Opts), vp, sz, vp, vp, vp, P(Info), vp], i32),
         "ranky_batch_workspace_bytes": ([i32, P(BatchItem), P(Opts)], sz),
         "ranky_batch": ([vp, i32, P(BatchItem), dbl, P(Opts), vp, sz, P(Info), vp], i32),
+        "ranky_serve_create": ([P(ServeCfg), P(vp)], i32),
+        "ranky_serve_submit": ([vp, P(Request), P(ctypes.c_uint64)], i32),
+        "ranky_serve_poll": ([vp, ctypes.c_uint64, P(Info)], i32),
+        "ranky_serve_wait": ([vp, ctypes.c_uint64, i64, P(Info)], i32),
+        "ranky_serve_cancel": ([vp, ctypes.c_uint64], i32),
+        "ranky_serve_stats": ([vp, P(ServeStats)], i32),
+        "ranky_serve_destroy": ([vp], i32),
         "ranky_step_workspace_bytes": ([i32, i64, i64, i32], sz),
         "ranky_occupancy": ([P(Csc), i32, i64, i32, vp, vp, vp, vp, vp, sz, vp], i32),
         "ranky_gram": ([P(Csc), i32, i64, i32, vp, vp, sz, vp], i32),
@@ -337,3 +366,72 @@ def batch_workspace_bytes(mats, ks, gram_prec="fp64", v_dtype=torch.float64, n_b
         items[i].k = k
         items[i].n_blocks = 0 if n_blocks is None else n_blocks[i]
     return int(lib().ranky_batch_workspace_bytes(n, items, ctypes.byref(opts)))
+
+
+class Server:
+    """Continuous-admission server (ranky_serve_*).  The arena is a device tensor owned by this
+    object; request inputs and outputs are the caller's device tensors and must stay alive
+    until the request completes."""
+
+    def __init__(self, arena_bytes: int, max_slots: int = 4, max_queue: int = 1024, device: int = 0, **opt_kw):
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=f"cuda:{device}")
+        cfg = ServeCfg()
+        cfg.arena = self.arena.data_ptr()
+        cfg.arena_bytes = arena_bytes
+        cfg.max_slots = max_slots
+        cfg.max_queue = max_queue
+        cfg.device = device
+        cfg.opts = make_opts(**opt_kw)
+        self.opts = cfg.opts
+        h = ctypes.c_void_p()
+        _check(lib().ranky_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def footprint(self, A: DeviceCSC, k: int) -> int:
+        return workspace_bytes(A.M, A.N, A.nnz, k, self.opts)
+
+    def submit(self, A: DeviceCSC, k: int, out: SVDResult, tol: float = 0.0):
+        """Returns (status, ticket); status E_BUSY / E_NOMEM is back-pressure, not an exception."""
+        r = Request()
+        r.A = A.struct()
+        r.N, r.M, r.k, r.tol = A.N, A.M, k, float(tol)
+        r.sigma, r.U, r.V = out.sigma.data_ptr(), out.U.data_ptr(), out.V.data_ptr()
+        t = ctypes.c_uint64(0)
+        st = lib().ranky_serve_submit(self.handle, ctypes.byref(r), ctypes.byref(t))
+        if st == OK:
+            self._keep[t.value] = (A, out)
+        return st, t.value
+
+    def poll(self, ticket: int):
+        inf = Info()
+        st = lib().ranky_serve_poll(self.handle, ticket, ctypes.byref(inf))
+        return st, inf.as_dict()
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        inf = Info()
+        st = lib().ranky_serve_wait(self.handle, ticket, timeout_us, ctypes.byref(inf))
+        if st != PENDING:
+            self._keep.pop(ticket, None)
+        return st, inf.as_dict()
+
+    def cancel(self, ticket: int) -> int:
+        return lib().ranky_serve_cancel(self.handle, ticket)
+
+    def stats(self) -> dict:
+        s = ServeStats()
+        _check(lib().ranky_serve_stats(self.handle, ctypes.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if self.handle:
+            st = lib().ranky_serve_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+            _check(st)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
