@@ -70,59 +70,78 @@ def test_mix_equals_alone(R):
 
 
 def test_admission_by_footprint(R):
-    """An arena that holds about two requests at a time: never more admitted than fit, all complete."""
+    """Eight copies of one request in an arena that holds two of them: never more than two
+    admitted at once, all eight complete, identical results."""
     import torch
 
-    mats = request_pool(8, seed=5)
-    dms = [R.to_device(A) for A in mats]
-    ks = [min(A.M, 64) for A in mats]
+    A = request_pool(1, seed=5)[0]
+    dA = R.to_device(A)
+    k = min(A.M, 64)
     probe = R.Server(arena_bytes=1 << 20, max_slots=1, max_queue=4)
-    foot = [probe.footprint(dA, k) + 4 * (A.N + 1) + 8 * A.nnz + 1024 for A, dA, k in zip(mats, dms, ks)]
+    foot = probe.footprint(dA, k) + 4 * (A.N + 1) + 8 * A.nnz + 768
     probe.close()
-    arena = int(2.2 * max(foot))
+    arena = int(2.5 * foot)
     srv = R.Server(arena_bytes=arena, max_slots=8, max_queue=64)
-    outs = [alloc_out(R, torch, A, k, torch.float64) for A, k in zip(mats, ks)]
-    tickets = [srv.submit(dA, k, o)[1] for dA, k, o in zip(dms, ks, outs)]
+    outs = [alloc_out(R, torch, A, k, torch.float64) for _ in range(8)]
+    tickets = [srv.submit(dA, k, o)[1] for o in outs]
     for t in tickets:
         assert srv.wait(t, 60_000_000)[0] == R.OK
     st = srv.stats()
     srv.close()
+    assert st["completed"] == 8
     assert st["arena_peak_bytes"] <= arena
-    assert st["completed"] == len(mats)
-    assert st["peak_running"] <= 3
+    assert 1 <= st["peak_running"] <= 2
+    for o in outs[1:]:
+        assert torch.equal(o.sigma, outs[0].sigma) and torch.equal(o.V, outs[0].V)
+
+
+def test_oversized_request_is_refused(R):
+    import torch
+
+    big = gen.cfg4_matrix(gen.Request(0.0, 1024, 1 << 20, 2_000_000, 64, 3))
+    dbig = R.to_device(big)
+    obig = alloc_out(R, torch, big, 64, torch.float64)
+    srv = R.Server(arena_bytes=1 << 22, max_slots=1, max_queue=2)
+    assert srv.submit(dbig, 64, obig)[0] == R.E_NOMEM
+    assert srv.stats()["rejected"] == 1
+    srv.close()
 
 
 def test_back_pressure_cancel_and_isolation(R):
     import torch
 
-    mats = request_pool(6, seed=9)
+    mats = request_pool(4, seed=9)
     dms = [R.to_device(A) for A in mats]
-    srv = R.Server(arena_bytes=1 << 30, max_slots=1, max_queue=2)
     outs = [alloc_out(R, torch, A, min(A.M, 64), torch.float64) for A in mats]
-    big = gen.cfg4_matrix(gen.Request(0.0, 1024, 1 << 20, 2_000_000, 64, 3))
-    dbig = R.to_device(big)
-    obig = alloc_out(R, torch, big, 64, torch.float64)
-    small_srv = R.Server(arena_bytes=1 << 22, max_slots=1, max_queue=2)
-    assert small_srv.submit(dbig, 64, obig)[0] == R.E_NOMEM      # could never fit
-    small_srv.close()
-    # a request with a broken CSC fails alone
+    # one slot and a queue of one: rapid submissions must meet back-pressure
+    srv = R.Server(arena_bytes=1 << 30, max_slots=1, max_queue=1)
+    codes, tickets = [], []
+    for _ in range(20):
+        st, t = srv.submit(dms[1], min(mats[1].M, 64), outs[1])
+        codes.append(st)
+        if st == R.OK:
+            tickets.append(t)
+    assert R.E_BUSY in codes
+    for t in tickets:
+        assert srv.wait(t, 60_000_000)[0] == R.OK
+    srv.close()
+    # a broken request fails alone; a queued request can be cancelled
+    srv = R.Server(arena_bytes=1 << 30, max_slots=1, max_queue=8)
     bad = R.to_device(mats[0])
     ri = mats[0].rowidx.copy()
     ri[0] = mats[0].M + 1
     bad.rowidx = torch.from_numpy(ri).cuda()
     st0, t0 = srv.submit(bad, min(mats[0].M, 64), outs[0])
-    results = {}
-    st1, t1 = srv.submit(dms[1], min(mats[1].M, 64), outs[1])
-    st2, t2 = srv.submit(dms[2], min(mats[2].M, 64), outs[2])
-    busy = [srv.submit(dms[3], min(mats[3].M, 64), outs[3])[0] for _ in range(4)]
-    assert R.E_BUSY in busy                                         # queue of 2 overflows
-    srv.cancel(t2)
-    results[t0] = srv.wait(t0, 60_000_000)[0]
-    results[t1] = srv.wait(t1, 60_000_000)[0]
-    results[t2] = srv.wait(t2, 60_000_000)[0]
+    st1, t1 = srv.submit(dms[2], min(mats[2].M, 64), outs[2])
+    st2, t2 = srv.submit(dms[3], min(mats[3].M, 64), outs[3])
+    assert (st0, st1, st2) == (R.OK, R.OK, R.OK)
+    assert srv.cancel(t2) == R.OK
+    r0 = srv.wait(t0, 60_000_000)[0]
+    r1 = srv.wait(t1, 60_000_000)[0]
+    r2 = srv.wait(t2, 60_000_000)[0]
     srv.close()
-    assert results[t0] == R.E_CSC
-    assert results[t1] == R.OK
-    assert results[t2] in (R.E_CANCELLED, R.OK)
-    alone = R.svd(dms[1], min(mats[1].M, 64), 0.0)
-    assert torch.equal(outs[1].sigma, alone.sigma)
+    assert r0 == R.E_CSC
+    assert r1 == R.OK
+    assert r2 in (R.E_CANCELLED, R.OK)     # cancelled if it was still queued
+    alone = R.svd(dms[2], min(mats[2].M, 64), 0.0)
+    assert torch.equal(outs[2].sigma, alone.sigma)
