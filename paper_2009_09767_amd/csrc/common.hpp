@@ -20,7 +20,7 @@ enum : int32_t {
     kScNotConv = 3,    // 1 if some off-diagonal entry still fails the Jacobi test
     kScCount = 16
 };
-enum : int32_t { kSdTau = 0, kSdSigmaMax = 1, kSdFloor = 2, kSdCount = 8 };
+enum : int32_t { kSdTau = 0, kSdSigmaMax = 1, kSdFloor = 2, kSdScale = 3, kSdCount = 8 };
 
 // Column range of chunk c: block b = c / cpb owns columns [floor(bN/D), floor((b+1)N/D)),
 // and its t-th chunk (t = c % cpb) is the t-th run of kChunkCols columns of it.

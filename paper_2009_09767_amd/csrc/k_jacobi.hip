@@ -6,61 +6,78 @@
 //
 // Layout: G (two ping-pong copies) and W are npad x npad row-major, npad a multiple
 // of 32; indices >= n are zero padding that no rotation touches (their couplings
-// stay exactly zero).  The index range is cut into nb = npad / 16 blocks; one sweep
-// is nb - 1 rounds of a round-robin tournament on the blocks, and in a round the
-// nb / 2 block pairs are disjoint.  Every round is ONE launch of k_jround:
+// stay exactly zero).  G is scaled by a power of two at the start (max |g_ii| in
+// [1/2, 1)), so the rotation formulas below can neither overflow nor underflow; the
+// eigenvalues are scaled back when they are read out.  The index range is cut into
+// nb = npad / 16 blocks; one sweep is nb - 1 rounds of a round-robin tournament on
+// the blocks, and in a round the nb / 2 block pairs are disjoint.  Every round is
+// ONE launch of k_jround:
 //   * workgroups [0, npairs) solve the round's 32 x 32 subproblems S = M_r[s, s]
-//     (s = the pair's two blocks) by cyclic Jacobi in LDS and write the rotation J
-//     (32 x 32) and the rotated S.  M_r is the matrix after the previous rounds; its
-//     diagonal subproblem blocks are built directly from M_{r-1} and the previous
-//     round's J (J_a^T M_{r-1}[s_a, s_b] J_b), so no workgroup waits for the update.
-//   * the other workgroups apply the previous round: M_r = Jp^T M_{r-1} Jp tile by
-//     tile (32 x 32 tiles of the previous pairing; the diagonal tiles are the rotated
-//     subproblems themselves) into the other G buffer, and W <- W Jp in place.
+//     (s = the pair's two blocks) with one cyclic Jacobi sweep in LDS and write the
+//     rotation J (32 x 32) and the rotated S.  The diagonal blocks of S are the
+//     previous round's rotated subproblems, the off-diagonal block is
+//     J_a^T M_{r-1}[s_a, s_b] J_b, so no workgroup waits for the update.
+//   * the other workgroups apply the previous round, one 32 x 32 tile per wave on the
+//     FP64 matrix cores: M_r = Jp^T M_{r-1} Jp tile by tile into the other G buffer
+//     (the diagonal tiles are the rotated subproblems themselves), W <- W Jp in place.
 // A flush launch (update only) ends every sweep; k_jcheck then tests every
-// off-diagonal entry against |g_pq| > max(tol sqrt|g_pp g_qq|, floor) with
-// tol = max(1e-15, sqrt(n) eps), floor = (n eps)^2 max|g_ii|.
-// Rotation (Rutishauser): zeta = (g_qq - g_pp) / (2 g_pq), t = sign(zeta) / (|zeta| +
-// sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = c t; then g_pp -= t g_pq, g_qq += t g_pq.
-// Rows: r_p <- c r_p - s r_q, r_q <- s r_p + c r_q; columns likewise.
+// off-diagonal entry: g_pq is rotated iff |g_pq| > floor and g_pq^2 > tol^2 |g_pp g_qq|,
+// tol = max(1e-15, sqrt(n) eps), floor = (n eps)^2 max|g_ii| (the solve uses the same
+// test, so the two can never disagree).
+//
+// Rotation of the pair (p, q), d = g_qq - g_pp, a = 2 g_pq, h = sqrt(d^2 + a^2),
+// w = |d| + h: the smaller-angle rotation has c = sqrt(w / (2h)), s = sign(d) a / sqrt(2hw)
+// and tangent t = s / c = sign(d) a / w (sign(0) = +1); then g_pp -= t g_pq,
+// g_qq += t g_pq, g_pq = 0.  Rows: r_p <- c r_p - s r_q, r_q <- s r_p + c r_q; columns
+// likewise; J <- J R.
+//
+// Inside a subproblem the 16 pairs of a step sit at fixed positions (i, 31 - i); after
+// every step the positions turn one place (the round-robin of the 32 indices), which
+// the step folds into where it writes, so every thread's LDS addresses are fixed for
+// the whole sweep and after 31 steps the positions are the indices again.  S lives in
+// LDS as one triangle, ping-pong between two buffers (one barrier per step).  Waves 0
+// and 1 rotate the 120 off-diagonal 2 x 2 blocks, wave 2 the 16 diagonal blocks (and
+// records every rotation of the sweep), wave 3 holds one row of J per lane in
+// registers and applies step k's rotations while step k + 1 runs.
 #include "batch.hpp"
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace ranky {
 
-constexpr int kB = 16;       // block of indices
-constexpr int kP = 32;       // subproblem = two blocks
-constexpr int kPS = 33;      // LDS row stride of 32-wide tiles
+constexpr int kB = 16;           // block of indices
+constexpr int kP = 32;           // subproblem = two blocks
+constexpr int kPS = 33;          // LDS row stride of 32-wide tiles
+constexpr int kSteps = kP - 1;   // steps of one sweep over a subproblem
+constexpr int kTileWaves = 4;    // update tiles per workgroup (one per wave)
+
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 // Round r of the round-robin tournament on `players` (even) seats: seat 0 stays, the
 // others turn one place per round; pair i joins seat i and seat players-1-i.
+__device__ __forceinline__ int seat_block(int players, int r, int seat) {
+    return seat == 0 ? 0 : 1 + (seat - 1 + r) % (players - 1);
+}
 __device__ __forceinline__ void tournament_pair(int players, int r, int i, int &a, int &b) {
-    const int ring = players - 1;
-    const int sa = i, sb = players - 1 - i;
-    a = sa == 0 ? 0 : 1 + (sa - 1 + r) % ring;
-    b = sb == 0 ? 0 : 1 + (sb - 1 + r) % ring;
+    a = seat_block(players, r, i);
+    b = seat_block(players, r, players - 1 - i);
     if (a > b) {
         const int t = a;
         a = b;
         b = t;
     }
 }
+// Where block X sat in round r: its pair and whether it was the larger block of it.
+__device__ __forceinline__ void block_seat(int players, int r, int X, int &pair, int &half) {
+    const int ring = players - 1;
+    const int seat = X == 0 ? 0 : 1 + (((X - 1 - r) % ring) + ring) % ring;
+    pair = seat < players - seat ? seat : players - 1 - seat;
+    const int other = seat_block(players, r, players - 1 - seat);
+    half = X > other ? 1 : 0;
+}
 
 // global index of position l (0..31) of the super-block made of blocks (P, Q)
 __device__ __forceinline__ int gidx(int l, int P, int Q) { return l < kB ? P * kB + l : Q * kB + (l - kB); }
-
-__device__ __forceinline__ void rotation(double app, double aqq, double apq, double &c, double &s, double &t) {
-    const double zeta = (aqq - app) / (2.0 * apq);
-    double tt;
-    if (fabs(zeta) > 1e150)
-        tt = 0.5 / zeta;
-    else
-        tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-    c = 1.0 / sqrt(1.0 + tt * tt);
-    s = c * tt;
-    t = tt;
-}
 
 // Per-matrix arguments of one round launch (a table of these covers a batch).
 struct RoundArgs {
@@ -87,34 +104,98 @@ struct RoundArgs {
     int32_t nrowtiles;     // npad / 32
 };
 
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---- subproblem solve -------------------------------------------------------
 
-__device__ void solve_pair(const RoundArgs &a, int pair, double *S, double *J, double *T, double *JA, double *JB,
-                           int *pos) {
-    const int tid = threadIdx.x;
-    const int npairs = a.nb / 2;
+// position after one step of the in-subproblem round-robin
+__device__ __forceinline__ int turn(int p) { return p == 0 ? 0 : (p == 1 ? kP - 1 : p - 1); }
+// one-triangle storage of a symmetric 32 x 32 tile
+__device__ __forceinline__ int sym(int a, int b) { return a < b ? a * kPS + b : b * kPS + a; }
+// index that sits at position `seat` after r steps
+__device__ __forceinline__ constexpr int pos_index(int seat, int r) { return seat == 0 ? 0 : 1 + (seat - 1 + r) % 31; }
+
+// The rotation of one pair; c = 1, s = t = 0 when the pair passes the test.
+__device__ __forceinline__ bool pair_rotation(double app, double aqq, double apq, double tol2, double floor_abs,
+                                              double &c, double &s, double &t) {
+#pragma clang fp contract(off)
+    const bool act = fabs(apq) > floor_abs && apq * apq > tol2 * fabs(app * aqq);
+    const double d = aqq - app, a = 2.0 * apq;
+    const double x2 = act ? fma(d, d, a * a) : 1.0;
+    const double h = x2 * rsqrt(x2);
+    const double w = fabs(d) + h;
+    const double q = rsqrt((2.0 * h) * w);
+    const double sa = d >= 0.0 ? a : -a;
+    c = act ? w * q : 1.0;
+    s = act ? sa * q : 0.0;
+    t = act ? s * ((2.0 * h) * q) : 0.0;
+    return act;
+}
+
+// J row (in registers) <- row * R_K for the 16 rotations of step K.
+template <int K>
+__device__ __forceinline__ void jrow_step(double (&jr)[kP], const double2 *__restrict__ cs) {
+#pragma unroll
+    for (int i = 0; i < kP / 2; ++i) {
+        const int x = pos_index(i, K), y = pos_index(kP - 1 - i, K);
+        const double2 r = cs[i];
+        const double u = jr[x], v = jr[y];
+        jr[x] = r.x * u - r.y * v;
+        jr[y] = r.y * u + r.x * v;
+    }
+}
+// Step K's rotations are applied after the barrier that ends step K; one barrier
+// between consecutive steps (kSteps - 1 in all).
+template <int K>
+__device__ __forceinline__ void jrow_sweep(double (&jr)[kP], const double2 (*tab)[kP / 2]) {
+    if constexpr (K < kSteps) {
+        jrow_step<K>(jr, tab[K]);
+        if constexpr (K + 1 < kSteps) {
+            __syncthreads();
+            jrow_sweep<K + 1>(jr, tab);
+        }
+    }
+}
+
+// LDS of a solve workgroup (doubles): S0 | S1 | rotation table [31][16] | per-wave (c, s).
+// The build of S uses S1 for the gathered tile T and the table area for J slices.
+constexpr int kSoS1 = kP * kPS, kSoTab = 2 * kP * kPS, kSoWcs = kSoTab + 2 * kSteps * (kP / 2),
+              kSoEnd = kSoWcs + 2 * 2 * (kP / 2);
+constexpr int kSmemDoubles = kTileWaves * kP * kPS;
+static_assert(kSoEnd <= kSmemDoubles, "solve LDS fits the update LDS");
+static_assert(kSoTab + 2 * kP * kB <= kSoEnd, "J slices fit the table area");
+
+__device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, double *smem) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    double *S0 = smem, *S1 = smem + kSoS1;
+    double2(*tab)[kP / 2] = reinterpret_cast<double2(*)[kP / 2]>(smem + kSoTab);
+    double2(*wcs)[kP / 2] = reinterpret_cast<double2(*)[kP / 2]>(smem + kSoWcs);
     int P, Q;
     tournament_pair(a.nb, a.round_cur, pair, P, Q);
+
+    // ---- build S (upper triangle) ----
     if (!a.has_prev) {
         for (int e = tid; e < kP * kP; e += 256) {
             const int x = e >> 5, y = e & 31;
-            S[x * kPS + y] = a.Gin[(int64_t)gidx(x, P, Q) * a.ld + gidx(y, P, Q)];
+            if (x <= y) S0[x * kPS + y] = a.Gin[(int64_t)gidx(x, P, Q) * a.ld + gidx(y, P, Q)];
         }
     } else {
-        // where blocks P and Q sat in the previous round: pos[block] = pair * 2 + half
-        for (int j = tid; j < npairs; j += 256) {
-            int x, y;
-            tournament_pair(a.nb, a.round_prev, j, x, y);
-            pos[x] = 2 * j;
-            pos[y] = 2 * j + 1;
-        }
-        __syncthreads();
-        const int pp = pos[P] >> 1, hp = pos[P] & 1, pq = pos[Q] >> 1, hq = pos[Q] & 1;
+        int pp, hp, pq, hq;
+        block_seat(a.nb, a.round_prev, P, pp, hp);
+        block_seat(a.nb, a.round_prev, Q, pq, hq);
+        double *T = S1, *JA = smem + kSoTab, *JB = smem + kSoTab + kP * kB;
         // diagonal blocks: the previous round's rotated subproblems
         for (int e = tid; e < kB * kB; e += 256) {
             const int x = e >> 4, y = e & 15;
-            S[x * kPS + y] = a.Sprev[(int64_t)pp * kP * kP + (hp * kB + x) * kP + hp * kB + y];
-            S[(kB + x) * kPS + kB + y] = a.Sprev[(int64_t)pq * kP * kP + (hq * kB + x) * kP + hq * kB + y];
+            if (x <= y) {
+                S0[x * kPS + y] = a.Sprev[(int64_t)pp * kP * kP + (hp * kB + x) * kP + hp * kB + y];
+                S0[(kB + x) * kPS + kB + y] = a.Sprev[(int64_t)pq * kP * kP + (hq * kB + x) * kP + hq * kB + y];
+            }
         }
         // off-diagonal block: J_pp[:, hp]^T  M_{r-1}[s_pp, s_pq]  J_pq[:, hq]
         int Pa, Qa, Pb, Qb;
@@ -153,131 +234,160 @@ __device__ void solve_pair(const RoundArgs &a, int pair, double *S, double *J, d
             const int x = tid >> 4, y = tid & 15;
             double v = 0.0;
             for (int z = 0; z < kP; ++z) v = fma(JA[z * kB + x], T[z * kPS + y], v);
-            S[x * kPS + kB + y] = v;
-            S[(kB + y) * kPS + x] = v;
+            S0[x * kPS + kB + y] = v;
         }
-    }
-    for (int e = tid; e < kP * kP; e += 256) {
-        const int x = e >> 5, y = e & 31;
-        J[x * kPS + y] = (x == y) ? 1.0 : 0.0;
     }
     __syncthreads();
 
-    __shared__ double rc[kP / 2], rs[kP / 2], rpp[kP / 2], rqq[kP / 2];
-    __shared__ int ra[kP / 2], rb[kP / 2], ract[kP / 2];
+    // ---- sweeps ----
+    const double tol2 = a.tol * a.tol;
     const double floor_abs = a.sdbl[kSdFloor];
-    int rotated = 0;
-    const int bi = tid >> 4, bj = tid & 15;   // this thread's 2x2 block of pair slots
-    for (int sw = 0; sw < a.inner_sweeps; ++sw) {
-        int sweep_rot = 0;
-        for (int step = 0; step < kP - 1; ++step) {
-            int act = 0;
-            if (tid < kP / 2) {
-                int x, y;
-                tournament_pair(kP, step, tid, x, y);
-                const double app = S[x * kPS + x], aqq = S[y * kPS + y], apq = S[x * kPS + y];
-                double c = 1.0, s = 0.0;
-                if (fabs(apq) > floor_abs && fabs(apq) > a.tol * sqrt(fabs(app * aqq))) {
-                    double t;
-                    rotation(app, aqq, apq, c, s, t);
-                    rpp[tid] = app - t * apq;
-                    rqq[tid] = aqq + t * apq;
-                    act = 1;
-                }
-                ra[tid] = x;
-                rb[tid] = y;
-                rc[tid] = c;
-                rs[tid] = s;
-                ract[tid] = act;
-            }
-            if (__syncthreads_or(act) == 0) continue;
-            sweep_rot += 1;
-            // two-sided update of this thread's 2x2 block: R_i^T X R_j
-            {
-                const int ai = ra[bi], bi2 = rb[bi], aj = ra[bj], bj2 = rb[bj];
-                const int acti = ract[bi], actj = ract[bj];
-                if (bi == bj) {
-                    if (acti) {
-                        S[ai * kPS + ai] = rpp[bi];
-                        S[bi2 * kPS + bi2] = rqq[bi];
-                        S[ai * kPS + bi2] = 0.0;
-                        S[bi2 * kPS + ai] = 0.0;
-                    }
-                } else if (acti || actj) {
-                    double x00 = S[ai * kPS + aj], x01 = S[ai * kPS + bj2];
-                    double x10 = S[bi2 * kPS + aj], x11 = S[bi2 * kPS + bj2];
-                    if (acti) {
-                        const double c = rc[bi], s = rs[bi];
-                        const double y00 = c * x00 - s * x10, y01 = c * x01 - s * x11;
-                        const double y10 = s * x00 + c * x10, y11 = s * x01 + c * x11;
-                        x00 = y00;
-                        x01 = y01;
-                        x10 = y10;
-                        x11 = y11;
-                    }
-                    if (actj) {
-                        const double c = rc[bj], s = rs[bj];
-                        const double y00 = c * x00 - s * x01, y01 = s * x00 + c * x01;
-                        const double y10 = c * x10 - s * x11, y11 = s * x10 + c * x11;
-                        x00 = y00;
-                        x01 = y01;
-                        x10 = y10;
-                        x11 = y11;
-                    }
-                    S[ai * kPS + aj] = x00;
-                    S[ai * kPS + bj2] = x01;
-                    S[bi2 * kPS + aj] = x10;
-                    S[bi2 * kPS + bj2] = x11;
-                }
-            }
-            // J <- J R: columns of the pair, two rows per thread
-            {
-                const int p = tid & 15;
-                if (ract[p]) {
-                    const int x0 = ra[p], y0 = rb[p];
-                    const double c = rc[p], s = rs[p];
-                    for (int row = tid >> 4; row < kP; row += 16) {
-                        const double u = J[row * kPS + x0], v = J[row * kPS + y0];
-                        J[row * kPS + x0] = c * u - s * v;
-                        J[row * kPS + y0] = s * u + c * v;
-                    }
-                }
-            }
-            __syncthreads();
+    // rotation lanes: lane & 15 reads pair (rP, rQ) of the step (rP < rQ)
+    const int rP = lane & 15, rQ = kP - 1 - rP;
+    const int aPP = rP * kPS + rP, aQQ = rQ * kPS + rQ, aPQ = rP * kPS + rQ;
+    // off-diagonal block (bi < bj) of waves 0-1; diagonal block rP of wave 2
+    int bi = 0, bj = 1;
+    if (wave < 2) {
+        int rem = tid < 120 ? tid : 0, i = 0;
+        while (rem >= 15 - i) {
+            rem -= 15 - i;
+            ++i;
         }
-        rotated += sweep_rot;
-        if (sweep_rot == 0) break;
+        bi = i;
+        bj = i + 1 + rem;
     }
+    const bool live = wave < 2 ? tid < 120 : lane < 16;
+    const int Pi = wave == 2 ? rP : bi, Qi = kP - 1 - Pi, Pj = bj, Qj = kP - 1 - bj;
+    const int tPi = turn(Pi), tQi = turn(Qi), tPj = turn(Pj), tQj = turn(Qj);
+    const int b00 = sym(Pi, Pj), b01 = sym(Pi, Qj), b10 = sym(Qi, Pj), b11 = sym(Qi, Qj);
+    const int w00 = sym(tPi, tPj), w01 = sym(tPi, tQj), w10 = sym(tQi, tPj), w11 = sym(tQi, tQj);
+    const int dPP = tPi * kPS + tPi, dQQ = tQi * kPS + tQi, dPQ = sym(tPi, tQi);
+    double jr[kP];
+#pragma unroll
+    for (int c = 0; c < kP; ++c) jr[c] = c == (lane & 31) ? 1.0 : 0.0;
+    int rotated = 0;
+    for (int sw = 0; sw < a.inner_sweeps; ++sw) {
+        int rot = 0;
+        if (wave == 3) {
+            __syncthreads();          // end of step 0
+            jrow_sweep<0>(jr, tab);   // the other kSteps - 1 barriers
+        } else {
+            for (int k = 0; k < kSteps; ++k) {
+                const double *__restrict__ Sc = (k & 1) ? S1 : S0;
+                double *__restrict__ Sn = (k & 1) ? S0 : S1;
+                const double app = Sc[aPP], aqq = Sc[aQQ], apq = Sc[aPQ];
+                double x00 = 0.0, x01 = 0.0, x10 = 0.0, x11 = 0.0;
+                if (wave < 2) {
+                    x00 = Sc[b00];
+                    x01 = Sc[b01];
+                    x10 = Sc[b10];
+                    x11 = Sc[b11];
+                }
+                double c, s, t;
+                const bool act = pair_rotation(app, aqq, apq, tol2, floor_abs, c, s, t);
+                if (wave == 2) {
+                    if (lane < 16) {
+                        rot |= act;
+                        tab[k][lane] = make_double2(c, s);
+                        Sn[dPP] = fma(-t, apq, app);
+                        Sn[dQQ] = fma(t, apq, aqq);
+                        Sn[dPQ] = act ? 0.0 : apq;
+                    }
+                } else {
+                    if (lane < 16) wcs[wave][lane] = make_double2(c, s);
+                    wave_fence();
+                    const double2 ri = wcs[wave][bi], rj = wcs[wave][bj];
+                    if (live) {
+                        const double y00 = ri.x * x00 - ri.y * x10, y01 = ri.x * x01 - ri.y * x11;
+                        const double y10 = ri.y * x00 + ri.x * x10, y11 = ri.y * x01 + ri.x * x11;
+                        Sn[w00] = rj.x * y00 - rj.y * y01;
+                        Sn[w01] = rj.y * y00 + rj.x * y01;
+                        Sn[w10] = rj.x * y10 - rj.y * y11;
+                        Sn[w11] = rj.y * y10 + rj.x * y11;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        rot = __syncthreads_or(rot);
+        rotated |= rot;
+        if (!rot || sw + 1 == a.inner_sweeps) break;
+        // another sweep (single-pair matrices): start again from S0
+        for (int e = tid; e < kP * kPS; e += 256) S0[e] = S1[e];
+        __syncthreads();
+    }
+    // after an odd number of steps the matrix is in S1, positions = indices again
     for (int e = tid; e < kP * kP; e += 256) {
         const int x = e >> 5, y = e & 31;
-        a.Jcur[(int64_t)pair * kP * kP + e] = J[x * kPS + y];
-        a.Scur[(int64_t)pair * kP * kP + e] = S[x * kPS + y];
+        a.Scur[(int64_t)pair * kP * kP + e] = S1[sym(x, y)];
     }
-    if (tid == 0) a.fcur[pair] = rotated > 0;
+    if (wave == 3 && lane < kP) {
+        double *dst = a.Jcur + (int64_t)pair * kP * kP + lane * kP;
+#pragma unroll
+        for (int c = 0; c < kP; ++c) dst[c] = jr[c];
+    }
+    if (tid == 0) a.fcur[pair] = rotated;
 }
 
-// ---- update of the previous round ------------------------------------------
+// ---- update of the previous round (FP64 matrix cores) ----------------------
+//
+// v_mfma_f64_16x16x4: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; the
+// 16 x 16 result leaves element i of lane l at row l / 16 + 4 i, column l % 16.  That
+// result layout is exactly the B-operand layout of the next product over the same
+// rows (k-chunk 4 * rowblock + i), so J_a^T (G J_b) keeps G J_b in registers.
 
-// C (2x2 per thread... 4 outputs) = A (32x32) * B (32x32); transA reads A^T.
-template <bool transA>
-__device__ __forceinline__ void gemm32(const double *__restrict__ A, const double *__restrict__ B, double c[4],
-                                       int row, int col0) {
-    c[0] = c[1] = c[2] = c[3] = 0.0;
-    for (int z = 0; z < kP; ++z) {
-        const double av = transA ? A[z * kPS + row] : A[row * kPS + z];
-        const double *b = B + z * kPS + col0;
-        c[0] = fma(av, b[0], c[0]);
-        c[1] = fma(av, b[1], c[1]);
-        c[2] = fma(av, b[2], c[2]);
-        c[3] = fma(av, b[3], c[3]);
-    }
+__device__ __forceinline__ d4 mfma4(double x, double y, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
 }
 
-__device__ void update_tile(const RoundArgs &a, int u, double *A, double *B) {
-    const int tid = threadIdx.x;
+// acc = A B, A a 32 x 32 tile in LDS (stride kPS), B row-major 32 x 32 in memory.
+__device__ __forceinline__ void mm_lds_mem(const double *__restrict__ A, const double *__restrict__ B, d4 (&acc)[2][2],
+                                           int l) {
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kc = 0; kc < 8; ++kc) {
+        const int k = kc * 4 + (l >> 4);
+        const double a0 = A[(l & 15) * kPS + k], a1 = A[(16 + (l & 15)) * kPS + k];
+        const double b0 = B[k * kP + (l & 15)], b1 = B[k * kP + 16 + (l & 15)];
+        acc[0][0] = mfma4(a0, b0, acc[0][0]);
+        acc[0][1] = mfma4(a0, b1, acc[0][1]);
+        acc[1][0] = mfma4(a1, b0, acc[1][0]);
+        acc[1][1] = mfma4(a1, b1, acc[1][1]);
+    }
+}
+// out = Ja^T T, T in result layout (registers), Ja row-major 32 x 32 in memory.
+__device__ __forceinline__ void mm_t_reg(const double *__restrict__ Ja, const d4 (&T)[2][2], d4 (&out)[2][2], int l) {
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) out[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kc = 0; kc < 8; ++kc) {
+        const int k = kc * 4 + (l >> 4);
+        const double a0 = Ja[k * kP + (l & 15)], a1 = Ja[k * kP + 16 + (l & 15)];
+        const double b0 = T[kc >> 2][0][kc & 3], b1 = T[kc >> 2][1][kc & 3];
+        out[0][0] = mfma4(a0, b0, out[0][0]);
+        out[0][1] = mfma4(a0, b1, out[0][1]);
+        out[1][0] = mfma4(a1, b0, out[1][0]);
+        out[1][1] = mfma4(a1, b1, out[1][1]);
+    }
+}
+// result layout <- 32 x 32 tile in LDS
+__device__ __forceinline__ void lds_to_acc(const double *__restrict__ A, d4 (&acc)[2][2], int l) {
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[rb][cb][i] = A[(16 * rb + (l >> 4) + 4 * i) * kPS + 16 * cb + (l & 15)];
+}
+
+__device__ __forceinline__ void update_tile(const RoundArgs &a, int u, double *buf) {
+    const int l = threadIdx.x & 63;
     const int npairs = a.nb / 2;
-    const int row = tid >> 3, col0 = (tid & 7) * 4;
-    double c[4];
     if (u < a.ntiles_g) {
         int ia = 0, rem = u;
         while (rem >= npairs - ia) {
@@ -290,38 +400,52 @@ __device__ void update_tile(const RoundArgs &a, int u, double *A, double *B) {
         tournament_pair(a.nb, a.round_prev, ib, Pb, Qb);
         if (ia == ib) {
             const double *s = a.Sprev + (int64_t)ia * kP * kP;
-            for (int e = tid; e < kP * kP; e += 256)
+            for (int e = l; e < kP * kP; e += 64)
                 a.Gout[(int64_t)gidx(e >> 5, Pa, Qa) * a.ld + gidx(e & 31, Pa, Qa)] = s[e];
             return;
         }
         const bool fa = a.fprev[ia] != 0, fb = a.fprev[ib] != 0;
-        for (int e = tid; e < kP * kP; e += 256) {
+        for (int e = l; e < kP * kP; e += 64) {
             const int x = e >> 5, y = e & 31;
-            A[x * kPS + y] = a.Gin[(int64_t)gidx(x, Pa, Qa) * a.ld + gidx(y, Pb, Qb)];
+            buf[x * kPS + y] = a.Gin[(int64_t)gidx(x, Pa, Qa) * a.ld + gidx(y, Pb, Qb)];
         }
-        if (fb) {
-            const double *jb = a.Jprev + (int64_t)ib * kP * kP;
-            for (int e = tid; e < kP * kP; e += 256) B[(e >> 5) * kPS + (e & 31)] = jb[e];
-            __syncthreads();
-            gemm32<false>(A, B, c, row, col0);
-            __syncthreads();
-            for (int v = 0; v < 4; ++v) A[row * kPS + col0 + v] = c[v];
-        }
+        wave_fence();
+        d4 t[2][2], o[2][2];
+        if (fb) mm_lds_mem(buf, a.Jprev + (int64_t)ib * kP * kP, t, l);
+        else lds_to_acc(buf, t, l);
         if (fa) {
-            const double *ja = a.Jprev + (int64_t)ia * kP * kP;
-            __syncthreads();
-            for (int e = tid; e < kP * kP; e += 256) B[(e >> 5) * kPS + (e & 31)] = ja[e];
-            __syncthreads();
-            gemm32<true>(B, A, c, row, col0);
-            __syncthreads();
-            for (int v = 0; v < 4; ++v) A[row * kPS + col0 + v] = c[v];
+            mm_t_reg(a.Jprev + (int64_t)ia * kP * kP, t, o, l);
+        } else {
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) o[rb][cb] = t[rb][cb];
         }
-        __syncthreads();
-        for (int e = tid; e < kP * kP; e += 256) {
-            const int x = e >> 5, y = e & 31;
-            const double v = A[x * kPS + y];
-            a.Gout[(int64_t)gidx(x, Pa, Qa) * a.ld + gidx(y, Pb, Qb)] = v;
-            a.Gout[(int64_t)gidx(y, Pb, Qb) * a.ld + gidx(x, Pa, Qa)] = v;
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                const d4 v = o[rb][cb];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int x = 16 * rb + (l >> 4) + 4 * i, y = 16 * cb + (l & 15);
+                    a.Gout[(int64_t)gidx(x, Pa, Qa) * a.ld + gidx(y, Pb, Qb)] = v[i];
+                }
+            }
+        // the mirror tile through LDS, so its stores are row runs as well
+        wave_fence();
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                const d4 v = o[rb][cb];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) buf[(16 * rb + (l >> 4) + 4 * i) * kPS + 16 * cb + (l & 15)] = v[i];
+            }
+        wave_fence();
+        for (int e = l; e < kP * kP; e += 64) {
+            const int x = e >> 5, y = e & 31;   // element (y, x) of the tile = (x, y) of its mirror
+            a.Gout[(int64_t)gidx(x, Pb, Qb) * a.ld + gidx(y, Pa, Qa)] = buf[y * kPS + x];
         }
         return;
     }
@@ -330,22 +454,27 @@ __device__ void update_tile(const RoundArgs &a, int u, double *A, double *B) {
     if (rt >= a.nrowtiles || !a.fprev[ib]) return;
     int Pb, Qb;
     tournament_pair(a.nb, a.round_prev, ib, Pb, Qb);
-    const double *jb = a.Jprev + (int64_t)ib * kP * kP;
-    for (int e = tid; e < kP * kP; e += 256) {
+    for (int e = l; e < kP * kP; e += 64) {
         const int x = e >> 5, y = e & 31;
-        A[x * kPS + y] = a.W[(int64_t)(rt * kP + x) * a.ld + gidx(y, Pb, Qb)];
-        B[x * kPS + y] = jb[e];
+        buf[x * kPS + y] = a.W[(int64_t)(rt * kP + x) * a.ld + gidx(y, Pb, Qb)];
     }
-    __syncthreads();
-    gemm32<false>(A, B, c, row, col0);
-    for (int v = 0; v < 4; ++v) a.W[(int64_t)(rt * kP + row) * a.ld + gidx(col0 + v, Pb, Qb)] = c[v];
+    wave_fence();
+    d4 t[2][2];
+    mm_lds_mem(buf, a.Jprev + (int64_t)ib * kP * kP, t, l);
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = 16 * rb + (l >> 4) + 4 * i, y = 16 * cb + (l & 15);
+                a.W[(int64_t)(rt * kP + x) * a.ld + gidx(y, Pb, Qb)] = t[rb][cb][i];
+            }
 }
 
 __global__ __launch_bounds__(256) void k_jround(const RoundArgs *__restrict__ table, const int32_t *__restrict__ wp,
                                                 int count, int32_t launch_r) {
-    __shared__ double L0[kP * kPS], L1[kP * kPS], L2[kP * kPS];
-    __shared__ double L3[kP * kB], L4[kP * kB];
-    __shared__ int pos[512];
+    __shared__ __align__(16) double smem[kSmemDoubles];
     const int mat = find_mat(wp, count, blockIdx.x);
     RoundArgs a = table[mat];
     if (a.jstate[kJsActive] == 0) return;
@@ -357,12 +486,13 @@ __global__ __launch_bounds__(256) void k_jround(const RoundArgs *__restrict__ ta
     int b = blockIdx.x - wp[mat];
     if (a.do_solve) {
         if (b < npairs) {
-            solve_pair(a, b, L0, L1, L2, L3, L4, pos);
+            solve_pair(a, b, smem);
             return;
         }
         b -= npairs;
     }
-    update_tile(a, b, L0, L1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    update_tile(a, b * kTileWaves + wave, smem + wave * kP * kPS);
 }
 
 // The G buffer holding the matrix after `sweeps` complete sweeps.
@@ -372,7 +502,7 @@ __device__ __forceinline__ const double *current_g(const MatDesc &d) {
 }
 
 // Sets jstate[kJsNotConv] = 1 if an off-diagonal entry of the leading n x n part
-// still fails the rotation test (one thread per entry of the upper triangle).
+// still fails the rotation test.  Row p of the upper triangle per workgroup pass.
 __global__ __launch_bounds__(256) void k_jcheck(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
                                                 int count) {
     const int mat = find_mat(wp, count, blockIdx.x);
@@ -382,13 +512,14 @@ __global__ __launch_bounds__(256) void k_jcheck(const MatDesc *__restrict__ desc
     const double *__restrict__ G = current_g(d);
     const double floor_abs = d.sdbl[kSdFloor];
     const double tol = fmax(1e-15, sqrt((double)n) * 2.220446049250313e-16);
+    const double tol2 = tol * tol;
     const int64_t nblk = wp[mat + 1] - wp[mat];
     int bad = 0;
     for (int64_t p = blockIdx.x - wp[mat]; p < n; p += nblk) {
         const double gpp = G[p * ld + p];
         for (int64_t q = p + 1 + threadIdx.x; q < n; q += blockDim.x) {
             const double g = G[p * ld + q];
-            if (fabs(g) > floor_abs && fabs(g) > tol * sqrt(fabs(gpp * G[q * ld + q]))) bad = 1;
+            if (fabs(g) > floor_abs && g * g > tol2 * fabs(gpp * G[q * ld + q])) bad = 1;
         }
     }
     if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(&d.jstate[kJsNotConv], 1);
@@ -413,8 +544,8 @@ __global__ __launch_bounds__(256) void k_jstate(const MatDesc *__restrict__ desc
     }
 }
 
-// Per matrix: W = I, floor = (n eps)^2 max|g_ii|, state cleared.  One workgroup per
-// (matrix, slice) for the identity; slice 0 also does the floor.
+// Per matrix: W = I; workgroup 0 also finds m = max|g_ii|, the power of two 2^-e that
+// brings m into [1/2, 1) and the floor (n eps)^2 m 2^-e, and clears the state.
 __global__ __launch_bounds__(256) void k_jinit(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
                                                int count) {
     __shared__ double red[256];
@@ -435,20 +566,39 @@ __global__ __launch_bounds__(256) void k_jinit(const MatDesc *__restrict__ descs
         __syncthreads();
     }
     if (threadIdx.x == 0) {
+        const double mx = red[0];
+        int e = 0;
+        if (mx > 0.0) (void)frexp(mx, &e);
+        const double scale = ldexp(1.0, -e);
         const double ne = (double)d.n * 2.220446049250313e-16;
-        d.sdbl[kSdFloor] = ne * ne * red[0];
+        d.sdbl[kSdScale] = scale;
+        d.sdbl[kSdFloor] = ne * ne * (mx * scale);
         d.jstate[kJsSweeps] = 0;
         d.jstate[kJsActive] = 0;
         d.jstate[kJsNotConv] = 0;
     }
 }
 
+// G *= 2^-e (exact), after k_jinit.
+__global__ __launch_bounds__(256) void k_jscale(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
+                                                int count) {
+    const int mat = find_mat(wp, count, blockIdx.x);
+    const MatDesc &d = descs[mat];
+    const int64_t npad = d.npad;
+    const int64_t nblk = wp[mat + 1] - wp[mat];
+    const int64_t b = blockIdx.x - wp[mat];
+    const double scale = d.sdbl[kSdScale];
+    if (scale == 1.0) return;
+    for (int64_t e = b * blockDim.x + threadIdx.x; e < npad * npad; e += nblk * blockDim.x) d.G[e] *= scale;
+}
+
+// lambda_i = g_ii 2^e
 __global__ __launch_bounds__(256) void k_jdiag(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
                                                int count) {
     const int mat = find_mat(wp, count, blockIdx.x);
     const MatDesc &d = descs[mat];
     const int32_t i = (blockIdx.x - wp[mat]) * blockDim.x + threadIdx.x;
-    if (i < d.n) d.lam[i] = current_g(d)[(int64_t)i * d.npad + i];
+    if (i < d.n) d.lam[i] = current_g(d)[(int64_t)i * d.npad + i] / d.sdbl[kSdScale];
 }
 
 // ---------------------------------------------------------------------------
@@ -458,6 +608,7 @@ int32_t jacobi_npad(int32_t n) { return ((n + kP - 1) / kP) * kP; }
 void launch_jacobi_init(const MatDesc *descs, const int32_t *wp, int64_t nblocks, int count, hipStream_t s) {
     if (nblocks <= 0) return;
     hipLaunchKernelGGL(k_jinit, dim3((unsigned)nblocks), dim3(256), 0, s, descs, wp, count);
+    hipLaunchKernelGGL(k_jscale, dim3((unsigned)nblocks), dim3(256), 0, s, descs, wp, count);
 }
 
 void launch_jacobi_state(const MatDesc *descs, int count, int32_t phase, int32_t max_sweeps, hipStream_t s) {
@@ -522,7 +673,10 @@ int64_t round_blocks(const MatDesc &d, int32_t r) {
     const int32_t npairs = nb / 2;
     int64_t b = 0;
     if (r < nb - 1) b += npairs;
-    if (r > 0 && r <= nb - 1) b += (int64_t)npairs * (npairs + 1) / 2 + (int64_t)(d.npad / kP) * npairs;
+    if (r > 0 && r <= nb - 1) {
+        const int64_t tiles = (int64_t)npairs * (npairs + 1) / 2 + (int64_t)(d.npad / kP) * npairs;
+        b += (tiles + kTileWaves - 1) / kTileWaves;
+    }
     return b;
 }
 
