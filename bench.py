@@ -49,18 +49,22 @@ def time_path(ranky, torch, np, dA, A, k, D, prec, steps, warmup):
                           torch.empty((A.M, k), dtype=torch.float64, device="cuda:0"),
                           torch.empty((A.N, k), dtype=vdt, device="cuda:0"), {})
     ctx = ranky.context(0)
-    for _ in range(warmup):
-        ranky.svd(dA, k, 0.0, ctx=ctx, out=out, workspace=ws, **kw)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        ranky.svd(dA, k, 0.0, ctx=ctx, out=out, workspace=ws, **kw)
-    torch.cuda.synchronize()
-    ms_step = 1e3 * (time.perf_counter() - t0) / steps
-    phases = np.zeros(8)
-    for _ in range(steps):
-        r = ranky.svd(dA, k, 0.0, ctx=ctx, out=out, workspace=ws, timing=True, **kw)
-        phases += np.array(r.info["ms"])
+    # a stream of our own, so the Jacobi sweep can be replayed as a captured HIP graph
+    stream = torch.cuda.Stream()
+    kw["graph"] = True
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            ranky.svd(dA, k, 0.0, ctx=ctx, out=out, workspace=ws, stream=stream, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ranky.svd(dA, k, 0.0, ctx=ctx, out=out, workspace=ws, stream=stream, **kw)
+        torch.cuda.synchronize()
+        ms_step = 1e3 * (time.perf_counter() - t0) / steps
+        phases = np.zeros(8)
+        for _ in range(steps):
+            r = ranky.svd(dA, k, 0.0, ctx=ctx, out=out, workspace=ws, stream=stream, timing=True, **kw)
+            phases += np.array(r.info["ms"])
     phases /= steps
     names = ["occupancy", "transpose", "gram", "eigensolve", "select", "refine", "backproject", "total"]
     return ms_step, dict(zip(names, phases.tolist())), r.info, out.sigma.cpu().numpy(), vdt

@@ -86,7 +86,8 @@ typedef struct {
     int32_t validate;   /* 1 = check the CSC contract and finiteness on the device (default 1) */
     int32_t v_dtype;    /* ranky_dtype of the output V (default F64) */
     int32_t timing;     /* 1 = fill ranky_info.ms with per-phase times (adds event records) */
-    int32_t reserved;   /* ranky_batch: 1 = replay the Jacobi sweep as a captured HIP graph */
+    int32_t reserved;   /* 1 = replay the Jacobi sweep as a captured HIP graph (ranky_svd and
+                           ranky_batch; needs a non-NULL stream, ignored on the NULL stream) */
 } ranky_opts;
 
 typedef struct {

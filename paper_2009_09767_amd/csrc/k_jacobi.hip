@@ -502,9 +502,12 @@ __device__ __forceinline__ const double *current_g(const MatDesc &d) {
 }
 
 // Sets jstate[kJsNotConv] = 1 if an off-diagonal entry of the leading n x n part
-// still fails the rotation test.  Row p of the upper triangle per workgroup pass.
+// still fails the rotation test.  One workgroup per 64 x 64 tile (ti <= tj) of the
+// upper triangle; the tile's row and column diagonal entries are staged in LDS.
 __global__ __launch_bounds__(256) void k_jcheck(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
                                                 int count) {
+    constexpr int kT = kJacobiCheckTile;
+    __shared__ double drow[kT], dcol[kT];
     const int mat = find_mat(wp, count, blockIdx.x);
     const MatDesc &d = descs[mat];
     const int32_t n = d.n;
@@ -513,13 +516,29 @@ __global__ __launch_bounds__(256) void k_jcheck(const MatDesc *__restrict__ desc
     const double floor_abs = d.sdbl[kSdFloor];
     const double tol = fmax(1e-15, sqrt((double)n) * 2.220446049250313e-16);
     const double tol2 = tol * tol;
-    const int64_t nblk = wp[mat + 1] - wp[mat];
+    const int T = (n + kT - 1) / kT;
+    int ti = 0, rem = blockIdx.x - wp[mat];
+    while (rem >= T - ti) {
+        rem -= T - ti;
+        ++ti;
+    }
+    const int tj = ti + rem;
+    const int64_t r0 = (int64_t)ti * kT, c0 = (int64_t)tj * kT;
+    if (threadIdx.x < kT) {
+        const int64_t p = r0 + threadIdx.x;
+        drow[threadIdx.x] = p < n ? G[p * ld + p] : 0.0;
+    } else if (threadIdx.x < 2 * kT) {
+        const int64_t q = c0 + threadIdx.x - kT;
+        dcol[threadIdx.x - kT] = q < n ? G[q * ld + q] : 0.0;
+    }
+    __syncthreads();
     int bad = 0;
-    for (int64_t p = blockIdx.x - wp[mat]; p < n; p += nblk) {
-        const double gpp = G[p * ld + p];
-        for (int64_t q = p + 1 + threadIdx.x; q < n; q += blockDim.x) {
+    for (int e = threadIdx.x; e < kT * kT; e += 256) {
+        const int r = e / kT, c = e % kT;
+        const int64_t p = r0 + r, q = c0 + c;
+        if (q > p && q < n) {
             const double g = G[p * ld + q];
-            if (fabs(g) > floor_abs && g * g > tol2 * fabs(gpp * G[q * ld + q])) bad = 1;
+            if (fabs(g) > floor_abs && g * g > tol2 * fabs(drow[r] * dcol[c])) bad = 1;
         }
     }
     if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(&d.jstate[kJsNotConv], 1);

@@ -42,6 +42,7 @@ hipError_t gram_set_attributes(size_t lds_limit);
 int32_t jacobi_npad(int32_t n);  // multiple of the 32-wide subproblem
 constexpr int32_t kJacobiPair = 32;
 constexpr int32_t kJacobiBlock = 16;
+constexpr int32_t kJacobiCheckTile = 64;   // k_jcheck: one workgroup per 64 x 64 tile of the upper triangle
 size_t round_args_bytes();
 void fill_round_args(void *dst, const MatDesc &d, int32_t r, int32_t inner_sweeps);
 int64_t round_blocks(const MatDesc &d, int32_t r);

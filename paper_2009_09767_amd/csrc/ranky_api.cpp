@@ -368,7 +368,11 @@ struct Engine {
             const int64_t sl = ((int64_t)d[i].npad * d[i].npad + 8191) / 8192;
             return std::min<int64_t>(std::max<int64_t>(sl, 1), 64);
         });
-        nblk[kPhJcheck] = fill_wp(hwp(kPhJcheck), count, [&](int i) { return live(i) ? (int64_t)std::min(d[i].n, 512) : 0; });
+        nblk[kPhJcheck] = fill_wp(hwp(kPhJcheck), count, [&](int i) -> int64_t {
+            if (!live(i)) return 0;
+            const int64_t t = (d[i].n + kJacobiCheckTile - 1) / kJacobiCheckTile;
+            return t * (t + 1) / 2;
+        });
         nblk[kPhJdiag] = fill_wp(hwp(kPhJdiag), count, [&](int i) { return live(i) ? (int64_t)(d[i].n + 255) / 256 : 0; });
         nblk[kPhGather] = fill_wp(hwp(kPhGather), count, [&](int i) { return status[i] == RANKY_OK ? (int64_t)d[i].k : 0; });
         nblk[kPhBack] = fill_wp(hwp(kPhBack), count, [&](int i) {
@@ -813,7 +817,8 @@ ranky_status ranky_svd(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N,
     if (st) return finish(st);
     if (o.refine && k > kMaxRefineK) return finish(fail(RANKY_E_INVALID, "refine needs k <= %d", kMaxRefineK));
     if (hipSetDevice(ctx->device) != hipSuccess) return finish(fail(RANKY_E_DEVICE, "hipSetDevice"));
-    return finish(run_path(ctx, {j}, tol, o, workspace, ws_bytes, inf, reinterpret_cast<hipStream_t>(stream), false));
+    return finish(run_path(ctx, {j}, tol, o, workspace, ws_bytes, inf, reinterpret_cast<hipStream_t>(stream),
+                           o.reserved == 1));
 }
 
 size_t ranky_batch_workspace_bytes(int32_t count, const ranky_batch_item *items, const ranky_opts *opts) {

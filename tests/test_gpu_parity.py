@@ -241,6 +241,27 @@ def test_deterministic_and_block_count_invariant(R):
         assert np.array_equal(o.V.cpu().numpy(), base.V.cpu().numpy())
 
 
+def test_graph_replay_equals_direct_launches(R):
+    """The sweep captured once as a HIP graph and replayed (same shapes, different data,
+    eager work in between) gives bitwise the results of direct launches."""
+    import torch
+
+    mats = [gen.random_sparse(96, 5000, 0.03, seed=s) for s in (1, 2, 3)]
+    dms = [R.to_device(A) for A in mats]
+    direct = [R.svd(dA, 40, 0.0, n_blocks=8) for dA in dms]
+    ctx = R.context(0)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for rep in range(2):
+            for dA, ref in zip(dms, direct):
+                out = R.svd(dA, 40, 0.0, n_blocks=8, ctx=ctx, stream=stream, graph=True)
+                torch.cuda.synchronize()
+                junk = torch.randn(1000, device="cuda").sum()   # eager work between replays
+                assert torch.isfinite(junk)
+                assert torch.equal(out.sigma, ref.sigma) and torch.equal(out.U, ref.U) and torch.equal(out.V, ref.V)
+                assert out.info["rank"] == ref.info["rank"] and out.info["sweeps"] == ref.info["sweeps"]
+
+
 def test_errors_are_reported(R):
     import torch
 
