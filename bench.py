@@ -29,7 +29,57 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-matrix leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--no-other", action="store_true", help="skip the other-precision leg of the headline matrix")
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                    help="only run a device-to-device copy of this many GiB (counter calibration) and exit")
     return ap.parse_args()
+
+
+# HBM bytes per working launch of k_jround on the cfg2 FP64 leg, from two rocprofv3 counter
+# runs (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, averaged over the launches that did work),
+# each scaled by what the same counter reads back for a plain device copy of 1 GiB (x2.0 for
+# FETCH_SIZE, x1.0 for WRITE_SIZE).  Valid only for the kernel source it was taken on.
+JROUND_TRAFFIC = {"bytes": (6623.26 * 2.0 + 15190.33) * 1024, "source_sha256": "40f9ead5096f4d91ca89a611a6ce36cb05ae39034a3ab9625570aea8c5a1e1b1"}
+
+
+def jround_traffic():
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_2009_09767_amd", "csrc", "k_jacobi.hip")
+    with open(src, "rb") as f:
+        ok = hashlib.sha256(f.read()).hexdigest() == JROUND_TRAFFIC["source_sha256"]
+    return JROUND_TRAFFIC["bytes"] if ok else None
+
+
+def jround_flops(n):
+    """Algorithmic FP64 flops of the Jacobi round launches of one sweep on an n x n Gram, per
+    launch.  npad = 32 ceil(n / 32), P = npad / 32 subproblems per round, nb = 2P launches.
+    Update (rounds 1..nb-1): the P(P-1)/2 off-diagonal 32 x 32 tiles of G take two 32^3
+    products (J_a^T G_ab J_b, the mirror tile is a copy), the npad/32 x P tiles of W one
+    (W J): 2 * 32^3 flops per product.  Solve (rounds 0..nb-2), per subproblem: the build
+    (32 x 32 x 16 and 16 x 32 x 16 products) and 31 steps of 120 off-diagonal 2 x 2 two-sided
+    rotations (24 flops), 16 diagonal ones (12), 16 x 32 J-row rotations (6) and 16 rotation
+    angles (about 20)."""
+    npad = 32 * ((n + 31) // 32)
+    P = npad // 32
+    nb = 2 * P
+    gemm = 2 * 32 ** 3
+    upd = (P * (P - 1) // 2) * 2 * gemm + (npad // 32) * P * gemm
+    solve = P * (2 * 32 * 32 * 16 + 2 * 16 * 32 * 16 + 31 * (120 * 24 + 16 * 12 + 16 * 32 * 6 + 16 * 20))
+    return (nb - 1) * (upd + solve) / nb
+
+
+def copy_calibration(gib):
+    """A plain device copy of known size, run under the same counters as the kernels."""
+    import torch
+
+    n = int(gib * 2**30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": 8 * n, "launches": 3}), flush=True)
 
 
 def spmm_bytes(nnz, N, k, M, val_bytes, out_bytes):
@@ -62,12 +112,18 @@ def time_path(ranky, torch, np, dA, A, k, D, prec, steps, warmup):
         torch.cuda.synchronize()
         ms_step = 1e3 * (time.perf_counter() - t0) / steps
         phases = np.zeros(8)
+        round_ms, round_launches = 0.0, 0
         for _ in range(steps):
             r = ranky.svd(dA, k, 0.0, ctx=ctx, out=out, workspace=ws, stream=stream, timing=True, **kw)
             phases += np.array(r.info["ms"])
+            round_ms += r.info["round_ms"]
+            round_launches += r.info["round_launches"]
     phases /= steps
     names = ["occupancy", "transpose", "gram", "eigensolve", "select", "refine", "backproject", "total"]
-    return ms_step, dict(zip(names, phases.tolist())), r.info, out.sigma.cpu().numpy(), vdt
+    info = dict(r.info)
+    info["round_us_avg"] = 1e3 * round_ms / max(round_launches, 1)
+    info["round_launches_per_call"] = round_launches / steps
+    return ms_step, dict(zip(names, phases.tolist())), info, out.sigma.cpu().numpy(), vdt
 
 
 def time_batch(ranky, torch, gen, steps, warmup):
@@ -162,6 +218,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration)
+        return
     import numpy as np
     import torch
 
@@ -172,13 +231,17 @@ def main():
     dA = ranky.to_device(A, "cuda:0")
     ms_step, phases, info, sig64, vdt = time_path(ranky, torch, np, dA, A, k, D, args.prec, args.steps, args.warmup)
     other = "fp32" if args.prec == "fp64" else "fp64"
-    ms2, phases2, info2, sig2, vdt2 = time_path(ranky, torch, np, dA, A, k, D, other, args.steps, args.warmup)
+    if not args.no_other:
+        ms2, phases2, info2, sig2, vdt2 = time_path(ranky, torch, np, dA, A, k, D, other, args.steps, args.warmup)
 
     val_bytes = 8 if A.values.dtype == np.float64 else 4
     out_bytes = 8 if vdt == torch.float64 else 4
     sb = spmm_bytes(A.nnz, A.N, k, A.M, val_bytes, out_bytes)
     spmm_ms = float(phases["backproject"])
     achieved = sb / (spmm_ms * 1e-3) / 1e9
+    # the dominant kernel: the Jacobi round (FP64 matrix cores for the update, FP64 ALU for the solve)
+    jf = jround_flops(info["n_nonempty"])
+    jr_tfs = jf / (info["round_us_avg"] * 1e-6) / 1e12
 
     line = {
         "metric": "nnz/s, full sparse SVD at stated sigma error vs FP64 path",
@@ -198,12 +261,18 @@ def main():
         "rank": info["rank"],
         "sweeps": info["sweeps"],
         "phase_ms": phases,
-        "roofline": {"kernel": "k_backproject (V = A^T U Sigma^-1)", "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": sb},
-        other + "_path": {"value": A.nnz / (ms2 * 1e-3), "ms_per_step": ms2, "phase_ms": phases2,
-                          "rank": info2["rank"], "sweeps": info2["sweeps"]},
+        "roofline": {"kernel": "k_jround (Jacobi round: subproblem sweep + FP64 MFMA tile update)",
+                     "bound": "mfma", "achieved": jr_tfs, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                     "frac": jr_tfs / FP64_PEAK_TFS, "traffic": jround_traffic(), "flops_per_launch": jf,
+                     "avg_launch_us": info["round_us_avg"], "launches_per_step": info["round_launches_per_call"],
+                     "dtype": "fp64"},
+        "roofline_spmm": {"kernel": "k_backproject (V = A^T U Sigma^-1)", "bound": "hbm", "achieved": achieved,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                          "bytes_per_launch": sb},
     }
+    if not args.no_other:
+        line[other + "_path"] = {"value": A.nnz / (ms2 * 1e-3), "ms_per_step": ms2, "phase_ms": phases2,
+                                 "rank": info2["rank"], "sweeps": info2["sweeps"]}
 
     if not args.no_batch:
         line["batch"] = time_batch(ranky, torch, gen, max(2, args.steps // 3), 1)
@@ -222,7 +291,9 @@ def main():
                                 "sample": "the whole workload once: FP64 sparse Gram + cyclic Jacobi + V (Gram route)",
                                 "seconds": t_cpu}
         line["sigma_rel_err_vs_oracle"] = float(np.max(np.abs(sig64[:r] - ref.sigma[:r]) / ref.sigma[:r]))
-        line[other + "_path"]["sigma_rel_err_vs_oracle"] = float(np.max(np.abs(sig2[:r] - ref.sigma[:r]) / ref.sigma[:r]))
+        if not args.no_other:
+            line[other + "_path"]["sigma_rel_err_vs_oracle"] = float(
+                np.max(np.abs(sig2[:r] - ref.sigma[:r]) / ref.sigma[:r]))
     print(json.dumps(line), flush=True)
 
 

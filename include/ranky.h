@@ -103,6 +103,10 @@ typedef struct {
     double sigma_max;      /* sigma_1 */
     float ms[8];           /* with opts.timing: [0] occupancy+plan, [1] transpose, [2] Gram,
                               [3] eigensolve, [4] select, [5] refine, [6] back-projection, [7] total */
+    float round_ms;        /* with opts.timing (ranky_svd): summed span of the Jacobi round launches of
+                              the sweeps that did work (HIP events on the call's stream; the sweep is
+                              launched directly, not replayed, in timing mode) */
+    int32_t round_launches; /* number of round launches inside round_ms */
 } ranky_info;
 
 typedef struct ranky_ctx ranky_ctx;

@@ -239,9 +239,30 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, double 
     }
     __syncthreads();
 
-    // ---- sweeps ----
     const double tol2 = a.tol * a.tol;
     const double floor_abs = a.sdbl[kSdFloor];
+    // a subproblem whose off-diagonal entries all pass the rotation test is left as is
+    {
+        int bad = 0;
+        for (int e = tid; e < kP * kP; e += 256) {
+            const int x = e >> 5, y = e & 31;
+            if (x < y) {
+                const double g = S0[x * kPS + y];
+                bad |= fabs(g) > floor_abs && g * g > tol2 * fabs(S0[x * kPS + x] * S0[y * kPS + y]);
+            }
+        }
+        if (__syncthreads_or(bad) == 0) {
+            for (int e = tid; e < kP * kP; e += 256) {
+                const int x = e >> 5, y = e & 31;
+                a.Scur[(int64_t)pair * kP * kP + e] = S0[sym(x, y)];
+                a.Jcur[(int64_t)pair * kP * kP + e] = x == y ? 1.0 : 0.0;
+            }
+            if (tid == 0) a.fcur[pair] = 0;
+            return;
+        }
+    }
+
+    // ---- sweeps ----
     // rotation lanes: lane & 15 reads pair (rP, rQ) of the step (rP < rQ)
     const int rP = lane & 15, rQ = kP - 1 - rP;
     const int aPP = rP * kPS + rP, aQQ = rQ * kPS + rQ, aPQ = rP * kPS + rQ;

@@ -130,9 +130,10 @@ __global__ __launch_bounds__(256) void k_gather_u(const MatDesc *__restrict__ de
 }
 
 // V[j][i] = (sum over the nonzeros a_mj of column j of a_mj U[m][i]) / sigma[i] for
-// i < rank, else 0.  One wave per column (grid-stride); a lane owns two consecutive
-// outputs i, so a wave covers 128 outputs per pass with 16-byte U loads.  The
-// column's nonzeros are read once per pass; U rows come from L2.
+// i < rank, else 0.  A wave handles one column at a time, over a contiguous run of
+// columns; a lane owns two consecutive outputs i, so a wave covers 128 outputs per pass
+// with 16-byte U loads.  The column's nonzeros are read once per pass; U rows come
+// from L2, and V goes out with non-temporal stores so it does not evict them.
 template <typename TV, typename TO>
 __device__ void backproject_cols(const int32_t *__restrict__ colptr, const int32_t *__restrict__ rowidx,
                                  const TV *__restrict__ vals, int64_t N, int32_t k, const double *__restrict__ U,
@@ -145,7 +146,11 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr, const int32
         const double s0 = (ok0 && i < rank) ? sigma[i] : 0.0;
         const double s1 = (ok1 && i + 1 < rank) ? sigma[i + 1] : 0.0;
         const bool live0 = ok0 && i < rank, live1 = ok1 && i + 1 < rank;
-        for (int64_t j = wave; j < N; j += nwaves) {
+        // a contiguous run of columns per wave: each line of colptr / rowidx / values is
+        // then read by one wave, hence one XCD's L2 (a stride would pull it into all of them)
+        const int64_t per = (N + nwaves - 1) / nwaves;
+        const int64_t jb = wave * per, je = jb + per < N ? jb + per : N;
+        for (int64_t j = jb; j < je; ++j) {
             const int32_t e0 = colptr[j], e1 = colptr[j + 1];
             double a0 = 0.0, a1 = 0.0;
             for (int32_t e = e0; e < e1; ++e) {
@@ -162,7 +167,12 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr, const int32
             const double v0 = live0 ? a0 / s0 : 0.0;
             const double v1 = live1 ? a1 / s1 : 0.0;
             TO *out = V + j * (int64_t)k + i;
-            if (ok1) {
+            if (ok1 && (k & 1) == 0) {
+                // one 2-wide store per lane (i is even and k is even, so it is aligned)
+                typedef TO TO2 __attribute__((ext_vector_type(2)));
+                const TO2 w = {static_cast<TO>(v0), static_cast<TO>(v1)};
+                __builtin_nontemporal_store(w, reinterpret_cast<TO2 *>(out));
+            } else if (ok1) {
                 __builtin_nontemporal_store(static_cast<TO>(v0), out);
                 __builtin_nontemporal_store(static_cast<TO>(v1), out + 1);
             } else if (ok0) {

@@ -23,7 +23,7 @@ struct ranky_ctx {
     size_t lds_limit = 0;      // dynamic LDS the Gram kernel may use per workgroup
     void *pinned = nullptr;    // host staging for descriptor uploads and scalar read-back
     size_t pinned_bytes = 0;
-    hipEvent_t ev[9] = {};
+    hipEvent_t ev[11] = {};     // [0..7] phase marks, [9] [10] span of a sweep's round launches
     hipGraphExec_t sweep_graph = nullptr;  // captured Jacobi sweep of the last graph batch
     const void *sweep_graph_key = nullptr;
     size_t sweep_graph_sig = 0;
@@ -292,6 +292,9 @@ struct Engine {
     std::vector<int64_t> rblk;
     int32_t maxM = 1, maxn = 1, nb_max = 0;
     int32_t sweeps_cap = kDefaultSweeps;
+    bool time_rounds = false;        // timing mode: events around the round launches of each active sweep
+    double round_ms = 0.0;
+    int32_t round_launches = 0;
 
     char *stage() { return static_cast<char *>(ctx->pinned); }
     MatDesc *ddesc() { return reinterpret_cast<MatDesc *>(hdr + h.o_desc); }
@@ -415,7 +418,7 @@ struct Engine {
         notconv.assign(count, 0);
         if (nb_max == 0) return RANKY_OK;
         hipGraphExec_t exec = nullptr;
-        if (use_graph && s != nullptr) {
+        if (use_graph && s != nullptr && !time_rounds) {
             size_t sig = (size_t)count * 1315423911u ^ (size_t)nb_max;
             for (int r = 0; r < nb_max; ++r) sig = sig * 31 + (size_t)rblk[r];
             for (int ph = 0; ph < kPhCount; ++ph) sig = sig * 31 + (size_t)nblk[ph];
@@ -441,6 +444,14 @@ struct Engine {
         for (int32_t sw = 0; sw <= sweeps_cap; ++sw) {
             if (exec) {
                 HIP_TRY(hipGraphLaunch(exec, s));
+            } else if (time_rounds) {
+                launch_jacobi_check(ddesc(), dwp(kPhJcheck), nblk[kPhJcheck], count, s);
+                launch_jacobi_state(ddesc(), count, 0, sweeps_cap, s);
+                HIP_TRY(hipEventRecord(ctx->ev[9], s));
+                for (int r = 0; r < nb_max; ++r) launch_jacobi_round(drtab(r), drwp(r), rblk[r], count, r, s);
+                HIP_TRY(hipEventRecord(ctx->ev[10], s));
+                launch_jacobi_state(ddesc(), count, 1, sweeps_cap, s);
+                HIP_TRY(hipGetLastError());
             } else {
                 enqueue_sweep();
                 HIP_TRY(hipGetLastError());
@@ -449,6 +460,12 @@ struct Engine {
             if (st) return st;
             bool still = false;
             for (int i = 0; i < count; ++i) still |= iv[8 * i + 7] != 0;
+            if (time_rounds && still) {
+                float t = 0.f;
+                HIP_TRY(hipEventElapsedTime(&t, ctx->ev[9], ctx->ev[10]));
+                round_ms += t;
+                for (int r = 0; r < nb_max; ++r) round_launches += rblk[r] > 0 ? 1 : 0;
+            }
             if (!still) break;
         }
         // convergence test of the final matrices, for the report
@@ -533,6 +550,7 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
         x.V = j.V;
     }
     const bool timing = o.timing != 0 && count == 1;
+    e.time_rounds = timing;
     if (timing) hipEventRecord(ctx->ev[0], s);
     st = e.scan();
     if (st) return st;
@@ -638,6 +656,8 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
                 }
                 hipEventElapsedTime(&t, ctx->ev[0], ctx->ev[7]);
                 in.ms[7] = t;
+                in.round_ms = (float)e.round_ms;
+                in.round_launches = e.round_launches;
             }
         }
     }

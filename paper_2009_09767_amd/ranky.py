@@ -69,7 +69,8 @@ class ServeStats(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
                 ("status", "rank", "n_nonempty", "empty_rows", "sweeps", "n_blocks", "lonely_max", "lonely_blocks")]
-    _fields_ += [("tau", ctypes.c_double), ("sigma_max", ctypes.c_double), ("ms", ctypes.c_float * 8)]
+    _fields_ += [("tau", ctypes.c_double), ("sigma_max", ctypes.c_double), ("ms", ctypes.c_float * 8),
+                 ("round_ms", ctypes.c_float), ("round_launches", ctypes.c_int32)]
 
     def as_dict(self):
         d = {n: getattr(self, n) for n, _ in self._fields_ if n != "ms"}
