@@ -31,6 +31,9 @@ struct MatDesc {
     int32_t *csrk, *csrend, *csrcol, *jflag, *perm;
     int32_t *cnt;             // optional [D x M] occupancy output (step call only)
     int32_t *jstate;          // Jacobi state: [0] sweeps done, [1] active this sweep, [2] not converged
+    int32_t *gsegp;           // [n + 1] first Gram segment of compacted row i (set by the scan)
+    int32_t *gslot;           // [n + 1] first partial row of compacted row i (rows with one segment take none)
+    double *gpart;            // [slots][npad] partial Gram rows of the cut rows
     double *sdbl, *G, *G2, *W, *J, *S, *lam;
     // outputs (caller-owned)
     double *sigma, *U;

@@ -18,8 +18,16 @@ enum : int32_t {
     kScNonempty = 1,   // M' (rows with a nonzero)
     kScRank = 2,       // rank after the threshold
     kScNotConv = 3,    // 1 if some off-diagonal entry still fails the Jacobi test
+    kScGramSegs = 4,   // Gram workgroups for the nonempty rows (one per row segment)
+    kScGramSlots = 5,  // partial rows of the rows cut into more than one segment
     kScCount = 16
 };
+// Nonzeros of one row segment of the Gram: a longer row is cut into segments handled by
+// separate workgroups, whose partial rows are added in segment order.
+constexpr int32_t kGramSeg = 1 << 16;
+// Ints per matrix in the per-matrix read-back (status, M', rank, sweeps, not-converged,
+// lonely max, lonely blocks, active, Gram segments, Gram partial rows).
+constexpr int kColI = 10;
 enum : int32_t { kSdTau = 0, kSdSigmaMax = 1, kSdFloor = 2, kSdScale = 3, kSdCount = 8 };
 
 // Column range of chunk c: block b = c / cpb owns columns [floor(bN/D), floor((b+1)N/D)),

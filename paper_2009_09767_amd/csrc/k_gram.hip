@@ -17,6 +17,13 @@
 // The diagonal a_pj^2 terms are summed per lane and reduced by a fixed shuffle tree.
 // G is written in compacted coordinates (empty rows removed), symmetric, padded
 // with zeros up to npad; every entry is written exactly once.
+//
+// A row with more than kGramSeg nonzeros is cut into segments of kGramSeg consecutive
+// nonzeros (in column order), one workgroup each, so a dense row does not serialise
+// the whole launch.  Each segment writes its partial row (FP64) to a slot, and
+// k_gram_reduce adds the slots in segment order: the sum order is a function of the
+// row alone (not of the block count D or of timing).  Rows of one segment write G
+// directly, as before.
 #include "batch.hpp"
 #include "common.hpp"
 #include "launch.hpp"
@@ -30,7 +37,8 @@ __device__ __forceinline__ Acc wave_sum(Acc v) {
 }
 
 template <typename TV, typename Acc>
-__device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals, int32_t i, double *lds_raw) {
+__device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals, int32_t i, int32_t seg, int32_t nseg,
+                         double *lds_raw) {
     const int32_t M = dsc.M, n = dsc.n, npad = dsc.npad;
     const int64_t ld = npad;
     const int32_t *__restrict__ rowidx = dsc.rowidx;
@@ -60,11 +68,13 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals, int32_
     __syncthreads();
 
     const int32_t p = r2m[i];
-    const int32_t e_begin = rowptr[p], e_end = rowptr[p + 1];
+    const int32_t r_begin = rowptr[p], r_end = rowptr[p + 1];
+    const int32_t e_begin = r_begin + seg * kGramSeg;
+    const int32_t e_end = (nseg == 1 || r_end - e_begin <= kGramSeg) ? r_end : e_begin + kGramSeg;
     const int32_t deg = e_end - e_begin;
-    const int32_t seg = (deg + nw - 1) / nw;
-    const int32_t wb = e_begin + wave * seg;
-    const int32_t we = (wb + seg < e_end) ? wb + seg : e_end;
+    const int32_t run = (deg + nw - 1) / nw;   // contiguous run of this segment per wave
+    const int32_t wb = e_begin + wave * run;
+    const int32_t we = (wb + run < e_end) ? wb + run : e_end;
     Acc *my = acc + (size_t)wave * M;
     int32_t *mytag = tag + (size_t)wave * M;
     Acc dg = Acc(0);
@@ -108,38 +118,96 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals, int32_
     if (lane == 0) dsum[wave] = dg;
     __syncthreads();
 
-    // row part G[i][j] and column part G[j][i] for j > i, summing the waves in order
-    for (int32_t j = i + 1 + threadIdx.x; j < npad; j += blockDim.x) {
-        double v = 0.0;
-        if (j < n) {
-            const int32_t q = r2m[j];
-            for (int w = 0; w < nw; ++w) v += static_cast<double>(acc[(size_t)w * M + q]);
+    if (nseg == 1) {
+        // row part G[i][j] and column part G[j][i] for j > i, summing the waves in order
+        for (int32_t j = i + 1 + threadIdx.x; j < npad; j += blockDim.x) {
+            double v = 0.0;
+            if (j < n) {
+                const int32_t q = r2m[j];
+                for (int w = 0; w < nw; ++w) v += static_cast<double>(acc[(size_t)w * M + q]);
+            }
+            G[(int64_t)i * ld + j] = v;
+            G[(int64_t)j * ld + i] = v;
         }
-        G[(int64_t)i * ld + j] = v;
-        G[(int64_t)j * ld + i] = v;
+        if (threadIdx.x == 0) {
+            double d = 0.0;
+            for (int w = 0; w < nw; ++w) d += static_cast<double>(dsum[w]);
+            G[(int64_t)i * ld + i] = d;
+        }
+        return;
+    }
+    // partial row of this segment: entry j >= i (the diagonal at j = i)
+    double *__restrict__ part = dsc.gpart + (int64_t)(dsc.gslot[i] + seg) * ld;
+    for (int32_t j = i + 1 + threadIdx.x; j < n; j += blockDim.x) {
+        const int32_t q = r2m[j];
+        double v = 0.0;
+        for (int w = 0; w < nw; ++w) v += static_cast<double>(acc[(size_t)w * M + q]);
+        part[j] = v;
     }
     if (threadIdx.x == 0) {
         double d = 0.0;
         for (int w = 0; w < nw; ++w) d += static_cast<double>(dsum[w]);
-        G[(int64_t)i * ld + i] = d;
+        part[i] = d;
     }
 }
 
 
+// Workgroup b of a matrix: segment b of the nonempty rows' segments (gsegp maps it to
+// compacted row i and segment seg), then one workgroup per padding row n..npad-1.
 __global__ __launch_bounds__(512) void k_gram_rows(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
                                                    int count) {
     extern __shared__ double lds_raw[];
     const int mat = find_mat(wp, count, blockIdx.x);
     const MatDesc &d = descs[mat];
-    const int32_t i = blockIdx.x - wp[mat];
+    const int32_t b = blockIdx.x - wp[mat];
+    const int32_t total = d.gsegp[d.n];
+    int32_t i, seg = 0, nseg = 1;
+    if (b >= total) {
+        i = d.n + (b - total);
+    } else {
+        int32_t lo = 0, hi = d.n - 1;   // last i with gsegp[i] <= b
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (d.gsegp[mid] <= b) lo = mid;
+            else hi = mid - 1;
+        }
+        i = lo;
+        seg = b - d.gsegp[i];
+        nseg = d.gsegp[i + 1] - d.gsegp[i];
+    }
     if (d.dtype == 1) {
         const double *v = static_cast<const double *>(d.values);
-        if (d.prec == 0) gram_row<double, double>(d, v, i, lds_raw);
-        else gram_row<double, float>(d, v, i, lds_raw);
+        if (d.prec == 0) gram_row<double, double>(d, v, i, seg, nseg, lds_raw);
+        else gram_row<double, float>(d, v, i, seg, nseg, lds_raw);
     } else {
         const float *v = static_cast<const float *>(d.values);
-        if (d.prec == 0) gram_row<float, double>(d, v, i, lds_raw);
-        else gram_row<float, float>(d, v, i, lds_raw);
+        if (d.prec == 0) gram_row<float, double>(d, v, i, seg, nseg, lds_raw);
+        else gram_row<float, float>(d, v, i, seg, nseg, lds_raw);
+    }
+}
+
+// One workgroup per compacted row; rows cut into segments add their partial rows in
+// segment order and write G[i][j], G[j][i] (j > i) and G[i][i].
+__global__ __launch_bounds__(256) void k_gram_reduce(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
+                                                     int count) {
+    const int mat = find_mat(wp, count, blockIdx.x);
+    const MatDesc &d = descs[mat];
+    const int32_t i = blockIdx.x - wp[mat];
+    if (i >= d.n) return;
+    const int32_t nseg = d.gsegp[i + 1] - d.gsegp[i];
+    if (nseg <= 1) return;
+    const int64_t ld = d.npad;
+    const double *__restrict__ part = d.gpart + (int64_t)d.gslot[i] * ld;
+    double *__restrict__ G = d.G;
+    for (int32_t j = i + threadIdx.x; j < d.n; j += blockDim.x) {
+        double v = 0.0;
+        for (int32_t s = 0; s < nseg; ++s) v += part[(int64_t)s * ld + j];
+        G[(int64_t)i * ld + j] = v;
+        if (j != i) G[(int64_t)j * ld + i] = v;
+    }
+    for (int32_t j = d.n + threadIdx.x; j < ld; j += blockDim.x) {
+        G[(int64_t)i * ld + j] = 0.0;
+        G[(int64_t)j * ld + i] = 0.0;
     }
 }
 
@@ -157,12 +225,20 @@ size_t gram_lds_bytes(int32_t maxM, size_t lds_limit) {
     return (size_t)nw * maxM * (8 + sizeof(int32_t));
 }
 
-void launch_gram(const MatDesc *descs, const int32_t *wp, int64_t nblocks, int count, int32_t maxM, size_t lds_limit,
-                 hipStream_t s) {
+void launch_gram(const MatDesc *descs, const int32_t *wp, int64_t nblocks, const int32_t *wp_red, int64_t nblocks_red,
+                 int count, int32_t maxM, size_t lds_limit, hipStream_t s) {
     if (nblocks <= 0) return;
     const int nw = gram_waves(maxM, 8, lds_limit);
     hipLaunchKernelGGL(k_gram_rows, dim3((unsigned)nblocks), dim3((unsigned)(64 * nw)), gram_lds_bytes(maxM, lds_limit),
                        s, descs, wp, count);
+    if (nblocks_red > 0)
+        hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)nblocks_red), dim3(256), 0, s, descs, wp_red, count);
+}
+
+int64_t gram_part_slots(int64_t nnz) {
+    // rows longer than kGramSeg number at most nnz / kGramSeg, and each takes at most
+    // deg / kGramSeg + 1 slots
+    return nnz > kGramSeg ? 2 * (nnz / kGramSeg) + 1 : 0;
 }
 
 hipError_t gram_set_attributes(size_t lds_limit) {

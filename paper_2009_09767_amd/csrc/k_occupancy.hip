@@ -119,40 +119,62 @@ __global__ __launch_bounds__(1024) void k_occ_scan(const MatDesc *__restrict__ d
     int32_t *__restrict__ r2m = d.r2m;
     int32_t *__restrict__ empty = d.empty;
     int32_t *__restrict__ scal = d.scal;
+    int32_t *__restrict__ gsegp = d.gsegp;
+    int32_t *__restrict__ gslot = d.gslot;
     __shared__ int64_t s_nnz[1024];
-    __shared__ int32_t s_ne[1024];
+    __shared__ int32_t s_ne[1024], s_seg[1024], s_slot[1024];
     const int32_t per = (M + 1023) / 1024;
     const int32_t m0 = threadIdx.x * per;
+    // a nonempty row of deg nonzeros takes ceil(deg / kGramSeg) Gram segments, and as many
+    // partial rows when that is more than one
+    auto segs = [](int32_t deg) { return (int32_t)(((int64_t)deg + kGramSeg - 1) / kGramSeg); };
     int64_t loc_nnz = 0;
-    int32_t loc_ne = 0;
+    int32_t loc_ne = 0, loc_seg = 0, loc_slot = 0;
     for (int32_t m = m0; m < m0 + per && m < M; ++m) {
         loc_nnz += rownnz[m];
         loc_ne += rownnz[m] > 0;
+        const int32_t sg = segs(rownnz[m]);
+        loc_seg += sg;
+        loc_slot += sg > 1 ? sg : 0;
     }
     s_nnz[threadIdx.x] = loc_nnz;
     s_ne[threadIdx.x] = loc_ne;
+    s_seg[threadIdx.x] = loc_seg;
+    s_slot[threadIdx.x] = loc_slot;
     __syncthreads();
     // Hillis-Steele inclusive scan (fixed order; integers)
     for (int32_t off = 1; off < 1024; off <<= 1) {
         int64_t a = 0;
-        int32_t b = 0;
+        int32_t b = 0, c = 0, e = 0;
         if ((int32_t)threadIdx.x >= off) {
             a = s_nnz[threadIdx.x - off];
             b = s_ne[threadIdx.x - off];
+            c = s_seg[threadIdx.x - off];
+            e = s_slot[threadIdx.x - off];
         }
         __syncthreads();
         s_nnz[threadIdx.x] += a;
         s_ne[threadIdx.x] += b;
+        s_seg[threadIdx.x] += c;
+        s_slot[threadIdx.x] += e;
         __syncthreads();
     }
     int64_t run = s_nnz[threadIdx.x] - loc_nnz;
     int32_t nr = s_ne[threadIdx.x] - loc_ne;
+    int32_t sr = s_seg[threadIdx.x] - loc_seg, pr = s_slot[threadIdx.x] - loc_slot;
     for (int32_t m = m0; m < m0 + per && m < M; ++m) {
         rowptr[m] = (int32_t)run;
         run += rownnz[m];
         if (rownnz[m] > 0) {
             m2r[m] = nr;
             r2m[nr] = m;
+            if (gsegp) {
+                gsegp[nr] = sr;
+                gslot[nr] = pr;
+            }
+            const int32_t sg = segs(rownnz[m]);
+            sr += sg;
+            pr += sg > 1 ? sg : 0;
             ++nr;
         } else {
             m2r[m] = -1;
@@ -162,6 +184,12 @@ __global__ __launch_bounds__(1024) void k_occ_scan(const MatDesc *__restrict__ d
     if (threadIdx.x == 1023) {
         rowptr[M] = (int32_t)s_nnz[1023];
         scal[kScNonempty] = s_ne[1023];
+        scal[kScGramSegs] = s_seg[1023];
+        scal[kScGramSlots] = s_slot[1023];
+        if (gsegp) {
+            gsegp[s_ne[1023]] = s_seg[1023];
+            gslot[s_ne[1023]] = s_slot[1023];
+        }
     }
 }
 
@@ -253,8 +281,8 @@ __global__ __launch_bounds__(256) void k_batch_prep(const MatDesc *__restrict__ 
 }
 
 // Gather every matrix's scalars into one compact array for a single read-back:
-// out_i32[8i..8i+7] = status, M', rank, sweeps, not-converged, lonely max, blocks with
-// lonely rows, 0;  out_f64[2i..2i+1] = tau, sigma_1.
+// out_i32[10i..10i+9] = status, M', rank, sweeps, not-converged, lonely max, blocks with
+// lonely rows, active, Gram segments, Gram partial rows;  out_f64[2i..2i+1] = tau, sigma_1.
 __global__ __launch_bounds__(256) void k_batch_collect(const MatDesc *__restrict__ descs, int count,
                                                        int32_t *__restrict__ out_i32, double *__restrict__ out_f64) {
     const int i = blockIdx.x;
@@ -277,14 +305,17 @@ __global__ __launch_bounds__(256) void k_batch_collect(const MatDesc *__restrict
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        out_i32[8 * i + 0] = d.scal[kScStatus];
-        out_i32[8 * i + 1] = d.scal[kScNonempty];
-        out_i32[8 * i + 2] = d.scal[kScRank];
-        out_i32[8 * i + 3] = d.jstate ? d.jstate[kJsSweeps] : 0;
-        out_i32[8 * i + 4] = d.jstate ? d.jstate[kJsNotConv] : 0;
-        out_i32[8 * i + 5] = mx[0];
-        out_i32[8 * i + 6] = nz[0];
-        out_i32[8 * i + 7] = d.jstate ? d.jstate[kJsActive] : 0;
+        int32_t *o = out_i32 + (size_t)kColI * i;
+        o[0] = d.scal[kScStatus];
+        o[1] = d.scal[kScNonempty];
+        o[2] = d.scal[kScRank];
+        o[3] = d.jstate ? d.jstate[kJsSweeps] : 0;
+        o[4] = d.jstate ? d.jstate[kJsNotConv] : 0;
+        o[5] = mx[0];
+        o[6] = nz[0];
+        o[7] = d.jstate ? d.jstate[kJsActive] : 0;
+        o[8] = d.scal[kScGramSegs];
+        o[9] = d.scal[kScGramSlots];
         out_f64[2 * i + 0] = d.sdbl[kSdTau];
         out_f64[2 * i + 1] = d.sdbl[kSdSigmaMax];
     }

@@ -64,6 +64,7 @@ struct Plan {
     int64_t N = 0, nnz = 0, nchunks = 0;
     size_t o_scal = 0, o_sdbl = 0, o_jstate = 0, o_hist = 0, o_rownnz = 0, o_rowptr = 0, o_m2r = 0, o_r2m = 0;
     size_t o_empty = 0, o_lonely = 0, o_single = 0, o_csrk = 0, o_csrend = 0, o_csrcol = 0;
+    size_t o_gsegp = 0, o_gslot = 0, o_gpart = 0;
     size_t o_G = 0, o_G2 = 0, o_W = 0, o_J = 0, o_S = 0, o_jflag = 0, o_lam = 0, o_perm = 0;
     size_t o_U0 = 0, o_Z = 0, o_part = 0, o_Y = 0, o_seg = 0, total = 0;
     bool solver = false, refine = false;
@@ -102,6 +103,9 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool sol
     p.o_csrk = take(sizeof(int32_t) * nz);
     p.o_csrend = take(sizeof(int32_t) * nz);
     p.o_csrcol = take(sizeof(int32_t) * nz);
+    p.o_gsegp = take(sizeof(int32_t) * (M + 1));
+    p.o_gslot = take(sizeof(int32_t) * (M + 1));
+    p.o_gpart = take(sizeof(double) * (size_t)gram_part_slots(nnz) * p.npad);
     p.o_G = take(sizeof(double) * (size_t)p.npad * p.npad);
     if (solver) {
         p.solver = true;
@@ -159,6 +163,9 @@ MatDesc carve(const Plan &p, char *base, Refine *rf) {
     d.csrk = i32(p.o_csrk);
     d.csrend = i32(p.o_csrend);
     d.csrcol = i32(p.o_csrcol);
+    d.gsegp = i32(p.o_gsegp);
+    d.gslot = i32(p.o_gslot);
+    d.gpart = f64(p.o_gpart);
     d.G = f64(p.o_G);
     if (p.solver) {
         d.G2 = f64(p.o_G2);
@@ -183,7 +190,7 @@ MatDesc carve(const Plan &p, char *base, Refine *rf) {
 // batch header: device descriptor table, workgroup maps, round tables, read-back
 // ---------------------------------------------------------------------------
 
-enum Phase { kPhChunks, kPhRows, kPhGram, kPhJinit, kPhJcheck, kPhJdiag, kPhGather, kPhBack, kPhCount };
+enum Phase { kPhChunks, kPhRows, kPhGram, kPhGramRed, kPhJinit, kPhJcheck, kPhJdiag, kPhGather, kPhBack, kPhCount };
 
 struct Header {
     size_t o_desc = 0, o_wp = 0, o_rwp = 0, o_rtab = 0, o_col_i = 0, o_col_f = 0, total = 0;
@@ -205,7 +212,7 @@ Header make_header(int32_t count, int32_t slots, int32_t nb_max) {
     h.o_wp = take(sizeof(int32_t) * (size_t)kPhCount * (slots + 1));
     h.o_rwp = take(sizeof(int32_t) * (size_t)nb_max * (slots + 1));
     h.o_rtab = take(round_args_bytes() * (size_t)nb_max * slots);
-    h.o_col_i = take(sizeof(int32_t) * 8 * slots);
+    h.o_col_i = take(sizeof(int32_t) * kColI * slots);
     h.o_col_f = take(sizeof(double) * 2 * slots);
     h.total = off;
     return h;
@@ -286,6 +293,7 @@ struct Engine {
     std::vector<MatDesc> d;          // host copies
     std::vector<int32_t> status;     // per matrix ranky_status so far
     std::vector<int32_t> sweeps, notconv;
+    std::vector<int32_t> gsegs;      // Gram workgroups of the nonempty rows, per matrix (from the scan)
     Header h;
     char *hdr = nullptr;             // device header base
     int64_t nblk[kPhCount] = {};
@@ -319,12 +327,12 @@ struct Engine {
         double *cf = reinterpret_cast<double *>(hdr + h.o_col_f);
         launch_batch_collect(ddesc(), count, ci, cf, s);
         HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(stage() + h.o_col_i, ci, sizeof(int32_t) * 8 * count, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(stage() + h.o_col_i, ci, sizeof(int32_t) * kColI * count, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(stage() + h.o_col_f, cf, sizeof(double) * 2 * count, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         const int32_t *pi = reinterpret_cast<const int32_t *>(stage() + h.o_col_i);
         const double *pf = reinterpret_cast<const double *>(stage() + h.o_col_f);
-        iv.assign(pi, pi + 8 * count);
+        iv.assign(pi, pi + kColI * count);
         fv.assign(pf, pf + 2 * count);
         return RANKY_OK;
     }
@@ -345,10 +353,11 @@ struct Engine {
         st = collect(iv, fv);
         if (st) return st;
         for (int i = 0; i < count; ++i) {
-            const int32_t bits = iv[8 * i];
+            const int32_t bits = iv[kColI * i];
             if (bits & kStCsc) status[i] = RANKY_E_CSC;
             else if (bits & kStNonfinite) status[i] = RANKY_E_NONFINITE;
-            d[i].n = status[i] == RANKY_OK ? iv[8 * i + 1] : 0;
+            d[i].n = status[i] == RANKY_OK ? iv[kColI * i + 1] : 0;
+            gsegs[i] = status[i] == RANKY_OK ? iv[kColI * i + 8] : 0;
             d[i].n_tau = d[i].n;
             d[i].npad = jacobi_npad(d[i].n > 0 ? d[i].n : 1);
             maxn = std::max(maxn, d[i].n);
@@ -365,7 +374,9 @@ struct Engine {
         nblk[kPhChunks] = fill_wp(hwp(kPhChunks), count, [&](int i) { return status[i] == RANKY_OK ? d[i].nchunks : 0; });
         nblk[kPhRows] = fill_wp(hwp(kPhRows), count,
                                 [&](int i) { return status[i] == RANKY_OK ? (int64_t)(d[i].M + 255) / 256 : 0; });
-        nblk[kPhGram] = fill_wp(hwp(kPhGram), count, [&](int i) { return live(i) ? (int64_t)d[i].npad : 0; });
+        nblk[kPhGram] = fill_wp(hwp(kPhGram), count,
+                                [&](int i) { return live(i) ? (int64_t)gsegs[i] + (d[i].npad - d[i].n) : 0; });
+        nblk[kPhGramRed] = fill_wp(hwp(kPhGramRed), count, [&](int i) { return live(i) ? (int64_t)d[i].n : 0; });
         nblk[kPhJinit] = fill_wp(hwp(kPhJinit), count, [&](int i) -> int64_t {
             if (!live(i)) return 0;
             const int64_t sl = ((int64_t)d[i].npad * d[i].npad + 8191) / 8192;
@@ -459,7 +470,7 @@ struct Engine {
             ranky_status st = collect(iv, fv);
             if (st) return st;
             bool still = false;
-            for (int i = 0; i < count; ++i) still |= iv[8 * i + 7] != 0;
+            for (int i = 0; i < count; ++i) still |= iv[kColI * i + 7] != 0;
             if (time_rounds && still) {
                 float t = 0.f;
                 HIP_TRY(hipEventElapsedTime(&t, ctx->ev[9], ctx->ev[10]));
@@ -473,8 +484,8 @@ struct Engine {
         ranky_status st = collect(iv, fv);
         if (st) return st;
         for (int i = 0; i < count; ++i) {
-            sweeps[i] = iv[8 * i + 3];
-            notconv[i] = iv[8 * i + 4];
+            sweeps[i] = iv[kColI * i + 3];
+            notconv[i] = iv[kColI * i + 4];
         }
         launch_jacobi_diag(ddesc(), dwp(kPhJdiag), nblk[kPhJdiag], count, s);
         HIP_TRY(hipGetLastError());
@@ -491,6 +502,7 @@ ranky_status make_engine(ranky_ctx *ctx, hipStream_t s, const Header &h, char *h
     e.h = h;
     e.hdr = hdr;
     e.status.assign(count, RANKY_OK);
+    e.gsegs.assign(count, 0);
     return RANKY_OK;
 }
 
@@ -567,7 +579,8 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
     if (st) return st;
     e.enqueue_transpose();
     if (timing) hipEventRecord(ctx->ev[2], s);
-    launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], count, maxM, ctx->lds_limit, s);
+    launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], e.dwp(kPhGramRed), e.nblk[kPhGramRed], count, maxM,
+                ctx->lds_limit, s);
     HIP_TRY(hipGetLastError());
     if (timing) hipEventRecord(ctx->ev[3], s);
     st = e.eigensolve(use_graph);
@@ -639,13 +652,13 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
             ranky_info &in = infos[i];
             std::memset(&in, 0, sizeof(in));
             in.status = si;
-            in.rank = iv[8 * i + 2];
+            in.rank = iv[kColI * i + 2];
             in.n_nonempty = e.d[i].n;
             in.empty_rows = jobs[i].M - e.d[i].n;
             in.sweeps = e.sweeps[i] + refine_sweeps;
             in.n_blocks = jobs[i].D;
-            in.lonely_max = iv[8 * i + 5];
-            in.lonely_blocks = iv[8 * i + 6];
+            in.lonely_max = iv[kColI * i + 5];
+            in.lonely_blocks = iv[kColI * i + 6];
             in.tau = fv[2 * i];
             in.sigma_max = fv[2 * i + 1];
             if (timing) {
@@ -919,12 +932,14 @@ ranky_status ranky_gram(const ranky_csc *A, int32_t M, int64_t N, int32_t prec, 
     MatDesc &x = e.d[0];
     x.prec = prec;
     if (x.n > 0) {
-        e.nblk[kPhGram] = fill_wp(e.hwp(kPhGram), 1, [&](int) { return (int64_t)x.npad; });
+        e.nblk[kPhGram] = fill_wp(e.hwp(kPhGram), 1, [&](int) { return (int64_t)e.gsegs[0] + (x.npad - x.n); });
+        e.nblk[kPhGramRed] = fill_wp(e.hwp(kPhGramRed), 1, [&](int) { return (int64_t)x.n; });
         st = e.upload_desc();
         if (!st) st = e.upload(e.h.o_wp, sizeof(int32_t) * (size_t)kPhCount * (e.h.slots + 1));
         if (st) return st;
         e.enqueue_transpose();
-        launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], 1, M, sc.c.lds_limit, s);
+        launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], e.dwp(kPhGramRed), e.nblk[kPhGramRed], 1, M,
+                    sc.c.lds_limit, s);
         launch_scatter_gram(x.G, x.npad, x.m2r, M, G, s);
     } else {
         launch_fill_f64(G, (int64_t)M * M, 0.0, s);

@@ -257,43 +257,53 @@ def cfg4_matrix(req: Request, s=1.1) -> CSC:
 
 
 def cfg5(seed: int | None = None, M=4096, N=1 << 24, D=256, nnz=200_000_000, s=1.2, zero_blocks=128,
-         zero_rows=1024, k=100) -> CSC:
+         zero_rows=1024, k=100, progress=None) -> CSC:
     """Large single matrix: Zipf(1.2) rows capped at N; zero_rows seeded rows emptied inside each of
-    zero_blocks seeded blocks.  The pre-zeroing target is scaled so about nnz entries remain."""
+    zero_blocks seeded blocks.  The pre-zeroing target is scaled so about nnz entries remain.
+    Rows are drawn in increasing row order, so one stable sort by column gives sorted CSC rows.
+    `progress(msg)` is called every 512 rows and at each later stage."""
     rng = rng_for(5, seed)
     frac_removed = (zero_blocks / D) * (zero_rows / M)
     target = int(round(nnz / (1.0 - frac_removed)))
     deg = zipf_degrees(M, N, target, s)
-    perm = rng.permutation(M)
+    perm = rng.permutation(M)                  # row perm[r] gets the r-th largest degree
+    deg_of_row = np.empty(M, dtype=np.int64)
+    deg_of_row[perm] = deg
     bs = block_starts(N, D)
     blocks = np.sort(rng.choice(D, size=zero_blocks, replace=False))
     zero_sets = [np.sort(rng.choice(M, size=zero_rows, replace=False)) for _ in blocks]
-    # row-major build, then one stable counting sort by column
     row_zero_blocks = [[] for _ in range(M)]
     for b, zr in zip(blocks, zero_sets):
         for m in zr:
             row_zero_blocks[int(m)].append(int(b))
-    cols_l, rows_l = [], []
-    for r in range(M):
-        m = int(perm[r])
-        c = rng.choice(N, size=int(deg[r]), replace=False)
+    total = int(deg_of_row.sum())
+    cols = np.empty(total, dtype=np.int32)
+    rows = np.empty(total, dtype=np.int32)
+    pos = 0
+    for m in range(M):
+        c = rng.choice(N, size=int(deg_of_row[m]), replace=False)
         if row_zero_blocks[m]:
-            keep = np.ones(c.size, dtype=bool)
             blk = np.searchsorted(bs, c, side="right") - 1
-            keep &= ~np.isin(blk, row_zero_blocks[m])
-            c = c[keep]
-        cols_l.append(c.astype(np.int32))
-        rows_l.append(np.full(c.size, m, dtype=np.int32))
-    cols = np.concatenate(cols_l)
-    del cols_l
-    rows = np.concatenate(rows_l)
-    del rows_l
-    order = np.lexsort((rows, cols))
+            c = c[~np.isin(blk, row_zero_blocks[m])]
+        cols[pos:pos + c.size] = c
+        rows[pos:pos + c.size] = m
+        pos += c.size
+        if progress is not None and m % 512 == 511:
+            progress(f"cfg5: {m + 1}/{M} rows drawn, {pos} entries")
+    cols = cols[:pos]
+    rows = rows[:pos]
+    # stable LSD radix sort by column in two 16-bit passes (numpy's stable sort is a radix
+    # sort for 16-bit keys); rows stay increasing within a column
+    o1 = np.argsort((cols & 0xFFFF).astype(np.uint16), kind="stable")
+    o2 = np.argsort((cols[o1] >> 16).astype(np.uint16), kind="stable")
+    order = o1[o2]
+    del o1, o2
+    if progress is not None:
+        progress("cfg5: sorted by column")
     rows = rows[order]
-    cols = cols[order]
-    del order
-    vals = draw_values(rng, rows.size, "uniform", np.float32)
     counts = np.bincount(cols, minlength=N)
+    del order, cols
+    vals = draw_values(rng, rows.size, "uniform", np.float32)
     colptr = np.zeros(N + 1, dtype=np.int64)
     np.cumsum(counts, out=colptr[1:])
     return CSC(M, N, colptr.astype(np.int32), rows, vals,

@@ -85,6 +85,46 @@ def test_gram_fp64(R, orc, name):
     assert np.array_equal(G, G2), "Gram is not bitwise deterministic"
 
 
+def long_rows_matrix(seed=11):
+    """48 x 2^19 with rows longer than one Gram segment (2^16 nonzeros): 300000 (5 segments),
+    140000 (3), exactly 65536 (1) and 65537 (2); the other rows sparse, row 40 empty."""
+    rng = np.random.default_rng(seed)
+    M, N = 48, 1 << 19
+    degs = {5: 300000, 20: 140000, 33: 65536, 34: 65537}
+    rows, cols = [], []
+    for m in range(M):
+        if m == 40:
+            continue
+        d = degs.get(m, int(rng.integers(50, 500)))
+        c = rng.choice(N, size=d, replace=False)
+        rows.append(np.full(d, m))
+        cols.append(c)
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    return gen.from_coo(M, N, rows, cols, rng.standard_normal(rows.size))
+
+
+def test_gram_long_rows_cut_into_segments(R, orc):
+    A = long_rows_matrix()
+    dA = R.to_device(A)
+    G = R.gram(dA).cpu().numpy()
+    ref = orc.gram(A.M, A.N, A.colptr, A.rowidx, A.values)
+    bound = 2.0 * max_row_nnz(A) * U64 * absgram(orc, A)
+    assert np.all(np.abs(G - ref) <= bound)
+    assert np.array_equal(G, G.T)
+    assert np.array_equal(G, R.gram(dA).cpu().numpy()), "Gram is not bitwise deterministic"
+    # the segment cut is a property of each row, not of the column blocks
+    outs = [R.svd(dA, 16, 0.0, n_blocks=D) for D in (8, 1, 64)]
+    for o in outs[1:]:
+        assert np.array_equal(o.sigma.cpu().numpy(), outs[0].sigma.cpu().numpy())
+        assert np.array_equal(o.U.cpu().numpy(), outs[0].U.cpu().numpy())
+    ref_svd = orc.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=16, method="gram", want_v=False)
+    r = ref_svd.rank
+    assert outs[0].info["rank"] == r
+    sig = outs[0].sigma.cpu().numpy()
+    assert np.max(np.abs(sig[:r] - ref_svd.sigma[:r]) / ref_svd.sigma[:r]) <= 1e-10
+
+
 def test_gram_fp32_accumulation(R, orc):
     A = CASES["cfg3_full_rank"]()
     G = R.gram(R.to_device(A), prec="fp32").cpu().numpy()
