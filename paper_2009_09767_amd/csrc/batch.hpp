@@ -34,6 +34,7 @@ struct MatDesc {
     int32_t *gsegp;           // [n + 1] first Gram segment of compacted row i (set by the scan)
     int32_t *gslot;           // [n + 1] first partial row of compacted row i (rows with one segment take none)
     double *gpart;            // [slots][npad] partial Gram rows of the cut rows
+    int32_t *dense;           // [kDenseRows] the densest rows (original index, by degree), -1 when unused
     double *sdbl, *G, *G2, *W, *J, *S, *lam;
     // outputs (caller-owned)
     double *sigma, *U;

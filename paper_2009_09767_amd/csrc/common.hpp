@@ -25,6 +25,10 @@ enum : int32_t {
 // Nonzeros of one row segment of the Gram: a longer row is cut into segments handled by
 // separate workgroups, whose partial rows are added in segment order.
 constexpr int32_t kGramSeg = 1 << 16;
+// Densest rows of the Gram (at most this many, each with at least max(4096, N / 64)
+// nonzeros): their products go to lane-private slots instead of the shared row, since
+// most lanes of a wave would otherwise meet on the same few rows.
+constexpr int kDenseRows = 32;
 // Ints per matrix in the per-matrix read-back (status, M', rank, sweeps, not-converged,
 // lonely max, lonely blocks, active, Gram segments, Gram partial rows).
 constexpr int kColI = 10;

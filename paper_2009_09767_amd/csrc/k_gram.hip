@@ -18,6 +18,10 @@
 // G is written in compacted coordinates (empty rows removed), symmetric, padded
 // with zeros up to npad; every entry is written exactly once.
 //
+// The densest rows (up to kDenseRows, chosen by the scan) meet in most columns, so most
+// lanes of a wave would elect on the same few addresses; their products go instead to
+// lane-private LDS slots, reduced over the lanes by a fixed shuffle tree at the end.
+//
 // A row with more than kGramSeg nonzeros is cut into segments of kGramSeg consecutive
 // nonzeros (in column order), one workgroup each, so a dense row does not serialise
 // the whole launch.  Each segment writes its partial row (FP64) to a slot, and
@@ -59,12 +63,20 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals, int32_
     }
     Acc *acc = reinterpret_cast<Acc *>(lds_raw);                  // nw x M
     int32_t *tag = reinterpret_cast<int32_t *>(acc + (size_t)nw * M);  // nw x M
+    // nw x kDenseRows x 64 lane-private slots, 16-byte aligned (M may be odd)
+    Acc *dslot = reinterpret_cast<Acc *>(reinterpret_cast<char *>(lds_raw) +
+                                         ((((size_t)nw * M * (sizeof(Acc) + sizeof(int32_t))) + 15) & ~(size_t)15));
+    int8_t *dmap = reinterpret_cast<int8_t *>(dslot + (size_t)nw * kDenseRows * 64);  // M: dense index or -1
     __shared__ Acc dsum[16];
     __syncthreads();
     for (int32_t t = threadIdx.x; t < nw * M; t += blockDim.x) {
         acc[t] = Acc(0);
         tag[t] = 64;
     }
+    for (int32_t t = threadIdx.x; t < nw * kDenseRows * 64; t += blockDim.x) dslot[t] = Acc(0);
+    for (int32_t t = threadIdx.x; t < M; t += blockDim.x) dmap[t] = -1;
+    __syncthreads();
+    if (threadIdx.x < kDenseRows && dsc.dense[threadIdx.x] >= 0) dmap[dsc.dense[threadIdx.x]] = (int8_t)threadIdx.x;
     __syncthreads();
 
     const int32_t p = r2m[i];
@@ -77,6 +89,7 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals, int32_
     const int32_t we = (wb + run < e_end) ? wb + run : e_end;
     Acc *my = acc + (size_t)wave * M;
     int32_t *mytag = tag + (size_t)wave * M;
+    Acc *myslot = dslot + (size_t)wave * kDenseRows * 64 + lane;
     Acc dg = Acc(0);
 
     for (int32_t base = wb; base < we; base += 64) {
@@ -95,11 +108,14 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals, int32_
             if (__ballot(act) == 0) break;
             int32_t q = 0;
             Acc v = Acc(0);
+            int di = -1;
             if (act) {
                 q = rowidx[kk + s];
                 v = a * static_cast<Acc>(vals[kk + s]);
+                di = dmap[q];
+                if (di >= 0) myslot[di * 64] += v;
             }
-            bool pend = act;
+            bool pend = act && di < 0;
             while (__ballot(pend) != 0) {
                 if (pend) atomicMin(&mytag[q], lane);
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -116,6 +132,13 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals, int32_
     }
     dg = wave_sum(dg);
     if (lane == 0) dsum[wave] = dg;
+    // the dense rows: lane-private sums reduced over the lanes into the wave's row
+    for (int t = 0; t < kDenseRows; ++t) {
+        const int32_t q = dsc.dense[t];
+        if (q < 0) break;
+        const Acc v = wave_sum(myslot[t * 64]);
+        if (lane == 0) my[q] = v;
+    }
     __syncthreads();
 
     if (nseg == 1) {
@@ -211,10 +234,15 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const MatDesc *__restrict__
     }
 }
 
+// LDS per wave: one accumulator row, one tag row and the lane-private dense slots; plus
+// one dense-index byte per row for the workgroup.
+static size_t gram_wave_bytes(int32_t M, int32_t acc_bytes) {
+    return (size_t)M * (acc_bytes + sizeof(int32_t)) + (size_t)kDenseRows * 64 * acc_bytes;
+}
+
 int gram_waves(int32_t M, int32_t acc_bytes, size_t lds_limit) {
-    // LDS per wave: one accumulator row and one tag row.
-    const size_t per_wave = (size_t)M * (acc_bytes + sizeof(int32_t));
-    int w = (int)(lds_limit / per_wave);
+    const size_t fixed = (((size_t)M + 15) & ~(size_t)15) + 16;
+    int w = lds_limit > fixed ? (int)((lds_limit - fixed) / gram_wave_bytes(M, acc_bytes)) : 1;
     if (w > 8) w = 8;
     if (w < 1) w = 1;
     return w;
@@ -222,7 +250,7 @@ int gram_waves(int32_t M, int32_t acc_bytes, size_t lds_limit) {
 
 size_t gram_lds_bytes(int32_t maxM, size_t lds_limit) {
     const int nw = gram_waves(maxM, 8, lds_limit);
-    return (size_t)nw * maxM * (8 + sizeof(int32_t));
+    return (size_t)nw * gram_wave_bytes(maxM, 8) + (((size_t)maxM + 15) & ~(size_t)15) + 16;
 }
 
 void launch_gram(const MatDesc *descs, const int32_t *wp, int64_t nblocks, const int32_t *wp_red, int64_t nblocks_red,

@@ -191,6 +191,36 @@ __global__ __launch_bounds__(1024) void k_occ_scan(const MatDesc *__restrict__ d
             gslot[s_ne[1023]] = s_slot[1023];
         }
     }
+    // the densest rows, in order of degree (then row index): one block-wide arg-max per pick
+    int32_t *__restrict__ dense = d.dense;
+    if (!dense) return;
+    __syncthreads();
+    int64_t *s_key = s_nnz;   // reused
+    const int64_t tmin = d.N / 64 > 4096 ? d.N / 64 : 4096;
+    int64_t last = INT64_MAX;
+    for (int t = 0; t < kDenseRows; ++t) {
+        int64_t best = -1;
+        for (int32_t m = m0; m < m0 + per && m < M; ++m) {
+            if (rownnz[m] < tmin) continue;
+            const int64_t key = ((int64_t)rownnz[m] << 32) | (int64_t)(uint32_t)(M - 1 - m);
+            if (key < last && key > best) best = key;
+        }
+        s_key[threadIdx.x] = best;
+        __syncthreads();
+        for (int off = 512; off > 0; off >>= 1) {
+            if ((int)threadIdx.x < off && s_key[threadIdx.x + off] > s_key[threadIdx.x])
+                s_key[threadIdx.x] = s_key[threadIdx.x + off];
+            __syncthreads();
+        }
+        best = s_key[0];
+        __syncthreads();
+        if (threadIdx.x == 0) dense[t] = best < 0 ? -1 : M - 1 - (int32_t)(best & 0xffffffff);
+        last = best;
+        if (best < 0) {
+            for (int u = t + 1 + (int)threadIdx.x; u < kDenseRows; u += blockDim.x) dense[u] = -1;
+            break;
+        }
+    }
 }
 
 // One thread per row: turn the chunk histograms into the start offset of every

@@ -64,7 +64,7 @@ struct Plan {
     int64_t N = 0, nnz = 0, nchunks = 0;
     size_t o_scal = 0, o_sdbl = 0, o_jstate = 0, o_hist = 0, o_rownnz = 0, o_rowptr = 0, o_m2r = 0, o_r2m = 0;
     size_t o_empty = 0, o_lonely = 0, o_single = 0, o_csrk = 0, o_csrend = 0, o_csrcol = 0;
-    size_t o_gsegp = 0, o_gslot = 0, o_gpart = 0;
+    size_t o_gsegp = 0, o_gslot = 0, o_gpart = 0, o_dense = 0;
     size_t o_G = 0, o_G2 = 0, o_W = 0, o_J = 0, o_S = 0, o_jflag = 0, o_lam = 0, o_perm = 0;
     size_t o_U0 = 0, o_Z = 0, o_part = 0, o_Y = 0, o_seg = 0, total = 0;
     bool solver = false, refine = false;
@@ -106,6 +106,7 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool sol
     p.o_gsegp = take(sizeof(int32_t) * (M + 1));
     p.o_gslot = take(sizeof(int32_t) * (M + 1));
     p.o_gpart = take(sizeof(double) * (size_t)gram_part_slots(nnz) * p.npad);
+    p.o_dense = take(sizeof(int32_t) * kDenseRows);
     p.o_G = take(sizeof(double) * (size_t)p.npad * p.npad);
     if (solver) {
         p.solver = true;
@@ -166,6 +167,7 @@ MatDesc carve(const Plan &p, char *base, Refine *rf) {
     d.gsegp = i32(p.o_gsegp);
     d.gslot = i32(p.o_gslot);
     d.gpart = f64(p.o_gpart);
+    d.dense = i32(p.o_dense);
     d.G = f64(p.o_G);
     if (p.solver) {
         d.G2 = f64(p.o_G2);
