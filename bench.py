@@ -103,6 +103,8 @@ def time_path(ranky, torch, np, dA, A, k, D, prec, steps, warmup):
     stream = torch.cuda.Stream()
     kw["graph"] = True
     with torch.cuda.stream(stream):
+        # launch shapes picked by measurement on this matrix, before (and outside) the timed region
+        tune = ranky.autotune(dA, k, ctx=ctx, out=out, workspace=ws, stream=stream, **kw)
         for _ in range(warmup):
             ranky.svd(dA, k, 0.0, ctx=ctx, out=out, workspace=ws, stream=stream, **kw)
         torch.cuda.synchronize()
@@ -121,6 +123,7 @@ def time_path(ranky, torch, np, dA, A, k, D, prec, steps, warmup):
     phases /= steps
     names = ["occupancy", "transpose", "gram", "eigensolve", "select", "refine", "backproject", "total"]
     info = dict(r.info)
+    info["autotune"] = tune
     info["round_us_avg"] = 1e3 * round_ms / max(round_launches, 1)
     info["round_launches_per_call"] = round_launches / steps
     return ms_step, dict(zip(names, phases.tolist())), info, out.sigma.cpu().numpy(), vdt
@@ -260,6 +263,7 @@ def main():
                                f"gram={args.prec}", "M": A.M, "N": A.N, "nnz": A.nnz, "n_blocks": D, "k": k},
         "rank": info["rank"],
         "sweeps": info["sweeps"],
+        "autotune": info["autotune"],
         "phase_ms": phases,
         "roofline": {"kernel": "k_jround (Jacobi round: subproblem sweep + FP64 MFMA tile update)",
                      "bound": "mfma", "achieved": jr_tfs, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",

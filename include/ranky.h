@@ -168,6 +168,41 @@ ranky_status ranky_svd(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N,
                        void *V, ranky_info *info, ranky_stream_t stream);
 
 /* ------------------------------------------------------------------------- */
+/* Autotuner                                                                  */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t bp_per_cu;              /* chosen back-projection workgroups per CU (0: not timed,
+                                       the refinement path computes V itself) */
+    int32_t jacobi_schedule;        /* chosen update-tile schedule: 0 linear, 1 grouped per XCD */
+    int32_t bp_candidates[4];       /* workgroups per CU tried ... */
+    float bp_ms[4];                 /* ... and the best back-projection time of each (ms) */
+    int32_t schedule_candidates[2]; /* schedules tried ... */
+    float eig_ms[2];                /* ... and the best eigensolve time of each (ms) */
+} ranky_tune_report;
+
+/* Picks the launch shapes of this problem shape by measurement and stores them in the
+ * context: later ranky_svd / ranky_batch calls on the same context with the same
+ * (M, N, nnz, k, value dtype, opts->v_dtype, opts->gram_prec) use them.  Candidates:
+ * back-projection workgroups per CU {8, 16, 32, 64} and the Jacobi update-tile schedule
+ * {linear, grouped per XCD: the tiles that share a rotation J run on one XCD's L2}.
+ * Neither changes any result (each V column and each tile is computed the same way
+ * whatever the launch shape), only the time.  Runs the whole path on A about a dozen
+ * times with phase timing (HIP events on `stream`), so it belongs before a timed region,
+ * not inside one.  Arguments and errors as ranky_svd (the outputs hold the last run's
+ * result); report (host) may be NULL.  Blocking; the context must not be in use by
+ * another thread. */
+ranky_status ranky_autotune(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N, int32_t k,
+                            const ranky_opts *opts, void *workspace, size_t ws_bytes, double *sigma, double *U, void *V,
+                            ranky_tune_report *report, ranky_stream_t stream);
+
+/* Stores launch shapes for a problem shape without measuring (a configuration kept
+ * from an earlier ranky_autotune, or a fixed choice).  Same key as ranky_autotune.
+ * E_INVALID for bp_per_cu outside [1, 1024] or a schedule other than 0 / 1. */
+ranky_status ranky_tune_set(ranky_ctx *ctx, int32_t M, int64_t N, int64_t nnz, int32_t k, ranky_dtype dtype,
+                            const ranky_opts *opts, int32_t bp_per_cu, int32_t jacobi_schedule);
+
+/* ------------------------------------------------------------------------- */
 /* Batches of independent matrices                                            */
 /* ------------------------------------------------------------------------- */
 

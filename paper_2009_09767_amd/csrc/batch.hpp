@@ -35,6 +35,9 @@ struct MatDesc {
     int32_t *gslot;           // [n + 1] first partial row of compacted row i (rows with one segment take none)
     double *gpart;            // [slots][npad] partial Gram rows of the cut rows
     int32_t *dense;           // [kDenseRows] the densest rows (original index, by degree), -1 when unused
+    // launch-shape knobs (results do not depend on them; set from the context's tuning cache)
+    int32_t bp_per_cu;        // back-projection workgroups per compute unit
+    int32_t jsched;           // Jacobi update-tile schedule: 0 linear, 1 grouped per XCD
     double *sdbl, *G, *G2, *W, *J, *S, *lam;
     // outputs (caller-owned)
     double *sigma, *U;

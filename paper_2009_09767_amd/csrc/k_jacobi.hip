@@ -102,6 +102,7 @@ struct RoundArgs {
     int32_t inner_sweeps;
     int32_t ntiles_g;      // npairs (npairs + 1) / 2
     int32_t nrowtiles;     // npad / 32
+    int32_t sched;         // update-tile schedule: 0 linear, 1 grouped per XCD (see k_jround)
 };
 
 __device__ __forceinline__ void wave_fence() {
@@ -471,7 +472,10 @@ __device__ __forceinline__ void update_tile(const RoundArgs &a, int u, double *b
         return;
     }
     u -= a.ntiles_g;
-    const int rt = u / npairs, ib = u % npairs;
+    if (u >= a.nrowtiles * npairs) return;   // spare wave of the last workgroup
+    // W tiles: row-tile-major (linear schedule) or pair-major (grouped schedule: the tiles
+    // that share J_ib are consecutive, so one XCD's L2 serves them)
+    const int rt = a.sched ? u % a.nrowtiles : u / npairs, ib = a.sched ? u / a.nrowtiles : u % npairs;
     if (rt >= a.nrowtiles || !a.fprev[ib]) return;
     int Pb, Qb;
     tournament_pair(a.nb, a.round_prev, ib, Pb, Qb);
@@ -513,6 +517,13 @@ __global__ __launch_bounds__(256) void k_jround(const RoundArgs *__restrict__ ta
         b -= npairs;
     }
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (a.sched) {
+        // consecutive workgroups go to consecutive XCDs; give the workgroups of one XCD a
+        // contiguous range of tiles (a bijection on the first 8 floor(U / 8) of them)
+        const int tiles = a.ntiles_g + a.nrowtiles * npairs;
+        const int U = (tiles + kTileWaves - 1) / kTileWaves, Q = U / 8;
+        if (b < 8 * Q) b = (b % 8) * Q + b / 8;
+    }
     update_tile(a, b * kTileWaves + wave, smem + wave * kP * kPS);
 }
 
@@ -703,6 +714,7 @@ void fill_round_args(void *dst, const MatDesc &d, int32_t r, int32_t inner_sweep
     a.inner_sweeps = npairs == 1 ? 40 : inner_sweeps;
     a.ntiles_g = npairs * (npairs + 1) / 2;
     a.nrowtiles = d.npad / kP;
+    a.sched = d.jsched;
     *static_cast<RoundArgs *>(dst) = a;
 }
 

@@ -237,9 +237,9 @@ void launch_gather_u(const MatDesc *descs, const int32_t *wp, int64_t nblocks, i
     hipLaunchKernelGGL(k_gather_u, dim3((unsigned)nblocks), dim3(256), 0, s, descs, wp, count);
 }
 
-int64_t backproject_blocks(int64_t N, int32_t cu_count) {
+int64_t backproject_blocks(int64_t N, int32_t cu_count, int32_t per_cu) {
     int64_t blocks = (N + 3) / 4;
-    const int64_t cap = (int64_t)cu_count * 32;
+    const int64_t cap = (int64_t)cu_count * (per_cu > 0 ? per_cu : 32);
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
     return blocks;

@@ -58,7 +58,7 @@ void launch_jacobi_diag(const MatDesc *descs, const int32_t *wp, int64_t nblocks
 // select / gather / back-projection (k_select.hip)
 void launch_select(const MatDesc *descs, int count, int32_t max_n, hipStream_t s);
 void launch_gather_u(const MatDesc *descs, const int32_t *wp, int64_t nblocks, int count, hipStream_t s);
-int64_t backproject_blocks(int64_t N, int32_t cu_count);
+int64_t backproject_blocks(int64_t N, int32_t cu_count, int32_t per_cu = 32);
 void launch_backproject_batch(const MatDesc *descs, const int32_t *wp, int64_t nblocks, int count, hipStream_t s);
 void launch_backproject(const CscView &A, int64_t N, int32_t k, const double *U, const double *sigma,
                         const int32_t *rank, void *V, int32_t v_dtype, int32_t cu_count, hipStream_t s);

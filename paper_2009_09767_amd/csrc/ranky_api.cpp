@@ -10,6 +10,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "batch.hpp"
@@ -17,7 +19,16 @@
 #include "launch.hpp"
 #include "launch_util.hpp"
 
+// Launch-shape choices of the autotuner for one problem shape (results do not depend on them).
+struct TuneCfg {
+    int32_t bp_per_cu = 32;   // back-projection workgroups per CU
+    int32_t jsched = 0;       // Jacobi update-tile schedule
+};
+// M, N, nnz, k, value dtype, V dtype, Gram precision
+using TuneKey = std::tuple<int32_t, int64_t, int64_t, int32_t, int32_t, int32_t, int32_t>;
+
 struct ranky_ctx {
+    std::map<TuneKey, TuneCfg> tuned;     // filled by ranky_autotune
     int device = 0;
     int cu_count = 0;
     size_t lds_limit = 0;      // dynamic LDS the Gram kernel may use per workgroup
@@ -168,6 +179,8 @@ MatDesc carve(const Plan &p, char *base, Refine *rf) {
     d.gslot = i32(p.o_gslot);
     d.gpart = f64(p.o_gpart);
     d.dense = i32(p.o_dense);
+    d.bp_per_cu = 32;
+    d.jsched = 0;
     d.G = f64(p.o_G);
     if (p.solver) {
         d.G2 = f64(p.o_G2);
@@ -392,7 +405,7 @@ struct Engine {
         nblk[kPhJdiag] = fill_wp(hwp(kPhJdiag), count, [&](int i) { return live(i) ? (int64_t)(d[i].n + 255) / 256 : 0; });
         nblk[kPhGather] = fill_wp(hwp(kPhGather), count, [&](int i) { return status[i] == RANKY_OK ? (int64_t)d[i].k : 0; });
         nblk[kPhBack] = fill_wp(hwp(kPhBack), count, [&](int i) {
-            return status[i] == RANKY_OK ? backproject_blocks(d[i].N, ctx->cu_count) : (int64_t)0;
+            return status[i] == RANKY_OK ? backproject_blocks(d[i].N, ctx->cu_count, d[i].bp_per_cu) : (int64_t)0;
         });
         nb_max = 0;
         for (int i = 0; i < count; ++i)
@@ -558,6 +571,11 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
         x.prec = o.gram_prec;
         x.validate = o.validate;
         x.tol = tol;
+        const auto tc = ctx->tuned.find(TuneKey{j.M, j.N, j.A.nnz, j.k, j.A.dtype, o.v_dtype, o.gram_prec});
+        if (tc != ctx->tuned.end()) {
+            x.bp_per_cu = tc->second.bp_per_cu;
+            x.jsched = tc->second.jsched;
+        }
         x.u_gram = (o.gram_prec == RANKY_PREC_FP64) ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
         x.sigma = j.sigma;
         x.U = refine ? rf.U0 : j.U;
@@ -854,6 +872,103 @@ ranky_status ranky_svd(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N,
     if (hipSetDevice(ctx->device) != hipSuccess) return finish(fail(RANKY_E_DEVICE, "hipSetDevice"));
     return finish(run_path(ctx, {j}, tol, o, workspace, ws_bytes, inf, reinterpret_cast<hipStream_t>(stream),
                            o.reserved == 1));
+}
+
+ranky_status ranky_tune_set(ranky_ctx *ctx, int32_t M, int64_t N, int64_t nnz, int32_t k, ranky_dtype dtype,
+                            const ranky_opts *opts, int32_t bp_per_cu, int32_t jacobi_schedule) {
+    if (!ctx) return fail(RANKY_E_INVALID, "ctx is NULL");
+    const ranky_opts o = resolved(opts);
+    const ranky_status st = check_opts(o);
+    if (st) return st;
+    if (bp_per_cu < 1 || bp_per_cu > 1024) return fail(RANKY_E_INVALID, "bp_per_cu=%d", bp_per_cu);
+    if (jacobi_schedule != 0 && jacobi_schedule != 1) return fail(RANKY_E_INVALID, "jacobi_schedule=%d", jacobi_schedule);
+    TuneCfg c;
+    c.bp_per_cu = bp_per_cu;
+    c.jsched = jacobi_schedule;
+    ctx->tuned[TuneKey{M, N, nnz, k, dtype, o.v_dtype, o.gram_prec}] = c;
+    return RANKY_OK;
+}
+
+ranky_status ranky_autotune(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N, int32_t k,
+                            const ranky_opts *opts, void *workspace, size_t ws_bytes, double *sigma, double *U, void *V,
+                            ranky_tune_report *report, ranky_stream_t stream) {
+    if (!ctx) return fail(RANKY_E_INVALID, "ctx is NULL");
+    if (!sigma || !U || !V) return fail(RANKY_E_INVALID, "NULL output");
+    ranky_opts o = resolved(opts);
+    ranky_status st = check_opts(o);
+    if (st) return st;
+    Job j;
+    st = make_job(A, M, N, k, o.n_blocks, sigma, U, V, &j);
+    if (st) return st;
+    if (o.refine && k > kMaxRefineK) return fail(RANKY_E_INVALID, "refine needs k <= %d", kMaxRefineK);
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(RANKY_E_DEVICE, "hipSetDevice");
+    o.timing = 1;      // phase times from HIP events
+    o.reserved = 0;    // direct launches while timing
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const TuneKey key{M, N, j.A.nnz, k, j.A.dtype, o.v_dtype, o.gram_prec};
+    const int32_t bp_cands[4] = {8, 16, 32, 64};
+    const int32_t sched_cands[2] = {0, 1};
+    const int reps = 2;
+    TuneCfg best;
+    ranky_info in;
+    // phase ms of the best of `reps` runs with configuration c: [6] back-projection, [3] eigensolve
+    auto measure = [&](const TuneCfg &c, int phase, float &ms) -> ranky_status {
+        ctx->tuned[key] = c;
+        ms = 1e30f;
+        for (int r = 0; r < reps; ++r) {
+            std::memset(&in, 0, sizeof(in));
+            const ranky_status rs = run_path(ctx, {j}, 0.0, o, workspace, ws_bytes, &in, s, false);
+            if (rs) return rs;
+            ms = std::min(ms, in.ms[phase]);
+        }
+        return RANKY_OK;
+    };
+    float bp_ms[4] = {0, 0, 0, 0}, eig_ms[2] = {0, 0}, t = 0.f;
+    st = measure(best, 3, t);   // warm-up (kernel loading, caches)
+    const bool has_bp = !wants_refine(o, k);   // with refinement V comes from the Rayleigh-Ritz step
+    if (!st && has_bp) {
+        float bmin = 1e30f;
+        for (int c = 0; c < 4 && !st; ++c) {
+            TuneCfg cfg = best;
+            cfg.bp_per_cu = bp_cands[c];
+            st = measure(cfg, 6, bp_ms[c]);
+            if (!st && bp_ms[c] < bmin) {
+                bmin = bp_ms[c];
+                best.bp_per_cu = bp_cands[c];
+            }
+        }
+    }
+    if (!st) {
+        float emin = 1e30f;
+        for (int c = 0; c < 2 && !st; ++c) {
+            TuneCfg cfg = best;
+            cfg.jsched = sched_cands[c];
+            st = measure(cfg, 3, eig_ms[c]);
+            if (!st && eig_ms[c] < emin) {
+                emin = eig_ms[c];
+                best.jsched = sched_cands[c];
+            }
+        }
+    }
+    if (st) {
+        ctx->tuned.erase(key);
+        return st;
+    }
+    ctx->tuned[key] = best;
+    if (report) {
+        std::memset(report, 0, sizeof(*report));
+        report->bp_per_cu = has_bp ? best.bp_per_cu : 0;
+        report->jacobi_schedule = best.jsched;
+        for (int c = 0; c < 4; ++c) {
+            report->bp_candidates[c] = bp_cands[c];
+            report->bp_ms[c] = has_bp ? bp_ms[c] : 0.f;
+        }
+        for (int c = 0; c < 2; ++c) {
+            report->schedule_candidates[c] = sched_cands[c];
+            report->eig_ms[c] = eig_ms[c];
+        }
+    }
+    return RANKY_OK;
 }
 
 size_t ranky_batch_workspace_bytes(int32_t count, const ranky_batch_item *items, const ranky_opts *opts) {

@@ -78,6 +78,17 @@ class Info(ctypes.Structure):
         return d
 
 
+class TuneReport(ctypes.Structure):
+    _fields_ = [("bp_per_cu", ctypes.c_int32), ("jacobi_schedule", ctypes.c_int32),
+                ("bp_candidates", ctypes.c_int32 * 4), ("bp_ms", ctypes.c_float * 4),
+                ("schedule_candidates", ctypes.c_int32 * 2), ("eig_ms", ctypes.c_float * 2)]
+
+    def as_dict(self):
+        return {"bp_per_cu": self.bp_per_cu, "jacobi_schedule": self.jacobi_schedule,
+                "bp_ms": dict(zip(list(self.bp_candidates), [round(x, 4) for x in self.bp_ms])),
+                "eig_ms": dict(zip(list(self.schedule_candidates), [round(x, 4) for x in self.eig_ms]))}
+
+
 _lib = None
 
 
@@ -98,6 +109,8 @@ def lib():
         "ranky_version": ([], ctypes.c_char_p),
         "ranky_workspace_bytes": ([i32, i64, i64, i32, P(Opts)], sz),
         "ranky_svd": ([vp, P(Csc), i32, i64, i32, dbl, P(Opts), vp, sz, vp, vp, vp, P(Info), vp], i32),
+        "ranky_autotune": ([vp, P(Csc), i32, i64, i32, P(Opts), vp, sz, vp, vp, vp, P(TuneReport), vp], i32),
+        "ranky_tune_set": ([vp, i32, i64, i64, i32, i32, P(Opts), i32, i32], i32),
         "ranky_batch_workspace_bytes": ([i32, P(BatchItem), P(Opts)], sz),
         "ranky_batch": ([vp, i32, P(BatchItem), dbl, P(Opts), vp, sz, P(Info), vp], i32),
         "ranky_serve_create": ([P(ServeCfg), P(vp)], i32),
@@ -254,6 +267,35 @@ def svd(A: DeviceCSC, k: int, tol: float = 0.0, ctx: Context | None = None, out:
     _check(st)
     out.info = info.as_dict()
     return out
+
+
+def autotune(A: DeviceCSC, k: int, ctx: Context | None = None, out: SVDResult | None = None,
+             workspace: torch.Tensor | None = None, stream=None, **opt_kw) -> dict:
+    """ranky_autotune: measure the launch-shape candidates on A and keep the fastest in ctx
+    (later svd / batch calls on ctx with this shape use them).  Returns the report."""
+    ctx = ctx or context(A.colptr.device.index or 0)
+    opts = make_opts(**opt_kw)
+    vdt = torch.float64 if opts.v_dtype == F64 else torch.float32
+    dev = A.colptr.device
+    if out is None:
+        out = SVDResult(torch.empty(k, dtype=torch.float64, device=dev),
+                        torch.empty((A.M, k), dtype=torch.float64, device=dev),
+                        torch.empty((A.N, k), dtype=vdt, device=dev), {})
+    nbytes = workspace_bytes(A.M, A.N, A.nnz, k, opts)
+    ws = workspace if workspace is not None else ctx.workspace(nbytes)
+    rep = TuneReport()
+    csc = A.struct()
+    _check(lib().ranky_autotune(ctx.handle, ctypes.byref(csc), A.M, A.N, k, ctypes.byref(opts), _ptr(ws), ws.numel(),
+                                _ptr(out.sigma), _ptr(out.U), _ptr(out.V), ctypes.byref(rep), _stream(stream)))
+    return rep.as_dict()
+
+
+def tune_set(A: DeviceCSC, k: int, bp_per_cu: int, jacobi_schedule: int, ctx: Context | None = None, **opt_kw):
+    """ranky_tune_set: fix the launch shapes for A's shape in ctx without measuring."""
+    ctx = ctx or context(A.colptr.device.index or 0)
+    opts = make_opts(**opt_kw)
+    dt = F64 if A.values.dtype == torch.float64 else F32
+    _check(lib().ranky_tune_set(ctx.handle, A.M, A.N, A.nnz, k, dt, ctypes.byref(opts), bp_per_cu, jacobi_schedule))
 
 
 def occupancy(A: DeviceCSC, D: int, stream=None):

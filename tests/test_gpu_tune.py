@@ -1,0 +1,75 @@
+"""The autotuner (ranky_autotune / ranky_tune_set): every launch-shape candidate gives
+bitwise the results of the default shapes, the chosen shapes are kept per context and
+problem shape, and the batch path takes them per matrix."""
+import numpy as np
+import pytest
+
+from paper_2009_09767_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_09767_amd import ranky
+
+    ranky.lib()
+    return ranky
+
+
+def same(a, b):
+    return (np.array_equal(a.sigma.cpu().numpy(), b.sigma.cpu().numpy())
+            and np.array_equal(a.U.cpu().numpy(), b.U.cpu().numpy())
+            and np.array_equal(a.V.cpu().numpy(), b.V.cpu().numpy()))
+
+
+def test_every_candidate_gives_the_default_result(R):
+    A = gen.cfg2_small()
+    dA = R.to_device(A)
+    k = 32
+    base = R.svd(dA, k, 0.0, ctx=R.Context(0), n_blocks=8)
+    for bp in (8, 16, 32, 64):
+        for sched in (0, 1):
+            ctx = R.Context(0)
+            R.tune_set(dA, k, bp, sched, ctx=ctx, n_blocks=8)
+            out = R.svd(dA, k, 0.0, ctx=ctx, n_blocks=8)
+            assert same(out, base), (bp, sched)
+
+
+def test_autotune_report_and_reuse(R):
+    import torch
+
+    A = gen.cfg2_small()
+    dA = R.to_device(A)
+    k = 32
+    base = R.svd(dA, k, 0.0, ctx=R.Context(0), n_blocks=8)
+    ctx = R.Context(0)
+    stream = torch.cuda.Stream()
+    rep = R.autotune(dA, k, ctx=ctx, stream=stream, n_blocks=8)
+    torch.cuda.synchronize()
+    assert rep["bp_per_cu"] in (8, 16, 32, 64)
+    assert rep["jacobi_schedule"] in (0, 1)
+    assert all(v > 0 for v in rep["bp_ms"].values()) and all(v > 0 for v in rep["eig_ms"].values())
+    assert min(rep["bp_ms"], key=rep["bp_ms"].get) == rep["bp_per_cu"]
+    out = R.svd(dA, k, 0.0, ctx=ctx, n_blocks=8)
+    assert same(out, base)
+    # the mixed path has no back-projection launch to time (V comes from the refinement)
+    rep2 = R.autotune(dA, k, ctx=ctx, n_blocks=8, gram_prec="fp32", v_dtype=torch.float32)
+    assert rep2["bp_per_cu"] == 0 and rep2["jacobi_schedule"] in (0, 1)
+
+
+def test_batch_takes_the_tuned_shapes(R):
+    mats = [gen.random_sparse(m, 4000, 0.02, seed=s) for s, m in ((1, 64), (2, 96), (3, 130))]
+    dms = [R.to_device(A) for A in mats]
+    ks = [A.M for A in mats]
+    base = R.batch(dms, ks, ctx=R.Context(0))
+    ctx = R.Context(0)
+    for dA, k in zip(dms, ks):
+        R.tune_set(dA, k, 8, 1, ctx=ctx)
+    outs = R.batch(dms, ks, ctx=ctx)
+    for o, b in zip(outs, base):
+        assert same(o, b)
