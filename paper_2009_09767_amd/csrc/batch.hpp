@@ -26,6 +26,7 @@ struct MatDesc {
     int32_t pad0;
     double tol;               // rank threshold option
     double u_gram;            // unit roundoff of the Gram entries for the threshold
+    double jtol;              // Jacobi rotation test tolerance (0: max(1e-15, sqrt(n) eps))
     // workspace (library-carved from caller memory)
     int32_t *scal, *hist, *rownnz, *rowptr, *m2r, *r2m, *empty, *lonely, *single;
     int32_t *csrk, *csrend, *csrcol, *jflag, *perm;

@@ -546,7 +546,7 @@ __global__ __launch_bounds__(256) void k_jcheck(const MatDesc *__restrict__ desc
     const int64_t ld = d.npad;
     const double *__restrict__ G = current_g(d);
     const double floor_abs = d.sdbl[kSdFloor];
-    const double tol = fmax(1e-15, sqrt((double)n) * 2.220446049250313e-16);
+    const double tol = d.jtol > 0.0 ? d.jtol : fmax(1e-15, sqrt((double)n) * 2.220446049250313e-16);
     const double tol2 = tol * tol;
     const int T = (n + kT - 1) / kT;
     int ti = 0, rem = blockIdx.x - wp[mat];
@@ -710,7 +710,7 @@ void fill_round_args(void *dst, const MatDesc &d, int32_t r, int32_t inner_sweep
     a.fcur = d.jflag + (r & 1) * npairs;
     a.sdbl = d.sdbl;
     a.jstate = d.jstate;
-    a.tol = fmax(1e-15, sqrt((double)d.n) * 2.220446049250313e-16);
+    a.tol = d.jtol > 0.0 ? d.jtol : fmax(1e-15, sqrt((double)d.n) * 2.220446049250313e-16);
     a.inner_sweeps = npairs == 1 ? 40 : inner_sweeps;
     a.ntiles_g = npairs * (npairs + 1) / 2;
     a.nrowtiles = d.npad / kP;

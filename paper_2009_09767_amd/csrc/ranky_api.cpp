@@ -49,6 +49,7 @@ constexpr int32_t kMaxM = 8192;
 constexpr int32_t kDefaultSweeps = 40;
 constexpr int32_t kInnerSweeps = 1;
 constexpr int32_t kMaxRefineK = 1024;
+constexpr double kJacobiTolFp32Gram = 1e-8;
 
 ranky_status fail(ranky_status st, const char *fmt, ...) {
     va_list ap;
@@ -577,6 +578,9 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
             x.jsched = tc->second.jsched;
         }
         x.u_gram = (o.gram_prec == RANKY_PREC_FP64) ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
+        // an FP32 Gram is accurate to about 6e-8: Jacobi stops at 1e-8 (the FP64 step of the
+        // Rayleigh-Ritz refinement, or the mixed-precision bar, covers the rest)
+        x.jtol = (o.gram_prec == RANKY_PREC_FP64) ? 0.0 : kJacobiTolFp32Gram;
         x.sigma = j.sigma;
         x.U = refine ? rf.U0 : j.U;
         x.V = j.V;
@@ -641,6 +645,7 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
         y.n_tau = x.n;
         y.k = k;
         y.u_gram = std::ldexp(1.0, -53);
+        y.jtol = 0.0;   // H is exact to FP64 rounding: the full-accuracy stopping test
         y.U = j.U;
         eh.maxn = k;
         st = eh.plan_rest();
