@@ -2,131 +2,119 @@
 //
 // The mixed-precision path accumulates the Gram matrix in FP32, so its eigenvectors
 // U0 carry FP32-size errors.  Projecting the exact operator onto span(U0),
-//   H = U0^T (A A^T) U0 = (A^T U0)^T (A^T U0),
+//   H = U0^T (A A^T) U0 = Z^T Z,  Z = A^T U0  (N x k),
 // and diagonalising H = Q Theta Q^T gives Ritz pairs U = U0 Q, sigma = sqrt(theta)
-// whose values are accurate to second order in U0's error.  Everything here is FP64:
-//   Z = A^T U0            one pass over the CSC (N x k)
-//   Y = A Z = (A A^T) U0  row owners over the row-major copy, rows cut into segments
-//                         whose partial rows are summed in segment order
-//   H = U0^T Y            one thread per entry, fixed-order sum over the rows
-// No floating-point atomics; the result is bitwise reproducible.
+// whose values are accurate to second order in U0's error.  Everything here is FP64.
+//
+// Z is never stored: H = sum over columns j of z_j z_j^T with z_j = sum over column j's
+// nonzeros of a_mj U0[m, :].  One workgroup owns one 64 x 64 tile of H and one fixed
+// range of columns; per chunk of 16 columns it builds the two 64-wide slices of z_j it
+// needs in LDS (U0 is small and stays in L2) and adds their outer products on the FP64
+// matrix cores (each wave a 32 x 32 quarter of the tile).  The partial tiles of the
+// column ranges are then added in range order: no floating-point atomics, bitwise
+// reproducible.
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace ranky {
 
-constexpr int kSeg = 2048;  // nonzeros per row segment
+typedef double d4 __attribute__((ext_vector_type(4)));
 
-// Z[j][i] = sum over column j's nonzeros of a_mj U0[m][i] (wave per column).
+constexpr int kRrTile = 64;     // H tile
+constexpr int kRrChunk = 16;    // columns per LDS chunk
+constexpr int kRrWgs = 2048;    // target workgroups per launch (tiles x column ranges)
+
+// workgroup b -> tile t = b / R (ta <= tb, row-major over the upper triangle), range b % R
 template <typename TV>
-__global__ __launch_bounds__(256) void k_rr_z(const int32_t *__restrict__ colptr, const int32_t *__restrict__ rowidx,
-                                              const TV *__restrict__ vals, int64_t N, int32_t k,
-                                              const double *__restrict__ U0, double *__restrict__ Z) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int32_t i0 = 0; i0 < k; i0 += 128) {
-        const int32_t i = i0 + 2 * lane;
-        const bool ok0 = i < k, ok1 = i + 1 < k;
-        for (int64_t j = wave; j < N; j += nwaves) {
-            const int32_t e0 = colptr[j], e1 = colptr[j + 1];
-            double a0 = 0.0, a1 = 0.0;
-            for (int32_t e = e0; e < e1; ++e) {
-                const double a = static_cast<double>(vals[e]);
-                const double *u = U0 + (int64_t)rowidx[e] * k + i;
-                if (ok0) a0 = fma(a, u[0], a0);
-                if (ok1) a1 = fma(a, u[1], a1);
+__global__ __launch_bounds__(256) void k_rr_syrk(const int32_t *__restrict__ colptr, const int32_t *__restrict__ rowidx,
+                                                 const TV *__restrict__ vals, int64_t N, int32_t k, int32_t R,
+                                                 const double *__restrict__ U0, double *__restrict__ part) {
+    __shared__ double ZA[kRrChunk][kRrTile + 1], ZB[kRrChunk][kRrTile + 1];
+    const int tid = threadIdx.x, l = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int32_t T = (k + kRrTile - 1) / kRrTile;
+    const int32_t t = blockIdx.x / R, r = blockIdx.x % R;
+    int32_t ta = 0, rem = t;
+    while (rem >= T - ta) {
+        rem -= T - ta;
+        ++ta;
+    }
+    const int32_t tb = ta + rem;
+    const int64_t c_begin = (N * r) / R, c_end = (N * (r + 1)) / R;
+    // LDS build: thread -> column c of the chunk and four entries of each slice
+    const int bc = tid >> 4, bq = (tid & 15) * 4;
+    const int32_t ia = ta * kRrTile + bq, ib = tb * kRrTile + bq;
+    // this wave's quarter of the tile
+    const int wa = wave >> 1, wb = wave & 1;
+    d4 acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int64_t c0 = c_begin; c0 < c_end; c0 += kRrChunk) {
+        double za[4] = {0.0, 0.0, 0.0, 0.0}, zb[4] = {0.0, 0.0, 0.0, 0.0};
+        const int64_t j = c0 + bc;
+        if (j < c_end) {
+            for (int32_t e = colptr[j]; e < colptr[j + 1]; ++e) {
+                const double av = static_cast<double>(vals[e]);
+                const double *u = U0 + (int64_t)rowidx[e] * k;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (ia + q < k) za[q] = fma(av, u[ia + q], za[q]);
+                    if (ib + q < k) zb[q] = fma(av, u[ib + q], zb[q]);
+                }
             }
-            double *z = Z + j * (int64_t)k + i;
-            if (ok0) z[0] = a0;
-            if (ok1) z[1] = a1;
         }
-    }
-}
-
-// segment table: seg_ptr[m] = first segment of row m (ceil(rownnz / kSeg) segments per row)
-__global__ __launch_bounds__(1024) void k_rr_segments(const int32_t *__restrict__ rownnz, int32_t M,
-                                                      int32_t *__restrict__ seg_ptr) {
-    __shared__ int32_t part[1024];
-    const int32_t per = (M + 1023) / 1024;
-    const int32_t m0 = threadIdx.x * per;
-    int32_t loc = 0;
-    for (int32_t m = m0; m < m0 + per && m < M; ++m) loc += (rownnz[m] + kSeg - 1) / kSeg;
-    part[threadIdx.x] = loc;
-    __syncthreads();
-    for (int32_t off = 1; off < 1024; off <<= 1) {
-        int32_t v = (int32_t)threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            ZA[bc][bq + q] = za[q];
+            ZB[bc][bq + q] = zb[q];
+        }
         __syncthreads();
-        part[threadIdx.x] += v;
+        // acc += ZA^T ZB over the chunk: A[row][c] = ZA[c][row], B[c][col] = ZB[c][col]
+#pragma unroll
+        for (int kc = 0; kc < kRrChunk / 4; ++kc) {
+            const int c = kc * 4 + (l >> 4);
+            const double a0 = ZA[c][32 * wa + (l & 15)], a1 = ZA[c][32 * wa + 16 + (l & 15)];
+            const double b0 = ZB[c][32 * wb + (l & 15)], b1 = ZB[c][32 * wb + 16 + (l & 15)];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
         __syncthreads();
     }
-    int32_t run = part[threadIdx.x] - loc;
-    for (int32_t m = m0; m < m0 + per && m < M; ++m) {
-        seg_ptr[m] = run;
-        run += (rownnz[m] + kSeg - 1) / kSeg;
-    }
-    if (threadIdx.x == 1023) seg_ptr[M] = part[1023];
+    // result layout: element i of lane l at row l / 16 + 4 i, column l % 16 of a 16 x 16 block
+    double *out = part + (int64_t)blockIdx.x * kRrTile * kRrTile;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 32 * wa + 16 * x + (l >> 4) + 4 * i, col = 32 * wb + 16 * y + (l & 15);
+                out[row * kRrTile + col] = acc[x][y][i];
+            }
 }
 
-// One wave per (row, segment): partial[seg][i] = sum over the segment's nonzeros a_mj Z[j][i].
-template <typename TV>
-__global__ __launch_bounds__(256) void k_rr_rows(const TV *__restrict__ vals, const int32_t *__restrict__ rowptr,
-                                                 const int32_t *__restrict__ seg_ptr, int32_t M, int32_t k,
-                                                 const int32_t *__restrict__ csr_k,
-                                                 const int32_t *__restrict__ csr_col, const double *__restrict__ Z,
-                                                 double *__restrict__ part) {
-    const int lane = threadIdx.x & 63;
-    const int32_t seg = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int32_t nseg = seg_ptr[M];
-    if (seg >= nseg) return;
-    // row owning this segment: last m with seg_ptr[m] <= seg
-    int32_t lo = 0, hi = M - 1;
-    while (lo < hi) {
-        const int32_t mid = (lo + hi + 1) >> 1;
-        if (seg_ptr[mid] <= seg) lo = mid;
-        else hi = mid - 1;
-    }
-    const int32_t m = lo;
-    const int32_t e_begin = rowptr[m] + (seg - seg_ptr[m]) * kSeg;
-    const int32_t e_end = min(rowptr[m + 1], e_begin + kSeg);
-    for (int32_t i0 = 0; i0 < k; i0 += 128) {
-        const int32_t i = i0 + 2 * lane;
-        const bool ok0 = i < k, ok1 = i + 1 < k;
-        double a0 = 0.0, a1 = 0.0;
-        for (int32_t e = e_begin; e < e_end; ++e) {
-            const double a = static_cast<double>(vals[csr_k[e]]);
-            const double *z = Z + (int64_t)csr_col[e] * k + i;
-            if (ok0) a0 = fma(a, z[0], a0);
-            if (ok1) a1 = fma(a, z[1], a1);
-        }
-        double *o = part + (int64_t)seg * k + i;
-        if (ok0) o[0] = a0;
-        if (ok1) o[1] = a1;
-    }
-}
-
-// Y[m][i] = sum of row m's segment partials in segment order (zero for empty rows).
-__global__ __launch_bounds__(256) void k_rr_reduce(const double *__restrict__ part, const int32_t *__restrict__ seg_ptr,
-                                                   int32_t M, int32_t k, double *__restrict__ Y) {
-    const int64_t total = (int64_t)M * k;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t m = (int32_t)(e / k), i = (int32_t)(e % k);
-        double v = 0.0;
-        for (int32_t s = seg_ptr[m]; s < seg_ptr[m + 1]; ++s) v += part[(int64_t)s * k + i];
-        Y[e] = v;
-    }
-}
-
-// H[a][b] = sum_m U0[m][a] Y[m][b] into an npad x npad buffer (zero outside k x k).
-__global__ __launch_bounds__(256) void k_rr_h(const double *__restrict__ U0, const double *__restrict__ Y, int32_t M,
-                                              int32_t k, int32_t npad, double *__restrict__ H) {
+// H[a][b] = H[b][a] = sum over the column ranges (in order) of the partial tiles; the
+// entry (a, b), a <= b, of a diagonal tile is used for both halves.  Zero outside k x k.
+__global__ __launch_bounds__(256) void k_rr_syrk_reduce(const double *__restrict__ part, int32_t k, int32_t R,
+                                                        int32_t npad, double *__restrict__ H) {
+    const int32_t T = (k + kRrTile - 1) / kRrTile;
     const int64_t total = (int64_t)npad * npad;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int32_t a = (int32_t)(e / npad), b = (int32_t)(e % npad);
+        if (a > b) continue;
         double v = 0.0;
-        if (a < k && b < k)
-            for (int32_t m = 0; m < M; ++m) v = fma(U0[(int64_t)m * k + a], Y[(int64_t)m * k + b], v);
-        H[e] = v;
+        if (b < k) {
+            const int32_t ta = a / kRrTile, tb = b / kRrTile;
+            const int32_t t = ta * T - ta * (ta - 1) / 2 + (tb - ta);
+            const double *p = part + ((int64_t)t * R) * kRrTile * kRrTile + (a % kRrTile) * kRrTile + (b % kRrTile);
+            for (int32_t r = 0; r < R; ++r) v += p[(int64_t)r * kRrTile * kRrTile];
+        }
+        H[(int64_t)a * npad + b] = v;
+        H[(int64_t)b * npad + a] = v;
     }
 }
 
@@ -176,42 +164,35 @@ __global__ __launch_bounds__(256) void k_rr_apply(const double *__restrict__ U0,
 
 // ---------------------------------------------------------------------------
 
-void launch_rr_z(const CscView &A, int64_t N, int32_t k, const double *U0, double *Z, int32_t cu_count, hipStream_t s) {
-    int64_t blocks = (N + 3) / 4;
-    const int64_t cap = (int64_t)cu_count * 32;
-    if (blocks > cap) blocks = cap;
-    if (blocks < 1) blocks = 1;
-    if (A.dtype == 1)
-        hipLaunchKernelGGL(k_rr_z<double>, dim3((unsigned)blocks), dim3(256), 0, s, A.colptr, A.rowidx,
-                           static_cast<const double *>(A.values), N, k, U0, Z);
-    else
-        hipLaunchKernelGGL(k_rr_z<float>, dim3((unsigned)blocks), dim3(256), 0, s, A.colptr, A.rowidx,
-                           static_cast<const float *>(A.values), N, k, U0, Z);
+int32_t rr_ranges(int64_t N, int32_t k) {
+    const int32_t T = (k + kRrTile - 1) / kRrTile;
+    const int32_t tiles = T * (T + 1) / 2;
+    int64_t R = kRrWgs / tiles;
+    const int64_t chunks = (N + kRrChunk - 1) / kRrChunk;
+    if (R > chunks) R = chunks;
+    if (R < 1) R = 1;
+    return (int32_t)R;
 }
 
-int64_t rr_max_segments(int32_t M, int64_t nnz) { return nnz / kSeg + M + 1; }
+size_t rr_part_doubles(int64_t N, int32_t k) {
+    const int32_t T = (k + kRrTile - 1) / kRrTile;
+    return (size_t)(T * (T + 1) / 2) * rr_ranges(N, k) * kRrTile * kRrTile;
+}
 
-void launch_rr_rows(const CscView &A, const int32_t *rownnz, const int32_t *rowptr, int32_t M, int64_t nnz, int32_t k,
-                    const int32_t *csr_k, const int32_t *csr_col, const double *Z, int32_t *seg_ptr, double *part,
-                    double *Y, hipStream_t s) {
-    hipLaunchKernelGGL(k_rr_segments, dim3(1), dim3(1024), 0, s, rownnz, M, seg_ptr);
-    const int64_t maxseg = rr_max_segments(M, nnz);
-    const int64_t blocks = (maxseg + 3) / 4;
+void launch_rr_h(const CscView &A, int64_t N, int32_t k, const double *U0, double *part, int32_t npad, double *H,
+                 hipStream_t s) {
+    const int32_t T = (k + kRrTile - 1) / kRrTile;
+    const int32_t R = rr_ranges(N, k);
+    const unsigned blocks = (unsigned)(T * (T + 1) / 2 * R);
     if (A.dtype == 1)
-        hipLaunchKernelGGL(k_rr_rows<double>, dim3((unsigned)blocks), dim3(256), 0, s,
-                           static_cast<const double *>(A.values), rowptr, seg_ptr, M, k, csr_k, csr_col, Z, part);
+        hipLaunchKernelGGL(k_rr_syrk<double>, dim3(blocks), dim3(256), 0, s, A.colptr, A.rowidx,
+                           static_cast<const double *>(A.values), N, k, R, U0, part);
     else
-        hipLaunchKernelGGL(k_rr_rows<float>, dim3((unsigned)blocks), dim3(256), 0, s,
-                           static_cast<const float *>(A.values), rowptr, seg_ptr, M, k, csr_k, csr_col, Z, part);
-    int64_t rb = ((int64_t)M * k + 255) / 256;
+        hipLaunchKernelGGL(k_rr_syrk<float>, dim3(blocks), dim3(256), 0, s, A.colptr, A.rowidx,
+                           static_cast<const float *>(A.values), N, k, R, U0, part);
+    int64_t rb = ((int64_t)npad * npad + 255) / 256;
     if (rb > 4096) rb = 4096;
-    hipLaunchKernelGGL(k_rr_reduce, dim3((unsigned)rb), dim3(256), 0, s, part, seg_ptr, M, k, Y);
-}
-
-void launch_rr_h(const double *U0, const double *Y, int32_t M, int32_t k, int32_t npad, double *H, hipStream_t s) {
-    int64_t b = ((int64_t)npad * npad + 255) / 256;
-    if (b > 4096) b = 4096;
-    hipLaunchKernelGGL(k_rr_h, dim3((unsigned)b), dim3(256), 0, s, U0, Y, M, k, npad, H);
+    hipLaunchKernelGGL(k_rr_syrk_reduce, dim3((unsigned)rb), dim3(256), 0, s, part, k, R, npad, H);
 }
 
 void launch_rr_apply(const double *U0, const double *Q, int64_t ldq, const int32_t *perm, int32_t M, int32_t k,

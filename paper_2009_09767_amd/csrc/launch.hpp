@@ -65,12 +65,9 @@ void launch_backproject(const CscView &A, int64_t N, int32_t k, const double *U,
 hipError_t select_set_attributes();
 
 // Rayleigh-Ritz refinement with the exact operator (k_refine.hip)
-void launch_rr_z(const CscView &A, int64_t N, int32_t k, const double *U0, double *Z, int32_t cu_count, hipStream_t s);
-int64_t rr_max_segments(int32_t M, int64_t nnz);
-void launch_rr_rows(const CscView &A, const int32_t *rownnz, const int32_t *rowptr, int32_t M, int64_t nnz, int32_t k,
-                    const int32_t *csr_k, const int32_t *csr_col, const double *Z, int32_t *seg_ptr, double *part,
-                    double *Y, hipStream_t s);
-void launch_rr_h(const double *U0, const double *Y, int32_t M, int32_t k, int32_t npad, double *H, hipStream_t s);
+size_t rr_part_doubles(int64_t N, int32_t k);   // partial H tiles of the Rayleigh-Ritz SYRK
+void launch_rr_h(const CscView &A, int64_t N, int32_t k, const double *U0, double *part, int32_t npad, double *H,
+                 hipStream_t s);
 void launch_rr_apply(const double *U0, const double *Q, int64_t ldq, const int32_t *perm, int32_t M, int32_t k,
                      double *U, hipStream_t s);
 

@@ -78,7 +78,7 @@ struct Plan {
     size_t o_empty = 0, o_lonely = 0, o_single = 0, o_csrk = 0, o_csrend = 0, o_csrcol = 0;
     size_t o_gsegp = 0, o_gslot = 0, o_gpart = 0, o_dense = 0;
     size_t o_G = 0, o_G2 = 0, o_W = 0, o_J = 0, o_S = 0, o_jflag = 0, o_lam = 0, o_perm = 0;
-    size_t o_U0 = 0, o_Z = 0, o_part = 0, o_Y = 0, o_seg = 0, total = 0;
+    size_t o_U0 = 0, o_part = 0, total = 0;
     bool solver = false, refine = false;
 };
 
@@ -133,10 +133,7 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool sol
         if (refine) {
             p.refine = true;
             p.o_U0 = take(sizeof(double) * (size_t)M * k);
-            p.o_Z = take(sizeof(double) * (size_t)N * k);
-            p.o_part = take(sizeof(double) * (size_t)rr_max_segments(M, nnz) * k);
-            p.o_Y = take(sizeof(double) * (size_t)M * k);
-            p.o_seg = take(sizeof(int32_t) * (size_t)(M + 1));
+            p.o_part = take(sizeof(double) * rr_part_doubles(N, k));
         }
     }
     p.total = off;
@@ -144,8 +141,7 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool sol
 }
 
 struct Refine {
-    double *U0 = nullptr, *Z = nullptr, *part = nullptr, *Y = nullptr;
-    int32_t *seg = nullptr;
+    double *U0 = nullptr, *part = nullptr;   // U0 (M x k) and the partial H tiles
 };
 
 // Descriptor of one matrix with its workspace carved at `base`.
@@ -194,10 +190,7 @@ MatDesc carve(const Plan &p, char *base, Refine *rf) {
     }
     if (rf && p.refine) {
         rf->U0 = f64(p.o_U0);
-        rf->Z = f64(p.o_Z);
         rf->part = f64(p.o_part);
-        rf->Y = f64(p.o_Y);
-        rf->seg = i32(p.o_seg);
     }
     return d;
 }
@@ -624,14 +617,9 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
         const Job &j = jobs[0];
         const CscView Av{j.A.nnz, j.A.colptr, j.A.rowidx, j.A.values, j.A.dtype};
         const int32_t k = j.k;
-        if (x.n > 0) {
-            launch_rr_z(Av, j.N, k, rf.U0, rf.Z, ctx->cu_count, s);
-            launch_rr_rows(Av, x.rownnz, x.rowptr, j.M, j.A.nnz, k, x.csrk, x.csrcol, rf.Z, rf.seg, rf.part, rf.Y, s);
-        } else {
-            launch_fill_f64(rf.Y, (int64_t)j.M * k, 0.0, s);
-        }
         const int32_t kpad = jacobi_npad(k);
-        launch_rr_h(rf.U0, rf.Y, j.M, k, kpad, x.G, s);
+        if (x.n > 0) launch_rr_h(Av, j.N, k, rf.U0, rf.part, kpad, x.G, s);
+        else launch_fill_f64(x.G, (int64_t)kpad * kpad, 0.0, s);
         HIP_TRY(hipGetLastError());
         // the main matrix's header entries are no longer read: reuse them for H
         Engine eh;
