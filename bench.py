@@ -30,6 +30,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--no-other", action="store_true", help="skip the other-precision leg of the headline matrix")
+    ap.add_argument("--cfg5", action="store_true",
+                    help="also time config 5 (4096 x 2^24, ~200M nnz, mixed path; generation takes ~25-60 s)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a device-to-device copy of this many GiB (counter calibration) and exit")
     return ap.parse_args()
@@ -164,6 +166,39 @@ def time_batch(ranky, torch, gen, steps, warmup):
     return out
 
 
+def time_cfg5(ranky, torch, np, gen, steps, warmup):
+    """Config 5: one large matrix (4096 x 2^24, Zipf(1.2) rows capped at N, ~200M nnz, FP32
+    values, 256 column blocks, k = 100) through the mixed path (FP32 Gram, FP64 eigensolve and
+    Rayleigh-Ritz, FP32 V), inputs resident in HBM."""
+    A = gen.cfg5(progress=lambda m: print(m, file=sys.stderr, flush=True))
+    dA = ranky.to_device(A, "cuda:0")
+    k, D = A.meta["k"], A.meta["D"]
+    kw = dict(n_blocks=D, gram_prec="fp32", refine=1, v_dtype=torch.float32)
+    out = ranky.SVDResult(torch.empty(k, dtype=torch.float64, device="cuda:0"),
+                          torch.empty((A.M, k), dtype=torch.float64, device="cuda:0"),
+                          torch.empty((A.N, k), dtype=torch.float32, device="cuda:0"), {})
+    ctx = ranky.context(0)
+    ws = torch.empty(ranky.workspace_bytes(A.M, A.N, A.nnz, k, ranky.make_opts(**kw)), dtype=torch.uint8,
+                     device="cuda:0")
+    for _ in range(warmup):
+        ranky.svd(dA, k, 0.0, ctx=ctx, out=out, workspace=ws, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ranky.svd(dA, k, 0.0, ctx=ctx, out=out, workspace=ws, **kw)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    r = ranky.svd(dA, k, 0.0, ctx=ctx, out=out, workspace=ws, timing=True, **kw)
+    names = ["occupancy", "transpose", "gram", "eigensolve", "select", "refine", "backproject", "total"]
+    res = {"workload": f"cfg5 M={A.M} N={A.N} nnz={A.nnz} Zipf(1.2) D={D} k={k} mixed (fp32 gram, fp64 eig+RR, fp32 V)",
+           "value": A.nnz / (ms * 1e-3), "unit": "nnz/s", "ms_per_step": ms, "steps": steps,
+           "phase_ms": dict(zip(names, [round(x, 4) for x in r.info["ms"]])), "rank": r.info["rank"],
+           "sweeps": r.info["sweeps"]}
+    del out, ws, dA
+    torch.cuda.empty_cache()
+    return res
+
+
 def time_serving(ranky, torch, gen, seconds, pool_size=48, slots=8):
     """Serving leg: cfg4's open-loop Poisson arrivals (200 req/s) replayed for `seconds`, each
     arrival drawing the next matrix of a seeded pool of cfg4 requests (M in {128..1024},
@@ -282,6 +317,8 @@ def main():
         line["batch"] = time_batch(ranky, torch, gen, max(2, args.steps // 3), 1)
     if not args.no_serve:
         line["serving"] = time_serving(ranky, torch, gen, args.serve_seconds)
+    if args.cfg5:
+        line["cfg5"] = time_cfg5(ranky, torch, np, gen, max(2, args.steps // 3), 1)
 
     if not args.no_cpu_baseline:
         import oracle

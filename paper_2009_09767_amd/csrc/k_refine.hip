@@ -55,14 +55,40 @@ __global__ __launch_bounds__(256) void k_rr_syrk(const int32_t *__restrict__ col
         double za[4] = {0.0, 0.0, 0.0, 0.0}, zb[4] = {0.0, 0.0, 0.0, 0.0};
         const int64_t j = c0 + bc;
         if (j < c_end) {
-            for (int32_t e = colptr[j]; e < colptr[j + 1]; ++e) {
+            // four nonzeros per step with independent loads, so their U0 rows are in
+            // flight together (the walk is otherwise bound by one gather's latency)
+            const int32_t e_end = colptr[j + 1];
+            int32_t e = colptr[j];
+            for (; e + 4 <= e_end; e += 4) {
+                double av[4];
+                const double *u[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    av[t] = static_cast<double>(vals[e + t]);
+                    u[t] = U0 + (int64_t)rowidx[e + t] * k;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (ia + q < k)
+                        za[q] = fma(av[3], u[3][ia + q], fma(av[2], u[2][ia + q],
+                                    fma(av[1], u[1][ia + q], fma(av[0], u[0][ia + q], za[q]))));
+                    if (ta != tb && ib + q < k)
+                        zb[q] = fma(av[3], u[3][ib + q], fma(av[2], u[2][ib + q],
+                                    fma(av[1], u[1][ib + q], fma(av[0], u[0][ib + q], zb[q]))));
+                }
+            }
+            for (; e < e_end; ++e) {
                 const double av = static_cast<double>(vals[e]);
                 const double *u = U0 + (int64_t)rowidx[e] * k;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     if (ia + q < k) za[q] = fma(av, u[ia + q], za[q]);
-                    if (ib + q < k) zb[q] = fma(av, u[ib + q], zb[q]);
+                    if (ta != tb && ib + q < k) zb[q] = fma(av, u[ib + q], zb[q]);
                 }
+            }
+            if (ta == tb) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) zb[q] = za[q];
             }
         }
 #pragma unroll

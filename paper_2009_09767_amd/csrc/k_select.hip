@@ -153,7 +153,24 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr, const int32
         for (int64_t j = jb; j < je; ++j) {
             const int32_t e0 = colptr[j], e1 = colptr[j + 1];
             double a0 = 0.0, a1 = 0.0;
-            for (int32_t e = e0; e < e1; ++e) {
+            int32_t e = e0;
+            // four nonzeros per step with independent loads (their U rows in flight together)
+            for (; e + 4 <= e1; e += 4) {
+                double av[4];
+                const double *Um[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    av[t] = static_cast<double>(vals[e + t]);
+                    Um[t] = U + (int64_t)rowidx[e + t] * k + i;
+                }
+                if (ok1) {
+                    a0 = fma(av[3], Um[3][0], fma(av[2], Um[2][0], fma(av[1], Um[1][0], fma(av[0], Um[0][0], a0))));
+                    a1 = fma(av[3], Um[3][1], fma(av[2], Um[2][1], fma(av[1], Um[1][1], fma(av[0], Um[0][1], a1))));
+                } else if (ok0) {
+                    a0 = fma(av[3], Um[3][0], fma(av[2], Um[2][0], fma(av[1], Um[1][0], fma(av[0], Um[0][0], a0))));
+                }
+            }
+            for (; e < e1; ++e) {
                 const int32_t m = rowidx[e];
                 const double a = static_cast<double>(vals[e]);
                 const double *Um = U + (int64_t)m * k + i;
