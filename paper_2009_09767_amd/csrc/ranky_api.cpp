@@ -398,9 +398,28 @@ struct Engine {
         });
         nblk[kPhJdiag] = fill_wp(hwp(kPhJdiag), count, [&](int i) { return live(i) ? (int64_t)(d[i].n + 255) / 256 : 0; });
         nblk[kPhGather] = fill_wp(hwp(kPhGather), count, [&](int i) { return status[i] == RANKY_OK ? (int64_t)d[i].k : 0; });
-        nblk[kPhBack] = fill_wp(hwp(kPhBack), count, [&](int i) {
-            return status[i] == RANKY_OK ? backproject_blocks(d[i].N, ctx->cu_count, d[i].bp_per_cu) : (int64_t)0;
-        });
+        // back-projection: one matrix gets the tuned grid; a batch shares one grid of that
+        // size in proportion to each matrix's V bytes (at least one workgroup each), so the
+        // waves walk longer column runs instead of launching millions of tiny workgroups
+        if (count == 1) {
+            nblk[kPhBack] = fill_wp(hwp(kPhBack), count, [&](int i) {
+                return status[i] == RANKY_OK ? backproject_blocks(d[i].N, ctx->cu_count, d[i].bp_per_cu) : (int64_t)0;
+            });
+        } else {
+            double work = 0.0;
+            int32_t per_cu = 0;
+            for (int i = 0; i < count; ++i)
+                if (status[i] == RANKY_OK) {
+                    work += (double)d[i].N * d[i].k;
+                    per_cu = std::max(per_cu, d[i].bp_per_cu);
+                }
+            const double grid = (double)ctx->cu_count * (per_cu > 0 ? per_cu : 32);
+            nblk[kPhBack] = fill_wp(hwp(kPhBack), count, [&](int i) -> int64_t {
+                if (status[i] != RANKY_OK) return 0;
+                const int64_t share = (int64_t)(grid * ((double)d[i].N * d[i].k) / (work > 0.0 ? work : 1.0));
+                return std::max<int64_t>(1, std::min(share, backproject_blocks(d[i].N, ctx->cu_count, d[i].bp_per_cu)));
+            });
+        }
         nb_max = 0;
         for (int i = 0; i < count; ++i)
             if (live(i)) nb_max = std::max(nb_max, d[i].npad / kJacobiBlock);
