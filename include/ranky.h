@@ -21,6 +21,8 @@
  *     (m, i) at index m * k + i.
  *   - The caller owns every buffer (inputs, outputs, workspace); the library never
  *     frees caller memory and never allocates device memory inside these calls.
+ *   - A workspace must start on a 256-byte boundary (hipMalloc and torch
+ *     allocations do); RANKY_E_INVALID otherwise.
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = the legacy default
  *     stream).  Calls documented as "blocking" synchronise that stream before
  *     returning; the others are stream-ordered and return after enqueueing.
@@ -174,18 +176,21 @@ ranky_status ranky_svd(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N,
 typedef struct {
     int32_t bp_per_cu;              /* chosen back-projection workgroups per CU (0: not timed,
                                        the refinement path computes V itself) */
-    int32_t jacobi_schedule;        /* chosen update-tile schedule: 0 linear, 1 grouped per XCD */
+    int32_t jacobi_schedule;        /* chosen Jacobi round launch shape, bit 0: update tiles grouped
+                                       per XCD (else linear), bit 1: one round workgroup per CU */
     int32_t bp_candidates[4];       /* workgroups per CU tried ... */
     float bp_ms[4];                 /* ... and the best back-projection time of each (ms) */
-    int32_t schedule_candidates[2]; /* schedules tried ... */
-    float eig_ms[2];                /* ... and the best eigensolve time of each (ms) */
+    int32_t schedule_candidates[4]; /* schedules tried ... */
+    float eig_ms[4];                /* ... and the best eigensolve time of each (ms) */
 } ranky_tune_report;
 
 /* Picks the launch shapes of this problem shape by measurement and stores them in the
  * context: later ranky_svd / ranky_batch calls on the same context with the same
  * (M, N, nnz, k, value dtype, opts->v_dtype, opts->gram_prec) use them.  Candidates:
- * back-projection workgroups per CU {8, 16, 32, 64} and the Jacobi update-tile schedule
- * {linear, grouped per XCD: the tiles that share a rotation J run on one XCD's L2}.
+ * back-projection workgroups per CU {8, 16, 32, 64} and the Jacobi round launch shape
+ * {0..3}: bit 0 groups the update tiles per XCD (the tiles that share a rotation J run on
+ * one XCD's L2), bit 1 gives every round workgroup a CU of its own (extra LDS), so no update
+ * workgroup shares a CU with a subproblem sweep, the round's critical path.
  * Neither changes any result (each V column and each tile is computed the same way
  * whatever the launch shape), only the time.  Runs the whole path on A about a dozen
  * times with phase timing (HIP events on `stream`), so it belongs before a timed region,
@@ -198,7 +203,8 @@ ranky_status ranky_autotune(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64
 
 /* Stores launch shapes for a problem shape without measuring (a configuration kept
  * from an earlier ranky_autotune, or a fixed choice).  Same key as ranky_autotune.
- * E_INVALID for bp_per_cu outside [1, 1024] or a schedule other than 0 / 1. */
+ * E_INVALID for bp_per_cu outside [1, 1024] or a schedule outside [0, 3].  In a batch, bit 1
+ * applies only when every matrix of the call has it. */
 ranky_status ranky_tune_set(ranky_ctx *ctx, int32_t M, int64_t N, int64_t nnz, int32_t k, ranky_dtype dtype,
                             const ranky_opts *opts, int32_t bp_per_cu, int32_t jacobi_schedule);
 
@@ -244,7 +250,8 @@ ranky_status ranky_batch(ranky_ctx *ctx, int32_t count, const ranky_batch_item *
 typedef struct ranky_server ranky_server;
 
 typedef struct {
-    void *arena;          /* device memory the server carves for admitted requests (caller-owned) */
+    void *arena;          /* device memory the server carves for admitted requests (caller-owned,
+                             256-byte aligned) */
     size_t arena_bytes;
     int32_t max_slots;    /* requests on the device at once (each has its own stream), >= 1 */
     int32_t max_queue;    /* waiting requests before submit answers RANKY_E_BUSY, >= 1 */

@@ -38,7 +38,7 @@ struct MatDesc {
     int32_t *dense;           // [kDenseRows] the densest rows (original index, by degree), -1 when unused
     // launch-shape knobs (results do not depend on them; set from the context's tuning cache)
     int32_t bp_per_cu;        // back-projection workgroups per compute unit
-    int32_t jsched;           // Jacobi update-tile schedule: 0 linear, 1 grouped per XCD
+    int32_t jsched;           // Jacobi round launch: bit 0 update tiles grouped per XCD, bit 1 one round workgroup per CU
     double *sdbl, *G, *G2, *W, *J, *S, *lam;
     // outputs (caller-owned)
     double *sigma, *U;

@@ -39,6 +39,8 @@
 // and 1 rotate the 120 off-diagonal 2 x 2 blocks, wave 2 the 16 diagonal blocks (and
 // records every rotation of the sweep), wave 3 holds one row of J per lane in
 // registers and applies step k's rotations while step k + 1 runs.
+#include <cstring>
+
 #include "batch.hpp"
 #include "common.hpp"
 #include "launch.hpp"
@@ -81,7 +83,7 @@ __device__ __forceinline__ int gidx(int l, int P, int Q) { return l < kB ? P * k
 
 // Per-matrix arguments of one round launch (a table of these covers a batch).
 struct RoundArgs {
-    const double *Gin;     // M_{r-1} (or M_r itself when there is no previous round); set in-kernel
+    const double *Gin;     // M_{r-1}; set in-kernel for the update part
     double *Gout;          // receives M_r = Jp^T M_{r-1} Jp (update part); set in-kernel
     double *G0, *G1;       // the two G buffers
     double *W;             // eigenvectors, updated in place by Jp
@@ -102,7 +104,7 @@ struct RoundArgs {
     int32_t inner_sweeps;
     int32_t ntiles_g;      // npairs (npairs + 1) / 2
     int32_t nrowtiles;     // npad / 32
-    int32_t sched;         // update-tile schedule: 0 linear, 1 grouped per XCD (see k_jround)
+    int32_t sched;         // bit 0: update tiles grouped per XCD (see k_jround); bit 1 is host-side
 };
 
 __device__ __forceinline__ void wave_fence() {
@@ -112,6 +114,12 @@ __device__ __forceinline__ void wave_fence() {
 }
 
 // ---- subproblem solve -------------------------------------------------------
+
+// One FP64 MFMA 16 x 16 x 4 step: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+// element i of lane l's result is C[l / 16 + 4 i][l % 16].
+__device__ __forceinline__ d4 mfma4(double x, double y, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
+}
 
 // position after one step of the in-subproblem round-robin
 __device__ __forceinline__ int turn(int p) { return p == 0 ? 0 : (p == 1 ? kP - 1 : p - 1); }
@@ -163,14 +171,14 @@ __device__ __forceinline__ void jrow_sweep(double (&jr)[kP], const double2 (*tab
 }
 
 // LDS of a solve workgroup (doubles): S0 | S1 | rotation table [31][16] | per-wave (c, s).
-// The build of S uses S1 for the gathered tile T and the table area for J slices.
+// The build of S uses the table area for the partial product P_1 (16 x 16).
 constexpr int kSoS1 = kP * kPS, kSoTab = 2 * kP * kPS, kSoWcs = kSoTab + 2 * kSteps * (kP / 2),
               kSoEnd = kSoWcs + 2 * 2 * (kP / 2);
 constexpr int kSmemDoubles = kTileWaves * kP * kPS;
 static_assert(kSoEnd <= kSmemDoubles, "solve LDS fits the update LDS");
-static_assert(kSoTab + 2 * kP * kB <= kSoEnd, "J slices fit the table area");
+static_assert(kB * kB <= 2 * kSteps * (kP / 2), "P_1 fits the table area");
 
-__device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, double *smem) {
+__device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t launch_r, double *smem) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     double *S0 = smem, *S1 = smem + kSoS1;
@@ -180,62 +188,105 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, double 
     tournament_pair(a.nb, a.round_cur, pair, P, Q);
 
     // ---- build S (upper triangle) ----
+    // Every global load of the build is issued before the first wait: the sweep state
+    // (it says which G buffer holds M_{r-1}), the tile from both G buffers, the two
+    // diagonal blocks and the J slices (the previous round stored J for every pair,
+    // the identity included), so the build costs one memory round trip.  With a
+    // previous round, the off-diagonal block J_pp[:, hp]^T M_{r-1}[s_pp, s_pq] J_pq[:, hq]
+    // is two products on the FP64 matrix cores: wave w (0, 1) takes tile rows
+    // 16w .. 16w + 15, U_w = T_w JB (k = 32) and P_w = JA_w^T U_w (k = 16, U_w stays in
+    // registers: the product's result layout is the next product's B layout), and
+    // S_PQ = P_0 + P_1.  Waves 2 and 3 bring the diagonal blocks.
+    const int32_t active = a.jstate[kJsActive], sweeps = a.jstate[kJsSweeps];
+    const int l16 = lane & 15, l4 = lane >> 4;
+    double g0[8], g1[8], jb[8], ja[4], dg[4];
+    int pp = 0, hp = 0, pq = 0, hq = 0;
     if (!a.has_prev) {
-        for (int e = tid; e < kP * kP; e += 256) {
-            const int x = e >> 5, y = e & 31;
-            if (x <= y) S0[x * kPS + y] = a.Gin[(int64_t)gidx(x, P, Q) * a.ld + gidx(y, P, Q)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int e = tid + 256 * j, x = e >> 5, y = e & 31;
+            g0[j] = g1[j] = 0.0;
+            if (x <= y) {
+                const int64_t off = (int64_t)gidx(x, P, Q) * a.ld + gidx(y, P, Q);
+                g0[j] = a.G0[off];
+                g1[j] = a.G1[off];
+            }
         }
     } else {
-        int pp, hp, pq, hq;
         block_seat(a.nb, a.round_prev, P, pp, hp);
         block_seat(a.nb, a.round_prev, Q, pq, hq);
-        double *T = S1, *JA = smem + kSoTab, *JB = smem + kSoTab + kP * kB;
-        // diagonal blocks: the previous round's rotated subproblems
-        for (int e = tid; e < kB * kB; e += 256) {
-            const int x = e >> 4, y = e & 15;
-            if (x <= y) {
-                S0[x * kPS + y] = a.Sprev[(int64_t)pp * kP * kP + (hp * kB + x) * kP + hp * kB + y];
-                S0[(kB + x) * kPS + kB + y] = a.Sprev[(int64_t)pq * kP * kP + (hq * kB + x) * kP + hq * kB + y];
+        if (wave < 2) {
+            int Pa, Qa, Pb, Qb;
+            tournament_pair(a.nb, a.round_prev, pp, Pa, Qa);
+            tournament_pair(a.nb, a.round_prev, pq, Pb, Qb);
+            // U_w: step q's contraction index for lane group l4 is k = 8 l4 + q, so each
+            // lane reads 8 consecutive entries of its T row (one block: 8 divides 16)
+            const int64_t off = (int64_t)gidx(16 * wave + l16, Pa, Qa) * a.ld + gidx(8 * l4, Pb, Qb);
+            const double2 *t0 = reinterpret_cast<const double2 *>(a.G0 + off);
+            const double2 *t1 = reinterpret_cast<const double2 *>(a.G1 + off);
+            const double *jpa = a.Jprev + (int64_t)pp * kP * kP + hp * kB + l16;
+            const double *jpb = a.Jprev + (int64_t)pq * kP * kP + hq * kB + l16;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double2 x0 = t0[v], x1 = t1[v];   // T[16w + l16][8 l4 + 2v, + 1]
+                g0[2 * v] = x0.x;
+                g0[2 * v + 1] = x0.y;
+                g1[2 * v] = x1.x;
+                g1[2 * v + 1] = x1.y;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) jb[q] = jpb[(8 * l4 + q) * kP];   // JB[8 l4 + q][l16]
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ja[q] = jpa[(16 * wave + 4 * q + l4) * kP];   // JA[16w + 4q + l4][l16]
+        } else {
+            // diagonal blocks: the previous round's rotated subproblems (upper triangles)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int e = tid - 128 + 128 * j, x = e >> 4, y = e & 15;
+                dg[j] = dg[2 + j] = 0.0;
+                if (x <= y) {
+                    dg[j] = a.Sprev[(int64_t)pp * kP * kP + (hp * kB + x) * kP + hp * kB + y];
+                    dg[2 + j] = a.Sprev[(int64_t)pq * kP * kP + (hq * kB + x) * kP + hq * kB + y];
+                }
             }
         }
-        // off-diagonal block: J_pp[:, hp]^T  M_{r-1}[s_pp, s_pq]  J_pq[:, hq]
-        int Pa, Qa, Pb, Qb;
-        tournament_pair(a.nb, a.round_prev, pp, Pa, Qa);
-        tournament_pair(a.nb, a.round_prev, pq, Pb, Qb);
-        const bool fa = a.fprev[pp] != 0, fb = a.fprev[pq] != 0;
-        for (int e = tid; e < kP * kP; e += 256) {
-            const int x = e >> 5, y = e & 31;
-            T[x * kPS + y] = a.Gin[(int64_t)gidx(x, Pa, Qa) * a.ld + gidx(y, Pb, Qb)];
+    }
+    if (active == 0) return;
+    // G buffer holding M_{r-1}: one flip per launch with a previous round, nb - 1 per sweep
+    const bool odd = ((sweeps * (a.nb - 1) + (launch_r > 0 ? launch_r - 1 : 0)) & 1) != 0;
+    if (!a.has_prev) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int e = tid + 256 * j, x = e >> 5, y = e & 31;
+            if (x <= y) S0[x * kPS + y] = odd ? g1[j] : g0[j];
         }
-        for (int e = tid; e < kP * kB; e += 256) {
-            const int x = e >> 4, y = e & 15;
-            JA[x * kB + y] = fa ? a.Jprev[(int64_t)pp * kP * kP + x * kP + hp * kB + y] : (x == hp * kB + y ? 1.0 : 0.0);
-            JB[x * kB + y] = fb ? a.Jprev[(int64_t)pq * kP * kP + x * kP + hq * kB + y] : (x == hq * kB + y ? 1.0 : 0.0);
-        }
-        __syncthreads();
-        // U1 = T JB (32 x 16): two outputs per thread, kept in registers
-        double u0 = 0.0, u1 = 0.0;
-        {
-            const int x = tid >> 3, y = (tid & 7) * 2;
-            for (int z = 0; z < kP; ++z) {
-                const double t = T[x * kPS + z];
-                u0 = fma(t, JB[z * kB + y], u0);
-                u1 = fma(t, JB[z * kB + y + 1], u1);
+    } else {
+        double *part = smem + kSoTab;   // P_1, 16 x 16
+        d4 pw = {0.0, 0.0, 0.0, 0.0};
+        if (wave < 2) {
+            d4 u = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < 8; ++q) u = mfma4(odd ? g1[q] : g0[q], jb[q], u);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pw = mfma4(ja[q], u[q], pw);
+            if (wave == 1) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) part[(l4 + 4 * i) * kB + l16] = pw[i];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int e = tid - 128 + 128 * j, x = e >> 4, y = e & 15;
+                if (x <= y) {
+                    S0[x * kPS + y] = dg[j];
+                    S0[(kB + x) * kPS + kB + y] = dg[2 + j];
+                }
             }
         }
         __syncthreads();
-        {
-            const int x = tid >> 3, y = (tid & 7) * 2;
-            T[x * kPS + y] = u0;
-            T[x * kPS + y + 1] = u1;
-        }
-        __syncthreads();
-        // S_PQ = JA^T U1 (16 x 16): one output per thread
-        {
-            const int x = tid >> 4, y = tid & 15;
-            double v = 0.0;
-            for (int z = 0; z < kP; ++z) v = fma(JA[z * kB + x], T[z * kPS + y], v);
-            S0[x * kPS + kB + y] = v;
+        if (wave == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) S0[(l4 + 4 * i) * kPS + kB + l16] = pw[i] + part[(l4 + 4 * i) * kB + l16];
         }
     }
     __syncthreads();
@@ -358,9 +409,6 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, double 
 // result layout is exactly the B-operand layout of the next product over the same
 // rows (k-chunk 4 * rowblock + i), so J_a^T (G J_b) keeps G J_b in registers.
 
-__device__ __forceinline__ d4 mfma4(double x, double y, d4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
-}
 
 // acc = A B, A a 32 x 32 tile in LDS (stride kPS), B row-major 32 x 32 in memory.
 __device__ __forceinline__ void mm_lds_mem(const double *__restrict__ A, const double *__restrict__ B, d4 (&acc)[2][2],
@@ -423,7 +471,7 @@ __device__ __forceinline__ void update_tile(const RoundArgs &a, int u, double *b
         if (ia == ib) {
             const double *s = a.Sprev + (int64_t)ia * kP * kP;
             for (int e = l; e < kP * kP; e += 64)
-                a.Gout[(int64_t)gidx(e >> 5, Pa, Qa) * a.ld + gidx(e & 31, Pa, Qa)] = s[e];
+                __builtin_nontemporal_store(s[e], &a.Gout[(int64_t)gidx(e >> 5, Pa, Qa) * a.ld + gidx(e & 31, Pa, Qa)]);
             return;
         }
         const bool fa = a.fprev[ia] != 0, fb = a.fprev[ib] != 0;
@@ -451,7 +499,7 @@ __device__ __forceinline__ void update_tile(const RoundArgs &a, int u, double *b
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int x = 16 * rb + (l >> 4) + 4 * i, y = 16 * cb + (l & 15);
-                    a.Gout[(int64_t)gidx(x, Pa, Qa) * a.ld + gidx(y, Pb, Qb)] = v[i];
+                    __builtin_nontemporal_store(v[i], &a.Gout[(int64_t)gidx(x, Pa, Qa) * a.ld + gidx(y, Pb, Qb)]);
                 }
             }
         // the mirror tile through LDS, so its stores are row runs as well
@@ -467,7 +515,7 @@ __device__ __forceinline__ void update_tile(const RoundArgs &a, int u, double *b
         wave_fence();
         for (int e = l; e < kP * kP; e += 64) {
             const int x = e >> 5, y = e & 31;   // element (y, x) of the tile = (x, y) of its mirror
-            a.Gout[(int64_t)gidx(x, Pb, Qb) * a.ld + gidx(y, Pa, Qa)] = buf[y * kPS + x];
+            __builtin_nontemporal_store(buf[y * kPS + x], &a.Gout[(int64_t)gidx(x, Pb, Qb) * a.ld + gidx(y, Pa, Qa)]);
         }
         return;
     }
@@ -493,31 +541,33 @@ __device__ __forceinline__ void update_tile(const RoundArgs &a, int u, double *b
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int x = 16 * rb + (l >> 4) + 4 * i, y = 16 * cb + (l & 15);
-                a.W[(int64_t)(rt * kP + x) * a.ld + gidx(y, Pb, Qb)] = t[rb][cb][i];
+                __builtin_nontemporal_store(t[rb][cb][i], &a.W[(int64_t)(rt * kP + x) * a.ld + gidx(y, Pb, Qb)]);
             }
 }
 
-__global__ __launch_bounds__(256) void k_jround(const RoundArgs *__restrict__ table, const int32_t *__restrict__ wp,
-                                                int count, int32_t launch_r) {
+// `one` holds the arguments when the launch covers a single matrix (count == 1), so
+// they arrive with the launch; a batch reads them from `table`.
+__global__ __launch_bounds__(256) void k_jround(const RoundArgs one, const RoundArgs *__restrict__ table,
+                                                const int32_t *__restrict__ wp, int count, int32_t launch_r) {
     __shared__ __align__(16) double smem[kSmemDoubles];
-    const int mat = find_mat(wp, count, blockIdx.x);
-    RoundArgs a = table[mat];
+    const int mat = count == 1 ? 0 : find_mat(wp, count, blockIdx.x);
+    RoundArgs a = count == 1 ? one : table[mat];
+    const int npairs = a.nb / 2;
+    int b = count == 1 ? (int)blockIdx.x : (int)blockIdx.x - wp[mat];
+    if (a.do_solve) {
+        if (b < npairs) {
+            solve_pair(a, b, launch_r, smem);
+            return;
+        }
+        b -= npairs;
+    }
     if (a.jstate[kJsActive] == 0) return;
     // G buffer holding M_{r-1}: one flip per launch with a previous round, nb - 1 per sweep
     const int32_t flips = a.jstate[kJsSweeps] * (a.nb - 1) + (launch_r > 0 ? launch_r - 1 : 0);
     a.Gin = (flips & 1) ? a.G1 : a.G0;
     a.Gout = (flips & 1) ? a.G0 : a.G1;
-    const int npairs = a.nb / 2;
-    int b = blockIdx.x - wp[mat];
-    if (a.do_solve) {
-        if (b < npairs) {
-            solve_pair(a, b, smem);
-            return;
-        }
-        b -= npairs;
-    }
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (a.sched) {
+    if (a.sched & 1) {
         // consecutive workgroups go to consecutive XCDs; give the workgroups of one XCD a
         // contiguous range of tiles (a bijection on the first 8 floor(U / 8) of them)
         const int tiles = a.ntiles_g + a.nrowtiles * npairs;
@@ -667,11 +717,18 @@ void launch_jacobi_state(const MatDesc *descs, int count, int32_t phase, int32_t
                        max_sweeps);
 }
 
-void launch_jacobi_round(const void *table, const int32_t *wp, int64_t nblocks, int count, int32_t launch_r,
-                         hipStream_t s) {
+void launch_jacobi_round(const void *host_table, const void *table, const int32_t *wp, int64_t nblocks, int count,
+                         int32_t launch_r, size_t lds_pad, hipStream_t s) {
     if (nblocks <= 0) return;
-    hipLaunchKernelGGL(k_jround, dim3((unsigned)nblocks), dim3(256), 0, s, static_cast<const RoundArgs *>(table), wp,
-                       count, launch_r);
+    RoundArgs one = {};
+    if (count == 1) one = *static_cast<const RoundArgs *>(host_table);
+    hipLaunchKernelGGL(k_jround, dim3((unsigned)nblocks), dim3(256), lds_pad, s, one,
+                       static_cast<const RoundArgs *>(table), wp, count, launch_r);
+}
+
+size_t jround_solo_pad(size_t lds_per_cu) {
+    const size_t own = sizeof(double) * kSmemDoubles, half = lds_per_cu / 2 + 1024;
+    return half > own ? half - own : 0;
 }
 
 void launch_jacobi_check(const MatDesc *descs, const int32_t *wp, int64_t nblocks, int count, hipStream_t s) {
@@ -688,6 +745,7 @@ size_t round_args_bytes() { return sizeof(RoundArgs); }
 
 void fill_round_args(void *dst, const MatDesc &d, int32_t r, int32_t inner_sweeps) {
     RoundArgs a;
+    std::memset(&a, 0, sizeof(a));   // padding too: the bytes are hashed to key captured graphs
     const int32_t nb = d.npad / kB;
     const int32_t npairs = nb / 2;
     const size_t jsz = (size_t)npairs * kP * kP;
@@ -715,7 +773,7 @@ void fill_round_args(void *dst, const MatDesc &d, int32_t r, int32_t inner_sweep
     a.ntiles_g = npairs * (npairs + 1) / 2;
     a.nrowtiles = d.npad / kP;
     a.sched = d.jsched;
-    *static_cast<RoundArgs *>(dst) = a;
+    std::memcpy(dst, &a, sizeof(a));
 }
 
 // workgroups matrix d needs in launch r of a sweep (0 when it has no work there)

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -22,7 +23,7 @@
 // Launch-shape choices of the autotuner for one problem shape (results do not depend on them).
 struct TuneCfg {
     int32_t bp_per_cu = 32;   // back-projection workgroups per CU
-    int32_t jsched = 0;       // Jacobi update-tile schedule
+    int32_t jsched = 0;       // Jacobi round launch shape (MatDesc::jsched)
 };
 // M, N, nnz, k, value dtype, V dtype, Gram precision
 using TuneKey = std::tuple<int32_t, int64_t, int64_t, int32_t, int32_t, int32_t, int32_t>;
@@ -65,6 +66,7 @@ ranky_status fail(ranky_status st, const char *fmt, ...) {
         if (e_ != hipSuccess) return fail(RANKY_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
+constexpr int kWorkspaceAlign = 256;   // workspace base; every carved buffer keeps it
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 // ---------------------------------------------------------------------------
@@ -312,6 +314,7 @@ struct Engine {
     bool time_rounds = false;        // timing mode: events around the round launches of each active sweep
     double round_ms = 0.0;
     int32_t round_launches = 0;
+    size_t jround_lds = 0;           // dynamic LDS of the round launches (one workgroup per CU when set)
 
     char *stage() { return static_cast<char *>(ctx->pinned); }
     MatDesc *ddesc() { return reinterpret_cast<MatDesc *>(hdr + h.o_desc); }
@@ -421,8 +424,17 @@ struct Engine {
             });
         }
         nb_max = 0;
+        bool solo = false, all_solo = true;
         for (int i = 0; i < count; ++i)
-            if (live(i)) nb_max = std::max(nb_max, d[i].npad / kJacobiBlock);
+            if (live(i)) {
+                nb_max = std::max(nb_max, d[i].npad / kJacobiBlock);
+                solo = true;
+                all_solo = all_solo && (d[i].jsched & 2) != 0;
+            }
+        // a round's solve workgroups are its critical path: with bit 1 of the schedule set
+        // on every matrix, each CU holds one round workgroup, so no update workgroup
+        // competes with a subproblem sweep for the CU's issue slots and LDS
+        jround_lds = solo && all_solo ? jround_solo_pad(ctx->lds_limit + 4096) : 0;
         rblk.assign(nb_max, 0);
         for (int r = 0; r < nb_max; ++r) {
             rblk[r] = fill_wp(hrwp(r), count, [&](int i) { return live(i) ? round_blocks(d[i], r) : (int64_t)0; });
@@ -443,7 +455,7 @@ struct Engine {
     void enqueue_sweep() {
         launch_jacobi_check(ddesc(), dwp(kPhJcheck), nblk[kPhJcheck], count, s);
         launch_jacobi_state(ddesc(), count, 0, sweeps_cap, s);
-        for (int r = 0; r < nb_max; ++r) launch_jacobi_round(drtab(r), drwp(r), rblk[r], count, r, s);
+        for (int r = 0; r < nb_max; ++r) launch_jacobi_round(hrtab(r), drtab(r), drwp(r), rblk[r], count, r, jround_lds, s);
         launch_jacobi_state(ddesc(), count, 1, sweeps_cap, s);
     }
 
@@ -461,6 +473,11 @@ struct Engine {
             size_t sig = (size_t)count * 1315423911u ^ (size_t)nb_max;
             for (int r = 0; r < nb_max; ++r) sig = sig * 31 + (size_t)rblk[r];
             for (int ph = 0; ph < kPhCount; ++ph) sig = sig * 31 + (size_t)nblk[ph];
+            sig = sig * 31 + jround_lds;
+            // a single matrix's round arguments are captured by value: any change re-captures
+            for (int r = 0; r < nb_max; ++r)
+                for (size_t i = 0, nb = round_args_bytes() * (size_t)count; i < nb; ++i)
+                    sig = sig * 131 + (unsigned char)hrtab(r)[i];
             if (ctx->sweep_graph && ctx->sweep_graph_key == hdr && ctx->sweep_graph_sig == sig) {
                 exec = ctx->sweep_graph;
             } else {
@@ -487,7 +504,8 @@ struct Engine {
                 launch_jacobi_check(ddesc(), dwp(kPhJcheck), nblk[kPhJcheck], count, s);
                 launch_jacobi_state(ddesc(), count, 0, sweeps_cap, s);
                 HIP_TRY(hipEventRecord(ctx->ev[9], s));
-                for (int r = 0; r < nb_max; ++r) launch_jacobi_round(drtab(r), drwp(r), rblk[r], count, r, s);
+                for (int r = 0; r < nb_max; ++r)
+                    launch_jacobi_round(hrtab(r), drtab(r), drwp(r), rblk[r], count, r, jround_lds, s);
                 HIP_TRY(hipEventRecord(ctx->ev[10], s));
                 launch_jacobi_state(ddesc(), count, 1, sweeps_cap, s);
                 HIP_TRY(hipGetLastError());
@@ -565,6 +583,8 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
         need += plans[i].total;
     }
     if (!workspace || ws_bytes < need) return fail(RANKY_E_NOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
+    if (reinterpret_cast<uintptr_t>(workspace) % kWorkspaceAlign)
+        return fail(RANKY_E_INVALID, "workspace is not %d-byte aligned", kWorkspaceAlign);
     char *ws = static_cast<char *>(workspace);
     Engine e;
     ranky_status st = make_engine(ctx, s, h, ws, count, e);
@@ -761,6 +781,8 @@ ranky_status step_scan(StepCtx &sc, const ranky_csc *A, int32_t M, int64_t N, in
     const Header h = make_header(1, 1, 1);
     if (!workspace || ws_bytes < h.total + p.total)
         return fail(RANKY_E_NOMEM, "workspace %zu < %zu", ws_bytes, h.total + p.total);
+    if (reinterpret_cast<uintptr_t>(workspace) % kWorkspaceAlign)
+        return fail(RANKY_E_INVALID, "workspace is not %d-byte aligned", kWorkspaceAlign);
     ranky_status st = step_device(sc);
     if (st) return st;
     char *ws = static_cast<char *>(workspace);
@@ -893,7 +915,7 @@ ranky_status ranky_tune_set(ranky_ctx *ctx, int32_t M, int64_t N, int64_t nnz, i
     const ranky_status st = check_opts(o);
     if (st) return st;
     if (bp_per_cu < 1 || bp_per_cu > 1024) return fail(RANKY_E_INVALID, "bp_per_cu=%d", bp_per_cu);
-    if (jacobi_schedule != 0 && jacobi_schedule != 1) return fail(RANKY_E_INVALID, "jacobi_schedule=%d", jacobi_schedule);
+    if (jacobi_schedule < 0 || jacobi_schedule > 3) return fail(RANKY_E_INVALID, "jacobi_schedule=%d", jacobi_schedule);
     TuneCfg c;
     c.bp_per_cu = bp_per_cu;
     c.jsched = jacobi_schedule;
@@ -919,7 +941,7 @@ ranky_status ranky_autotune(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const TuneKey key{M, N, j.A.nnz, k, j.A.dtype, o.v_dtype, o.gram_prec};
     const int32_t bp_cands[4] = {8, 16, 32, 64};
-    const int32_t sched_cands[2] = {0, 1};
+    const int32_t sched_cands[4] = {0, 1, 2, 3};
     const int reps = 2;
     TuneCfg best;
     ranky_info in;
@@ -935,7 +957,7 @@ ranky_status ranky_autotune(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64
         }
         return RANKY_OK;
     };
-    float bp_ms[4] = {0, 0, 0, 0}, eig_ms[2] = {0, 0}, t = 0.f;
+    float bp_ms[4] = {0, 0, 0, 0}, eig_ms[4] = {0, 0, 0, 0}, t = 0.f;
     st = measure(best, 3, t);   // warm-up (kernel loading, caches)
     const bool has_bp = !wants_refine(o, k);   // with refinement V comes from the Rayleigh-Ritz step
     if (!st && has_bp) {
@@ -952,7 +974,7 @@ ranky_status ranky_autotune(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64
     }
     if (!st) {
         float emin = 1e30f;
-        for (int c = 0; c < 2 && !st; ++c) {
+        for (int c = 0; c < 4 && !st; ++c) {
             TuneCfg cfg = best;
             cfg.jsched = sched_cands[c];
             st = measure(cfg, 3, eig_ms[c]);
@@ -975,7 +997,7 @@ ranky_status ranky_autotune(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64
             report->bp_candidates[c] = bp_cands[c];
             report->bp_ms[c] = has_bp ? bp_ms[c] : 0.f;
         }
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < 4; ++c) {
             report->schedule_candidates[c] = sched_cands[c];
             report->eig_ms[c] = eig_ms[c];
         }
@@ -1098,6 +1120,8 @@ ranky_status ranky_eigh(int32_t n, const double *G, double *lambda, double *Q, i
     if (!G || !lambda || !Q) return fail(RANKY_E_INVALID, "NULL argument");
     const size_t need = ranky_eigh_workspace_bytes(n);
     if (!workspace || ws_bytes < need) return fail(RANKY_E_NOMEM, "workspace %zu < %zu", ws_bytes, need);
+    if (reinterpret_cast<uintptr_t>(workspace) % kWorkspaceAlign)
+        return fail(RANKY_E_INVALID, "workspace is not %d-byte aligned", kWorkspaceAlign);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int32_t npad = jacobi_npad(n);
     const size_t npairs = (size_t)(npad / kJacobiPair);

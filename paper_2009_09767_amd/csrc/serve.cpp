@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdint>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -224,6 +225,7 @@ extern "C" {
 ranky_status ranky_serve_create(const ranky_serve_cfg *cfg, ranky_server **out) {
     if (!cfg || !out || !cfg->arena || cfg->arena_bytes == 0 || cfg->max_slots < 1 || cfg->max_queue < 1)
         return RANKY_E_INVALID;
+    if (reinterpret_cast<uintptr_t>(cfg->arena) % 256) return RANKY_E_INVALID;   // carved workspaces keep it
     auto *s = new ranky_server();
     s->cfg = *cfg;
     s->arena.reset(cfg->arena_bytes);

@@ -81,7 +81,7 @@ class Info(ctypes.Structure):
 class TuneReport(ctypes.Structure):
     _fields_ = [("bp_per_cu", ctypes.c_int32), ("jacobi_schedule", ctypes.c_int32),
                 ("bp_candidates", ctypes.c_int32 * 4), ("bp_ms", ctypes.c_float * 4),
-                ("schedule_candidates", ctypes.c_int32 * 2), ("eig_ms", ctypes.c_float * 2)]
+                ("schedule_candidates", ctypes.c_int32 * 4), ("eig_ms", ctypes.c_float * 4)]
 
     def as_dict(self):
         return {"bp_per_cu": self.bp_per_cu, "jacobi_schedule": self.jacobi_schedule,

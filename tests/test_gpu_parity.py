@@ -341,6 +341,13 @@ def test_errors_are_reported(R):
     with pytest.raises(R.RankyError) as e:
         R.svd(good, 3, workspace=torch.empty(64, dtype=torch.uint8, device="cuda"))
     assert e.value.status == R.E_NOMEM
+    # a workspace off the 256-byte boundary is refused before anything is launched
+    need = R.workspace_bytes(good.M, good.N, good.nnz, 3, R.make_opts())
+    ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(R.RankyError) as e:
+        R.svd(good, 3, workspace=ws[8:])
+    assert e.value.status == R.E_INVALID
+    assert np.allclose(R.svd(good, 3, workspace=ws[256:]).sigma.cpu().numpy(), R.svd(good, 3).sigma.cpu().numpy())
 
 
 # --------------------------------------------------------------------------------------

@@ -33,7 +33,7 @@ def test_every_candidate_gives_the_default_result(R):
     k = 32
     base = R.svd(dA, k, 0.0, ctx=R.Context(0), n_blocks=8)
     for bp in (8, 16, 32, 64):
-        for sched in (0, 1):
+        for sched in (0, 1, 2, 3):
             ctx = R.Context(0)
             R.tune_set(dA, k, bp, sched, ctx=ctx, n_blocks=8)
             out = R.svd(dA, k, 0.0, ctx=ctx, n_blocks=8)
@@ -52,14 +52,14 @@ def test_autotune_report_and_reuse(R):
     rep = R.autotune(dA, k, ctx=ctx, stream=stream, n_blocks=8)
     torch.cuda.synchronize()
     assert rep["bp_per_cu"] in (8, 16, 32, 64)
-    assert rep["jacobi_schedule"] in (0, 1)
+    assert rep["jacobi_schedule"] in (0, 1, 2, 3) and len(rep["eig_ms"]) == 4
     assert all(v > 0 for v in rep["bp_ms"].values()) and all(v > 0 for v in rep["eig_ms"].values())
     assert min(rep["bp_ms"], key=rep["bp_ms"].get) == rep["bp_per_cu"]
     out = R.svd(dA, k, 0.0, ctx=ctx, n_blocks=8)
     assert same(out, base)
     # the mixed path has no back-projection launch to time (V comes from the refinement)
     rep2 = R.autotune(dA, k, ctx=ctx, n_blocks=8, gram_prec="fp32", v_dtype=torch.float32)
-    assert rep2["bp_per_cu"] == 0 and rep2["jacobi_schedule"] in (0, 1)
+    assert rep2["bp_per_cu"] == 0 and rep2["jacobi_schedule"] in (0, 1, 2, 3)
 
 
 def test_batch_takes_the_tuned_shapes(R):
@@ -67,9 +67,14 @@ def test_batch_takes_the_tuned_shapes(R):
     dms = [R.to_device(A) for A in mats]
     ks = [A.M for A in mats]
     base = R.batch(dms, ks, ctx=R.Context(0))
-    ctx = R.Context(0)
-    for dA, k in zip(dms, ks):
-        R.tune_set(dA, k, 8, 1, ctx=ctx)
-    outs = R.batch(dms, ks, ctx=ctx)
-    for o, b in zip(outs, base):
-        assert same(o, b)
+    # schedule 3 on every matrix: grouped tiles and one round workgroup per CU; schedule 2
+    # on some matrices only: the batch keeps the shared launch shape
+    for scheds in ((3, 3, 3), (2, 0, 1)):
+        ctx = R.Context(0)
+        for dA, k, sc in zip(dms, ks, scheds):
+            R.tune_set(dA, k, 8, sc, ctx=ctx)
+        outs = R.batch(dms, ks, ctx=ctx)
+        for o, b in zip(outs, base):
+            assert same(o, b), scheds
+    with pytest.raises(R.RankyError):
+        R.tune_set(dms[0], ks[0], 8, 4, ctx=R.Context(0))
