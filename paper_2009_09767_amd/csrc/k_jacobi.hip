@@ -14,7 +14,11 @@
 // ONE launch of k_jround:
 //   * workgroups [0, npairs) solve the round's 32 x 32 subproblems S = M_r[s, s]
 //     (s = the pair's two blocks) with one cyclic Jacobi sweep in LDS and write the
-//     rotation J (32 x 32) and the rotated S.  The diagonal blocks of S are the
+//     rotation J (32 x 32) and the rotated S.  The sweep is full (all 496 pairs, 31
+//     steps) in about every quarter of the rounds, round 0 included, and covers only
+//     the 256 pairs joining the two blocks (16 steps) in the others: every pair of
+//     indices is still rotated at least once per sweep of the whole matrix, while the
+//     pairs inside a block are not swept again in every round.  The diagonal blocks of S are the
 //     previous round's rotated subproblems, the off-diagonal block is
 //     J_a^T M_{r-1}[s_a, s_b] J_b, so no workgroup waits for the update.
 //   * the other workgroups apply the previous round, one 32 x 32 tile per wave on the
@@ -39,6 +43,7 @@
 // and 1 rotate the 120 off-diagonal 2 x 2 blocks, wave 2 the 16 diagonal blocks (and
 // records every rotation of the sweep), wave 3 holds one row of J per lane in
 // registers and applies step k's rotations while step k + 1 runs.
+#include <algorithm>
 #include <cstring>
 
 #include "batch.hpp"
@@ -50,7 +55,8 @@ namespace ranky {
 constexpr int kB = 16;           // block of indices
 constexpr int kP = 32;           // subproblem = two blocks
 constexpr int kPS = 33;          // LDS row stride of 32-wide tiles
-constexpr int kSteps = kP - 1;   // steps of one sweep over a subproblem
+constexpr int kSteps = kP - 1;   // steps of a full sweep over a subproblem (all 496 pairs)
+constexpr int kCrossSteps = kB;  // steps of a cross sweep (the 256 pairs joining the two blocks)
 constexpr int kTileWaves = 4;    // update tiles per workgroup (one per wave)
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -102,6 +108,7 @@ struct RoundArgs {
     const int32_t *jstate; // sweeps done / active (device state of this matrix)
     double tol;
     int32_t inner_sweeps;
+    int32_t cross;         // 1: the solve sweeps only the pairs that join the two blocks
     int32_t ntiles_g;      // npairs (npairs + 1) / 2
     int32_t nrowtiles;     // npad / 32
     int32_t sched;         // bit 0: update tiles grouped per XCD (see k_jround); bit 1 is host-side
@@ -123,6 +130,8 @@ __device__ __forceinline__ d4 mfma4(double x, double y, d4 c) {
 
 // position after one step of the in-subproblem round-robin
 __device__ __forceinline__ int turn(int p) { return p == 0 ? 0 : (p == 1 ? kP - 1 : p - 1); }
+// cross sweep: the first block's positions stay, the second block's shift by one
+__device__ __forceinline__ int turn_cross(int p) { return p < kB ? p : kB + ((p - kB + kB - 1) & (kB - 1)); }
 // one-triangle storage of a symmetric 32 x 32 tile
 __device__ __forceinline__ int sym(int a, int b) { return a < b ? a * kPS + b : b * kPS + a; }
 // index that sits at position `seat` after r steps
@@ -166,6 +175,29 @@ __device__ __forceinline__ void jrow_sweep(double (&jr)[kP], const double2 (*tab
         if constexpr (K + 1 < kSteps) {
             __syncthreads();
             jrow_sweep<K + 1>(jr, tab);
+        }
+    }
+}
+
+// Cross sweep: step K pairs index i (first block) with index 16 + (i + K) mod 16.
+template <int K>
+__device__ __forceinline__ void jrow_step_cross(double (&jr)[kP], const double2 *__restrict__ cs) {
+#pragma unroll
+    for (int i = 0; i < kB; ++i) {
+        const int x = i, y = kB + ((i + K) & (kB - 1));
+        const double2 r = cs[i];
+        const double u = jr[x], v = jr[y];
+        jr[x] = r.x * u - r.y * v;
+        jr[y] = r.y * u + r.x * v;
+    }
+}
+template <int K>
+__device__ __forceinline__ void jrow_sweep_cross(double (&jr)[kP], const double2 (*tab)[kP / 2]) {
+    if constexpr (K < kCrossSteps) {
+        jrow_step_cross<K>(jr, tab[K]);
+        if constexpr (K + 1 < kCrossSteps) {
+            __syncthreads();
+            jrow_sweep_cross<K + 1>(jr, tab);
         }
     }
 }
@@ -293,12 +325,13 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
 
     const double tol2 = a.tol * a.tol;
     const double floor_abs = a.sdbl[kSdFloor];
-    // a subproblem whose off-diagonal entries all pass the rotation test is left as is
+    // a subproblem whose entries to be swept all pass the rotation test is left as is
+    const bool cross = a.cross != 0;
     {
         int bad = 0;
         for (int e = tid; e < kP * kP; e += 256) {
             const int x = e >> 5, y = e & 31;
-            if (x < y) {
+            if (x < y && (!cross || (x < kB && y >= kB))) {
                 const double g = S0[x * kPS + y];
                 bad |= fabs(g) > floor_abs && g * g > tol2 * fabs(S0[x * kPS + x] * S0[y * kPS + y]);
             }
@@ -314,9 +347,16 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
         }
     }
 
-    // ---- sweeps ----
+    // ---- sweep ----
+    // A full sweep rotates the 16 pairs at positions (i, 31 - i) in each of 31 steps (all
+    // 496 pairs); a cross sweep rotates (i, 16 + i) in each of 16 steps (the 256 pairs
+    // that join the two blocks).  After every step the positions turn (full: round-robin
+    // of positions 1..31; cross: the second block's positions shift by one), which the
+    // step folds into where it writes.  Every lane works: lanes without a block of their
+    // own repeat another lane's block and write the same values to the same places.
+    const int nsteps = cross ? kCrossSteps : kSteps;
     // rotation lanes: lane & 15 reads pair (rP, rQ) of the step (rP < rQ)
-    const int rP = lane & 15, rQ = kP - 1 - rP;
+    const int rP = lane & 15, rQ = cross ? rP + kB : kP - 1 - rP;
     const int aPP = rP * kPS + rP, aQQ = rQ * kPS + rQ, aPQ = rP * kPS + rQ;
     // off-diagonal block (bi < bj) of waves 0-1; diagonal block rP of wave 2
     int bi = 0, bj = 1;
@@ -329,9 +369,10 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
         bi = i;
         bj = i + 1 + rem;
     }
-    const bool live = wave < 2 ? tid < 120 : lane < 16;
-    const int Pi = wave == 2 ? rP : bi, Qi = kP - 1 - Pi, Pj = bj, Qj = kP - 1 - bj;
-    const int tPi = turn(Pi), tQi = turn(Qi), tPj = turn(Pj), tQj = turn(Qj);
+    const int Pi = wave == 2 ? rP : bi, Pj = bj;
+    const int Qi = cross ? Pi + kB : kP - 1 - Pi, Qj = cross ? Pj + kB : kP - 1 - Pj;
+    const int tPi = cross ? turn_cross(Pi) : turn(Pi), tQi = cross ? turn_cross(Qi) : turn(Qi);
+    const int tPj = cross ? turn_cross(Pj) : turn(Pj), tQj = cross ? turn_cross(Qj) : turn(Qj);
     const int b00 = sym(Pi, Pj), b01 = sym(Pi, Qj), b10 = sym(Qi, Pj), b11 = sym(Qi, Qj);
     const int w00 = sym(tPi, tPj), w01 = sym(tPi, tQj), w10 = sym(tQi, tPj), w11 = sym(tQi, tQj);
     const int dPP = tPi * kPS + tPi, dQQ = tQi * kPS + tQi, dPQ = sym(tPi, tQi);
@@ -339,13 +380,15 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
 #pragma unroll
     for (int c = 0; c < kP; ++c) jr[c] = c == (lane & 31) ? 1.0 : 0.0;
     int rotated = 0;
+    double *Sfin = (nsteps & 1) ? S1 : S0;   // where the sweep leaves S
     for (int sw = 0; sw < a.inner_sweeps; ++sw) {
         int rot = 0;
         if (wave == 3) {
-            __syncthreads();          // end of step 0
-            jrow_sweep<0>(jr, tab);   // the other kSteps - 1 barriers
+            __syncthreads();   // end of step 0; the sweep holds the other nsteps - 1 barriers
+            if (cross) jrow_sweep_cross<0>(jr, tab);
+            else jrow_sweep<0>(jr, tab);
         } else {
-            for (int k = 0; k < kSteps; ++k) {
+            for (int k = 0; k < nsteps; ++k) {
                 const double *__restrict__ Sc = (k & 1) ? S1 : S0;
                 double *__restrict__ Sn = (k & 1) ? S0 : S1;
                 const double app = Sc[aPP], aqq = Sc[aQQ], apq = Sc[aPQ];
@@ -359,25 +402,21 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
                 double c, s, t;
                 const bool act = pair_rotation(app, aqq, apq, tol2, floor_abs, c, s, t);
                 if (wave == 2) {
-                    if (lane < 16) {
-                        rot |= act;
-                        tab[k][lane] = make_double2(c, s);
-                        Sn[dPP] = fma(-t, apq, app);
-                        Sn[dQQ] = fma(t, apq, aqq);
-                        Sn[dPQ] = act ? 0.0 : apq;
-                    }
+                    rot |= act;
+                    tab[k][rP] = make_double2(c, s);
+                    Sn[dPP] = fma(-t, apq, app);
+                    Sn[dQQ] = fma(t, apq, aqq);
+                    Sn[dPQ] = act ? 0.0 : apq;
                 } else {
-                    if (lane < 16) wcs[wave][lane] = make_double2(c, s);
+                    wcs[wave][rP] = make_double2(c, s);
                     wave_fence();
                     const double2 ri = wcs[wave][bi], rj = wcs[wave][bj];
-                    if (live) {
-                        const double y00 = ri.x * x00 - ri.y * x10, y01 = ri.x * x01 - ri.y * x11;
-                        const double y10 = ri.y * x00 + ri.x * x10, y11 = ri.y * x01 + ri.x * x11;
-                        Sn[w00] = rj.x * y00 - rj.y * y01;
-                        Sn[w01] = rj.y * y00 + rj.x * y01;
-                        Sn[w10] = rj.x * y10 - rj.y * y11;
-                        Sn[w11] = rj.y * y10 + rj.x * y11;
-                    }
+                    const double y00 = ri.x * x00 - ri.y * x10, y01 = ri.x * x01 - ri.y * x11;
+                    const double y10 = ri.y * x00 + ri.x * x10, y11 = ri.y * x01 + ri.x * x11;
+                    Sn[w00] = rj.x * y00 - rj.y * y01;
+                    Sn[w01] = rj.y * y00 + rj.x * y01;
+                    Sn[w10] = rj.x * y10 - rj.y * y11;
+                    Sn[w11] = rj.y * y10 + rj.x * y11;
                 }
                 __syncthreads();
             }
@@ -386,13 +425,15 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
         rotated |= rot;
         if (!rot || sw + 1 == a.inner_sweeps) break;
         // another sweep (single-pair matrices): start again from S0
-        for (int e = tid; e < kP * kPS; e += 256) S0[e] = S1[e];
-        __syncthreads();
+        if (Sfin != S0) {
+            for (int e = tid; e < kP * kPS; e += 256) S0[e] = Sfin[e];
+            __syncthreads();
+        }
     }
-    // after an odd number of steps the matrix is in S1, positions = indices again
+    // positions are the indices again
     for (int e = tid; e < kP * kP; e += 256) {
         const int x = e >> 5, y = e & 31;
-        a.Scur[(int64_t)pair * kP * kP + e] = S1[sym(x, y)];
+        a.Scur[(int64_t)pair * kP * kP + e] = Sfin[sym(x, y)];
     }
     if (wave == 3 && lane < kP) {
         double *dst = a.Jcur + (int64_t)pair * kP * kP + lane * kP;
@@ -547,7 +588,7 @@ __device__ __forceinline__ void update_tile(const RoundArgs &a, int u, double *b
 
 // `one` holds the arguments when the launch covers a single matrix (count == 1), so
 // they arrive with the launch; a batch reads them from `table`.
-__global__ __launch_bounds__(256) void k_jround(const RoundArgs one, const RoundArgs *__restrict__ table,
+__global__ __launch_bounds__(256, 2) void k_jround(const RoundArgs one, const RoundArgs *__restrict__ table,
                                                 const int32_t *__restrict__ wp, int count, int32_t launch_r) {
     __shared__ __align__(16) double smem[kSmemDoubles];
     const int mat = count == 1 ? 0 : find_mat(wp, count, blockIdx.x);
@@ -770,6 +811,9 @@ void fill_round_args(void *dst, const MatDesc &d, int32_t r, int32_t inner_sweep
     a.jstate = d.jstate;
     a.tol = d.jtol > 0.0 ? d.jtol : fmax(1e-15, sqrt((double)d.n) * 2.220446049250313e-16);
     a.inner_sweeps = npairs == 1 ? 40 : inner_sweeps;
+    // a full subproblem sweep in about every quarter of the rounds (round 0 included, so
+    // every pair inside a block is rotated once per sweep), cross sweeps in the others
+    a.cross = npairs > 1 && r % std::max(1, (nb - 1) / 4) != 0;
     a.ntiles_g = npairs * (npairs + 1) / 2;
     a.nrowtiles = d.npad / kP;
     a.sched = d.jsched;
