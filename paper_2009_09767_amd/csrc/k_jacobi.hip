@@ -496,6 +496,23 @@ __device__ __forceinline__ void lds_to_acc(const double *__restrict__ A, d4 (&ac
             for (int i = 0; i < 4; ++i) acc[rb][cb][i] = A[(16 * rb + (l >> 4) + 4 * i) * kPS + 16 * cb + (l & 15)];
 }
 
+// A 32 x 32 tile whose row x starts at rows[x] and whose columns are gidx(., Pb, Qb),
+// staged in LDS (stride kPS) by one wave: all eight 16-byte loads of a lane are issued
+// before the first LDS store, so the tile costs one memory round trip.
+__device__ __forceinline__ void tile_to_lds(const double *__restrict__ base, const int64_t (&rows)[8], int Pb, int Qb,
+                                            double *buf, int l) {
+    const int y = 2 * (l & 15), col = gidx(y, Pb, Qb);
+    double2 v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = *reinterpret_cast<const double2 *>(base + rows[j] + col);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int x = (l >> 4) + 4 * j;
+        buf[x * kPS + y] = v[j].x;
+        buf[x * kPS + y + 1] = v[j].y;
+    }
+}
+
 __device__ __forceinline__ void update_tile(const RoundArgs &a, int u, double *buf) {
     const int l = threadIdx.x & 63;
     const int npairs = a.nb / 2;
@@ -510,15 +527,26 @@ __device__ __forceinline__ void update_tile(const RoundArgs &a, int u, double *b
         tournament_pair(a.nb, a.round_prev, ia, Pa, Qa);
         tournament_pair(a.nb, a.round_prev, ib, Pb, Qb);
         if (ia == ib) {
-            const double *s = a.Sprev + (int64_t)ia * kP * kP;
-            for (int e = l; e < kP * kP; e += 64)
-                __builtin_nontemporal_store(s[e], &a.Gout[(int64_t)gidx(e >> 5, Pa, Qa) * a.ld + gidx(e & 31, Pa, Qa)]);
+            // diagonal tile: the rotated subproblem itself (loads first, then the stores)
+            const double2 *s = reinterpret_cast<const double2 *>(a.Sprev + (int64_t)ia * kP * kP);
+            double2 v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = s[l + 64 * j];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int e = 2 * (l + 64 * j), x = e >> 5, y = e & 31;
+                double *d = &a.Gout[(int64_t)gidx(x, Pa, Qa) * a.ld + gidx(y, Pa, Qa)];
+                __builtin_nontemporal_store(v[j].x, d);
+                __builtin_nontemporal_store(v[j].y, d + 1);
+            }
             return;
         }
         const bool fa = a.fprev[ia] != 0, fb = a.fprev[ib] != 0;
-        for (int e = l; e < kP * kP; e += 64) {
-            const int x = e >> 5, y = e & 31;
-            buf[x * kPS + y] = a.Gin[(int64_t)gidx(x, Pa, Qa) * a.ld + gidx(y, Pb, Qb)];
+        {
+            int64_t rows[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) rows[j] = (int64_t)gidx((l >> 4) + 4 * j, Pa, Qa) * a.ld;
+            tile_to_lds(a.Gin, rows, Pb, Qb, buf, l);
         }
         wave_fence();
         d4 t[2][2], o[2][2];
@@ -568,9 +596,11 @@ __device__ __forceinline__ void update_tile(const RoundArgs &a, int u, double *b
     if (rt >= a.nrowtiles || !a.fprev[ib]) return;
     int Pb, Qb;
     tournament_pair(a.nb, a.round_prev, ib, Pb, Qb);
-    for (int e = l; e < kP * kP; e += 64) {
-        const int x = e >> 5, y = e & 31;
-        buf[x * kPS + y] = a.W[(int64_t)(rt * kP + x) * a.ld + gidx(y, Pb, Qb)];
+    {
+        int64_t rows[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) rows[j] = (int64_t)(rt * kP + (l >> 4) + 4 * j) * a.ld;
+        tile_to_lds(a.W, rows, Pb, Qb, buf, l);
     }
     wave_fence();
     d4 t[2][2];
