@@ -41,7 +41,7 @@ def parse():
 # runs (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, averaged over the launches that did work),
 # each scaled by what the same counter reads back for a plain device copy of 1 GiB (x2.0 for
 # FETCH_SIZE, x1.0 for WRITE_SIZE).  Valid only for the kernel source it was taken on.
-JROUND_TRAFFIC = {"bytes": (6574.03 * 2.0 + 15190.33) * 1024, "source_sha256": "05b7b9ac2d54cc349a8f83cfa6b96e18c5ec6de8f2f1daf6a720990012ee9832"}
+JROUND_TRAFFIC = {"bytes": (6777.58 * 2.0 + 15467.44) * 1024, "source_sha256": "719eafec5f5ef0e48707d7cab4bafc5e526512af16fa5c30d7a00e88bb7f292b"}
 
 
 def jround_traffic():
@@ -59,16 +59,20 @@ def jround_flops(n):
     Update (rounds 1..nb-1): the P(P-1)/2 off-diagonal 32 x 32 tiles of G take two 32^3
     products (J_a^T G_ab J_b, the mirror tile is a copy), the npad/32 x P tiles of W one
     (W J): 2 * 32^3 flops per product.  Solve (rounds 0..nb-2), per subproblem: the build
-    (32 x 32 x 16 and 16 x 32 x 16 products) and 31 steps of 120 off-diagonal 2 x 2 two-sided
-    rotations (24 flops), 16 diagonal ones (12), 16 x 32 J-row rotations (6) and 16 rotation
-    angles (about 20)."""
+    (32 x 32 x 16 and 16 x 32 x 16 products) and the steps of the subproblem sweep, 31 in
+    the full rounds (every max(1, (nb-1) // 4)-th round from round 0) and 16 (cross pairs
+    only) in the others; a step is 120 off-diagonal 2 x 2 two-sided rotations (24 flops),
+    16 diagonal ones (12), 16 x 32 J-row rotations (6) and 16 rotation angles (about 20)."""
     npad = 32 * ((n + 31) // 32)
     P = npad // 32
     nb = 2 * P
     gemm = 2 * 32 ** 3
     upd = (P * (P - 1) // 2) * 2 * gemm + (npad // 32) * P * gemm
-    solve = P * (2 * 32 * 32 * 16 + 2 * 16 * 32 * 16 + 31 * (120 * 24 + 16 * 12 + 16 * 32 * 6 + 16 * 20))
-    return (nb - 1) * (upd + solve) / nb
+    build = 2 * 32 * 32 * 16 + 2 * 16 * 32 * 16
+    step = 120 * 24 + 16 * 12 + 16 * 32 * 6 + 16 * 20
+    period = max(1, (nb - 1) // 4)
+    solve = sum(P * (build + (31 if r % period == 0 else 16) * step) for r in range(nb - 1))
+    return ((nb - 1) * upd + solve) / nb
 
 
 def copy_calibration(gib):
