@@ -339,8 +339,8 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
         if (__syncthreads_or(bad) == 0) {
             for (int e = tid; e < kP * kP; e += 256) {
                 const int x = e >> 5, y = e & 31;
-                a.Scur[(int64_t)pair * kP * kP + e] = S0[sym(x, y)];
-                a.Jcur[(int64_t)pair * kP * kP + e] = x == y ? 1.0 : 0.0;
+                __builtin_nontemporal_store(S0[sym(x, y)], &a.Scur[(int64_t)pair * kP * kP + e]);
+                __builtin_nontemporal_store(x == y ? 1.0 : 0.0, &a.Jcur[(int64_t)pair * kP * kP + e]);
             }
             if (tid == 0) a.fcur[pair] = 0;
             return;
@@ -433,12 +433,12 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
     // positions are the indices again
     for (int e = tid; e < kP * kP; e += 256) {
         const int x = e >> 5, y = e & 31;
-        a.Scur[(int64_t)pair * kP * kP + e] = Sfin[sym(x, y)];
+        __builtin_nontemporal_store(Sfin[sym(x, y)], &a.Scur[(int64_t)pair * kP * kP + e]);
     }
     if (wave == 3 && lane < kP) {
         double *dst = a.Jcur + (int64_t)pair * kP * kP + lane * kP;
 #pragma unroll
-        for (int c = 0; c < kP; ++c) dst[c] = jr[c];
+        for (int c = 0; c < kP; ++c) __builtin_nontemporal_store(jr[c], &dst[c]);
     }
     if (tid == 0) a.fcur[pair] = rotated;
 }
@@ -616,15 +616,23 @@ __device__ __forceinline__ void update_tile(const RoundArgs &a, int u, double *b
             }
 }
 
-// `one` holds the arguments when the launch covers a single matrix (count == 1), so
-// they arrive with the launch; a batch reads them from `table`.
+// kOne: the launch covers a single matrix whose arguments arrive by value in `one`
+// (no dependent load before the round's own loads); otherwise a batch reads them from
+// `table` (`one` unused).
+template <bool kOne>
 __global__ __launch_bounds__(256, 2) void k_jround(const RoundArgs one, const RoundArgs *__restrict__ table,
-                                                const int32_t *__restrict__ wp, int count, int32_t launch_r) {
+                                                   const int32_t *__restrict__ wp, int count, int32_t launch_r) {
     __shared__ __align__(16) double smem[kSmemDoubles];
-    const int mat = count == 1 ? 0 : find_mat(wp, count, blockIdx.x);
-    RoundArgs a = count == 1 ? one : table[mat];
+    RoundArgs a;
+    int b = (int)blockIdx.x;
+    if constexpr (kOne) {
+        a = one;
+    } else {
+        const int mat = find_mat(wp, count, blockIdx.x);
+        a = table[mat];
+        b -= wp[mat];
+    }
     const int npairs = a.nb / 2;
-    int b = count == 1 ? (int)blockIdx.x : (int)blockIdx.x - wp[mat];
     if (a.do_solve) {
         if (b < npairs) {
             solve_pair(a, b, launch_r, smem);
@@ -792,9 +800,14 @@ void launch_jacobi_round(const void *host_table, const void *table, const int32_
                          int32_t launch_r, size_t lds_pad, hipStream_t s) {
     if (nblocks <= 0) return;
     RoundArgs one = {};
-    if (count == 1) one = *static_cast<const RoundArgs *>(host_table);
-    hipLaunchKernelGGL(k_jround, dim3((unsigned)nblocks), dim3(256), lds_pad, s, one,
-                       static_cast<const RoundArgs *>(table), wp, count, launch_r);
+    if (count == 1) {
+        one = *static_cast<const RoundArgs *>(host_table);
+        hipLaunchKernelGGL(k_jround<true>, dim3((unsigned)nblocks), dim3(256), lds_pad, s, one,
+                           static_cast<const RoundArgs *>(table), wp, count, launch_r);
+    } else {
+        hipLaunchKernelGGL(k_jround<false>, dim3((unsigned)nblocks), dim3(256), lds_pad, s, one,
+                           static_cast<const RoundArgs *>(table), wp, count, launch_r);
+    }
 }
 
 size_t jround_solo_pad(size_t lds_per_cu) {
