@@ -131,76 +131,110 @@ __global__ __launch_bounds__(256) void k_gather_u(const MatDesc *__restrict__ de
 
 // V[j][i] = (sum over the nonzeros a_mj of column j of a_mj U[m][i]) / sigma[i] for
 // i < rank, else 0.  A wave handles one column at a time, over a contiguous run of
-// columns; a lane owns two consecutive outputs i, so a wave covers 128 outputs per pass
-// with 16-byte U loads.  The column's nonzeros are read once per pass; U rows come
-// from L2, and V goes out with non-temporal stores so it does not evict them.
-template <typename TV, typename TO>
+// columns; a lane owns P pairs of outputs, i = i0 + 128 p + 2 lane (P = 1 for k <= 128,
+// 2 for k <= 256, 4 above: one pass over the columns covers k <= 512), so every load of
+// a U row and every store of a V row is one contiguous 1 KB per wave, and the column's
+// dependent chain (bounds -> row index -> U row) is walked once per pass.  The column's
+// nonzeros are taken four (P = 1) or two at a time with independent loads; each output
+// adds them in order.  U rows come from L2, and V goes out with non-temporal stores so
+// it does not evict them.
+template <typename TV, typename TO, int P>
 __device__ void backproject_cols(const int32_t *__restrict__ colptr, const int32_t *__restrict__ rowidx,
                                  const TV *__restrict__ vals, int64_t N, int32_t k, const double *__restrict__ U,
                                  const double *__restrict__ sigma, int32_t rank, TO *__restrict__ V, int64_t wave,
                                  int64_t nwaves) {
+    constexpr int kNz = P == 1 ? 4 : 2;
     const int lane = threadIdx.x & 63;
-    for (int32_t i0 = 0; i0 < k; i0 += 128) {
-        const int32_t i = i0 + 2 * lane;
-        const bool ok0 = i < k, ok1 = i + 1 < k;
-        const double s0 = (ok0 && i < rank) ? sigma[i] : 0.0;
-        const double s1 = (ok1 && i + 1 < rank) ? sigma[i + 1] : 0.0;
-        const bool live0 = ok0 && i < rank, live1 = ok1 && i + 1 < rank;
+    for (int32_t i0 = 0; i0 < k; i0 += 128 * P) {
+        int32_t i[P];
+        bool ok0[P], ok1[P], live0[P], live1[P];
+        double s0[P], s1[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            i[p] = i0 + 128 * p + 2 * lane;
+            ok0[p] = i[p] < k;
+            ok1[p] = i[p] + 1 < k;
+            live0[p] = ok0[p] && i[p] < rank;
+            live1[p] = ok1[p] && i[p] + 1 < rank;
+            s0[p] = live0[p] ? sigma[i[p]] : 0.0;
+            s1[p] = live1[p] ? sigma[i[p] + 1] : 0.0;
+        }
         // a contiguous run of columns per wave: each line of colptr / rowidx / values is
         // then read by one wave, hence one XCD's L2 (a stride would pull it into all of them)
         const int64_t per = (N + nwaves - 1) / nwaves;
         const int64_t jb = wave * per, je = jb + per < N ? jb + per : N;
         for (int64_t j = jb; j < je; ++j) {
             const int32_t e0 = colptr[j], e1 = colptr[j + 1];
-            double a0 = 0.0, a1 = 0.0;
-            int32_t e = e0;
-            // four nonzeros per step with independent loads (their U rows in flight together)
-            for (; e + 4 <= e1; e += 4) {
-                double av[4];
-                const double *Um[4];
+            double a0[P], a1[P];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
+            for (int p = 0; p < P; ++p) a0[p] = a1[p] = 0.0;
+            int32_t e = e0;
+            // kNz nonzeros per step with independent loads (their U rows in flight together)
+            for (; e + kNz <= e1; e += kNz) {
+                double av[kNz];
+                const double *Um[kNz];
+#pragma unroll
+                for (int t = 0; t < kNz; ++t) {
                     av[t] = static_cast<double>(vals[e + t]);
-                    Um[t] = U + (int64_t)rowidx[e + t] * k + i;
+                    Um[t] = U + (int64_t)rowidx[e + t] * k;
                 }
-                if (ok1) {
-                    a0 = fma(av[3], Um[3][0], fma(av[2], Um[2][0], fma(av[1], Um[1][0], fma(av[0], Um[0][0], a0))));
-                    a1 = fma(av[3], Um[3][1], fma(av[2], Um[2][1], fma(av[1], Um[1][1], fma(av[0], Um[0][1], a1))));
-                } else if (ok0) {
-                    a0 = fma(av[3], Um[3][0], fma(av[2], Um[2][0], fma(av[1], Um[1][0], fma(av[0], Um[0][0], a0))));
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    if (ok1[p]) {
+                        double x = a0[p], y = a1[p];
+#pragma unroll
+                        for (int t = 0; t < kNz; ++t) {
+                            x = fma(av[t], Um[t][i[p]], x);
+                            y = fma(av[t], Um[t][i[p] + 1], y);
+                        }
+                        a0[p] = x;
+                        a1[p] = y;
+                    } else if (ok0[p]) {
+                        double x = a0[p];
+#pragma unroll
+                        for (int t = 0; t < kNz; ++t) x = fma(av[t], Um[t][i[p]], x);
+                        a0[p] = x;
+                    }
                 }
             }
             for (; e < e1; ++e) {
-                const int32_t m = rowidx[e];
                 const double a = static_cast<double>(vals[e]);
-                const double *Um = U + (int64_t)m * k + i;
-                if (ok1) {
-                    a0 = fma(a, Um[0], a0);
-                    a1 = fma(a, Um[1], a1);
-                } else if (ok0) {
-                    a0 = fma(a, Um[0], a0);
+                const double *Um = U + (int64_t)rowidx[e] * k;
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    if (ok1[p]) {
+                        a0[p] = fma(a, Um[i[p]], a0[p]);
+                        a1[p] = fma(a, Um[i[p] + 1], a1[p]);
+                    } else if (ok0[p]) {
+                        a0[p] = fma(a, Um[i[p]], a0[p]);
+                    }
                 }
             }
-            const double v0 = live0 ? a0 / s0 : 0.0;
-            const double v1 = live1 ? a1 / s1 : 0.0;
-            TO *out = V + j * (int64_t)k + i;
-            if (ok1 && (k & 1) == 0) {
-                // one 2-wide store per lane (i is even and k is even, so it is aligned)
-                typedef TO TO2 __attribute__((ext_vector_type(2)));
-                const TO2 w = {static_cast<TO>(v0), static_cast<TO>(v1)};
-                __builtin_nontemporal_store(w, reinterpret_cast<TO2 *>(out));
-            } else if (ok1) {
-                __builtin_nontemporal_store(static_cast<TO>(v0), out);
-                __builtin_nontemporal_store(static_cast<TO>(v1), out + 1);
-            } else if (ok0) {
-                __builtin_nontemporal_store(static_cast<TO>(v0), out);
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const double v0 = live0[p] ? a0[p] / s0[p] : 0.0;
+                const double v1 = live1[p] ? a1[p] / s1[p] : 0.0;
+                TO *out = V + j * (int64_t)k + i[p];
+                if (ok1[p] && (k & 1) == 0) {
+                    // one 2-wide store (i and k are even, so it is aligned)
+                    typedef TO TO2 __attribute__((ext_vector_type(2)));
+                    const TO2 w = {static_cast<TO>(v0), static_cast<TO>(v1)};
+                    __builtin_nontemporal_store(w, reinterpret_cast<TO2 *>(out));
+                } else if (ok1[p]) {
+                    __builtin_nontemporal_store(static_cast<TO>(v0), out);
+                    __builtin_nontemporal_store(static_cast<TO>(v1), out + 1);
+                } else if (ok0[p]) {
+                    __builtin_nontemporal_store(static_cast<TO>(v0), out);
+                }
             }
         }
     }
 }
 
 // Batched back-projection: matrix `mat` owns workgroups [wp[mat], wp[mat+1]) and its
-// waves stride over its columns.
+// waves take contiguous runs of its columns.  One launch per number P of output pairs
+// per lane; the matrices of other widths own no workgroups in it.
+template <int P>
 __global__ __launch_bounds__(256) void k_backproject(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
                                                      int count) {
     const int mat = find_mat(wp, count, blockIdx.x);
@@ -211,24 +245,24 @@ __global__ __launch_bounds__(256) void k_backproject(const MatDesc *__restrict__
     if (d.dtype == 1) {
         const double *v = static_cast<const double *>(d.values);
         if (d.v_dtype == 1)
-            backproject_cols<double, double>(d.colptr, d.rowidx, v, d.N, d.k, d.U, d.sigma, rank,
-                                             static_cast<double *>(d.V), wave, nwaves);
+            backproject_cols<double, double, P>(d.colptr, d.rowidx, v, d.N, d.k, d.U, d.sigma, rank,
+                                                  static_cast<double *>(d.V), wave, nwaves);
         else
-            backproject_cols<double, float>(d.colptr, d.rowidx, v, d.N, d.k, d.U, d.sigma, rank,
-                                            static_cast<float *>(d.V), wave, nwaves);
+            backproject_cols<double, float, P>(d.colptr, d.rowidx, v, d.N, d.k, d.U, d.sigma, rank,
+                                                 static_cast<float *>(d.V), wave, nwaves);
     } else {
         const float *v = static_cast<const float *>(d.values);
         if (d.v_dtype == 1)
-            backproject_cols<float, double>(d.colptr, d.rowidx, v, d.N, d.k, d.U, d.sigma, rank,
-                                            static_cast<double *>(d.V), wave, nwaves);
+            backproject_cols<float, double, P>(d.colptr, d.rowidx, v, d.N, d.k, d.U, d.sigma, rank,
+                                                 static_cast<double *>(d.V), wave, nwaves);
         else
-            backproject_cols<float, float>(d.colptr, d.rowidx, v, d.N, d.k, d.U, d.sigma, rank,
-                                           static_cast<float *>(d.V), wave, nwaves);
+            backproject_cols<float, float, P>(d.colptr, d.rowidx, v, d.N, d.k, d.U, d.sigma, rank,
+                                                static_cast<float *>(d.V), wave, nwaves);
     }
 }
 
 // Stand-alone back-projection with an explicit device rank (step call).
-template <typename TV, typename TO>
+template <typename TV, typename TO, int P>
 __global__ __launch_bounds__(256) void k_backproject_one(const int32_t *__restrict__ colptr,
                                                          const int32_t *__restrict__ rowidx,
                                                          const TV *__restrict__ vals, int64_t N, int32_t k,
@@ -237,7 +271,7 @@ __global__ __launch_bounds__(256) void k_backproject_one(const int32_t *__restri
                                                          const int32_t *__restrict__ rank_ptr, TO *__restrict__ V) {
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    backproject_cols<TV, TO>(colptr, rowidx, vals, N, k, U, sigma, *rank_ptr, V, wave, nwaves);
+    backproject_cols<TV, TO, P>(colptr, rowidx, vals, N, k, U, sigma, *rank_ptr, V, wave, nwaves);
 }
 
 // ---------------------------------------------------------------------------
@@ -262,31 +296,45 @@ int64_t backproject_blocks(int64_t N, int32_t cu_count, int32_t per_cu) {
     return blocks;
 }
 
-void launch_backproject_batch(const MatDesc *descs, const int32_t *wp, int64_t nblocks, int count, hipStream_t s) {
+void launch_backproject_batch(const MatDesc *descs, const int32_t *wp, int64_t nblocks, int count, int32_t pairs,
+                              hipStream_t s) {
     if (nblocks <= 0) return;
-    hipLaunchKernelGGL(k_backproject, dim3((unsigned)nblocks), dim3(256), 0, s, descs, wp, count);
+    const dim3 grid((unsigned)nblocks), block(256);
+    if (pairs == 4) hipLaunchKernelGGL(k_backproject<4>, grid, block, 0, s, descs, wp, count);
+    else if (pairs == 2) hipLaunchKernelGGL(k_backproject<2>, grid, block, 0, s, descs, wp, count);
+    else hipLaunchKernelGGL(k_backproject<1>, grid, block, 0, s, descs, wp, count);
+}
+
+template <int P>
+static void launch_one(const CscView &A, int64_t N, int32_t k, const double *U, const double *sigma,
+                       const int32_t *rank, void *V, int32_t v_dtype, dim3 grid, hipStream_t s) {
+    const dim3 block(256);
+    if (A.dtype == 1) {
+        const double *v = static_cast<const double *>(A.values);
+        if (v_dtype == 1)
+            hipLaunchKernelGGL((k_backproject_one<double, double, P>), grid, block, 0, s, A.colptr, A.rowidx, v, N,
+                               k, U, sigma, rank, static_cast<double *>(V));
+        else
+            hipLaunchKernelGGL((k_backproject_one<double, float, P>), grid, block, 0, s, A.colptr, A.rowidx, v, N,
+                               k, U, sigma, rank, static_cast<float *>(V));
+    } else {
+        const float *v = static_cast<const float *>(A.values);
+        if (v_dtype == 1)
+            hipLaunchKernelGGL((k_backproject_one<float, double, P>), grid, block, 0, s, A.colptr, A.rowidx, v, N,
+                               k, U, sigma, rank, static_cast<double *>(V));
+        else
+            hipLaunchKernelGGL((k_backproject_one<float, float, P>), grid, block, 0, s, A.colptr, A.rowidx, v, N,
+                               k, U, sigma, rank, static_cast<float *>(V));
+    }
 }
 
 void launch_backproject(const CscView &A, int64_t N, int32_t k, const double *U, const double *sigma,
                         const int32_t *rank, void *V, int32_t v_dtype, int32_t cu_count, hipStream_t s) {
-    const dim3 grid((unsigned)backproject_blocks(N, cu_count)), block(256);
-    if (A.dtype == 1) {
-        const double *v = static_cast<const double *>(A.values);
-        if (v_dtype == 1)
-            hipLaunchKernelGGL((k_backproject_one<double, double>), grid, block, 0, s, A.colptr, A.rowidx, v, N, k, U,
-                               sigma, rank, static_cast<double *>(V));
-        else
-            hipLaunchKernelGGL((k_backproject_one<double, float>), grid, block, 0, s, A.colptr, A.rowidx, v, N, k, U,
-                               sigma, rank, static_cast<float *>(V));
-    } else {
-        const float *v = static_cast<const float *>(A.values);
-        if (v_dtype == 1)
-            hipLaunchKernelGGL((k_backproject_one<float, double>), grid, block, 0, s, A.colptr, A.rowidx, v, N, k, U,
-                               sigma, rank, static_cast<double *>(V));
-        else
-            hipLaunchKernelGGL((k_backproject_one<float, float>), grid, block, 0, s, A.colptr, A.rowidx, v, N, k, U,
-                               sigma, rank, static_cast<float *>(V));
-    }
+    const dim3 grid((unsigned)backproject_blocks(N, cu_count));
+    const int32_t pairs = backproject_pairs(k);
+    if (pairs == 4) launch_one<4>(A, N, k, U, sigma, rank, V, v_dtype, grid, s);
+    else if (pairs == 2) launch_one<2>(A, N, k, U, sigma, rank, V, v_dtype, grid, s);
+    else launch_one<1>(A, N, k, U, sigma, rank, V, v_dtype, grid, s);
 }
 
 hipError_t select_set_attributes() {

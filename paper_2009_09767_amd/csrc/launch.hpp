@@ -63,7 +63,10 @@ void launch_jacobi_diag(const MatDesc *descs, const int32_t *wp, int64_t nblocks
 void launch_select(const MatDesc *descs, int count, int32_t max_n, hipStream_t s);
 void launch_gather_u(const MatDesc *descs, const int32_t *wp, int64_t nblocks, int count, hipStream_t s);
 int64_t backproject_blocks(int64_t N, int32_t cu_count, int32_t per_cu = 32);
-void launch_backproject_batch(const MatDesc *descs, const int32_t *wp, int64_t nblocks, int count, hipStream_t s);
+// output pairs per lane of the back-projection for k outputs per column (one pass for k <= 512)
+inline int32_t backproject_pairs(int32_t k) { return k <= 128 ? 1 : (k <= 256 ? 2 : 4); }
+void launch_backproject_batch(const MatDesc *descs, const int32_t *wp, int64_t nblocks, int count, int32_t pairs,
+                              hipStream_t s);
 void launch_backproject(const CscView &A, int64_t N, int32_t k, const double *U, const double *sigma,
                         const int32_t *rank, void *V, int32_t v_dtype, int32_t cu_count, hipStream_t s);
 hipError_t select_set_attributes();

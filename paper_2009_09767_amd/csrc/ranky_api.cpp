@@ -201,7 +201,8 @@ MatDesc carve(const Plan &p, char *base, Refine *rf) {
 // batch header: device descriptor table, workgroup maps, round tables, read-back
 // ---------------------------------------------------------------------------
 
-enum Phase { kPhChunks, kPhRows, kPhGram, kPhGramRed, kPhJinit, kPhJcheck, kPhJdiag, kPhGather, kPhBack, kPhCount };
+// kPhBack, kPhBack2, kPhBack4: back-projection of the matrices with 1, 2, 4 output pairs per lane
+enum Phase { kPhChunks, kPhRows, kPhGram, kPhGramRed, kPhJinit, kPhJcheck, kPhJdiag, kPhGather, kPhBack, kPhBack2, kPhBack4, kPhCount };
 
 struct Header {
     size_t o_desc = 0, o_wp = 0, o_rwp = 0, o_rtab = 0, o_col_i = 0, o_col_f = 0, total = 0;
@@ -403,11 +404,11 @@ struct Engine {
         nblk[kPhGather] = fill_wp(hwp(kPhGather), count, [&](int i) { return status[i] == RANKY_OK ? (int64_t)d[i].k : 0; });
         // back-projection: one matrix gets the tuned grid; a batch shares one grid of that
         // size in proportion to each matrix's V bytes (at least one workgroup each), so the
-        // waves walk longer column runs instead of launching millions of tiny workgroups
+        // waves walk longer column runs instead of launching millions of tiny workgroups.
+        // Each output width (backproject_pairs) has its own launch and workgroup table.
+        std::vector<int64_t> bpb(count, 0);
         if (count == 1) {
-            nblk[kPhBack] = fill_wp(hwp(kPhBack), count, [&](int i) {
-                return status[i] == RANKY_OK ? backproject_blocks(d[i].N, ctx->cu_count, d[i].bp_per_cu) : (int64_t)0;
-            });
+            if (status[0] == RANKY_OK) bpb[0] = backproject_blocks(d[0].N, ctx->cu_count, d[0].bp_per_cu);
         } else {
             double work = 0.0;
             int32_t per_cu = 0;
@@ -417,12 +418,17 @@ struct Engine {
                     per_cu = std::max(per_cu, d[i].bp_per_cu);
                 }
             const double grid = (double)ctx->cu_count * (per_cu > 0 ? per_cu : 32);
-            nblk[kPhBack] = fill_wp(hwp(kPhBack), count, [&](int i) -> int64_t {
-                if (status[i] != RANKY_OK) return 0;
-                const int64_t share = (int64_t)(grid * ((double)d[i].N * d[i].k) / (work > 0.0 ? work : 1.0));
-                return std::max<int64_t>(1, std::min(share, backproject_blocks(d[i].N, ctx->cu_count, d[i].bp_per_cu)));
-            });
+            for (int i = 0; i < count; ++i)
+                if (status[i] == RANKY_OK) {
+                    const int64_t share = (int64_t)(grid * ((double)d[i].N * d[i].k) / (work > 0.0 ? work : 1.0));
+                    bpb[i] = std::max<int64_t>(1, std::min(share, backproject_blocks(d[i].N, ctx->cu_count, d[i].bp_per_cu)));
+                }
         }
+        const int32_t widths[3] = {1, 2, 4};
+        for (int c = 0; c < 3; ++c)
+            nblk[kPhBack + c] = fill_wp(hwp(kPhBack + c), count, [&](int i) -> int64_t {
+                return backproject_pairs(d[i].k) == widths[c] ? bpb[i] : 0;
+            });
         nb_max = 0;
         bool solo = false, all_solo = true;
         for (int i = 0; i < count; ++i)
@@ -690,7 +696,11 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
         if (st) return st;
     }
     if (timing) hipEventRecord(ctx->ev[6], s);
-    if (!refine) launch_backproject_batch(e.ddesc(), e.dwp(kPhBack), e.nblk[kPhBack], count, s);
+    if (!refine) {
+        const int32_t widths[3] = {1, 2, 4};
+        for (int c = 0; c < 3; ++c)
+            launch_backproject_batch(e.ddesc(), e.dwp(kPhBack + c), e.nblk[kPhBack + c], count, widths[c], s);
+    }
     HIP_TRY(hipGetLastError());
     if (timing) hipEventRecord(ctx->ev[7], s);
     st = e.collect(iv, fv);

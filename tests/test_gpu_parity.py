@@ -45,6 +45,10 @@ CASES = {
     "ragged_65": lambda: gen.random_sparse(65, 3000, 0.01, seed=65),
     "ragged_127_f32": lambda: gen.random_sparse(127, 5000, 0.004, seed=127, dtype=np.float32),
     "tiny_3x40": lambda: gen.random_sparse(3, 40, 0.3, seed=3),
+    # back-projection with 4 outputs per lane: odd k (single stores), then k = 256 (the
+    # width's upper bound, paired stores, FP32 values)
+    "wide_201": lambda: gen.random_sparse(201, 4000, 0.01, seed=201),
+    "wide_256_f32": lambda: gen.random_sparse(256, 3000, 0.012, seed=256, dtype=np.float32),
 }
 
 
@@ -163,11 +167,16 @@ def test_eigh_graded_relative_accuracy(R):
 
 
 @pytest.mark.parametrize("vdt", ["f64", "f32"])
-def test_backproject(R, orc, vdt):
+@pytest.mark.parametrize("case", ["cfg1_k48", "wide_k300"])
+def test_backproject(R, orc, vdt, case):
+    """The step call: 2 outputs per lane (k = 48) and 8 (k = 300)."""
     import torch
 
-    A = gen.cfg1()
-    ref = orc.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=48, tol=1e-12, method="whole")
+    if case == "cfg1_k48":
+        A, k, tol, method = gen.cfg1(), 48, 1e-12, "whole"
+    else:
+        A, k, tol, method = gen.random_sparse(300, 2500, 0.02, seed=9), 300, 0.0, "whole_qr"
+    ref = orc.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=k, tol=tol, method=method)
     dA = R.to_device(A)
     V = R.backproject(dA, torch.from_numpy(ref.U).cuda(), torch.from_numpy(ref.sigma).cuda(), ref.rank,
                       v_dtype=torch.float64 if vdt == "f64" else torch.float32).cpu().numpy().astype(np.float64)
