@@ -217,7 +217,7 @@ __device__ __forceinline__ void jrow_sweep_cross(double (&jr)[kP], const double2
 constexpr int kSoS1 = kP * kPS, kSoTab = 2 * kP * kPS, kSoWcs = kSoTab + 2 * kSteps * (kP / 2),
               kSoEnd = kSoWcs + 2 * 2 * (kP / 2);
 constexpr int kSmemDoubles = kTileWaves * kP * kPS;
-static_assert(kSoEnd <= kSmemDoubles, "solve LDS fits the update LDS");
+static_assert(kSoEnd + 2 <= kSmemDoubles, "solve LDS (and the four votes) fits the update LDS");
 static_assert(kB * kB <= 2 * kSteps * (kP / 2), "P_1 fits the table area");
 
 __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t launch_r, double *smem) {
@@ -240,7 +240,42 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
     // registers: the product's result layout is the next product's B layout), and
     // S_PQ = P_0 + P_1.  Waves 2 and 3 bring the diagonal blocks.
     const int32_t active = a.jstate[kJsActive], sweeps = a.jstate[kJsSweeps];
+    const double floor_abs = a.sdbl[kSdFloor];   // loaded with the build, used by the test
     const int l16 = lane & 15, l4 = lane >> 4;
+    // the sweep's fixed indices and J = I, set up while the build's loads are in flight
+    const bool cross = a.cross != 0;
+    // A full sweep rotates the 16 pairs at positions (i, 31 - i) in each of 31 steps (all
+    // 496 pairs); a cross sweep rotates (i, 16 + i) in each of 16 steps (the 256 pairs
+    // that join the two blocks).  After every step the positions turn (full: round-robin
+    // of positions 1..31; cross: the second block's positions shift by one), which the
+    // step folds into where it writes.  Every lane works: lanes without a block of their
+    // own repeat another lane's block and write the same values to the same places.
+    const int nsteps = cross ? kCrossSteps : kSteps;
+    // rotation lanes: lane & 15 reads pair (rP, rQ) of the step (rP < rQ)
+    const int rP = lane & 15, rQ = cross ? rP + kB : kP - 1 - rP;
+    const int aPP = rP * kPS + rP, aQQ = rQ * kPS + rQ, aPQ = rP * kPS + rQ;
+    // off-diagonal block (bi < bj) of waves 0-1, numbered row by row (row i holds 15 - i
+    // blocks and starts at 15 i - i (i - 1) / 2); diagonal block rP of wave 2
+    int bi = 0, bj = 1;
+    if (wave < 2) {
+        const int b = tid < 120 ? tid : 0;
+        int i = 0;
+#pragma unroll
+        for (int r = 1; r < kB; ++r) i += b >= 15 * r - r * (r - 1) / 2 ? 1 : 0;
+        bi = i;
+        bj = i + 1 + (b - (15 * i - i * (i - 1) / 2));
+    }
+    const int Pi = wave == 2 ? rP : bi, Pj = bj;
+    const int Qi = cross ? Pi + kB : kP - 1 - Pi, Qj = cross ? Pj + kB : kP - 1 - Pj;
+    const int tPi = cross ? turn_cross(Pi) : turn(Pi), tQi = cross ? turn_cross(Qi) : turn(Qi);
+    const int tPj = cross ? turn_cross(Pj) : turn(Pj), tQj = cross ? turn_cross(Qj) : turn(Qj);
+    const int b00 = sym(Pi, Pj), b01 = sym(Pi, Qj), b10 = sym(Qi, Pj), b11 = sym(Qi, Qj);
+    const int w00 = sym(tPi, tPj), w01 = sym(tPi, tQj), w10 = sym(tQi, tPj), w11 = sym(tQi, tQj);
+    const int dPP = tPi * kPS + tPi, dQQ = tQi * kPS + tQi, dPQ = sym(tPi, tQi);
+    double jr[kP];
+#pragma unroll
+    for (int c = 0; c < kP; ++c) jr[c] = c == (lane & 31) ? 1.0 : 0.0;
+    double *Sfin = (nsteps & 1) ? S1 : S0;   // where the sweep leaves S
     double g0[8], g1[8], jb[8], ja[4], dg[4];
     int pp = 0, hp = 0, pq = 0, hq = 0;
     if (!a.has_prev) {
@@ -334,19 +369,37 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
     __syncthreads();
 
     const double tol2 = a.tol * a.tol;
-    const double floor_abs = a.sdbl[kSdFloor];
     // a subproblem whose entries to be swept all pass the rotation test is left as is
-    const bool cross = a.cross != 0;
+    // (a cross sweep's 256 entries one per thread, a full sweep's four candidates per
+    // thread, loads issued at once; one vote per wave, one barrier)
     {
-        int bad = 0;
-        for (int e = tid; e < kP * kP; e += 256) {
-            const int x = e >> 5, y = e & 31;
-            if (x < y && (!cross || (x < kB && y >= kB))) {
-                const double g = S0[x * kPS + y];
-                bad |= fabs(g) > floor_abs && g * g > tol2 * fabs(S0[x * kPS + x] * S0[y * kPS + y]);
+        bool bad = false;
+        if (cross) {
+            const int x = tid >> 4, y = kB + (tid & 15);
+            const double g = S0[x * kPS + y], gx = S0[x * kPS + x], gy = S0[y * kPS + y];
+            // `&`, not `&&`: all three loads leave before the first compare
+            bad = (fabs(g) > floor_abs) & (g * g > tol2 * fabs(gx * gy));
+        } else {
+            double g[4], gx[4], gy[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int e = tid + 256 * j, x = e >> 5, y = e & 31;
+                g[j] = S0[sym(x, y)];
+                gx[j] = S0[x * kPS + x];
+                gy[j] = S0[y * kPS + y];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int e = tid + 256 * j, x = e >> 5, y = e & 31;
+                bad |= (x < y) & (fabs(g[j]) > floor_abs) & (g[j] * g[j] > tol2 * fabs(gx[j] * gy[j]));
             }
         }
-        if (__syncthreads_or(bad) == 0) {
+        int32_t *vote = reinterpret_cast<int32_t *>(smem + kSoEnd);
+        const bool wave_bad = __ballot(bad) != 0;
+        if (lane == 0) vote[wave] = wave_bad;
+        __syncthreads();
+        const bool any_bad = (vote[0] | vote[1] | vote[2] | vote[3]) != 0;
+        if (!any_bad) {
             for (int e = tid; e < kP * kP; e += 256) {
                 const int x = e >> 5, y = e & 31;
                 __builtin_nontemporal_store(S0[sym(x, y)], &a.Scur[(int64_t)pair * kP * kP + e]);
@@ -358,39 +411,7 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
     }
 
     // ---- sweep ----
-    // A full sweep rotates the 16 pairs at positions (i, 31 - i) in each of 31 steps (all
-    // 496 pairs); a cross sweep rotates (i, 16 + i) in each of 16 steps (the 256 pairs
-    // that join the two blocks).  After every step the positions turn (full: round-robin
-    // of positions 1..31; cross: the second block's positions shift by one), which the
-    // step folds into where it writes.  Every lane works: lanes without a block of their
-    // own repeat another lane's block and write the same values to the same places.
-    const int nsteps = cross ? kCrossSteps : kSteps;
-    // rotation lanes: lane & 15 reads pair (rP, rQ) of the step (rP < rQ)
-    const int rP = lane & 15, rQ = cross ? rP + kB : kP - 1 - rP;
-    const int aPP = rP * kPS + rP, aQQ = rQ * kPS + rQ, aPQ = rP * kPS + rQ;
-    // off-diagonal block (bi < bj) of waves 0-1; diagonal block rP of wave 2
-    int bi = 0, bj = 1;
-    if (wave < 2) {
-        int rem = tid < 120 ? tid : 0, i = 0;
-        while (rem >= 15 - i) {
-            rem -= 15 - i;
-            ++i;
-        }
-        bi = i;
-        bj = i + 1 + rem;
-    }
-    const int Pi = wave == 2 ? rP : bi, Pj = bj;
-    const int Qi = cross ? Pi + kB : kP - 1 - Pi, Qj = cross ? Pj + kB : kP - 1 - Pj;
-    const int tPi = cross ? turn_cross(Pi) : turn(Pi), tQi = cross ? turn_cross(Qi) : turn(Qi);
-    const int tPj = cross ? turn_cross(Pj) : turn(Pj), tQj = cross ? turn_cross(Qj) : turn(Qj);
-    const int b00 = sym(Pi, Pj), b01 = sym(Pi, Qj), b10 = sym(Qi, Pj), b11 = sym(Qi, Qj);
-    const int w00 = sym(tPi, tPj), w01 = sym(tPi, tQj), w10 = sym(tQi, tPj), w11 = sym(tQi, tQj);
-    const int dPP = tPi * kPS + tPi, dQQ = tQi * kPS + tQi, dPQ = sym(tPi, tQi);
-    double jr[kP];
-#pragma unroll
-    for (int c = 0; c < kP; ++c) jr[c] = c == (lane & 31) ? 1.0 : 0.0;
     int rotated = 0;
-    double *Sfin = (nsteps & 1) ? S1 : S0;   // where the sweep leaves S
     for (int sw = 0; sw < a.inner_sweeps; ++sw) {
         int rot = 0;
         if (wave == 3) {
@@ -431,6 +452,12 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
                 __syncthreads();
             }
         }
+        if (a.inner_sweeps == 1) {
+            // only wave 2 records rotations; the other waves need no further barrier (the
+            // last step's barrier published S, and wave 3 finishes J on its own)
+            if (wave == 2) rotated = __ballot(rot != 0) != 0;
+            break;
+        }
         rot = __syncthreads_or(rot);
         rotated |= rot;
         if (!rot || sw + 1 == a.inner_sweeps) break;
@@ -450,7 +477,7 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
 #pragma unroll
         for (int c = 0; c < kP; ++c) __builtin_nontemporal_store(jr[c], &dst[c]);
     }
-    if (tid == 0) a.fcur[pair] = rotated;
+    if (tid == 128) a.fcur[pair] = rotated;   // lane 0 of wave 2 holds the flag
 }
 
 // ---- update of the previous round (FP64 matrix cores) ----------------------
