@@ -419,26 +419,25 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
             if (cross) jrow_sweep_cross<0>(jr, tab);
             else jrow_sweep<0>(jr, tab);
         } else {
+            // each role issues its own loads and computes the rotation in its own branch
+            // (one straight path per wave and step)
             for (int k = 0; k < nsteps; ++k) {
                 const double *__restrict__ Sc = (k & 1) ? S1 : S0;
                 double *__restrict__ Sn = (k & 1) ? S0 : S1;
-                const double app = Sc[aPP], aqq = Sc[aQQ], apq = Sc[aPQ];
-                double x00 = 0.0, x01 = 0.0, x10 = 0.0, x11 = 0.0;
-                if (wave < 2) {
-                    x00 = Sc[b00];
-                    x01 = Sc[b01];
-                    x10 = Sc[b10];
-                    x11 = Sc[b11];
-                }
-                double c, s, t;
-                const bool act = pair_rotation(app, aqq, apq, tol2, floor_abs, c, s, t);
                 if (wave == 2) {
+                    const double app = Sc[aPP], aqq = Sc[aQQ], apq = Sc[aPQ];
+                    double c, s, t;
+                    const bool act = pair_rotation(app, aqq, apq, tol2, floor_abs, c, s, t);
                     rot |= act;
                     tab[k][rP] = make_double2(c, s);
                     Sn[dPP] = fma(-t, apq, app);
                     Sn[dQQ] = fma(t, apq, aqq);
                     Sn[dPQ] = act ? 0.0 : apq;
                 } else {
+                    const double x00 = Sc[b00], x01 = Sc[b01], x10 = Sc[b10], x11 = Sc[b11];
+                    const double app = Sc[aPP], aqq = Sc[aQQ], apq = Sc[aPQ];
+                    double c, s, t;
+                    pair_rotation(app, aqq, apq, tol2, floor_abs, c, s, t);
                     wcs[wave][rP] = make_double2(c, s);
                     wave_fence();
                     const double2 ri = wcs[wave][bi], rj = wcs[wave][bj];
