@@ -169,6 +169,23 @@ ranky_status ranky_svd(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N,
                        const ranky_opts *opts, void *workspace, size_t ws_bytes, double *sigma, double *U,
                        void *V, ranky_info *info, ranky_stream_t stream);
 
+/* Non-blocking ranky_svd: validates the arguments like ranky_svd (its host-checkable
+ * errors are returned here, at once), starts the same computation on a worker thread
+ * of the context and returns RANKY_OK with *ticket (host) set.  A, opts (copied), the
+ * workspace and the outputs must stay valid, and the context unused by other calls,
+ * until ranky_query has returned a status other than RANKY_PENDING for the ticket.
+ * At most one call is in flight per context: E_BUSY otherwise.  The result is the
+ * result of ranky_svd on the same arguments, bit for bit. */
+ranky_status ranky_svd_async(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N, int32_t k, double tol,
+                             const ranky_opts *opts, void *workspace, size_t ws_bytes, double *sigma, double *U,
+                             void *V, ranky_stream_t stream, uint64_t *ticket);
+
+/* State of an asynchronous call: RANKY_PENDING while it runs; then, once, the status
+ * ranky_svd returned, with *info (host, may be NULL) filled and ranky_last_error() set
+ * on an error.  The ticket is released by that answer: E_INVALID for a ticket that is
+ * unknown, superseded or already answered.  Non-blocking. */
+ranky_status ranky_query(ranky_ctx *ctx, uint64_t ticket, ranky_info *info);
+
 /* ------------------------------------------------------------------------- */
 /* Autotuner                                                                  */
 /* ------------------------------------------------------------------------- */

@@ -11,7 +11,11 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <map>
+#include <mutex>
+#include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -39,6 +43,14 @@ struct ranky_ctx {
     hipGraphExec_t sweep_graph = nullptr;  // captured Jacobi sweep of the last graph batch
     const void *sweep_graph_key = nullptr;
     size_t sweep_graph_sig = 0;
+    // ranky_svd_async: at most one call in flight per context, run on `worker`
+    std::mutex amu;
+    std::thread worker;
+    uint64_t aticket = 0;    // ticket of the last call started
+    int astate = 0;          // 0 idle (or result handed over), 1 running, 2 finished, not yet queried
+    ranky_status aresult = RANKY_OK;
+    ranky_info ainfo = {};
+    std::string aerr;
 };
 
 namespace {
@@ -870,6 +882,7 @@ ranky_status ranky_ctx_create(int device, ranky_ctx **out) {
 
 ranky_status ranky_ctx_destroy(ranky_ctx *ctx) {
     if (!ctx) return RANKY_OK;
+    if (ctx->worker.joinable()) ctx->worker.join();   // an async call still running finishes first
     for (auto &ev : ctx->ev)
         if (ev) hipEventDestroy(ev);
     if (ctx->sweep_graph) hipGraphExecDestroy(ctx->sweep_graph);
@@ -916,6 +929,52 @@ ranky_status ranky_svd(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N,
     if (hipSetDevice(ctx->device) != hipSuccess) return finish(fail(RANKY_E_DEVICE, "hipSetDevice"));
     return finish(run_path(ctx, {j}, tol, o, workspace, ws_bytes, inf, reinterpret_cast<hipStream_t>(stream),
                            o.reserved == 1));
+}
+
+ranky_status ranky_svd_async(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N, int32_t k, double tol,
+                             const ranky_opts *opts, void *workspace, size_t ws_bytes, double *sigma, double *U,
+                             void *V, ranky_stream_t stream, uint64_t *ticket) {
+    if (!ctx || !ticket) return fail(RANKY_E_INVALID, "ctx or ticket is NULL");
+    // the host-checkable errors of ranky_svd, at once
+    if (!(tol >= 0.0)) return fail(RANKY_E_INVALID, "tol must be >= 0");
+    if (!sigma || !U || !V) return fail(RANKY_E_INVALID, "NULL output");
+    const ranky_opts o = resolved(opts);
+    ranky_status st = check_opts(o);
+    if (st) return st;
+    Job j;
+    st = make_job(A, M, N, k, o.n_blocks, sigma, U, V, &j);
+    if (st) return st;
+    if (o.refine && k > kMaxRefineK) return fail(RANKY_E_INVALID, "refine needs k <= %d", kMaxRefineK);
+    std::lock_guard<std::mutex> lk(ctx->amu);
+    if (ctx->astate != 0) return fail(RANKY_E_BUSY, "an asynchronous call is in flight on this context");
+    if (ctx->worker.joinable()) ctx->worker.join();
+    const ranky_csc a = *A;
+    const uint64_t t = ++ctx->aticket;
+    ctx->astate = 1;
+    ctx->worker = std::thread([ctx, a, M, N, k, tol, o, workspace, ws_bytes, sigma, U, V, stream]() {
+        ranky_info inf;
+        const ranky_status rs = ranky_svd(ctx, &a, M, N, k, tol, &o, workspace, ws_bytes, sigma, U, V, &inf, stream);
+        std::lock_guard<std::mutex> g(ctx->amu);
+        ctx->aresult = rs;
+        ctx->ainfo = inf;
+        ctx->aerr = rs ? ranky_last_error() : "";
+        ctx->astate = 2;
+    });
+    *ticket = t;
+    return RANKY_OK;
+}
+
+ranky_status ranky_query(ranky_ctx *ctx, uint64_t ticket, ranky_info *info) {
+    if (!ctx) return fail(RANKY_E_INVALID, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(ctx->amu);
+    if (ticket == 0 || ticket != ctx->aticket || ctx->astate == 0)
+        return fail(RANKY_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+    if (ctx->astate == 1) return RANKY_PENDING;
+    ctx->worker.join();   // finished: the worker only returns after setting astate
+    ctx->astate = 0;
+    if (info) *info = ctx->ainfo;
+    if (ctx->aresult) return fail(ctx->aresult, "%s", ctx->aerr.c_str());
+    return RANKY_OK;
 }
 
 ranky_status ranky_tune_set(ranky_ctx *ctx, int32_t M, int64_t N, int64_t nnz, int32_t k, ranky_dtype dtype,

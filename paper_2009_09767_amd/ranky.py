@@ -109,6 +109,8 @@ def lib():
         "ranky_version": ([], ctypes.c_char_p),
         "ranky_workspace_bytes": ([i32, i64, i64, i32, P(Opts)], sz),
         "ranky_svd": ([vp, P(Csc), i32, i64, i32, dbl, P(Opts), vp, sz, vp, vp, vp, P(Info), vp], i32),
+        "ranky_svd_async": ([vp, P(Csc), i32, i64, i32, dbl, P(Opts), vp, sz, vp, vp, vp, vp, P(ctypes.c_uint64)], i32),
+        "ranky_query": ([vp, ctypes.c_uint64, P(Info)], i32),
         "ranky_autotune": ([vp, P(Csc), i32, i64, i32, P(Opts), vp, sz, vp, vp, vp, P(TuneReport), vp], i32),
         "ranky_tune_set": ([vp, i32, i64, i64, i32, i32, P(Opts), i32, i32], i32),
         "ranky_batch_workspace_bytes": ([i32, P(BatchItem), P(Opts)], sz),
@@ -267,6 +269,51 @@ def svd(A: DeviceCSC, k: int, tol: float = 0.0, ctx: Context | None = None, out:
     _check(st)
     out.info = info.as_dict()
     return out
+
+
+@dataclass
+class AsyncSVD:
+    """A ranky_svd_async call in flight: its ticket, where the result goes, and the
+    tensors the call reads (kept alive until it finishes)."""
+    ticket: int
+    out: SVDResult
+    ctx: "Context"
+    keep: tuple
+
+
+def svd_async(A: DeviceCSC, k: int, tol: float = 0.0, ctx: Context | None = None, out: SVDResult | None = None,
+              workspace: torch.Tensor | None = None, stream=None, **opt_kw) -> AsyncSVD:
+    """Starts ranky_svd_async and returns at once; `query` tells when the result is in `out`."""
+    ctx = ctx or context(A.colptr.device.index or 0)
+    opts = make_opts(**opt_kw)
+    vdt = torch.float64 if opts.v_dtype == F64 else torch.float32
+    dev = A.colptr.device
+    if out is None:
+        out = SVDResult(torch.empty(k, dtype=torch.float64, device=dev),
+                        torch.empty((A.M, k), dtype=torch.float64, device=dev),
+                        torch.empty((A.N, k), dtype=vdt, device=dev), {})
+    nbytes = workspace_bytes(A.M, A.N, A.nnz, k, opts)
+    if nbytes == 0:
+        raise RankyError(E_INVALID, "invalid sizes for the workspace")
+    ws = workspace if workspace is not None else ctx.workspace(nbytes)
+    csc = A.struct()
+    t = ctypes.c_uint64(0)
+    st = lib().ranky_svd_async(ctx.handle, ctypes.byref(csc), A.M, A.N, k, float(tol), ctypes.byref(opts), _ptr(ws),
+                               ws.numel(), _ptr(out.sigma), _ptr(out.U), _ptr(out.V), _stream(stream), ctypes.byref(t))
+    _check(st)
+    return AsyncSVD(t.value, out, ctx, (A, ws))
+
+
+def query(job: AsyncSVD) -> bool:
+    """False while the call runs; True once it has finished (the result is in job.out and
+    its info in job.out.info); an error of the call raises RankyError."""
+    info = Info()
+    st = lib().ranky_query(job.ctx.handle, job.ticket, ctypes.byref(info))
+    if st == PENDING:
+        return False
+    _check(st)
+    job.out.info = info.as_dict()
+    return True
 
 
 def autotune(A: DeviceCSC, k: int, ctx: Context | None = None, out: SVDResult | None = None,

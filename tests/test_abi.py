@@ -75,6 +75,11 @@ def test_host_checks_return_before_device_work(L):
     assert st == ranky.E_INVALID and info.status == ranky.E_INVALID
     assert L.ranky_last_error()
     assert L.ranky_eigh(0, None, None, None, 0, None, None, 0, None) == ranky.E_INVALID
+    t = ctypes.c_uint64(7)
+    assert L.ranky_svd_async(None, ctypes.byref(csc), 4, 4, 1, 0.0, ctypes.byref(o), None, 0, None, None, None, None,
+                             ctypes.byref(t)) == ranky.E_INVALID
+    assert t.value == 7   # untouched on an error
+    assert L.ranky_query(None, 1, None) == ranky.E_INVALID
     assert L.ranky_eigh_workspace_bytes(0) == 0 and L.ranky_eigh_workspace_bytes(100) > 2 * 128 * 128 * 8
 
 

@@ -1,0 +1,69 @@
+"""ranky_svd_async / ranky_query: the same result as ranky_svd, bit for bit; one call in
+flight per context; errors of the call come back through the query; a ticket is answered
+once."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2009_09767_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_09767_amd import ranky
+
+    ranky.lib()
+    return ranky
+
+
+def wait(R, job, limit=60.0):
+    t0 = time.time()
+    while not R.query(job):
+        assert time.time() - t0 < limit, "asynchronous call did not finish"
+        time.sleep(0.001)
+
+
+def test_async_equals_blocking_call(R):
+    A = gen.cfg2_small()
+    dA = R.to_device(A)
+    k = 32
+    base = R.svd(dA, k, 0.0, ctx=R.Context(0), n_blocks=8)
+    ctx = R.Context(0)
+    job = R.svd_async(dA, k, 0.0, ctx=ctx, n_blocks=8)
+    # a second call on the context while the first one runs is refused, not queued
+    with pytest.raises(R.RankyError) as e:
+        R.svd_async(dA, k, 0.0, ctx=ctx, n_blocks=8)
+    assert e.value.status == R.E_BUSY
+    wait(R, job)
+    assert torch.equal(job.out.sigma, base.sigma) and torch.equal(job.out.U, base.U) and torch.equal(job.out.V, base.V)
+    assert job.out.info["rank"] == base.info["rank"] and job.out.info["sweeps"] == base.info["sweeps"]
+    # the answer releases the ticket
+    with pytest.raises(R.RankyError) as e:
+        R.query(job)
+    assert e.value.status == R.E_INVALID
+    # the context takes the next call
+    job2 = R.svd_async(dA, k, 0.0, ctx=ctx, n_blocks=8)
+    wait(R, job2)
+    assert torch.equal(job2.out.sigma, base.sigma)
+
+
+def test_async_reports_device_errors(R):
+    A = gen.cfg1()
+    bad = R.to_device(A)
+    v = A.values.copy()
+    v[5] = np.inf
+    bad.values = torch.from_numpy(v).cuda()
+    job = R.svd_async(bad, 8, 0.0, ctx=R.Context(0))
+    with pytest.raises(R.RankyError) as e:
+        wait(R, job)
+    assert e.value.status == R.E_NONFINITE
+    # host-checkable errors come back from the call itself
+    with pytest.raises(R.RankyError) as e:
+        R.svd_async(R.to_device(A), A.M + 1, 0.0, ctx=R.Context(0))
+    assert e.value.status == R.E_INVALID
