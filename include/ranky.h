@@ -90,6 +90,12 @@ typedef struct {
     int32_t timing;     /* 1 = fill ranky_info.ms with per-phase times (adds event records) */
     int32_t reserved;   /* 1 = replay the Jacobi sweep as a captured HIP graph (ranky_svd and
                            ranky_batch; needs a non-NULL stream, ignored on the NULL stream) */
+    const int64_t *block_start; /* host, optional: D + 1 column boundaries, block b = columns
+                           [block_start[b], block_start[b+1]); block_start[0] = 0, non-decreasing,
+                           block_start[D] = N, with n_blocks = D >= 1 given (E_INVALID otherwise).
+                           NULL = floor(bN/D).  Read during the call (ranky_svd_async: until the
+                           query answers); ranky_svd, ranky_svd_async and ranky_autotune only
+                           (E_INVALID in ranky_batch and serving, whose matrices differ in N) */
 } ranky_opts;
 
 typedef struct {

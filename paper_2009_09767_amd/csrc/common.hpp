@@ -35,11 +35,12 @@ constexpr int kColI = 10;
 enum : int32_t { kSdTau = 0, kSdSigmaMax = 1, kSdFloor = 2, kSdScale = 3, kSdCount = 8 };
 
 // Column range of chunk c: block b = c / cpb owns columns [floor(bN/D), floor((b+1)N/D)),
-// and its t-th chunk (t = c % cpb) is the t-th run of kChunkCols columns of it.
-__device__ __forceinline__ void chunk_columns(int64_t c, int32_t cpb, int64_t N, int32_t D, int64_t &c0,
-                                              int64_t &c1) {
+// or [bstart[b], bstart[b+1]) when the caller gave the boundaries, and its t-th chunk
+// (t = c % cpb) is the t-th run of kChunkCols columns of it.
+__device__ __forceinline__ void chunk_columns(int64_t c, int32_t cpb, int64_t N, int32_t D,
+                                              const int64_t *__restrict__ bstart, int64_t &c0, int64_t &c1) {
     const int64_t b = c / cpb, t = c % cpb;
-    const int64_t bs = (b * N) / D, be = ((b + 1) * N) / D;
+    const int64_t bs = bstart ? bstart[b] : (b * N) / D, be = bstart ? bstart[b + 1] : ((b + 1) * N) / D;
     c0 = bs + t * kChunkCols;
     c1 = c0 + kChunkCols < be ? c0 + kChunkCols : be;
     if (c0 > c1) c0 = c1;

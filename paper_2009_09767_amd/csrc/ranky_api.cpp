@@ -93,17 +93,25 @@ struct Plan {
     size_t o_gsegp = 0, o_gslot = 0, o_gpart = 0, o_dense = 0;
     size_t o_G = 0, o_G2 = 0, o_W = 0, o_J = 0, o_S = 0, o_jflag = 0, o_lam = 0, o_perm = 0;
     size_t o_U0 = 0, o_part = 0, total = 0;
-    bool solver = false, refine = false;
+    size_t o_bstart = 0;
+    bool solver = false, refine = false, explicit_blocks = false;
 };
 
-Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool solver, bool refine) {
+// bstart (host, may be NULL): the caller's D + 1 block boundaries; the widest block sets
+// the chunks per block, and the boundaries get a device copy in the workspace.
+Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool solver, bool refine,
+               const int64_t *bstart = nullptr) {
     Plan p;
     p.M = M;
     p.N = N;
     p.nnz = nnz;
     p.k = k;
     p.D = D;
-    const int64_t maxw = (N + D - 1) / D;
+    int64_t maxw = (N + D - 1) / D;
+    if (bstart) {
+        maxw = 0;
+        for (int32_t b = 0; b < D; ++b) maxw = std::max<int64_t>(maxw, bstart[b + 1] - bstart[b]);
+    }
     p.cpb = (int32_t)((maxw + kChunkCols - 1) / kChunkCols);
     if (p.cpb < 1) p.cpb = 1;
     p.nchunks = (int64_t)D * p.cpb;
@@ -114,6 +122,8 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool sol
         off = align_up(off + bytes);
         return o;
     };
+    p.explicit_blocks = bstart != nullptr;
+    if (bstart) p.o_bstart = take(sizeof(int64_t) * ((size_t)D + 1));
     const size_t nz = (size_t)(nnz > 0 ? nnz : 1);
     p.o_scal = take(sizeof(int32_t) * kScCount);
     p.o_sdbl = take(sizeof(double) * kSdCount);
@@ -170,6 +180,7 @@ MatDesc carve(const Plan &p, char *base, Refine *rf) {
     d.k = p.k;
     d.D = p.D;
     d.cpb = p.cpb;
+    d.bstart = p.explicit_blocks ? reinterpret_cast<const int64_t *>(base + p.o_bstart) : nullptr;
     d.nchunks = p.nchunks;
     d.npad = kJacobiPair;
     d.scal = i32(p.o_scal);
@@ -282,6 +293,7 @@ ranky_status check_opts(const ranky_opts &o) {
 // One matrix of a job (host view).
 struct Job {
     ranky_csc A;
+    const int64_t *bstart;   // host: the caller's block boundaries, or NULL
     int64_t N;
     int32_t M, k, D;
     double *sigma, *U;
@@ -576,7 +588,7 @@ size_t path_bytes(const std::vector<Job> &jobs, const ranky_opts &o) {
     int32_t maxM = 1;
     size_t total = 0;
     for (const Job &j : jobs) {
-        total += make_plan(j.M, j.N, j.A.nnz, j.k, j.D, true, refine).total;
+        total += make_plan(j.M, j.N, j.A.nnz, j.k, j.D, true, refine, j.bstart).total;
         maxM = std::max(maxM, j.M);
     }
     return total + make_header(count, count, jacobi_npad(maxM) / kJacobiBlock).total;
@@ -590,7 +602,7 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
     std::vector<Plan> plans(count);
     int32_t maxM = 1;
     for (int i = 0; i < count; ++i) {
-        plans[i] = make_plan(jobs[i].M, jobs[i].N, jobs[i].A.nnz, jobs[i].k, jobs[i].D, true, refine);
+        plans[i] = make_plan(jobs[i].M, jobs[i].N, jobs[i].A.nnz, jobs[i].k, jobs[i].D, true, refine, jobs[i].bstart);
         maxM = std::max(maxM, jobs[i].M);
     }
     const Header h = make_header(count, count, jacobi_npad(maxM) / kJacobiBlock);
@@ -614,6 +626,9 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
         const Job &j = jobs[i];
         MatDesc &x = e.d[i];
         x = carve(plans[i], ws + base[i], i == 0 ? &rf : nullptr);
+        if (j.bstart)
+            HIP_TRY(hipMemcpyAsync(const_cast<int64_t *>(x.bstart), j.bstart, sizeof(int64_t) * ((size_t)j.D + 1),
+                                   hipMemcpyHostToDevice, s));
         x.colptr = j.A.colptr;
         x.rowidx = j.A.rowidx;
         x.values = j.A.values;
@@ -755,13 +770,27 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
     return overall;
 }
 
+ranky_status check_block_start(const int64_t *bstart, int32_t D, int64_t N) {
+    if (!bstart) return RANKY_OK;
+    if (D < 1) return fail(RANKY_E_INVALID, "block_start needs n_blocks >= 1");
+    if (bstart[0] != 0 || bstart[D] != N)
+        return fail(RANKY_E_INVALID, "block_start must run from 0 to N=%lld", (long long)N);
+    for (int32_t b = 0; b < D; ++b)
+        if (bstart[b + 1] < bstart[b]) return fail(RANKY_E_INVALID, "block_start decreases at block %d", b);
+    return RANKY_OK;
+}
+
 ranky_status make_job(const ranky_csc *A, int32_t M, int64_t N, int32_t k, int32_t D, double *sigma, double *U,
-                      void *V, Job *out) {
+                      void *V, Job *out, const int64_t *bstart = nullptr) {
     ranky_status st = check_csc_args(A, M, N);
     if (st) return st;
     if (k < 1 || k > M) return fail(RANKY_E_INVALID, "k=%d must be in [1, M=%d]", k, M);
+    if (bstart && D < 1) return fail(RANKY_E_INVALID, "block_start needs n_blocks >= 1");
     if (D == 0) D = default_blocks(N);
     if (D < 1 || D > N) return fail(RANKY_E_INVALID, "n_blocks=%d outside [1, N]", D);
+    st = check_block_start(bstart, D, N);
+    if (st) return st;
+    out->bstart = bstart;
     out->A = *A;
     out->N = N;
     out->M = M;
@@ -894,10 +923,12 @@ ranky_status ranky_ctx_destroy(ranky_ctx *ctx) {
 size_t ranky_workspace_bytes(int32_t M, int64_t N, int64_t nnz, int32_t k, const ranky_opts *opts) {
     if (M < 1 || N < 1 || k < 1 || k > M || M > kMaxM || nnz < 0) return 0;
     const ranky_opts o = resolved(opts);
+    if (o.block_start && o.n_blocks < 1) return 0;
     const int32_t D = o.n_blocks == 0 ? default_blocks(N) : o.n_blocks;
     if (D < 1 || D > N) return 0;
     Job j;
     std::memset(&j, 0, sizeof(j));
+    j.bstart = o.block_start;
     j.A.nnz = nnz;
     j.M = M;
     j.N = N;
@@ -923,7 +954,7 @@ ranky_status ranky_svd(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N,
     ranky_status st = check_opts(o);
     if (st) return finish(st);
     Job j;
-    st = make_job(A, M, N, k, o.n_blocks, sigma, U, V, &j);
+    st = make_job(A, M, N, k, o.n_blocks, sigma, U, V, &j, o.block_start);
     if (st) return finish(st);
     if (o.refine && k > kMaxRefineK) return finish(fail(RANKY_E_INVALID, "refine needs k <= %d", kMaxRefineK));
     if (hipSetDevice(ctx->device) != hipSuccess) return finish(fail(RANKY_E_DEVICE, "hipSetDevice"));
@@ -942,7 +973,7 @@ ranky_status ranky_svd_async(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int6
     ranky_status st = check_opts(o);
     if (st) return st;
     Job j;
-    st = make_job(A, M, N, k, o.n_blocks, sigma, U, V, &j);
+    st = make_job(A, M, N, k, o.n_blocks, sigma, U, V, &j, o.block_start);
     if (st) return st;
     if (o.refine && k > kMaxRefineK) return fail(RANKY_E_INVALID, "refine needs k <= %d", kMaxRefineK);
     std::lock_guard<std::mutex> lk(ctx->amu);
@@ -1001,7 +1032,7 @@ ranky_status ranky_autotune(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64
     ranky_status st = check_opts(o);
     if (st) return st;
     Job j;
-    st = make_job(A, M, N, k, o.n_blocks, sigma, U, V, &j);
+    st = make_job(A, M, N, k, o.n_blocks, sigma, U, V, &j, o.block_start);
     if (st) return st;
     if (o.refine && k > kMaxRefineK) return fail(RANKY_E_INVALID, "refine needs k <= %d", kMaxRefineK);
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(RANKY_E_DEVICE, "hipSetDevice");
@@ -1078,6 +1109,7 @@ size_t ranky_batch_workspace_bytes(int32_t count, const ranky_batch_item *items,
     if (count < 1 || !items) return 0;
     ranky_opts o = resolved(opts);
     o.refine = 0;
+    if (o.block_start) return 0;
     std::vector<Job> jobs(count);
     for (int i = 0; i < count; ++i) {
         const ranky_batch_item &it = items[i];
@@ -1104,6 +1136,7 @@ ranky_status ranky_batch(ranky_ctx *ctx, int32_t count, const ranky_batch_item *
     ranky_status st = check_opts(o);
     if (st) return st;
     if (o.refine) return fail(RANKY_E_INVALID, "ranky_batch runs without refinement (use ranky_svd per matrix)");
+    if (o.block_start) return fail(RANKY_E_INVALID, "block_start is for one matrix (ranky_svd)");
     std::vector<Job> jobs(count);
     for (int i = 0; i < count; ++i) {
         const ranky_batch_item &it = items[i];

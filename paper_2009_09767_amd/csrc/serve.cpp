@@ -226,6 +226,7 @@ ranky_status ranky_serve_create(const ranky_serve_cfg *cfg, ranky_server **out) 
     if (!cfg || !out || !cfg->arena || cfg->arena_bytes == 0 || cfg->max_slots < 1 || cfg->max_queue < 1)
         return RANKY_E_INVALID;
     if (reinterpret_cast<uintptr_t>(cfg->arena) % 256) return RANKY_E_INVALID;   // carved workspaces keep it
+    if (cfg->opts.block_start) return RANKY_E_INVALID;   // requests differ in N: no shared boundaries
     auto *s = new ranky_server();
     s->cfg = *cfg;
     s->arena.reset(cfg->arena_bytes);

@@ -35,7 +35,8 @@ class Csc(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
-                ("n_blocks", "gram_prec", "refine", "max_sweeps", "validate", "v_dtype", "timing", "reserved")]
+                ("n_blocks", "gram_prec", "refine", "max_sweeps", "validate", "v_dtype", "timing", "reserved")] + \
+               [("block_start", ctypes.c_void_p)]
 
 
 class BatchItem(ctypes.Structure):
@@ -221,7 +222,8 @@ def context(device: int = 0) -> Context:
 
 
 def make_opts(n_blocks=0, gram_prec="fp64", refine=None, max_sweeps=0, validate=True, v_dtype=torch.float64,
-              timing=False, graph=False) -> Opts:
+              timing=False, graph=False, block_start=None) -> Opts:
+    """block_start: optional D + 1 column boundaries (host; kept alive by the Opts)."""
     o = Opts()
     _check(lib().ranky_default_opts(ctypes.byref(o)))
     o.n_blocks = n_blocks
@@ -232,6 +234,13 @@ def make_opts(n_blocks=0, gram_prec="fp64", refine=None, max_sweeps=0, validate=
     o.v_dtype = F64 if v_dtype == torch.float64 else F32
     o.timing = int(timing)
     o.reserved = int(graph)
+    if block_start is not None:
+        import numpy as np
+
+        o._block_start = np.ascontiguousarray(np.asarray(block_start, dtype=np.int64))
+        o.block_start = o._block_start.ctypes.data
+        if n_blocks == 0:
+            o.n_blocks = o._block_start.size - 1
     return o
 
 
@@ -301,7 +310,7 @@ def svd_async(A: DeviceCSC, k: int, tol: float = 0.0, ctx: Context | None = None
     st = lib().ranky_svd_async(ctx.handle, ctypes.byref(csc), A.M, A.N, k, float(tol), ctypes.byref(opts), _ptr(ws),
                                ws.numel(), _ptr(out.sigma), _ptr(out.U), _ptr(out.V), _stream(stream), ctypes.byref(t))
     _check(st)
-    return AsyncSVD(t.value, out, ctx, (A, ws))
+    return AsyncSVD(t.value, out, ctx, (A, ws, opts))
 
 
 def query(job: AsyncSVD) -> bool:

@@ -279,6 +279,38 @@ def test_empty_matrix_and_single_row(R):
     assert torch.all(got.U == 1.0)
 
 
+def test_explicit_block_boundaries(R, orc):
+    """opts.block_start: the formula's own boundaries give the default result bit for bit;
+    uneven ones (an empty block included) give the oracle's sigma and U, and the scan's
+    lonely-row statistics for those blocks (counted here from the dense matrix)."""
+    import torch
+
+    A = gen.cfg1()
+    dA = R.to_device(A)
+    D, k = 8, 32
+    base = R.svd(dA, k, 0.0, n_blocks=D)
+    formula = [(b * A.N) // D for b in range(D + 1)]
+    same = R.svd(dA, k, 0.0, n_blocks=D, block_start=formula)
+    assert torch.equal(same.sigma, base.sigma) and torch.equal(same.U, base.U) and torch.equal(same.V, base.V)
+    assert same.info["lonely_max"] == base.info["lonely_max"]
+    bs = [0, 100, 100, 1500, 1501, 3000, A.N]
+    tol = A.meta.get("tol", 0.0)
+    got = R.svd(dA, k, tol, block_start=bs)
+    ref = orc.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=k, tol=tol, method="whole")
+    compare_svd(A, got, ref, k)
+    X = np.zeros((A.M, A.N))
+    for j in range(A.N):
+        X[A.rowidx[A.colptr[j]:A.colptr[j + 1]], j] = 1.0
+    lonely = [int((X[:, bs[b]:bs[b + 1]].sum(axis=1) == 0).sum()) for b in range(len(bs) - 1)]
+    assert got.info["n_blocks"] == len(bs) - 1
+    assert got.info["lonely_max"] == max(lonely)
+    assert got.info["lonely_blocks"] == sum(1 for x in lonely if x > 0)
+    for bad in ([1, 10, A.N], [0, 10, 5, A.N], [0, 10, A.N - 1]):
+        with pytest.raises(R.RankyError) as e:
+            R.svd(dA, 8, 0.0, block_start=bad)
+        assert e.value.status == R.E_INVALID
+
+
 def test_deterministic_and_block_count_invariant(R):
     A = gen.cfg2_small()
     dA = R.to_device(A)
