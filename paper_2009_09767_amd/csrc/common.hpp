@@ -46,6 +46,14 @@ __device__ __forceinline__ void chunk_columns(int64_t c, int32_t cpb, int64_t N,
     if (c0 > c1) c0 = c1;
 }
 
+// Global-memory view of a device pointer the compiler cannot prove global (one read from
+// a descriptor table): its accesses become global loads and stores instead of FLAT ones,
+// which also count against the LDS / scalar wait counter.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gmem(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 template <typename T>
 __device__ __forceinline__ double as_double(T v) {
     return static_cast<double>(v);

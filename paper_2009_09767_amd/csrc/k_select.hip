@@ -139,10 +139,16 @@ __global__ __launch_bounds__(256) void k_gather_u(const MatDesc *__restrict__ de
 // adds them in order.  U rows come from L2, and V goes out with non-temporal stores so
 // it does not evict them.
 template <typename TV, typename TO, int P>
-__device__ void backproject_cols(const int32_t *__restrict__ colptr, const int32_t *__restrict__ rowidx,
-                                 const TV *__restrict__ vals, int64_t N, int32_t k, const double *__restrict__ U,
-                                 const double *__restrict__ sigma, int32_t rank, TO *__restrict__ V, int64_t wave,
+__device__ void backproject_cols(const int32_t *__restrict__ colptr_, const int32_t *__restrict__ rowidx_,
+                                 const TV *__restrict__ vals_, int64_t N, int32_t k, const double *__restrict__ U_,
+                                 const double *__restrict__ sigma_, int32_t rank, TO *__restrict__ V_, int64_t wave,
                                  int64_t nwaves) {
+    const auto colptr = gmem(colptr_);
+    const auto rowidx = gmem(rowidx_);
+    const auto vals = gmem(vals_);
+    const auto U = gmem(U_);
+    const auto sigma = gmem(sigma_);
+    const auto V = gmem(V_);
     constexpr int kNz = P == 1 ? 4 : 2;
     const int lane = threadIdx.x & 63;
     for (int32_t i0 = 0; i0 < k; i0 += 128 * P) {
@@ -172,7 +178,7 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr, const int32
             // kNz nonzeros per step with independent loads (their U rows in flight together)
             for (; e + kNz <= e1; e += kNz) {
                 double av[kNz];
-                const double *Um[kNz];
+                __attribute__((address_space(1))) const double *Um[kNz];
 #pragma unroll
                 for (int t = 0; t < kNz; ++t) {
                     av[t] = static_cast<double>(vals[e + t]);
@@ -199,7 +205,7 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr, const int32
             }
             for (; e < e1; ++e) {
                 const double a = static_cast<double>(vals[e]);
-                const double *Um = U + (int64_t)rowidx[e] * k;
+                const auto Um = U + (int64_t)rowidx[e] * k;
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
                     if (ok1[p]) {
@@ -214,12 +220,12 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr, const int32
             for (int p = 0; p < P; ++p) {
                 const double v0 = live0[p] ? a0[p] / s0[p] : 0.0;
                 const double v1 = live1[p] ? a1[p] / s1[p] : 0.0;
-                TO *out = V + j * (int64_t)k + i[p];
+                const auto out = V + j * (int64_t)k + i[p];
                 if (ok1[p] && (k & 1) == 0) {
                     // one 2-wide store (i and k are even, so it is aligned)
                     typedef TO TO2 __attribute__((ext_vector_type(2)));
                     const TO2 w = {static_cast<TO>(v0), static_cast<TO>(v1)};
-                    __builtin_nontemporal_store(w, reinterpret_cast<TO2 *>(out));
+                    __builtin_nontemporal_store(w, reinterpret_cast<__attribute__((address_space(1))) TO2 *>(out));
                 } else if (ok1[p]) {
                     __builtin_nontemporal_store(static_cast<TO>(v0), out);
                     __builtin_nontemporal_store(static_cast<TO>(v1), out + 1);

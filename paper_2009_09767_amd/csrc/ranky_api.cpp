@@ -434,17 +434,19 @@ struct Engine {
         if (count == 1) {
             if (status[0] == RANKY_OK) bpb[0] = backproject_blocks(d[0].N, ctx->cu_count, d[0].bp_per_cu);
         } else {
-            double work = 0.0;
+            // the width classes run one after the other, so each launch gets the whole grid
+            double work[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
             int32_t per_cu = 0;
             for (int i = 0; i < count; ++i)
                 if (status[i] == RANKY_OK) {
-                    work += (double)d[i].N * d[i].k;
+                    work[backproject_pairs(d[i].k)] += (double)d[i].N * d[i].k;
                     per_cu = std::max(per_cu, d[i].bp_per_cu);
                 }
             const double grid = (double)ctx->cu_count * (per_cu > 0 ? per_cu : 32);
             for (int i = 0; i < count; ++i)
                 if (status[i] == RANKY_OK) {
-                    const int64_t share = (int64_t)(grid * ((double)d[i].N * d[i].k) / (work > 0.0 ? work : 1.0));
+                    const double w = work[backproject_pairs(d[i].k)];
+                    const int64_t share = (int64_t)(grid * ((double)d[i].N * d[i].k) / (w > 0.0 ? w : 1.0));
                     bpb[i] = std::max<int64_t>(1, std::min(share, backproject_blocks(d[i].N, ctx->cu_count, d[i].bp_per_cu)));
                 }
         }
