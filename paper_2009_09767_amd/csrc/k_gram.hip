@@ -41,16 +41,19 @@ __device__ __forceinline__ Acc wave_sum(Acc v) {
 }
 
 template <typename TV, typename Acc>
-__device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals, int32_t i, int32_t seg, int32_t nseg,
+__device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32_t i, int32_t seg, int32_t nseg,
                          double *lds_raw) {
     const int32_t M = dsc.M, n = dsc.n, npad = dsc.npad;
     const int64_t ld = npad;
-    const int32_t *__restrict__ rowidx = dsc.rowidx;
-    const int32_t *__restrict__ rowptr = dsc.rowptr;
-    const int32_t *__restrict__ r2m = dsc.r2m;
-    const int32_t *__restrict__ csr_k = dsc.csrk;
-    const int32_t *__restrict__ csr_end = dsc.csrend;
-    double *__restrict__ G = dsc.G;
+    // global (not FLAT) accesses: FLAT ones would also hold up the LDS waits below
+    const auto vals = gmem(vals_);
+    const auto rowidx = gmem(dsc.rowidx);
+    const auto rowptr = gmem(dsc.rowptr);
+    const auto r2m = gmem(dsc.r2m);
+    const auto csr_k = gmem(dsc.csrk);
+    const auto csr_end = gmem(dsc.csrend);
+    const auto dense = gmem(dsc.dense);
+    const auto G = gmem(dsc.G);
     const int nw = blockDim.x >> 6;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -76,7 +79,7 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals, int32_
     for (int32_t t = threadIdx.x; t < nw * kDenseRows * 64; t += blockDim.x) dslot[t] = Acc(0);
     for (int32_t t = threadIdx.x; t < M; t += blockDim.x) dmap[t] = -1;
     __syncthreads();
-    if (threadIdx.x < kDenseRows && dsc.dense[threadIdx.x] >= 0) dmap[dsc.dense[threadIdx.x]] = (int8_t)threadIdx.x;
+    if (threadIdx.x < kDenseRows && dense[threadIdx.x] >= 0) dmap[dense[threadIdx.x]] = (int8_t)threadIdx.x;
     __syncthreads();
 
     const int32_t p = r2m[i];
@@ -134,7 +137,7 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals, int32_
     if (lane == 0) dsum[wave] = dg;
     // the dense rows: lane-private sums reduced over the lanes into the wave's row
     for (int t = 0; t < kDenseRows; ++t) {
-        const int32_t q = dsc.dense[t];
+        const int32_t q = dense[t];
         if (q < 0) break;
         const Acc v = wave_sum(myslot[t * 64]);
         if (lane == 0) my[q] = v;
@@ -160,7 +163,7 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals, int32_
         return;
     }
     // partial row of this segment: entry j >= i (the diagonal at j = i)
-    double *__restrict__ part = dsc.gpart + (int64_t)(dsc.gslot[i] + seg) * ld;
+    const auto part = gmem(dsc.gpart) + (int64_t)(gmem(dsc.gslot)[i] + seg) * ld;
     for (int32_t j = i + 1 + threadIdx.x; j < n; j += blockDim.x) {
         const int32_t q = r2m[j];
         double v = 0.0;
@@ -183,7 +186,8 @@ __global__ __launch_bounds__(512) void k_gram_rows(const MatDesc *__restrict__ d
     const int mat = find_mat(wp, count, blockIdx.x);
     const MatDesc &d = descs[mat];
     const int32_t b = blockIdx.x - wp[mat];
-    const int32_t total = d.gsegp[d.n];
+    const auto gsegp = gmem(d.gsegp);
+    const int32_t total = gsegp[d.n];
     int32_t i, seg = 0, nseg = 1;
     if (b >= total) {
         i = d.n + (b - total);
@@ -191,12 +195,12 @@ __global__ __launch_bounds__(512) void k_gram_rows(const MatDesc *__restrict__ d
         int32_t lo = 0, hi = d.n - 1;   // last i with gsegp[i] <= b
         while (lo < hi) {
             const int32_t mid = (lo + hi + 1) >> 1;
-            if (d.gsegp[mid] <= b) lo = mid;
+            if (gsegp[mid] <= b) lo = mid;
             else hi = mid - 1;
         }
         i = lo;
-        seg = b - d.gsegp[i];
-        nseg = d.gsegp[i + 1] - d.gsegp[i];
+        seg = b - gsegp[i];
+        nseg = gsegp[i + 1] - gsegp[i];
     }
     if (d.dtype == 1) {
         const double *v = static_cast<const double *>(d.values);
@@ -217,11 +221,11 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const MatDesc *__restrict__
     const MatDesc &d = descs[mat];
     const int32_t i = blockIdx.x - wp[mat];
     if (i >= d.n) return;
-    const int32_t nseg = d.gsegp[i + 1] - d.gsegp[i];
+    const int32_t nseg = gmem(d.gsegp)[i + 1] - gmem(d.gsegp)[i];
     if (nseg <= 1) return;
     const int64_t ld = d.npad;
-    const double *__restrict__ part = d.gpart + (int64_t)d.gslot[i] * ld;
-    double *__restrict__ G = d.G;
+    const auto part = gmem(d.gpart) + (int64_t)gmem(d.gslot)[i] * ld;
+    const auto G = gmem(d.G);
     for (int32_t j = i + threadIdx.x; j < d.n; j += blockDim.x) {
         double v = 0.0;
         for (int32_t s = 0; s < nseg; ++s) v += part[(int64_t)s * ld + j];

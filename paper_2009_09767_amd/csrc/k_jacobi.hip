@@ -60,6 +60,7 @@ constexpr int kCrossSteps = kB;  // steps of a cross sweep (the 256 pairs joinin
 constexpr int kTileWaves = 4;    // update tiles per workgroup (one per wave)
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 // Round r of the round-robin tournament on `players` (even) seats: seat 0 stays, the
 // others turn one place per round; pair i joins seat i and seat players-1-i.
@@ -239,8 +240,8 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
     // 16w .. 16w + 15, U_w = T_w JB (k = 32) and P_w = JA_w^T U_w (k = 16, U_w stays in
     // registers: the product's result layout is the next product's B layout), and
     // S_PQ = P_0 + P_1.  Waves 2 and 3 bring the diagonal blocks.
-    const int32_t active = a.jstate[kJsActive], sweeps = a.jstate[kJsSweeps];
-    const double floor_abs = a.sdbl[kSdFloor];   // loaded with the build, used by the test
+    const int32_t active = gmem(a.jstate)[kJsActive], sweeps = gmem(a.jstate)[kJsSweeps];
+    const double floor_abs = gmem(a.sdbl)[kSdFloor];   // loaded with the build, used by the test
     const int l16 = lane & 15, l4 = lane >> 4;
     // the sweep's fixed indices and J = I, set up while the build's loads are in flight
     const bool cross = a.cross != 0;
@@ -285,8 +286,8 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
             g0[j] = g1[j] = 0.0;
             if (x <= y) {
                 const int64_t off = (int64_t)gidx(x, P, Q) * a.ld + gidx(y, P, Q);
-                g0[j] = a.G0[off];
-                g1[j] = a.G1[off];
+                g0[j] = gmem(a.G0)[off];
+                g1[j] = gmem(a.G1)[off];
             }
         }
     } else {
@@ -299,13 +300,13 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
             // U_w: step q's contraction index for lane group l4 is k = 8 l4 + q, so each
             // lane reads 8 consecutive entries of its T row (one block: 8 divides 16)
             const int64_t off = (int64_t)gidx(16 * wave + l16, Pa, Qa) * a.ld + gidx(8 * l4, Pb, Qb);
-            const double2 *t0 = reinterpret_cast<const double2 *>(a.G0 + off);
-            const double2 *t1 = reinterpret_cast<const double2 *>(a.G1 + off);
-            const double *jpa = a.Jprev + (int64_t)pp * kP * kP + hp * kB + l16;
-            const double *jpb = a.Jprev + (int64_t)pq * kP * kP + hq * kB + l16;
+            const auto t0 = reinterpret_cast<__attribute__((address_space(1))) const d2 *>(gmem(a.G0) + off);
+            const auto t1 = reinterpret_cast<__attribute__((address_space(1))) const d2 *>(gmem(a.G1) + off);
+            const auto jpa = gmem(a.Jprev) + (int64_t)pp * kP * kP + hp * kB + l16;
+            const auto jpb = gmem(a.Jprev) + (int64_t)pq * kP * kP + hq * kB + l16;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const double2 x0 = t0[v], x1 = t1[v];   // T[16w + l16][8 l4 + 2v, + 1]
+                const d2 x0 = t0[v], x1 = t1[v];   // T[16w + l16][8 l4 + 2v, + 1]
                 g0[2 * v] = x0.x;
                 g0[2 * v + 1] = x0.y;
                 g1[2 * v] = x1.x;
@@ -322,8 +323,8 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
                 const int e = tid - 128 + 128 * j, x = e >> 4, y = e & 15;
                 dg[j] = dg[2 + j] = 0.0;
                 if (x <= y) {
-                    dg[j] = a.Sprev[(int64_t)pp * kP * kP + (hp * kB + x) * kP + hp * kB + y];
-                    dg[2 + j] = a.Sprev[(int64_t)pq * kP * kP + (hq * kB + x) * kP + hq * kB + y];
+                    dg[j] = gmem(a.Sprev)[(int64_t)pp * kP * kP + (hp * kB + x) * kP + hp * kB + y];
+                    dg[2 + j] = gmem(a.Sprev)[(int64_t)pq * kP * kP + (hq * kB + x) * kP + hq * kB + y];
                 }
             }
         }
@@ -402,10 +403,10 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
         if (!any_bad) {
             for (int e = tid; e < kP * kP; e += 256) {
                 const int x = e >> 5, y = e & 31;
-                __builtin_nontemporal_store(S0[sym(x, y)], &a.Scur[(int64_t)pair * kP * kP + e]);
-                __builtin_nontemporal_store(x == y ? 1.0 : 0.0, &a.Jcur[(int64_t)pair * kP * kP + e]);
+                __builtin_nontemporal_store(S0[sym(x, y)], &gmem(a.Scur)[(int64_t)pair * kP * kP + e]);
+                __builtin_nontemporal_store(x == y ? 1.0 : 0.0, &gmem(a.Jcur)[(int64_t)pair * kP * kP + e]);
             }
-            if (tid == 0) a.fcur[pair] = 0;
+            if (tid == 0) gmem(a.fcur)[pair] = 0;
             return;
         }
     }
@@ -469,14 +470,14 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
     // positions are the indices again
     for (int e = tid; e < kP * kP; e += 256) {
         const int x = e >> 5, y = e & 31;
-        __builtin_nontemporal_store(Sfin[sym(x, y)], &a.Scur[(int64_t)pair * kP * kP + e]);
+        __builtin_nontemporal_store(Sfin[sym(x, y)], &gmem(a.Scur)[(int64_t)pair * kP * kP + e]);
     }
     if (wave == 3 && lane < kP) {
-        double *dst = a.Jcur + (int64_t)pair * kP * kP + lane * kP;
+        const auto dst = gmem(a.Jcur) + (int64_t)pair * kP * kP + lane * kP;
 #pragma unroll
         for (int c = 0; c < kP; ++c) __builtin_nontemporal_store(jr[c], &dst[c]);
     }
-    if (tid == 128) a.fcur[pair] = rotated;   // lane 0 of wave 2 holds the flag
+    if (tid == 128) gmem(a.fcur)[pair] = rotated;   // lane 0 of wave 2 holds the flag
 }
 
 // ---- update of the previous round (FP64 matrix cores) ----------------------
@@ -488,7 +489,7 @@ __device__ __forceinline__ void solve_pair(const RoundArgs &a, int pair, int32_t
 
 
 // acc = A B, A a 32 x 32 tile in LDS (stride kPS), B row-major 32 x 32 in memory.
-__device__ __forceinline__ void mm_lds_mem(const double *__restrict__ A, const double *__restrict__ B, d4 (&acc)[2][2],
+__device__ __forceinline__ void mm_lds_mem(const double *__restrict__ A, __attribute__((address_space(1))) const double *__restrict__ B, d4 (&acc)[2][2],
                                            int l) {
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
@@ -506,7 +507,7 @@ __device__ __forceinline__ void mm_lds_mem(const double *__restrict__ A, const d
     }
 }
 // out = Ja^T T, T in result layout (registers), Ja row-major 32 x 32 in memory.
-__device__ __forceinline__ void mm_t_reg(const double *__restrict__ Ja, const d4 (&T)[2][2], d4 (&out)[2][2], int l) {
+__device__ __forceinline__ void mm_t_reg(__attribute__((address_space(1))) const double *__restrict__ Ja, const d4 (&T)[2][2], d4 (&out)[2][2], int l) {
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
@@ -535,12 +536,12 @@ __device__ __forceinline__ void lds_to_acc(const double *__restrict__ A, d4 (&ac
 // A 32 x 32 tile whose row x starts at rows[x] and whose columns are gidx(., Pb, Qb),
 // staged in LDS (stride kPS) by one wave: all eight 16-byte loads of a lane are issued
 // before the first LDS store, so the tile costs one memory round trip.
-__device__ __forceinline__ void tile_to_lds(const double *__restrict__ base, const int64_t (&rows)[8], int Pb, int Qb,
+__device__ __forceinline__ void tile_to_lds(__attribute__((address_space(1))) const double *__restrict__ base, const int64_t (&rows)[8], int Pb, int Qb,
                                             double *buf, int l) {
     const int y = 2 * (l & 15), col = gidx(y, Pb, Qb);
-    double2 v[8];
+    d2 v[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = *reinterpret_cast<const double2 *>(base + rows[j] + col);
+    for (int j = 0; j < 8; ++j) v[j] = *reinterpret_cast<__attribute__((address_space(1))) const d2 *>(base + rows[j] + col);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int x = (l >> 4) + 4 * j;
@@ -564,32 +565,32 @@ __device__ __forceinline__ void update_tile(const RoundArgs &a, int u, double *b
         tournament_pair(a.nb, a.round_prev, ib, Pb, Qb);
         if (ia == ib) {
             // diagonal tile: the rotated subproblem itself (loads first, then the stores)
-            const double2 *s = reinterpret_cast<const double2 *>(a.Sprev + (int64_t)ia * kP * kP);
-            double2 v[8];
+            const auto s = reinterpret_cast<__attribute__((address_space(1))) const d2 *>(gmem(a.Sprev) + (int64_t)ia * kP * kP);
+            d2 v[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) v[j] = s[l + 64 * j];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int e = 2 * (l + 64 * j), x = e >> 5, y = e & 31;
-                double *d = &a.Gout[(int64_t)gidx(x, Pa, Qa) * a.ld + gidx(y, Pa, Qa)];
+                const auto d = &gmem(a.Gout)[(int64_t)gidx(x, Pa, Qa) * a.ld + gidx(y, Pa, Qa)];
                 __builtin_nontemporal_store(v[j].x, d);
                 __builtin_nontemporal_store(v[j].y, d + 1);
             }
             return;
         }
-        const bool fa = a.fprev[ia] != 0, fb = a.fprev[ib] != 0;
+        const bool fa = gmem(a.fprev)[ia] != 0, fb = gmem(a.fprev)[ib] != 0;
         {
             int64_t rows[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) rows[j] = (int64_t)gidx((l >> 4) + 4 * j, Pa, Qa) * a.ld;
-            tile_to_lds(a.Gin, rows, Pb, Qb, buf, l);
+            tile_to_lds(gmem(a.Gin), rows, Pb, Qb, buf, l);
         }
         wave_fence();
         d4 t[2][2], o[2][2];
-        if (fb) mm_lds_mem(buf, a.Jprev + (int64_t)ib * kP * kP, t, l);
+        if (fb) mm_lds_mem(buf, gmem(a.Jprev) + (int64_t)ib * kP * kP, t, l);
         else lds_to_acc(buf, t, l);
         if (fa) {
-            mm_t_reg(a.Jprev + (int64_t)ia * kP * kP, t, o, l);
+            mm_t_reg(gmem(a.Jprev) + (int64_t)ia * kP * kP, t, o, l);
         } else {
 #pragma unroll
             for (int rb = 0; rb < 2; ++rb)
@@ -604,7 +605,7 @@ __device__ __forceinline__ void update_tile(const RoundArgs &a, int u, double *b
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int x = 16 * rb + (l >> 4) + 4 * i, y = 16 * cb + (l & 15);
-                    __builtin_nontemporal_store(v[i], &a.Gout[(int64_t)gidx(x, Pa, Qa) * a.ld + gidx(y, Pb, Qb)]);
+                    __builtin_nontemporal_store(v[i], &gmem(a.Gout)[(int64_t)gidx(x, Pa, Qa) * a.ld + gidx(y, Pb, Qb)]);
                 }
             }
         // the mirror tile through LDS, so its stores are row runs as well
@@ -620,7 +621,7 @@ __device__ __forceinline__ void update_tile(const RoundArgs &a, int u, double *b
         wave_fence();
         for (int e = l; e < kP * kP; e += 64) {
             const int x = e >> 5, y = e & 31;   // element (y, x) of the tile = (x, y) of its mirror
-            __builtin_nontemporal_store(buf[y * kPS + x], &a.Gout[(int64_t)gidx(x, Pb, Qb) * a.ld + gidx(y, Pa, Qa)]);
+            __builtin_nontemporal_store(buf[y * kPS + x], &gmem(a.Gout)[(int64_t)gidx(x, Pb, Qb) * a.ld + gidx(y, Pa, Qa)]);
         }
         return;
     }
@@ -629,18 +630,18 @@ __device__ __forceinline__ void update_tile(const RoundArgs &a, int u, double *b
     // W tiles: row-tile-major (linear schedule) or pair-major (grouped schedule: the tiles
     // that share J_ib are consecutive, so one XCD's L2 serves them)
     const int rt = a.sched ? u % a.nrowtiles : u / npairs, ib = a.sched ? u / a.nrowtiles : u % npairs;
-    if (rt >= a.nrowtiles || !a.fprev[ib]) return;
+    if (rt >= a.nrowtiles || !gmem(a.fprev)[ib]) return;
     int Pb, Qb;
     tournament_pair(a.nb, a.round_prev, ib, Pb, Qb);
     {
         int64_t rows[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) rows[j] = (int64_t)(rt * kP + (l >> 4) + 4 * j) * a.ld;
-        tile_to_lds(a.W, rows, Pb, Qb, buf, l);
+        tile_to_lds(gmem(a.W), rows, Pb, Qb, buf, l);
     }
     wave_fence();
     d4 t[2][2];
-    mm_lds_mem(buf, a.Jprev + (int64_t)ib * kP * kP, t, l);
+    mm_lds_mem(buf, gmem(a.Jprev) + (int64_t)ib * kP * kP, t, l);
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
@@ -648,7 +649,7 @@ __device__ __forceinline__ void update_tile(const RoundArgs &a, int u, double *b
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int x = 16 * rb + (l >> 4) + 4 * i, y = 16 * cb + (l & 15);
-                __builtin_nontemporal_store(t[rb][cb][i], &a.W[(int64_t)(rt * kP + x) * a.ld + gidx(y, Pb, Qb)]);
+                __builtin_nontemporal_store(t[rb][cb][i], &gmem(a.W)[(int64_t)(rt * kP + x) * a.ld + gidx(y, Pb, Qb)]);
             }
 }
 
@@ -676,9 +677,9 @@ __global__ __launch_bounds__(256, 2) void k_jround(const RoundArgs one, const Ro
         }
         b -= npairs;
     }
-    if (a.jstate[kJsActive] == 0) return;
+    if (gmem(a.jstate)[kJsActive] == 0) return;
     // G buffer holding M_{r-1}: one flip per launch with a previous round, nb - 1 per sweep
-    const int32_t flips = a.jstate[kJsSweeps] * (a.nb - 1) + (launch_r > 0 ? launch_r - 1 : 0);
+    const int32_t flips = gmem(a.jstate)[kJsSweeps] * (a.nb - 1) + (launch_r > 0 ? launch_r - 1 : 0);
     a.Gin = (flips & 1) ? a.G1 : a.G0;
     a.Gout = (flips & 1) ? a.G0 : a.G1;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
