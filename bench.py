@@ -41,7 +41,7 @@ def parse():
 # runs (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, averaged over the launches that did work),
 # each scaled by what the same counter reads back for a plain device copy of 1 GiB (x2.0 for
 # FETCH_SIZE, x1.0 for WRITE_SIZE).  Valid only for the kernel source it was taken on.
-JROUND_TRAFFIC = {"bytes": (6777.58 * 2.0 + 15467.44) * 1024, "source_sha256": "719eafec5f5ef0e48707d7cab4bafc5e526512af16fa5c30d7a00e88bb7f292b"}
+JROUND_TRAFFIC = {"bytes": (6732.91 * 2.0 + 15467.99) * 1024, "source_sha256": "0bb7476ef026e4e3dd39bd52c2ae6673527494c23ad805d88dba00e9e2217ca4"}
 
 
 def jround_traffic():
