@@ -29,6 +29,8 @@ constexpr int32_t kGramSeg = 1 << 16;
 // nonzeros): their products go to lane-private slots instead of the shared row, since
 // most lanes of a wave would otherwise meet on the same few rows.
 constexpr int kDenseRows = 32;
+// Column entries each lane of the Gram walk loads ahead (one group of gathers in flight).
+constexpr int kGramStep = 4;
 // Ints per matrix in the per-matrix read-back (status, M', rank, sweeps, not-converged,
 // lonely max, lonely blocks, active, Gram segments, Gram partial rows).
 constexpr int kColI = 10;

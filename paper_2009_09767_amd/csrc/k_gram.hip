@@ -95,43 +95,62 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
     Acc *myslot = dslot + (size_t)wave * kDenseRows * 64 + lane;
     Acc dg = Acc(0);
 
+    // Each lane walks the later entries of its column kGramStep steps at a time: the
+    // loads of a group are all issued before the first product is added, and the next
+    // batch's CSR positions are fetched during the walk.  The additions still run step
+    // by step in lane order, so the sums are those of a one-step walk.
+    // Lanes past the end of the run load the run's last entry (a valid address) and
+    // discard it: with no conditional loads, all of a group's loads stay in flight.
+    int32_t kk = 0, kend = 0;
+    if (wb < we) {
+        const int32_t e0 = wb + lane < we ? wb + lane : we - 1;
+        kk = csr_k[e0];
+        kend = csr_end[e0];
+    }
     for (int32_t base = wb; base < we; base += 64) {
-        const int32_t e = base + lane;
-        const bool has = e < we;
-        int32_t kk = 0, kend = 0;
-        Acc a = Acc(0);
-        if (has) {
-            kk = csr_k[e];
-            kend = csr_end[e];
-            a = static_cast<Acc>(vals[kk]);
-            dg += a * a;
-        }
-        for (int32_t s = 1;; ++s) {
-            const bool act = has && (kk + s < kend);
-            if (__ballot(act) == 0) break;
-            int32_t q = 0;
-            Acc v = Acc(0);
-            int di = -1;
-            if (act) {
-                q = rowidx[kk + s];
-                v = a * static_cast<Acc>(vals[kk + s]);
-                di = dmap[q];
-                if (di >= 0) myslot[di * 64] += v;
+        const bool has = base + lane < we;
+        const int32_t nb = base + 64 + lane < we ? base + 64 + lane : we - 1;
+        const int32_t kk_next = csr_k[nb], kend_next = csr_end[nb];
+        const Acc a = static_cast<Acc>(vals[kk]);   // used only where has holds
+        for (int32_t s = 1;; s += kGramStep) {
+            if (__ballot(has && kk + s < kend) == 0) break;
+            int32_t qs[kGramStep];
+            Acc vs[kGramStep];
+#pragma unroll
+            for (int u = 0; u < kGramStep; ++u) {
+                const int32_t at = kk + s + u < kend ? kk + s + u : kk;
+                qs[u] = rowidx[at];
+                vs[u] = static_cast<Acc>(vals[at]);
             }
-            bool pend = act && di < 0;
-            while (__ballot(pend) != 0) {
-                if (pend) atomicMin(&mytag[q], lane);
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                const bool win = pend && (__hip_atomic_load(&mytag[q], __ATOMIC_RELAXED,
-                                                            __HIP_MEMORY_SCOPE_WAVEFRONT) == lane);
-                if (win) {
-                    my[q] += v;
-                    mytag[q] = 64;
+            __builtin_amdgcn_sched_barrier(0);   // keep every load of the group ahead of its uses
+#pragma unroll
+            for (int u = 0; u < kGramStep; ++u) {
+                const bool act = has && (kk + s + u < kend);
+                const int32_t q = qs[u];
+                const Acc v = a * vs[u];
+                int di = -1;
+                if (act) {
+                    di = dmap[q];
+                    if (di >= 0) myslot[di * 64] += v;
                 }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                pend = pend && !win;
+                bool pend = act && di < 0;
+                while (__ballot(pend) != 0) {
+                    if (pend) atomicMin(&mytag[q], lane);
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    const bool win = pend && (__hip_atomic_load(&mytag[q], __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_WAVEFRONT) == lane);
+                    if (win) {
+                        my[q] += v;
+                        mytag[q] = 64;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    pend = pend && !win;
+                }
             }
         }
+        if (has) dg += a * a;
+        kk = kk_next;
+        kend = kend_next;
     }
     dg = wave_sum(dg);
     if (lane == 0) dsum[wave] = dg;
