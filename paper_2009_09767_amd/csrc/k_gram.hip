@@ -11,8 +11,13 @@
 // Inside a wave the 64 lanes hold 64 different columns, and two of them may reach
 // the same q at the same step.  Each such collision is resolved by electing the
 // lowest lane through an integer min in LDS; the winner adds its product, the others
-// retry, so the sum per address runs in lane order.  Integer min commutes, so the
-// election -- and therefore every floating-point result -- is independent of timing.
+// retry, so the sum per address runs in lane order.  The tag row of the election is
+// shared by the workgroup's waves (ids are workgroup-wide lane numbers): a winner
+// clears the tag only while it still holds its own id (compare-and-swap), so no wave
+// can erase another wave's id, and within a wave a higher lane never reads its own id
+// while a lower lane of the same wave is pending on the same q.  Each wave adds into
+// its own row, so the additions per address still run in lane order, and the result
+// is independent of timing.
 //
 // The diagonal a_pj^2 terms are summed per lane and reduced by a fixed shuffle tree.
 // G is written in compacted coordinates (empty rows removed), symmetric, padded
@@ -65,17 +70,15 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
         return;
     }
     Acc *acc = reinterpret_cast<Acc *>(lds_raw);                  // nw x M
-    int32_t *tag = reinterpret_cast<int32_t *>(acc + (size_t)nw * M);  // nw x M
     // nw x kDenseRows x 64 lane-private slots, 16-byte aligned (M may be odd)
     Acc *dslot = reinterpret_cast<Acc *>(reinterpret_cast<char *>(lds_raw) +
-                                         ((((size_t)nw * M * (sizeof(Acc) + sizeof(int32_t))) + 15) & ~(size_t)15));
-    int8_t *dmap = reinterpret_cast<int8_t *>(dslot + (size_t)nw * kDenseRows * 64);  // M: dense index or -1
+                                         ((((size_t)nw * M * sizeof(Acc)) + 15) & ~(size_t)15));
+    int32_t *tag = reinterpret_cast<int32_t *>(dslot + (size_t)nw * kDenseRows * 64);  // M, shared
+    int8_t *dmap = reinterpret_cast<int8_t *>(tag + M);  // M: dense index or -1
     __shared__ Acc dsum[16];
     __syncthreads();
-    for (int32_t t = threadIdx.x; t < nw * M; t += blockDim.x) {
-        acc[t] = Acc(0);
-        tag[t] = 64;
-    }
+    for (int32_t t = threadIdx.x; t < nw * M; t += blockDim.x) acc[t] = Acc(0);
+    for (int32_t t = threadIdx.x; t < M; t += blockDim.x) tag[t] = kTagFree;
     for (int32_t t = threadIdx.x; t < nw * kDenseRows * 64; t += blockDim.x) dslot[t] = Acc(0);
     for (int32_t t = threadIdx.x; t < M; t += blockDim.x) dmap[t] = -1;
     __syncthreads();
@@ -91,7 +94,7 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
     const int32_t wb = e_begin + wave * run;
     const int32_t we = (wb + run < e_end) ? wb + run : e_end;
     Acc *my = acc + (size_t)wave * M;
-    int32_t *mytag = tag + (size_t)wave * M;
+    const int32_t gid = threadIdx.x;   // workgroup-wide id in the election
     Acc *myslot = dslot + (size_t)wave * kDenseRows * 64 + lane;
     Acc dg = Acc(0);
 
@@ -135,13 +138,13 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
                 }
                 bool pend = act && di < 0;
                 while (__ballot(pend) != 0) {
-                    if (pend) atomicMin(&mytag[q], lane);
+                    if (pend) atomicMin(&tag[q], gid);
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                    const bool win = pend && (__hip_atomic_load(&mytag[q], __ATOMIC_RELAXED,
-                                                                __HIP_MEMORY_SCOPE_WAVEFRONT) == lane);
+                    const bool win = pend && (__hip_atomic_load(&tag[q], __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_WORKGROUP) == gid);
                     if (win) {
                         my[q] += v;
-                        mytag[q] = 64;
+                        atomicCAS(&tag[q], gid, kTagFree);
                     }
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     pend = pend && !win;
@@ -257,31 +260,35 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const MatDesc *__restrict__
     }
 }
 
-// LDS per wave: one accumulator row, one tag row and the lane-private dense slots; plus
-// one dense-index byte per row for the workgroup.
+// LDS per wave: one accumulator row and the lane-private dense slots; per workgroup:
+// the shared tag row, one dense-index byte per row and the alignment pad.
 static size_t gram_wave_bytes(int32_t M, int32_t acc_bytes) {
-    return (size_t)M * (acc_bytes + sizeof(int32_t)) + (size_t)kDenseRows * 64 * acc_bytes;
+    return (size_t)M * acc_bytes + (size_t)kDenseRows * 64 * acc_bytes;
+}
+
+static size_t gram_fixed_bytes(int32_t M) {
+    return (size_t)M * sizeof(int32_t) + (((size_t)M + 15) & ~(size_t)15) + 16;
 }
 
 int gram_waves(int32_t M, int32_t acc_bytes, size_t lds_limit) {
-    const size_t fixed = (((size_t)M + 15) & ~(size_t)15) + 16;
+    const size_t fixed = gram_fixed_bytes(M);
     int w = lds_limit > fixed ? (int)((lds_limit - fixed) / gram_wave_bytes(M, acc_bytes)) : 1;
     if (w > 8) w = 8;
     if (w < 1) w = 1;
     return w;
 }
 
-size_t gram_lds_bytes(int32_t maxM, size_t lds_limit) {
-    const int nw = gram_waves(maxM, 8, lds_limit);
-    return (size_t)nw * gram_wave_bytes(maxM, 8) + (((size_t)maxM + 15) & ~(size_t)15) + 16;
+size_t gram_lds_bytes(int32_t maxM, int32_t acc_bytes, size_t lds_limit) {
+    const int nw = gram_waves(maxM, acc_bytes, lds_limit);
+    return (size_t)nw * gram_wave_bytes(maxM, acc_bytes) + gram_fixed_bytes(maxM);
 }
 
 void launch_gram(const MatDesc *descs, const int32_t *wp, int64_t nblocks, const int32_t *wp_red, int64_t nblocks_red,
-                 int count, int32_t maxM, size_t lds_limit, hipStream_t s) {
+                 int count, int32_t maxM, int32_t acc_bytes, size_t lds_limit, hipStream_t s) {
     if (nblocks <= 0) return;
-    const int nw = gram_waves(maxM, 8, lds_limit);
-    hipLaunchKernelGGL(k_gram_rows, dim3((unsigned)nblocks), dim3((unsigned)(64 * nw)), gram_lds_bytes(maxM, lds_limit),
-                       s, descs, wp, count);
+    const int nw = gram_waves(maxM, acc_bytes, lds_limit);
+    hipLaunchKernelGGL(k_gram_rows, dim3((unsigned)nblocks), dim3((unsigned)(64 * nw)),
+                       gram_lds_bytes(maxM, acc_bytes, lds_limit), s, descs, wp, count);
     if (nblocks_red > 0)
         hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)nblocks_red), dim3(256), 0, s, descs, wp_red, count);
 }

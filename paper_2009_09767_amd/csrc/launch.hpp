@@ -33,11 +33,10 @@ hipError_t occupancy_set_attributes(int32_t maxM);
 
 // Gram (k_gram.hip)
 int gram_waves(int32_t M, int32_t acc_bytes, size_t lds_limit);
-size_t gram_lds_bytes(int32_t maxM, size_t lds_limit);
+size_t gram_lds_bytes(int32_t maxM, int32_t acc_bytes, size_t lds_limit);
 int64_t gram_part_slots(int64_t nnz);   // partial Gram rows the workspace must hold
 void launch_gram(const MatDesc *descs, const int32_t *wp, int64_t nblocks, const int32_t *wp_red, int64_t nblocks_red,
-                 int count, int32_t maxM, size_t lds_limit,
-                 hipStream_t s);
+                 int count, int32_t maxM, int32_t acc_bytes, size_t lds_limit, hipStream_t s);
 hipError_t gram_set_attributes(size_t lds_limit);
 
 // Jacobi eigensolver (k_jacobi.hip)

@@ -670,8 +670,11 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
     if (st) return st;
     e.enqueue_transpose();
     if (timing) hipEventRecord(ctx->ev[2], s);
+    int32_t gram_acc = 4;   // accumulator bytes: FP64 if any matrix of the launch asks for it
+    for (int i = 0; i < count; ++i)
+        if (e.d[i].prec == RANKY_PREC_FP64) gram_acc = 8;
     launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], e.dwp(kPhGramRed), e.nblk[kPhGramRed], count, maxM,
-                ctx->lds_limit, s);
+                gram_acc, ctx->lds_limit, s);
     HIP_TRY(hipGetLastError());
     if (timing) hipEventRecord(ctx->ev[3], s);
     st = e.eigensolve(use_graph);
@@ -1194,7 +1197,7 @@ ranky_status ranky_gram(const ranky_csc *A, int32_t M, int64_t N, int32_t prec, 
         if (st) return st;
         e.enqueue_transpose();
         launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], e.dwp(kPhGramRed), e.nblk[kPhGramRed], 1, M,
-                    sc.c.lds_limit, s);
+                    prec == RANKY_PREC_FP64 ? 8 : 4, sc.c.lds_limit, s);
         launch_scatter_gram(x.G, x.npad, x.m2r, M, G, s);
     } else {
         launch_fill_f64(G, (int64_t)M * M, 0.0, s);
