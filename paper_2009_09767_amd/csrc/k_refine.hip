@@ -7,12 +7,14 @@
 // whose values are accurate to second order in U0's error.  Everything here is FP64.
 //
 // Z is never stored: H = sum over columns j of z_j z_j^T with z_j = sum over column j's
-// nonzeros of a_mj U0[m, :].  One workgroup owns one 64 x 64 tile of H and one fixed
-// range of columns; per chunk of 16 columns it builds the two 64-wide slices of z_j it
-// needs in LDS (U0 is small and stays in L2) and adds their outer products on the FP64
-// matrix cores (each wave a 32 x 32 quarter of the tile).  The partial tiles of the
-// column ranges are then added in range order: no floating-point atomics, bitwise
-// reproducible.
+// nonzeros of a_mj U0[m, :].  One workgroup owns one 128 x 128 tile of H and one fixed
+// range of columns; per chunk of 16 columns it builds the 128-wide slices of z_j it
+// needs in LDS (U0 is small and stays in L2; 16 lanes read one row slice as sixteen
+// 16-byte loads, eight nonzeros in flight) and adds their outer products on the FP64
+// matrix cores (each wave one 64 x 64 quadrant; a diagonal tile skips its lower one).
+// With k <= 128 there is one tile, so every U0 row is gathered once per nonzero.  The
+// partial tiles of the column ranges are then added in range order: no floating-point
+// atomics, bitwise reproducible.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -20,16 +22,108 @@ namespace ranky {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int kRrTile = 64;     // H tile
+constexpr int kRrTile = 128;    // H tile
 constexpr int kRrChunk = 16;    // columns per LDS chunk
-constexpr int kRrWgs = 2048;    // target workgroups per launch (tiles x column ranges)
+constexpr int kRrWgs = 512;     // target workgroups per launch (tiles x column ranges)
+constexpr int kRrLd = kRrTile + 2;   // LDS row stride (doubles): 16-byte rows, staggered banks
 
-// workgroup b -> tile t = b / R (ta <= tb, row-major over the upper triangle), range b % R
-template <typename TV>
-__global__ __launch_bounds__(256) void k_rr_syrk(const int32_t *__restrict__ colptr, const int32_t *__restrict__ rowidx,
-                                                 const TV *__restrict__ vals, int64_t N, int32_t k, int32_t R,
-                                                 const double *__restrict__ U0, double *__restrict__ part) {
-    __shared__ double ZA[kRrChunk][kRrTile + 1], ZB[kRrChunk][kRrTile + 1];
+// Nonzeros of a chunk staged in LDS (row index and value), one chunk ahead; a chunk with
+// more reads the rest from memory.
+constexpr int kRrStage = 1024;
+// Nonzeros of a column whose U0 rows are gathered together.
+constexpr int kRrNz = 8;
+
+// One pair of U0 entries (row, c), (row, c + 1) with c even; an entry at or past k reads
+// as zero.  Branch-free (clamped addresses, masked values), so a group's loads all stay in
+// flight.  With k even the pair is one aligned 16-byte load.
+template <bool kEven>
+__device__ __forceinline__ double2 u0_pair(__attribute__((address_space(1))) const double *U0, int64_t row, int32_t k,
+                                           int32_t c) {
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    double2 r;
+    if (kEven) {
+        const int32_t cc = c < k ? c : 0;
+        const d2v v = *reinterpret_cast<__attribute__((address_space(1))) const d2v *>(U0 + row * k + cc);
+        r.x = c < k ? v.x : 0.0;
+        r.y = c < k ? v.y : 0.0;
+    } else {
+        const int32_t c0 = c < k ? c : 0, c1 = c + 1 < k ? c + 1 : 0;
+        const double x0 = U0[row * k + c0], x1 = U0[row * k + c1];
+        r.x = c < k ? x0 : 0.0;
+        r.y = c + 1 < k ? x1 : 0.0;
+    }
+    return r;
+}
+
+// z slice of one column: lane t (0..15) of the column's 16 holds entries 2t + 32q, +1
+// (q = 0..3) of the 128-wide slice starting at row offset i0 of U0 (k columns).  The
+// column's nonzeros [e, e_end) come from the staged copy (index e - base) when the whole
+// chunk is staged (a uniform choice), else from memory.
+template <typename TV, bool kEven>
+__device__ __forceinline__ void rr_build_slices(const int32_t *srow, const double *sval, int32_t base, bool staged,
+                                                __attribute__((address_space(1))) const int32_t *rowidx,
+                                                __attribute__((address_space(1))) const TV *vals,
+                                                __attribute__((address_space(1))) const double *U0, int32_t k,
+                                                int32_t e, int32_t e_end, int32_t ia, int32_t ib, bool two,
+                                                double2 (&za)[4], double2 (&zb)[4]) {
+    for (; e < e_end; e += kRrNz) {
+        double av[kRrNz];
+        int64_t rw[kRrNz];
+        if (staged) {
+#pragma unroll
+            for (int t = 0; t < kRrNz; ++t) {
+                const int32_t li = (e + t < e_end ? e + t : e) - base;
+                rw[t] = srow[li];
+                av[t] = e + t < e_end ? sval[li] : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < kRrNz; ++t) {
+                const int32_t x = e + t < e_end ? e + t : e;
+                rw[t] = rowidx[x];
+                const double v = static_cast<double>(vals[x]);
+                av[t] = e + t < e_end ? v : 0.0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double2 ua[kRrNz];
+#pragma unroll
+            for (int t = 0; t < kRrNz; ++t) ua[t] = u0_pair<kEven>(U0, rw[t], k, ia + 32 * q);
+#pragma unroll
+            for (int t = 0; t < kRrNz; ++t) {
+                za[q].x = fma(av[t], ua[t].x, za[q].x);
+                za[q].y = fma(av[t], ua[t].y, za[q].y);
+            }
+            if (two) {
+                double2 ub[kRrNz];
+#pragma unroll
+                for (int t = 0; t < kRrNz; ++t) ub[t] = u0_pair<kEven>(U0, rw[t], k, ib + 32 * q);
+#pragma unroll
+                for (int t = 0; t < kRrNz; ++t) {
+                    zb[q].x = fma(av[t], ub[t].x, zb[q].x);
+                    zb[q].y = fma(av[t], ub[t].y, zb[q].y);
+                }
+            }
+        }
+    }
+}
+
+// workgroup b -> tile t = b / R (ta <= tb, row-major over the upper triangle), range b % R.
+// Per chunk q of 16 columns: the build of chunk q reads its staged nonzeros and waits only
+// for its U0 gathers; the loads of chunk q + 1's nonzeros (stored to LDS after the matrix-
+// core step) and of the next bounds are issued right after it.
+template <typename TV, bool kEven>
+__global__ __launch_bounds__(256) void k_rr_syrk(const int32_t *__restrict__ colptr_, const int32_t *__restrict__ rowidx_,
+                                                 const TV *__restrict__ vals_, int64_t N, int32_t k, int32_t R,
+                                                 const double *__restrict__ U0_, double *__restrict__ part) {
+    __shared__ double Z[2 * kRrChunk * kRrLd];   // slice A, then slice B
+    __shared__ int32_t Srow[2][kRrStage];
+    __shared__ double Sval[2][kRrStage];
+    const auto colptr = gmem(colptr_);
+    const auto rowidx = gmem(rowidx_);
+    const auto vals = gmem(vals_);
+    const auto U0 = gmem(U0_);
     const int tid = threadIdx.x, l = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int32_t T = (k + kRrTile - 1) / kRrTile;
@@ -40,85 +134,128 @@ __global__ __launch_bounds__(256) void k_rr_syrk(const int32_t *__restrict__ col
         ++ta;
     }
     const int32_t tb = ta + rem;
+    const bool two = ta != tb;
     const int64_t c_begin = (N * r) / R, c_end = (N * (r + 1)) / R;
-    // LDS build: thread -> column c of the chunk and four entries of each slice
-    const int bc = tid >> 4, bq = (tid & 15) * 4;
-    const int32_t ia = ta * kRrTile + bq, ib = tb * kRrTile + bq;
-    // this wave's quarter of the tile
-    const int wa = wave >> 1, wb = wave & 1;
-    d4 acc[2][2];
+    const int64_t nchunks = (c_end - c_begin + kRrChunk - 1) / kRrChunk;
+    // build: thread -> column bc of the chunk, lane bt of its 16
+    const int bc = tid >> 4, bt = tid & 15;
+    const int32_t ia = ta * kRrTile + 2 * bt, ib = tb * kRrTile + 2 * bt;
+    // this wave's 64 x 64 quadrant (qa, qb); a diagonal tile needs (0,0), (0,1), (1,1)
+    const int qa = two ? (wave >> 1) : (wave == 2 ? 1 : 0);
+    const int qb = two ? (wave & 1) : (wave == 0 ? 0 : 1);
+    const bool mm = two || wave < 3;
+    const int zb_off = two ? kRrChunk * kRrLd : 0;
+    // chunk q: columns [c_begin + 16 q, min(+16, c_end)); its nonzeros [lo(q), hi(q))
+    auto col_lo = [&](int64_t q) { return c_begin + q * kRrChunk; };
+    auto col_hi = [&](int64_t q) { return c_begin + q * kRrChunk + kRrChunk < c_end ? c_begin + q * kRrChunk + kRrChunk : c_end; };
+    d4 acc[4][4];
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int64_t c0 = c_begin; c0 < c_end; c0 += kRrChunk) {
-        double za[4] = {0.0, 0.0, 0.0, 0.0}, zb[4] = {0.0, 0.0, 0.0, 0.0};
-        const int64_t j = c0 + bc;
-        if (j < c_end) {
-            // four nonzeros per step with independent loads, so their U0 rows are in
-            // flight together (the walk is otherwise bound by one gather's latency)
-            const int32_t e_end = colptr[j + 1];
-            int32_t e = colptr[j];
-            for (; e + 4 <= e_end; e += 4) {
-                double av[4];
-                const double *u[4];
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    av[t] = static_cast<double>(vals[e + t]);
-                    u[t] = U0 + (int64_t)rowidx[e + t] * k;
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (ia + q < k)
-                        za[q] = fma(av[3], u[3][ia + q], fma(av[2], u[2][ia + q],
-                                    fma(av[1], u[1][ia + q], fma(av[0], u[0][ia + q], za[q]))));
-                    if (ta != tb && ib + q < k)
-                        zb[q] = fma(av[3], u[3][ib + q], fma(av[2], u[2][ib + q],
-                                    fma(av[1], u[1][ib + q], fma(av[0], u[0][ib + q], zb[q]))));
-                }
-            }
-            for (; e < e_end; ++e) {
-                const double av = static_cast<double>(vals[e]);
-                const double *u = U0 + (int64_t)rowidx[e] * k;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (ia + q < k) za[q] = fma(av, u[ia + q], za[q]);
-                    if (ta != tb && ib + q < k) zb[q] = fma(av, u[ib + q], zb[q]);
-                }
-            }
-            if (ta == tb) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) zb[q] = za[q];
-            }
+        for (int y = 0; y < 4; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+    if (nchunks <= 0) goto write_out;
+    {
+        // prologue: chunk 0 staged, its column bounds, chunk 1's nonzero range
+        int32_t lo0 = colptr[col_lo(0)], hi0 = colptr[col_hi(0)];
+        int32_t st0 = hi0 - lo0 < kRrStage ? hi0 - lo0 : kRrStage;
+        for (int32_t x = tid; x < st0; x += 256) {
+            Srow[0][x] = rowidx[lo0 + x];
+            Sval[0][x] = static_cast<double>(vals[lo0 + x]);
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            ZA[bc][bq + q] = za[q];
-            ZB[bc][bq + q] = zb[q];
+        int32_t eb = 0, ee = 0;
+        if (col_lo(0) + bc < col_hi(0)) {
+            eb = colptr[col_lo(0) + bc];
+            ee = colptr[col_lo(0) + bc + 1];
+        }
+        int32_t lo1 = 0, hi1 = 0;
+        if (nchunks > 1) {
+            lo1 = colptr[col_lo(1)];
+            hi1 = colptr[col_hi(1)];
         }
         __syncthreads();
-        // acc += ZA^T ZB over the chunk: A[row][c] = ZA[c][row], B[c][col] = ZB[c][col]
+        for (int64_t q = 0; q < nchunks; ++q) {
+            const int buf = (int)(q & 1);
+            double2 za[4], zb[4];
 #pragma unroll
-        for (int kc = 0; kc < kRrChunk / 4; ++kc) {
-            const int c = kc * 4 + (l >> 4);
-            const double a0 = ZA[c][32 * wa + (l & 15)], a1 = ZA[c][32 * wa + 16 + (l & 15)];
-            const double b0 = ZB[c][32 * wb + (l & 15)], b1 = ZB[c][32 * wb + 16 + (l & 15)];
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+            for (int x = 0; x < 4; ++x) {
+                za[x] = make_double2(0.0, 0.0);
+                zb[x] = make_double2(0.0, 0.0);
+            }
+            rr_build_slices<TV, kEven>(Srow[buf], Sval[buf], lo0, hi0 - lo0 <= kRrStage, rowidx, vals, U0, k, eb, ee, ia, ib, two, za, zb);
+            // prefetch: chunk q+1's nonzeros (registers), column bounds; chunk q+2's range
+            const int32_t st1 = hi1 - lo1 < kRrStage ? hi1 - lo1 : kRrStage;
+            int32_t pr[kRrStage / 256];
+            double pv[kRrStage / 256];
+#pragma unroll
+            for (int i = 0; i < kRrStage / 256; ++i) {
+                const int32_t x = tid + 256 * i;
+                const int32_t at = x < st1 ? lo1 + x : 0;   // entry 0 exists (the matrix has a nonzero)
+                pr[i] = rowidx[at];
+                pv[i] = static_cast<double>(vals[at]);
+            }
+            int32_t eb1 = 0, ee1 = 0;
+            if (q + 1 < nchunks && col_lo(q + 1) + bc < col_hi(q + 1)) {
+                eb1 = colptr[col_lo(q + 1) + bc];
+                ee1 = colptr[col_lo(q + 1) + bc + 1];
+            }
+            int32_t lo2 = 0, hi2 = 0;
+            if (q + 2 < nchunks) {
+                lo2 = colptr[col_lo(q + 2)];
+                hi2 = colptr[col_hi(q + 2)];
+            }
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                *reinterpret_cast<double2 *>(&Z[bc * kRrLd + 2 * bt + 32 * x]) = za[x];
+                if (two) *reinterpret_cast<double2 *>(&Z[kRrChunk * kRrLd + bc * kRrLd + 2 * bt + 32 * x]) = zb[x];
+            }
+            __syncthreads();
+            // acc += A^T B over the chunk: A[row][c] = slice A[c][row], B[c][col] = slice B (or A)[c][col]
+            if (mm) {
+#pragma unroll
+                for (int kc = 0; kc < kRrChunk / 4; ++kc) {
+                    const int c = kc * 4 + (l >> 4);
+                    double a[4], b[4];
+#pragma unroll
+                    for (int x = 0; x < 4; ++x) {
+                        a[x] = Z[c * kRrLd + 64 * qa + 16 * x + (l & 15)];
+                        b[x] = Z[zb_off + c * kRrLd + 64 * qb + 16 * x + (l & 15)];
+                    }
+#pragma unroll
+                    for (int x = 0; x < 4; ++x)
+#pragma unroll
+                        for (int y = 0; y < 4; ++y)
+                            acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kRrStage / 256; ++i) {
+                const int32_t x = tid + 256 * i;
+                if (x < st1) {
+                    Srow[buf ^ 1][x] = pr[i];
+                    Sval[buf ^ 1][x] = pv[i];
+                }
+            }
+            __syncthreads();
+            lo0 = lo1;
+            hi0 = hi1;
+            st0 = st1;
+            lo1 = lo2;
+            hi1 = hi2;
+            eb = eb1;
+            ee = ee1;
         }
-        __syncthreads();
     }
+write_out:
     // result layout: element i of lane l at row l / 16 + 4 i, column l % 16 of a 16 x 16 block
-    double *out = part + (int64_t)blockIdx.x * kRrTile * kRrTile;
+    if (!mm) return;
+    const auto out = gmem(part) + (int64_t)blockIdx.x * kRrTile * kRrTile;
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < 4; ++y)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int row = 32 * wa + 16 * x + (l >> 4) + 4 * i, col = 32 * wb + 16 * y + (l & 15);
+                const int row = 64 * qa + 16 * x + (l >> 4) + 4 * i, col = 64 * qb + 16 * y + (l & 15);
                 out[row * kRrTile + col] = acc[x][y][i];
             }
 }
@@ -210,12 +347,16 @@ void launch_rr_h(const CscView &A, int64_t N, int32_t k, const double *U0, doubl
     const int32_t T = (k + kRrTile - 1) / kRrTile;
     const int32_t R = rr_ranges(N, k);
     const unsigned blocks = (unsigned)(T * (T + 1) / 2 * R);
-    if (A.dtype == 1)
-        hipLaunchKernelGGL(k_rr_syrk<double>, dim3(blocks), dim3(256), 0, s, A.colptr, A.rowidx,
-                           static_cast<const double *>(A.values), N, k, R, U0, part);
-    else
-        hipLaunchKernelGGL(k_rr_syrk<float>, dim3(blocks), dim3(256), 0, s, A.colptr, A.rowidx,
-                           static_cast<const float *>(A.values), N, k, R, U0, part);
+    const bool even = (k & 1) == 0;
+    if (A.dtype == 1) {
+        const double *v = static_cast<const double *>(A.values);
+        if (even) hipLaunchKernelGGL((k_rr_syrk<double, true>), dim3(blocks), dim3(256), 0, s, A.colptr, A.rowidx, v, N, k, R, U0, part);
+        else hipLaunchKernelGGL((k_rr_syrk<double, false>), dim3(blocks), dim3(256), 0, s, A.colptr, A.rowidx, v, N, k, R, U0, part);
+    } else {
+        const float *v = static_cast<const float *>(A.values);
+        if (even) hipLaunchKernelGGL((k_rr_syrk<float, true>), dim3(blocks), dim3(256), 0, s, A.colptr, A.rowidx, v, N, k, R, U0, part);
+        else hipLaunchKernelGGL((k_rr_syrk<float, false>), dim3(blocks), dim3(256), 0, s, A.colptr, A.rowidx, v, N, k, R, U0, part);
+    }
     int64_t rb = ((int64_t)npad * npad + 255) / 256;
     if (rb > 4096) rb = 4096;
     hipLaunchKernelGGL(k_rr_syrk_reduce, dim3((unsigned)rb), dim3(256), 0, s, part, k, R, npad, H);

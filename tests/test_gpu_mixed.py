@@ -71,6 +71,31 @@ def test_mixed_refined_against_fp64_oracle(R, orc, name):
     assert err <= 1e-10
 
 
+@pytest.mark.parametrize("k", [77, 129, 300])
+def test_refine_tiles_and_odd_k(R, orc, k):
+    """The Rayleigh-Ritz H = Z^T Z over one tile (odd k: U0 rows are not 16-byte aligned),
+    two tiles (one off-diagonal tile) and three tiles of H."""
+    import torch
+
+    A = gen.random_sparse(320, 30000, 0.01, seed=21, dtype=np.float32)
+    ref = orc.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=k, method="whole_qr")
+    got = R.svd(R.to_device(A), k, 0.0, n_blocks=8, gram_prec="fp32", refine=1, v_dtype=torch.float32)
+    err = check(A, got, ref, 1e-6)
+    assert err <= 1e-10
+
+
+def test_refine_dense_columns(R, orc):
+    """Columns with ~100 nonzeros: a 16-column chunk holds more nonzeros than the
+    Rayleigh-Ritz kernel stages in LDS, so the rest are read from memory."""
+    import torch
+
+    A = gen.random_sparse(320, 4000, 0.3, seed=22, dtype=np.float32)
+    ref = orc.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=64, method="whole_qr")
+    got = R.svd(R.to_device(A), 64, 0.0, n_blocks=8, gram_prec="fp32", refine=1, v_dtype=torch.float32)
+    err = check(A, got, ref, 1e-6)
+    assert err <= 1e-10
+
+
 def test_mixed_without_refinement_meets_the_mixed_bar(R, orc):
     import torch
 
