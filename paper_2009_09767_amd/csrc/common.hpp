@@ -31,6 +31,8 @@ constexpr int32_t kGramSeg = 1 << 16;
 constexpr int kDenseRows = 32;
 // Column entries each lane of the Gram walk loads ahead (one group of gathers in flight).
 constexpr int kGramStep = 4;
+// Column entries the occupancy scan loads per step.
+constexpr int kOccGroup = 8;
 // Free value of a Gram election tag (above every workgroup-wide lane id).
 constexpr int32_t kTagFree = 0x7fffffff;
 // Ints per matrix in the per-matrix read-back (status, M', rank, sweeps, not-converged,

@@ -10,6 +10,8 @@
 //
 // The same counts give the offsets of a stable counting sort of the nonzeros by
 // row (column order kept inside a row), used by the Gram pass.
+#include <algorithm>
+
 #include "batch.hpp"
 #include "common.hpp"
 #include "launch.hpp"
@@ -38,23 +40,40 @@ __device__ void occ_chunk(const MatDesc &d, const TV *__restrict__ vals, int64_t
     for (int32_t m = threadIdx.x; m < M; m += blockDim.x) lds_hist[m] = 0;
     __syncthreads();
     int32_t err = 0;
+    const auto colptr = gmem(d.colptr);
+    const auto rowidx = gmem(d.rowidx);
+    const auto gv = gmem(vals);
     for (int64_t j = c0 + threadIdx.x; j < c1; j += blockDim.x) {
-        const int64_t e0 = d.colptr[j], e1 = d.colptr[j + 1];
+        const int64_t e0 = colptr[j], e1 = colptr[j + 1];
         if (e0 < 0 || e1 < e0 || e1 > nnz) {
             err |= kStCsc;
             continue;
         }
         int32_t prev = -1;
-        for (int64_t e = e0; e < e1; ++e) {
-            const int32_t r = d.rowidx[e];
-            if (r < 0 || r >= M) {
-                err |= kStCsc;
-                continue;
+        // kOccGroup entries per step, loaded unconditionally (clamped to the column's last
+        // entry) so that they are all in flight before the first is used
+        for (int64_t e = e0; e < e1; e += kOccGroup) {
+            int32_t rr[kOccGroup];
+            bool fin[kOccGroup];
+#pragma unroll
+            for (int t = 0; t < kOccGroup; ++t) {
+                const int64_t x = e + t < e1 ? e + t : e1 - 1;
+                rr[t] = rowidx[x];
+                fin[t] = !d.validate || finite_value(gv[x]);
             }
-            if (r <= prev) err |= kStCsc;
-            prev = r;
-            atomicAdd(&lds_hist[r], 1);
-            if (d.validate && !finite_value(vals[e])) err |= kStNonfinite;
+#pragma unroll
+            for (int t = 0; t < kOccGroup; ++t) {
+                if (e + t >= e1) break;
+                const int32_t r = rr[t];
+                if (r < 0 || r >= M) {
+                    err |= kStCsc;
+                    continue;
+                }
+                if (r <= prev) err |= kStCsc;
+                prev = r;
+                atomicAdd(&lds_hist[r], 1);
+                if (!fin[t]) err |= kStNonfinite;
+            }
         }
     }
     if (threadIdx.x == 0) {
@@ -79,31 +98,39 @@ __global__ __launch_bounds__(256) void k_occ_chunks(const MatDesc *__restrict__ 
         occ_chunk<float>(d, static_cast<const float *>(d.values), c, lds_hist);
 }
 
-// One thread per row: per-block occupancy (sum of the block's chunk histograms),
-// lonely / single-entry row counts per block, and the row's total.
+// One thread per (block, row): the block's occupancy of the row (sum of its chunk
+// histograms), the lonely / single-entry row counts of the block, and the row's total
+// (integer atomics: exact, so independent of their order).  Blocks b = blockIdx.y,
+// + gridDim.y, ...
 __global__ __launch_bounds__(256) void k_occ_rows(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
                                                   int count) {
     const int mat = find_mat(wp, count, blockIdx.x);
     const MatDesc &d = descs[mat];
-    const int32_t M = d.M, D = d.D, cpb = d.cpb;
+    const int32_t M = d.M, cpb = d.cpb;
     const int32_t m = (blockIdx.x - wp[mat]) * blockDim.x + threadIdx.x;
     const bool valid = m < M;
     const int lane = threadIdx.x & 63;
     int32_t total = 0;
-    for (int32_t b = 0; b < D; ++b) {
+    for (int32_t b = blockIdx.y; b < d.D; b += gridDim.y) {
+        const auto hist = gmem(d.hist) + (int64_t)b * cpb * M + (valid ? m : 0);
         int32_t cb = 0;
-        if (valid)
-            for (int32_t t = 0; t < cpb; ++t) cb += d.hist[((int64_t)b * cpb + t) * M + m];
+        int32_t t = 0;
+        for (; t + 4 <= cpb; t += 4) {
+            const int32_t h0 = hist[(int64_t)t * M], h1 = hist[(int64_t)(t + 1) * M];
+            const int32_t h2 = hist[(int64_t)(t + 2) * M], h3 = hist[(int64_t)(t + 3) * M];
+            cb += h0 + h1 + h2 + h3;
+        }
+        for (; t < cpb; ++t) cb += hist[(int64_t)t * M];
         if (valid && d.cnt) d.cnt[(int64_t)b * M + m] = cb;
-        total += cb;
         const uint64_t z = __ballot(valid && cb == 0);
-        const uint64_t s = __ballot(valid && cb == 1);
+        const uint64_t sg = __ballot(valid && cb == 1);
         if (lane == 0) {
             if (z) atomicAdd(&d.lonely[b], __popcll(z));
-            if (s) atomicAdd(&d.single[b], __popcll(s));
+            if (sg) atomicAdd(&d.single[b], __popcll(sg));
         }
+        total += cb;
     }
-    if (valid) d.rownnz[m] = total;
+    if (valid && total) atomicAdd(&d.rownnz[m], total);
 }
 
 // One workgroup of 1024 threads: exclusive scan of the row counts (row pointers of
@@ -223,19 +250,54 @@ __global__ __launch_bounds__(1024) void k_occ_scan(const MatDesc *__restrict__ d
     }
 }
 
-// One thread per row: turn the chunk histograms into the start offset of every
-// (chunk, row) run in the row-major copy (row pointer + earlier chunks), in place.
-__global__ __launch_bounds__(256) void k_occ_offsets(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
-                                                     int count) {
+// Turn the chunk histograms into the start offset of every (chunk, row) run in the
+// row-major copy (row pointer + earlier chunks), in place.  A workgroup of 1024 threads
+// takes 64 rows (lanes) and cuts the chunks into 16 contiguous segments (waves): each
+// wave sums its segment, the segment totals are scanned in LDS, and each wave rewrites
+// its segment from its starting offset.  Integer sums: exact.  blockIdx.y = which 64
+// rows of the 256-row tile.
+__global__ __launch_bounds__(1024) void k_occ_offsets(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
+                                                      int count) {
+    __shared__ int32_t seg_sum[16][64];
     const int mat = find_mat(wp, count, blockIdx.x);
     const MatDesc &d = descs[mat];
     const int32_t M = d.M;
-    const int32_t m = (blockIdx.x - wp[mat]) * blockDim.x + threadIdx.x;
-    if (m >= M) return;
-    int32_t run = d.rowptr[m];
-    for (int64_t c = 0; c < d.nchunks; ++c) {
-        const int32_t h = d.hist[c * M + m];
-        d.hist[c * M + m] = run;
+    const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
+    const int32_t m = (blockIdx.x - wp[mat]) * 256 + blockIdx.y * 64 + lane;
+    if ((blockIdx.x - wp[mat]) * 256 + blockIdx.y * 64 >= M) return;   // uniform per workgroup
+    const bool valid = m < M;
+    const int64_t nch = d.nchunks, per = (nch + 15) / 16;
+    const int64_t c0 = seg * per < nch ? seg * per : nch, c1 = c0 + per < nch ? c0 + per : nch;
+    const auto hist = gmem(d.hist) + (valid ? m : 0);
+    int32_t sum = 0;
+    int64_t c = c0;
+    for (; c + 8 <= c1; c += 8) {
+        int32_t h[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) h[t] = hist[(c + t) * M];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) sum += h[t];
+    }
+    for (; c < c1; ++c) sum += hist[c * M];
+    seg_sum[seg][lane] = sum;
+    __syncthreads();
+    if (!valid) return;
+    int32_t run = gmem(d.rowptr)[m];
+    for (int s = 0; s < seg; ++s) run += seg_sum[s][lane];
+    c = c0;
+    for (; c + 8 <= c1; c += 8) {
+        int32_t h[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) h[t] = hist[(c + t) * M];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            hist[(c + t) * M] = run;
+            run += h[t];
+        }
+    }
+    for (; c < c1; ++c) {
+        const int32_t h = hist[c * M];
+        hist[c * M] = run;
         run += h;
     }
 }
@@ -248,55 +310,110 @@ __global__ __launch_bounds__(256) void k_occ_offsets(const MatDesc *__restrict__
 // the row's running offset plus that rank; the lowest lane then advances the offset.
 // csr_k[slot] = CSC position of the entry, csr_end[slot] = end of its column,
 // csr_col[slot] = its column.
+// The first kTrRegs row indices of each lane's column are held in registers for the
+// four passes, loaded (with the next group's column bounds) while the previous group's
+// passes run; entries past kTrRegs are read from memory in each pass.
+constexpr int kTrRegs = 24;
+
+__device__ __forceinline__ void tr_load_rows(__attribute__((address_space(1))) const int32_t *rowidx, int32_t e0,
+                                             int32_t e1, int32_t (&rows)[kTrRegs]) {
+    const int32_t n = e1 - e0;
+#pragma unroll
+    for (int t = 0; t < kTrRegs; ++t) {
+        // a valid address for every lane: entry 0 exists (the kernel returns when nnz = 0)
+        const int32_t x = n > 0 ? e0 + (t < n ? t : n - 1) : 0;
+        rows[t] = rowidx[x];
+    }
+}
+
 __global__ __launch_bounds__(64) void k_transpose(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
                                                   int count) {
     const int mat = find_mat(wp, count, blockIdx.x);
     const MatDesc &d = descs[mat];
+    if (d.nnz == 0) return;
     const int32_t M = d.M;
-    const int32_t *__restrict__ colptr = d.colptr;
-    const int32_t *__restrict__ rowidx = d.rowidx;
-    int32_t *__restrict__ csr_k = d.csrk;
-    int32_t *__restrict__ csr_end = d.csrend;
-    int32_t *__restrict__ csr_col = d.csrcol;
+    const auto colptr = gmem(d.colptr);
+    const auto rowidx = gmem(d.rowidx);
+    const auto csr_k = gmem(d.csrk);
+    const auto csr_end = gmem(d.csrend);
+    const auto csr_col = gmem(d.csrcol);
     extern __shared__ uint64_t lds_mask[];
     int32_t *ctr = reinterpret_cast<int32_t *>(lds_mask + M);
     const int64_t c = blockIdx.x - wp[mat];
     int64_t c0, c1;
     chunk_columns(c, d.cpb, d.N, d.D, d.bstart, c0, c1);
-    const int32_t *off = d.hist + c * (int64_t)M;
+    const auto off = gmem(d.hist) + c * (int64_t)M;
     for (int32_t m = threadIdx.x; m < M; m += 64) {
         lds_mask[m] = 0;
         ctr[m] = off[m];
     }
-    __syncthreads();
     const int lane = threadIdx.x;
     const uint64_t bit = 1ull << lane;
     const uint64_t lower = bit - 1;
+    int32_t e0 = 0, e1 = 0;
+    if (c0 + lane < c1) {
+        e0 = colptr[c0 + lane];
+        e1 = colptr[c0 + lane + 1];
+    }
+    int32_t rows[kTrRegs];
+    tr_load_rows(rowidx, e0, e1, rows);
+    __syncthreads();
     for (int64_t g = c0; g < c1; g += 64) {
         const int64_t j = g + lane;
-        int32_t e0 = 0, e1 = 0;
-        if (j < c1) {
-            e0 = colptr[j];
-            e1 = colptr[j + 1];
+        const int32_t n = e1 - e0;
+        // next group: bounds now, its rows after pass 1 (they are in flight during passes 2-4)
+        int32_t f0 = 0, f1 = 0;
+        if (j + 64 < c1) {
+            f0 = colptr[j + 64];
+            f1 = colptr[j + 65];
         }
-        for (int32_t e = e0; e < e1; ++e) atomicOr(reinterpret_cast<unsigned long long *>(&lds_mask[rowidx[e]]), bit);
+#pragma unroll
+        for (int t = 0; t < kTrRegs; ++t)
+            if (t < n) atomicOr(reinterpret_cast<unsigned long long *>(&lds_mask[rows[t]]), bit);
+        for (int32_t t = kTrRegs; t < n; ++t)
+            atomicOr(reinterpret_cast<unsigned long long *>(&lds_mask[rowidx[e0 + t]]), bit);
+        int32_t next[kTrRegs];
+        tr_load_rows(rowidx, f0, f1, next);
         __syncthreads();
-        for (int32_t e = e0; e < e1; ++e) {
-            const int32_t r = rowidx[e];
+#pragma unroll
+        for (int t = 0; t < kTrRegs; ++t)
+            if (t < n) {
+                const int32_t r = rows[t];
+                const int32_t slot = ctr[r] + __popcll(lds_mask[r] & lower);
+                csr_k[slot] = e0 + t;
+                csr_end[slot] = e1;
+                csr_col[slot] = (int32_t)j;
+            }
+        for (int32_t t = kTrRegs; t < n; ++t) {
+            const int32_t r = rowidx[e0 + t];
             const int32_t slot = ctr[r] + __popcll(lds_mask[r] & lower);
-            csr_k[slot] = e;
+            csr_k[slot] = e0 + t;
             csr_end[slot] = e1;
             csr_col[slot] = (int32_t)j;
         }
         __syncthreads();
-        for (int32_t e = e0; e < e1; ++e) {
-            const int32_t r = rowidx[e];
+#pragma unroll
+        for (int t = 0; t < kTrRegs; ++t)
+            if (t < n) {
+                const int32_t r = rows[t];
+                const uint64_t mk = lds_mask[r];
+                if ((mk & lower) == 0) ctr[r] += __popcll(mk);
+            }
+        for (int32_t t = kTrRegs; t < n; ++t) {
+            const int32_t r = rowidx[e0 + t];
             const uint64_t mk = lds_mask[r];
             if ((mk & lower) == 0) ctr[r] += __popcll(mk);
         }
         __syncthreads();
-        for (int32_t e = e0; e < e1; ++e) lds_mask[rowidx[e]] = 0;
+#pragma unroll
+        for (int t = 0; t < kTrRegs; ++t)
+            if (t < n) lds_mask[rows[t]] = 0;
+        for (int32_t t = kTrRegs; t < n; ++t) lds_mask[rowidx[e0 + t]] = 0;
         __syncthreads();
+        e0 = f0;
+        e1 = f1;
+#pragma unroll
+        for (int t = 0; t < kTrRegs; ++t) rows[t] = next[t];
     }
 }
 
@@ -308,6 +425,7 @@ __global__ __launch_bounds__(256) void k_batch_prep(const MatDesc *__restrict__ 
         d.lonely[b] = 0;
         d.single[b] = 0;
     }
+    for (int32_t m = threadIdx.x; m < d.M; m += blockDim.x) d.rownnz[m] = 0;
 }
 
 // Gather every matrix's scalars into one compact array for a single read-back:
@@ -378,16 +496,18 @@ void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s) {
 }
 
 void launch_occupancy(const MatDesc *descs, const int32_t *wp_chunks, int64_t n_chunk_blocks,
-                      const int32_t *wp_rows, int64_t n_row_blocks, int count, int32_t maxM, hipStream_t s) {
+                      const int32_t *wp_rows, int64_t n_row_blocks, int count, int32_t maxM, int32_t maxD,
+                      hipStream_t s) {
     hipLaunchKernelGGL(k_occ_chunks, dim3((unsigned)n_chunk_blocks), dim3(256), sizeof(int32_t) * (size_t)maxM, s,
                        descs, wp_chunks, count);
-    hipLaunchKernelGGL(k_occ_rows, dim3((unsigned)n_row_blocks), dim3(256), 0, s, descs, wp_rows, count);
+    hipLaunchKernelGGL(k_occ_rows, dim3((unsigned)n_row_blocks, (unsigned)std::min(maxD, 1024)), dim3(256), 0, s,
+                       descs, wp_rows, count);
     hipLaunchKernelGGL(k_occ_scan, dim3((unsigned)count), dim3(1024), 0, s, descs);
 }
 
 void launch_row_offsets(const MatDesc *descs, const int32_t *wp_rows, int64_t n_row_blocks, int count, hipStream_t s) {
     if (n_row_blocks <= 0) return;
-    hipLaunchKernelGGL(k_occ_offsets, dim3((unsigned)n_row_blocks), dim3(256), 0, s, descs, wp_rows, count);
+    hipLaunchKernelGGL(k_occ_offsets, dim3((unsigned)n_row_blocks, 4), dim3(1024), 0, s, descs, wp_rows, count);
 }
 
 void launch_transpose(const MatDesc *descs, const int32_t *wp_chunks, int64_t n_chunk_blocks, int count, int32_t maxM,

@@ -24,7 +24,8 @@ void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 void launch_batch_prep(const MatDesc *descs, int count, hipStream_t s);
 void launch_batch_collect(const MatDesc *descs, int count, int32_t *out_i32, double *out_f64, hipStream_t s);
 void launch_occupancy(const MatDesc *descs, const int32_t *wp_chunks, int64_t n_chunk_blocks,
-                      const int32_t *wp_rows, int64_t n_row_blocks, int count, int32_t maxM, hipStream_t s);
+                      const int32_t *wp_rows, int64_t n_row_blocks, int count, int32_t maxM, int32_t maxD,
+                      hipStream_t s);
 void launch_row_offsets(const MatDesc *descs, const int32_t *wp_rows, int64_t n_row_blocks, int count, hipStream_t s);
 void launch_transpose(const MatDesc *descs, const int32_t *wp_chunks, int64_t n_chunk_blocks, int count, int32_t maxM,
                       hipStream_t s);

@@ -376,14 +376,18 @@ struct Engine {
 
     // Alg. 1 scan, validation and structural rank of every matrix; sets n / npad.
     ranky_status scan() {
-        for (const MatDesc &x : d) maxM = std::max(maxM, x.M);
+        int32_t maxD = 1;
+        for (const MatDesc &x : d) {
+            maxM = std::max(maxM, x.M);
+            maxD = std::max(maxD, x.D);
+        }
         nblk[kPhChunks] = fill_wp(hwp(kPhChunks), count, [&](int i) { return d[i].nchunks; });
         nblk[kPhRows] = fill_wp(hwp(kPhRows), count, [&](int i) { return (int64_t)(d[i].M + 255) / 256; });
         ranky_status st = upload_desc();
         if (!st) st = upload(h.o_wp, sizeof(int32_t) * (size_t)kPhCount * (h.slots + 1));
         if (st) return st;
         launch_batch_prep(ddesc(), count, s);
-        launch_occupancy(ddesc(), dwp(kPhChunks), nblk[kPhChunks], dwp(kPhRows), nblk[kPhRows], count, maxM, s);
+        launch_occupancy(ddesc(), dwp(kPhChunks), nblk[kPhChunks], dwp(kPhRows), nblk[kPhRows], count, maxM, maxD, s);
         HIP_TRY(hipGetLastError());
         std::vector<int32_t> iv;
         std::vector<double> fv;
