@@ -488,16 +488,23 @@ struct Engine {
         launch_transpose(ddesc(), dwp(kPhChunks), nblk[kPhChunks], count, maxM, s);
     }
 
-    void enqueue_sweep() {
+    // the next sweep's activity: convergence test of the current matrices, then active =
+    // not converged and under the sweep cap
+    void enqueue_activity() {
         launch_jacobi_check(ddesc(), dwp(kPhJcheck), nblk[kPhJcheck], count, s);
         launch_jacobi_state(ddesc(), count, 0, sweeps_cap, s);
-        for (int r = 0; r < nb_max; ++r) launch_jacobi_round(hrtab(r), drtab(r), drwp(r), rblk[r], count, r, jround_lds, s);
-        launch_jacobi_state(ddesc(), count, 1, sweeps_cap, s);
     }
 
-    // Jacobi on every live matrix.  Each sweep = convergence test, activity update,
-    // nb_max round launches, sweep count; one read-back per sweep decides whether
-    // any matrix is still active.  With use_graph the sweep is a replayed HIP graph.
+    void enqueue_sweep() {
+        for (int r = 0; r < nb_max; ++r) launch_jacobi_round(hrtab(r), drtab(r), drwp(r), rblk[r], count, r, jround_lds, s);
+        launch_jacobi_state(ddesc(), count, 1, sweeps_cap, s);
+        enqueue_activity();
+    }
+
+    // Jacobi on every live matrix.  Each sweep = nb_max round launches, sweep count, then
+    // the convergence test and activity of the next sweep; one read-back per sweep decides
+    // whether any matrix is still active, so no sweep is launched only to find that the
+    // previous one converged.  With use_graph the sweep is a replayed HIP graph.
     ranky_status eigensolve(bool use_graph) {
         launch_jacobi_init(ddesc(), dwp(kPhJinit), nblk[kPhJinit], count, s);
         HIP_TRY(hipGetLastError());
@@ -533,17 +540,31 @@ struct Engine {
         }
         std::vector<int32_t> iv;
         std::vector<double> fv;
-        for (int32_t sw = 0; sw <= sweeps_cap; ++sw) {
+        auto any_active = [&]() {
+            bool a = false;
+            for (int i = 0; i < count; ++i) a |= iv[kColI * i + 7] != 0;
+            return a;
+        };
+        // the first sweep's activity (read back only when its rounds are timed; otherwise a
+        // matrix that is already diagonal just runs one sweep of rounds that exit at once)
+        enqueue_activity();
+        HIP_TRY(hipGetLastError());
+        bool active = true;
+        if (time_rounds) {
+            ranky_status st = collect(iv, fv);
+            if (st) return st;
+            active = any_active();
+        }
+        for (int32_t sw = 0; sw <= sweeps_cap && active; ++sw) {
             if (exec) {
                 HIP_TRY(hipGraphLaunch(exec, s));
             } else if (time_rounds) {
-                launch_jacobi_check(ddesc(), dwp(kPhJcheck), nblk[kPhJcheck], count, s);
-                launch_jacobi_state(ddesc(), count, 0, sweeps_cap, s);
                 HIP_TRY(hipEventRecord(ctx->ev[9], s));
                 for (int r = 0; r < nb_max; ++r)
                     launch_jacobi_round(hrtab(r), drtab(r), drwp(r), rblk[r], count, r, jround_lds, s);
                 HIP_TRY(hipEventRecord(ctx->ev[10], s));
                 launch_jacobi_state(ddesc(), count, 1, sweeps_cap, s);
+                enqueue_activity();
                 HIP_TRY(hipGetLastError());
             } else {
                 enqueue_sweep();
@@ -551,20 +572,15 @@ struct Engine {
             }
             ranky_status st = collect(iv, fv);
             if (st) return st;
-            bool still = false;
-            for (int i = 0; i < count; ++i) still |= iv[kColI * i + 7] != 0;
-            if (time_rounds && still) {
+            if (time_rounds) {
                 float t = 0.f;
                 HIP_TRY(hipEventElapsedTime(&t, ctx->ev[9], ctx->ev[10]));
                 round_ms += t;
                 for (int r = 0; r < nb_max; ++r) round_launches += rblk[r] > 0 ? 1 : 0;
             }
-            if (!still) break;
+            active = any_active();
         }
-        // convergence test of the final matrices, for the report
-        launch_jacobi_check(ddesc(), dwp(kPhJcheck), nblk[kPhJcheck], count, s);
-        ranky_status st = collect(iv, fv);
-        if (st) return st;
+        // the last read-back holds the convergence test of the final matrices
         for (int i = 0; i < count; ++i) {
             sweeps[i] = iv[kColI * i + 3];
             notconv[i] = iv[kColI * i + 4];
