@@ -6,8 +6,12 @@
 
 namespace ranky {
 
-// Columns handled by one workgroup of the occupancy and transpose passes.
+// Columns handled by one workgroup of the occupancy and transpose passes: at most
+// kChunkCols, halved down to kChunkColsMin while a matrix has fewer than kChunkTarget
+// chunks (so a matrix of a million columns still fills the device).
 constexpr int kChunkCols = 4096;
+constexpr int kChunkColsMin = 512;
+constexpr int kChunkTarget = 1024;
 
 // Bits of the device status word.
 enum : int32_t { kStCsc = 1, kStNonfinite = 2 };
@@ -42,13 +46,13 @@ enum : int32_t { kSdTau = 0, kSdSigmaMax = 1, kSdFloor = 2, kSdScale = 3, kSdCou
 
 // Column range of chunk c: block b = c / cpb owns columns [floor(bN/D), floor((b+1)N/D)),
 // or [bstart[b], bstart[b+1]) when the caller gave the boundaries, and its t-th chunk
-// (t = c % cpb) is the t-th run of kChunkCols columns of it.
-__device__ __forceinline__ void chunk_columns(int64_t c, int32_t cpb, int64_t N, int32_t D,
+// (t = c % cpb) is the t-th run of cc columns of it.
+__device__ __forceinline__ void chunk_columns(int64_t c, int32_t cpb, int32_t cc, int64_t N, int32_t D,
                                               const int64_t *__restrict__ bstart, int64_t &c0, int64_t &c1) {
     const int64_t b = c / cpb, t = c % cpb;
     const int64_t bs = bstart ? bstart[b] : (b * N) / D, be = bstart ? bstart[b + 1] : ((b + 1) * N) / D;
-    c0 = bs + t * kChunkCols;
-    c1 = c0 + kChunkCols < be ? c0 + kChunkCols : be;
+    c0 = bs + t * cc;
+    c1 = c0 + cc < be ? c0 + cc : be;
     if (c0 > c1) c0 = c1;
 }
 

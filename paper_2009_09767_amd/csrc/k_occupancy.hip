@@ -36,7 +36,7 @@ __device__ void occ_chunk(const MatDesc &d, const TV *__restrict__ vals, int64_t
     const int32_t M = d.M;
     const int64_t N = d.N, nnz = d.nnz;
     int64_t c0, c1;
-    chunk_columns(c, d.cpb, N, d.D, d.bstart, c0, c1);
+    chunk_columns(c, d.cpb, d.ccols, N, d.D, d.bstart, c0, c1);
     for (int32_t m = threadIdx.x; m < M; m += blockDim.x) lds_hist[m] = 0;
     __syncthreads();
     int32_t err = 0;
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(64) void k_transpose(const MatDesc *__restrict__ de
     int32_t *ctr = reinterpret_cast<int32_t *>(lds_mask + M);
     const int64_t c = blockIdx.x - wp[mat];
     int64_t c0, c1;
-    chunk_columns(c, d.cpb, d.N, d.D, d.bstart, c0, c1);
+    chunk_columns(c, d.cpb, d.ccols, d.N, d.D, d.bstart, c0, c1);
     const auto off = gmem(d.hist) + c * (int64_t)M;
     for (int32_t m = threadIdx.x; m < M; m += 64) {
         lds_mask[m] = 0;

@@ -86,7 +86,7 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 // ---------------------------------------------------------------------------
 
 struct Plan {
-    int32_t M = 0, k = 0, D = 0, cpb = 0, npad = 0;
+    int32_t M = 0, k = 0, D = 0, cpb = 0, ccols = 0, npad = 0;
     int64_t N = 0, nnz = 0, nchunks = 0;
     size_t o_scal = 0, o_sdbl = 0, o_jstate = 0, o_hist = 0, o_rownnz = 0, o_rowptr = 0, o_m2r = 0, o_r2m = 0;
     size_t o_empty = 0, o_lonely = 0, o_single = 0, o_csrk = 0, o_csrend = 0, o_csrcol = 0;
@@ -112,8 +112,13 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool sol
         maxw = 0;
         for (int32_t b = 0; b < D; ++b) maxw = std::max<int64_t>(maxw, bstart[b + 1] - bstart[b]);
     }
-    p.cpb = (int32_t)((maxw + kChunkCols - 1) / kChunkCols);
-    if (p.cpb < 1) p.cpb = 1;
+    // chunks of kChunkCols columns, halved (down to kChunkColsMin) while the matrix has
+    // fewer than kChunkTarget of them: the scan and the transpose run one workgroup per
+    // chunk, and the row-major copy does not depend on the cut
+    p.ccols = kChunkCols;
+    auto chunks_of = [&](int64_t cc) { return (int64_t)D * std::max<int64_t>(1, (maxw + cc - 1) / cc); };
+    while (p.ccols > kChunkColsMin && chunks_of(p.ccols) < kChunkTarget) p.ccols /= 2;
+    p.cpb = (int32_t)std::max<int64_t>(1, (maxw + p.ccols - 1) / p.ccols);
     p.nchunks = (int64_t)D * p.cpb;
     p.npad = jacobi_npad(M);
     size_t off = 0;
@@ -180,6 +185,7 @@ MatDesc carve(const Plan &p, char *base, Refine *rf) {
     d.k = p.k;
     d.D = p.D;
     d.cpb = p.cpb;
+    d.ccols = p.ccols;
     d.bstart = p.explicit_blocks ? reinterpret_cast<const int64_t *>(base + p.o_bstart) : nullptr;
     d.nchunks = p.nchunks;
     d.npad = kJacobiPair;
