@@ -20,6 +20,7 @@ struct MatDesc {
     const int64_t *bstart;    // D + 1 column boundaries of the blocks, or NULL for floor(bN/D)
     int32_t M, k, D, cpb;
     int32_t ccols;            // columns per chunk (the last chunk of a block may be shorter)
+    int32_t gseg;             // Gram segment length (nonzeros of a row per workgroup)
     int32_t dtype, v_dtype;
     int32_t n, npad;          // non-empty rows and the eigensolver order (set after the scan)
     int32_t prec;             // Gram accumulation: 0 FP64, 1 FP32

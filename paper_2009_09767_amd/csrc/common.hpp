@@ -29,6 +29,16 @@ enum : int32_t {
 // Nonzeros of one row segment of the Gram: a longer row is cut into segments handled by
 // separate workgroups, whose partial rows are added in segment order.
 constexpr int32_t kGramSeg = 1 << 16;
+// A matrix's segment length: nnz / kGramSegTarget rounded down to a power of two, within
+// [kGramSegMin, kGramSeg], so that a few dense rows of a small matrix do not leave one
+// workgroup with most of the work.  A function of the matrix alone (not of D).
+constexpr int32_t kGramSegMin = 1 << 12;
+constexpr int64_t kGramSegTarget = 1024;
+inline int32_t gram_seg_len(int64_t nnz) {
+    int32_t s = kGramSeg;
+    while (s > kGramSegMin && (int64_t)s * kGramSegTarget > nnz) s >>= 1;
+    return s;
+}
 // Densest rows of the Gram (at most this many, each with at least max(4096, N / 64)
 // nonzeros): their products go to lane-private slots instead of the shared row, since
 // most lanes of a wave would otherwise meet on the same few rows.

@@ -27,9 +27,9 @@
 // lanes of a wave would elect on the same few addresses; their products go instead to
 // lane-private LDS slots, reduced over the lanes by a fixed shuffle tree at the end.
 //
-// A row with more than kGramSeg nonzeros is cut into segments of kGramSeg consecutive
-// nonzeros (in column order), one workgroup each, so a dense row does not serialise
-// the whole launch.  Each segment writes its partial row (FP64) to a slot, and
+// A row with more than gseg nonzeros (a per-matrix power of two, at most 2^16) is cut
+// into segments of gseg consecutive nonzeros (in column order), one workgroup each, so
+// a dense row does not serialise the whole launch.  Each segment writes its partial row (FP64) to a slot, and
 // k_gram_reduce adds the slots in segment order: the sum order is a function of the
 // row alone (not of the block count D or of timing).  Rows of one segment write G
 // directly, as before.
@@ -87,8 +87,9 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
 
     const int32_t p = r2m[i];
     const int32_t r_begin = rowptr[p], r_end = rowptr[p + 1];
-    const int32_t e_begin = r_begin + seg * kGramSeg;
-    const int32_t e_end = (nseg == 1 || r_end - e_begin <= kGramSeg) ? r_end : e_begin + kGramSeg;
+    const int32_t gs = dsc.gseg;
+    const int32_t e_begin = r_begin + seg * gs;
+    const int32_t e_end = (nseg == 1 || r_end - e_begin <= gs) ? r_end : e_begin + gs;
     const int32_t deg = e_end - e_begin;
     const int32_t run = (deg + nw - 1) / nw;   // contiguous run of this segment per wave
     const int32_t wb = e_begin + wave * run;
@@ -294,9 +295,10 @@ void launch_gram(const MatDesc *descs, const int32_t *wp, int64_t nblocks, const
 }
 
 int64_t gram_part_slots(int64_t nnz) {
-    // rows longer than kGramSeg number at most nnz / kGramSeg, and each takes at most
-    // deg / kGramSeg + 1 slots
-    return nnz > kGramSeg ? 2 * (nnz / kGramSeg) + 1 : 0;
+    // rows longer than the segment length s number at most nnz / s, and each takes at
+    // most deg / s + 1 slots
+    const int64_t s = gram_seg_len(nnz);
+    return nnz > s ? 2 * (nnz / s) + 1 : 0;
 }
 
 hipError_t gram_set_attributes(size_t lds_limit) {

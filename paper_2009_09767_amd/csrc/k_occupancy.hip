@@ -152,9 +152,10 @@ __global__ __launch_bounds__(1024) void k_occ_scan(const MatDesc *__restrict__ d
     __shared__ int32_t s_ne[1024], s_seg[1024], s_slot[1024];
     const int32_t per = (M + 1023) / 1024;
     const int32_t m0 = threadIdx.x * per;
-    // a nonempty row of deg nonzeros takes ceil(deg / kGramSeg) Gram segments, and as many
+    // a nonempty row of deg nonzeros takes ceil(deg / gseg) Gram segments, and as many
     // partial rows when that is more than one
-    auto segs = [](int32_t deg) { return (int32_t)(((int64_t)deg + kGramSeg - 1) / kGramSeg); };
+    const int64_t gs = d.gseg;
+    auto segs = [gs](int32_t deg) { return (int32_t)(((int64_t)deg + gs - 1) / gs); };
     int64_t loc_nnz = 0;
     int32_t loc_ne = 0, loc_seg = 0, loc_slot = 0;
     for (int32_t m = m0; m < m0 + per && m < M; ++m) {

@@ -186,6 +186,7 @@ MatDesc carve(const Plan &p, char *base, Refine *rf) {
     d.D = p.D;
     d.cpb = p.cpb;
     d.ccols = p.ccols;
+    d.gseg = gram_seg_len(p.nnz);
     d.bstart = p.explicit_blocks ? reinterpret_cast<const int64_t *>(base + p.o_bstart) : nullptr;
     d.nchunks = p.nchunks;
     d.npad = kJacobiPair;
