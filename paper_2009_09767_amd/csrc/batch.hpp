@@ -48,7 +48,8 @@ struct MatDesc {
     void *V;
 };
 
-enum : int32_t { kJsSweeps = 0, kJsActive = 1, kJsNotConv = 2, kJsCount = 4 };
+// kJsCheck: the running convergence test's flag, folded into kJsNotConv by the state update
+enum : int32_t { kJsSweeps = 0, kJsActive = 1, kJsNotConv = 2, kJsCheck = 3, kJsCount = 4 };
 
 // Matrix owning workgroup b: the last i with wp[i] <= b (wp has count + 1 entries).
 __device__ __forceinline__ int find_mat(const int32_t *__restrict__ wp, int count, int b) {

@@ -693,14 +693,16 @@ __global__ __launch_bounds__(256, 2) void k_jround(const RoundArgs one, const Ro
     update_tile(a, b * kTileWaves + wave, smem + wave * kP * kPS);
 }
 
-// The G buffer holding the matrix after `sweeps` complete sweeps.
-__device__ __forceinline__ const double *current_g(const MatDesc &d) {
+// The G buffer holding the matrix after `sweeps` complete sweeps (plus the sweep just run
+// when `pending`: the test at the end of a sweep runs before its count is updated).
+__device__ __forceinline__ const double *current_g(const MatDesc &d, bool pending = false) {
     const int32_t nb = d.npad / kB;
-    return ((d.jstate[kJsSweeps] * (nb - 1)) & 1) ? d.G2 : d.G;
+    const int32_t sw = d.jstate[kJsSweeps] + (pending ? d.jstate[kJsActive] : 0);
+    return ((sw * (nb - 1)) & 1) ? d.G2 : d.G;
 }
 
-// Sets jstate[kJsNotConv] = 1 if an off-diagonal entry of the leading n x n part
-// still fails the rotation test.  One workgroup per 64 x 64 tile (ti <= tj) of the
+// Sets jstate[kJsCheck] = 1 if an off-diagonal entry of the leading n x n part
+// still fails the rotation test (run at the end of a sweep, before the state update).  One workgroup per 64 x 64 tile (ti <= tj) of the
 // upper triangle; the tile's row and column diagonal entries are staged in LDS.
 __global__ __launch_bounds__(256) void k_jcheck(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
                                                 int count) {
@@ -710,7 +712,7 @@ __global__ __launch_bounds__(256) void k_jcheck(const MatDesc *__restrict__ desc
     const MatDesc &d = descs[mat];
     const int32_t n = d.n;
     const int64_t ld = d.npad;
-    const double *__restrict__ G = current_g(d);
+    const double *__restrict__ G = current_g(d, true);
     const double floor_abs = d.sdbl[kSdFloor];
     const double tol = d.jtol > 0.0 ? d.jtol : fmax(1e-15, sqrt((double)n) * 2.220446049250313e-16);
     const double tol2 = tol * tol;
@@ -739,25 +741,35 @@ __global__ __launch_bounds__(256) void k_jcheck(const MatDesc *__restrict__ desc
             if (fabs(g) > floor_abs && g * g > tol2 * fabs(drow[r] * dcol[c])) bad = 1;
         }
     }
-    if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(&d.jstate[kJsNotConv], 1);
+    if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(&d.jstate[kJsCheck], 1);
 }
 
 // Per matrix: start of a sweep (active = not converged and under the cap, clear the
 // flag) or end of a sweep (count it).
-__global__ __launch_bounds__(256) void k_jstate(const MatDesc *__restrict__ descs, int count, int32_t phase,
-                                                int32_t max_sweeps) {
+// End of a sweep, per matrix (after the rounds and the convergence test): count the sweep
+// if it ran, take the test's verdict, decide the next sweep (not converged and under the
+// cap), clear the test flag, and publish active / sweeps / not-converged to `out` (host
+// memory the caller reads after synchronising the stream; NULL: no copy).
+__global__ __launch_bounds__(256) void k_jstate(const MatDesc *__restrict__ descs, int count, int32_t max_sweeps,
+                                                int32_t *__restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     int32_t *js = descs[i].jstate;
-    if (descs[i].n <= 0) {
-        js[kJsActive] = 0;
-        return;
+    int32_t active = 0, sweeps = js[kJsSweeps], nc = 0;
+    if (descs[i].n > 0) {
+        sweeps += js[kJsActive];
+        nc = js[kJsCheck];
+        active = (nc != 0 && sweeps < max_sweeps) ? 1 : 0;
     }
-    if (phase == 0) {
-        js[kJsActive] = (js[kJsNotConv] != 0 && js[kJsSweeps] < max_sweeps) ? 1 : 0;
-    } else if (phase == 1) {
-        if (js[kJsActive]) js[kJsSweeps] += 1;
-        js[kJsNotConv] = 0;
+    js[kJsSweeps] = sweeps;
+    js[kJsNotConv] = nc;
+    js[kJsCheck] = 0;
+    js[kJsActive] = active;
+    if (out) {
+        out[3 * i + 0] = active;
+        out[3 * i + 1] = sweeps;
+        out[3 * i + 2] = nc;
+        __threadfence_system();
     }
 }
 
@@ -793,6 +805,7 @@ __global__ __launch_bounds__(256) void k_jinit(const MatDesc *__restrict__ descs
         d.jstate[kJsSweeps] = 0;
         d.jstate[kJsActive] = 0;
         d.jstate[kJsNotConv] = 0;
+        d.jstate[kJsCheck] = 0;
     }
 }
 
@@ -828,9 +841,9 @@ void launch_jacobi_init(const MatDesc *descs, const int32_t *wp, int64_t nblocks
     hipLaunchKernelGGL(k_jscale, dim3((unsigned)nblocks), dim3(256), 0, s, descs, wp, count);
 }
 
-void launch_jacobi_state(const MatDesc *descs, int count, int32_t phase, int32_t max_sweeps, hipStream_t s) {
-    hipLaunchKernelGGL(k_jstate, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, descs, count, phase,
-                       max_sweeps);
+void launch_jacobi_state(const MatDesc *descs, int count, int32_t max_sweeps, int32_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_jstate, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, descs, count, max_sweeps,
+                       out);
 }
 
 void launch_jacobi_round(const void *host_table, const void *table, const int32_t *wp, int64_t nblocks, int count,

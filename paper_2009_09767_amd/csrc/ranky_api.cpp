@@ -38,6 +38,7 @@ struct ranky_ctx {
     int cu_count = 0;
     size_t lds_limit = 0;      // dynamic LDS the Gram kernel may use per workgroup
     void *pinned = nullptr;    // host staging for descriptor uploads and scalar read-back
+    void *pinned_dev = nullptr;   // the same memory as a device address (kernels write sweep state there)
     size_t pinned_bytes = 0;
     hipEvent_t ev[11] = {};     // [0..7] phase marks, [9] [10] span of a sweep's round launches
     hipGraphExec_t sweep_graph = nullptr;  // captured Jacobi sweep of the last graph batch
@@ -235,7 +236,7 @@ MatDesc carve(const Plan &p, char *base, Refine *rf) {
 enum Phase { kPhChunks, kPhRows, kPhGram, kPhGramRed, kPhJinit, kPhJcheck, kPhJdiag, kPhGather, kPhBack, kPhBack2, kPhBack4, kPhCount };
 
 struct Header {
-    size_t o_desc = 0, o_wp = 0, o_rwp = 0, o_rtab = 0, o_col_i = 0, o_col_f = 0, total = 0;
+    size_t o_desc = 0, o_wp = 0, o_rwp = 0, o_rtab = 0, o_col_i = 0, o_col_f = 0, o_js = 0, total = 0;
     int32_t count = 0, slots = 0, nb_max = 0;
 };
 
@@ -256,6 +257,7 @@ Header make_header(int32_t count, int32_t slots, int32_t nb_max) {
     h.o_rtab = take(round_args_bytes() * (size_t)nb_max * slots);
     h.o_col_i = take(sizeof(int32_t) * kColI * slots);
     h.o_col_f = take(sizeof(double) * 2 * slots);
+    h.o_js = take(sizeof(int32_t) * 3 * slots);   // host only: the sweep state the device writes
     h.total = off;
     return h;
 }
@@ -311,9 +313,11 @@ ranky_status ensure_pinned(ranky_ctx *ctx, size_t bytes) {
     if (ctx->pinned_bytes >= bytes) return RANKY_OK;
     if (ctx->pinned) hipHostFree(ctx->pinned);
     ctx->pinned = nullptr;
+    ctx->pinned_dev = nullptr;
     ctx->pinned_bytes = 0;
     const size_t want = std::max<size_t>(bytes, 1 << 16);
     HIP_TRY(hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault));
+    HIP_TRY(hipHostGetDevicePointer(&ctx->pinned_dev, ctx->pinned, 0));
     ctx->pinned_bytes = want;
     return RANKY_OK;
 }
@@ -495,16 +499,25 @@ struct Engine {
         launch_transpose(ddesc(), dwp(kPhChunks), nblk[kPhChunks], count, maxM, s);
     }
 
-    // the next sweep's activity: convergence test of the current matrices, then active =
-    // not converged and under the sweep cap
+    // sweep state per matrix (active, sweeps, not converged), written by the device
+    int32_t *js_dev() { return reinterpret_cast<int32_t *>(static_cast<char *>(ctx->pinned_dev) + h.o_js); }
+    const int32_t *js_host() { return reinterpret_cast<const int32_t *>(stage() + h.o_js); }
+    bool any_active() {
+        const int32_t *js = js_host();
+        for (int i = 0; i < count; ++i)
+            if (js[3 * i] != 0) return true;
+        return false;
+    }
+
+    // end of a sweep: convergence test of the current matrices, then the state update
+    // (sweep count, verdict, next sweep's activity) published to host memory
     void enqueue_activity() {
         launch_jacobi_check(ddesc(), dwp(kPhJcheck), nblk[kPhJcheck], count, s);
-        launch_jacobi_state(ddesc(), count, 0, sweeps_cap, s);
+        launch_jacobi_state(ddesc(), count, sweeps_cap, js_dev(), s);
     }
 
     void enqueue_sweep() {
         for (int r = 0; r < nb_max; ++r) launch_jacobi_round(hrtab(r), drtab(r), drwp(r), rblk[r], count, r, jround_lds, s);
-        launch_jacobi_state(ddesc(), count, 1, sweeps_cap, s);
         enqueue_activity();
     }
 
@@ -524,6 +537,7 @@ struct Engine {
             for (int r = 0; r < nb_max; ++r) sig = sig * 31 + (size_t)rblk[r];
             for (int ph = 0; ph < kPhCount; ++ph) sig = sig * 31 + (size_t)nblk[ph];
             sig = sig * 31 + jround_lds;
+            sig = sig * 31 + reinterpret_cast<uintptr_t>(ctx->pinned_dev);
             // a single matrix's round arguments are captured by value: any change re-captures
             for (int r = 0; r < nb_max; ++r)
                 for (size_t i = 0, nb = round_args_bytes() * (size_t)count; i < nb; ++i)
@@ -545,21 +559,13 @@ struct Engine {
                 ctx->sweep_graph_sig = sig;
             }
         }
-        std::vector<int32_t> iv;
-        std::vector<double> fv;
-        auto any_active = [&]() {
-            bool a = false;
-            for (int i = 0; i < count; ++i) a |= iv[kColI * i + 7] != 0;
-            return a;
-        };
         // the first sweep's activity (read back only when its rounds are timed; otherwise a
         // matrix that is already diagonal just runs one sweep of rounds that exit at once)
         enqueue_activity();
         HIP_TRY(hipGetLastError());
         bool active = true;
         if (time_rounds) {
-            ranky_status st = collect(iv, fv);
-            if (st) return st;
+            HIP_TRY(hipStreamSynchronize(s));
             active = any_active();
         }
         for (int32_t sw = 0; sw <= sweeps_cap && active; ++sw) {
@@ -570,15 +576,13 @@ struct Engine {
                 for (int r = 0; r < nb_max; ++r)
                     launch_jacobi_round(hrtab(r), drtab(r), drwp(r), rblk[r], count, r, jround_lds, s);
                 HIP_TRY(hipEventRecord(ctx->ev[10], s));
-                launch_jacobi_state(ddesc(), count, 1, sweeps_cap, s);
                 enqueue_activity();
                 HIP_TRY(hipGetLastError());
             } else {
                 enqueue_sweep();
                 HIP_TRY(hipGetLastError());
             }
-            ranky_status st = collect(iv, fv);
-            if (st) return st;
+            HIP_TRY(hipStreamSynchronize(s));
             if (time_rounds) {
                 float t = 0.f;
                 HIP_TRY(hipEventElapsedTime(&t, ctx->ev[9], ctx->ev[10]));
@@ -587,10 +591,12 @@ struct Engine {
             }
             active = any_active();
         }
-        // the last read-back holds the convergence test of the final matrices
+        // the last state holds the convergence test of the final matrices (synchronise in
+        // case no sweep ran)
+        HIP_TRY(hipStreamSynchronize(s));
         for (int i = 0; i < count; ++i) {
-            sweeps[i] = iv[kColI * i + 3];
-            notconv[i] = iv[kColI * i + 4];
+            sweeps[i] = js_host()[3 * i + 1];
+            notconv[i] = js_host()[3 * i + 2];
         }
         launch_jacobi_diag(ddesc(), dwp(kPhJdiag), nblk[kPhJdiag], count, s);
         HIP_TRY(hipGetLastError());
