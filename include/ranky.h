@@ -61,10 +61,17 @@ typedef enum {
 typedef enum { RANKY_F32 = 0, RANKY_F64 = 1 } ranky_dtype;
 
 /* Precision of the Gram accumulation (step 2 of the path).  The eigensolve, the
- * rank decision and the Rayleigh-Ritz refinement are FP64 in every mode. */
+ * rank decision and the Rayleigh-Ritz refinement are FP64 in every mode.
+ * For a single matrix the Gram block of its densest rows (up to 32 rows with at least
+ * max(4096, N/64) nonzeros each) is computed as dense tiles on the matrix cores in the
+ * mode's precision; every other pair of rows goes through the sparse pass. */
 typedef enum {
-    RANKY_PREC_FP64 = 0, /* products and sums in FP64 (FP32 inputs are promoted exactly) */
-    RANKY_PREC_FP32 = 1  /* products and sums in FP32, merged into the FP64 Gram per row */
+    RANKY_PREC_FP64 = 0,  /* products and sums in FP64 (FP32 inputs are promoted exactly) */
+    RANKY_PREC_FP32 = 1,  /* products and sums in FP32, merged into the FP64 Gram per row */
+    RANKY_PREC_BF16X3 = 2 /* as FP32, with the dense tiles as split-bf16 products
+                             hi*hi + hi*lo + lo*hi (x = hi + lo, FP32 accumulation, FP64
+                             across 64-column steps): relative product error ~2^-16, so
+                             the refinement step is what brings sigma back */
 } ranky_prec;
 
 /* Compressed sparse columns.  colptr[0] = 0, colptr non-decreasing,

@@ -53,13 +53,16 @@ def _load():
     lib.ro_rank_prob.argtypes = [i64, i64]
     lib.ro_rank_prob.restype = dbl
     lib.ro_gram.argtypes = [i32, i64, vp, vp, vp, ctypes.c_int, vp]
+    lib.ro_bf16_split.argtypes = [i64, vp, vp, vp]
+    lib.ro_gram_bf16x3.argtypes = [i32, i64, vp, vp, vp, ctypes.c_int, i32, vp, vp]
     lib.ro_hestenes.argtypes = [i32, i64, vp, vp, vp, i32, vp]
     lib.ro_qr_r.argtypes = [i64, i32, vp, vp]
     lib.ro_eig_jacobi.argtypes = [i32, vp, vp, i32, vp]
     lib.ro_backproject.argtypes = [i32, i64, vp, vp, vp, ctypes.c_int, i32, vp, vp, i32, vp]
     lib.ro_svd.argtypes = [i32, i32, i64, i64, vp, vp, vp, ctypes.c_int, i32, i32, dbl, dbl, i32,
                            vp, vp, vp, vp, vp, vp]
-    for name in ("ro_check_csc", "ro_block_bounds", "ro_occupancy", "ro_gram", "ro_hestenes",
+    for name in ("ro_check_csc", "ro_block_bounds", "ro_occupancy", "ro_gram", "ro_bf16_split", "ro_gram_bf16x3",
+                 "ro_hestenes",
                  "ro_qr_r", "ro_eig_jacobi", "ro_backproject", "ro_svd"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -125,6 +128,24 @@ def gram(M, N, colptr, rowidx, values) -> np.ndarray:
     colptr, rowidx, values, dt = _csc_arrays(colptr, rowidx, values)
     G = np.zeros((M, M), dtype=np.float64)
     _load().ro_gram(M, N, _ptr(colptr), _ptr(rowidx), _ptr(values), dt, _ptr(G))
+    return G
+
+
+def bf16_split(x) -> tuple:
+    """x (FP32) = hi + lo + rest with hi = bf16(x), lo = bf16(x - hi), round to nearest even."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    hi = np.empty_like(x)
+    lo = np.empty_like(x)
+    _load().ro_bf16_split(x.size, _ptr(x), _ptr(hi), _ptr(lo))
+    return hi, lo
+
+
+def gram_bf16x3(M, N, colptr, rowidx, values, rows) -> np.ndarray:
+    """The split-bf16 Gram block of `rows`: sum over columns of hi_p hi_q + hi_p lo_q + lo_p hi_q."""
+    colptr, rowidx, values, dt = _csc_arrays(colptr, rowidx, values)
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    G = np.zeros((rows.size, rows.size), dtype=np.float64)
+    _load().ro_gram_bf16x3(M, N, _ptr(colptr), _ptr(rowidx), _ptr(values), dt, rows.size, _ptr(rows), _ptr(G))
     return G
 
 

@@ -18,6 +18,9 @@
  *                     and rows with exactly one entry (the NO of Eq. 4)
  *   ro_rank_prob      Eq. 4: Pr ~= 1 - NO/NC
  *   ro_gram           G = A A^T = sum over blocks of A^i A^i^T (Eq. 2), by definition
+ *   ro_bf16_split     x (FP32) = hi + lo + rest, hi = bf16(x), lo = bf16(x - hi), round to nearest even
+ *   ro_gram_bf16x3    sum over columns of hi_p hi_q + hi_p lo_q + lo_p hi_q for a chosen set of rows:
+ *                     the split-bf16 product of the mixed path's dense tiles, by definition
  *   ro_hestenes       one-sided (Hestenes) Jacobi SVD of a dense row block: the "truth" route
  *   ro_qr_r           Householder QR of a tall matrix (R factor only), a preconditioner for Hestenes
  *   ro_eig_jacobi     two-sided cyclic Jacobi eigensolver of a dense symmetric matrix
@@ -140,6 +143,54 @@ double ro_rank_prob(int64_t NC, int64_t NO) { return 1.0 - (1.0 / (double)NC) * 
 
 /* G is M x M row-major, full (both triangles).  Columns are visited in order,
  * which visits the blocks in order, so G accumulates G_1 + G_2 + ... + G_D. */
+/* bf16 of an FP32 value, round to nearest even (finite values), returned as the FP32
+ * value it stands for: the top 16 bits of the FP32 pattern after adding half an ulp of
+ * bf16 (plus one when the kept part is odd, which breaks ties to even). */
+static float bf16_rne(float x) {
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    const uint32_t r = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+    float y;
+    memcpy(&y, &r, 4);
+    return y;
+}
+
+int ro_bf16_split(int64_t n, const float *x, float *hi, float *lo) {
+    for (int64_t i = 0; i < n; ++i) {
+        hi[i] = bf16_rne(x[i]);
+        lo[i] = bf16_rne(x[i] - hi[i]);   /* exact difference in FP32 (Sterbenz) */
+    }
+    return RO_OK;
+}
+
+/* G[a][b], a, b < nr (rows rows[0..nr)), of the split-bf16 product: the values are taken
+ * in FP32 (FP64 values are rounded to FP32 first), split, and the three kept products
+ * summed in FP64. */
+int ro_gram_bf16x3(int32_t M, int64_t N, const int32_t *colptr, const int32_t *rowidx, const void *vals,
+                   int dtype, int32_t nr, const int32_t *rows, double *G) {
+    int32_t *slot = (int32_t *)malloc(sizeof(int32_t) * (size_t)(M > 0 ? M : 1));
+    if (!slot) return RO_E_NOMEM;
+    for (int32_t m = 0; m < M; ++m) slot[m] = -1;
+    for (int32_t a = 0; a < nr; ++a) slot[rows[a]] = a;
+    memset(G, 0, sizeof(double) * (size_t)nr * (size_t)nr);
+    for (int64_t j = 0; j < N; ++j)
+        for (int64_t k1 = colptr[j]; k1 < colptr[j + 1]; ++k1) {
+            const int32_t a = slot[rowidx[k1]];
+            if (a < 0) continue;
+            const float x = (float)value_at(vals, dtype, k1);
+            const double h1 = bf16_rne(x), l1 = bf16_rne(x - bf16_rne(x));
+            for (int64_t k2 = colptr[j]; k2 < colptr[j + 1]; ++k2) {
+                const int32_t b = slot[rowidx[k2]];
+                if (b < 0) continue;
+                const float y = (float)value_at(vals, dtype, k2);
+                const double h2 = bf16_rne(y), l2 = bf16_rne(y - bf16_rne(y));
+                G[(size_t)a * nr + b] += h1 * h2 + h1 * l2 + l1 * h2;
+            }
+        }
+    free(slot);
+    return RO_OK;
+}
+
 int ro_gram(int32_t M, int64_t N, const int32_t *colptr, const int32_t *rowidx,
             const void *vals, int dtype, double *G) {
     memset(G, 0, sizeof(double) * (size_t)M * (size_t)M);

@@ -23,10 +23,10 @@ struct MatDesc {
     int32_t gseg;             // Gram segment length (nonzeros of a row per workgroup)
     int32_t dtype, v_dtype;
     int32_t n, npad;          // non-empty rows and the eigensolver order (set after the scan)
-    int32_t prec;             // Gram accumulation: 0 FP64, 1 FP32
+    int32_t prec;             // Gram accumulation: 0 FP64, 1 FP32, 2 FP32 with BF16x3 dense tiles
     int32_t validate;
     int32_t n_tau;            // row count entering the threshold sqrt(n_tau u_gram)
-    int32_t pad0;
+    int32_t dwg;              // split-bf16 dense-tile workgroups (0: the dense rows stay in the sparse pass)
     double tol;               // rank threshold option
     double u_gram;            // unit roundoff of the Gram entries for the threshold
     double jtol;              // Jacobi rotation test tolerance (0: max(1e-15, sqrt(n) eps))
@@ -38,6 +38,7 @@ struct MatDesc {
     int32_t *gsegp;           // [n + 1] first Gram segment of compacted row i (set by the scan)
     int32_t *gslot;           // [n + 1] first partial row of compacted row i (rows with one segment take none)
     double *gpart;            // [slots][npad] partial Gram rows of the cut rows
+    double *dpart;            // [dwg][kDenseRows^2] partial dense-row Gram tiles
     int32_t *dense;           // [kDenseRows] the densest rows (original index, by degree), -1 when unused
     // launch-shape knobs (results do not depend on them; set from the context's tuning cache)
     int32_t bp_per_cu;        // back-projection workgroups per compute unit

@@ -10,6 +10,8 @@ namespace ranky {
 // kChunkCols, halved down to kChunkColsMin while a matrix has fewer than kChunkTarget
 // chunks (so a matrix of a million columns still fills the device).
 constexpr int kChunkCols = 4096;
+// Largest row count M the library takes.
+constexpr int32_t kMaxM = 8192;
 constexpr int kChunkColsMin = 512;
 constexpr int kChunkTarget = 1024;
 

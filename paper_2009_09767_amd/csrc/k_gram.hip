@@ -86,6 +86,8 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
     __syncthreads();
 
     const int32_t p = r2m[i];
+    // with dense tiles on, a dense row's pairs with other dense rows are theirs
+    const bool skip_dense = dsc.dwg > 0 && dmap[p] >= 0;
     const int32_t r_begin = rowptr[p], r_end = rowptr[p + 1];
     const int32_t gs = dsc.gseg;
     const int32_t e_begin = r_begin + seg * gs;
@@ -135,7 +137,7 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
                 int di = -1;
                 if (act) {
                     di = dmap[q];
-                    if (di >= 0) myslot[di * 64] += v;
+                    if (di >= 0 && !skip_dense) myslot[di * 64] += v;
                 }
                 bool pend = act && di < 0;
                 while (__ballot(pend) != 0) {
@@ -259,6 +261,132 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const MatDesc *__restrict__
         G[(int64_t)i * ld + j] = 0.0;
         G[(int64_t)j * ld + i] = 0.0;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Split-bf16 Gram tiles of the densest rows on the matrix cores (gram_prec BF16X3).
+//
+// The densest rows H (the scan's dense list, |H| <= 32) meet in most columns, so their
+// block of the Gram, G_HH = A_H A_H^T, is a dense contraction: each workgroup owns a fixed
+// range of columns (a function of N alone), densifies A[H, 64 columns] in LDS (FP32) step
+// by step, splits every value as x = hi + lo (two bf16, round to nearest even) and adds
+// hi hi^T + hi lo^T + lo hi^T with v_mfma_f32_16x16x16_bf16 (lo lo^T, about 2^-16 of the
+// product, is dropped), FP32 within a step and FP64 across steps.  The sparse pass leaves
+// the pairs of two dense rows out.  The 32 x 32 output is four 16 x 16 blocks; waves 0, 1,
+// 2 own blocks (0,0), (0,1), (1,1), the upper triangle.  Partial tiles go to dpart[wg], and
+// k_gram_dense_reduce adds them in workgroup order into G: bitwise reproducible and
+// independent of D.  (FP64 and FP32 keep these pairs in the sparse pass: measured, tiles
+// over every column cost more than the few dense-slot additions they replace.)
+constexpr int kDc = 64;          // columns per densified step
+constexpr int kDcLd = kDc + 4;   // LDS row stride
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef short s4v __attribute__((ext_vector_type(4)));
+
+// round to nearest even (finite inputs), as the top 16 bits of an FP32
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+__global__ __launch_bounds__(256) void k_gram_dense(const MatDesc *__restrict__ descs) {
+    __shared__ float X[kDenseRows][kDcLd];
+    __shared__ int8_t dmap[kMaxM];
+    const MatDesc &d = descs[0];
+    const int32_t M = d.M;
+    const int64_t N = d.N;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const auto dense = gmem(d.dense);
+    if (dense[1] < 0) return;   // fewer than two dense rows: no pair to compute
+    const auto colptr = gmem(d.colptr);
+    const auto rowidx = gmem(d.rowidx);
+    for (int32_t m = tid; m < M; m += 256) dmap[m] = -1;
+    __syncthreads();
+    if (tid < kDenseRows && dense[tid] >= 0) dmap[dense[tid]] = (int8_t)tid;
+    // this wave's 16 x 16 block (qa, qb) of the 32 x 32 tile
+    const int qa = wave == 2 ? 1 : 0, qb = wave == 0 ? 0 : 1;
+    const bool mm = wave < 3;
+    double acc64[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t c_begin = (N * blockIdx.x) / gridDim.x, c_end = (N * (blockIdx.x + 1)) / gridDim.x;
+    const int col = tid & (kDc - 1), sub = tid >> 6;   // 4 threads per column
+    for (int64_t c0 = c_begin; c0 < c_end; c0 += kDc) {
+        for (int e = tid; e < kDenseRows * kDc; e += 256) X[e / kDc][e % kDc] = 0.f;
+        __syncthreads();
+        const int64_t j = c0 + col;
+        if (j < c_end) {
+            const int32_t e1 = colptr[j + 1];
+            for (int32_t e = colptr[j] + sub; e < e1; e += 4) {
+                const int h = dmap[rowidx[e]];
+                if (h >= 0) {
+                    if (d.dtype == 1) X[h][col] = (float)gmem(static_cast<const double *>(d.values))[e];
+                    else X[h][col] = gmem(static_cast<const float *>(d.values))[e];
+                }
+            }
+        }
+        __syncthreads();
+        if (mm) {
+            const int ra = 16 * qa + (lane & 15), rb = 16 * qb + (lane & 15);
+            f4v a32 = {0.f, 0.f, 0.f, 0.f};
+            // operands: lane l holds A[l % 16][4 (l / 16) + v] and B[4 (l / 16) + v][l % 16], B = X^T
+#pragma unroll
+            for (int kb = 0; kb < kDc; kb += 16) {
+                s4v ahi, alo, bhi, blo;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int kk = kb + 4 * (lane >> 4) + v;
+                    const float xa = X[ra][kk], xb = X[rb][kk];
+                    const uint32_t ha = bf16_bits(xa), hb = bf16_bits(xb);
+                    ahi[v] = (short)ha;
+                    bhi[v] = (short)hb;
+                    alo[v] = (short)bf16_bits(xa - __uint_as_float(ha << 16));
+                    blo[v] = (short)bf16_bits(xb - __uint_as_float(hb << 16));
+                }
+                a32 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, a32, 0, 0, 0);
+                a32 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, a32, 0, 0, 0);
+                a32 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, a32, 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc64[i] += (double)a32[i];
+        }
+        __syncthreads();
+    }
+    if (!mm) return;
+    // result layout: element i of lane l at row 4 (l / 16) + i, column l % 16
+    const auto out = gmem(d.dpart) + (int64_t)blockIdx.x * kDenseRows * kDenseRows;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        out[(16 * qa + 4 * (lane >> 4) + i) * kDenseRows + 16 * qb + (lane & 15)] = acc64[i];
+}
+
+// G[a][b] = G[b][a] for the dense rows a < b (compacted indices): the partial tiles added
+// in workgroup order.  Runs after the sparse pass, which left these entries zero.
+__global__ __launch_bounds__(1024) void k_gram_dense_reduce(const MatDesc *__restrict__ descs) {
+    const MatDesc &d = descs[0];
+    const int t = threadIdx.x, h1 = t / kDenseRows, h2 = t % kDenseRows;
+    const auto dense = gmem(d.dense);
+    if (h1 >= h2 || dense[h1] < 0 || dense[h2] < 0) return;
+    const auto part = gmem(d.dpart) + h1 * kDenseRows + h2;
+    double v = 0.0;
+    for (int32_t b = 0; b < d.dwg; ++b) v += part[(int64_t)b * kDenseRows * kDenseRows];
+    const int64_t i1 = gmem(d.m2r)[dense[h1]], i2 = gmem(d.m2r)[dense[h2]];
+    const auto G = gmem(d.G);
+    G[i1 * d.npad + i2] = v;
+    G[i2 * d.npad + i1] = v;
+}
+
+int32_t gram_dense_wgs(int64_t N) {
+    const int64_t w = (N + 4095) / 4096;
+    return (int32_t)(w < 1 ? 1 : (w > 1024 ? 1024 : w));
+}
+
+void launch_gram_dense(const MatDesc *descs, int32_t dwg, hipStream_t s) {
+    if (dwg <= 0) return;
+    hipLaunchKernelGGL(k_gram_dense, dim3((unsigned)dwg), dim3(256), 0, s, descs);
+}
+
+void launch_gram_dense_reduce(const MatDesc *descs, int32_t dwg, hipStream_t s) {
+    if (dwg <= 0) return;
+    hipLaunchKernelGGL(k_gram_dense_reduce, dim3(1), dim3(kDenseRows * kDenseRows), 0, s, descs);
 }
 
 // LDS per wave: one accumulator row and the lane-private dense slots; per workgroup:

@@ -39,6 +39,9 @@ int64_t gram_part_slots(int64_t nnz);   // partial Gram rows the workspace must 
 void launch_gram(const MatDesc *descs, const int32_t *wp, int64_t nblocks, const int32_t *wp_red, int64_t nblocks_red,
                  int count, int32_t maxM, int32_t acc_bytes, size_t lds_limit, hipStream_t s);
 hipError_t gram_set_attributes(size_t lds_limit);
+int32_t gram_dense_wgs(int64_t N);   // workgroups of the split-bf16 dense-row tiles (a function of N)
+void launch_gram_dense(const MatDesc *descs, int32_t dwg, hipStream_t s);   // BF16X3 dense tiles
+void launch_gram_dense_reduce(const MatDesc *descs, int32_t dwg, hipStream_t s);
 
 // Jacobi eigensolver (k_jacobi.hip)
 int32_t jacobi_npad(int32_t n);  // multiple of the 32-wide subproblem

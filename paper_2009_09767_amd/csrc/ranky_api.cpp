@@ -59,7 +59,6 @@ namespace {
 using namespace ranky;
 
 thread_local char g_err[512] = "";
-constexpr int32_t kMaxM = 8192;
 constexpr int32_t kDefaultSweeps = 40;
 constexpr int32_t kInnerSweeps = 1;
 constexpr int32_t kMaxRefineK = 1024;
@@ -91,7 +90,8 @@ struct Plan {
     int64_t N = 0, nnz = 0, nchunks = 0;
     size_t o_scal = 0, o_sdbl = 0, o_jstate = 0, o_hist = 0, o_rownnz = 0, o_rowptr = 0, o_m2r = 0, o_r2m = 0;
     size_t o_empty = 0, o_lonely = 0, o_single = 0, o_csrk = 0, o_csrend = 0, o_csrcol = 0;
-    size_t o_gsegp = 0, o_gslot = 0, o_gpart = 0, o_dense = 0;
+    size_t o_gsegp = 0, o_gslot = 0, o_gpart = 0, o_dense = 0, o_dpart = 0;
+    int32_t dwg = 0;
     size_t o_G = 0, o_G2 = 0, o_W = 0, o_J = 0, o_S = 0, o_jflag = 0, o_lam = 0, o_perm = 0;
     size_t o_U0 = 0, o_part = 0, total = 0;
     size_t o_bstart = 0;
@@ -100,8 +100,9 @@ struct Plan {
 
 // bstart (host, may be NULL): the caller's D + 1 block boundaries; the widest block sets
 // the chunks per block, and the boundaries get a device copy in the workspace.
+// dense: room for the split-bf16 dense tiles (a single matrix; used with gram_prec BF16X3).
 Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool solver, bool refine,
-               const int64_t *bstart = nullptr) {
+               const int64_t *bstart = nullptr, bool dense = false) {
     Plan p;
     p.M = M;
     p.N = N;
@@ -149,6 +150,8 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool sol
     p.o_gslot = take(sizeof(int32_t) * (M + 1));
     p.o_gpart = take(sizeof(double) * (size_t)gram_part_slots(nnz) * p.npad);
     p.o_dense = take(sizeof(int32_t) * kDenseRows);
+    p.dwg = dense ? gram_dense_wgs(N) : 0;
+    p.o_dpart = take(sizeof(double) * kDenseRows * kDenseRows * (size_t)p.dwg);
     p.o_G = take(sizeof(double) * (size_t)p.npad * p.npad);
     if (solver) {
         p.solver = true;
@@ -209,6 +212,8 @@ MatDesc carve(const Plan &p, char *base, Refine *rf) {
     d.gslot = i32(p.o_gslot);
     d.gpart = f64(p.o_gpart);
     d.dense = i32(p.o_dense);
+    d.dwg = p.dwg;
+    d.dpart = f64(p.o_dpart);
     d.bp_per_cu = 32;
     d.jsched = 0;
     d.G = f64(p.o_G);
@@ -292,7 +297,7 @@ ranky_status check_csc_args(const ranky_csc *A, int32_t M, int64_t N) {
 }
 
 ranky_status check_opts(const ranky_opts &o) {
-    if (o.gram_prec != RANKY_PREC_FP64 && o.gram_prec != RANKY_PREC_FP32)
+    if (o.gram_prec != RANKY_PREC_FP64 && o.gram_prec != RANKY_PREC_FP32 && o.gram_prec != RANKY_PREC_BF16X3)
         return fail(RANKY_E_INVALID, "gram_prec=%d", o.gram_prec);
     if (o.v_dtype != RANKY_F32 && o.v_dtype != RANKY_F64) return fail(RANKY_E_INVALID, "v_dtype=%d", o.v_dtype);
     if (o.refine < 0 || o.refine > 1) return fail(RANKY_E_INVALID, "refine=%d (0 or 1)", o.refine);
@@ -623,7 +628,7 @@ size_t path_bytes(const std::vector<Job> &jobs, const ranky_opts &o) {
     int32_t maxM = 1;
     size_t total = 0;
     for (const Job &j : jobs) {
-        total += make_plan(j.M, j.N, j.A.nnz, j.k, j.D, true, refine, j.bstart).total;
+        total += make_plan(j.M, j.N, j.A.nnz, j.k, j.D, true, refine, j.bstart, count == 1).total;
         maxM = std::max(maxM, j.M);
     }
     return total + make_header(count, count, jacobi_npad(maxM) / kJacobiBlock).total;
@@ -637,7 +642,8 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
     std::vector<Plan> plans(count);
     int32_t maxM = 1;
     for (int i = 0; i < count; ++i) {
-        plans[i] = make_plan(jobs[i].M, jobs[i].N, jobs[i].A.nnz, jobs[i].k, jobs[i].D, true, refine, jobs[i].bstart);
+        plans[i] = make_plan(jobs[i].M, jobs[i].N, jobs[i].A.nnz, jobs[i].k, jobs[i].D, true, refine, jobs[i].bstart,
+                             count == 1);
         maxM = std::max(maxM, jobs[i].M);
     }
     const Header h = make_header(count, count, jacobi_npad(maxM) / kJacobiBlock);
@@ -670,6 +676,7 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
         x.dtype = j.A.dtype;
         x.v_dtype = o.v_dtype;
         x.prec = o.gram_prec;
+        if (x.prec != RANKY_PREC_BF16X3) x.dwg = 0;   // FP64 / FP32: the sparse pass takes every pair
         x.validate = o.validate;
         x.tol = tol;
         const auto tc = ctx->tuned.find(TuneKey{j.M, j.N, j.A.nnz, j.k, j.A.dtype, o.v_dtype, o.gram_prec});
@@ -677,7 +684,9 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
             x.bp_per_cu = tc->second.bp_per_cu;
             x.jsched = tc->second.jsched;
         }
-        x.u_gram = (o.gram_prec == RANKY_PREC_FP64) ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
+        // unit roundoff of the Gram entries: FP64, FP32, or the bf16x3 products (2^-16)
+        x.u_gram = o.gram_prec == RANKY_PREC_FP64 ? std::ldexp(1.0, -53)
+                   : o.gram_prec == RANKY_PREC_FP32 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -16);
         // an FP32 Gram is accurate to about 6e-8: Jacobi stops at 1e-8 (the FP64 step of the
         // Rayleigh-Ritz refinement, or the mixed-precision bar, covers the rest)
         x.jtol = (o.gram_prec == RANKY_PREC_FP64) ? 0.0 : kJacobiTolFp32Gram;
@@ -706,8 +715,10 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
     int32_t gram_acc = 4;   // accumulator bytes: FP64 if any matrix of the launch asks for it
     for (int i = 0; i < count; ++i)
         if (e.d[i].prec == RANKY_PREC_FP64) gram_acc = 8;
+    if (count == 1) launch_gram_dense(e.ddesc(), e.d[0].dwg, s);
     launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], e.dwp(kPhGramRed), e.nblk[kPhGramRed], count, maxM,
                 gram_acc, ctx->lds_limit, s);
+    if (count == 1) launch_gram_dense_reduce(e.ddesc(), e.d[0].dwg, s);
     HIP_TRY(hipGetLastError());
     if (timing) hipEventRecord(ctx->ev[3], s);
     st = e.eigensolve(use_graph);
@@ -866,7 +877,7 @@ ranky_status step_device(StepCtx &sc) {
 ranky_status step_scan(StepCtx &sc, const ranky_csc *A, int32_t M, int64_t N, int32_t D, void *workspace,
                        size_t ws_bytes, hipStream_t s, Engine &e, int32_t *cnt, int32_t *rownnz, int32_t *lonely,
                        int32_t *single) {
-    const Plan p = make_plan(M, N, A->nnz, 1, D, false, false);
+    const Plan p = make_plan(M, N, A->nnz, 1, D, false, false, nullptr, true);
     const Header h = make_header(1, 1, 1);
     if (!workspace || ws_bytes < h.total + p.total)
         return fail(RANKY_E_NOMEM, "workspace %zu < %zu", ws_bytes, h.total + p.total);
@@ -1193,7 +1204,7 @@ ranky_status ranky_batch(ranky_ctx *ctx, int32_t count, const ranky_batch_item *
 
 size_t ranky_step_workspace_bytes(int32_t M, int64_t N, int64_t nnz, int32_t D) {
     if (M < 1 || N < 1 || M > kMaxM || nnz < 0 || D < 1 || D > N) return 0;
-    return make_header(1, 1, 1).total + make_plan(M, N, nnz, 1, D, false, false).total;
+    return make_header(1, 1, 1).total + make_plan(M, N, nnz, 1, D, false, false, nullptr, true).total;
 }
 
 ranky_status ranky_occupancy(const ranky_csc *A, int32_t M, int64_t N, int32_t D, int32_t *cnt, int32_t *rownnz,
@@ -1214,7 +1225,8 @@ ranky_status ranky_gram(const ranky_csc *A, int32_t M, int64_t N, int32_t prec, 
     ranky_status st = check_csc_args(A, M, N);
     if (st) return st;
     if (!G) return fail(RANKY_E_INVALID, "G is NULL");
-    if (prec != RANKY_PREC_FP64 && prec != RANKY_PREC_FP32) return fail(RANKY_E_INVALID, "prec=%d", prec);
+    if (prec != RANKY_PREC_FP64 && prec != RANKY_PREC_FP32 && prec != RANKY_PREC_BF16X3)
+        return fail(RANKY_E_INVALID, "prec=%d", prec);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     StepCtx sc;
     Engine e;
@@ -1222,6 +1234,7 @@ ranky_status ranky_gram(const ranky_csc *A, int32_t M, int64_t N, int32_t prec, 
     if (st) return st;
     MatDesc &x = e.d[0];
     x.prec = prec;
+    if (x.prec != RANKY_PREC_BF16X3) x.dwg = 0;
     if (x.n > 0) {
         e.nblk[kPhGram] = fill_wp(e.hwp(kPhGram), 1, [&](int) { return (int64_t)e.gsegs[0] + (x.npad - x.n); });
         e.nblk[kPhGramRed] = fill_wp(e.hwp(kPhGramRed), 1, [&](int) { return (int64_t)x.n; });
@@ -1229,8 +1242,10 @@ ranky_status ranky_gram(const ranky_csc *A, int32_t M, int64_t N, int32_t prec, 
         if (!st) st = e.upload(e.h.o_wp, sizeof(int32_t) * (size_t)kPhCount * (e.h.slots + 1));
         if (st) return st;
         e.enqueue_transpose();
+        launch_gram_dense(e.ddesc(), x.dwg, s);
         launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], e.dwp(kPhGramRed), e.nblk[kPhGramRed], 1, M,
                     prec == RANKY_PREC_FP64 ? 8 : 4, sc.c.lds_limit, s);
+        launch_gram_dense_reduce(e.ddesc(), x.dwg, s);
         launch_scatter_gram(x.G, x.npad, x.m2r, M, G, s);
     } else {
         launch_fill_f64(G, (int64_t)M * M, 0.0, s);

@@ -19,7 +19,7 @@ OK, E_INVALID, E_CSC, E_NONFINITE, E_NOMEM, E_DEVICE, E_BUSY, E_CANCELLED, E_NOT
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_CSC", 3: "E_NONFINITE", 4: "E_NOMEM", 5: "E_DEVICE", 6: "E_BUSY",
                 7: "E_CANCELLED", 8: "E_NOT_CONVERGED", 9: "PENDING"}
 F32, F64 = 0, 1
-PREC = {"fp64": 0, "fp32": 1}
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 
 class RankyError(RuntimeError):

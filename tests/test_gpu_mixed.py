@@ -121,3 +121,17 @@ def test_refine_rejects_large_k(R):
     with pytest.raises(R.RankyError) as e:
         R.svd(R.to_device(A), 1100, 0.0, gram_prec="fp32", refine=1)
     assert e.value.status == R.E_INVALID
+
+
+def test_bf16x3_refined_against_fp64_oracle(R, orc):
+    """Split-bf16 dense tiles (relative product error ~2^-16) plus the FP64 Rayleigh-Ritz
+    step with the exact operator: sigma within the mixed bar of the FP64 oracle."""
+    import torch
+
+    from tests.test_gpu_dense_tiles import dense_rows_matrix
+
+    A = dense_rows_matrix(np.float32)
+    k = 32
+    ref = orc.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=k, method="whole_qr")
+    got = R.svd(R.to_device(A), k, 0.0, n_blocks=8, gram_prec="bf16x3", refine=1, v_dtype=torch.float32)
+    check(A, got, ref, 1e-6)

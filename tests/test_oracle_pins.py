@@ -382,3 +382,62 @@ def test_paper_metrics_reading():
     assert H.paper_e_sigma(s, s, 7) == 0.0
     assert H.paper_e_u(-U, U, 7) == 0.0
     assert H.paper_e_u(U + 1e-3, U, 7) > 0.0
+
+
+# --------------------------------------------------------------------------------------
+# split-bf16 products (the mixed path's dense tiles)
+
+
+def test_bf16_split_hand_values(orc):
+    """Round to nearest even at bf16's 8 significant bits, worked by hand: 1 + 2^-8 is a tie
+    between 1 and 1 + 2^-7 (odd) and goes to 1; 1 + 3 2^-8 is a tie between 1 + 2^-7 (odd)
+    and 1 + 2^-6 (even) and goes up; 1 + 2^-7 + 2^-9 is nearer 1 + 2^-7."""
+    x = np.array([1.0, 1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, 1 + 2.0 ** -7 + 2.0 ** -9, -3.0, 0.0], dtype=np.float32)
+    hi, lo = orc.bf16_split(x)
+    assert hi.tolist() == [1.0, 1.0, 1 + 2.0 ** -6, 1 + 2.0 ** -7, -3.0, 0.0]
+    assert lo.tolist() == [0.0, 2.0 ** -8, -(2.0 ** -8), 2.0 ** -9, 0.0, 0.0]
+
+
+def test_bf16_split_error_bound(orc):
+    """x - hi - lo is at most half a bf16 ulp of lo: |rest| <= 2^-17 |x| (two 8-bit pieces)."""
+    x = np.random.default_rng(5).standard_normal(10000).astype(np.float32)
+    hi, lo = orc.bf16_split(x)
+    rest = x.astype(np.float64) - hi.astype(np.float64) - lo.astype(np.float64)
+    assert np.all(np.abs(rest) <= 2.0 ** -17 * np.abs(x.astype(np.float64)))
+    h2, l2 = orc.bf16_split(hi)
+    assert np.array_equal(h2, hi) and np.all(l2 == 0)   # bf16 values split exactly
+
+
+def _dense_block_matrix(values):
+    # 3 rows x 5 columns, all entries present, so the block is X X^T over the columns
+    M, N = 3, 5
+    rows = np.repeat(np.arange(M), N)
+    cols = np.tile(np.arange(N), M)
+    return gen.from_coo(M, N, rows, cols, values.reshape(-1))
+
+
+def test_gram_bf16x3_reduces_to_exact_gram_on_bf16_values(orc):
+    """Values that are bf16 numbers have lo = 0: the split product is the exact Gram."""
+    X = np.array([[1.5, -2.0, 0.25, 3.0, 0.0], [0.5, 1.0, -1.0, 0.125, 2.0], [4.0, 0.75, 1.0, -0.5, 1.25]],
+                 dtype=np.float32)
+    A = _dense_block_matrix(X)
+    G = orc.gram_bf16x3(A.M, A.N, A.colptr, A.rowidx, A.values, np.arange(3))
+    assert np.array_equal(G, X.astype(np.float64) @ X.astype(np.float64).T)
+
+
+def test_gram_bf16x3_drops_only_lo_lo(orc):
+    """x = hi + lo exactly, |hi| in [1, 2) with 8 significant bits and |lo| < 2^-9 (under half
+    a bf16 ulp of hi, so hi is x rounded): the split product is X X^T - Lo Lo^T, the one
+    term it leaves out."""
+    rng = np.random.default_rng(9)
+    sign = rng.choice([-1.0, 1.0], size=(3, 5))
+    Hi = sign * (1.0 + rng.integers(0, 128, size=(3, 5)) / 128.0)
+    Lo = rng.choice([-1.0, 1.0], size=(3, 5)) * rng.integers(1, 128, size=(3, 5)) * 2.0 ** -16
+    X = (Hi + Lo).astype(np.float32)
+    assert np.array_equal(X.astype(np.float64), Hi + Lo)
+    A = _dense_block_matrix(X)
+    G = orc.gram_bf16x3(A.M, A.N, A.colptr, A.rowidx, A.values, np.arange(3))
+    hi, lo = orc.bf16_split(X)
+    assert np.array_equal(hi.astype(np.float64), Hi) and np.array_equal(lo.astype(np.float64), Lo)
+    assert np.allclose(G, Hi @ Hi.T + Hi @ Lo.T + Lo @ Hi.T, rtol=0, atol=1e-12)
+    assert np.allclose(G, X.astype(np.float64) @ X.astype(np.float64).T - Lo @ Lo.T, rtol=0, atol=1e-12)
