@@ -23,7 +23,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--prec", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--prec", choices=["fp64", "fp32", "bf16x3"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-matrix leg")
@@ -272,9 +272,13 @@ def main():
     k, D = 128, 64
     dA = ranky.to_device(A, "cuda:0")
     ms_step, phases, info, sig64, vdt = time_path(ranky, torch, np, dA, A, k, D, args.prec, args.steps, args.warmup)
-    other = "fp32" if args.prec == "fp64" else "fp64"
+    # the other precisions of the same workload (FP32 Gram and split-bf16 dense tiles, both
+    # with the FP64 Rayleigh-Ritz step), reported beside the headline
+    others = [p for p in ("fp64", "fp32", "bf16x3") if p != args.prec]
+    other_res = {}
     if not args.no_other:
-        ms2, phases2, info2, sig2, vdt2 = time_path(ranky, torch, np, dA, A, k, D, other, args.steps, args.warmup)
+        for p in others:
+            other_res[p] = time_path(ranky, torch, np, dA, A, k, D, p, args.steps, args.warmup)
 
     val_bytes = 8 if A.values.dtype == np.float64 else 4
     out_bytes = 8 if vdt == torch.float64 else 4
@@ -296,7 +300,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.prec == "fp64" else "f32-gram/f64-eig",
+        "dtype": {"fp64": "f64", "fp32": "f32-gram/f64-eig", "bf16x3": "bf16x3-gram/f64-eig"}[args.prec],
         "data": "synthetic",
         "config": {"workload": f"cfg2 power-law CSC M={A.M} N={A.N} nnz={A.nnz} Zipf(1.1) D={D} k={k} "
                                f"gram={args.prec}", "M": A.M, "N": A.N, "nnz": A.nnz, "n_blocks": D, "k": k},
@@ -313,9 +317,9 @@ def main():
                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                           "bytes_per_launch": sb},
     }
-    if not args.no_other:
-        line[other + "_path"] = {"value": A.nnz / (ms2 * 1e-3), "ms_per_step": ms2, "phase_ms": phases2,
-                                 "rank": info2["rank"], "sweeps": info2["sweeps"]}
+    for p, (ms2, phases2, info2, sig2, vdt2) in other_res.items():
+        line[p + "_path"] = {"value": A.nnz / (ms2 * 1e-3), "ms_per_step": ms2, "phase_ms": phases2,
+                             "rank": info2["rank"], "sweeps": info2["sweeps"]}
 
     if not args.no_batch:
         line["batch"] = time_batch(ranky, torch, gen, max(2, args.steps // 3), 1)
@@ -336,9 +340,9 @@ def main():
                                 "sample": "the whole workload once: FP64 sparse Gram + cyclic Jacobi + V (Gram route)",
                                 "seconds": t_cpu}
         line["sigma_rel_err_vs_oracle"] = float(np.max(np.abs(sig64[:r] - ref.sigma[:r]) / ref.sigma[:r]))
-        if not args.no_other:
-            line[other + "_path"]["sigma_rel_err_vs_oracle"] = float(
-                np.max(np.abs(sig2[:r] - ref.sigma[:r]) / ref.sigma[:r]))
+        for p, res in other_res.items():
+            sig2 = res[3]
+            line[p + "_path"]["sigma_rel_err_vs_oracle"] = float(np.max(np.abs(sig2[:r] - ref.sigma[:r]) / ref.sigma[:r]))
     print(json.dumps(line), flush=True)
 
 
