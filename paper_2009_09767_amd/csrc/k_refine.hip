@@ -30,8 +30,10 @@ constexpr int kRrLd = kRrTile + 2;   // LDS row stride (doubles): 16-byte rows, 
 // Nonzeros of a chunk staged in LDS (row index and value), one chunk ahead; a chunk with
 // more reads the rest from memory.
 constexpr int kRrStage = 1024;
-// Nonzeros of a column whose U0 rows are gathered together.
+// Nonzeros of a column whose U0 rows are gathered together; the first kRrNz0 of a chunk's
+// column are gathered ahead, during the previous chunk's matrix-core step.
 constexpr int kRrNz = 8;
+constexpr int kRrNz0 = 4;
 
 // One pair of U0 entries (row, c), (row, c + 1) with c even; an entry at or past k reads
 // as zero.  Branch-free (clamped addresses, masked values), so a group's loads all stay in
@@ -110,14 +112,16 @@ __device__ __forceinline__ void rr_build_slices(const int32_t *srow, const doubl
 }
 
 // workgroup b -> tile t = b / R (ta <= tb, row-major over the upper triangle), range b % R.
-// Per chunk q of 16 columns: the build of chunk q reads its staged nonzeros and waits only
-// for its U0 gathers; the loads of chunk q + 1's nonzeros (stored to LDS after the matrix-
-// core step) and of the next bounds are issued right after it.
+// Z is double-buffered in LDS: iteration q issues the U0 gathers of chunk q + 1's first
+// nonzeros, runs the matrix-core step of chunk q while they are in flight, then finishes
+// chunk q + 1's slices; the nonzeros of chunk q + 2 are staged meanwhile.  One barrier per
+// chunk.
 template <typename TV, bool kEven>
 __global__ __launch_bounds__(256) void k_rr_syrk(const int32_t *__restrict__ colptr_, const int32_t *__restrict__ rowidx_,
                                                  const TV *__restrict__ vals_, int64_t N, int32_t k, int32_t R,
                                                  const double *__restrict__ U0_, double *__restrict__ part) {
-    __shared__ double Z[2 * kRrChunk * kRrLd];   // slice A, then slice B
+    constexpr int kZ = 2 * kRrChunk * kRrLd;     // one chunk's slices A and B
+    __shared__ double Z[2 * kZ];                 // chunk q in Z[(q & 1) kZ ..]
     __shared__ int32_t Srow[2][kRrStage];
     __shared__ double Sval[2][kRrStage];
     const auto colptr = gmem(colptr_);
@@ -148,101 +152,160 @@ __global__ __launch_bounds__(256) void k_rr_syrk(const int32_t *__restrict__ col
     // chunk q: columns [c_begin + 16 q, min(+16, c_end)); its nonzeros [lo(q), hi(q))
     auto col_lo = [&](int64_t q) { return c_begin + q * kRrChunk; };
     auto col_hi = [&](int64_t q) { return c_begin + q * kRrChunk + kRrChunk < c_end ? c_begin + q * kRrChunk + kRrChunk : c_end; };
+    auto range = [&](int64_t q, int32_t &lo, int32_t &hi) {
+        lo = hi = 0;
+        if (q < nchunks) {
+            lo = colptr[col_lo(q)];
+            hi = colptr[col_hi(q)];
+        }
+    };
+    auto bounds = [&](int64_t q, int32_t &eb, int32_t &ee) {
+        eb = ee = 0;
+        if (q < nchunks && col_lo(q) + bc < col_hi(q)) {
+            eb = colptr[col_lo(q) + bc];
+            ee = colptr[col_lo(q) + bc + 1];
+        }
+    };
+    auto write_z = [&](double *zbuf, const double2 (&za)[4], const double2 (&zb)[4]) {
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            *reinterpret_cast<double2 *>(&zbuf[bc * kRrLd + 2 * bt + 32 * x]) = za[x];
+            if (two) *reinterpret_cast<double2 *>(&zbuf[kRrChunk * kRrLd + bc * kRrLd + 2 * bt + 32 * x]) = zb[x];
+        }
+    };
     d4 acc[4][4];
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
         for (int y = 0; y < 4; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+    // acc += A^T B over one chunk: A[row][c] = slice A[c][row], B[c][col] = slice B (or A)[c][col]
+    auto mfma_chunk = [&](const double *zbuf) {
+#pragma unroll
+        for (int kc = 0; kc < kRrChunk / 4; ++kc) {
+            const int c = kc * 4 + (l >> 4);
+            double a[4], b[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                a[x] = zbuf[c * kRrLd + 64 * qa + 16 * x + (l & 15)];
+                b[x] = zbuf[zb_off + c * kRrLd + 64 * qb + 16 * x + (l & 15)];
+            }
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+        }
+    };
     if (nchunks <= 0) goto write_out;
     {
-        // prologue: chunk 0 staged, its column bounds, chunk 1's nonzero range
-        int32_t lo0 = colptr[col_lo(0)], hi0 = colptr[col_hi(0)];
-        int32_t st0 = hi0 - lo0 < kRrStage ? hi0 - lo0 : kRrStage;
-        for (int32_t x = tid; x < st0; x += 256) {
+        // prologue: chunk 0 staged and built into Z[0]; chunk 1 staged
+        int32_t lo0, hi0, lo1, hi1, lo2, hi2, eb0, ee0, eb1, ee1;
+        range(0, lo0, hi0);
+        for (int32_t x = tid; x < hi0 - lo0 && x < kRrStage; x += 256) {
             Srow[0][x] = rowidx[lo0 + x];
             Sval[0][x] = static_cast<double>(vals[lo0 + x]);
         }
-        int32_t eb = 0, ee = 0;
-        if (col_lo(0) + bc < col_hi(0)) {
-            eb = colptr[col_lo(0) + bc];
-            ee = colptr[col_lo(0) + bc + 1];
-        }
-        int32_t lo1 = 0, hi1 = 0;
-        if (nchunks > 1) {
-            lo1 = colptr[col_lo(1)];
-            hi1 = colptr[col_hi(1)];
-        }
+        bounds(0, eb0, ee0);
+        range(1, lo1, hi1);
         __syncthreads();
-        for (int64_t q = 0; q < nchunks; ++q) {
-            const int buf = (int)(q & 1);
+        {
             double2 za[4], zb[4];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) {
-                za[x] = make_double2(0.0, 0.0);
-                zb[x] = make_double2(0.0, 0.0);
+            for (int x = 0; x < 4; ++x) za[x] = zb[x] = make_double2(0.0, 0.0);
+            rr_build_slices<TV, kEven>(Srow[0], Sval[0], lo0, hi0 - lo0 <= kRrStage, rowidx, vals, U0, k, eb0, ee0, ia,
+                                       ib, two, za, zb);
+            write_z(Z, za, zb);
+        }
+        for (int32_t x = tid; x < hi1 - lo1 && x < kRrStage; x += 256) {
+            Srow[1][x] = rowidx[lo1 + x];
+            Sval[1][x] = static_cast<double>(vals[lo1 + x]);
+        }
+        bounds(1, eb1, ee1);
+        range(2, lo2, hi2);
+        __syncthreads();
+        for (int64_t q = 0; q < nchunks; ++q) {
+            const int zq = (int)(q & 1), zn = zq ^ 1;
+            // chunk q + 1's first kRrNz0 nonzeros of this thread's column (empty: row 0, weight 0)
+            const bool st1 = hi1 - lo1 <= kRrStage;
+            int32_t rw[kRrNz0];
+            double av[kRrNz0];
+#pragma unroll
+            for (int u = 0; u < kRrNz0; ++u) {
+                const bool in = eb1 + u < ee1;
+                const int32_t x = in ? eb1 + u : 0;
+                int32_t rr;
+                double vv;
+                if (st1) {
+                    const int32_t li = in ? x - lo1 : 0;
+                    rr = Srow[zn][li];
+                    vv = Sval[zn][li];
+                } else {
+                    rr = rowidx[x];
+                    vv = static_cast<double>(vals[x]);
+                }
+                rw[u] = in ? rr : 0;
+                av[u] = in ? vv : 0.0;
             }
-            rr_build_slices<TV, kEven>(Srow[buf], Sval[buf], lo0, hi0 - lo0 <= kRrStage, rowidx, vals, U0, k, eb, ee, ia, ib, two, za, zb);
-            // prefetch: chunk q+1's nonzeros (registers), column bounds; chunk q+2's range
-            const int32_t st1 = hi1 - lo1 < kRrStage ? hi1 - lo1 : kRrStage;
+            double2 ua[4][kRrNz0], ub[4][kRrNz0];
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int u = 0; u < kRrNz0; ++u) ua[x][u] = u0_pair<kEven>(U0, rw[u], k, ia + 32 * x);
+            if (two) {
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int u = 0; u < kRrNz0; ++u) ub[x][u] = u0_pair<kEven>(U0, rw[u], k, ib + 32 * x);
+            }
+            // chunk q + 2's nonzeros (staged after the step) and the next bounds
+            const int32_t st2 = hi2 - lo2 < kRrStage ? hi2 - lo2 : kRrStage;
             int32_t pr[kRrStage / 256];
             double pv[kRrStage / 256];
 #pragma unroll
             for (int i = 0; i < kRrStage / 256; ++i) {
                 const int32_t x = tid + 256 * i;
-                const int32_t at = x < st1 ? lo1 + x : 0;   // entry 0 exists (the matrix has a nonzero)
+                const int32_t at = x < st2 ? lo2 + x : 0;   // entry 0 exists (the matrix has a nonzero)
                 pr[i] = rowidx[at];
                 pv[i] = static_cast<double>(vals[at]);
             }
-            int32_t eb1 = 0, ee1 = 0;
-            if (q + 1 < nchunks && col_lo(q + 1) + bc < col_hi(q + 1)) {
-                eb1 = colptr[col_lo(q + 1) + bc];
-                ee1 = colptr[col_lo(q + 1) + bc + 1];
-            }
-            int32_t lo2 = 0, hi2 = 0;
-            if (q + 2 < nchunks) {
-                lo2 = colptr[col_lo(q + 2)];
-                hi2 = colptr[col_hi(q + 2)];
-            }
+            int32_t eb2, ee2, lo3, hi3;
+            bounds(q + 2, eb2, ee2);
+            range(q + 3, lo3, hi3);
+            // the matrix-core step of chunk q while the gathers are in flight
+            if (mm) mfma_chunk(Z + zq * kZ);
+            // chunk q + 1's slices: the first nonzeros from the registers, the rest from memory
+            double2 za[4], zb[4];
 #pragma unroll
             for (int x = 0; x < 4; ++x) {
-                *reinterpret_cast<double2 *>(&Z[bc * kRrLd + 2 * bt + 32 * x]) = za[x];
-                if (two) *reinterpret_cast<double2 *>(&Z[kRrChunk * kRrLd + bc * kRrLd + 2 * bt + 32 * x]) = zb[x];
-            }
-            __syncthreads();
-            // acc += A^T B over the chunk: A[row][c] = slice A[c][row], B[c][col] = slice B (or A)[c][col]
-            if (mm) {
+                za[x] = zb[x] = make_double2(0.0, 0.0);
 #pragma unroll
-                for (int kc = 0; kc < kRrChunk / 4; ++kc) {
-                    const int c = kc * 4 + (l >> 4);
-                    double a[4], b[4];
-#pragma unroll
-                    for (int x = 0; x < 4; ++x) {
-                        a[x] = Z[c * kRrLd + 64 * qa + 16 * x + (l & 15)];
-                        b[x] = Z[zb_off + c * kRrLd + 64 * qb + 16 * x + (l & 15)];
+                for (int u = 0; u < kRrNz0; ++u) {
+                    za[x].x = fma(av[u], ua[x][u].x, za[x].x);
+                    za[x].y = fma(av[u], ua[x][u].y, za[x].y);
+                    if (two) {
+                        zb[x].x = fma(av[u], ub[x][u].x, zb[x].x);
+                        zb[x].y = fma(av[u], ub[x][u].y, zb[x].y);
                     }
-#pragma unroll
-                    for (int x = 0; x < 4; ++x)
-#pragma unroll
-                        for (int y = 0; y < 4; ++y)
-                            acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
                 }
             }
+            rr_build_slices<TV, kEven>(Srow[zn], Sval[zn], lo1, st1, rowidx, vals, U0, k, eb1 + kRrNz0, ee1, ia, ib,
+                                       two, za, zb);
+            write_z(Z + zn * kZ, za, zb);
 #pragma unroll
             for (int i = 0; i < kRrStage / 256; ++i) {
                 const int32_t x = tid + 256 * i;
-                if (x < st1) {
-                    Srow[buf ^ 1][x] = pr[i];
-                    Sval[buf ^ 1][x] = pv[i];
+                if (x < st2) {
+                    Srow[zq][x] = pr[i];
+                    Sval[zq][x] = pv[i];
                 }
             }
             __syncthreads();
-            lo0 = lo1;
-            hi0 = hi1;
-            st0 = st1;
             lo1 = lo2;
             hi1 = hi2;
-            eb = eb1;
-            ee = ee1;
+            lo2 = lo3;
+            hi2 = hi3;
+            eb1 = eb2;
+            ee1 = ee2;
         }
     }
 write_out:
