@@ -35,6 +35,14 @@ MUTANTS = {
     "threshold_without_sqrt": ("double tau = fmax(tol, sqrt((double)n * u_gram)) * s1;",
                                "double tau = fmax(tol, (double)n * u_gram) * s1;"),
     "stale_row_in_two_sided_update": ("gq[c] = sn * x + cs * y;", "gq[c] = sn * x + cs * gq[c] * 0.0;"),
+    "bf16_truncates_instead_of_rounding": ("const uint32_t r = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;",
+                                           "const uint32_t r = u & 0xffff0000u;"),
+    "bf16_ties_away_from_even": ("const uint32_t r = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;",
+                                 "const uint32_t r = (u + 0x8000u) & 0xffff0000u;"),
+    "split_product_drops_cross_term": ("G[(size_t)a * nr + b] += h1 * h2 + h1 * l2 + l1 * h2;",
+                                       "G[(size_t)a * nr + b] += h1 * h2 + h1 * l2;"),
+    "split_product_keeps_lo_lo": ("G[(size_t)a * nr + b] += h1 * h2 + h1 * l2 + l1 * h2;",
+                                  "G[(size_t)a * nr + b] += h1 * h2 + h1 * l2 + l1 * h2 + l1 * l2;"),
 }
 
 
