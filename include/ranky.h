@@ -354,7 +354,9 @@ ranky_status ranky_occupancy(const ranky_csc *A, int32_t M, int64_t N, int32_t D
 
 /* The Gram matrix G = sum_i A^i A^i^T (Eq. 2), full M x M row-major FP64 in the
  * original row order (rows and columns of empty rows are zero), accumulated
- * in `prec`.  Blocking (it reads back the validation status). */
+ * in `prec` (a ranky_prec; with RANKY_PREC_BF16X3 the densest rows' block comes from
+ * the split-bf16 tiles).  Blocking (it reads back the validation status).
+ * E_INVALID for another `prec`. */
 ranky_status ranky_gram(const ranky_csc *A, int32_t M, int64_t N, int32_t prec, double *G, void *workspace,
                         size_t ws_bytes, ranky_stream_t stream);
 
