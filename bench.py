@@ -30,14 +30,14 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--no-other", action="store_true", help="skip the other-precision leg of the headline matrix")
-    ap.add_argument("--cfg5", action="store_true",
+    ap.add_argument("--powerlaw-200m", action="store_true",
                     help="also time config 5 (4096 x 2^24, ~200M nnz, mixed path; generation takes ~25-60 s)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a device-to-device copy of this many GiB (counter calibration) and exit")
     return ap.parse_args()
 
 
-# HBM bytes per working launch of k_jround on the cfg2 FP64 leg, from two rocprofv3 counter
+# HBM bytes per working launch of k_jround on the powerlaw_1m FP64 leg, from two rocprofv3 counter
 # runs (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, averaged over the launches that did work),
 # each scaled by what the same counter reads back for a plain device copy of 1 GiB (x2.0 for
 # FETCH_SIZE, x1.0 for WRITE_SIZE).  Valid only for the kernel source it was taken on.
@@ -139,13 +139,13 @@ def time_batch(ranky, torch, gen, steps, warmup):
     """Batched leg: 256 independent matrices (M ~ U{32..512}, N ~ U{1e4..1e5}, density 0.5%,
     FP32 values, 20% with half their rows zeroed), full spectrum each, through ranky_batch
     with the Jacobi sweep replayed as a captured graph.  FP64 Gram and FP32 Gram."""
-    mats = gen.cfg3()
+    mats = gen.batch_mixed()
     dms = [ranky.to_device(A, "cuda:0") for A in mats]
     ks = [A.M for A in mats]
     Ds = [int(A.meta["D"]) for A in mats]
     nnz = sum(A.nnz for A in mats)
     stream = torch.cuda.Stream()
-    out = {"workload": "cfg3: 256 matrices, M~U{32..512}, N~U{1e4..1e5}, density 0.5%, 20% half-rank, full spectrum",
+    out = {"workload": "batch of 256 matrices, M~U{32..512}, N~U{1e4..1e5}, density 0.5%, 20% half-rank, full spectrum",
            "matrices": len(mats), "nnz": nnz}
     for prec, vdt in (("fp64", torch.float64), ("fp32", torch.float32)):
         outs = [ranky.SVDResult(torch.empty(k, dtype=torch.float64, device="cuda:0"),
@@ -170,11 +170,11 @@ def time_batch(ranky, torch, gen, steps, warmup):
     return out
 
 
-def time_cfg5(ranky, torch, np, gen, steps, warmup):
+def time_powerlaw_200m(ranky, torch, np, gen, steps, warmup):
     """Config 5: one large matrix (4096 x 2^24, Zipf(1.2) rows capped at N, ~200M nnz, FP32
     values, 256 column blocks, k = 100) through the mixed path (FP32 Gram, FP64 eigensolve and
     Rayleigh-Ritz, FP32 V), inputs resident in HBM."""
-    A = gen.cfg5(progress=lambda m: print(m, file=sys.stderr, flush=True))
+    A = gen.powerlaw_200m(progress=lambda m: print(m, file=sys.stderr, flush=True))
     dA = ranky.to_device(A, "cuda:0")
     k, D = A.meta["k"], A.meta["D"]
     kw = dict(n_blocks=D, gram_prec="fp32", refine=1, v_dtype=torch.float32)
@@ -194,7 +194,7 @@ def time_cfg5(ranky, torch, np, gen, steps, warmup):
     ms = 1e3 * (time.perf_counter() - t0) / steps
     r = ranky.svd(dA, k, 0.0, ctx=ctx, out=out, workspace=ws, timing=True, **kw)
     names = ["occupancy", "transpose", "gram", "eigensolve", "select", "refine", "backproject", "total"]
-    res = {"workload": f"cfg5 M={A.M} N={A.N} nnz={A.nnz} Zipf(1.2) D={D} k={k} mixed (fp32 gram, fp64 eig+RR, fp32 V)",
+    res = {"workload": f"power-law CSC M={A.M} N={A.N} nnz={A.nnz} Zipf(1.2) D={D} k={k} mixed (fp32 gram, fp64 eig+RR, fp32 V)",
            "value": A.nnz / (ms * 1e-3), "unit": "nnz/s", "ms_per_step": ms, "steps": steps,
            "phase_ms": dict(zip(names, [round(x, 4) for x in r.info["ms"]])), "rank": r.info["rank"],
            "sweeps": r.info["sweeps"]}
@@ -204,16 +204,16 @@ def time_cfg5(ranky, torch, np, gen, steps, warmup):
 
 
 def time_serving(ranky, torch, gen, seconds, pool_size=48, slots=8):
-    """Serving leg: cfg4's open-loop Poisson arrivals (200 req/s) replayed for `seconds`, each
-    arrival drawing the next matrix of a seeded pool of cfg4 requests (M in {128..1024},
+    """Serving leg: the open-loop Poisson arrivals (200 req/s) replayed for `seconds`, each
+    arrival drawing the next matrix of a seeded pool of serving requests (M in {128..1024},
     N = 2^U{14..20}, LogUniform nnz up to 20M, Zipf(1.1) rows, FP32 values, k = min(M, 64)).
     Latency = completion - submit through ranky_serve_*.  Requests that share a pool entry
     share its output buffers (identical results)."""
-    reqs = gen.cfg4_requests()
-    pool = [gen.cfg4_matrix(r) for r in reqs[:pool_size]]
+    reqs = gen.serving_requests()
+    pool = [gen.serving_matrix(r) for r in reqs[:pool_size]]
     dpool = [ranky.to_device(A, "cuda:0") for A in pool]
     arrivals = [r.arrival_s for r in reqs if r.arrival_s < seconds]
-    res = {"workload": f"cfg4: Poisson 200 req/s for {seconds:g} s over a pool of {pool_size} requests",
+    res = {"workload": f"serving: Poisson 200 req/s for {seconds:g} s over a pool of {pool_size} requests",
            "requests": len(arrivals), "slots": slots}
     for prec in ("fp64", "fp32"):
         vdt = torch.float64 if prec == "fp64" else torch.float32
@@ -268,7 +268,7 @@ def main():
 
     from paper_2009_09767_amd import gen, ranky
 
-    A = gen.cfg2(seed=args.seed)
+    A = gen.powerlaw_1m(seed=args.seed)
     k, D = 128, 64
     dA = ranky.to_device(A, "cuda:0")
     ms_step, phases, info, sig64, vdt = time_path(ranky, torch, np, dA, A, k, D, args.prec, args.steps, args.warmup)
@@ -302,7 +302,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32-gram/f64-eig", "bf16x3": "bf16x3-gram/f64-eig"}[args.prec],
         "data": "synthetic",
-        "config": {"workload": f"cfg2 power-law CSC M={A.M} N={A.N} nnz={A.nnz} Zipf(1.1) D={D} k={k} "
+        "config": {"workload": f"power-law CSC M={A.M} N={A.N} nnz={A.nnz} Zipf(1.1) D={D} k={k} "
                                f"gram={args.prec}", "M": A.M, "N": A.N, "nnz": A.nnz, "n_blocks": D, "k": k},
         "rank": info["rank"],
         "sweeps": info["sweeps"],
@@ -325,8 +325,8 @@ def main():
         line["batch"] = time_batch(ranky, torch, gen, max(2, args.steps // 3), 1)
     if not args.no_serve:
         line["serving"] = time_serving(ranky, torch, gen, args.serve_seconds)
-    if args.cfg5:
-        line["cfg5"] = time_cfg5(ranky, torch, np, gen, max(2, args.steps // 3), 1)
+    if args.powerlaw_200m:
+        line["powerlaw_200m"] = time_powerlaw_200m(ranky, torch, np, gen, max(2, args.steps // 3), 1)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -7,20 +7,20 @@ oracle can both consume its bytes without sharing any computation.
 The paper's own matrix (a 539 x 170897 job/candidate bipartite graph, Sec. IV)
 is not available; the generators below stand in for it with power-law row
 degrees, uniform columns and seeded block-local or global zero rows, at the
-sizes of the five benchmark configurations:
+sizes of the five benchmark workloads:
 
-  cfg1  64 x 4096, Bernoulli(0.02), U(-1,1) FP64, block 3 (0-based) rows 24..63 zeroed
-  cfg2  1024 x 2^20, Zipf(1.1) row degrees (~1.05M nnz), N(0,1) FP64,
-        8 seeded blocks with 30% of rows emptied inside the block
-  cfg3  256 matrices, M ~ U{32..512}, N ~ U{1e4..1e5}, Bernoulli(0.005), N(0,1) FP32,
-        20% of matrices with a random half of rows zeroed (global zero rows)
-  cfg4  Poisson arrivals at 200/s for 60 s; M in {128,256,512,1024}, N = 2^U{14..20},
-        nnz ~ LogUniform[1e5, min(2e7, 0.02 M N)], Zipf(1.1) rows, U(-1,1) FP32, k = min(M, 64)
-  cfg5  4096 x 2^24, ~200M nnz, Zipf(1.2) rows capped at N, U(-1,1) FP32,
-        1024 rows emptied in 128 seeded blocks
+  small_deficient   64 x 4096, Bernoulli(0.02), U(-1,1) FP64, block 3 (0-based) rows 24..63 zeroed
+  powerlaw_1m       1024 x 2^20, Zipf(1.1) row degrees (~1.05M nnz), N(0,1) FP64,
+                    8 seeded blocks with 30% of rows emptied inside the block
+  batch_mixed       256 matrices, M ~ U{32..512}, N ~ U{1e4..1e5}, Bernoulli(0.005), N(0,1) FP32,
+                    20% of matrices with a random half of rows zeroed (global zero rows)
+  serving_requests  Poisson arrivals at 200/s for 60 s; M in {128,256,512,1024}, N = 2^U{14..20},
+                    nnz ~ LogUniform[1e5, min(2e7, 0.02 M N)], Zipf(1.1) rows, U(-1,1) FP32, k = min(M, 64)
+  powerlaw_200m     4096 x 2^24, ~200M nnz, Zipf(1.2) rows capped at N, U(-1,1) FP32,
+                    1024 rows emptied in 128 seeded blocks
 
-All draws use numpy's PCG64 with seed = 2009097670 + config index unless a seed is
-given.  Rows are assigned degrees in a seeded random order (the heavy rows are
+All draws use numpy's PCG64 with seed = 2009097670 + the workload's stream number (1 to 5,
+in the order above) unless a seed is given.  Rows are assigned degrees in a seeded random order (the heavy rows are
 spread over the index range), and a row's columns are drawn without replacement.
 """
 from __future__ import annotations
@@ -57,8 +57,8 @@ class CSC:
         return CSC(self.M, self.N, self.colptr, self.rowidx, self.values.astype(dtype), dict(self.meta))
 
 
-def rng_for(cfg_index: int, seed: int | None = None) -> np.random.Generator:
-    return np.random.Generator(np.random.PCG64(BASE_SEED + cfg_index if seed is None else seed))
+def rng_for(stream: int, seed: int | None = None) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(BASE_SEED + stream if seed is None else seed))
 
 
 def from_coo(M: int, N: int, rows, cols, vals, meta=None) -> CSC:
@@ -148,7 +148,7 @@ def draw_values(rng: np.random.Generator, n: int, kind: str, dtype) -> np.ndarra
 # Benchmark configurations
 # ----------------------------------------------------------------------------
 
-def cfg1(seed: int | None = None, M=64, N=4096, D=8, p=0.02, zero_block=3, zero_rows=(24, 64)) -> CSC:
+def small_deficient(seed: int | None = None, M=64, N=4096, D=8, p=0.02, zero_block=3, zero_rows=(24, 64)) -> CSC:
     """Plain method, small: Bernoulli(p) entries, U(-1,1) FP64, one block with rows emptied."""
     rng = rng_for(1, seed)
     mask = rng.random((M, N)) < p
@@ -158,10 +158,10 @@ def cfg1(seed: int | None = None, M=64, N=4096, D=8, p=0.02, zero_block=3, zero_
     c0, c1 = bs[zero_block], bs[zero_block + 1]
     keep = ~((cols >= c0) & (cols < c1) & (rows >= zero_rows[0]) & (rows < zero_rows[1]))
     return from_coo(M, N, rows[keep], cols[keep], vals[keep],
-                    dict(name="cfg1", D=D, k=M, tol=1e-12, zero_block=zero_block, zero_rows=zero_rows))
+                    dict(name="small_deficient", D=D, k=M, tol=1e-12, zero_block=zero_block, zero_rows=zero_rows))
 
 
-def cfg2(seed: int | None = None, M=1024, N=1 << 20, D=64, nnz=1_050_000, s=1.1, zero_blocks=8,
+def powerlaw_1m(seed: int | None = None, M=1024, N=1 << 20, D=64, nnz=1_050_000, s=1.1, zero_blocks=8,
          zero_frac=0.3, k=128, dtype=np.float64) -> CSC:
     """Power-law rows (Zipf(s) degrees), uniform columns, N(0,1) values; zero_blocks seeded
     blocks have floor(zero_frac M) seeded rows emptied inside the block only."""
@@ -178,18 +178,18 @@ def cfg2(seed: int | None = None, M=1024, N=1 << 20, D=64, nnz=1_050_000, s=1.1,
         inblk = (cols >= bs[b]) & (cols < bs[b + 1])
         keep &= ~(inblk & np.isin(rows, zr))
     return from_coo(M, N, rows[keep], cols[keep], vals[keep],
-                    dict(name="cfg2", D=D, k=k, tol=0.0, zeroed_blocks=zeroed))
+                    dict(name="powerlaw_1m", D=D, k=k, tol=0.0, zeroed_blocks=zeroed))
 
 
-def cfg2_small(seed: int | None = None, M=128, N=1 << 14, D=8, k=32, dtype=np.float64) -> CSC:
-    """cfg2's recipe at a size the oracle solves in seconds (nnz ~ N, as in cfg2)."""
-    A = cfg2(seed=BASE_SEED + 20 if seed is None else seed, M=M, N=N, D=D, nnz=N, zero_blocks=2, k=k,
+def powerlaw_small(seed: int | None = None, M=128, N=1 << 14, D=8, k=32, dtype=np.float64) -> CSC:
+    """powerlaw_1m's recipe at a size the oracle solves in seconds (nnz ~ N, as in powerlaw_1m)."""
+    A = powerlaw_1m(seed=BASE_SEED + 20 if seed is None else seed, M=M, N=N, D=D, nnz=N, zero_blocks=2, k=k,
              dtype=dtype)
-    A.meta["name"] = "cfg2_small"
+    A.meta["name"] = "powerlaw_small"
     return A
 
 
-def cfg3_matrix(rng: np.random.Generator, M: int, N: int, density=0.005, zero_half=False,
+def batch_matrix(rng: np.random.Generator, M: int, N: int, density=0.005, zero_half=False,
                 D: int = 8) -> CSC:
     total = M * N
     nnz = int(rng.binomial(total, density))
@@ -201,10 +201,10 @@ def cfg3_matrix(rng: np.random.Generator, M: int, N: int, density=0.005, zero_ha
         zeroed = np.sort(rng.choice(M, size=M // 2, replace=False))
         keep = ~np.isin(rows, zeroed)
         rows, cols, vals = rows[keep], cols[keep], vals[keep]
-    return from_coo(M, N, rows, cols, vals, dict(name="cfg3", D=D, k=M, tol=0.0, zeroed_rows=zeroed))
+    return from_coo(M, N, rows, cols, vals, dict(name="batch_mixed", D=D, k=M, tol=0.0, zeroed_rows=zeroed))
 
 
-def cfg3(seed: int | None = None, count=256, M_range=(32, 512), N_range=(10_000, 100_000),
+def batch_mixed(seed: int | None = None, count=256, M_range=(32, 512), N_range=(10_000, 100_000),
          density=0.005, deficient_frac=0.2) -> list[CSC]:
     """Batch of independent matrices; a seeded 20% get a random half of their rows zeroed."""
     rng = rng_for(3, seed)
@@ -216,7 +216,7 @@ def cfg3(seed: int | None = None, count=256, M_range=(32, 512), N_range=(10_000,
     out = []
     for i in range(count):
         r = np.random.Generator(np.random.PCG64(int(seeds[i])))
-        A = cfg3_matrix(r, int(Ms[i]), int(Ns[i]), density, i in deficient, int(Ds[i]))
+        A = batch_matrix(r, int(Ms[i]), int(Ns[i]), density, i in deficient, int(Ds[i]))
         A.meta["index"] = i
         out.append(A)
     return out
@@ -232,7 +232,7 @@ class Request:
     seed: int
 
 
-def cfg4_requests(seed: int | None = None, rate=200.0, duration_s=60.0,
+def serving_requests(seed: int | None = None, rate=200.0, duration_s=60.0,
                   Ms=(128, 256, 512, 1024), log2N=(14, 20), nnz_lo=1e5, nnz_hi=2e7) -> list[Request]:
     """Open-loop Poisson arrivals; each request's matrix is drawn later from its own seed."""
     rng = rng_for(4, seed)
@@ -250,13 +250,13 @@ def cfg4_requests(seed: int | None = None, rate=200.0, duration_s=60.0,
     return reqs
 
 
-def cfg4_matrix(req: Request, s=1.1) -> CSC:
+def serving_matrix(req: Request, s=1.1) -> CSC:
     rng = np.random.Generator(np.random.PCG64(req.seed))
     rows, cols, vals = powerlaw_rows(rng, req.M, req.N, req.nnz, s, "uniform", np.float32)
-    return from_coo(req.M, req.N, rows, cols, vals, dict(name="cfg4", D=max(1, req.N >> 14), k=req.k, tol=0.0))
+    return from_coo(req.M, req.N, rows, cols, vals, dict(name="serving", D=max(1, req.N >> 14), k=req.k, tol=0.0))
 
 
-def cfg5(seed: int | None = None, M=4096, N=1 << 24, D=256, nnz=200_000_000, s=1.2, zero_blocks=128,
+def powerlaw_200m(seed: int | None = None, M=4096, N=1 << 24, D=256, nnz=200_000_000, s=1.2, zero_blocks=128,
          zero_rows=1024, k=100, progress=None) -> CSC:
     """Large single matrix: Zipf(1.2) rows capped at N; zero_rows seeded rows emptied inside each of
     zero_blocks seeded blocks.  The pre-zeroing target is scaled so about nnz entries remain.
@@ -289,7 +289,7 @@ def cfg5(seed: int | None = None, M=4096, N=1 << 24, D=256, nnz=200_000_000, s=1
         rows[pos:pos + c.size] = m
         pos += c.size
         if progress is not None and m % 512 == 511:
-            progress(f"cfg5: {m + 1}/{M} rows drawn, {pos} entries")
+            progress(f"powerlaw_200m: {m + 1}/{M} rows drawn, {pos} entries")
     cols = cols[:pos]
     rows = rows[:pos]
     # stable LSD radix sort by column in two 16-bit passes (numpy's stable sort is a radix
@@ -299,7 +299,7 @@ def cfg5(seed: int | None = None, M=4096, N=1 << 24, D=256, nnz=200_000_000, s=1
     order = o1[o2]
     del o1, o2
     if progress is not None:
-        progress("cfg5: sorted by column")
+        progress("powerlaw_200m: sorted by column")
     rows = rows[order]
     counts = np.bincount(cols, minlength=N)
     del order, cols
@@ -307,7 +307,7 @@ def cfg5(seed: int | None = None, M=4096, N=1 << 24, D=256, nnz=200_000_000, s=1
     colptr = np.zeros(N + 1, dtype=np.int64)
     np.cumsum(counts, out=colptr[1:])
     return CSC(M, N, colptr.astype(np.int32), rows, vals,
-               dict(name="cfg5", D=D, k=k, tol=0.0, zeroed_blocks=dict(zip(blocks.tolist(), zero_sets))))
+               dict(name="powerlaw_200m", D=D, k=k, tol=0.0, zeroed_blocks=dict(zip(blocks.tolist(), zero_sets))))
 
 
 # ----------------------------------------------------------------------------

@@ -15,13 +15,13 @@ def digest(A):
 
 
 def test_same_seed_same_bytes():
-    assert digest(gen.cfg1()) == digest(gen.cfg1())
-    assert digest(gen.cfg1()) != digest(gen.cfg1(seed=1))
-    assert digest(gen.cfg2_small()) == digest(gen.cfg2_small())
+    assert digest(gen.small_deficient()) == digest(gen.small_deficient())
+    assert digest(gen.small_deficient()) != digest(gen.small_deficient(seed=1))
+    assert digest(gen.powerlaw_small()) == digest(gen.powerlaw_small())
 
 
 def test_csc_contract():
-    for A in (gen.cfg1(), gen.cfg2_small(), gen.cfg3(count=3)[0]):
+    for A in (gen.small_deficient(), gen.powerlaw_small(), gen.batch_mixed(count=3)[0]):
         assert A.colptr.dtype == np.int32 and A.rowidx.dtype == np.int32
         assert A.colptr[0] == 0 and A.colptr[-1] == A.nnz
         assert np.all(np.diff(A.colptr) >= 0)
@@ -31,8 +31,8 @@ def test_csc_contract():
         assert A.rowidx.min() >= 0 and A.rowidx.max() < A.M
 
 
-def test_cfg1_recipe():
-    A = gen.cfg1()
+def test_small_deficient_recipe():
+    A = gen.small_deficient()
     assert (A.M, A.N) == (64, 4096)
     assert abs(A.nnz / (64 * 4096) - 0.02) < 0.002
     X = A.dense()
@@ -40,8 +40,8 @@ def test_cfg1_recipe():
     assert np.abs(A.values).max() < 1.0 and A.values.dtype == np.float64
 
 
-def test_cfg2_recipe():
-    A = gen.cfg2()
+def test_powerlaw_1m_recipe():
+    A = gen.powerlaw_1m()
     assert (A.M, A.N) == (1024, 1 << 20)
     assert 0.95e6 < A.nnz < 1.06e6
     deg = np.bincount(A.rowidx, minlength=A.M)
@@ -57,8 +57,8 @@ def test_cfg2_recipe():
         assert not np.isin(A.rowidx[inblk], rows).any()
 
 
-def test_cfg3_recipe():
-    batch = gen.cfg3(count=20, deficient_frac=0.25)
+def test_batch_mixed_recipe():
+    batch = gen.batch_mixed(count=20, deficient_frac=0.25)
     assert len(batch) == 20
     deficient = [A for A in batch if A.meta["zeroed_rows"].size]
     assert len(deficient) == 5
@@ -68,14 +68,14 @@ def test_cfg3_recipe():
         assert abs(A.nnz / (A.M * A.N) - 0.005 * (0.5 if A.meta["zeroed_rows"].size else 1.0)) < 0.001
 
 
-def test_cfg4_arrivals():
-    reqs = gen.cfg4_requests()
+def test_serving_arrivals():
+    reqs = gen.serving_requests()
     assert 11_000 < len(reqs) < 13_000       # 200/s for 60 s
     gaps = np.diff([r.arrival_s for r in reqs])
     assert abs(gaps.mean() - 1 / 200) < 2e-4
     assert all(r.M in (128, 256, 512, 1024) and r.k == min(r.M, 64) for r in reqs)
     assert max(r.nnz for r in reqs) <= 2e7
-    A = gen.cfg4_matrix(reqs[0])
+    A = gen.serving_matrix(reqs[0])
     assert A.M == reqs[0].M and A.N == reqs[0].N and abs(A.nnz - reqs[0].nnz) <= 0.01 * reqs[0].nnz + 64
 
 

@@ -30,7 +30,7 @@ def wait(R, job, limit=60.0):
 
 
 def test_async_equals_blocking_call(R):
-    A = gen.cfg2_small()
+    A = gen.powerlaw_small()
     dA = R.to_device(A)
     k = 32
     base = R.svd(dA, k, 0.0, ctx=R.Context(0), n_blocks=8)
@@ -54,7 +54,7 @@ def test_async_equals_blocking_call(R):
 
 
 def test_async_reports_device_errors(R):
-    A = gen.cfg1()
+    A = gen.small_deficient()
     bad = R.to_device(A)
     v = A.values.copy()
     v[5] = np.inf

@@ -31,8 +31,8 @@ def orc():
 
 
 def small_batch(count=12):
-    """cfg3's recipe at reduced sizes so the oracle checks every member."""
-    return gen.cfg3(seed=77, count=count, M_range=(20, 150), N_range=(1500, 6000), density=0.01,
+    """batch_mixed's recipe at reduced sizes so the oracle checks every member."""
+    return gen.batch_mixed(seed=77, count=count, M_range=(20, 150), N_range=(1500, 6000), density=0.01,
                     deficient_frac=0.25)
 
 

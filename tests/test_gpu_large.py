@@ -23,11 +23,11 @@ def R():
     return ranky
 
 
-def test_cfg5_full_size_properties(R):
+def test_powerlaw_200m_full_size_properties(R):
     import torch
 
-    A = gen.cfg5(progress=lambda m: print(m, flush=True))
-    print(f"cfg5: M={A.M} N={A.N} nnz={A.nnz}", flush=True)
+    A = gen.powerlaw_200m(progress=lambda m: print(m, flush=True))
+    print(f"powerlaw_200m: M={A.M} N={A.N} nnz={A.nnz}", flush=True)
     dA = R.to_device(A)
     k, D = A.meta["k"], A.meta["D"]
     out = R.svd(dA, k, 0.0, n_blocks=D, gram_prec="fp32", refine=1, v_dtype=torch.float32)

@@ -31,10 +31,10 @@ def orc():
 
 
 CASES = {
-    "cfg2_small_f32": lambda: gen.cfg2_small(dtype=np.float32),
-    "cfg3_full_rank": lambda: [A for A in gen.cfg3(count=6, deficient_frac=0.5) if not A.meta["zeroed_rows"].size][0],
-    "cfg3_half_rows_zero": lambda: [A for A in gen.cfg3(count=6, deficient_frac=0.5) if A.meta["zeroed_rows"].size][0],
-    "cfg1_f64": lambda: gen.cfg1(),
+    "powerlaw_small_f32": lambda: gen.powerlaw_small(dtype=np.float32),
+    "batch_mixed_full_rank": lambda: [A for A in gen.batch_mixed(count=6, deficient_frac=0.5) if not A.meta["zeroed_rows"].size][0],
+    "batch_mixed_half_rows_zero": lambda: [A for A in gen.batch_mixed(count=6, deficient_frac=0.5) if A.meta["zeroed_rows"].size][0],
+    "small_deficient_f64": lambda: gen.small_deficient(),
 }
 
 
@@ -99,7 +99,7 @@ def test_refine_dense_columns(R, orc):
 def test_mixed_without_refinement_meets_the_mixed_bar(R, orc):
     import torch
 
-    A = CASES["cfg3_full_rank"]()
+    A = CASES["batch_mixed_full_rank"]()
     k = 32
     ref = orc.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=k, method="whole_qr")
     got = R.svd(R.to_device(A), k, 0.0, n_blocks=8, gram_prec="fp32", refine=0, v_dtype=torch.float32)
@@ -109,7 +109,7 @@ def test_mixed_without_refinement_meets_the_mixed_bar(R, orc):
 def test_mixed_is_deterministic(R):
     import torch
 
-    A = gen.cfg2_small(dtype=np.float32)
+    A = gen.powerlaw_small(dtype=np.float32)
     dA = R.to_device(A)
     a = R.svd(dA, 32, 0.0, n_blocks=8, gram_prec="fp32", refine=1, v_dtype=torch.float32)
     b = R.svd(dA, 32, 0.0, n_blocks=8, gram_prec="fp32", refine=1, v_dtype=torch.float32)

@@ -33,15 +33,15 @@ def orc():
     return oracle
 
 
-def cfg3_member(i, count=6):
-    return gen.cfg3(count=count, deficient_frac=0.5)[i]
+def batch_mixed_member(i, count=6):
+    return gen.batch_mixed(count=count, deficient_frac=0.5)[i]
 
 
 CASES = {
-    "cfg1": lambda: gen.cfg1(),
-    "cfg2_small": lambda: gen.cfg2_small(),
-    "cfg3_full_rank": lambda: [A for A in gen.cfg3(count=6, deficient_frac=0.5) if not A.meta["zeroed_rows"].size][0],
-    "cfg3_half_rows_zero": lambda: [A for A in gen.cfg3(count=6, deficient_frac=0.5) if A.meta["zeroed_rows"].size][0],
+    "small_deficient": lambda: gen.small_deficient(),
+    "powerlaw_small": lambda: gen.powerlaw_small(),
+    "batch_mixed_full_rank": lambda: [A for A in gen.batch_mixed(count=6, deficient_frac=0.5) if not A.meta["zeroed_rows"].size][0],
+    "batch_mixed_half_rows_zero": lambda: [A for A in gen.batch_mixed(count=6, deficient_frac=0.5) if A.meta["zeroed_rows"].size][0],
     "ragged_65": lambda: gen.random_sparse(65, 3000, 0.01, seed=65),
     "ragged_127_f32": lambda: gen.random_sparse(127, 5000, 0.004, seed=127, dtype=np.float32),
     "tiny_3x40": lambda: gen.random_sparse(3, 40, 0.3, seed=3),
@@ -64,7 +64,7 @@ def max_row_nnz(A):
 # step parity
 # --------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("name", ["cfg1", "cfg2_small", "cfg3_half_rows_zero", "ragged_127_f32"])
+@pytest.mark.parametrize("name", ["small_deficient", "powerlaw_small", "batch_mixed_half_rows_zero", "ragged_127_f32"])
 def test_occupancy_bit_exact(R, orc, name):
     A = CASES[name]()
     D = A.meta.get("D", 8)
@@ -76,7 +76,7 @@ def test_occupancy_bit_exact(R, orc, name):
     assert np.array_equal(single.cpu().numpy(), ref.single)
 
 
-@pytest.mark.parametrize("name", ["cfg1", "cfg2_small", "cfg3_full_rank", "cfg3_half_rows_zero", "ragged_65"])
+@pytest.mark.parametrize("name", ["small_deficient", "powerlaw_small", "batch_mixed_full_rank", "batch_mixed_half_rows_zero", "ragged_65"])
 def test_gram_fp64(R, orc, name):
     A = CASES[name]()
     dA = R.to_device(A)
@@ -130,7 +130,7 @@ def test_gram_long_rows_cut_into_segments(R, orc):
 
 
 def test_gram_fp32_accumulation(R, orc):
-    A = CASES["cfg3_full_rank"]()
+    A = CASES["batch_mixed_full_rank"]()
     G = R.gram(R.to_device(A), prec="fp32").cpu().numpy()
     ref = orc.gram(A.M, A.N, A.colptr, A.rowidx, A.values)
     bound = 2.0 * (max_row_nnz(A) + 2) * 2.0 ** -24 * absgram(orc, A)
@@ -167,13 +167,13 @@ def test_eigh_graded_relative_accuracy(R):
 
 
 @pytest.mark.parametrize("vdt", ["f64", "f32"])
-@pytest.mark.parametrize("case", ["cfg1_k48", "wide_k300"])
+@pytest.mark.parametrize("case", ["small_deficient_k48", "wide_k300"])
 def test_backproject(R, orc, vdt, case):
     """The step call: 2 outputs per lane (k = 48) and 8 (k = 300)."""
     import torch
 
-    if case == "cfg1_k48":
-        A, k, tol, method = gen.cfg1(), 48, 1e-12, "whole"
+    if case == "small_deficient_k48":
+        A, k, tol, method = gen.small_deficient(), 48, 1e-12, "whole"
     else:
         A, k, tol, method = gen.random_sparse(300, 2500, 0.02, seed=9), 300, 0.0, "whole_qr"
     ref = orc.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=k, tol=tol, method=method)
@@ -228,9 +228,9 @@ def test_svd_against_oracle(R, orc, name):
     compare_svd(A, got, ref, k)
 
 
-def test_svd_merge_oracle_cfg1(R, orc):
-    """The paper's own procedure (per-block SVD, proxy P, SVD of P) on the block-rank-deficient cfg1."""
-    A = gen.cfg1()
+def test_svd_merge_oracle_small_deficient(R, orc):
+    """The paper's own procedure (per-block SVD, proxy P, SVD of P) on the block-rank-deficient small_deficient."""
+    A = gen.small_deficient()
     ref = orc.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=64, tol=1e-12, method="merge", D=8)
     got = R.svd(R.to_device(A), 64, 1e-12, n_blocks=8)
     compare_svd(A, got, ref, 64)
@@ -285,7 +285,7 @@ def test_explicit_block_boundaries(R, orc):
     lonely-row statistics for those blocks (counted here from the dense matrix)."""
     import torch
 
-    A = gen.cfg1()
+    A = gen.small_deficient()
     dA = R.to_device(A)
     D, k = 8, 32
     base = R.svd(dA, k, 0.0, n_blocks=D)
@@ -312,7 +312,7 @@ def test_explicit_block_boundaries(R, orc):
 
 
 def test_deterministic_and_block_count_invariant(R):
-    A = gen.cfg2_small()
+    A = gen.powerlaw_small()
     dA = R.to_device(A)
     outs = [R.svd(dA, 32, 0.0, n_blocks=D) for D in (8, 8, 1, 64)]
     base = outs[0]
@@ -395,11 +395,11 @@ def test_errors_are_reported(R):
 # full size, in the launch configuration the benchmark times
 # --------------------------------------------------------------------------------------
 
-def test_cfg2_full_size(R, orc):
+def test_powerlaw_1m_full_size(R, orc):
     """1024 x 2^20, ~1M nnz, k = 128, D = 64: all 128 sigmas and U against the oracle's Gram route
     (FP64 Gram + cyclic Jacobi on the CPU), V on a seeded sample of 2048 columns against the oracle's
     back-projection of its own U."""
-    A = gen.cfg2()
+    A = gen.powerlaw_1m()
     k = 128
     ref = orc.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=k, method="gram", want_v=False)
     got = R.svd(R.to_device(A), k, 0.0, n_blocks=64)

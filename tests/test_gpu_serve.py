@@ -24,13 +24,13 @@ def R():
 
 
 def request_pool(count=10, seed=31):
-    reqs = gen.cfg4_requests(seed=seed, duration_s=1.0)[:count]
+    reqs = gen.serving_requests(seed=seed, duration_s=1.0)[:count]
     out = []
     for r in reqs:
-        # smaller N so the test stays short; the recipe is cfg4's (Zipf rows, U(-1,1) FP32)
+        # smaller N so the test stays short; the recipe is serving's (Zipf rows, U(-1,1) FP32)
         r.N = min(r.N, 1 << 15)
         r.nnz = min(r.nnz, 40 * r.N)
-        out.append(gen.cfg4_matrix(r))
+        out.append(gen.serving_matrix(r))
     return out
 
 
@@ -98,7 +98,7 @@ def test_admission_by_footprint(R):
 def test_oversized_request_is_refused(R):
     import torch
 
-    big = gen.cfg4_matrix(gen.Request(0.0, 1024, 1 << 20, 2_000_000, 64, 3))
+    big = gen.serving_matrix(gen.Request(0.0, 1024, 1 << 20, 2_000_000, 64, 3))
     dbig = R.to_device(big)
     obig = alloc_out(R, torch, big, 64, torch.float64)
     srv = R.Server(arena_bytes=1 << 22, max_slots=1, max_queue=2)

@@ -28,7 +28,7 @@ def same(a, b):
 
 
 def test_every_candidate_gives_the_default_result(R):
-    A = gen.cfg2_small()
+    A = gen.powerlaw_small()
     dA = R.to_device(A)
     k = 32
     base = R.svd(dA, k, 0.0, ctx=R.Context(0), n_blocks=8)
@@ -43,7 +43,7 @@ def test_every_candidate_gives_the_default_result(R):
 def test_autotune_report_and_reuse(R):
     import torch
 
-    A = gen.cfg2_small()
+    A = gen.powerlaw_small()
     dA = R.to_device(A)
     k = 32
     base = R.svd(dA, k, 0.0, ctx=R.Context(0), n_blocks=8)

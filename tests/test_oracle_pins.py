@@ -132,7 +132,7 @@ def test_brute_force_tiny(orc, seed, method):
 
 @pytest.mark.parametrize("D", [1, 2, 3, 8, 64, 128])
 def test_merge_equals_whole(orc, D):
-    A = gen.cfg1()
+    A = gen.small_deficient()
     whole = run(orc, A, method="whole_qr", tol=1e-12)
     merged = run(orc, A, method="merge", D=D, tol=1e-12)
     assert merged.rank == whole.rank == A.M
@@ -155,7 +155,7 @@ def test_merge_rank_deficient_blocks(orc):
 # --------------------------------------------------------------------------------------
 
 def test_invariants_full_spectrum(orc):
-    A = gen.cfg1()
+    A = gen.small_deficient()
     r = run(orc, A, method="whole", tol=1e-12)
     X = A.dense()
     fro2 = float(np.sum(X * X))
@@ -169,7 +169,7 @@ def test_invariants_full_spectrum(orc):
 
 
 def test_eckart_young_topk(orc):
-    A = gen.cfg2_small()
+    A = gen.powerlaw_small()
     k = 24
     r = run(orc, A, k=k, method="whole_qr")
     X = A.dense()
@@ -195,8 +195,8 @@ def test_scaling_and_permutations(orc):
 
 
 def test_block_local_zeros_keep_rank(orc):
-    """cfg1: rows 24..63 are empty inside block 3 only; the rank stays M."""
-    A = gen.cfg1()
+    """small_deficient: rows 24..63 are empty inside block 3 only; the rank stays M."""
+    A = gen.small_deficient()
     occ = orc.occupancy(A.M, A.N, A.colptr, A.rowidx, 8)
     assert np.all(occ.cnt[3, 24:] == 0)
     assert np.all(occ.rownnz > 0)
@@ -205,9 +205,9 @@ def test_block_local_zeros_keep_rank(orc):
 
 
 def test_global_zero_rows_exact_rank(orc):
-    """Zeroed rows (the cfg3 recipe): rank = M - |E| exactly, e_row columns, sigma = 0."""
+    """Zeroed rows (the batch_mixed recipe): rank = M - |E| exactly, e_row columns, sigma = 0."""
     rng = np.random.default_rng(3)
-    A = gen.cfg3_matrix(rng, 48, 3000, density=0.02, zero_half=True)
+    A = gen.batch_matrix(rng, 48, 3000, density=0.02, zero_half=True)
     E = A.meta["zeroed_rows"]
     for method in METHODS:
         r = run(orc, A, method=method, D=4)
@@ -223,7 +223,7 @@ def test_global_zero_rows_exact_rank(orc):
 # --------------------------------------------------------------------------------------
 
 def test_occupancy_brute_force(orc):
-    A = gen.cfg1()
+    A = gen.small_deficient()
     X = A.dense() != 0
     D = 8
     occ = orc.occupancy(A.M, A.N, A.colptr, A.rowidx, D)
@@ -273,7 +273,7 @@ def test_eq5_worked_example(orc):
 # --------------------------------------------------------------------------------------
 
 def test_gram_matches_dense_and_is_block_additive(orc):
-    A = gen.cfg1()
+    A = gen.small_deficient()
     X = A.dense()
     G = orc.gram(A.M, A.N, A.colptr, A.rowidx, A.values)
     np.testing.assert_allclose(G, X @ X.T, rtol=1e-13, atol=1e-13)
@@ -369,7 +369,7 @@ def test_check_csc_error_codes(orc):
 
 
 def test_fp32_values_promote_exactly(orc):
-    A = gen.cfg2_small(dtype=np.float32)
+    A = gen.powerlaw_small(dtype=np.float32)
     r32 = run(orc, A, k=16, method="gram")
     r64 = run(orc, A.astype(np.float64), k=16, method="gram")
     assert np.array_equal(r32.sigma, r64.sigma)
