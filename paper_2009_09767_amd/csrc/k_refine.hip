@@ -325,23 +325,43 @@ write_out:
 
 // H[a][b] = H[b][a] = sum over the column ranges (in order) of the partial tiles; the
 // entry (a, b), a <= b, of a diagonal tile is used for both halves.  Zero outside k x k.
-__global__ __launch_bounds__(256) void k_rr_syrk_reduce(const double *__restrict__ part, int32_t k, int32_t R,
-                                                        int32_t npad, double *__restrict__ H) {
+// A workgroup takes 64 consecutive entries (lanes) and cuts the R ranges into 16
+// contiguous segments (waves); the segment sums are added in segment order.
+__global__ __launch_bounds__(1024) void k_rr_syrk_reduce(const double *__restrict__ part_, int32_t k, int32_t R,
+                                                         int32_t npad, double *__restrict__ H_) {
+    __shared__ double seg_sum[16][64];
+    const auto part = gmem(part_);
+    const auto H = gmem(H_);
+    const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
     const int32_t T = (k + kRrTile - 1) / kRrTile;
     const int64_t total = (int64_t)npad * npad;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t a = (int32_t)(e / npad), b = (int32_t)(e % npad);
-        if (a > b) continue;
-        double v = 0.0;
-        if (b < k) {
-            const int32_t ta = a / kRrTile, tb = b / kRrTile;
-            const int32_t t = ta * T - ta * (ta - 1) / 2 + (tb - ta);
-            const double *p = part + ((int64_t)t * R) * kRrTile * kRrTile + (a % kRrTile) * kRrTile + (b % kRrTile);
-            for (int32_t r = 0; r < R; ++r) v += p[(int64_t)r * kRrTile * kRrTile];
+    const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+    const int32_t a = e < total ? (int32_t)(e / npad) : 0, b = e < total ? (int32_t)(e % npad) : 0;
+    const bool live = e < total && a <= b && b < k;
+    double v = 0.0;
+    if (live) {
+        const int32_t ta = a / kRrTile, tb = b / kRrTile;
+        const int32_t t = ta * T - ta * (ta - 1) / 2 + (tb - ta);
+        const auto p = part + ((int64_t)t * R) * kRrTile * kRrTile + (a % kRrTile) * kRrTile + (b % kRrTile);
+        const int32_t per = (R + 15) / 16, r0 = seg * per < R ? seg * per : R, r1 = r0 + per < R ? r0 + per : R;
+        int32_t r = r0;
+        for (; r + 4 <= r1; r += 4) {
+            const double x0 = p[(int64_t)r * kRrTile * kRrTile], x1 = p[(int64_t)(r + 1) * kRrTile * kRrTile];
+            const double x2 = p[(int64_t)(r + 2) * kRrTile * kRrTile], x3 = p[(int64_t)(r + 3) * kRrTile * kRrTile];
+            v += x0;
+            v += x1;
+            v += x2;
+            v += x3;
         }
-        H[(int64_t)a * npad + b] = v;
-        H[(int64_t)b * npad + a] = v;
+        for (; r < r1; ++r) v += p[(int64_t)r * kRrTile * kRrTile];
     }
+    seg_sum[seg][lane] = v;
+    __syncthreads();
+    if (seg != 0 || e >= total || a > b) return;
+    double sum = 0.0;
+    for (int g = 0; g < 16; ++g) sum += seg_sum[g][lane];
+    H[(int64_t)a * npad + b] = sum;
+    H[(int64_t)b * npad + a] = sum;
 }
 
 // U[:, i] = U0 Q[:, perm[i]] with the sign rule (largest-magnitude entry positive,
@@ -420,9 +440,8 @@ void launch_rr_h(const CscView &A, int64_t N, int32_t k, const double *U0, doubl
         if (even) hipLaunchKernelGGL((k_rr_syrk<float, true>), dim3(blocks), dim3(256), 0, s, A.colptr, A.rowidx, v, N, k, R, U0, part);
         else hipLaunchKernelGGL((k_rr_syrk<float, false>), dim3(blocks), dim3(256), 0, s, A.colptr, A.rowidx, v, N, k, R, U0, part);
     }
-    int64_t rb = ((int64_t)npad * npad + 255) / 256;
-    if (rb > 4096) rb = 4096;
-    hipLaunchKernelGGL(k_rr_syrk_reduce, dim3((unsigned)rb), dim3(256), 0, s, part, k, R, npad, H);
+    const int64_t rb = ((int64_t)npad * npad + 63) / 64;
+    hipLaunchKernelGGL(k_rr_syrk_reduce, dim3((unsigned)rb), dim3(1024), 0, s, part, k, R, npad, H);
 }
 
 void launch_rr_apply(const double *U0, const double *Q, int64_t ldq, const int32_t *perm, int32_t M, int32_t k,
