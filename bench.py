@@ -37,11 +37,11 @@ def parse():
     return ap.parse_args()
 
 
-# HBM bytes per working launch of k_jround on the powerlaw_1m FP64 leg, from two rocprofv3 counter
+# HBM bytes per working launch of k_jround on the 1M power-law FP64 leg, from two rocprofv3 counter
 # runs (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, averaged over the launches that did work),
 # each scaled by what the same counter reads back for a plain device copy of 1 GiB (x2.0 for
 # FETCH_SIZE, x1.0 for WRITE_SIZE).  Valid only for the kernel source it was taken on.
-JROUND_TRAFFIC = {"bytes": (6732.91 * 2.0 + 15467.99) * 1024, "source_sha256": "0bb7476ef026e4e3dd39bd52c2ae6673527494c23ad805d88dba00e9e2217ca4"}
+JROUND_TRAFFIC = {"bytes": (6775.88 * 2.0 + 15472.86) * 1024, "source_sha256": "3c367046c94a771096a218f1cf97f0da2985a6a04ac81e2a1a9b2f7a651d4fbd"}
 
 
 def jround_traffic():
