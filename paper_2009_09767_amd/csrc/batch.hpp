@@ -46,6 +46,7 @@ struct MatDesc {
     double *sdbl, *G, *G2, *W, *J, *S, *lam;
     // outputs (caller-owned)
     double *sigma, *U;
+    float *Uf;                // FP32 copy of U for an FP32 V (the back-projection reads it), or NULL
     void *V;
 };
 

@@ -368,7 +368,7 @@ __global__ __launch_bounds__(1024) void k_rr_syrk_reduce(const double *__restric
 // lowest row on a tie).  One workgroup per output column; Q's column is staged in LDS.
 __global__ __launch_bounds__(256) void k_rr_apply(const double *__restrict__ U0, const double *__restrict__ Q,
                                                   int64_t ldq, const int32_t *__restrict__ perm, int32_t M,
-                                                  int32_t k, double *__restrict__ U) {
+                                                  int32_t k, double *__restrict__ U, float *__restrict__ Uf) {
     extern __shared__ double qcol[];
     __shared__ double best_abs[256];
     __shared__ int32_t best_row[256];
@@ -404,8 +404,15 @@ __global__ __launch_bounds__(256) void k_rr_apply(const double *__restrict__ U0,
     }
     const int32_t top = best_row[0];
     __syncthreads();
-    if (U[(int64_t)top * k + i] < 0.0)
-        for (int32_t m = threadIdx.x; m < M; m += blockDim.x) U[(int64_t)m * k + i] = -U[(int64_t)m * k + i];
+    // every wave reads the pivot before any wave flips it (the pivot row is one of the rows
+    // flipped below)
+    const bool flip = U[(int64_t)top * k + i] < 0.0;
+    __syncthreads();
+    for (int32_t m = threadIdx.x; m < M; m += blockDim.x) {
+        const double u = flip ? -U[(int64_t)m * k + i] : U[(int64_t)m * k + i];
+        if (flip) U[(int64_t)m * k + i] = u;
+        if (Uf) Uf[(int64_t)m * k + i] = (float)u;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -445,9 +452,9 @@ void launch_rr_h(const CscView &A, int64_t N, int32_t k, const double *U0, doubl
 }
 
 void launch_rr_apply(const double *U0, const double *Q, int64_t ldq, const int32_t *perm, int32_t M, int32_t k,
-                     double *U, hipStream_t s) {
+                     double *U, float *Uf, hipStream_t s) {
     hipLaunchKernelGGL(k_rr_apply, dim3((unsigned)k), dim3(256), sizeof(double) * (size_t)k, s, U0, Q, ldq, perm, M,
-                       k, U);
+                       k, U, Uf);
 }
 
 }  // namespace ranky

@@ -93,7 +93,10 @@ __global__ __launch_bounds__(256) void k_gather_u(const MatDesc *__restrict__ de
     const int32_t i = blockIdx.x - wp[mat];
     if (i >= n) {
         const int32_t e = empty[i - n];
-        for (int32_t m = threadIdx.x; m < M; m += blockDim.x) U[(int64_t)m * k + i] = (m == e) ? 1.0 : 0.0;
+        for (int32_t m = threadIdx.x; m < M; m += blockDim.x) {
+            U[(int64_t)m * k + i] = (m == e) ? 1.0 : 0.0;
+            if (d.Uf) d.Uf[(int64_t)m * k + i] = (m == e) ? 1.f : 0.f;
+        }
         return;
     }
     const int32_t col = perm[i];
@@ -125,7 +128,9 @@ __global__ __launch_bounds__(256) void k_gather_u(const MatDesc *__restrict__ de
     const double sgn = W[(int64_t)best_row[0] * ld + col] < 0.0 ? -1.0 : 1.0;
     for (int32_t m = threadIdx.x; m < M; m += blockDim.x) {
         const int32_t p = m2r[m];
-        U[(int64_t)m * k + i] = p >= 0 ? sgn * W[(int64_t)p * ld + col] : 0.0;
+        const double u = p >= 0 ? sgn * W[(int64_t)p * ld + col] : 0.0;
+        U[(int64_t)m * k + i] = u;
+        if (d.Uf) d.Uf[(int64_t)m * k + i] = (float)u;
     }
 }
 
@@ -138,9 +143,9 @@ __global__ __launch_bounds__(256) void k_gather_u(const MatDesc *__restrict__ de
 // nonzeros are taken four (P = 1) or two at a time with independent loads; each output
 // adds them in order.  U rows come from L2, and V goes out with non-temporal stores so
 // it does not evict them.
-template <typename TV, typename TO, int P>
+template <typename TV, typename TO, typename TU, int P>
 __device__ void backproject_cols(const int32_t *__restrict__ colptr_, const int32_t *__restrict__ rowidx_,
-                                 const TV *__restrict__ vals_, int64_t N, int32_t k, const double *__restrict__ U_,
+                                 const TV *__restrict__ vals_, int64_t N, int32_t k, const TU *__restrict__ U_,
                                  const double *__restrict__ sigma_, int32_t rank, TO *__restrict__ V_, int64_t wave,
                                  int64_t nwaves) {
     const auto colptr = gmem(colptr_);
@@ -178,7 +183,7 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr_, const int3
             // kNz nonzeros per step with independent loads (their U rows in flight together)
             for (; e + kNz <= e1; e += kNz) {
                 double av[kNz];
-                __attribute__((address_space(1))) const double *Um[kNz];
+                __attribute__((address_space(1))) const TU *Um[kNz];
 #pragma unroll
                 for (int t = 0; t < kNz; ++t) {
                     av[t] = static_cast<double>(vals[e + t]);
@@ -190,15 +195,15 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr_, const int3
                         double x = a0[p], y = a1[p];
 #pragma unroll
                         for (int t = 0; t < kNz; ++t) {
-                            x = fma(av[t], Um[t][i[p]], x);
-                            y = fma(av[t], Um[t][i[p] + 1], y);
+                            x = fma(av[t], static_cast<double>(Um[t][i[p]]), x);
+                            y = fma(av[t], static_cast<double>(Um[t][i[p] + 1]), y);
                         }
                         a0[p] = x;
                         a1[p] = y;
                     } else if (ok0[p]) {
                         double x = a0[p];
 #pragma unroll
-                        for (int t = 0; t < kNz; ++t) x = fma(av[t], Um[t][i[p]], x);
+                        for (int t = 0; t < kNz; ++t) x = fma(av[t], static_cast<double>(Um[t][i[p]]), x);
                         a0[p] = x;
                     }
                 }
@@ -209,10 +214,10 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr_, const int3
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
                     if (ok1[p]) {
-                        a0[p] = fma(a, Um[i[p]], a0[p]);
-                        a1[p] = fma(a, Um[i[p] + 1], a1[p]);
+                        a0[p] = fma(a, static_cast<double>(Um[i[p]]), a0[p]);
+                        a1[p] = fma(a, static_cast<double>(Um[i[p] + 1]), a1[p]);
                     } else if (ok0[p]) {
-                        a0[p] = fma(a, Um[i[p]], a0[p]);
+                        a0[p] = fma(a, static_cast<double>(Um[i[p]]), a0[p]);
                     }
                 }
             }
@@ -248,36 +253,44 @@ __global__ __launch_bounds__(256) void k_backproject(const MatDesc *__restrict__
     const int64_t wave = (((int64_t)blockIdx.x - wp[mat]) * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)(wp[mat + 1] - wp[mat]) * blockDim.x) >> 6;
     const int32_t rank = d.scal[kScRank];
+    // an FP32 V reads the FP32 copy of U (half the bytes per gathered row)
     if (d.dtype == 1) {
         const double *v = static_cast<const double *>(d.values);
         if (d.v_dtype == 1)
-            backproject_cols<double, double, P>(d.colptr, d.rowidx, v, d.N, d.k, d.U, d.sigma, rank,
-                                                  static_cast<double *>(d.V), wave, nwaves);
+            backproject_cols<double, double, double, P>(d.colptr, d.rowidx, v, d.N, d.k, d.U, d.sigma, rank,
+                                                        static_cast<double *>(d.V), wave, nwaves);
+        else if (d.Uf)
+            backproject_cols<double, float, float, P>(d.colptr, d.rowidx, v, d.N, d.k, d.Uf, d.sigma, rank,
+                                                      static_cast<float *>(d.V), wave, nwaves);
         else
-            backproject_cols<double, float, P>(d.colptr, d.rowidx, v, d.N, d.k, d.U, d.sigma, rank,
-                                                 static_cast<float *>(d.V), wave, nwaves);
+            backproject_cols<double, float, double, P>(d.colptr, d.rowidx, v, d.N, d.k, d.U, d.sigma, rank,
+                                                       static_cast<float *>(d.V), wave, nwaves);
     } else {
         const float *v = static_cast<const float *>(d.values);
         if (d.v_dtype == 1)
-            backproject_cols<float, double, P>(d.colptr, d.rowidx, v, d.N, d.k, d.U, d.sigma, rank,
-                                                 static_cast<double *>(d.V), wave, nwaves);
+            backproject_cols<float, double, double, P>(d.colptr, d.rowidx, v, d.N, d.k, d.U, d.sigma, rank,
+                                                       static_cast<double *>(d.V), wave, nwaves);
+        else if (d.Uf)
+            backproject_cols<float, float, float, P>(d.colptr, d.rowidx, v, d.N, d.k, d.Uf, d.sigma, rank,
+                                                     static_cast<float *>(d.V), wave, nwaves);
         else
-            backproject_cols<float, float, P>(d.colptr, d.rowidx, v, d.N, d.k, d.U, d.sigma, rank,
-                                                static_cast<float *>(d.V), wave, nwaves);
+            backproject_cols<float, float, double, P>(d.colptr, d.rowidx, v, d.N, d.k, d.U, d.sigma, rank,
+                                                      static_cast<float *>(d.V), wave, nwaves);
     }
 }
 
-// Stand-alone back-projection with an explicit device rank (step call).
-template <typename TV, typename TO, int P>
+// Stand-alone back-projection with an explicit device rank (step call, and the refined
+// path's final V).
+template <typename TV, typename TO, typename TU, int P>
 __global__ __launch_bounds__(256) void k_backproject_one(const int32_t *__restrict__ colptr,
                                                          const int32_t *__restrict__ rowidx,
                                                          const TV *__restrict__ vals, int64_t N, int32_t k,
-                                                         const double *__restrict__ U,
+                                                         const TU *__restrict__ U,
                                                          const double *__restrict__ sigma,
                                                          const int32_t *__restrict__ rank_ptr, TO *__restrict__ V) {
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    backproject_cols<TV, TO, P>(colptr, rowidx, vals, N, k, U, sigma, *rank_ptr, V, wave, nwaves);
+    backproject_cols<TV, TO, TU, P>(colptr, rowidx, vals, N, k, U, sigma, *rank_ptr, V, wave, nwaves);
 }
 
 // ---------------------------------------------------------------------------
@@ -311,36 +324,38 @@ void launch_backproject_batch(const MatDesc *descs, const int32_t *wp, int64_t n
     else hipLaunchKernelGGL(k_backproject<1>, grid, block, 0, s, descs, wp, count);
 }
 
-template <int P>
-static void launch_one(const CscView &A, int64_t N, int32_t k, const double *U, const double *sigma,
-                       const int32_t *rank, void *V, int32_t v_dtype, dim3 grid, hipStream_t s) {
+template <typename TV, int P>
+static void launch_one_tv(const CscView &A, const TV *v, int64_t N, int32_t k, const double *U, const float *Uf,
+                          const double *sigma, const int32_t *rank, void *V, int32_t v_dtype, dim3 grid,
+                          hipStream_t s) {
     const dim3 block(256);
-    if (A.dtype == 1) {
-        const double *v = static_cast<const double *>(A.values);
-        if (v_dtype == 1)
-            hipLaunchKernelGGL((k_backproject_one<double, double, P>), grid, block, 0, s, A.colptr, A.rowidx, v, N,
-                               k, U, sigma, rank, static_cast<double *>(V));
-        else
-            hipLaunchKernelGGL((k_backproject_one<double, float, P>), grid, block, 0, s, A.colptr, A.rowidx, v, N,
-                               k, U, sigma, rank, static_cast<float *>(V));
-    } else {
-        const float *v = static_cast<const float *>(A.values);
-        if (v_dtype == 1)
-            hipLaunchKernelGGL((k_backproject_one<float, double, P>), grid, block, 0, s, A.colptr, A.rowidx, v, N,
-                               k, U, sigma, rank, static_cast<double *>(V));
-        else
-            hipLaunchKernelGGL((k_backproject_one<float, float, P>), grid, block, 0, s, A.colptr, A.rowidx, v, N,
-                               k, U, sigma, rank, static_cast<float *>(V));
-    }
+    if (v_dtype == 1)
+        hipLaunchKernelGGL((k_backproject_one<TV, double, double, P>), grid, block, 0, s, A.colptr, A.rowidx, v, N, k,
+                           U, sigma, rank, static_cast<double *>(V));
+    else if (Uf)   // an FP32 V from the FP32 copy of U
+        hipLaunchKernelGGL((k_backproject_one<TV, float, float, P>), grid, block, 0, s, A.colptr, A.rowidx, v, N, k,
+                           Uf, sigma, rank, static_cast<float *>(V));
+    else
+        hipLaunchKernelGGL((k_backproject_one<TV, float, double, P>), grid, block, 0, s, A.colptr, A.rowidx, v, N, k,
+                           U, sigma, rank, static_cast<float *>(V));
 }
 
-void launch_backproject(const CscView &A, int64_t N, int32_t k, const double *U, const double *sigma,
+template <int P>
+static void launch_one(const CscView &A, int64_t N, int32_t k, const double *U, const float *Uf, const double *sigma,
+                       const int32_t *rank, void *V, int32_t v_dtype, dim3 grid, hipStream_t s) {
+    if (A.dtype == 1)
+        launch_one_tv<double, P>(A, static_cast<const double *>(A.values), N, k, U, Uf, sigma, rank, V, v_dtype, grid, s);
+    else
+        launch_one_tv<float, P>(A, static_cast<const float *>(A.values), N, k, U, Uf, sigma, rank, V, v_dtype, grid, s);
+}
+
+void launch_backproject(const CscView &A, int64_t N, int32_t k, const double *U, const float *Uf, const double *sigma,
                         const int32_t *rank, void *V, int32_t v_dtype, int32_t cu_count, hipStream_t s) {
     const dim3 grid((unsigned)backproject_blocks(N, cu_count));
     const int32_t pairs = backproject_pairs(k);
-    if (pairs == 4) launch_one<4>(A, N, k, U, sigma, rank, V, v_dtype, grid, s);
-    else if (pairs == 2) launch_one<2>(A, N, k, U, sigma, rank, V, v_dtype, grid, s);
-    else launch_one<1>(A, N, k, U, sigma, rank, V, v_dtype, grid, s);
+    if (pairs == 4) launch_one<4>(A, N, k, U, Uf, sigma, rank, V, v_dtype, grid, s);
+    else if (pairs == 2) launch_one<2>(A, N, k, U, Uf, sigma, rank, V, v_dtype, grid, s);
+    else launch_one<1>(A, N, k, U, Uf, sigma, rank, V, v_dtype, grid, s);
 }
 
 hipError_t select_set_attributes() {

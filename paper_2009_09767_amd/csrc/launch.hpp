@@ -70,15 +70,18 @@ int64_t backproject_blocks(int64_t N, int32_t cu_count, int32_t per_cu = 32);
 inline int32_t backproject_pairs(int32_t k) { return k <= 128 ? 1 : (k <= 256 ? 2 : 4); }
 void launch_backproject_batch(const MatDesc *descs, const int32_t *wp, int64_t nblocks, int count, int32_t pairs,
                               hipStream_t s);
-void launch_backproject(const CscView &A, int64_t N, int32_t k, const double *U, const double *sigma,
-                        const int32_t *rank, void *V, int32_t v_dtype, int32_t cu_count, hipStream_t s);
+// Uf (or NULL): the FP32 copy of U, read instead of U when V is FP32
+void launch_backproject(const CscView &A, int64_t N, int32_t k, const double *U, const float *Uf,
+                        const double *sigma, const int32_t *rank, void *V, int32_t v_dtype, int32_t cu_count,
+                        hipStream_t s);
 hipError_t select_set_attributes();
 
 // Rayleigh-Ritz refinement with the exact operator (k_refine.hip)
 size_t rr_part_doubles(int64_t N, int32_t k);   // partial H tiles of the Rayleigh-Ritz SYRK
 void launch_rr_h(const CscView &A, int64_t N, int32_t k, const double *U0, double *part, int32_t npad, double *H,
                  hipStream_t s);
+// U = U0 Q (sign rule applied); Uf (or NULL) gets the same U in FP32
 void launch_rr_apply(const double *U0, const double *Q, int64_t ldq, const int32_t *perm, int32_t M, int32_t k,
-                     double *U, hipStream_t s);
+                     double *U, float *Uf, hipStream_t s);
 
 }  // namespace ranky

@@ -93,16 +93,17 @@ struct Plan {
     size_t o_gsegp = 0, o_gslot = 0, o_gpart = 0, o_dense = 0, o_dpart = 0;
     int32_t dwg = 0;
     size_t o_G = 0, o_G2 = 0, o_W = 0, o_J = 0, o_S = 0, o_jflag = 0, o_lam = 0, o_perm = 0;
-    size_t o_U0 = 0, o_part = 0, total = 0;
+    size_t o_U0 = 0, o_part = 0, o_uf = 0, total = 0;
     size_t o_bstart = 0;
-    bool solver = false, refine = false, explicit_blocks = false;
+    bool solver = false, refine = false, explicit_blocks = false, uf = false;
 };
 
 // bstart (host, may be NULL): the caller's D + 1 block boundaries; the widest block sets
 // the chunks per block, and the boundaries get a device copy in the workspace.
 // dense: room for the split-bf16 dense tiles (a single matrix; used with gram_prec BF16X3).
+// uf: room for an FP32 copy of U (solver plans with an FP32 V: the back-projection gathers it).
 Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool solver, bool refine,
-               const int64_t *bstart = nullptr, bool dense = false) {
+               const int64_t *bstart = nullptr, bool dense = false, bool uf = false) {
     Plan p;
     p.M = M;
     p.N = N;
@@ -168,6 +169,10 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool sol
             p.o_U0 = take(sizeof(double) * (size_t)M * k);
             p.o_part = take(sizeof(double) * rr_part_doubles(N, k));
         }
+        if (uf) {
+            p.uf = true;
+            p.o_uf = take(sizeof(float) * (size_t)M * k);
+        }
     }
     p.total = off;
     return p;
@@ -225,6 +230,7 @@ MatDesc carve(const Plan &p, char *base, Refine *rf) {
         d.jflag = i32(p.o_jflag);
         d.lam = f64(p.o_lam);
         d.perm = i32(p.o_perm);
+        d.Uf = p.uf ? reinterpret_cast<float *>(base + p.o_uf) : nullptr;
     }
     if (rf && p.refine) {
         rf->U0 = f64(p.o_U0);
@@ -628,7 +634,8 @@ size_t path_bytes(const std::vector<Job> &jobs, const ranky_opts &o) {
     int32_t maxM = 1;
     size_t total = 0;
     for (const Job &j : jobs) {
-        total += make_plan(j.M, j.N, j.A.nnz, j.k, j.D, true, refine, j.bstart, count == 1).total;
+        total += make_plan(j.M, j.N, j.A.nnz, j.k, j.D, true, refine, j.bstart, count == 1, o.v_dtype == RANKY_F32)
+                     .total;
         maxM = std::max(maxM, j.M);
     }
     return total + make_header(count, count, jacobi_npad(maxM) / kJacobiBlock).total;
@@ -643,7 +650,7 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
     int32_t maxM = 1;
     for (int i = 0; i < count; ++i) {
         plans[i] = make_plan(jobs[i].M, jobs[i].N, jobs[i].A.nnz, jobs[i].k, jobs[i].D, true, refine, jobs[i].bstart,
-                             count == 1);
+                             count == 1, o.v_dtype == RANKY_F32);
         maxM = std::max(maxM, jobs[i].M);
     }
     const Header h = make_header(count, count, jacobi_npad(maxM) / kJacobiBlock);
@@ -764,8 +771,8 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
         refine_sweeps = eh.sweeps[0];
         refine_notconv = eh.notconv[0];
         launch_select(eh.ddesc(), 1, k, s);
-        launch_rr_apply(rf.U0, y.W, kpad, y.perm, j.M, k, j.U, s);
-        launch_backproject(Av, j.N, k, j.U, j.sigma, y.scal + kScRank, j.V, o.v_dtype, ctx->cu_count, s);
+        launch_rr_apply(rf.U0, y.W, kpad, y.perm, j.M, k, j.U, x.Uf, s);
+        launch_backproject(Av, j.N, k, j.U, x.Uf, j.sigma, y.scal + kScRank, j.V, o.v_dtype, ctx->cu_count, s);
         HIP_TRY(hipGetLastError());
         e.d[0].U = j.U;
         st = e.upload_desc();
@@ -1342,7 +1349,7 @@ ranky_status ranky_backproject(const ranky_csc *A, int32_t M, int64_t N, int32_t
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const CscView Av{A->nnz, A->colptr, A->rowidx, A->values, A->dtype};
-    launch_backproject(Av, N, k, U, sigma, rank, V, v_dtype, cus, reinterpret_cast<hipStream_t>(stream));
+    launch_backproject(Av, N, k, U, nullptr, sigma, rank, V, v_dtype, cus, reinterpret_cast<hipStream_t>(stream));
     HIP_TRY(hipGetLastError());
     return RANKY_OK;
 }
