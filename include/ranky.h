@@ -173,7 +173,10 @@ size_t ranky_workspace_bytes(int32_t M, int64_t N, int64_t nnz, int32_t k, const
  *                        (lowest row on an exact tie); columns i >= M' are e_row for
  *                        the empty rows in ascending row order
  *   V     [N x k]        row-major, v_dtype; V[:, i] = A^T u_i / sigma_i for i < rank,
- *                        exactly 0 for i >= rank (no division by a vanishing sigma)
+ *                        exactly 0 for i >= rank (no division by a vanishing sigma).
+ *                        An F32 V is formed from U rounded to FP32 (a copy kept in
+ *                        the workspace), with FP64 products and sums and one
+ *                        rounding at the store; an F64 V from the FP64 U
  *   info  (host, may be NULL)
  * Errors: E_INVALID (M < 1, N < 1, k < 1 or k > M, tol < 0 or NaN, nnz outside
  * [0, 2^31), D outside [1, N], M > 8192, a NULL pointer), E_NOMEM (ws_bytes too
@@ -379,7 +382,9 @@ ranky_status ranky_eigh(int32_t n, const double *G, double *lambda, double *Q, i
  *   V[j][i] = (sum_m a_mj U[m][i]) / sigma[i]   for i < *rank
  *   V[j][i] = 0                                 for i >= *rank
  *   U [M x k] FP64 row-major, sigma [k] FP64, rank: device int32 scalar,
- *   V [N x k] row-major of v_dtype.  Stream-ordered; no workspace. */
+ *   V [N x k] row-major of v_dtype (FP64 products and sums from the FP64 U, one
+ *   rounding at the store; ranky_svd's F32 V reads U rounded to FP32 instead, so
+ *   the two F32 results may differ in the last bits).  Stream-ordered; no workspace. */
 ranky_status ranky_backproject(const ranky_csc *A, int32_t M, int64_t N, int32_t k, const double *U,
                                const double *sigma, const int32_t *rank, void *V, int32_t v_dtype,
                                ranky_stream_t stream);
