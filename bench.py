@@ -331,13 +331,21 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
 
+        # the oracle's OpenMP loops run OMP_NUM_THREADS threads (all cores of the affinity mask if unset)
         cores = len(os.sched_getaffinity(0))
-        t0 = time.perf_counter()
-        ref = oracle.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=k, method="gram", want_v=True)
-        t_cpu = time.perf_counter() - t0
+        if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+            cores = min(cores, max(1, int(os.environ["OMP_NUM_THREADS"])))
+        # the whole workload, repeated until at least 10 s of CPU work (at most 30 passes)
+        reps, t_cpu = 0, 0.0
+        while reps < 30 and (reps == 0 or t_cpu < 10.0):
+            t0 = time.perf_counter()
+            ref = oracle.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=k, method="gram", want_v=True)
+            t_cpu += time.perf_counter() - t0
+            reps += 1
         r = ref.rank
-        line["cpu_baseline"] = {"value": A.nnz / t_cpu, "unit": "nnz/s", "cores": cores, "kind": "oracle",
-                                "sample": "the whole workload once: FP64 sparse Gram + cyclic Jacobi + V (Gram route)",
+        line["cpu_baseline"] = {"value": reps * A.nnz / t_cpu, "unit": "nnz/s", "cores": cores, "kind": "oracle",
+                                "sample": "the whole workload, %d passes: FP64 sparse Gram + cyclic Jacobi + V "
+                                          "(Gram route)" % reps,
                                 "seconds": t_cpu}
         line["sigma_rel_err_vs_oracle"] = float(np.max(np.abs(sig64[:r] - ref.sigma[:r]) / ref.sigma[:r]))
         for p, res in other_res.items():
