@@ -69,6 +69,34 @@ def test_mix_equals_alone(R):
         assert torch.equal(o.V, alone.V)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_mix_equals_alone_reduced_precision(R, prec):
+    """FP32 or split-bf16 Gram, the FP64 Rayleigh-Ritz step and an FP32 V (read from the FP32
+    copy of U in each request's workspace): served results are bitwise those of ranky_svd."""
+    import torch
+
+    mats = request_pool(count=6, seed=37)
+    dms = [R.to_device(A) for A in mats]
+    ks = [min(A.M, 48) for A in mats]
+    kw = dict(gram_prec=prec, refine=1, v_dtype=torch.float32)
+    srv = R.Server(arena_bytes=1 << 30, max_slots=3, max_queue=64, **kw)
+    outs = [alloc_out(R, torch, A, k, torch.float32) for A, k in zip(mats, ks)]
+    tickets = []
+    for dA, k, o in zip(dms, ks, outs):
+        st, t = srv.submit(dA, k, o)
+        assert st == R.OK
+        tickets.append(t)
+    for t in tickets:
+        st, info = srv.wait(t, 60_000_000)
+        assert st == R.OK, (st, info)
+    srv.close()
+    for dA, k, o in zip(dms, ks, outs):
+        alone = R.svd(dA, k, 0.0, **kw)
+        assert torch.equal(o.sigma, alone.sigma)
+        assert torch.equal(o.U, alone.U)
+        assert torch.equal(o.V, alone.V)
+
+
 def test_admission_by_footprint(R):
     """Eight copies of one request in an arena that holds two of them: never more than two
     admitted at once, all eight complete, identical results."""
