@@ -41,16 +41,21 @@ def parse():
 # runs (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, averaged over the launches that did work),
 # each scaled by what the same counter reads back for a plain device copy of 1 GiB (x2.0 for
 # FETCH_SIZE, x1.0 for WRITE_SIZE).  Valid only for the kernel source it was taken on.
-JROUND_TRAFFIC = {"bytes": (6775.88 * 2.0 + 15472.86) * 1024, "source_sha256": "3c367046c94a771096a218f1cf97f0da2985a6a04ac81e2a1a9b2f7a651d4fbd"}
+JROUND_TRAFFIC = {"bytes": (6775.88 * 2.0 + 15472.86) * 1024, "source": "k_jacobi.hip",
+                  "source_sha256": "3c367046c94a771096a218f1cf97f0da2985a6a04ac81e2a1a9b2f7a651d4fbd"}
+# The same for k_backproject on that leg (FP64 V, 32 workgroups per CU): the CSC, U and V.
+BACKPROJECT_TRAFFIC = {"bytes": (13612.26 * 2.0 + 1048741.97) * 1024, "source": "k_select.hip",
+                       "source_sha256": "6c0cf99f7c66e1cac59dec25b2f30bf522ba41419c1dee450b49e42eda28484d"}
 
 
-def jround_traffic():
+def counted_traffic(entry):
+    """The counted bytes per launch, or None once the kernel's source differs from the one counted."""
     import hashlib
 
-    src = os.path.join(ROOT, "paper_2009_09767_amd", "csrc", "k_jacobi.hip")
+    src = os.path.join(ROOT, "paper_2009_09767_amd", "csrc", entry["source"])
     with open(src, "rb") as f:
-        ok = hashlib.sha256(f.read()).hexdigest() == JROUND_TRAFFIC["source_sha256"]
-    return JROUND_TRAFFIC["bytes"] if ok else None
+        ok = hashlib.sha256(f.read()).hexdigest() == entry["source_sha256"]
+    return entry["bytes"] if ok else None
 
 
 def jround_flops(n):
@@ -310,11 +315,12 @@ def main():
         "phase_ms": phases,
         "roofline": {"kernel": "k_jround (Jacobi round: subproblem sweep + FP64 MFMA tile update)",
                      "bound": "mfma", "achieved": jr_tfs, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
-                     "frac": jr_tfs / FP64_PEAK_TFS, "traffic": jround_traffic(), "flops_per_launch": jf,
+                     "frac": jr_tfs / FP64_PEAK_TFS, "traffic": counted_traffic(JROUND_TRAFFIC), "flops_per_launch": jf,
                      "avg_launch_us": info["round_us_avg"], "launches_per_step": info["round_launches_per_call"],
                      "dtype": "fp64"},
         "roofline_spmm": {"kernel": "k_backproject (V = A^T U Sigma^-1)", "bound": "hbm", "achieved": achieved,
-                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                          "traffic": counted_traffic(BACKPROJECT_TRAFFIC),
                           "bytes_per_launch": sb},
     }
     for p, (ms2, phases2, info2, sig2, vdt2) in other_res.items():
