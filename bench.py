@@ -263,7 +263,7 @@ def time_serving(ranky, torch, gen, seconds, pool_size=48, slots=8):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
+        print(json.dumps({"error": "the path runs on one GPU (no collectives); --gpus above 1 is not supported"}))
         sys.exit(2)
     if args.copy_calibration > 0:
         copy_calibration(args.copy_calibration)
