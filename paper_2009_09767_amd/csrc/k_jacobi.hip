@@ -724,6 +724,18 @@ __global__ __launch_bounds__(256) void k_jcheck(const MatDesc *__restrict__ desc
     }
     const int tj = ti + rem;
     const int64_t r0 = (int64_t)ti * kT, c0 = (int64_t)tj * kT;
+    // every load of the tile issued first, then the diagonal's, before any test (a load under
+    // the test's branch would wait on its own); indices clamped into the n x n part, so each
+    // load is in bounds
+    constexpr int kPer = kT * kT / 256;
+    const auto Gm = gmem(G);
+    double g[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+        const int e = threadIdx.x + 256 * t;
+        const int64_t p = min(r0 + e / kT, (int64_t)n - 1), q = min(c0 + e % kT, (int64_t)n - 1);
+        g[t] = Gm[p * ld + q];
+    }
     if (threadIdx.x < kT) {
         const int64_t p = r0 + threadIdx.x;
         drow[threadIdx.x] = p < n ? G[p * ld + p] : 0.0;
@@ -733,13 +745,12 @@ __global__ __launch_bounds__(256) void k_jcheck(const MatDesc *__restrict__ desc
     }
     __syncthreads();
     int bad = 0;
-    for (int e = threadIdx.x; e < kT * kT; e += 256) {
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+        const int e = threadIdx.x + 256 * t;
         const int r = e / kT, c = e % kT;
         const int64_t p = r0 + r, q = c0 + c;
-        if (q > p && q < n) {
-            const double g = G[p * ld + q];
-            if (fabs(g) > floor_abs && g * g > tol2 * fabs(drow[r] * dcol[c])) bad = 1;
-        }
+        if (q > p && q < n && fabs(g[t]) > floor_abs && g[t] * g[t] > tol2 * fabs(drow[r] * dcol[c])) bad = 1;
     }
     if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(&d.jstate[kJsCheck], 1);
 }
