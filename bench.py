@@ -41,8 +41,8 @@ def parse():
 # runs (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, averaged over the launches that did work),
 # each scaled by what the same counter reads back for a plain device copy of 1 GiB (x2.0 for
 # FETCH_SIZE, x1.0 for WRITE_SIZE).  Valid only for the kernel source it was taken on.
-JROUND_TRAFFIC = {"bytes": (6734.43 * 2.0 + 15472.86) * 1024, "source": "k_jacobi.hip",
-                  "source_sha256": "c967a49045f538acd59647e3ffa1598679148b69d659f0e6acf1df0de3bdc380"}
+JROUND_TRAFFIC = {"bytes": (6778.62 * 2.0 + 15473.13) * 1024, "source": "k_jacobi.hip",
+                  "source_sha256": "fc714e93f5894848e58f024434390430ad3155f9b849fb6a2a593d53dc8f4f0d"}
 # The same for k_backproject on that leg (FP64 V, 32 workgroups per CU): the CSC, U and V.
 BACKPROJECT_TRAFFIC = {"bytes": (13612.26 * 2.0 + 1048741.97) * 1024, "source": "k_select.hip",
                        "source_sha256": "6c0cf99f7c66e1cac59dec25b2f30bf522ba41419c1dee450b49e42eda28484d"}

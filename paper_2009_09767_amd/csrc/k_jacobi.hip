@@ -755,31 +755,39 @@ __global__ __launch_bounds__(256) void k_jcheck(const MatDesc *__restrict__ desc
     if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(&d.jstate[kJsCheck], 1);
 }
 
-// Per matrix: start of a sweep (active = not converged and under the cap, clear the
-// flag) or end of a sweep (count it).
 // End of a sweep, per matrix (after the rounds and the convergence test): count the sweep
 // if it ran, take the test's verdict, decide the next sweep (not converged and under the
 // cap), clear the test flag, and publish active / sweeps / not-converged to `out` (host
-// memory the caller reads after synchronising the stream; NULL: no copy).
+// memory; NULL: no copy), then the launch's epoch.  One workgroup for all matrices.
 __global__ __launch_bounds__(256) void k_jstate(const MatDesc *__restrict__ descs, int count, int32_t max_sweeps,
-                                                int32_t *__restrict__ out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    int32_t *js = descs[i].jstate;
-    int32_t active = 0, sweeps = js[kJsSweeps], nc = 0;
-    if (descs[i].n > 0) {
-        sweeps += js[kJsActive];
-        nc = js[kJsCheck];
-        active = (nc != 0 && sweeps < max_sweeps) ? 1 : 0;
+                                                int32_t *__restrict__ out, int32_t *__restrict__ epoch) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) {
+        int32_t *js = descs[i].jstate;
+        int32_t active = 0, sweeps = js[kJsSweeps], nc = 0;
+        if (descs[i].n > 0) {
+            sweeps += js[kJsActive];
+            nc = js[kJsCheck];
+            active = (nc != 0 && sweeps < max_sweeps) ? 1 : 0;
+        }
+        js[kJsSweeps] = sweeps;
+        js[kJsNotConv] = nc;
+        js[kJsCheck] = 0;
+        js[kJsActive] = active;
+        if (out) {
+            out[3 * i + 0] = active;
+            out[3 * i + 1] = sweeps;
+            out[3 * i + 2] = nc;
+        }
     }
-    js[kJsSweeps] = sweeps;
-    js[kJsNotConv] = nc;
-    js[kJsCheck] = 0;
-    js[kJsActive] = active;
-    if (out) {
-        out[3 * i + 0] = active;
-        out[3 * i + 1] = sweeps;
-        out[3 * i + 2] = nc;
+    if (!out) return;
+    // every entry out before the epoch: the device counter, incremented once per launch and
+    // copied to out[3 count], tells the host which launch's entries it is reading
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int32_t e = *epoch + 1;
+        *epoch = e;
+        out[3 * count] = e;
         __threadfence_system();
     }
 }
@@ -852,9 +860,9 @@ void launch_jacobi_init(const MatDesc *descs, const int32_t *wp, int64_t nblocks
     hipLaunchKernelGGL(k_jscale, dim3((unsigned)nblocks), dim3(256), 0, s, descs, wp, count);
 }
 
-void launch_jacobi_state(const MatDesc *descs, int count, int32_t max_sweeps, int32_t *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_jstate, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, descs, count, max_sweeps,
-                       out);
+void launch_jacobi_state(const MatDesc *descs, int count, int32_t max_sweeps, int32_t *out, int32_t *epoch,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_jstate, dim3(1), dim3(256), 0, s, descs, count, max_sweeps, out, epoch);
 }
 
 void launch_jacobi_round(const void *host_table, const void *table, const int32_t *wp, int64_t nblocks, int count,

@@ -52,7 +52,11 @@ size_t round_args_bytes();
 void fill_round_args(void *dst, const MatDesc &d, int32_t r, int32_t inner_sweeps);
 int64_t round_blocks(const MatDesc &d, int32_t r);
 void launch_jacobi_init(const MatDesc *descs, const int32_t *wp, int64_t nblocks, int count, hipStream_t s);
-void launch_jacobi_state(const MatDesc *descs, int count, int32_t max_sweeps, int32_t *out, hipStream_t s);
+// end of a sweep (one workgroup): state per matrix, and with out != NULL the entries
+// (active, sweeps, not converged) per matrix in out[3 i ..] followed by the launch's epoch
+// (the device counter *epoch, incremented) in out[3 count]
+void launch_jacobi_state(const MatDesc *descs, int count, int32_t max_sweeps, int32_t *out, int32_t *epoch,
+                         hipStream_t s);
 // host_table: the host copy of the launch's argument table (read when count == 1)
 void launch_jacobi_round(const void *host_table, const void *table, const int32_t *wp, int64_t nblocks, int count,
                          int32_t launch_r, size_t lds_pad, hipStream_t s);

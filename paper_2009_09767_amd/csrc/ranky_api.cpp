@@ -268,7 +268,9 @@ Header make_header(int32_t count, int32_t slots, int32_t nb_max) {
     h.o_rtab = take(round_args_bytes() * (size_t)nb_max * slots);
     h.o_col_i = take(sizeof(int32_t) * kColI * slots);
     h.o_col_f = take(sizeof(double) * 2 * slots);
-    h.o_js = take(sizeof(int32_t) * 3 * slots);   // host only: the sweep state the device writes
+    // the sweep state the device writes to host memory (3 per matrix, then the epoch); the
+    // device copy of this range holds the epoch counter
+    h.o_js = take(sizeof(int32_t) * (3 * (size_t)slots + 1));
     h.total = off;
     return h;
 }
@@ -513,6 +515,25 @@ struct Engine {
     // sweep state per matrix (active, sweeps, not converged), written by the device
     int32_t *js_dev() { return reinterpret_cast<int32_t *>(static_cast<char *>(ctx->pinned_dev) + h.o_js); }
     const int32_t *js_host() { return reinterpret_cast<const int32_t *>(stage() + h.o_js); }
+    int32_t *epoch_dev() { return reinterpret_cast<int32_t *>(hdr + h.o_js); }
+    volatile int32_t *epoch_host() { return reinterpret_cast<volatile int32_t *>(stage() + h.o_js) + 3 * count; }
+    int32_t epochs = 0;   // state launches queued (run, not captured) since the counter was reset
+
+    // Waits until the state of the last queued launch is in host memory: the host watches the
+    // epoch word instead of sleeping in a stream synchronisation, and falls back to one when
+    // the stream has ended or failed (a failure is then reported by the synchronisation).
+    ranky_status wait_state() {
+        volatile int32_t *ep = epoch_host();
+        for (uint32_t it = 1;; ++it) {
+            if (*ep == epochs) {
+                std::atomic_thread_fence(std::memory_order_acquire);
+                return RANKY_OK;
+            }
+            if ((it & 63) == 0 && hipStreamQuery(s) != hipErrorNotReady) break;
+        }
+        HIP_TRY(hipStreamSynchronize(s));
+        return RANKY_OK;
+    }
     bool any_active() {
         const int32_t *js = js_host();
         for (int i = 0; i < count; ++i)
@@ -524,7 +545,7 @@ struct Engine {
     // (sweep count, verdict, next sweep's activity) published to host memory
     void enqueue_activity() {
         launch_jacobi_check(ddesc(), dwp(kPhJcheck), nblk[kPhJcheck], count, s);
-        launch_jacobi_state(ddesc(), count, sweeps_cap, js_dev(), s);
+        launch_jacobi_state(ddesc(), count, sweeps_cap, js_dev(), epoch_dev(), s);
     }
 
     void enqueue_sweep() {
@@ -537,6 +558,11 @@ struct Engine {
     // whether any matrix is still active, so no sweep is launched only to find that the
     // previous one converged.  With use_graph the sweep is a replayed HIP graph.
     ranky_status eigensolve(bool use_graph) {
+        // the epoch counter starts again at 0 on both sides (the previous solve on this context
+        // ended with a synchronisation, so no device write to the host word is pending)
+        *epoch_host() = 0;
+        epochs = 0;
+        launch_fill_i32(epoch_dev(), 1, 0, s);
         launch_jacobi_init(ddesc(), dwp(kPhJinit), nblk[kPhJinit], count, s);
         HIP_TRY(hipGetLastError());
         sweeps.assign(count, 0);
@@ -573,6 +599,7 @@ struct Engine {
         // the first sweep's activity (read back only when its rounds are timed; otherwise a
         // matrix that is already diagonal just runs one sweep of rounds that exit at once)
         enqueue_activity();
+        ++epochs;
         HIP_TRY(hipGetLastError());
         bool active = true;
         if (time_rounds) {
@@ -593,8 +620,12 @@ struct Engine {
                 enqueue_sweep();
                 HIP_TRY(hipGetLastError());
             }
-            HIP_TRY(hipStreamSynchronize(s));
-            if (time_rounds) {
+            ++epochs;
+            if (!time_rounds) {
+                const ranky_status ws = wait_state();
+                if (ws) return ws;
+            } else {
+                HIP_TRY(hipStreamSynchronize(s));
                 float t = 0.f;
                 HIP_TRY(hipEventElapsedTime(&t, ctx->ev[9], ctx->ev[10]));
                 round_ms += t;
