@@ -44,8 +44,8 @@ def parse():
 JROUND_TRAFFIC = {"bytes": (6778.62 * 2.0 + 15473.13) * 1024, "source": "k_jacobi.hip",
                   "source_sha256": "fc714e93f5894848e58f024434390430ad3155f9b849fb6a2a593d53dc8f4f0d"}
 # The same for k_backproject on that leg (FP64 V, 32 workgroups per CU): the CSC, U and V.
-BACKPROJECT_TRAFFIC = {"bytes": (13612.26 * 2.0 + 1048741.97) * 1024, "source": "k_select.hip",
-                       "source_sha256": "6c0cf99f7c66e1cac59dec25b2f30bf522ba41419c1dee450b49e42eda28484d"}
+BACKPROJECT_TRAFFIC = {"bytes": (13605.64 * 2.0 + 1048841.05) * 1024, "source": "k_select.hip",
+                       "source_sha256": "10ec62b8b56e6f7f358da962eb913eaae2dca55ea1235111e7c3b02a437fe775"}
 
 
 def counted_traffic(entry):

@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void k_gather_u(const MatDesc *__restrict__ de
 
 // V[j][i] = (sum over the nonzeros a_mj of column j of a_mj U[m][i]) / sigma[i] for
 // i < rank, else 0.  A wave handles one column at a time, over a contiguous run of
-// columns; a lane owns P pairs of outputs, i = i0 + 128 p + 2 lane (P = 1 for k <= 128,
+// columns whose bounds it loads 64 at a time; a lane owns P pairs of outputs, i = i0 + 128 p + 2 lane (P = 1 for k <= 128,
 // 2 for k <= 256, 4 above: one pass over the columns covers k <= 512), so every load of
 // a U row and every store of a V row is one contiguous 1 KB per wave, and the column's
 // dependent chain (bounds -> row index -> U row) is walked once per pass.  The column's
@@ -174,68 +174,79 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr_, const int3
         // then read by one wave, hence one XCD's L2 (a stride would pull it into all of them)
         const int64_t per = (N + nwaves - 1) / nwaves;
         const int64_t jb = wave * per, je = jb + per < N ? jb + per : N;
-        for (int64_t j = jb; j < je; ++j) {
-            const int32_t e0 = colptr[j], e1 = colptr[j + 1];
-            double a0[P], a1[P];
+        for (int64_t jc = jb; jc < je; jc += 64) {
+            // the bounds of the next 64 columns in one load, lane t holding column jc + t's
+            // (clamped to the run's last column, so jl + 1 <= N); each column reads its pair
+            // from the lanes instead of waiting on its own load
+            const int32_t nc = (int32_t)(je - jc < 64 ? je - jc : 64);
+            const int64_t jl = jc + (lane < nc ? lane : nc - 1);
+            const int32_t cp0 = colptr[jl], cp1 = colptr[jl + 1];
+            for (int32_t c = 0; c < nc; ++c) {
+                const int64_t j = jc + c;
+                const int32_t e0 = __builtin_amdgcn_readlane(cp0, c);
+                const int32_t e1 = __builtin_amdgcn_readlane(cp1, c);
+                double a0[P], a1[P];
 #pragma unroll
-            for (int p = 0; p < P; ++p) a0[p] = a1[p] = 0.0;
-            int32_t e = e0;
-            // kNz nonzeros per step with independent loads (their U rows in flight together)
-            for (; e + kNz <= e1; e += kNz) {
-                double av[kNz];
-                __attribute__((address_space(1))) const TU *Um[kNz];
+                for (int p = 0; p < P; ++p) a0[p] = a1[p] = 0.0;
+                int32_t e = e0;
+                // kNz nonzeros per step with independent loads (their U rows in flight together)
+                for (; e + kNz <= e1; e += kNz) {
+                    double av[kNz];
+                    __attribute__((address_space(1))) const TU *Um[kNz];
 #pragma unroll
-                for (int t = 0; t < kNz; ++t) {
-                    av[t] = static_cast<double>(vals[e + t]);
-                    Um[t] = U + (int64_t)rowidx[e + t] * k;
-                }
+                    for (int t = 0; t < kNz; ++t) {
+                        av[t] = static_cast<double>(vals[e + t]);
+                        Um[t] = U + (int64_t)rowidx[e + t] * k;
+                    }
 #pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    if (ok1[p]) {
-                        double x = a0[p], y = a1[p];
+                    for (int p = 0; p < P; ++p) {
+                        if (ok1[p]) {
+                            double x = a0[p], y = a1[p];
 #pragma unroll
-                        for (int t = 0; t < kNz; ++t) {
-                            x = fma(av[t], static_cast<double>(Um[t][i[p]]), x);
-                            y = fma(av[t], static_cast<double>(Um[t][i[p] + 1]), y);
+                            for (int t = 0; t < kNz; ++t) {
+                                x = fma(av[t], static_cast<double>(Um[t][i[p]]), x);
+                                y = fma(av[t], static_cast<double>(Um[t][i[p] + 1]), y);
+                            }
+                            a0[p] = x;
+                            a1[p] = y;
+                        } else if (ok0[p]) {
+                            double x = a0[p];
+#pragma unroll
+                            for (int t = 0; t < kNz; ++t) x = fma(av[t], static_cast<double>(Um[t][i[p]]), x);
+                            a0[p] = x;
                         }
-                        a0[p] = x;
-                        a1[p] = y;
-                    } else if (ok0[p]) {
-                        double x = a0[p];
-#pragma unroll
-                        for (int t = 0; t < kNz; ++t) x = fma(av[t], static_cast<double>(Um[t][i[p]]), x);
-                        a0[p] = x;
                     }
                 }
-            }
-            for (; e < e1; ++e) {
-                const double a = static_cast<double>(vals[e]);
-                const auto Um = U + (int64_t)rowidx[e] * k;
+                for (; e < e1; ++e) {
+                    const double a = static_cast<double>(vals[e]);
+                    const auto Um = U + (int64_t)rowidx[e] * k;
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        if (ok1[p]) {
+                            a0[p] = fma(a, static_cast<double>(Um[i[p]]), a0[p]);
+                            a1[p] = fma(a, static_cast<double>(Um[i[p] + 1]), a1[p]);
+                        } else if (ok0[p]) {
+                            a0[p] = fma(a, static_cast<double>(Um[i[p]]), a0[p]);
+                        }
+                    }
+                }
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
-                    if (ok1[p]) {
-                        a0[p] = fma(a, static_cast<double>(Um[i[p]]), a0[p]);
-                        a1[p] = fma(a, static_cast<double>(Um[i[p] + 1]), a1[p]);
+                    const double v0 = live0[p] ? a0[p] / s0[p] : 0.0;
+                    const double v1 = live1[p] ? a1[p] / s1[p] : 0.0;
+                    const auto out = V + j * (int64_t)k + i[p];
+                    if (ok1[p] && (k & 1) == 0) {
+                        // one 2-wide store (i and k are even, so it is aligned)
+                        typedef TO TO2 __attribute__((ext_vector_type(2)));
+                        const TO2 w = {static_cast<TO>(v0), static_cast<TO>(v1)};
+                        __builtin_nontemporal_store(
+                            w, reinterpret_cast<__attribute__((address_space(1))) TO2 *>(out));
+                    } else if (ok1[p]) {
+                        __builtin_nontemporal_store(static_cast<TO>(v0), out);
+                        __builtin_nontemporal_store(static_cast<TO>(v1), out + 1);
                     } else if (ok0[p]) {
-                        a0[p] = fma(a, static_cast<double>(Um[i[p]]), a0[p]);
+                        __builtin_nontemporal_store(static_cast<TO>(v0), out);
                     }
-                }
-            }
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                const double v0 = live0[p] ? a0[p] / s0[p] : 0.0;
-                const double v1 = live1[p] ? a1[p] / s1[p] : 0.0;
-                const auto out = V + j * (int64_t)k + i[p];
-                if (ok1[p] && (k & 1) == 0) {
-                    // one 2-wide store (i and k are even, so it is aligned)
-                    typedef TO TO2 __attribute__((ext_vector_type(2)));
-                    const TO2 w = {static_cast<TO>(v0), static_cast<TO>(v1)};
-                    __builtin_nontemporal_store(w, reinterpret_cast<__attribute__((address_space(1))) TO2 *>(out));
-                } else if (ok1[p]) {
-                    __builtin_nontemporal_store(static_cast<TO>(v0), out);
-                    __builtin_nontemporal_store(static_cast<TO>(v1), out + 1);
-                } else if (ok0[p]) {
-                    __builtin_nontemporal_store(static_cast<TO>(v0), out);
                 }
             }
         }
