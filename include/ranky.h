@@ -29,7 +29,9 @@
  *   - Errors are status codes; nothing throws across the ABI.  On an error the
  *     outputs are undefined.  ranky_last_error() returns a thread-local message.
  *   - Results are bitwise deterministic: every floating-point reduction runs in
- *     a fixed order, so the same inputs give the same bits on every run.
+ *     a fixed order, so the same inputs give the same bits on every run.  There is
+ *     no non-deterministic mode to opt into (no floating-point atomics anywhere), so
+ *     there is no option for it.
  */
 #ifndef RANKY_H
 #define RANKY_H
@@ -89,13 +91,14 @@ typedef struct {
     int32_t n_blocks;   /* D; block b = columns [floor(b N / D), floor((b+1) N / D)).
                            0 selects ceil(N / 16384).  1 <= D <= N. */
     int32_t gram_prec;  /* ranky_prec (default FP64) */
-    int32_t refine;     /* Rayleigh-Ritz steps after the eigensolve (0 or 1); default 1 when
-                           gram_prec != FP64, else 0 */
+    int32_t refine;     /* Rayleigh-Ritz steps after the eigensolve: 0, 1, or -1 = automatic
+                           (the default): 1 when gram_prec != FP64 and the call refines (ranky_svd,
+                           ranky_svd_async, ranky_autotune, serving; k <= 1024), else 0 */
     int32_t max_sweeps; /* Jacobi sweep cap (0 = 40) */
     int32_t validate;   /* 1 = check the CSC contract and finiteness on the device (default 1) */
     int32_t v_dtype;    /* ranky_dtype of the output V (default F64) */
     int32_t timing;     /* 1 = fill ranky_info.ms with per-phase times (adds event records) */
-    int32_t reserved;   /* 1 = replay the Jacobi sweep as a captured HIP graph (ranky_svd and
+    int32_t graph;      /* 1 = replay the Jacobi sweep as a captured HIP graph (ranky_svd and
                            ranky_batch; needs a non-NULL stream, ignored on the NULL stream) */
     const int64_t *block_start; /* host, optional: D + 1 column boundaries, block b = columns
                            [block_start[b], block_start[b+1]); block_start[0] = 0, non-decreasing,
@@ -110,7 +113,7 @@ typedef struct {
     int32_t rank;          /* r = #{sigma_i > tau}, at most k */
     int32_t n_nonempty;    /* M' = rows with at least one nonzero */
     int32_t empty_rows;    /* |E| = M - M' */
-    int32_t sweeps;        /* Jacobi sweeps used */
+    int32_t sweeps;        /* Jacobi sweeps of the eigensolve of G */
     int32_t n_blocks;      /* D actually used */
     int32_t lonely_max;    /* largest number of rows empty inside one block (Alg. 1 scan) */
     int32_t lonely_blocks; /* number of blocks with at least one empty row */
@@ -122,6 +125,14 @@ typedef struct {
                               the sweeps that did work (HIP events on the call's stream; the sweep is
                               launched directly, not replayed, in timing mode) */
     int32_t round_launches; /* number of round launches inside round_ms */
+    int32_t rr_sweeps;     /* Jacobi sweeps of the Rayleigh-Ritz eigensolve of H (0 without refinement) */
+    /* Alg. 1 scan of every block, host copies of D entries each (NULL when the call failed before
+     * the scan): rows with no entry inside block b (lonely rows), and rows with exactly one entry
+     * (NO of Eq. 4).  The memory belongs to the library: it stays valid until the next call on the
+     * same context (ranky_svd, ranky_batch, ranky_autotune), and for a served request until
+     * ranky_serve_destroy. */
+    const int32_t *lonely_per_block;
+    const int32_t *single_per_block;
 } ranky_info;
 
 typedef struct ranky_ctx ranky_ctx;
@@ -162,8 +173,10 @@ size_t ranky_workspace_bytes(int32_t M, int64_t N, int64_t nnz, int32_t k, const
  * Rayleigh-Ritz step with the exact operator; V = A^T U Sigma^{-1}.
  *
  * Rank rule: sigma_i = sqrt(max(lambda_i, 0)); sigma_i counts as zero iff
- * sigma_i <= tau = max(tol, sqrt(M' u_G)) sigma_1, u_G = 2^-53 for the FP64 Gram
- * (2^-24 for the FP32 Gram without refinement).  rank = #{sigma_i > tau}.
+ * sigma_i <= tau = max(tol, sqrt(M' u_G)) sigma_1, u_G = the unit roundoff of what was
+ * accumulated: 2^-53 for the FP64 Gram and after the FP64 Rayleigh-Ritz step, 2^-24 for
+ * the FP32 Gram, 2^-16 for a BF16X3 Gram whose split-bf16 tiles ran (at least two dense
+ * rows; otherwise it is an FP32 Gram).  rank = #{sigma_i > tau}.
  *
  * Outputs (device, caller-allocated):
  *   sigma [k]            descending; sigma_i = 0 exactly for i >= rank
@@ -253,7 +266,7 @@ typedef struct {
     int32_t M;
     int32_t k;        /* 1 <= k <= M */
     int32_t n_blocks; /* D for this matrix; 0 selects ceil(N / 16384) */
-    int32_t reserved;
+    int32_t pad;      /* alignment padding, ignored */
     double *sigma;    /* [k] */
     double *U;        /* [M x k] row-major */
     void *V;          /* [N x k] row-major, opts->v_dtype */
@@ -266,12 +279,14 @@ size_t ranky_batch_workspace_bytes(int32_t count, const ranky_batch_item *items,
  * run together: every phase is one launch whose workgroups are spread over all
  * matrices (a per-matrix descriptor table maps workgroups to matrices), and the
  * Jacobi sweeps of all matrices advance in lock-step, each matrix dropping out when
- * its own convergence test passes.  With opts->reserved = 1 the sweep is captured
+ * its own convergence test passes.  With opts->graph = 1 the sweep is captured
  * once as a HIP graph and replayed.  Blocking.
  *   items [count] host; infos [count] host (may be NULL): per-matrix ranky_info.
  * The return value is RANKY_OK only if every matrix succeeded; a matrix whose CSC
  * breaks the contract gets its own status in infos[i].status and does not stop the
- * others.  opts->refine must be 0 (Rayleigh-Ritz is per matrix: use ranky_svd). */
+ * others.  opts->refine must be 0 or -1 (Rayleigh-Ritz is per matrix: use ranky_svd); the
+ * split-bf16 tiles are a single-matrix step, so BF16X3 runs as FP32 here and the threshold
+ * uses the FP32 Gram's u_G = 2^-24. */
 ranky_status ranky_batch(ranky_ctx *ctx, int32_t count, const ranky_batch_item *items, double tol,
                          const ranky_opts *opts, void *workspace, size_t ws_bytes, ranky_info *infos,
                          ranky_stream_t stream);
@@ -289,7 +304,7 @@ typedef struct {
     int32_t max_slots;    /* requests on the device at once (each has its own stream), >= 1 */
     int32_t max_queue;    /* waiting requests before submit answers RANKY_E_BUSY, >= 1 */
     int device;
-    int32_t reserved;
+    int32_t pad;          /* alignment padding, ignored */
     ranky_opts opts;      /* path options used for every request */
 } ranky_serve_cfg;
 
@@ -316,11 +331,14 @@ typedef struct {
     size_t arena_peak_bytes;
 } ranky_serve_summary;
 
-/* Starts max_slots worker threads, each with its own context and stream.  The arena
- * is used as a first-fit heap: a request is admitted (FIFO) when a slot is free and
- * its footprint (CSC copy + ranky_workspace_bytes) fits; requests that arrive while
- * others run join as soon as memory and a slot free up, and their kernels overlap
- * on the device.  Results are bitwise those of ranky_svd alone (no shared state). */
+/* Creates max_slots contexts and HIP streams on the calling thread, one after the other,
+ * then starts one worker thread per slot.  The arena is used as a first-fit heap: a
+ * request is admitted (FIFO) when a slot is free and its footprint (CSC copy +
+ * ranky_workspace_bytes) fits; requests that arrive while others run join as soon as
+ * memory and a slot free up, and their kernels overlap on the device.  Results are
+ * bitwise those of ranky_svd alone (no shared state).  E_INVALID for a bad cfg (NULL or
+ * unaligned arena, max_slots or max_queue < 1, block_start set), E_DEVICE / E_INVALID
+ * from creating a slot's context or stream. */
 ranky_status ranky_serve_create(const ranky_serve_cfg *cfg, ranky_server **out);
 /* E_BUSY when the queue is full (back-pressure); E_NOMEM when the request could never
  * fit in the arena; E_INVALID for bad sizes.  *ticket receives the request's id. */

@@ -27,6 +27,7 @@ struct MatDesc {
     int32_t validate;
     int32_t n_tau;            // row count entering the threshold sqrt(n_tau u_gram)
     int32_t dwg;              // split-bf16 dense-tile workgroups (0: the dense rows stay in the sparse pass)
+    int32_t blk_off;          // first entry of this matrix's per-block counts in the read-back array
     double tol;               // rank threshold option
     double u_gram;            // unit roundoff of the Gram entries for the threshold
     double jtol;              // Jacobi rotation test tolerance (0: max(1e-15, sqrt(n) eps))

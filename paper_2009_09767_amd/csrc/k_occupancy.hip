@@ -432,11 +432,21 @@ __global__ __launch_bounds__(256) void k_batch_prep(const MatDesc *__restrict__ 
 // Gather every matrix's scalars into one compact array for a single read-back:
 // out_i32[10i..10i+9] = status, M', rank, sweeps, not-converged, lonely max, blocks with
 // lonely rows, active, Gram segments, Gram partial rows;  out_f64[2i..2i+1] = tau, sigma_1.
+// With out_blk != NULL also the Alg. 1 counts per block: out_blk[2 blk_off + b] = lonely rows of
+// block b, out_blk[2 blk_off + D + b] = rows with one entry in block b.
 __global__ __launch_bounds__(256) void k_batch_collect(const MatDesc *__restrict__ descs, int count,
-                                                       int32_t *__restrict__ out_i32, double *__restrict__ out_f64) {
+                                                       int32_t *__restrict__ out_i32, double *__restrict__ out_f64,
+                                                       int32_t *__restrict__ out_blk) {
     const int i = blockIdx.x;
     if (i >= count) return;
     const MatDesc &d = descs[i];
+    if (out_blk) {
+        int32_t *ob = out_blk + 2 * (int64_t)d.blk_off;
+        for (int32_t b = threadIdx.x; b < d.D; b += blockDim.x) {
+            ob[b] = d.lonely[b];
+            ob[d.D + b] = d.single[b];
+        }
+    }
     __shared__ int32_t mx[256], nz[256];
     int32_t m = 0, z = 0;
     for (int32_t b = threadIdx.x; b < d.D; b += blockDim.x) {
@@ -474,8 +484,10 @@ void launch_batch_prep(const MatDesc *descs, int count, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)count), dim3(256), 0, s, descs);
 }
 
-void launch_batch_collect(const MatDesc *descs, int count, int32_t *out_i32, double *out_f64, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_collect, dim3((unsigned)count), dim3(256), 0, s, descs, count, out_i32, out_f64);
+void launch_batch_collect(const MatDesc *descs, int count, int32_t *out_i32, double *out_f64, int32_t *out_blk,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_collect, dim3((unsigned)count), dim3(256), 0, s, descs, count, out_i32, out_f64,
+                       out_blk);
 }
 
 // ---------------------------------------------------------------------------

@@ -19,7 +19,10 @@ __global__ __launch_bounds__(1024) void k_select_sort(const MatDesc *__restrict_
     const MatDesc &d = descs[blockIdx.x];
     const double *__restrict__ lam = d.lam;
     const int32_t n = d.n, k = d.k, n_tau = d.n_tau;
-    const double tol = d.tol, u_gram = d.u_gram;
+    const double tol = d.tol;
+    // the split-bf16 tiles run only when the scan found two dense rows or more; otherwise
+    // the whole Gram came from the FP32 sparse pass and its roundoff is FP32's
+    const double u_gram = (d.dwg > 0 && gmem(d.dense)[1] < 0) ? fmin(d.u_gram, 0x1p-24) : d.u_gram;
     int32_t *__restrict__ perm = d.perm;
     double *__restrict__ sigma = d.sigma;
     int32_t *__restrict__ scal = d.scal;

@@ -22,7 +22,9 @@ void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 
 // occupancy / validation / structural rank / stable transpose (k_occupancy.hip)
 void launch_batch_prep(const MatDesc *descs, int count, hipStream_t s);
-void launch_batch_collect(const MatDesc *descs, int count, int32_t *out_i32, double *out_f64, hipStream_t s);
+// out_blk (or NULL): the per-block lonely and single-entry counts of every matrix (MatDesc::blk_off)
+void launch_batch_collect(const MatDesc *descs, int count, int32_t *out_i32, double *out_f64, int32_t *out_blk,
+                          hipStream_t s);
 void launch_occupancy(const MatDesc *descs, const int32_t *wp_chunks, int64_t n_chunk_blocks,
                       const int32_t *wp_rows, int64_t n_row_blocks, int count, int32_t maxM, int32_t maxD,
                       hipStream_t s);

@@ -52,6 +52,8 @@ struct ranky_ctx {
     ranky_status aresult = RANKY_OK;
     ranky_info ainfo = {};
     std::string aerr;
+    // per-block lonely and single-entry counts of the last call (ranky_info points here)
+    std::vector<int32_t> blk_host;
 };
 
 namespace {
@@ -80,6 +82,22 @@ ranky_status fail(ranky_status st, const char *fmt, ...) {
 
 constexpr int kWorkspaceAlign = 256;   // workspace base; every carved buffer keeps it
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Kernel attributes (dynamic LDS limits) are set once per device for the whole process,
+// under a lock: contexts created on several threads (serving slots) never set them while
+// another thread launches.
+std::mutex g_attr_mu;
+std::vector<int> g_attr_devices;
+
+hipError_t kernel_attributes(int device, size_t lds_limit) {
+    std::lock_guard<std::mutex> lk(g_attr_mu);
+    if (std::find(g_attr_devices.begin(), g_attr_devices.end(), device) != g_attr_devices.end()) return hipSuccess;
+    hipError_t e = occupancy_set_attributes(kMaxM);
+    if (e == hipSuccess) e = gram_set_attributes(lds_limit);
+    if (e == hipSuccess) e = select_set_attributes();
+    if (e == hipSuccess) g_attr_devices.push_back(device);
+    return e;
+}
 
 // ---------------------------------------------------------------------------
 // per-matrix workspace plan
@@ -247,15 +265,17 @@ MatDesc carve(const Plan &p, char *base, Refine *rf) {
 enum Phase { kPhChunks, kPhRows, kPhGram, kPhGramRed, kPhJinit, kPhJcheck, kPhJdiag, kPhGather, kPhBack, kPhBack2, kPhBack4, kPhCount };
 
 struct Header {
-    size_t o_desc = 0, o_wp = 0, o_rwp = 0, o_rtab = 0, o_col_i = 0, o_col_f = 0, o_js = 0, total = 0;
+    size_t o_desc = 0, o_wp = 0, o_rwp = 0, o_rtab = 0, o_col_i = 0, o_col_f = 0, o_col_b = 0, o_js = 0, total = 0;
     int32_t count = 0, slots = 0, nb_max = 0;
+    int64_t sum_d = 0;   // blocks over all matrices (the per-block counts read back at the end)
 };
 
-Header make_header(int32_t count, int32_t slots, int32_t nb_max) {
+Header make_header(int32_t count, int32_t slots, int32_t nb_max, int64_t sum_d = 0) {
     Header h;
     h.count = count;
     h.slots = slots;
     h.nb_max = nb_max;
+    h.sum_d = sum_d;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -268,6 +288,7 @@ Header make_header(int32_t count, int32_t slots, int32_t nb_max) {
     h.o_rtab = take(round_args_bytes() * (size_t)nb_max * slots);
     h.o_col_i = take(sizeof(int32_t) * kColI * slots);
     h.o_col_f = take(sizeof(double) * 2 * slots);
+    h.o_col_b = take(sizeof(int32_t) * 2 * (size_t)(sum_d > 0 ? sum_d : 1));
     // the sweep state the device writes to host memory (3 per matrix, then the epoch); the
     // device copy of this range holds the epoch counter
     h.o_js = take(sizeof(int32_t) * (3 * (size_t)slots + 1));
@@ -282,11 +303,15 @@ int32_t default_blocks(int64_t N) {
     return (int32_t)d;
 }
 
-ranky_opts resolved(const ranky_opts *in) {
+// refining: the call runs the Rayleigh-Ritz step for a single matrix (ranky_svd and its
+// relatives, serving); refine = -1 (automatic) resolves to 1 there for a non-FP64 Gram and
+// k <= kMaxRefineK, and to 0 everywhere else (ranky_batch).
+ranky_opts resolved(const ranky_opts *in, bool refining, int32_t k = 1) {
     ranky_opts o;
     ranky_default_opts(&o);
     if (in) o = *in;
     if (o.max_sweeps <= 0) o.max_sweeps = kDefaultSweeps;
+    if (o.refine < 0) o.refine = refining && o.gram_prec != RANKY_PREC_FP64 && k <= kMaxRefineK ? 1 : 0;
     return o;
 }
 
@@ -308,7 +333,7 @@ ranky_status check_opts(const ranky_opts &o) {
     if (o.gram_prec != RANKY_PREC_FP64 && o.gram_prec != RANKY_PREC_FP32 && o.gram_prec != RANKY_PREC_BF16X3)
         return fail(RANKY_E_INVALID, "gram_prec=%d", o.gram_prec);
     if (o.v_dtype != RANKY_F32 && o.v_dtype != RANKY_F64) return fail(RANKY_E_INVALID, "v_dtype=%d", o.v_dtype);
-    if (o.refine < 0 || o.refine > 1) return fail(RANKY_E_INVALID, "refine=%d (0 or 1)", o.refine);
+    if (o.refine < 0 || o.refine > 1) return fail(RANKY_E_INVALID, "refine=%d (0, 1, or -1 = automatic)", o.refine);
     return RANKY_OK;
 }
 
@@ -324,7 +349,12 @@ struct Job {
 
 ranky_status ensure_pinned(ranky_ctx *ctx, size_t bytes) {
     if (ctx->pinned_bytes >= bytes) return RANKY_OK;
-    if (ctx->pinned) hipHostFree(ctx->pinned);
+    // a call that failed part-way may have left kernels writing sweep state into the old
+    // buffer: let them finish before it is freed
+    if (ctx->pinned) {
+        hipDeviceSynchronize();
+        hipHostFree(ctx->pinned);
+    }
     ctx->pinned = nullptr;
     ctx->pinned_dev = nullptr;
     ctx->pinned_bytes = 0;
@@ -382,19 +412,28 @@ struct Engine {
         std::memcpy(stage() + h.o_desc, d.data(), sizeof(MatDesc) * count);
         return upload(h.o_desc, sizeof(MatDesc) * count);
     }
-    // compact per-matrix scalars (blocking)
-    ranky_status collect(std::vector<int32_t> &iv, std::vector<double> &fv) {
+    // compact per-matrix scalars (blocking); with blk != NULL also every matrix's per-block
+    // lonely and single-entry counts (the header must have room for them: sum_d)
+    ranky_status collect(std::vector<int32_t> &iv, std::vector<double> &fv, std::vector<int32_t> *blk = nullptr) {
         int32_t *ci = reinterpret_cast<int32_t *>(hdr + h.o_col_i);
         double *cf = reinterpret_cast<double *>(hdr + h.o_col_f);
-        launch_batch_collect(ddesc(), count, ci, cf, s);
+        int32_t *cb = blk && h.sum_d > 0 ? reinterpret_cast<int32_t *>(hdr + h.o_col_b) : nullptr;
+        launch_batch_collect(ddesc(), count, ci, cf, cb, s);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(stage() + h.o_col_i, ci, sizeof(int32_t) * kColI * count, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(stage() + h.o_col_f, cf, sizeof(double) * 2 * count, hipMemcpyDeviceToHost, s));
+        if (cb)
+            HIP_TRY(hipMemcpyAsync(stage() + h.o_col_b, cb, sizeof(int32_t) * 2 * (size_t)h.sum_d,
+                                   hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         const int32_t *pi = reinterpret_cast<const int32_t *>(stage() + h.o_col_i);
         const double *pf = reinterpret_cast<const double *>(stage() + h.o_col_f);
         iv.assign(pi, pi + kColI * count);
         fv.assign(pf, pf + 2 * count);
+        if (cb) {
+            const int32_t *pb = reinterpret_cast<const int32_t *>(stage() + h.o_col_b);
+            blk->assign(pb, pb + 2 * h.sum_d);
+        }
         return RANKY_OK;
     }
 
@@ -663,13 +702,15 @@ size_t path_bytes(const std::vector<Job> &jobs, const ranky_opts &o) {
     const int count = (int)jobs.size();
     const bool refine = count == 1 && wants_refine(o, jobs[0].k);
     int32_t maxM = 1;
+    int64_t sum_d = 0;
     size_t total = 0;
     for (const Job &j : jobs) {
         total += make_plan(j.M, j.N, j.A.nnz, j.k, j.D, true, refine, j.bstart, count == 1, o.v_dtype == RANKY_F32)
                      .total;
         maxM = std::max(maxM, j.M);
+        sum_d += j.D;
     }
-    return total + make_header(count, count, jacobi_npad(maxM) / kJacobiBlock).total;
+    return total + make_header(count, count, jacobi_npad(maxM) / kJacobiBlock, sum_d).total;
 }
 
 // The whole path for a batch (Rayleigh-Ritz refinement only for a batch of one).
@@ -678,13 +719,17 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
     const int count = (int)jobs.size();
     const bool refine = count == 1 && wants_refine(o, jobs[0].k);
     std::vector<Plan> plans(count);
+    std::vector<int32_t> blk_off(count);
     int32_t maxM = 1;
+    int64_t sum_d = 0;
     for (int i = 0; i < count; ++i) {
         plans[i] = make_plan(jobs[i].M, jobs[i].N, jobs[i].A.nnz, jobs[i].k, jobs[i].D, true, refine, jobs[i].bstart,
                              count == 1, o.v_dtype == RANKY_F32);
         maxM = std::max(maxM, jobs[i].M);
+        blk_off[i] = (int32_t)sum_d;
+        sum_d += jobs[i].D;
     }
-    const Header h = make_header(count, count, jacobi_npad(maxM) / kJacobiBlock);
+    const Header h = make_header(count, count, jacobi_npad(maxM) / kJacobiBlock, sum_d);
     size_t need = h.total;
     std::vector<size_t> base(count);
     for (int i = 0; i < count; ++i) {
@@ -705,6 +750,7 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
         const Job &j = jobs[i];
         MatDesc &x = e.d[i];
         x = carve(plans[i], ws + base[i], i == 0 ? &rf : nullptr);
+        x.blk_off = blk_off[i];
         if (j.bstart)
             HIP_TRY(hipMemcpyAsync(const_cast<int64_t *>(x.bstart), j.bstart, sizeof(int64_t) * ((size_t)j.D + 1),
                                    hipMemcpyHostToDevice, s));
@@ -722,9 +768,12 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
             x.bp_per_cu = tc->second.bp_per_cu;
             x.jsched = tc->second.jsched;
         }
-        // unit roundoff of the Gram entries: FP64, FP32, or the bf16x3 products (2^-16)
+        // unit roundoff of the Gram entries as they are computed: FP64, FP32, or the bf16x3
+        // products (2^-16) when the split-bf16 tiles run (a single matrix; the selection
+        // falls back to 2^-24 when the scan found fewer than two dense rows, since then no tile
+        // runs and the whole Gram is the FP32 sparse pass)
         x.u_gram = o.gram_prec == RANKY_PREC_FP64 ? std::ldexp(1.0, -53)
-                   : o.gram_prec == RANKY_PREC_FP32 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -16);
+                   : (o.gram_prec == RANKY_PREC_BF16X3 && x.dwg > 0) ? std::ldexp(1.0, -16) : std::ldexp(1.0, -24);
         // an FP32 Gram is accurate to about 6e-8: Jacobi stops at 1e-8 (the FP64 step of the
         // Rayleigh-Ritz refinement, or the mixed-precision bar, covers the rest)
         x.jtol = (o.gram_prec == RANKY_PREC_FP64) ? 0.0 : kJacobiTolFp32Gram;
@@ -792,6 +841,7 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
         y.n_tau = x.n;
         y.k = k;
         y.u_gram = std::ldexp(1.0, -53);
+        y.dwg = 0;      // no split-bf16 tiles in H: its threshold keeps the FP64 roundoff
         y.jtol = 0.0;   // H is exact to FP64 rounding: the full-accuracy stopping test
         y.U = j.U;
         eh.maxn = k;
@@ -817,7 +867,7 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
     }
     HIP_TRY(hipGetLastError());
     if (timing) hipEventRecord(ctx->ev[7], s);
-    st = e.collect(iv, fv);
+    st = e.collect(iv, fv, &ctx->blk_host);
     if (st) return st;
     ranky_status overall = RANKY_OK;
     for (int i = 0; i < count; ++i) {
@@ -831,10 +881,15 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
             in.rank = iv[kColI * i + 2];
             in.n_nonempty = e.d[i].n;
             in.empty_rows = jobs[i].M - e.d[i].n;
-            in.sweeps = e.sweeps[i] + refine_sweeps;
+            in.sweeps = e.sweeps[i];
+            in.rr_sweeps = refine_sweeps;
             in.n_blocks = jobs[i].D;
             in.lonely_max = iv[kColI * i + 5];
             in.lonely_blocks = iv[kColI * i + 6];
+            if (e.status[i] == RANKY_OK) {
+                in.lonely_per_block = ctx->blk_host.data() + 2 * (size_t)blk_off[i];
+                in.single_per_block = in.lonely_per_block + jobs[i].D;
+            }
             in.tau = fv[2 * i];
             in.sigma_max = fv[2 * i + 1];
             if (timing) {
@@ -906,9 +961,8 @@ ranky_status step_device(StepCtx &sc) {
     if (lds > 160 * 1024) lds = 160 * 1024;
     sc.c.lds_limit = lds > 4096 ? lds - 4096 : lds;
     sc.c.cu_count = prop.multiProcessorCount;
-    HIP_TRY(occupancy_set_attributes(kMaxM));
-    HIP_TRY(gram_set_attributes(sc.c.lds_limit));
-    HIP_TRY(select_set_attributes());
+    sc.c.device = dev;
+    HIP_TRY(kernel_attributes(dev, sc.c.lds_limit));
     return RANKY_OK;
 }
 
@@ -956,7 +1010,7 @@ ranky_status ranky_default_opts(ranky_opts *o) {
     std::memset(o, 0, sizeof(*o));
     o->n_blocks = 0;
     o->gram_prec = RANKY_PREC_FP64;
-    o->refine = 0;
+    o->refine = -1;
     o->max_sweeps = kDefaultSweeps;
     o->validate = 1;
     o->v_dtype = RANKY_F64;
@@ -985,9 +1039,7 @@ ranky_status ranky_ctx_create(int device, ranky_ctx **out) {
             return fail(RANKY_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
         }
     }
-    hipError_t e = occupancy_set_attributes(kMaxM);
-    if (e == hipSuccess) e = gram_set_attributes(c->lds_limit);
-    if (e == hipSuccess) e = select_set_attributes();
+    const hipError_t e = kernel_attributes(device, c->lds_limit);
     if (e != hipSuccess) {
         ranky_ctx_destroy(c);
         return fail(RANKY_E_DEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(e));
@@ -1009,7 +1061,7 @@ ranky_status ranky_ctx_destroy(ranky_ctx *ctx) {
 
 size_t ranky_workspace_bytes(int32_t M, int64_t N, int64_t nnz, int32_t k, const ranky_opts *opts) {
     if (M < 1 || N < 1 || k < 1 || k > M || M > kMaxM || nnz < 0) return 0;
-    const ranky_opts o = resolved(opts);
+    const ranky_opts o = resolved(opts, true, k);
     if (o.block_start && o.n_blocks < 1) return 0;
     const int32_t D = o.n_blocks == 0 ? default_blocks(N) : o.n_blocks;
     if (D < 1 || D > N) return 0;
@@ -1037,7 +1089,7 @@ ranky_status ranky_svd(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N,
     if (!ctx) return finish(fail(RANKY_E_INVALID, "ctx is NULL"));
     if (!(tol >= 0.0)) return finish(fail(RANKY_E_INVALID, "tol must be >= 0"));
     if (!sigma || !U || !V) return finish(fail(RANKY_E_INVALID, "NULL output"));
-    const ranky_opts o = resolved(opts);
+    const ranky_opts o = resolved(opts, true, k);
     ranky_status st = check_opts(o);
     if (st) return finish(st);
     Job j;
@@ -1046,7 +1098,7 @@ ranky_status ranky_svd(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N,
     if (o.refine && k > kMaxRefineK) return finish(fail(RANKY_E_INVALID, "refine needs k <= %d", kMaxRefineK));
     if (hipSetDevice(ctx->device) != hipSuccess) return finish(fail(RANKY_E_DEVICE, "hipSetDevice"));
     return finish(run_path(ctx, {j}, tol, o, workspace, ws_bytes, inf, reinterpret_cast<hipStream_t>(stream),
-                           o.reserved == 1));
+                           o.graph == 1));
 }
 
 ranky_status ranky_svd_async(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N, int32_t k, double tol,
@@ -1056,7 +1108,7 @@ ranky_status ranky_svd_async(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int6
     // the host-checkable errors of ranky_svd, at once
     if (!(tol >= 0.0)) return fail(RANKY_E_INVALID, "tol must be >= 0");
     if (!sigma || !U || !V) return fail(RANKY_E_INVALID, "NULL output");
-    const ranky_opts o = resolved(opts);
+    const ranky_opts o = resolved(opts, true, k);
     ranky_status st = check_opts(o);
     if (st) return st;
     Job j;
@@ -1098,7 +1150,7 @@ ranky_status ranky_query(ranky_ctx *ctx, uint64_t ticket, ranky_info *info) {
 ranky_status ranky_tune_set(ranky_ctx *ctx, int32_t M, int64_t N, int64_t nnz, int32_t k, ranky_dtype dtype,
                             const ranky_opts *opts, int32_t bp_per_cu, int32_t jacobi_schedule) {
     if (!ctx) return fail(RANKY_E_INVALID, "ctx is NULL");
-    const ranky_opts o = resolved(opts);
+    const ranky_opts o = resolved(opts, true, k);
     const ranky_status st = check_opts(o);
     if (st) return st;
     if (bp_per_cu < 1 || bp_per_cu > 1024) return fail(RANKY_E_INVALID, "bp_per_cu=%d", bp_per_cu);
@@ -1115,7 +1167,7 @@ ranky_status ranky_autotune(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64
                             ranky_tune_report *report, ranky_stream_t stream) {
     if (!ctx) return fail(RANKY_E_INVALID, "ctx is NULL");
     if (!sigma || !U || !V) return fail(RANKY_E_INVALID, "NULL output");
-    ranky_opts o = resolved(opts);
+    ranky_opts o = resolved(opts, true, k);
     ranky_status st = check_opts(o);
     if (st) return st;
     Job j;
@@ -1124,7 +1176,7 @@ ranky_status ranky_autotune(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64
     if (o.refine && k > kMaxRefineK) return fail(RANKY_E_INVALID, "refine needs k <= %d", kMaxRefineK);
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(RANKY_E_DEVICE, "hipSetDevice");
     o.timing = 1;      // phase times from HIP events
-    o.reserved = 0;    // direct launches while timing
+    o.graph = 0;       // direct launches while timing
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const TuneKey key{M, N, j.A.nnz, k, j.A.dtype, o.v_dtype, o.gram_prec};
     const int32_t bp_cands[4] = {8, 16, 32, 64};
@@ -1194,8 +1246,8 @@ ranky_status ranky_autotune(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64
 
 size_t ranky_batch_workspace_bytes(int32_t count, const ranky_batch_item *items, const ranky_opts *opts) {
     if (count < 1 || !items) return 0;
-    ranky_opts o = resolved(opts);
-    o.refine = 0;
+    ranky_opts o = resolved(opts, false);
+    if (o.refine != 0) return 0;
     if (o.block_start) return 0;
     std::vector<Job> jobs(count);
     for (int i = 0; i < count; ++i) {
@@ -1219,7 +1271,7 @@ ranky_status ranky_batch(ranky_ctx *ctx, int32_t count, const ranky_batch_item *
     if (!ctx) return fail(RANKY_E_INVALID, "ctx is NULL");
     if (count < 1 || !items) return fail(RANKY_E_INVALID, "empty batch");
     if (!(tol >= 0.0)) return fail(RANKY_E_INVALID, "tol must be >= 0");
-    const ranky_opts o = resolved(opts);
+    const ranky_opts o = resolved(opts, false);
     ranky_status st = check_opts(o);
     if (st) return st;
     if (o.refine) return fail(RANKY_E_INVALID, "ranky_batch runs without refinement (use ranky_svd per matrix)");
@@ -1233,7 +1285,7 @@ ranky_status ranky_batch(ranky_ctx *ctx, int32_t count, const ranky_batch_item *
     }
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(RANKY_E_DEVICE, "hipSetDevice");
     return run_path(ctx, jobs, tol, o, workspace, ws_bytes, infos, reinterpret_cast<hipStream_t>(stream),
-                    o.reserved == 1);
+                    o.graph == 1);
 }
 
 // ---------------------------------------------------------------------------

@@ -35,19 +35,19 @@ class Csc(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
-                ("n_blocks", "gram_prec", "refine", "max_sweeps", "validate", "v_dtype", "timing", "reserved")] + \
+                ("n_blocks", "gram_prec", "refine", "max_sweeps", "validate", "v_dtype", "timing", "graph")] + \
                [("block_start", ctypes.c_void_p)]
 
 
 class BatchItem(ctypes.Structure):
     _fields_ = [("A", Csc), ("N", ctypes.c_int64), ("M", ctypes.c_int32), ("k", ctypes.c_int32),
-                ("n_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32), ("sigma", ctypes.c_void_p),
+                ("n_blocks", ctypes.c_int32), ("pad", ctypes.c_int32), ("sigma", ctypes.c_void_p),
                 ("U", ctypes.c_void_p), ("V", ctypes.c_void_p)]
 
 
 class ServeCfg(ctypes.Structure):
     _fields_ = [("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
-                ("max_queue", ctypes.c_int32), ("device", ctypes.c_int), ("reserved", ctypes.c_int32),
+                ("max_queue", ctypes.c_int32), ("device", ctypes.c_int), ("pad", ctypes.c_int32),
                 ("opts", Opts)]
 
 
@@ -71,11 +71,19 @@ class Info(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
                 ("status", "rank", "n_nonempty", "empty_rows", "sweeps", "n_blocks", "lonely_max", "lonely_blocks")]
     _fields_ += [("tau", ctypes.c_double), ("sigma_max", ctypes.c_double), ("ms", ctypes.c_float * 8),
-                 ("round_ms", ctypes.c_float), ("round_launches", ctypes.c_int32)]
+                 ("round_ms", ctypes.c_float), ("round_launches", ctypes.c_int32), ("rr_sweeps", ctypes.c_int32),
+                 ("lonely_per_block", ctypes.POINTER(ctypes.c_int32)),
+                 ("single_per_block", ctypes.POINTER(ctypes.c_int32))]
 
     def as_dict(self):
-        d = {n: getattr(self, n) for n, _ in self._fields_ if n != "ms"}
+        """Copies every field; the per-block counts (library memory) become lists."""
+        d = {n: getattr(self, n) for n, _ in self._fields_
+             if n not in ("ms", "lonely_per_block", "single_per_block")}
         d["ms"] = list(self.ms)
+        D = self.n_blocks
+        for n in ("lonely_per_block", "single_per_block"):
+            p = getattr(self, n)
+            d[n] = [p[b] for b in range(D)] if p and D > 0 else None
         return d
 
 
@@ -223,17 +231,19 @@ def context(device: int = 0) -> Context:
 
 def make_opts(n_blocks=0, gram_prec="fp64", refine=None, max_sweeps=0, validate=True, v_dtype=torch.float64,
               timing=False, graph=False, block_start=None) -> Opts:
-    """block_start: optional D + 1 column boundaries (host; kept alive by the Opts)."""
+    """block_start: optional D + 1 column boundaries (host; kept alive by the Opts).
+    refine=None keeps the library's automatic choice (-1)."""
     o = Opts()
     _check(lib().ranky_default_opts(ctypes.byref(o)))
     o.n_blocks = n_blocks
     o.gram_prec = PREC[gram_prec]
-    o.refine = (0 if gram_prec == "fp64" else 1) if refine is None else int(refine)
+    if refine is not None:
+        o.refine = int(refine)
     o.max_sweeps = max_sweeps
     o.validate = int(validate)
     o.v_dtype = F64 if v_dtype == torch.float64 else F32
     o.timing = int(timing)
-    o.reserved = int(graph)
+    o.graph = int(graph)
     if block_start is not None:
         import numpy as np
 

@@ -45,6 +45,7 @@ def test_default_opts_and_version(L):
     o = ranky.Opts()
     assert L.ranky_default_opts(ctypes.byref(o)) == 0
     assert (o.gram_prec, o.validate, o.v_dtype, o.max_sweeps) == (0, 1, 1, 40)
+    assert o.refine == -1 and o.graph == 0    # refinement chosen per call; no graph replay by default
     assert b"gfx950" in L.ranky_version()
 
 
@@ -90,3 +91,39 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(ranky, "_lib", None)
     with pytest.raises(ranky.RankyError):
         ranky.lib()
+
+
+def test_struct_layouts_match_the_binding(tmp_path):
+    """Every field offset and struct size of the C header, as gcc lays them out, equals the
+    ctypes binding's (a drift would pass garbage across the boundary)."""
+    import shutil
+    import subprocess
+
+    from paper_2009_09767_amd import ranky
+
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    structs = {"ranky_csc": ranky.Csc, "ranky_opts": ranky.Opts, "ranky_info": ranky.Info,
+               "ranky_batch_item": ranky.BatchItem, "ranky_serve_cfg": ranky.ServeCfg,
+               "ranky_request": ranky.Request, "ranky_serve_summary": ranky.ServeStats,
+               "ranky_tune_report": ranky.TuneReport}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ranky.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = str(tmp_path / "layout")
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", exe], check=True)
+    out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            a, b, c = line.split()
+            got[(a, b)] = int(c)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

@@ -135,3 +135,32 @@ def test_bf16x3_refined_against_fp64_oracle(R, orc):
     ref = orc.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=k, method="whole_qr")
     got = R.svd(R.to_device(A), k, 0.0, n_blocks=8, gram_prec="bf16x3", refine=1, v_dtype=torch.float32)
     check(A, got, ref, 1e-6)
+
+
+def test_bf16x3_with_the_c_default_refine(R, orc):
+    """gram_prec BF16X3 with every other option at the C default (refine = -1, automatic): the
+    call refines (one FP64 Rayleigh-Ritz step), so rank and sigma match the FP64 oracle."""
+    import torch
+
+    A = gen.powerlaw_small()
+    k = A.meta["k"]
+    got = R.svd(R.to_device(A), k, 0.0, gram_prec="bf16x3", v_dtype=torch.float32)   # refine left to the library
+    assert got.info["rr_sweeps"] > 0
+    ref = orc.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=k, method="whole")
+    assert got.info["rank"] == ref.rank
+    assert H.rel_sigma_err(got.sigma.cpu().numpy(), ref.sigma, ref.rank) <= 1e-10
+
+
+def test_bf16x3_unrefined_without_dense_rows_uses_the_fp32_threshold(R, orc):
+    """Unrefined BF16X3 on a matrix with no row dense enough for the split-bf16 tiles: the whole
+    Gram is the FP32 sparse pass, so tau must be sqrt(M' 2^-24) sigma_1 (not 2^-16) and the rank
+    equals the oracle's with that roundoff."""
+    import torch
+
+    A = gen.powerlaw_small(seed=901, M=192, N=1 << 13, k=192)
+    assert np.bincount(A.rowidx, minlength=A.M).max() < 4096     # below the dense-row threshold
+    got = R.svd(R.to_device(A), A.M, 0.0, gram_prec="bf16x3", refine=0, v_dtype=torch.float32)
+    ref = orc.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=A.M, method="gram", u_gram=2.0 ** -24)
+    n = got.info["n_nonempty"]
+    assert got.info["tau"] <= np.sqrt(n * 2.0 ** -24) * got.info["sigma_max"] * (1 + 1e-12)
+    assert got.info["rank"] == ref.rank == A.M

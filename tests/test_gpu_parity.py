@@ -76,6 +76,28 @@ def test_occupancy_bit_exact(R, orc, name):
     assert np.array_equal(single.cpu().numpy(), ref.single)
 
 
+@pytest.mark.parametrize("name", ["small_deficient", "powerlaw_small", "batch_mixed_half_rows_zero", "ragged_127_f32"])
+def test_info_per_block_counts(R, orc, name):
+    """ranky_info.lonely_per_block / single_per_block of a whole-path call (ranky_svd and a batch)
+    equal the oracle's Alg. 1 scan block by block."""
+    A = CASES[name]()
+    D = A.meta.get("D", 8)
+    ref = orc.occupancy(A.M, A.N, A.colptr, A.rowidx, D)
+    dA = R.to_device(A)
+    got = R.svd(dA, min(A.meta.get("k", A.M), A.M), 0.0, n_blocks=D)
+    assert got.info["n_blocks"] == D
+    assert got.info["lonely_per_block"] == ref.lonely.tolist()
+    assert got.info["single_per_block"] == ref.single.tolist()
+    assert got.info["lonely_max"] == int(ref.lonely.max())
+    assert got.info["lonely_blocks"] == int(np.count_nonzero(ref.lonely))
+    other = gen.small_deficient()
+    outs = R.batch([R.to_device(other), dA], [other.M, A.M], 0.0, n_blocks=[8, D])
+    ref_o = orc.occupancy(other.M, other.N, other.colptr, other.rowidx, 8)
+    assert outs[0].info["lonely_per_block"] == ref_o.lonely.tolist()
+    assert outs[1].info["lonely_per_block"] == ref.lonely.tolist()
+    assert outs[1].info["single_per_block"] == ref.single.tolist()
+
+
 @pytest.mark.parametrize("name", ["small_deficient", "powerlaw_small", "batch_mixed_full_rank", "batch_mixed_half_rows_zero", "ragged_65"])
 def test_gram_fp64(R, orc, name):
     A = CASES[name]()
