@@ -61,9 +61,10 @@ def _load():
     lib.ro_backproject.argtypes = [i32, i64, vp, vp, vp, ctypes.c_int, i32, vp, vp, i32, vp]
     lib.ro_svd.argtypes = [i32, i32, i64, i64, vp, vp, vp, ctypes.c_int, i32, i32, dbl, dbl, i32,
                            vp, vp, vp, vp, vp, vp]
+    lib.ro_checker.argtypes = [i32, i64, i64, vp, vp, vp, ctypes.c_int, i32, i32, ctypes.c_uint64, vp, vp, vp, vp, vp]
     for name in ("ro_check_csc", "ro_block_bounds", "ro_occupancy", "ro_gram", "ro_bf16_split", "ro_gram_bf16x3",
                  "ro_hestenes",
-                 "ro_qr_r", "ro_eig_jacobi", "ro_backproject", "ro_svd"):
+                 "ro_qr_r", "ro_eig_jacobi", "ro_backproject", "ro_svd", "ro_checker"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -221,3 +222,23 @@ def svd(M, N, colptr, rowidx, values, k, tol=0.0, method="whole", D=1, u_gram=U_
     if st:
         raise OracleError(st, f"svd[{method}]")
     return SVD(sigma, U, V, int(rank[0]), float(tau[0]), int(sw[0]))
+
+
+CHECKERS = {"random": 0, "neighbor": 1, "neighbor_random": 2}
+
+
+def checker(M, N, colptr, rowidx, values, D, kind, seed):
+    """Alg. 2-4 on a copy of A: (colptr', rowidx', values' FP64, inserted) of A' (CSC)."""
+    colptr, rowidx, values, dt = _csc_arrays(colptr, rowidx, values)
+    cap = len(rowidx) + 2 * D * M
+    cp = np.zeros(N + 1, dtype=np.int32)
+    ri = np.zeros(max(cap, 1), dtype=np.int32)
+    va = np.zeros(max(cap, 1), dtype=np.float64)
+    nz = np.zeros(1, dtype=np.int64)
+    ins = np.zeros(1, dtype=np.int64)
+    st = _load().ro_checker(M, N, len(rowidx), _ptr(colptr), _ptr(rowidx), _ptr(values), dt, D, CHECKERS[kind],
+                            int(seed), _ptr(cp), _ptr(ri), _ptr(va), _ptr(nz), _ptr(ins))
+    if st:
+        raise OracleError(st, "checker")
+    n = int(nz[0])
+    return cp, ri[:n].copy(), va[:n].copy(), int(ins[0])

@@ -733,3 +733,168 @@ int ro_svd(int32_t method, int32_t M, int64_t N, int64_t nnz, const int32_t *col
     free(empty);
     return st;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Alg. 2-4: the paper's checkers (lonely-node repair), on a copy of A        */
+/* ------------------------------------------------------------------------- */
+
+/* SplitMix64 (Steele, Lea, Flood, "Fast splittable pseudorandom number generators", OOPSLA
+ * 2014) used as a counter-based generator: output i of the stream with seed s is the
+ * generator's mixing function applied to s + (i + 1) * 0x9E3779B97F4A7C15. */
+static uint64_t splitmix64_at(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+#define RO_CHECK_RANDOM 0
+#define RO_CHECK_NEIGHBOR 1
+#define RO_CHECK_NEIGHBOR_RANDOM 2
+
+static int cmp_i64(const void *a, const void *b) {
+    const int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* For every block b and every row m with no entry of A inside block b (Alg. 1), the checker
+ * chosen by `kind` sets one entry of value 1 in row m inside block b of the copy A':
+ *   RandomChecker (Alg. 2): column start[b] + (r0 mod width_b);
+ *   NeighborChecker (Alg. 3): the neighbours of m are the rows that share a column with m outside
+ *     block b; the candidate columns are the columns of block b holding an entry of a neighbour;
+ *     the chosen one is the (r1 mod count)-th candidate in ascending column order (no candidate:
+ *     the RandomChecker column);
+ *   NeighborRandomChecker (Alg. 4): both entries (one if they coincide);
+ * with r0 = output 2 (b M + m) and r1 = output 2 (b M + m) + 1 of the counter-based generator
+ * above for `seed`.  Every decision reads the unmodified A (the repairs do not feed each other).
+ * Output A' (CSC, FP64 values; rows strictly increasing in every column): colptr_out [N + 1],
+ * rowidx_out and vals_out with room for nnz + 2 D M entries; *nnz_out; *inserted = entries added. */
+int ro_checker(int32_t M, int64_t N, int64_t nnz, const int32_t *colptr, const int32_t *rowidx, const void *vals,
+               int dtype, int32_t D, int32_t kind, uint64_t seed, int32_t *colptr_out, int32_t *rowidx_out,
+               double *vals_out, int64_t *nnz_out, int64_t *inserted) {
+    if (kind < RO_CHECK_RANDOM || kind > RO_CHECK_NEIGHBOR_RANDOM) return RO_E_INVALID;
+    int st = ro_check_csc(M, N, nnz, colptr, rowidx, vals, dtype);
+    if (st != RO_OK) return st;
+    if (D < 1 || D > N) return RO_E_INVALID;
+    int64_t *start = (int64_t *)malloc(sizeof(int64_t) * (size_t)(D + 1));
+    int32_t *cnt = (int32_t *)malloc(sizeof(int32_t) * (size_t)D * (size_t)M);
+    int32_t *rownnz = (int32_t *)malloc(sizeof(int32_t) * (size_t)M);
+    int32_t *lon = (int32_t *)malloc(sizeof(int32_t) * (size_t)D);
+    int32_t *sgl = (int32_t *)malloc(sizeof(int32_t) * (size_t)D);
+    int64_t *rowptr = (int64_t *)calloc((size_t)M + 1, sizeof(int64_t));
+    int64_t *rcol = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nnz > 0 ? nnz : 1));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)M);
+    char *cand = (char *)malloc((size_t)M);
+    int64_t *ins = (int64_t *)malloc(sizeof(int64_t) * 2 * (size_t)D * (size_t)M);   /* col * M + row */
+    char *mark = NULL;
+    int64_t nins = 0;
+    if (!start || !cnt || !rownnz || !lon || !sgl || !rowptr || !rcol || !fill || !cand || !ins) {
+        st = RO_E_NOMEM;
+        goto done;
+    }
+    ro_block_bounds(N, D, start);
+    ro_occupancy(M, N, colptr, rowidx, D, start, cnt, rownnz, lon, sgl);
+    /* the rows of A: columns of each row in ascending order */
+    for (int64_t k = 0; k < nnz; ++k) rowptr[rowidx[k] + 1] += 1;
+    for (int32_t m = 0; m < M; ++m) rowptr[m + 1] += rowptr[m];
+    for (int32_t m = 0; m < M; ++m) fill[m] = rowptr[m];
+    for (int64_t j = 0; j < N; ++j)
+        for (int64_t k = colptr[j]; k < colptr[j + 1]; ++k) rcol[fill[rowidx[k]]++] = j;
+    int64_t wmax = 0;
+    for (int32_t b = 0; b < D; ++b)
+        if (start[b + 1] - start[b] > wmax) wmax = start[b + 1] - start[b];
+    mark = (char *)malloc((size_t)(wmax > 0 ? wmax : 1));
+    if (!mark) {
+        st = RO_E_NOMEM;
+        goto done;
+    }
+    for (int32_t b = 0; b < D; ++b) {
+        const int64_t c0 = start[b], c1 = start[b + 1], w = c1 - c0;
+        for (int32_t m = 0; m < M; ++m) {
+            if (cnt[(size_t)b * M + m] != 0) continue;   /* Alg. 1: the row has an entry in block b */
+            const uint64_t i0 = 2 * ((uint64_t)b * (uint64_t)M + (uint64_t)m);
+            const int64_t rand_col = c0 + (int64_t)(splitmix64_at(seed, i0) % (uint64_t)w);
+            int64_t neigh_col = -1;
+            if (kind != RO_CHECK_RANDOM) {
+                /* neighbours of m: rows sharing a column with m outside block b */
+                memset(cand, 0, (size_t)M);
+                for (int64_t e = rowptr[m]; e < rowptr[m + 1]; ++e) {
+                    const int64_t n1 = rcol[e];
+                    if (n1 >= c0 && n1 < c1) continue;
+                    for (int64_t k = colptr[n1]; k < colptr[n1 + 1]; ++k) cand[rowidx[k]] = 1;
+                }
+                /* candidate columns: block-b columns of the neighbours */
+                memset(mark, 0, (size_t)w);
+                int64_t count = 0;
+                for (int32_t m1 = 0; m1 < M; ++m1) {
+                    if (!cand[m1]) continue;
+                    for (int64_t e = rowptr[m1]; e < rowptr[m1 + 1]; ++e) {
+                        const int64_t n2 = rcol[e];
+                        if (n2 >= c0 && n2 < c1 && !mark[n2 - c0]) {
+                            mark[n2 - c0] = 1;
+                            count += 1;
+                        }
+                    }
+                }
+                if (count > 0) {
+                    int64_t want = (int64_t)(splitmix64_at(seed, i0 + 1) % (uint64_t)count);
+                    for (int64_t c = 0; c < w; ++c) {
+                        if (!mark[c]) continue;
+                        if (want == 0) {
+                            neigh_col = c0 + c;
+                            break;
+                        }
+                        want -= 1;
+                    }
+                }
+            }
+            if (kind == RO_CHECK_RANDOM) {
+                ins[nins++] = rand_col * M + m;
+            } else if (kind == RO_CHECK_NEIGHBOR) {
+                ins[nins++] = (neigh_col >= 0 ? neigh_col : rand_col) * M + m;
+            } else {
+                if (neigh_col >= 0) ins[nins++] = neigh_col * M + m;
+                if (neigh_col != rand_col) ins[nins++] = rand_col * M + m;
+            }
+        }
+    }
+    /* A' = A plus the inserted ones, column by column, rows ascending */
+    qsort(ins, (size_t)nins, sizeof(int64_t), cmp_i64);
+    {
+        int64_t pos = 0, q = 0;
+        colptr_out[0] = 0;
+        for (int64_t j = 0; j < N; ++j) {
+            int64_t k = colptr[j];
+            while (k < colptr[j + 1] || (q < nins && ins[q] / M == j)) {
+                const int take_ins = q < nins && ins[q] / M == j &&
+                                     (k >= colptr[j + 1] || (int64_t)(ins[q] % M) < (int64_t)rowidx[k]);
+                if (take_ins) {
+                    rowidx_out[pos] = (int32_t)(ins[q] % M);
+                    vals_out[pos] = 1.0;
+                    q += 1;
+                } else {
+                    rowidx_out[pos] = rowidx[k];
+                    vals_out[pos] = value_at(vals, dtype, k);
+                    k += 1;
+                }
+                pos += 1;
+            }
+            colptr_out[j + 1] = (int32_t)pos;
+        }
+        *nnz_out = pos;
+        *inserted = nins;
+    }
+done:
+    free(start);
+    free(cnt);
+    free(rownnz);
+    free(lon);
+    free(sgl);
+    free(rowptr);
+    free(rcol);
+    free(fill);
+    free(cand);
+    free(ins);
+    free(mark);
+    return st;
+}

@@ -41,6 +41,11 @@ MUTANTS = {
                                  "const uint32_t r = (u + 0x8000u) & 0xffff0000u;"),
     "split_product_drops_cross_term": ("G[(size_t)a * nr + b] += h1 * h2 + h1 * l2 + l1 * h2;",
                                        "G[(size_t)a * nr + b] += h1 * h2 + h1 * l2;"),
+    "checker_inserts_two": ("vals_out[pos] = 1.0;", "vals_out[pos] = 2.0;"),
+    "checker_no_fallback": ("ins[nins++] = (neigh_col >= 0 ? neigh_col : rand_col) * M + m;",
+                            "if (neigh_col >= 0) ins[nins++] = neigh_col * M + m;"),
+    "checker_neighbour_columns_of_next_block": ("if (n2 >= c0 && n2 < c1 && !mark[n2 - c0]) {",
+                                                "if (n2 >= c1 && n2 < c1 + w && !mark[n2 - c1]) {"),
     "split_product_keeps_lo_lo": ("G[(size_t)a * nr + b] += h1 * h2 + h1 * l2 + l1 * h2;",
                                   "G[(size_t)a * nr + b] += h1 * h2 + h1 * l2 + l1 * h2 + l1 * l2;"),
 }

@@ -441,3 +441,110 @@ def test_gram_bf16x3_drops_only_lo_lo(orc):
     assert np.array_equal(hi.astype(np.float64), Hi) and np.array_equal(lo.astype(np.float64), Lo)
     assert np.allclose(G, Hi @ Hi.T + Hi @ Lo.T + Lo @ Hi.T, rtol=0, atol=1e-12)
     assert np.allclose(G, X.astype(np.float64) @ X.astype(np.float64).T - Lo @ Lo.T, rtol=0, atol=1e-12)
+
+
+# --------------------------------------------------------------------------------------
+# Alg. 2-4: the checkers (lonely-node repair) on a copy of A
+# --------------------------------------------------------------------------------------
+
+def _dense(M, N, colptr, rowidx, values):
+    X = np.zeros((M, N))
+    for j in range(N):
+        for e in range(colptr[j], colptr[j + 1]):
+            X[rowidx[e], j] = values[e]
+    return X
+
+
+def _checker_cases():
+    return {
+        "small_deficient": (gen.small_deficient(), 8),
+        "random_lonely": (gen.random_sparse(24, 600, 0.01, seed=41), 6),
+        "power_law": (gen.powerlaw_small(M=48, N=2048, D=8, k=8, seed=5), 8),
+    }
+
+
+@pytest.mark.parametrize("kind", ["random", "neighbor", "neighbor_random"])
+@pytest.mark.parametrize("case", ["small_deficient", "random_lonely", "power_law"])
+def test_checker_post_conditions(orc, case, kind):
+    """After the repair no block leaves a row without an entry; A' holds every entry of A with its
+    value; every added entry is a 1 in a (block, row) that was lonely, inside that block; the number
+    of additions is the number of lonely (block, row) pairs (up to twice that for Alg. 4)."""
+    A, D = _checker_cases()[case]
+    occ = orc.occupancy(A.M, A.N, A.colptr, A.rowidx, D)
+    lonely_pairs = int(occ.lonely.sum())
+    assert lonely_pairs > 0
+    cp, ri, va, ins = orc.checker(A.M, A.N, A.colptr, A.rowidx, A.values, D, kind, seed=2009)
+    occ2 = orc.occupancy(A.M, A.N, cp, ri, D)
+    assert np.all(occ2.lonely == 0)
+    X, X2 = _dense(A.M, A.N, A.colptr, A.rowidx, A.values), _dense(A.M, A.N, cp, ri, va)
+    added = (X2 != X)
+    assert np.all(X2[X != 0] == X[X != 0])
+    assert np.all(X2[added] == 1.0) and np.all(X[added] == 0.0)
+    bounds = orc.block_bounds(A.N, D)
+    rows, cols = np.nonzero(added)
+    blk = np.searchsorted(bounds, cols, side="right") - 1
+    assert np.all(occ.cnt[blk, rows] == 0)   # the row had no entry in the block of the new one
+    assert ins == len(rows)
+    if kind == "neighbor_random":
+        assert lonely_pairs <= ins <= 2 * lonely_pairs
+    else:
+        assert ins == lonely_pairs
+    # rows stay strictly increasing inside every column of A'
+    for j in range(A.N):
+        assert np.all(np.diff(ri[cp[j]:cp[j + 1]]) > 0)
+
+
+@pytest.mark.parametrize("case", ["small_deficient", "random_lonely", "power_law"])
+def test_neighbor_checker_stays_in_the_two_hop_neighbourhood(orc, case):
+    """Alg. 3: each new entry (m, c) sits in a column c of the lonely block that holds an entry of a
+    row sharing a column with m outside that block -- or, when no such column exists, anywhere in
+    the block (the RandomChecker fallback).  Checked by brute force on the dense matrix."""
+    A, D = _checker_cases()[case]
+    X = _dense(A.M, A.N, A.colptr, A.rowidx, A.values) != 0
+    bounds = orc.block_bounds(A.N, D)
+    cp, ri, va, _ = orc.checker(A.M, A.N, A.colptr, A.rowidx, A.values, D, "neighbor", seed=77)
+    X2 = _dense(A.M, A.N, cp, ri, va) != 0
+    rows, cols = np.nonzero(X2 & ~X)
+    fallback = 0
+    for m, c in zip(rows, cols):
+        b = int(np.searchsorted(bounds, c, side="right") - 1)
+        c0, c1 = bounds[b], bounds[b + 1]
+        outside = X[m].copy()
+        outside[c0:c1] = False
+        neigh = np.nonzero(X[:, outside].any(axis=1))[0]
+        cand = np.nonzero(X[neigh][:, c0:c1].any(axis=0))[0] + c0
+        if cand.size:
+            assert c in cand
+        else:
+            fallback += 1
+            assert c0 <= c < c1
+    assert fallback < len(rows)   # the neighbourhood is used, not only the fallback
+
+
+def test_neighbor_checker_hand_worked_example(orc):
+    """3 x 4, two blocks of two columns.  Row 1 has no entry in block 0: its only column outside the
+    block is 2, shared with row 0, whose only block-0 column is 0, so the new entry is (1, 0).  Row 2
+    has no entry in block 1: its only column, 1, holds no other row, so no neighbour exists and the
+    RandomChecker fallback puts the entry in column 2 or 3.  Row 0 has entries in both blocks."""
+    X = np.array([[2.0, 0.0, 3.0, 0.0],
+                  [0.0, 0.0, 5.0, 0.0],
+                  [0.0, 7.0, 0.0, 0.0]])
+    A = gen.from_dense(X)
+    for seed in range(6):
+        cp, ri, va, ins = orc.checker(3, 4, A.colptr, A.rowidx, A.values, 2, "neighbor", seed=seed)
+        X2 = _dense(3, 4, cp, ri, va)
+        assert ins == 2
+        assert X2[1, 0] == 1.0
+        new2 = [c for c in (2, 3) if X2[2, c] == 1.0]
+        assert len(new2) == 1
+        keep = X2.copy()
+        keep[1, 0] = 0.0
+        keep[2, new2[0]] = 0.0
+        assert np.array_equal(keep, X)
+    # the fallback's choice depends on the seed (both columns occur over a few seeds)
+    seen = set()
+    for seed in range(16):
+        cp, ri, va, _ = orc.checker(3, 4, A.colptr, A.rowidx, A.values, 2, "neighbor", seed=seed)
+        X2 = _dense(3, 4, cp, ri, va)
+        seen.add(2 if X2[2, 2] == 1.0 else 3)
+    assert seen == {2, 3}
