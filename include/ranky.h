@@ -100,6 +100,15 @@ typedef struct {
     int32_t timing;     /* 1 = fill ranky_info.ms with per-phase times (adds event records) */
     int32_t graph;      /* 1 = replay the Jacobi sweep as a captured HIP graph (ranky_svd and
                            ranky_batch; needs a non-NULL stream, ignored on the NULL stream) */
+    int32_t eigensolver; /* how the k leading eigenpairs of G are found (the proxy SVD needs only
+                           those): 0 = automatic (the default), 1 = the full two-sided Jacobi,
+                           2 = Chebyshev-filtered subspace iteration whenever its block of
+                           p = k + max(k/2, 32) rounded up to 64 vectors is at most M'/2 (and 256).
+                           Automatic takes the subspace iteration for a single matrix when p is at
+                           most M'/8, the full Jacobi otherwise (always in ranky_batch).  A subspace
+                           iteration that has not converged after max_iters falls back to the full
+                           Jacobi; ranky_info.eig_iters tells which ran. */
+    int32_t max_iters;  /* cap on the subspace iterations (0 = 60) */
     const int64_t *block_start; /* host, optional: D + 1 column boundaries, block b = columns
                            [block_start[b], block_start[b+1]); block_start[0] = 0, non-decreasing,
                            block_start[D] = N, with n_blocks = D >= 1 given (E_INVALID otherwise).
@@ -126,6 +135,10 @@ typedef struct {
                               launched directly, not replayed, in timing mode) */
     int32_t round_launches; /* number of round launches inside round_ms */
     int32_t rr_sweeps;     /* Jacobi sweeps of the Rayleigh-Ritz eigensolve of H (0 without refinement) */
+    int32_t eig_iters;     /* subspace iterations of the eigensolve of G (0: the full Jacobi ran, and
+                              sweeps counts its sweeps) */
+    double eig_flops;      /* algorithmic FP64 flops of the subspace iteration's matrix products
+                              (2 x rows x columns x inner length over the unpadded sizes; 0 for the Jacobi) */
     /* Alg. 1 scan of every block, host copies of D entries each (NULL when the call failed before
      * the scan): rows with no entry inside block b (lonely rows), and rows with exactly one entry
      * (NO of Eq. 4).  The memory belongs to the library: it stays valid until the next call on the
@@ -406,6 +419,92 @@ ranky_status ranky_eigh(int32_t n, const double *G, double *lambda, double *Q, i
 ranky_status ranky_backproject(const ranky_csc *A, int32_t M, int64_t N, int32_t k, const double *U,
                                const double *sigma, const int32_t *rank, void *V, int32_t v_dtype,
                                ranky_stream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* The paper's own procedure (for comparison with the Gram-form path)         */
+/* ------------------------------------------------------------------------- */
+
+/* The checkers of Alg. 2-4, on the device, for the blocks b = columns [floor(bN/D), floor((b+1)N/D)):
+ * for every block b and row m with no entry of A inside block b (the Alg. 1 scan), one entry of
+ * value 1 is set in row m inside block b of a copy A' (A is never altered):
+ *   kind 0 RandomChecker (Alg. 2): column c0 + (r0 mod width);
+ *   kind 1 NeighborChecker (Alg. 3): the neighbours of m are the rows that share a column with m
+ *          outside block b; the candidates are the columns of block b holding an entry of a
+ *          neighbour; the chosen one is the (r1 mod count)-th candidate in ascending order, and
+ *          the RandomChecker column when there is no candidate;
+ *   kind 2 NeighborRandomChecker (Alg. 4): both entries (one when they coincide).
+ * Every decision reads the unmodified A (a repair does not feed later ones).  r0 and r1 are draws
+ * 2(bM + m) and 2(bM + m) + 1 of a counter-based SplitMix64 (Steele, Lea and Flood 2014): draw i
+ * of `seed` is the generator's mixing function applied to seed + (i + 1) * 0x9E3779B97F4A7C15.
+ *   colptr_out [N + 1], rowidx_out / values_out (FP64) with room for `capacity` >= nnz + 2 D M
+ *   entries (device); nnz_out, added (host): entries of A' and entries added.
+ * The width of a block is limited by the LDS bit set of its columns (about 1.2 M columns; E_INVALID
+ * beyond).  Blocking.  The result is a function of (A, D, kind, seed) alone. */
+size_t ranky_checker_workspace_bytes(int32_t M, int64_t N, int64_t nnz, int32_t D);
+ranky_status ranky_checker(const ranky_csc *A, int32_t M, int64_t N, int32_t D, int32_t kind, uint64_t seed,
+                           int32_t *colptr_out, int32_t *rowidx_out, double *values_out, int64_t capacity,
+                           int64_t *nnz_out, int64_t *added, void *workspace, size_t ws_bytes, ranky_stream_t stream);
+
+typedef struct {
+    int64_t added;        /* entries the checker added */
+    int64_t nnz_repaired; /* entries of A' */
+    int64_t proxy_cols;   /* columns of P: the blocks' retained triplets */
+    int32_t rank;         /* rank of P (the rank rule of ranky_svd on P P^T) */
+    int32_t n_nonempty;   /* non-empty rows of A' */
+    double tau;           /* threshold on the singular values of P */
+    float ms[4];          /* [0] checker, [1] scan and block factors, [2] proxy and P P^T, [3] its eigensolve */
+} ranky_paper_info;
+
+/* The paper's route (Alg. 1 with Eq. 1-3), all on the device: the optional checker (checker = -1:
+ * none, A must then be FP64; 0, 1, 2: the kinds of ranky_checker), the reduced factors U^i S^i of
+ * every block (its Gram and a full Jacobi eigensolve; triplets above the block's rank threshold are
+ * kept), the proxy P = [U^1 S^1 | ... | U^D S^D] (Eq. 1), P P^T on the FP64 matrix cores (Eq. 3), and
+ * its eigenpairs as the SVD of P: sigma [k] (descending, exactly 0 past the rank) and U [M x k]
+ * (row-major, the sign and empty-row rules of ranky_svd).  No V (the paper computes none).
+ * Blocking.  pinfo (host) may be NULL. */
+size_t ranky_paper_workspace_bytes(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, int32_t checker);
+ranky_status ranky_svd_paper(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N, int32_t k, int32_t D,
+                             int32_t checker, uint64_t seed, double tol, void *workspace, size_t ws_bytes,
+                             double *sigma, double *U, ranky_paper_info *pinfo, ranky_stream_t stream);
+
+/* The paper's error sums (Sec. IV, as read here): e_sigma = sum_{i<k} |sigma_hat_i - sigma_i| and
+ * e_u = sum_{i<k} sum_m |s_i U_hat[m][i] - U[m][i]| with s_i = sign <u_hat_i, u_i>, on the device
+ * (fixed-order sums).  U_hat, U: M x k row-major; e_sigma, e_u: host.  workspace: (k + 2) doubles.
+ * Blocking. */
+ranky_status ranky_paper_errors(int32_t M, int32_t k, const double *sigma_hat, const double *U_hat, const double *sigma,
+                                const double *U, double *e_sigma, double *e_u, void *workspace, size_t ws_bytes,
+                                ranky_stream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* Tall and skinny (M >> N)                                                   */
+/* ------------------------------------------------------------------------- */
+
+/* The CSC of A^T (= the CSR of A) for any row count M: colptr_t [M + 1], rowidx_t [nnz] (the
+ * column indices of A, increasing inside each row), values_t [nnz] of A's dtype.  The CSC contract
+ * of A is checked first (E_CSC / E_NONFINITE).  workspace: at least
+ * ranky_tall_workspace_bytes(M, 1, nnz, 1, NULL) bytes (the transpose's counters use a prefix of
+ * it).  Blocking.  Integer work: the result is exact and does not depend on scheduling. */
+ranky_status ranky_transpose(const ranky_csc *A, int64_t M, int64_t N, int32_t *colptr_t, int32_t *rowidx_t,
+                             void *values_t, void *workspace, size_t ws_bytes, ranky_stream_t stream);
+
+/* Bytes of workspace ranky_svd_tall needs (0 if the sizes are invalid). */
+size_t ranky_tall_workspace_bytes(int64_t M, int32_t N, int64_t nnz, int32_t k, const ranky_opts *opts);
+
+/* Top-k singular triplets of a tall-and-skinny A (M x N, M >> N; the paper's problem statement
+ * takes the short-and-fat case, Sec. I, and notes the split by rows for the other, Sec. II) by the
+ * same method on A^T: A is transposed on the device (ranky_transpose), A^T's column blocks are A's
+ * row blocks (opts.n_blocks D splits the M rows as floor(bM/D)), and the path of ranky_svd runs on
+ * A^T, whose left vectors are A's right vectors and whose right vectors are A's left vectors.
+ *   sigma [k]          as ranky_svd
+ *   U     [M x k]      row-major, opts.v_dtype: u_i = A v_i / sigma_i for i < rank, 0 beyond
+ *   V     [N x k]      row-major FP64: eigenvectors of A^T A, sign fixed so the entry of largest
+ *                      magnitude is positive; columns of A with no entry come last as e_col
+ *   info  (host, may be NULL): n_nonempty counts A's non-empty columns; the per-block counts are
+ *                      those of A's row blocks (columns of A empty inside a row block)
+ * N <= 8192 and 1 <= k <= N (E_INVALID otherwise); M up to 2^31 - 2.  Blocking. */
+ranky_status ranky_svd_tall(ranky_ctx *ctx, const ranky_csc *A, int64_t M, int32_t N, int32_t k, double tol,
+                            const ranky_opts *opts, void *workspace, size_t ws_bytes, double *sigma, void *U, double *V,
+                            ranky_info *info, ranky_stream_t stream);
 
 #ifdef __cplusplus
 }

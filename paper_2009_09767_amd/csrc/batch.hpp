@@ -23,11 +23,13 @@ struct MatDesc {
     int32_t gseg;             // Gram segment length (nonzeros of a row per workgroup)
     int32_t dtype, v_dtype;
     int32_t n, npad;          // non-empty rows and the eigensolver order (set after the scan)
+    int32_t neig;             // eigenpairs the eigensolve leaves in lam / W (n, or the subspace block width)
     int32_t prec;             // Gram accumulation: 0 FP64, 1 FP32, 2 FP32 with BF16x3 dense tiles
     int32_t validate;
     int32_t n_tau;            // row count entering the threshold sqrt(n_tau u_gram)
     int32_t dwg;              // split-bf16 dense-tile workgroups (0: the dense rows stay in the sparse pass)
     int32_t blk_off;          // first entry of this matrix's per-block counts in the read-back array
+    int32_t gwaves;           // Gram walk waves per workgroup (a function of M and the accumulator alone)
     double tol;               // rank threshold option
     double u_gram;            // unit roundoff of the Gram entries for the threshold
     double jtol;              // Jacobi rotation test tolerance (0: max(1e-15, sqrt(n) eps))

@@ -59,9 +59,12 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
     const auto csr_end = gmem(dsc.csrend);
     const auto dense = gmem(dsc.dense);
     const auto G = gmem(dsc.G);
-    const int nw = blockDim.x >> 6;
+    // the matrix's own wave count (a function of its M alone, so a batch sums in the order a
+    // single call does); waves of a wider launch at or past it take no part in the walk
+    const int nw = dsc.gwaves;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
+    const bool walker = wave < nw;
     if (i >= n) {  // padding row and column of the Jacobi layout
         for (int32_t j = i + threadIdx.x; j < npad; j += blockDim.x) {
             G[(int64_t)i * ld + j] = 0.0;
@@ -108,12 +111,12 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
     // Lanes past the end of the run load the run's last entry (a valid address) and
     // discard it: with no conditional loads, all of a group's loads stay in flight.
     int32_t kk = 0, kend = 0;
-    if (wb < we) {
+    if (walker && wb < we) {
         const int32_t e0 = wb + lane < we ? wb + lane : we - 1;
         kk = csr_k[e0];
         kend = csr_end[e0];
     }
-    for (int32_t base = wb; base < we; base += 64) {
+    for (int32_t base = wb; walker && base < we; base += 64) {
         const bool has = base + lane < we;
         const int32_t nb = base + 64 + lane < we ? base + 64 + lane : we - 1;
         const int32_t kk_next = csr_k[nb], kend_next = csr_end[nb];
@@ -161,7 +164,7 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
     dg = wave_sum(dg);
     if (lane == 0) dsum[wave] = dg;
     // the dense rows: lane-private sums reduced over the lanes into the wave's row
-    for (int t = 0; t < kDenseRows; ++t) {
+    for (int t = 0; walker && t < kDenseRows; ++t) {
         const int32_t q = dense[t];
         if (q < 0) break;
         const Acc v = wave_sum(myslot[t * 64]);
@@ -407,17 +410,15 @@ int gram_waves(int32_t M, int32_t acc_bytes, size_t lds_limit) {
     return w;
 }
 
-size_t gram_lds_bytes(int32_t maxM, int32_t acc_bytes, size_t lds_limit) {
-    const int nw = gram_waves(maxM, acc_bytes, lds_limit);
-    return (size_t)nw * gram_wave_bytes(maxM, acc_bytes) + gram_fixed_bytes(maxM);
+size_t gram_lds_bytes(int32_t M, int32_t acc_bytes, int32_t nw) {
+    return (size_t)nw * gram_wave_bytes(M, acc_bytes) + gram_fixed_bytes(M);
 }
 
 void launch_gram(const MatDesc *descs, const int32_t *wp, int64_t nblocks, const int32_t *wp_red, int64_t nblocks_red,
-                 int count, int32_t maxM, int32_t acc_bytes, size_t lds_limit, hipStream_t s) {
+                 int count, int32_t max_waves, size_t lds_bytes, hipStream_t s) {
     if (nblocks <= 0) return;
-    const int nw = gram_waves(maxM, acc_bytes, lds_limit);
-    hipLaunchKernelGGL(k_gram_rows, dim3((unsigned)nblocks), dim3((unsigned)(64 * nw)),
-                       gram_lds_bytes(maxM, acc_bytes, lds_limit), s, descs, wp, count);
+    hipLaunchKernelGGL(k_gram_rows, dim3((unsigned)nblocks), dim3((unsigned)(64 * max_waves)), lds_bytes, s, descs, wp,
+                       count);
     if (nblocks_red > 0)
         hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)nblocks_red), dim3(256), 0, s, descs, wp_red, count);
 }

@@ -18,7 +18,9 @@ __global__ __launch_bounds__(1024) void k_select_sort(const MatDesc *__restrict_
     extern __shared__ double lds_key[];
     const MatDesc &d = descs[blockIdx.x];
     const double *__restrict__ lam = d.lam;
-    const int32_t n = d.n, k = d.k, n_tau = d.n_tau;
+    // neig eigenpairs were computed (M' for the full Jacobi, the block width for the
+    // subspace iteration); the threshold still counts the M' rows
+    const int32_t n = d.neig, k = d.k, n_tau = d.n_tau;
     const double tol = d.tol;
     // the split-bf16 tiles run only when the scan found two dense rows or more; otherwise
     // the whole Gram came from the FP32 sparse pass and its roundoff is FP32's

@@ -35,11 +35,14 @@ size_t transpose_lds_bytes(int32_t M);
 hipError_t occupancy_set_attributes(int32_t maxM);
 
 // Gram (k_gram.hip)
+// waves per Gram workgroup of an M-row matrix (a function of the matrix alone: it fixes the
+// order of the sums) and the LDS that matrix's workgroups use with nw waves
 int gram_waves(int32_t M, int32_t acc_bytes, size_t lds_limit);
-size_t gram_lds_bytes(int32_t maxM, int32_t acc_bytes, size_t lds_limit);
+size_t gram_lds_bytes(int32_t M, int32_t acc_bytes, int32_t nw);
 int64_t gram_part_slots(int64_t nnz);   // partial Gram rows the workspace must hold
+// max_waves, lds_bytes: the largest MatDesc::gwaves and LDS over the launch's matrices
 void launch_gram(const MatDesc *descs, const int32_t *wp, int64_t nblocks, const int32_t *wp_red, int64_t nblocks_red,
-                 int count, int32_t maxM, int32_t acc_bytes, size_t lds_limit, hipStream_t s);
+                 int count, int32_t max_waves, size_t lds_bytes, hipStream_t s);
 hipError_t gram_set_attributes(size_t lds_limit);
 int32_t gram_dense_wgs(int64_t N);   // workgroups of the split-bf16 dense-row tiles (a function of N)
 void launch_gram_dense(const MatDesc *descs, int32_t dwg, hipStream_t s);   // BF16X3 dense tiles
@@ -89,5 +92,63 @@ void launch_rr_h(const CscView &A, int64_t N, int32_t k, const double *U0, doubl
 // U = U0 Q (sign rule applied); Uf (or NULL) gets the same U in FP32
 void launch_rr_apply(const double *U0, const double *Q, int64_t ldq, const int32_t *perm, int32_t M, int32_t k,
                      double *U, float *Uf, hipStream_t s);
+
+// Leading eigenpairs by Chebyshev-filtered subspace iteration (k_topk.hip).  Block matrices are
+// rows x p row-major (ld p); rows and p are multiples of 64.
+constexpr int32_t kTopkTile = 64;
+// part[z] = op(A) B over the z-th k range of klen (k ranges past K empty); then
+// launch_tk_combine adds the splits in order: out = alpha sum + beta E + gamma F
+void launch_tk_gemm(bool trans_a, const double *A, int64_t lda, const double *B, int64_t ldb, double *part,
+                    int32_t rows, int32_t cols, int32_t K, int32_t splits, int32_t klen, int32_t a_valid,
+                    int32_t k_valid, hipStream_t s);
+void launch_tk_combine(const double *part, int32_t splits, int64_t count, double alpha, double beta, const double *E,
+                       double gamma, const double *F, double *out, hipStream_t s);
+void launch_tk_start(const double *G, int64_t ldg, int32_t n, int32_t p, int32_t rows, double *X, hipStream_t s);
+void launch_tk_symcopy(const double *src, int32_t p, double *dst, double *dvec, hipStream_t s);
+void launch_tk_svqb_w(const double *V, const double *lam, const double *dvec, int32_t p, double *Wm, hipStream_t s);
+void launch_tk_permute(const double *V, const double *lam, const int32_t *perm, int32_t p, double *Qs, double *theta,
+                       hipStream_t s);
+void launch_tk_resid(const double *GX, const double *X, const double *theta, int32_t n, int32_t p, double *out,
+                     hipStream_t s);
+void launch_tk_place(const double *src, int32_t rows, int32_t p, double *dst, int64_t ldd, hipStream_t s);
+
+// Tall-and-skinny layout (k_tall.hip): the CSC of A^T (= the CSR of A) for any row count M.
+// counts, cursor, long_rows: M ints; btot: tall_scan_blocks(M) ints; ptr: M + 1 (the colptr of
+// A^T); nlong: 1; trow: nnz ints (row indices of A^T); tval: nnz values of A's dtype.  Rows of
+// A outside [0, M) are dropped (run launch_validate_csc first to report them).
+int64_t tall_scan_blocks(int64_t M);
+void launch_transpose_csc(const CscView &A, int64_t M, int64_t N, int32_t *counts, int32_t *btot, int32_t *ptr,
+                          int32_t *cursor, int32_t *long_rows, int32_t *nlong, int32_t *trow, void *tval,
+                          hipStream_t s);
+// the CSC contract of A (any M) into *status (kStCsc / kStNonfinite bits)
+void launch_validate_csc(const CscView &A, int64_t M, int64_t N, int32_t *status, hipStream_t s);
+// ptr[0..n] = exclusive scan of counts[0..n) (btot: tall_scan_blocks(n) ints of scratch)
+void launch_exclusive_scan(const int32_t *counts, int64_t n, int32_t *btot, int32_t *ptr, hipStream_t s);
+// each segment [ptr[i], ptr[i+1]) of keys (distinct inside a segment, at most 8192 long) sorted
+// ascending with its values; long_rows: nseg ints of scratch, nlong: 1
+void launch_sort_segments(const int32_t *ptr, int64_t nseg, int32_t *keys, double *vals, int32_t *long_rows,
+                          int32_t *nlong, hipStream_t s);
+
+// The paper's own procedure (k_paper.hip): checkers, proxy matrix, error sums.
+size_t checker_lds_bytes(int32_t M, int64_t width);
+hipError_t paper_set_attributes(size_t lds_limit);
+// ins [2 D M]: the new entries (col * M + row) of every (block, row) pair, -1 for none.  cnt is the
+// scan's [D x M] occupancy, rowptr / csr_col the rows of A from the transpose.
+void launch_checker(const CscView &A, int32_t M, int64_t N, int32_t D, const int32_t *cnt, const int32_t *rowptr,
+                    const int32_t *csr_col, int32_t kind, uint64_t seed, int64_t *ins, hipStream_t s);
+// A' = A plus the new entries: counts, cursor, long_rows: N ints; btot: tall_scan_blocks(N); iptr:
+// N + 1; irow, ival: the new entries (nins); nlong: 1.  colptr_out [N + 1], rowidx_out / vals_out (FP64).
+void launch_checker_apply(const CscView &A, int32_t M, int64_t N, const int64_t *ins, int64_t nins, int32_t *counts,
+                          int32_t *btot, int32_t *iptr, int32_t *cursor, int32_t *irow, double *ival,
+                          int32_t *long_rows, int32_t *nlong, int32_t *colptr_out, int32_t *rowidx_out,
+                          double *vals_out, hipStream_t s);
+// out [N + D]: block b's columns as their own CSC column pointers, at offset floor(bN/D) + b
+void launch_block_slices(const int32_t *colptr, int64_t N, int32_t D, int32_t *out, hipStream_t s);
+// rows [0, rank) of P^T from one block's U_b (M x M) and sigma_b over the compacted rows
+void launch_proxy_rows(const double *Ub, const double *sb, int32_t M, int32_t rank, const int32_t *m2r, double *Pt,
+                       int64_t ldp, hipStream_t s);
+// out[0] = e_sigma, out[1] = e_u over k columns (col_err: k doubles of scratch)
+void launch_paper_errors(const double *sh, const double *Uh, const double *s_ref, const double *U_ref, int32_t M,
+                         int32_t k, double *col_err, double *out, hipStream_t s);
 
 }  // namespace ranky

@@ -95,8 +95,86 @@ hipError_t kernel_attributes(int device, size_t lds_limit) {
     hipError_t e = occupancy_set_attributes(kMaxM);
     if (e == hipSuccess) e = gram_set_attributes(lds_limit);
     if (e == hipSuccess) e = select_set_attributes();
+    if (e == hipSuccess) e = paper_set_attributes(lds_limit);
     if (e == hipSuccess) g_attr_devices.push_back(device);
     return e;
+}
+
+// ---------------------------------------------------------------------------
+// subspace iteration for the k leading eigenpairs (k << M')
+// ---------------------------------------------------------------------------
+
+constexpr int32_t kTopkMaxBlock = 256;    // widest block (the p x p problems run on the Jacobi)
+constexpr int32_t kTopkWgTarget = 512;    // workgroups a split product aims for
+constexpr int32_t kTopkDefaultIters = 60;
+
+// Block width for k wanted pairs: k plus half again (at least 32) of oversampling, in 64s.
+int32_t topk_block(int32_t k) {
+    const int32_t want = k + std::max(k / 2, 32);
+    return ((want + kTopkTile - 1) / kTopkTile) * kTopkTile;
+}
+
+// k split of a product with `tiles` output tiles over K: (splits, klen), klen a multiple of 16.
+void topk_split(int64_t tiles, int32_t K, int32_t &splits, int32_t &klen) {
+    int64_t sp = (kTopkWgTarget + tiles - 1) / tiles;
+    if (sp > K / 64) sp = K / 64;
+    if (sp < 1) sp = 1;
+    klen = (int32_t)((((K + sp - 1) / sp) + 15) / 16 * 16);
+    splits = (K + klen - 1) / klen;
+}
+
+struct TopkLayout {
+    int32_t p = 0, rows = 0;   // block width; block rows (the eigensolver order rounded up to 64)
+    size_t o_blk[5] = {}, o_part = 0, o_Sp = 0, o_Wm = 0, o_Qs = 0, o_theta = 0, o_dvec = 0, o_sig = 0;
+    size_t o_hdr = 0, o_jscal = 0, o_jsdbl = 0, o_jstate = 0, o_jG = 0, o_jG2 = 0, o_jW = 0, o_jJ = 0, o_jS = 0;
+    size_t o_jflag = 0, o_jlam = 0, o_jperm = 0, part_doubles = 0, hdr_bytes = 0, total = 0;
+};
+
+size_t topk_small_header_bytes(int32_t p);
+
+// Region of the subspace iteration for an M-row matrix and block width p, at offset 0.
+TopkLayout topk_layout(int32_t M, int32_t p) {
+    TopkLayout t;
+    t.p = p;
+    const int32_t npad = jacobi_npad(M);
+    t.rows = ((npad + kTopkTile - 1) / kTopkTile) * kTopkTile;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    const size_t blk = sizeof(double) * (size_t)t.rows * p, sq = sizeof(double) * (size_t)p * p;
+    for (size_t &o : t.o_blk) o = take(blk);
+    int32_t sp1, kl1, sp2, kl2;
+    topk_split((int64_t)(t.rows / kTopkTile) * (p / kTopkTile), npad, sp1, kl1);     // G Y
+    topk_split((int64_t)(p / kTopkTile) * (p / kTopkTile), t.rows, sp2, kl2);        // Y^T Y, Y^T T
+    int32_t sp3, kl3;
+    topk_split((int64_t)(t.rows / kTopkTile) * (p / kTopkTile), p, sp3, kl3);        // Y W
+    t.part_doubles = std::max({(size_t)sp1 * t.rows * p, (size_t)sp2 * p * p, (size_t)sp3 * t.rows * p});
+    t.o_part = take(sizeof(double) * t.part_doubles);
+    t.o_Sp = take(sq);
+    t.o_Wm = take(sq);
+    t.o_Qs = take(sq);
+    t.o_theta = take(sizeof(double) * p);
+    t.o_dvec = take(sizeof(double) * p);
+    t.o_sig = take(sizeof(double) * p);
+    t.hdr_bytes = topk_small_header_bytes(p);
+    t.o_hdr = take(t.hdr_bytes);
+    const size_t npairs = (size_t)(p / kJacobiPair);
+    t.o_jscal = take(sizeof(int32_t) * kScCount);
+    t.o_jsdbl = take(sizeof(double) * kSdCount);
+    t.o_jstate = take(sizeof(int32_t) * kJsCount);
+    t.o_jG = take(sq);
+    t.o_jG2 = take(sq);
+    t.o_jW = take(sq);
+    t.o_jJ = take(sizeof(double) * 2 * npairs * kJacobiPair * kJacobiPair);
+    t.o_jS = take(sizeof(double) * 2 * npairs * kJacobiPair * kJacobiPair);
+    t.o_jflag = take(sizeof(int32_t) * 2 * npairs);
+    t.o_jlam = take(sizeof(double) * p);
+    t.o_jperm = take(sizeof(int32_t) * p);
+    t.total = off;
+    return t;
 }
 
 // ---------------------------------------------------------------------------
@@ -114,14 +192,17 @@ struct Plan {
     size_t o_U0 = 0, o_part = 0, o_uf = 0, total = 0;
     size_t o_bstart = 0;
     bool solver = false, refine = false, explicit_blocks = false, uf = false;
+    size_t o_topk = 0;     // the subspace iteration's region (topk.p > 0)
+    TopkLayout topk;
 };
 
 // bstart (host, may be NULL): the caller's D + 1 block boundaries; the widest block sets
 // the chunks per block, and the boundaries get a device copy in the workspace.
 // dense: room for the split-bf16 dense tiles (a single matrix; used with gram_prec BF16X3).
 // uf: room for an FP32 copy of U (solver plans with an FP32 V: the back-projection gathers it).
+// topk_p: block width of the subspace iteration (0: the full Jacobi only).
 Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool solver, bool refine,
-               const int64_t *bstart = nullptr, bool dense = false, bool uf = false) {
+               const int64_t *bstart = nullptr, bool dense = false, bool uf = false, int32_t topk_p = 0) {
     Plan p;
     p.M = M;
     p.N = N;
@@ -190,6 +271,10 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool sol
         if (uf) {
             p.uf = true;
             p.o_uf = take(sizeof(float) * (size_t)M * k);
+        }
+        if (topk_p > 0) {
+            p.topk = topk_layout(M, topk_p);
+            p.o_topk = take(p.topk.total);
         }
     }
     p.total = off;
@@ -334,6 +419,8 @@ ranky_status check_opts(const ranky_opts &o) {
         return fail(RANKY_E_INVALID, "gram_prec=%d", o.gram_prec);
     if (o.v_dtype != RANKY_F32 && o.v_dtype != RANKY_F64) return fail(RANKY_E_INVALID, "v_dtype=%d", o.v_dtype);
     if (o.refine < 0 || o.refine > 1) return fail(RANKY_E_INVALID, "refine=%d (0, 1, or -1 = automatic)", o.refine);
+    if (o.eigensolver < 0 || o.eigensolver > 2) return fail(RANKY_E_INVALID, "eigensolver=%d (0, 1 or 2)", o.eigensolver);
+    if (o.max_iters < 0) return fail(RANKY_E_INVALID, "max_iters=%d", o.max_iters);
     return RANKY_OK;
 }
 
@@ -363,6 +450,19 @@ ranky_status ensure_pinned(ranky_ctx *ctx, size_t bytes) {
     HIP_TRY(hipHostGetDevicePointer(&ctx->pinned_dev, ctx->pinned, 0));
     ctx->pinned_bytes = want;
     return RANKY_OK;
+}
+
+// Launch shape of the Gram walk over a batch: as many waves as the matrix with the most, and
+// the LDS of the hungriest matrix (each matrix's workgroups use its own count and layout).
+void gram_shape(const std::vector<MatDesc> &d, size_t lds_limit, int32_t &max_waves, size_t &lds_bytes) {
+    max_waves = 1;
+    lds_bytes = 0;
+    for (const MatDesc &x : d) {
+        const int32_t acc = x.prec == RANKY_PREC_FP64 ? 8 : 4;
+        max_waves = std::max(max_waves, x.gwaves);
+        lds_bytes = std::max(lds_bytes, gram_lds_bytes(x.M, acc, x.gwaves));   // <= lds_limit by gram_waves
+    }
+    (void)lds_limit;
 }
 
 // Fills the workgroup prefix for one phase: wp[i+1] = wp[i] + blocks(i).
@@ -463,6 +563,7 @@ struct Engine {
             d[i].n = status[i] == RANKY_OK ? iv[kColI * i + 1] : 0;
             gsegs[i] = status[i] == RANKY_OK ? iv[kColI * i + 8] : 0;
             d[i].n_tau = d[i].n;
+            d[i].neig = d[i].n;
             d[i].npad = jacobi_npad(d[i].n > 0 ? d[i].n : 1);
             maxn = std::max(maxn, d[i].n);
         }
@@ -517,6 +618,8 @@ struct Engine {
                     bpb[i] = std::max<int64_t>(1, std::min(share, backproject_blocks(d[i].N, ctx->cu_count, d[i].bp_per_cu)));
                 }
         }
+        for (int i = 0; i < count; ++i)
+            if (d[i].V == nullptr) bpb[i] = 0;   // a member whose right vectors are not wanted
         const int32_t widths[3] = {1, 2, 4};
         for (int c = 0; c < 3; ++c)
             nblk[kPhBack + c] = fill_wp(hwp(kPhBack + c), count, [&](int i) -> int64_t {
@@ -698,14 +801,219 @@ ranky_status make_engine(ranky_ctx *ctx, hipStream_t s, const Header &h, char *h
     return RANKY_OK;
 }
 
+size_t topk_small_header_bytes(int32_t p) { return make_header(1, 1, p / kJacobiBlock).total; }
+
+// Block width of the subspace iteration for a call on `count` matrices of which the first has
+// M rows and k wanted pairs (0: the full Jacobi runs).  eigensolver 2 asks for it whenever the
+// block is at most half the rows; 0 (automatic) takes it when the block is at most an eighth.
+int32_t topk_plan_p(const ranky_opts &o, int count, int32_t M, int32_t k) {
+    if (count != 1 || o.eigensolver == 1) return 0;
+    const int32_t p = topk_block(k);
+    if (p > kTopkMaxBlock) return 0;
+    return (o.eigensolver == 2 ? 2 * p : 8 * p) <= M ? p : 0;
+}
+
+// The subspace iteration on the main matrix of engine e (a batch of one): Chebyshev filter,
+// two SVQB passes, Rayleigh-Ritz, until the k leading Ritz pairs have residuals at most
+// tol_r theta_1 (or stop improving at the rounding level).  On success the Ritz values are in
+// lam[0, p) (descending), the Ritz vectors in W's first p columns, neig = p, and *iters
+// holds the iterations; *iters = 0 when it did not converge (the caller runs the Jacobi).
+struct Topk {
+    ranky_ctx *ctx;
+    hipStream_t s;
+    TopkLayout L;
+    char *base;               // the region in the workspace
+    MatDesc *x;               // the main matrix (host copy)
+    Engine es;                // the p x p Jacobi
+    double *blk[5];
+    double *part, *Sp, *Wm, *Qs, *theta, *dvec;
+    int32_t n = 0;           // rows of G (the products' useful rows)
+    double flops = 0.0;      // algorithmic flops of the products: 2 (useful rows) x cols x (useful k)
+
+    double *at(size_t o) { return reinterpret_cast<double *>(base + o); }
+
+    // out = alpha op(A) B + beta E + gamma F  (rows x cols, ld cols)
+    void gemm(bool ta, const double *A, int64_t lda, const double *B, int64_t ldb, double *out, int32_t rows,
+              int32_t cols, int32_t K, int32_t a_valid, int32_t k_valid, double alpha, double beta = 0.0,
+              const double *E = nullptr, double gamma = 0.0, const double *F = nullptr) {
+        int32_t splits, klen;
+        topk_split((int64_t)(rows / kTopkTile) * (cols / kTopkTile), K, splits, klen);
+        flops += 2.0 * (ta ? rows : std::min(rows, n)) * cols * std::min(K, std::min(k_valid, n));
+        launch_tk_gemm(ta, A, lda, B, ldb, part, rows, cols, K, splits, klen, a_valid, k_valid, s);
+        launch_tk_combine(part, splits, (int64_t)rows * cols, alpha, beta, E, gamma, F, out, s);
+    }
+    // the p x p Jacobi on the matrix already in es's G; eigenvectors in its W, values in lam
+    ranky_status eig() {
+        launch_fill_i32(es.d[0].scal, kScCount, 0, s);
+        const ranky_status st = es.eigensolve(false);
+        if (st) return st;
+        if (es.notconv[0]) return fail(RANKY_E_NOT_CONVERGED, "Jacobi on a %d x %d block did not converge", L.p, L.p);
+        return RANKY_OK;
+    }
+    // Y (orthonormal afterwards) <- Y D^-1 V L^-1/2, written to out
+    ranky_status svqb(const double *Y, double *out) {
+        const int32_t p = L.p;
+        gemm(true, Y, p, Y, p, Sp, p, p, L.rows, L.rows, L.rows, 1.0);
+        launch_tk_symcopy(Sp, p, es.d[0].G, dvec, s);
+        ranky_status st = eig();
+        if (st) return st;
+        launch_tk_svqb_w(es.d[0].W, es.d[0].lam, dvec, p, Wm, s);
+        gemm(false, Y, p, Wm, p, out, L.rows, p, p, L.rows, p, 1.0);
+        return RANKY_OK;
+    }
+};
+
+ranky_status topk_eigensolve(ranky_ctx *ctx, Engine &e, const Plan &plan, char *mat_base, double tol_r,
+                             int32_t max_iters, hipStream_t s, int32_t *iters, double *flops) {
+    *iters = 0;
+    MatDesc &x = e.d[0];
+    Topk t;
+    t.n = x.n;
+    t.ctx = ctx;
+    t.s = s;
+    t.L = plan.topk;
+    t.base = mat_base + plan.o_topk;
+    t.x = &x;
+    for (int i = 0; i < 5; ++i) t.blk[i] = t.at(t.L.o_blk[i]);
+    t.part = t.at(t.L.o_part);
+    t.Sp = t.at(t.L.o_Sp);
+    t.Wm = t.at(t.L.o_Wm);
+    t.Qs = t.at(t.L.o_Qs);
+    t.theta = t.at(t.L.o_theta);
+    t.dvec = t.at(t.L.o_dvec);
+    const int32_t p = t.L.p, rows = t.L.rows, n = x.n, npad = x.npad, k = x.k;
+    // the p x p Jacobi: its own descriptor and header in the region; the read-back of the Ritz
+    // values and residuals (2p doubles) goes through the pinned staging past both headers.  The
+    // staging is sized first, so that no later growth drops what the small engine stages there.
+    const Header hs = make_header(1, 1, p / kJacobiBlock);
+    const size_t rb_off = align_up(std::max(hs.total, e.h.total));
+    ranky_status st = ensure_pinned(ctx, rb_off + sizeof(double) * 2 * (size_t)p);
+    if (st) return st;
+    st = make_engine(ctx, s, hs, t.base + t.L.o_hdr, 1, t.es);
+    if (st) return st;
+    MatDesc jd;
+    std::memset(&jd, 0, sizeof(jd));
+    jd.scal = reinterpret_cast<int32_t *>(t.base + t.L.o_jscal);
+    jd.sdbl = t.at(t.L.o_jsdbl);
+    jd.jstate = reinterpret_cast<int32_t *>(t.base + t.L.o_jstate);
+    jd.G = t.at(t.L.o_jG);
+    jd.G2 = t.at(t.L.o_jG2);
+    jd.W = t.at(t.L.o_jW);
+    jd.J = t.at(t.L.o_jJ);
+    jd.S = t.at(t.L.o_jS);
+    jd.jflag = reinterpret_cast<int32_t *>(t.base + t.L.o_jflag);
+    jd.lam = t.at(t.L.o_jlam);
+    jd.perm = reinterpret_cast<int32_t *>(t.base + t.L.o_jperm);
+    jd.sigma = t.at(t.L.o_sig);
+    jd.M = jd.k = jd.n = jd.n_tau = jd.neig = jd.npad = p;
+    jd.u_gram = std::ldexp(1.0, -53);
+    t.es.d.assign(1, jd);
+    t.es.sweeps_cap = kDefaultSweeps;
+    t.es.maxn = p;
+    st = t.es.plan_rest();
+    if (st) return st;
+
+    double *rb_dev = reinterpret_cast<double *>(static_cast<char *>(ctx->pinned_dev) + rb_off);
+    const double *rb_host = reinterpret_cast<const double *>(static_cast<const char *>(ctx->pinned) + rb_off);
+
+    // three rotating block buffers (the basis Y, the Ritz vectors X, the filter's third term)
+    // plus T = G Y and G X
+    double *R3[3] = {t.blk[0], t.blk[1], t.blk[2]};
+    double *T = t.blk[3], *GX = t.blk[4];
+    const double *G = x.G;
+    launch_tk_start(G, npad, n, p, rows, R3[1], s);
+    double *Y = R3[0];
+    st = t.svqb(R3[1], Y);
+    if (st) return st;
+    double prev_res = 1e300;
+    bool done = false;
+    double *X = R3[1];   // Ritz vectors of the current iteration
+    int32_t it = 0;
+    for (; it < max_iters; ++it) {
+        // Rayleigh-Ritz on the orthonormal Y
+        t.gemm(false, G, npad, Y, p, T, rows, p, npad, npad, npad, 1.0);
+        t.gemm(true, Y, p, T, p, t.Sp, p, p, rows, rows, rows, 1.0);
+        launch_tk_symcopy(t.Sp, p, t.es.d[0].G, nullptr, s);
+        st = t.eig();
+        if (st) return st;
+        launch_select(t.es.ddesc(), 1, p, s);
+        launch_tk_permute(t.es.d[0].W, t.es.d[0].lam, t.es.d[0].perm, p, t.Qs, t.theta, s);
+        X = (Y == R3[0]) ? R3[1] : R3[0];
+        t.gemm(false, Y, p, t.Qs, p, X, rows, p, p, rows, p, 1.0);
+        t.gemm(false, T, p, t.Qs, p, GX, rows, p, p, rows, p, 1.0);
+        launch_tk_resid(GX, X, t.theta, n, p, rb_dev, s);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(s));
+        const double th0 = rb_host[0];
+        double worst = 0.0;
+        for (int32_t i = 0; i < k; ++i) worst = std::max(worst, rb_host[p + i]);
+        if (!(th0 > 0.0) || worst <= tol_r * th0) {
+            done = true;
+            break;
+        }
+        // at the rounding level the residuals stop shrinking: accept once they are close to it
+        if (it >= 3 && worst > 0.5 * prev_res && worst <= 8.0 * tol_r * th0) {
+            done = true;
+            break;
+        }
+        prev_res = worst;
+        // Chebyshev filter of X damping [0, b], b = the smallest Ritz value, scaled at theta_1;
+        // the degree keeps the growth of the leading direction below 1e7 so that the block
+        // stays well conditioned for the SVQB
+        const double b = std::max(rb_host[p - 1], th0 * 1e-12);
+        const double c = 0.5 * b, ew = 0.5 * b;
+        const double x0 = (th0 - c) / ew;
+        int32_t m = 1;
+        if (x0 > 1.0) {
+            const double ac = std::acosh(x0);
+            while (m < 8 && std::cosh((m + 1) * ac) <= 1e7) ++m;
+        }
+        const double sigma1 = ew / (th0 - c);
+        const double tau = 2.0 / sigma1;
+        double sig = sigma1;
+        // the recurrence's three terms rotate over the three buffers, starting from X (Y is free now)
+        double *prev = X, *cur = nullptr, *spare = nullptr;
+        for (double *b : R3)
+            if (b != X) (cur ? spare : cur) = b;
+        t.gemm(false, G, npad, prev, p, cur, rows, p, npad, npad, npad, sigma1 / ew, -c * sigma1 / ew, prev);
+        for (int32_t d = 2; d <= m; ++d) {
+            const double sig2 = 1.0 / (tau - sig);
+            t.gemm(false, G, npad, cur, p, spare, rows, p, npad, npad, npad, 2.0 * sig2 / ew, -c * 2.0 * sig2 / ew, cur,
+                   -sig * sig2, prev);
+            double *np_ = prev;
+            prev = cur;
+            cur = spare;
+            spare = np_;
+            sig = sig2;
+        }
+        // two SVQB passes: the filtered block into spare, then back into a free buffer as Y
+        st = t.svqb(cur, spare);
+        if (st) return st;
+        st = t.svqb(spare, prev);
+        if (st) return st;
+        Y = prev;
+    }
+    if (!done) return RANKY_OK;   // *iters stays 0: the caller falls back to the full Jacobi
+    *iters = it + 1;
+    *flops = t.flops;
+    // the Ritz pairs become the eigensolve's output: lam[0, p) and W[:, 0, p)
+    HIP_TRY(hipMemcpyAsync(x.lam, t.theta, sizeof(double) * p, hipMemcpyDeviceToDevice, s));
+    launch_tk_place(X, npad, p, x.W, npad, s);
+    HIP_TRY(hipGetLastError());
+    x.neig = p;
+    return e.upload_desc();
+}
+
 size_t path_bytes(const std::vector<Job> &jobs, const ranky_opts &o) {
     const int count = (int)jobs.size();
     const bool refine = count == 1 && wants_refine(o, jobs[0].k);
     int32_t maxM = 1;
     int64_t sum_d = 0;
     size_t total = 0;
+    const int32_t topk_p = topk_plan_p(o, count, jobs[0].M, jobs[0].k);
     for (const Job &j : jobs) {
-        total += make_plan(j.M, j.N, j.A.nnz, j.k, j.D, true, refine, j.bstart, count == 1, o.v_dtype == RANKY_F32)
+        total += make_plan(j.M, j.N, j.A.nnz, j.k, j.D, true, refine, j.bstart, count == 1, o.v_dtype == RANKY_F32,
+                           topk_p)
                      .total;
         maxM = std::max(maxM, j.M);
         sum_d += j.D;
@@ -722,9 +1030,10 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
     std::vector<int32_t> blk_off(count);
     int32_t maxM = 1;
     int64_t sum_d = 0;
+    const int32_t topk_p = topk_plan_p(o, count, jobs[0].M, jobs[0].k);
     for (int i = 0; i < count; ++i) {
         plans[i] = make_plan(jobs[i].M, jobs[i].N, jobs[i].A.nnz, jobs[i].k, jobs[i].D, true, refine, jobs[i].bstart,
-                             count == 1, o.v_dtype == RANKY_F32);
+                             count == 1, o.v_dtype == RANKY_F32, topk_p);
         maxM = std::max(maxM, jobs[i].M);
         blk_off[i] = (int32_t)sum_d;
         sum_d += jobs[i].D;
@@ -768,6 +1077,7 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
             x.bp_per_cu = tc->second.bp_per_cu;
             x.jsched = tc->second.jsched;
         }
+        x.gwaves = gram_waves(x.M, x.prec == RANKY_PREC_FP64 ? 8 : 4, ctx->lds_limit);
         // unit roundoff of the Gram entries as they are computed: FP64, FP32, or the bf16x3
         // products (2^-16) when the split-bf16 tiles run (a single matrix; the selection
         // falls back to 2^-24 when the scan found fewer than two dense rows, since then no tile
@@ -799,17 +1109,37 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
     if (st) return st;
     e.enqueue_transpose();
     if (timing) hipEventRecord(ctx->ev[2], s);
-    int32_t gram_acc = 4;   // accumulator bytes: FP64 if any matrix of the launch asks for it
-    for (int i = 0; i < count; ++i)
-        if (e.d[i].prec == RANKY_PREC_FP64) gram_acc = 8;
+    int32_t gram_nw = 1;
+    size_t gram_lds = 0;
+    gram_shape(e.d, ctx->lds_limit, gram_nw, gram_lds);
     if (count == 1) launch_gram_dense(e.ddesc(), e.d[0].dwg, s);
-    launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], e.dwp(kPhGramRed), e.nblk[kPhGramRed], count, maxM,
-                gram_acc, ctx->lds_limit, s);
+    launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], e.dwp(kPhGramRed), e.nblk[kPhGramRed], count, gram_nw,
+                gram_lds, s);
     if (count == 1) launch_gram_dense_reduce(e.ddesc(), e.d[0].dwg, s);
     HIP_TRY(hipGetLastError());
     if (timing) hipEventRecord(ctx->ev[3], s);
-    st = e.eigensolve(use_graph);
-    if (st) return st;
+    // the k leading pairs by subspace iteration when the block is narrow next to M' (and the
+    // full Jacobi if that does not converge); otherwise the full Jacobi
+    int32_t eig_iters = 0;
+    double eig_flops = 0.0;
+    const int32_t tkp = plans[0].topk.p;
+    if (tkp > 0 && e.status[0] == RANKY_OK && (o.eigensolver == 2 ? 2 * tkp : 8 * tkp) <= e.d[0].n &&
+        jobs[0].k <= tkp) {
+        const double tol_r = e.d[0].prec == RANKY_PREC_FP64 ? std::sqrt((double)e.d[0].n) * std::ldexp(1.0, -52)
+                                                             : kJacobiTolFp32Gram;
+        st = topk_eigensolve(ctx, e, plans[0], ws + base[0], tol_r, o.max_iters > 0 ? o.max_iters : kTopkDefaultIters,
+                             s, &eig_iters, &eig_flops);
+        if (st) return st;
+        if (eig_iters == 0) st = e.plan_rest();   // the staging was reused: rebuild the round tables
+        if (st) return st;
+    }
+    if (eig_iters > 0) {
+        e.sweeps.assign(count, 0);
+        e.notconv.assign(count, 0);
+    } else {
+        st = e.eigensolve(use_graph);
+        if (st) return st;
+    }
     if (timing) hipEventRecord(ctx->ev[4], s);
     launch_select(e.ddesc(), count, e.maxn, s);
     launch_gather_u(e.ddesc(), e.dwp(kPhGather), e.nblk[kPhGather], count, s);
@@ -837,6 +1167,7 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
         eh.d.assign(1, x);
         MatDesc &y = eh.d[0];
         y.n = k;
+        y.neig = k;
         y.npad = kpad;
         y.n_tau = x.n;
         y.k = k;
@@ -883,6 +1214,8 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
             in.empty_rows = jobs[i].M - e.d[i].n;
             in.sweeps = e.sweeps[i];
             in.rr_sweeps = refine_sweeps;
+            in.eig_iters = i == 0 ? eig_iters : 0;
+            in.eig_flops = i == 0 ? eig_flops : 0.0;
             in.n_blocks = jobs[i].D;
             in.lonely_max = iv[kColI * i + 5];
             in.lonely_blocks = iv[kColI * i + 6];
@@ -995,6 +1328,222 @@ ranky_status step_scan(StepCtx &sc, const ranky_csc *A, int32_t M, int64_t N, in
     if (st) return st;
     if (e.status[0] == RANKY_E_CSC) return fail(RANKY_E_CSC, "CSC contract violated (colptr, row range or row order)");
     if (e.status[0] == RANKY_E_NONFINITE) return fail(RANKY_E_NONFINITE, "non-finite value in A");
+    return RANKY_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the paper's own procedure: checkers, per-block factors, proxy matrix
+// ---------------------------------------------------------------------------
+
+// Checker region: the scan's workspace (with the [D x M] occupancy), the new entries and the
+// scratch of A' = A plus them.
+struct CheckerPlan {
+    Plan scan;
+    Header h;
+    size_t o_scan = 0, o_cnt = 0, o_ins = 0, o_counts = 0, o_cursor = 0, o_long = 0, o_btot = 0, o_iptr = 0;
+    size_t o_nlong = 0, o_irow = 0, o_ival = 0, total = 0;
+};
+
+CheckerPlan checker_plan(int32_t M, int64_t N, int64_t nnz, int32_t D) {
+    CheckerPlan c;
+    c.h = make_header(1, 1, 1);
+    c.scan = make_plan(M, N, nnz, 1, D, false, false, nullptr, true);   // the step scan's own plan
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    c.o_scan = take(c.h.total + c.scan.total);
+    const size_t nin = 2 * (size_t)D * (size_t)M;
+    c.o_cnt = take(sizeof(int32_t) * (size_t)D * M);
+    c.o_ins = take(sizeof(int64_t) * nin);
+    c.o_counts = take(sizeof(int32_t) * (size_t)N);
+    c.o_cursor = take(sizeof(int32_t) * (size_t)N);
+    c.o_long = take(sizeof(int32_t) * (size_t)N);
+    c.o_btot = take(sizeof(int32_t) * (size_t)tall_scan_blocks(N));
+    c.o_iptr = take(sizeof(int32_t) * ((size_t)N + 1));
+    c.o_nlong = take(sizeof(int32_t));
+    c.o_irow = take(sizeof(int32_t) * nin);
+    c.o_ival = take(sizeof(double) * nin);
+    c.total = off;
+    return c;
+}
+
+ranky_status check_checker_args(const ranky_csc *A, int32_t M, int64_t N, int32_t D, int32_t kind) {
+    ranky_status st = check_csc_args(A, M, N);
+    if (st) return st;
+    if (D < 1 || D > N) return fail(RANKY_E_INVALID, "D=%d outside [1, N]", D);
+    if (kind < 0 || kind > 2) return fail(RANKY_E_INVALID, "checker kind %d (0, 1 or 2)", kind);
+    const int64_t wmax = (N + D - 1) / D;
+    if (checker_lds_bytes(M, wmax) > 150 * 1024)
+        return fail(RANKY_E_INVALID, "blocks of %lld columns are too wide for the neighbour sets", (long long)wmax);
+    return RANKY_OK;
+}
+
+// A' into (colptr_out, rowidx_out, vals_out); *added (host) = entries added.  Blocking.
+ranky_status run_checker(StepCtx &sc, const ranky_csc *A, int32_t M, int64_t N, int32_t D, int32_t kind, uint64_t seed,
+                         int32_t *colptr_out, int32_t *rowidx_out, double *vals_out, char *ws, hipStream_t s,
+                         int64_t *added) {
+    const CheckerPlan c = checker_plan(M, N, A->nnz, D);
+    auto i32 = [&](size_t o) { return reinterpret_cast<int32_t *>(ws + o); };
+    Engine e;
+    ranky_status st = step_scan(sc, A, M, N, D, ws + c.o_scan, c.h.total + c.scan.total, s, e, i32(c.o_cnt), nullptr,
+                                nullptr, nullptr);
+    if (st) return st;
+    const MatDesc &x = e.d[0];
+    e.enqueue_transpose();   // the rows of A: rowptr and the column of every entry
+    const CscView Av{A->nnz, A->colptr, A->rowidx, A->values, A->dtype};
+    int64_t *ins = reinterpret_cast<int64_t *>(ws + c.o_ins);
+    launch_checker(Av, M, N, D, i32(c.o_cnt), x.rowptr, x.csrcol, kind, seed, ins, s);
+    launch_fill_f64(reinterpret_cast<double *>(ws + c.o_ival), 2 * (int64_t)D * M, 1.0, s);
+    launch_checker_apply(Av, M, N, ins, 2 * (int64_t)D * M, i32(c.o_counts), i32(c.o_btot), i32(c.o_iptr),
+                         i32(c.o_cursor), i32(c.o_irow), reinterpret_cast<double *>(ws + c.o_ival), i32(c.o_long),
+                         i32(c.o_nlong), colptr_out, rowidx_out, vals_out, s);
+    HIP_TRY(hipGetLastError());
+    int32_t tot = 0;
+    HIP_TRY(hipMemcpyAsync(&tot, i32(c.o_iptr) + N, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *added = tot;
+    return RANKY_OK;
+}
+
+// Layout of the paper's route for an M x N matrix with nnz entries, D blocks, k outputs: the
+// checker's region and A' (when a checker runs), the scan of A', the D block matrices' batch
+// (each block's Gram, full Jacobi, its U and sigma), P^T and the products' partials, and the
+// Jacobi of P P^T with its selection.  Block entries are bounded by nnz + 2 D M (the checker adds
+// at most two entries per (block, row)) and by the block's size.
+struct PaperPlan {
+    CheckerPlan chk;
+    Plan scan;
+    Header hscan;
+    int32_t np = 0;           // P P^T order: M rounded up to 64
+    int64_t nnz1 = 0;         // entries of A' at most
+    size_t o_chk = 0, o_cp = 0, o_ri = 0, o_va = 0, o_scan = 0, o_slices = 0, o_bsig = 0, o_bU = 0, o_rank = 0;
+    size_t o_Pt = 0, o_part = 0, o_Gp = 0, o_jhdr = 0, o_jscal = 0, o_jsdbl = 0, o_jstate = 0, o_jG2 = 0, o_jW = 0;
+    size_t o_jJ = 0, o_jS = 0, o_jflag = 0, o_jlam = 0, o_jperm = 0, o_err = 0, o_batch = 0, batch = 0, total = 0;
+    int32_t part_splits = 1;
+};
+
+std::vector<Job> paper_block_jobs(int32_t M, int64_t N, int32_t D, const std::vector<int64_t> &bnnz) {
+    std::vector<Job> jobs(D);
+    for (int32_t b = 0; b < D; ++b) {
+        std::memset(&jobs[b], 0, sizeof(Job));
+        jobs[b].A.nnz = bnnz[b];
+        jobs[b].A.dtype = RANKY_F64;
+        jobs[b].M = M;
+        jobs[b].N = ((int64_t)(b + 1) * N) / D - ((int64_t)b * N) / D;
+        jobs[b].k = M;
+        jobs[b].D = 1;
+    }
+    return jobs;
+}
+
+ranky_opts paper_block_opts() {
+    ranky_opts o;
+    ranky_default_opts(&o);
+    o.refine = 0;
+    o.eigensolver = 1;
+    o.max_sweeps = kDefaultSweeps;
+    return o;
+}
+
+PaperPlan paper_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool checker) {
+    PaperPlan pp;
+    pp.np = ((M + kTopkTile - 1) / kTopkTile) * kTopkTile;
+    pp.nnz1 = checker ? nnz + 2 * (int64_t)D * M : nnz;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    const size_t nz1 = (size_t)(pp.nnz1 > 0 ? pp.nnz1 : 1);
+    if (checker) {
+        pp.chk = checker_plan(M, N, nnz, D);
+        pp.o_chk = take(pp.chk.total);
+        pp.o_cp = take(sizeof(int32_t) * ((size_t)N + 1));
+        pp.o_ri = take(sizeof(int32_t) * nz1);
+        pp.o_va = take(sizeof(double) * nz1);
+    }
+    pp.hscan = make_header(1, 1, 1);
+    pp.scan = make_plan(M, N, pp.nnz1, 1, D, false, false, nullptr, true);
+    pp.o_scan = take(pp.hscan.total + pp.scan.total);
+    pp.o_slices = take(sizeof(int32_t) * ((size_t)N + D));
+    pp.o_bsig = take(sizeof(double) * (size_t)D * M);
+    pp.o_bU = take(sizeof(double) * (size_t)D * M * M);
+    pp.o_rank = take(sizeof(int32_t) * (size_t)D);
+    const size_t np = pp.np;
+    pp.o_Pt = take(sizeof(double) * (size_t)D * M * np);   // at most M retained triplets per block
+    int32_t klen = 0;
+    topk_split((int64_t)(np / kTopkTile) * (np / kTopkTile), (int32_t)std::min<int64_t>((int64_t)D * M, 0x7fffffff),
+               pp.part_splits, klen);
+    pp.o_part = take(sizeof(double) * (size_t)pp.part_splits * np * np);
+    pp.o_Gp = take(sizeof(double) * np * np);
+    const Header hj = make_header(1, 1, (int32_t)(np / kJacobiBlock));
+    pp.o_jhdr = take(hj.total);
+    const size_t npairs = np / kJacobiPair;
+    pp.o_jscal = take(sizeof(int32_t) * kScCount);
+    pp.o_jsdbl = take(sizeof(double) * kSdCount);
+    pp.o_jstate = take(sizeof(int32_t) * kJsCount);
+    pp.o_jG2 = take(sizeof(double) * np * np);
+    pp.o_jW = take(sizeof(double) * np * np);
+    pp.o_jJ = take(sizeof(double) * 2 * npairs * kJacobiPair * kJacobiPair);
+    pp.o_jS = take(sizeof(double) * 2 * npairs * kJacobiPair * kJacobiPair);
+    pp.o_jflag = take(sizeof(int32_t) * 2 * npairs);
+    pp.o_jlam = take(sizeof(double) * np);
+    pp.o_jperm = take(sizeof(int32_t) * np);
+    pp.o_err = take(sizeof(double) * ((size_t)k + 2));
+    // the blocks' batch, each block sized for the most entries it can hold
+    std::vector<int64_t> bnnz(D);
+    for (int32_t b = 0; b < D; ++b) {
+        const int64_t w = ((int64_t)(b + 1) * N) / D - ((int64_t)b * N) / D;
+        bnnz[b] = std::min<int64_t>(pp.nnz1, w * (int64_t)M);
+    }
+    pp.batch = path_bytes(paper_block_jobs(M, N, D, bnnz), paper_block_opts());
+    pp.o_batch = take(pp.batch);
+    pp.total = off;
+    return pp;
+}
+
+// Tall-and-skinny layout: the transposed CSC and the scratch of the transpose, ahead of the
+// short-and-fat path's workspace for A^T (values sized for FP64).
+struct TallPlan {
+    size_t o_status = 0, o_counts = 0, o_cursor = 0, o_long = 0, o_btot = 0, o_ptr = 0, o_nlong = 0, o_trow = 0;
+    size_t o_tval = 0, o_path = 0;
+};
+
+TallPlan tall_plan(int64_t M, int64_t nnz) {
+    TallPlan t;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    const size_t nz = (size_t)(nnz > 0 ? nnz : 1);
+    t.o_status = take(sizeof(int32_t));
+    t.o_counts = take(sizeof(int32_t) * (size_t)M);
+    t.o_cursor = take(sizeof(int32_t) * (size_t)M);
+    t.o_long = take(sizeof(int32_t) * (size_t)M);
+    t.o_btot = take(sizeof(int32_t) * (size_t)tall_scan_blocks(M));
+    t.o_ptr = take(sizeof(int32_t) * ((size_t)M + 1));
+    t.o_nlong = take(sizeof(int32_t));
+    t.o_trow = take(sizeof(int32_t) * nz);
+    t.o_tval = take(sizeof(double) * nz);
+    t.o_path = off;
+    return t;
+}
+
+ranky_status check_tall_args(const ranky_csc *A, int64_t M, int32_t N, int32_t k) {
+    if (!A) return fail(RANKY_E_INVALID, "A is NULL");
+    if (M < 1 || N < 1) return fail(RANKY_E_INVALID, "M=%lld N=%d must be >= 1", (long long)M, N);
+    if (N > kMaxM) return fail(RANKY_E_INVALID, "N=%d exceeds %d (the narrow side of a tall matrix)", N, kMaxM);
+    if (M > (int64_t)0x7ffffffe) return fail(RANKY_E_INVALID, "M=%lld exceeds int32 row pointers", (long long)M);
+    if (A->nnz < 0 || A->nnz > (int64_t)0x7fffffff) return fail(RANKY_E_INVALID, "nnz=%lld out of range", (long long)A->nnz);
+    if (!A->colptr || (A->nnz > 0 && (!A->rowidx || !A->values))) return fail(RANKY_E_INVALID, "NULL CSC array");
+    if (A->dtype != RANKY_F32 && A->dtype != RANKY_F64) return fail(RANKY_E_INVALID, "bad dtype %d", A->dtype);
+    if (k < 1 || k > N) return fail(RANKY_E_INVALID, "k=%d must be in [1, N=%d]", k, N);
     return RANKY_OK;
 }
 
@@ -1325,6 +1874,7 @@ ranky_status ranky_gram(const ranky_csc *A, int32_t M, int64_t N, int32_t prec, 
     MatDesc &x = e.d[0];
     x.prec = prec;
     if (x.prec != RANKY_PREC_BF16X3) x.dwg = 0;
+    x.gwaves = gram_waves(M, prec == RANKY_PREC_FP64 ? 8 : 4, sc.c.lds_limit);
     if (x.n > 0) {
         e.nblk[kPhGram] = fill_wp(e.hwp(kPhGram), 1, [&](int) { return (int64_t)e.gsegs[0] + (x.npad - x.n); });
         e.nblk[kPhGramRed] = fill_wp(e.hwp(kPhGramRed), 1, [&](int) { return (int64_t)x.n; });
@@ -1333,8 +1883,11 @@ ranky_status ranky_gram(const ranky_csc *A, int32_t M, int64_t N, int32_t prec, 
         if (st) return st;
         e.enqueue_transpose();
         launch_gram_dense(e.ddesc(), x.dwg, s);
-        launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], e.dwp(kPhGramRed), e.nblk[kPhGramRed], 1, M,
-                    prec == RANKY_PREC_FP64 ? 8 : 4, sc.c.lds_limit, s);
+        int32_t gram_nw = 1;
+        size_t gram_lds = 0;
+        gram_shape(e.d, sc.c.lds_limit, gram_nw, gram_lds);
+        launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], e.dwp(kPhGramRed), e.nblk[kPhGramRed], 1, gram_nw,
+                    gram_lds, s);
         launch_gram_dense_reduce(e.ddesc(), x.dwg, s);
         launch_scatter_gram(x.G, x.npad, x.m2r, M, G, s);
     } else {
@@ -1395,6 +1948,7 @@ ranky_status ranky_eigh(int32_t n, const double *G, double *lambda, double *Q, i
     x.D = 0;  // no column blocks: no per-block counters to read back
     x.n = n;
     x.n_tau = n;
+    x.neig = n;
     x.npad = npad;
     StepCtx sc;
     ranky_status st = step_device(sc);
@@ -1435,6 +1989,327 @@ ranky_status ranky_backproject(const ranky_csc *A, int32_t M, int64_t N, int32_t
     launch_backproject(Av, N, k, U, nullptr, sigma, rank, V, v_dtype, cus, reinterpret_cast<hipStream_t>(stream));
     HIP_TRY(hipGetLastError());
     return RANKY_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tall and skinny
+// ---------------------------------------------------------------------------
+
+size_t ranky_tall_workspace_bytes(int64_t M, int32_t N, int64_t nnz, int32_t k, const ranky_opts *opts) {
+    if (M < 1 || N < 1 || N > kMaxM || k < 1 || k > N || nnz < 0 || M > (int64_t)0x7ffffffe) return 0;
+    const size_t path = ranky_workspace_bytes(N, M, nnz, k, opts);
+    if (path == 0) return 0;
+    return tall_plan(M, nnz).o_path + path;
+}
+
+ranky_status ranky_transpose(const ranky_csc *A, int64_t M, int64_t N, int32_t *colptr_t, int32_t *rowidx_t,
+                             void *values_t, void *workspace, size_t ws_bytes, ranky_stream_t stream) {
+    if (!A || M < 1 || N < 1 || M > (int64_t)0x7ffffffe || N > (int64_t)0x7ffffffe)
+        return fail(RANKY_E_INVALID, "bad sizes");
+    if (A->nnz < 0 || A->nnz > (int64_t)0x7fffffff) return fail(RANKY_E_INVALID, "nnz out of range");
+    if (!A->colptr || (A->nnz > 0 && (!A->rowidx || !A->values || !rowidx_t || !values_t)) || !colptr_t)
+        return fail(RANKY_E_INVALID, "NULL array");
+    if (A->dtype != RANKY_F32 && A->dtype != RANKY_F64) return fail(RANKY_E_INVALID, "bad dtype %d", A->dtype);
+    const TallPlan t = tall_plan(M, A->nnz);
+    if (!workspace || ws_bytes < t.o_trow) return fail(RANKY_E_NOMEM, "workspace %zu < %zu", ws_bytes, t.o_trow);
+    if (reinterpret_cast<uintptr_t>(workspace) % kWorkspaceAlign)
+        return fail(RANKY_E_INVALID, "workspace is not %d-byte aligned", kWorkspaceAlign);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(workspace);
+    auto i32 = [&](size_t o) { return reinterpret_cast<int32_t *>(w + o); };
+    const CscView Av{A->nnz, A->colptr, A->rowidx, A->values, A->dtype};
+    launch_validate_csc(Av, M, N, i32(t.o_status), s);
+    int32_t bits = 0;
+    HIP_TRY(hipMemcpyAsync(&bits, i32(t.o_status), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (bits & kStCsc) return fail(RANKY_E_CSC, "CSC contract violated (colptr, row range or row order)");
+    if (bits & kStNonfinite) return fail(RANKY_E_NONFINITE, "non-finite value in A");
+    launch_transpose_csc(Av, M, N, i32(t.o_counts), i32(t.o_btot), colptr_t, i32(t.o_cursor), i32(t.o_long),
+                         i32(t.o_nlong), rowidx_t, values_t, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    return RANKY_OK;
+}
+
+size_t ranky_paper_workspace_bytes(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, int32_t checker) {
+    if (M < 1 || N < 1 || M > kMaxM || nnz < 0 || D < 1 || D > N || k < 1 || k > M || checker < -1 || checker > 2)
+        return 0;
+    return paper_plan(M, N, nnz, k, D, checker >= 0).total;
+}
+
+ranky_status ranky_svd_paper(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N, int32_t k, int32_t D,
+                             int32_t checker, uint64_t seed, double tol, void *workspace, size_t ws_bytes,
+                             double *sigma, double *U, ranky_paper_info *pinfo, ranky_stream_t stream) {
+    if (!ctx) return fail(RANKY_E_INVALID, "ctx is NULL");
+    if (!(tol >= 0.0)) return fail(RANKY_E_INVALID, "tol must be >= 0");
+    if (!sigma || !U) return fail(RANKY_E_INVALID, "NULL output");
+    if (k < 1 || k > M) return fail(RANKY_E_INVALID, "k=%d must be in [1, M=%d]", k, M);
+    ranky_status st = checker >= 0 ? check_checker_args(A, M, N, D, checker) : check_csc_args(A, M, N);
+    if (st) return st;
+    if (D < 1 || D > N) return fail(RANKY_E_INVALID, "D=%d outside [1, N]", D);
+    const PaperPlan pp = paper_plan(M, N, A->nnz, k, D, checker >= 0);
+    if (!workspace || ws_bytes < pp.total) return fail(RANKY_E_NOMEM, "workspace %zu bytes < %zu needed", ws_bytes, pp.total);
+    if (reinterpret_cast<uintptr_t>(workspace) % kWorkspaceAlign)
+        return fail(RANKY_E_INVALID, "workspace is not %d-byte aligned", kWorkspaceAlign);
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(RANKY_E_DEVICE, "hipSetDevice");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(workspace);
+    auto i32 = [&](size_t o) { return reinterpret_cast<int32_t *>(w + o); };
+    auto f64 = [&](size_t o) { return reinterpret_cast<double *>(w + o); };
+    if (pinfo) std::memset(pinfo, 0, sizeof(*pinfo));
+    hipEvent_t *ev = ctx->ev;
+    HIP_TRY(hipEventRecord(ev[0], s));
+    // 1. A' (Alg. 2-4) or A itself
+    ranky_csc A1 = *A;
+    int64_t added = 0;
+    if (checker >= 0) {
+        StepCtx sc;
+        st = run_checker(sc, A, M, N, D, checker, seed, i32(pp.o_cp), i32(pp.o_ri), f64(pp.o_va), w + pp.o_chk, s, &added);
+        if (st) return st;
+        A1.nnz = A->nnz + added;
+        A1.colptr = i32(pp.o_cp);
+        A1.rowidx = i32(pp.o_ri);
+        A1.values = f64(pp.o_va);
+        A1.dtype = RANKY_F64;
+    } else if (A->dtype != RANKY_F64) {
+        return fail(RANKY_E_INVALID, "without a checker the paper's route takes FP64 values");
+    }
+    HIP_TRY(hipEventRecord(ev[1], s));
+    // 2. the scan of A' (validation, non-empty rows: the compaction of P P^T)
+    StepCtx sc2;
+    Engine es;
+    st = step_scan(sc2, &A1, M, N, D, w + pp.o_scan, pp.hscan.total + pp.scan.total, s, es, nullptr, nullptr, nullptr,
+                   nullptr);
+    if (st) return st;
+    const MatDesc xs = es.d[0];
+    const int32_t n = xs.n;
+    // 3. every block's reduced factors (Eq. 1): the D blocks as a batch, V not formed
+    launch_block_slices(A1.colptr, N, D, i32(pp.o_slices), s);
+    std::vector<int32_t> bcol(D + 1);
+    {
+        st = ensure_pinned(ctx, sizeof(int32_t) * ((size_t)D + 1));
+        if (st) return st;
+        int32_t *hp = static_cast<int32_t *>(ctx->pinned);
+        for (int32_t b = 0; b <= D; ++b)
+            HIP_TRY(hipMemcpyAsync(hp + b, A1.colptr + ((int64_t)b * N) / D, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int32_t b = 0; b <= D; ++b) bcol[b] = hp[b];
+    }
+    std::vector<int64_t> bnnz(D);
+    for (int32_t b = 0; b < D; ++b) bnnz[b] = bcol[b + 1] - bcol[b];
+    std::vector<Job> jobs = paper_block_jobs(M, N, D, bnnz);
+    for (int32_t b = 0; b < D; ++b) {
+        const int64_t c0 = ((int64_t)b * N) / D;
+        jobs[b].A.colptr = i32(pp.o_slices) + c0 + b;
+        jobs[b].A.rowidx = A1.rowidx + bcol[b];
+        jobs[b].A.values = static_cast<const double *>(A1.values) + bcol[b];
+        jobs[b].sigma = f64(pp.o_bsig) + (size_t)b * M;
+        jobs[b].U = f64(pp.o_bU) + (size_t)b * M * M;
+        jobs[b].V = nullptr;
+    }
+    std::vector<ranky_info> binfo(D);
+    st = run_path(ctx, jobs, 0.0, paper_block_opts(), w + pp.o_batch, pp.batch, binfo.data(), s, false);
+    if (st) return st;
+    HIP_TRY(hipEventRecord(ev[2], s));
+    // 4. the proxy P = [U^1 S^1 | ... | U^D S^D] over the retained triplets, as rows of P^T
+    const int32_t np = pp.np;
+    int64_t R = 0;
+    for (int32_t b = 0; b < D; ++b) R += binfo[b].rank;
+    const int64_t Rpad = std::max<int64_t>(16, ((R + 15) / 16) * 16);
+    launch_fill_f64(f64(pp.o_Pt), Rpad * np, 0.0, s);
+    for (int32_t b = 0, off = 0; b < D; off += binfo[b].rank, ++b)
+        launch_proxy_rows(f64(pp.o_bU) + (size_t)b * M * M, f64(pp.o_bsig) + (size_t)b * M, M, binfo[b].rank, xs.m2r,
+                          f64(pp.o_Pt) + (size_t)off * np, np, s);
+    // 5. P P^T (Eq. 3) on the FP64 matrix cores, the k splits added in order
+    {
+        int32_t splits, klen;
+        topk_split((int64_t)(np / kTopkTile) * (np / kTopkTile), (int32_t)Rpad, splits, klen);
+        splits = std::min(splits, pp.part_splits);
+        klen = (int32_t)((((Rpad + splits - 1) / splits) + 15) / 16 * 16);
+        splits = (int32_t)((Rpad + klen - 1) / klen);
+        launch_tk_gemm(true, f64(pp.o_Pt), np, f64(pp.o_Pt), np, f64(pp.o_part), np, np, (int32_t)Rpad, splits, klen,
+                       np, (int32_t)Rpad, s);
+        launch_tk_combine(f64(pp.o_part), splits, (int64_t)np * np, 1.0, 0.0, nullptr, 0.0, nullptr, f64(pp.o_Gp), s);
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipEventRecord(ev[3], s));
+    // 6. the SVD of P by the eigenpairs of P P^T (the last step of Alg. 1), threshold, signs
+    int32_t rank = 0;
+    double tau = 0.0;
+    if (n > 0) {
+        const Header hj = make_header(1, 1, np / kJacobiBlock);
+        Engine ej;
+        st = make_engine(ctx, s, hj, w + pp.o_jhdr, 1, ej);
+        if (st) return st;
+        MatDesc jd = xs;
+        jd.scal = i32(pp.o_jscal);
+        jd.sdbl = f64(pp.o_jsdbl);
+        jd.jstate = i32(pp.o_jstate);
+        jd.G = f64(pp.o_Gp);
+        jd.G2 = f64(pp.o_jG2);
+        jd.W = f64(pp.o_jW);
+        jd.J = f64(pp.o_jJ);
+        jd.S = f64(pp.o_jS);
+        jd.jflag = i32(pp.o_jflag);
+        jd.lam = f64(pp.o_jlam);
+        jd.perm = i32(pp.o_jperm);
+        jd.npad = np;
+        jd.n = n;
+        jd.neig = n;
+        jd.n_tau = n;
+        jd.k = k;
+        jd.tol = tol;
+        jd.u_gram = std::ldexp(1.0, -53);
+        jd.jtol = 0.0;
+        jd.dwg = 0;
+        jd.jsched = 0;
+        jd.sigma = sigma;
+        jd.U = U;
+        jd.Uf = nullptr;
+        jd.V = nullptr;
+        ej.d.assign(1, jd);
+        ej.sweeps_cap = kDefaultSweeps;
+        ej.maxn = n;
+        ej.status.assign(1, RANKY_OK);
+        st = ej.plan_rest();
+        if (st) return st;
+        launch_fill_i32(jd.scal, kScCount, 0, s);
+        st = ej.eigensolve(false);
+        if (st) return st;
+        if (ej.notconv[0]) return fail(RANKY_E_NOT_CONVERGED, "Jacobi on P P^T did not converge");
+        launch_select(ej.ddesc(), 1, n, s);
+        launch_gather_u(ej.ddesc(), ej.dwp(kPhGather), ej.nblk[kPhGather], 1, s);
+        HIP_TRY(hipGetLastError());
+        std::vector<int32_t> iv;
+        std::vector<double> fv;
+        st = ej.collect(iv, fv);
+        if (st) return st;
+        rank = iv[2];
+        tau = fv[0];
+    } else {
+        launch_fill_f64(sigma, k, 0.0, s);
+        launch_fill_f64(U, (int64_t)M * k, 0.0, s);
+    }
+    HIP_TRY(hipEventRecord(ev[4], s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (pinfo) {
+        pinfo->added = added;
+        pinfo->nnz_repaired = A1.nnz;
+        pinfo->proxy_cols = R;
+        pinfo->rank = rank;
+        pinfo->n_nonempty = n;
+        pinfo->tau = tau;
+        for (int q = 0; q < 4; ++q) hipEventElapsedTime(&pinfo->ms[q], ev[q], ev[q + 1]);
+    }
+    return RANKY_OK;
+}
+
+ranky_status ranky_paper_errors(int32_t M, int32_t k, const double *sigma_hat, const double *U_hat, const double *sigma,
+                                const double *U, double *e_sigma, double *e_u, void *workspace, size_t ws_bytes,
+                                ranky_stream_t stream) {
+    if (M < 1 || k < 1 || k > M || !sigma_hat || !U_hat || !sigma || !U || !e_sigma || !e_u)
+        return fail(RANKY_E_INVALID, "bad arguments");
+    const size_t need = sizeof(double) * ((size_t)k + 2);
+    if (!workspace || ws_bytes < need) return fail(RANKY_E_NOMEM, "workspace %zu < %zu", ws_bytes, need);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    double *col = static_cast<double *>(workspace);
+    launch_paper_errors(sigma_hat, U_hat, sigma, U, M, k, col, col + k, s);
+    HIP_TRY(hipGetLastError());
+    double out[2] = {0.0, 0.0};
+    HIP_TRY(hipMemcpyAsync(out, col + k, sizeof(out), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *e_sigma = out[0];
+    *e_u = out[1];
+    return RANKY_OK;
+}
+
+size_t ranky_checker_workspace_bytes(int32_t M, int64_t N, int64_t nnz, int32_t D) {
+    if (M < 1 || N < 1 || M > kMaxM || nnz < 0 || D < 1 || D > N) return 0;
+    return checker_plan(M, N, nnz, D).total;
+}
+
+ranky_status ranky_checker(const ranky_csc *A, int32_t M, int64_t N, int32_t D, int32_t kind, uint64_t seed,
+                           int32_t *colptr_out, int32_t *rowidx_out, double *values_out, int64_t capacity,
+                           int64_t *nnz_out, int64_t *added, void *workspace, size_t ws_bytes, ranky_stream_t stream) {
+    ranky_status st = check_checker_args(A, M, N, D, kind);
+    if (st) return st;
+    if (!colptr_out || !rowidx_out || !values_out || !nnz_out || !added) return fail(RANKY_E_INVALID, "NULL output");
+    if (capacity < A->nnz + 2 * (int64_t)D * M)
+        return fail(RANKY_E_INVALID, "capacity %lld < nnz + 2 D M = %lld", (long long)capacity,
+                    (long long)(A->nnz + 2 * (int64_t)D * M));
+    const size_t need = ranky_checker_workspace_bytes(M, N, A->nnz, D);
+    if (!workspace || ws_bytes < need) return fail(RANKY_E_NOMEM, "workspace %zu < %zu", ws_bytes, need);
+    if (reinterpret_cast<uintptr_t>(workspace) % kWorkspaceAlign)
+        return fail(RANKY_E_INVALID, "workspace is not %d-byte aligned", kWorkspaceAlign);
+    StepCtx sc;
+    int64_t add = 0;
+    st = run_checker(sc, A, M, N, D, kind, seed, colptr_out, rowidx_out, values_out, static_cast<char *>(workspace),
+                     reinterpret_cast<hipStream_t>(stream), &add);
+    if (st) return st;
+    *added = add;
+    *nnz_out = A->nnz + add;
+    return RANKY_OK;
+}
+
+ranky_status ranky_svd_tall(ranky_ctx *ctx, const ranky_csc *A, int64_t M, int32_t N, int32_t k, double tol,
+                            const ranky_opts *opts, void *workspace, size_t ws_bytes, double *sigma, void *U, double *V,
+                            ranky_info *info, ranky_stream_t stream) {
+    ranky_info local;
+    ranky_info *inf = info ? info : &local;
+    std::memset(inf, 0, sizeof(*inf));
+    auto finish = [&](ranky_status st) {
+        if (inf->status == RANKY_OK) inf->status = st;
+        return st;
+    };
+    if (!ctx) return finish(fail(RANKY_E_INVALID, "ctx is NULL"));
+    if (!(tol >= 0.0)) return finish(fail(RANKY_E_INVALID, "tol must be >= 0"));
+    if (!sigma || !U || !V) return finish(fail(RANKY_E_INVALID, "NULL output"));
+    ranky_status st = check_tall_args(A, M, N, k);
+    if (st) return finish(st);
+    const ranky_opts o = resolved(opts, true, k);
+    st = check_opts(o);
+    if (st) return finish(st);
+    if (o.block_start) return finish(fail(RANKY_E_INVALID, "block_start is for ranky_svd"));
+    if (o.refine && k > kMaxRefineK) return finish(fail(RANKY_E_INVALID, "refine needs k <= %d", kMaxRefineK));
+    const TallPlan t = tall_plan(M, A->nnz);
+    const size_t need = ranky_tall_workspace_bytes(M, N, A->nnz, k, &o);
+    if (need == 0) return finish(fail(RANKY_E_INVALID, "invalid sizes"));
+    if (!workspace || ws_bytes < need) return finish(fail(RANKY_E_NOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need));
+    if (reinterpret_cast<uintptr_t>(workspace) % kWorkspaceAlign)
+        return finish(fail(RANKY_E_INVALID, "workspace is not %d-byte aligned", kWorkspaceAlign));
+    if (hipSetDevice(ctx->device) != hipSuccess) return finish(fail(RANKY_E_DEVICE, "hipSetDevice"));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(workspace);
+    auto i32 = [&](size_t off) { return reinterpret_cast<int32_t *>(w + off); };
+    const CscView Av{A->nnz, A->colptr, A->rowidx, A->values, A->dtype};
+    // the contract of A (any row count), then A^T = the CSR of A
+    if (o.validate) {
+        st = ensure_pinned(ctx, 64);
+        if (st) return finish(st);
+        launch_validate_csc(Av, M, N, i32(t.o_status), s);
+        int32_t *bits = static_cast<int32_t *>(ctx->pinned);
+        HIP_TRY(hipMemcpyAsync(bits, i32(t.o_status), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (*bits & kStCsc) return finish(fail(RANKY_E_CSC, "CSC contract violated (colptr, row range or row order)"));
+        if (*bits & kStNonfinite) return finish(fail(RANKY_E_NONFINITE, "non-finite value in A"));
+    }
+    launch_transpose_csc(Av, M, N, i32(t.o_counts), i32(t.o_btot), i32(t.o_ptr), i32(t.o_cursor), i32(t.o_long),
+                         i32(t.o_nlong), i32(t.o_trow), w + t.o_tval, s);
+    HIP_TRY(hipGetLastError());
+    // the short-and-fat path on A^T (N x M): its column blocks are A's row blocks; its left
+    // vectors (N x k, FP64) are A's right vectors V, its right vectors (M x k) A's left vectors U
+    ranky_csc At;
+    At.nnz = A->nnz;
+    At.colptr = i32(t.o_ptr);
+    At.rowidx = i32(t.o_trow);
+    At.values = w + t.o_tval;
+    At.dtype = A->dtype;
+    Job j;
+    ranky_opts ot = o;
+    ot.validate = 0;   // A^T is well formed by construction (A was checked, or the caller vouches for it)
+    st = make_job(&At, N, M, k, ot.n_blocks, sigma, V, U, &j);
+    if (st) return finish(st);
+    return finish(run_path(ctx, {j}, tol, ot, w + t.o_path, ws_bytes - t.o_path, inf, s, ot.graph == 1));
 }
 
 }  // extern "C"

@@ -35,7 +35,8 @@ class Csc(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
-                ("n_blocks", "gram_prec", "refine", "max_sweeps", "validate", "v_dtype", "timing", "graph")] + \
+                ("n_blocks", "gram_prec", "refine", "max_sweeps", "validate", "v_dtype", "timing", "graph",
+                 "eigensolver", "max_iters")] + \
                [("block_start", ctypes.c_void_p)]
 
 
@@ -72,6 +73,7 @@ class Info(ctypes.Structure):
                 ("status", "rank", "n_nonempty", "empty_rows", "sweeps", "n_blocks", "lonely_max", "lonely_blocks")]
     _fields_ += [("tau", ctypes.c_double), ("sigma_max", ctypes.c_double), ("ms", ctypes.c_float * 8),
                  ("round_ms", ctypes.c_float), ("round_launches", ctypes.c_int32), ("rr_sweeps", ctypes.c_int32),
+                 ("eig_iters", ctypes.c_int32), ("eig_flops", ctypes.c_double),
                  ("lonely_per_block", ctypes.POINTER(ctypes.c_int32)),
                  ("single_per_block", ctypes.POINTER(ctypes.c_int32))]
 
@@ -137,6 +139,9 @@ def lib():
         "ranky_eigh_workspace_bytes": ([i32], sz),
         "ranky_eigh": ([i32, vp, vp, vp, i32, P(i32), vp, sz, vp], i32),
         "ranky_backproject": ([P(Csc), i32, i64, i32, vp, vp, vp, vp, i32, vp], i32),
+        "ranky_transpose": ([P(Csc), i64, i64, vp, vp, vp, vp, sz, vp], i32),
+        "ranky_tall_workspace_bytes": ([i64, i32, i64, i32, P(Opts)], sz),
+        "ranky_svd_tall": ([vp, P(Csc), i64, i32, i32, dbl, P(Opts), vp, sz, vp, vp, vp, P(Info), vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -229,8 +234,11 @@ def context(device: int = 0) -> Context:
     return _default_ctx[device]
 
 
+EIGENSOLVER = {"auto": 0, "jacobi": 1, "subspace": 2}
+
+
 def make_opts(n_blocks=0, gram_prec="fp64", refine=None, max_sweeps=0, validate=True, v_dtype=torch.float64,
-              timing=False, graph=False, block_start=None) -> Opts:
+              timing=False, graph=False, block_start=None, eigensolver="auto", max_iters=0) -> Opts:
     """block_start: optional D + 1 column boundaries (host; kept alive by the Opts).
     refine=None keeps the library's automatic choice (-1)."""
     o = Opts()
@@ -244,6 +252,8 @@ def make_opts(n_blocks=0, gram_prec="fp64", refine=None, max_sweeps=0, validate=
     o.v_dtype = F64 if v_dtype == torch.float64 else F32
     o.timing = int(timing)
     o.graph = int(graph)
+    o.eigensolver = EIGENSOLVER[eigensolver]
+    o.max_iters = int(max_iters)
     if block_start is not None:
         import numpy as np
 
@@ -286,6 +296,45 @@ def svd(A: DeviceCSC, k: int, tol: float = 0.0, ctx: Context | None = None, out:
     st = lib().ranky_svd(ctx.handle, ctypes.byref(csc), A.M, A.N, k, float(tol), ctypes.byref(opts), _ptr(ws),
                          ws.numel(), _ptr(out.sigma), _ptr(out.U), _ptr(out.V), ctypes.byref(info), _stream(stream))
     _check(st)
+    out.info = info.as_dict()
+    return out
+
+
+def transpose(A: DeviceCSC, stream=None) -> DeviceCSC:
+    """ranky_transpose: the CSC of A^T (N x M) as a new DeviceCSC."""
+    dev = A.colptr.device
+    colptr = torch.empty(A.M + 1, dtype=torch.int32, device=dev)
+    rowidx = torch.empty(max(A.nnz, 1), dtype=torch.int32, device=dev)[:A.nnz]
+    values = torch.empty(max(A.nnz, 1), dtype=A.values.dtype, device=dev)[:A.nnz]
+    nbytes = int(lib().ranky_tall_workspace_bytes(A.M, 1, A.nnz, 1, None))
+    if nbytes == 0:
+        raise RankyError(E_INVALID, "invalid sizes")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    csc = A.struct()
+    _check(lib().ranky_transpose(ctypes.byref(csc), A.M, A.N, _ptr(colptr), _ptr(rowidx), _ptr(values), _ptr(ws),
+                                 nbytes, _stream(stream)))
+    return DeviceCSC(A.N, A.M, colptr, rowidx, values)
+
+
+def svd_tall(A: DeviceCSC, k: int, tol: float = 0.0, ctx: Context | None = None, stream=None,
+             **opt_kw) -> SVDResult:
+    """Top-k singular triplets of a tall-and-skinny A by ranky_svd_tall (U is M x k of v_dtype,
+    V is N x k FP64)."""
+    ctx = ctx or context(A.colptr.device.index or 0)
+    opts = make_opts(**opt_kw)
+    vdt = torch.float64 if opts.v_dtype == F64 else torch.float32
+    dev = A.colptr.device
+    out = SVDResult(torch.empty(k, dtype=torch.float64, device=dev), torch.empty((A.M, k), dtype=vdt, device=dev),
+                    torch.empty((A.N, k), dtype=torch.float64, device=dev), {})
+    nbytes = int(lib().ranky_tall_workspace_bytes(A.M, A.N, A.nnz, k, ctypes.byref(opts)))
+    if nbytes == 0:
+        raise RankyError(E_INVALID, "invalid sizes for the workspace")
+    ws = ctx.workspace(nbytes)
+    info = Info()
+    csc = A.struct()
+    _check(lib().ranky_svd_tall(ctx.handle, ctypes.byref(csc), A.M, A.N, k, float(tol), ctypes.byref(opts), _ptr(ws),
+                                ws.numel(), _ptr(out.sigma), _ptr(out.U), _ptr(out.V), ctypes.byref(info),
+                                _stream(stream)))
     out.info = info.as_dict()
     return out
 

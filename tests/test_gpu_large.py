@@ -71,7 +71,8 @@ def check_against_golden(A, gold, got, k, sig_bar, vec_bar, res_bar, A_csr, At, 
     import torch
 
     info = got.info
-    print("info", {n: info[n] for n in ("status", "rank", "sweeps", "rr_sweeps", "tau", "sigma_max")}, flush=True)
+    print("info", {n: info[n] for n in ("status", "rank", "sweeps", "eig_iters", "rr_sweeps", "tau", "sigma_max")},
+          flush=True)
     assert info["status"] == 0
     assert info["n_nonempty"] == int(gold["n_nonempty"]) == A.M   # rows are emptied inside blocks only
     r = int(gold["rank"])
@@ -108,14 +109,17 @@ def check_against_golden(A, gold, got, k, sig_bar, vec_bar, res_bar, A_csr, At, 
         assert np.all(verr <= vbar)
 
 
-def test_powerlaw_200m_fp64_against_golden(R, case, orc):
-    """The FP64 path (FP64 Gram of the FP32 values, promoted exactly; FP64 eigensolve; FP64 V).  The
+@pytest.mark.parametrize("eigensolver", ["auto", "jacobi"])
+def test_powerlaw_200m_fp64_against_golden(R, case, orc, eigensolver):
+    """The FP64 path (FP64 Gram of the FP32 values, promoted exactly; FP64 V), with the leading
+    eigenpairs by the automatic choice (the subspace iteration here) and by the full Jacobi.  The
     eigen-residual bar is 1e-11: the Gram and the eigensolve each round at about n eps = 4.5e-13."""
     import torch
 
     A, dA, gold, A_csr, At = case
     k, D = A.meta["k"], A.meta["D"]
-    got = R.svd(dA, k, 0.0, n_blocks=D, gram_prec="fp64", v_dtype=torch.float64)
+    got = R.svd(dA, k, 0.0, n_blocks=D, gram_prec="fp64", v_dtype=torch.float64, eigensolver=eigensolver)
+    assert (got.info["eig_iters"] > 0) == (eigensolver == "auto")
     check_against_golden(A, gold, got, k, 1e-10, 1e-12, 1e-11, A_csr, At, orc)
     assert got.info["rr_sweeps"] == 0
     del got
