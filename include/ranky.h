@@ -476,6 +476,29 @@ ranky_status ranky_paper_errors(int32_t M, int32_t k, const double *sigma_hat, c
                                 ranky_stream_t stream);
 
 /* ------------------------------------------------------------------------- */
+/* Without allocation                                                         */
+/* ------------------------------------------------------------------------- */
+
+/* Bytes of the fixed device array ranky_svd_noalloc works in (one per GPU, held by the library
+ * from the first context on that GPU until the process ends). */
+#define RANKY_NOALLOC_WORKSPACE_BYTES ((size_t)64 << 20)
+
+/* ranky_svd without a workspace argument and without any allocation inside the call, for callers
+ * that cannot allocate device or pinned memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  The workspace is the library's fixed device array of
+ * RANKY_NOALLOC_WORKSPACE_BYTES on the context's device; the host staging is the one the context
+ * allocated when it was created.  Everything else -- arguments, outputs, results, bit for bit, and
+ * errors -- is as ranky_svd with the same options, except that opts->graph is ignored (no graph
+ * is captured).  E_NOMEM when ranky_workspace_bytes(M, N, nnz, k, opts) exceeds the array, or when
+ * the context's staging is too small for the problem (it is sized for any single matrix the array
+ * can hold).  All calls on one GPU share its array: calls that overlap on one GPU (from several
+ * threads or on several streams at once) race and must not be issued; consecutive calls are
+ * independent (the path initialises everything it reads).  Blocking. */
+ranky_status ranky_svd_noalloc(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N, int32_t k, double tol,
+                               const ranky_opts *opts, double *sigma, double *U, void *V, ranky_info *info,
+                               ranky_stream_t stream);
+
+/* ------------------------------------------------------------------------- */
 /* Tall and skinny (M >> N)                                                   */
 /* ------------------------------------------------------------------------- */
 

@@ -21,6 +21,7 @@
 
 #include "batch.hpp"
 #include "common.hpp"
+#include "internal.hpp"
 #include "launch.hpp"
 #include "launch_util.hpp"
 
@@ -54,6 +55,7 @@ struct ranky_ctx {
     std::string aerr;
     // per-block lonely and single-entry counts of the last call (ranky_info points here)
     std::vector<int32_t> blk_host;
+    bool no_alloc = false;   // set during ranky_svd_noalloc: the staging must not grow
 };
 
 namespace {
@@ -62,6 +64,7 @@ using namespace ranky;
 
 thread_local char g_err[512] = "";
 constexpr int32_t kDefaultSweeps = 40;
+constexpr size_t kStagingBytes = 1 << 20;   // host staging allocated with a context
 constexpr int32_t kInnerSweeps = 1;
 constexpr int32_t kMaxRefineK = 1024;
 constexpr double kJacobiTolFp32Gram = 1e-8;
@@ -436,6 +439,9 @@ struct Job {
 
 ranky_status ensure_pinned(ranky_ctx *ctx, size_t bytes) {
     if (ctx->pinned_bytes >= bytes) return RANKY_OK;
+    if (ctx->no_alloc)
+        return fail(RANKY_E_NOMEM, "the context's staging holds %zu bytes, %zu needed (no allocation in this call)",
+                    ctx->pinned_bytes, bytes);
     // a call that failed part-way may have left kernels writing sweep state into the old
     // buffer: let them finish before it is freed
     if (ctx->pinned) {
@@ -1549,6 +1555,33 @@ ranky_status check_tall_args(const ranky_csc *A, int64_t M, int32_t N, int32_t k
 
 }  // namespace
 
+namespace ranky {
+
+ranky_status set_error(ranky_status st, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+int ctx_device(const ranky_ctx *ctx) { return ctx ? ctx->device : -1; }
+
+ranky_status svd_fixed_workspace(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64_t N, int32_t k, double tol,
+                                 const ranky_opts *opts, void *workspace, size_t ws_bytes, double *sigma, double *U,
+                                 void *V, ranky_info *info, ranky_stream_t stream) {
+    ranky_opts o;
+    ranky_default_opts(&o);
+    if (opts) o = *opts;
+    o.graph = 0;   // a captured graph is instantiated with allocations of its own
+    ctx->no_alloc = true;
+    const ranky_status st = ranky_svd(ctx, A, M, N, k, tol, &o, workspace, ws_bytes, sigma, U, V, info, stream);
+    ctx->no_alloc = false;
+    return st;
+}
+
+}  // namespace ranky
+
 extern "C" {
 
 const char *ranky_last_error(void) { return g_err; }
@@ -1588,10 +1621,18 @@ ranky_status ranky_ctx_create(int device, ranky_ctx **out) {
             return fail(RANKY_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
         }
     }
-    const hipError_t e = kernel_attributes(device, c->lds_limit);
+    hipError_t e = kernel_attributes(device, c->lds_limit);
+    if (e == hipSuccess) e = noalloc_setup(device);
     if (e != hipSuccess) {
         ranky_ctx_destroy(c);
         return fail(RANKY_E_DEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(e));
+    }
+    // staging sized for a single matrix of any size up front, so that the call that may not
+    // allocate (ranky_svd_noalloc) finds it ready
+    const ranky_status ps = ensure_pinned(c, kStagingBytes);
+    if (ps != RANKY_OK) {
+        ranky_ctx_destroy(c);
+        return ps;
     }
     *out = c;
     return RANKY_OK;

@@ -140,6 +140,7 @@ def lib():
         "ranky_eigh": ([i32, vp, vp, vp, i32, P(i32), vp, sz, vp], i32),
         "ranky_backproject": ([P(Csc), i32, i64, i32, vp, vp, vp, vp, i32, vp], i32),
         "ranky_transpose": ([P(Csc), i64, i64, vp, vp, vp, vp, sz, vp], i32),
+        "ranky_svd_noalloc": ([vp, P(Csc), i32, i64, i32, dbl, P(Opts), vp, vp, vp, P(Info), vp], i32),
         "ranky_tall_workspace_bytes": ([i64, i32, i64, i32, P(Opts)], sz),
         "ranky_svd_tall": ([vp, P(Csc), i64, i32, i32, dbl, P(Opts), vp, sz, vp, vp, vp, P(Info), vp], i32),
     }
@@ -335,6 +336,29 @@ def svd_tall(A: DeviceCSC, k: int, tol: float = 0.0, ctx: Context | None = None,
     _check(lib().ranky_svd_tall(ctx.handle, ctypes.byref(csc), A.M, A.N, k, float(tol), ctypes.byref(opts), _ptr(ws),
                                 ws.numel(), _ptr(out.sigma), _ptr(out.U), _ptr(out.V), ctypes.byref(info),
                                 _stream(stream)))
+    out.info = info.as_dict()
+    return out
+
+
+NOALLOC_WORKSPACE_BYTES = 64 << 20
+
+
+def svd_noalloc(A: DeviceCSC, k: int, tol: float = 0.0, ctx: Context | None = None, out: SVDResult | None = None,
+                stream=None, **opt_kw) -> SVDResult:
+    """ranky_svd_noalloc: the whole path in the library's fixed device array (no workspace)."""
+    ctx = ctx or context(A.colptr.device.index or 0)
+    opts = make_opts(**opt_kw)
+    vdt = torch.float64 if opts.v_dtype == F64 else torch.float32
+    dev = A.colptr.device
+    if out is None:
+        out = SVDResult(torch.empty(k, dtype=torch.float64, device=dev),
+                        torch.empty((A.M, k), dtype=torch.float64, device=dev),
+                        torch.empty((A.N, k), dtype=vdt, device=dev), {})
+    info = Info()
+    csc = A.struct()
+    st = lib().ranky_svd_noalloc(ctx.handle, ctypes.byref(csc), A.M, A.N, k, float(tol), ctypes.byref(opts),
+                                 _ptr(out.sigma), _ptr(out.U), _ptr(out.V), ctypes.byref(info), _stream(stream))
+    _check(st)
     out.info = info.as_dict()
     return out
 
