@@ -421,6 +421,33 @@ ranky_status ranky_backproject(const ranky_csc *A, int32_t M, int64_t N, int32_t
                                ranky_stream_t stream);
 
 /* ------------------------------------------------------------------------- */
+/* Incremental merge: column blocks added over time to a resident Gram         */
+/* ------------------------------------------------------------------------- */
+
+/* The Gram form of the merge is additive over blocks (Eq. 2-3: A A^T = sum_i A^i A^i^T), so the
+ * blocks of a matrix may arrive in any number of steps: each append adds one block's Gram (FP64) to
+ * a resident M x M Gram in the original row order, in the order the blocks arrive, and a solve
+ * returns the leading singular values and left vectors of all columns appended so far.  A solve
+ * starts the subspace iteration (when it applies: opts.eigensolver as for ranky_svd) from the Ritz
+ * vectors of the previous solve, so a solve after a small append takes few iterations.  Rows whose
+ * entries arrive late simply join the non-empty rows.  V is not kept (the blocks are not stored):
+ * V of any block is ranky_backproject(block, U, sigma, rank).  The state lives in the caller's
+ * workspace; one call at a time per state.  max_cols / max_nnz bound one appended block. */
+typedef struct ranky_inc ranky_inc;
+size_t ranky_inc_workspace_bytes(int32_t M, int64_t max_cols, int64_t max_nnz, int32_t k, const ranky_opts *opts);
+ranky_status ranky_inc_create(ranky_ctx *ctx, int32_t M, int32_t k, int64_t max_cols, int64_t max_nnz,
+                              const ranky_opts *opts, void *workspace, size_t ws_bytes, ranky_inc **out,
+                              ranky_stream_t stream);
+/* Adds block^T's Gram: block is an M x cols CSC (the contract of ranky_svd, checked).  Blocking. */
+ranky_status ranky_inc_append(ranky_inc *inc, const ranky_csc *block, int64_t cols, ranky_stream_t stream);
+/* sigma [k], U [M x k] as ranky_svd (rank rule with u_G = 2^-53, sign and empty-row rules) for the
+ * matrix of every block appended so far.  info (host, may be NULL): rank, non-empty rows, sweeps or
+ * eig_iters, n_blocks = blocks appended.  Blocking. */
+ranky_status ranky_inc_solve(ranky_inc *inc, double tol, double *sigma, double *U, ranky_info *info,
+                             ranky_stream_t stream);
+ranky_status ranky_inc_destroy(ranky_inc *inc);
+
+/* ------------------------------------------------------------------------- */
 /* The paper's own procedure (for comparison with the Gram-form path)         */
 /* ------------------------------------------------------------------------- */
 

@@ -869,8 +869,10 @@ struct Topk {
     }
 };
 
+// start (or NULL): a start block (rows x p, ld p) in place of the one built from G's diagonal.
 ranky_status topk_eigensolve(ranky_ctx *ctx, Engine &e, const Plan &plan, char *mat_base, double tol_r,
-                             int32_t max_iters, hipStream_t s, int32_t *iters, double *flops) {
+                             int32_t max_iters, hipStream_t s, int32_t *iters, double *flops,
+                             const double *start = nullptr) {
     *iters = 0;
     MatDesc &x = e.d[0];
     Topk t;
@@ -927,7 +929,10 @@ ranky_status topk_eigensolve(ranky_ctx *ctx, Engine &e, const Plan &plan, char *
     double *R3[3] = {t.blk[0], t.blk[1], t.blk[2]};
     double *T = t.blk[3], *GX = t.blk[4];
     const double *G = x.G;
-    launch_tk_start(G, npad, n, p, rows, R3[1], s);
+    if (start)
+        HIP_TRY(hipMemcpyAsync(R3[1], start, sizeof(double) * (size_t)rows * p, hipMemcpyDeviceToDevice, s));
+    else
+        launch_tk_start(G, npad, n, p, rows, R3[1], s);
     double *Y = R3[0];
     st = t.svqb(R3[1], Y);
     if (st) return st;
@@ -1512,6 +1517,49 @@ PaperPlan paper_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bo
     return pp;
 }
 
+// ---------------------------------------------------------------------------
+// incremental merge: a resident Gram that column blocks are added to
+// ---------------------------------------------------------------------------
+
+struct IncLayout {
+    Plan step, solve;
+    Header hstep, hsolve;
+    int32_t p = 0;
+    size_t o_G = 0, o_step = 0, o_solve = 0, o_keep = 0, o_start = 0, total = 0;
+};
+
+IncLayout inc_layout(int32_t M, int64_t max_cols, int64_t max_nnz, int32_t k, const ranky_opts &o) {
+    IncLayout L;
+    L.p = topk_plan_p(o, 1, M, k);
+    const int32_t D = default_blocks(max_cols);
+    L.hstep = make_header(1, 1, 1);
+    // the largest step plan over the blocks the state takes: the partial Gram rows per entry are
+    // largest just below each doubling of the segment length, so those sizes are tried too
+    L.step = make_plan(M, max_cols, max_nnz, 1, D, false, false, nullptr, true);
+    for (int64_t seg = kGramSegMin; seg <= kGramSeg; seg *= 2) {
+        const int64_t nz = std::min<int64_t>(max_nnz, seg * kGramSegTarget * 2 - 1);
+        const Plan q = make_plan(M, max_cols, nz, 1, D, false, false, nullptr, true);
+        if (q.total > L.step.total) L.step = q;
+    }
+    L.hsolve = make_header(1, 1, jacobi_npad(M) / kJacobiBlock);
+    L.solve = make_plan(M, 1, 0, k, 1, true, false, nullptr, false, false, L.p);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t of = off;
+        off = align_up(off + bytes);
+        return of;
+    };
+    L.o_G = take(sizeof(double) * (size_t)M * M);
+    L.o_step = take(L.hstep.total + L.step.total);
+    L.o_solve = take(L.hsolve.total + L.solve.total);
+    if (L.p > 0) {
+        L.o_keep = take(sizeof(double) * (size_t)M * L.p);
+        L.o_start = take(sizeof(double) * (size_t)L.solve.topk.rows * L.p);
+    }
+    L.total = off;
+    return L;
+}
+
 // Tall-and-skinny layout: the transposed CSC and the scratch of the transpose, ahead of the
 // short-and-fat path's workspace for A^T (values sized for FP64).
 struct TallPlan {
@@ -1554,6 +1602,17 @@ ranky_status check_tall_args(const ranky_csc *A, int64_t M, int32_t N, int32_t k
 }
 
 }  // namespace
+
+struct ranky_inc {
+    ranky_ctx *ctx = nullptr;
+    int32_t M = 0, k = 0;
+    int64_t max_cols = 0, max_nnz = 0;
+    ranky_opts o;
+    IncLayout L;
+    char *ws = nullptr;
+    int64_t blocks = 0, cols = 0, nnz = 0;
+    bool has_prev = false;   // Ritz vectors of an earlier solve are kept for a warm start
+};
 
 namespace ranky {
 
@@ -2069,6 +2128,189 @@ ranky_status ranky_transpose(const ranky_csc *A, int64_t M, int64_t N, int32_t *
                          i32(t.o_nlong), rowidx_t, values_t, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
+    return RANKY_OK;
+}
+
+size_t ranky_inc_workspace_bytes(int32_t M, int64_t max_cols, int64_t max_nnz, int32_t k, const ranky_opts *opts) {
+    if (M < 1 || M > kMaxM || max_cols < 1 || max_nnz < 0 || k < 1 || k > M || max_cols > (int64_t)0x7ffffffe) return 0;
+    const ranky_opts o = resolved(opts, false, k);
+    return inc_layout(M, max_cols, max_nnz, k, o).total;
+}
+
+ranky_status ranky_inc_create(ranky_ctx *ctx, int32_t M, int32_t k, int64_t max_cols, int64_t max_nnz,
+                              const ranky_opts *opts, void *workspace, size_t ws_bytes, ranky_inc **out,
+                              ranky_stream_t stream) {
+    if (!ctx || !out) return fail(RANKY_E_INVALID, "ctx or out is NULL");
+    const ranky_opts o = resolved(opts, false, k);
+    ranky_status st = check_opts(o);
+    if (st) return st;
+    const size_t need = ranky_inc_workspace_bytes(M, max_cols, max_nnz, k, &o);
+    if (need == 0) return fail(RANKY_E_INVALID, "invalid sizes");
+    if (!workspace || ws_bytes < need) return fail(RANKY_E_NOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
+    if (reinterpret_cast<uintptr_t>(workspace) % kWorkspaceAlign)
+        return fail(RANKY_E_INVALID, "workspace is not %d-byte aligned", kWorkspaceAlign);
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(RANKY_E_DEVICE, "hipSetDevice");
+    ranky_inc *inc = new ranky_inc();
+    inc->ctx = ctx;
+    inc->M = M;
+    inc->k = k;
+    inc->max_cols = max_cols;
+    inc->max_nnz = max_nnz;
+    inc->o = o;
+    inc->L = inc_layout(M, max_cols, max_nnz, k, o);
+    inc->ws = static_cast<char *>(workspace);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    launch_fill_f64(reinterpret_cast<double *>(inc->ws + inc->L.o_G), (int64_t)M * M, 0.0, s);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        delete inc;
+        return fail(RANKY_E_DEVICE, "%s", hipGetErrorString(e));
+    }
+    *out = inc;
+    return RANKY_OK;
+}
+
+ranky_status ranky_inc_append(ranky_inc *inc, const ranky_csc *block, int64_t cols, ranky_stream_t stream) {
+    if (!inc) return fail(RANKY_E_INVALID, "inc is NULL");
+    ranky_status st = check_csc_args(block, inc->M, cols);
+    if (st) return st;
+    if (cols > inc->max_cols || block->nnz > inc->max_nnz)
+        return fail(RANKY_E_INVALID, "block of %lld columns / %lld entries beyond the state's %lld / %lld",
+                    (long long)cols, (long long)block->nnz, (long long)inc->max_cols, (long long)inc->max_nnz);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const IncLayout &L = inc->L;
+    StepCtx sc;
+    Engine e;
+    const int32_t D = default_blocks(cols);
+    // the block's own Gram (Eq. 2 summand) on the step region, then added to the resident G in
+    // the order the blocks arrive
+    const Plan p = make_plan(inc->M, cols, block->nnz, 1, D, false, false, nullptr, true);
+    if (L.hstep.total + p.total > L.hstep.total + L.step.total) return fail(RANKY_E_NOMEM, "step region too small");
+    st = step_scan(sc, block, inc->M, cols, D, inc->ws + L.o_step, L.hstep.total + L.step.total, s, e, nullptr,
+                   nullptr, nullptr, nullptr);
+    if (st) return st;
+    MatDesc &x = e.d[0];
+    if (x.n > 0) {
+        x.prec = RANKY_PREC_FP64;
+        x.dwg = 0;
+        x.gwaves = gram_waves(inc->M, 8, sc.c.lds_limit);
+        e.nblk[kPhGram] = fill_wp(e.hwp(kPhGram), 1, [&](int) { return (int64_t)e.gsegs[0] + (x.npad - x.n); });
+        e.nblk[kPhGramRed] = fill_wp(e.hwp(kPhGramRed), 1, [&](int) { return (int64_t)x.n; });
+        st = e.upload_desc();
+        if (!st) st = e.upload(e.h.o_wp, sizeof(int32_t) * (size_t)kPhCount * (e.h.slots + 1));
+        if (st) return st;
+        e.enqueue_transpose();
+        int32_t gram_nw = 1;
+        size_t gram_lds = 0;
+        gram_shape(e.d, sc.c.lds_limit, gram_nw, gram_lds);
+        launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], e.dwp(kPhGramRed), e.nblk[kPhGramRed], 1, gram_nw,
+                    gram_lds, s);
+        launch_scatter_add_gram(x.G, x.npad, x.m2r, inc->M, reinterpret_cast<double *>(inc->ws + L.o_G), s);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    inc->blocks += 1;
+    inc->cols += cols;
+    inc->nnz += block->nnz;
+    return RANKY_OK;
+}
+
+ranky_status ranky_inc_solve(ranky_inc *inc, double tol, double *sigma, double *U, ranky_info *info,
+                             ranky_stream_t stream) {
+    if (!inc) return fail(RANKY_E_INVALID, "inc is NULL");
+    if (!(tol >= 0.0)) return fail(RANKY_E_INVALID, "tol must be >= 0");
+    if (!sigma || !U) return fail(RANKY_E_INVALID, "NULL output");
+    ranky_ctx *ctx = inc->ctx;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(RANKY_E_DEVICE, "hipSetDevice");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const IncLayout &L = inc->L;
+    const int32_t M = inc->M, k = inc->k;
+    char *base = inc->ws + L.o_solve + L.hsolve.total;
+    MatDesc x = carve(L.solve, base, nullptr);
+    const double *Gfull = reinterpret_cast<const double *>(inc->ws + L.o_G);
+    // the rows with an entry so far, and G restricted to them
+    launch_fill_i32(x.scal, kScCount, 0, s);
+    launch_inc_rows(Gfull, M, x.m2r, x.r2m, x.empty, x.scal + kScNonempty, s);
+    ranky_status st = ensure_pinned(ctx, 64);
+    if (st) return st;
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, x.scal + kScNonempty, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int32_t n = *static_cast<int32_t *>(ctx->pinned);
+    x.n = x.n_tau = x.neig = n;
+    x.npad = jacobi_npad(n > 0 ? n : 1);
+    launch_inc_gather(Gfull, M, x.r2m, x.scal + kScNonempty, x.npad, x.G, s);
+    x.M = M;
+    x.k = k;
+    x.D = 0;
+    x.prec = RANKY_PREC_FP64;
+    x.tol = tol;
+    x.u_gram = std::ldexp(1.0, -53);
+    x.jtol = 0.0;
+    x.sigma = sigma;
+    x.U = U;
+    x.V = nullptr;
+    Engine e;
+    st = make_engine(ctx, s, L.hsolve, inc->ws + L.o_solve, 1, e);
+    if (st) return st;
+    e.d.assign(1, x);
+    e.sweeps_cap = inc->o.max_sweeps;
+    e.maxn = n > 0 ? n : 1;
+    st = e.plan_rest();
+    if (st) return st;
+    // the leading pairs: the subspace iteration from the previous solve's Ritz vectors when it
+    // applies (the appended blocks move the leading subspace a little), else the full Jacobi
+    int32_t iters = 0;
+    double flops = 0.0;
+    const int32_t p = L.p;
+    if (p > 0 && n > 0 && (inc->o.eigensolver == 2 ? 2 * p : 8 * p) <= n) {
+        double *start = nullptr;
+        if (inc->has_prev) {
+            start = reinterpret_cast<double *>(inc->ws + L.o_start);
+            launch_inc_start(reinterpret_cast<const double *>(inc->ws + L.o_keep), x.r2m, n, L.solve.topk.rows, p,
+                             start, s);
+        }
+        st = topk_eigensolve(ctx, e, L.solve, base, std::sqrt((double)n) * std::ldexp(1.0, -52),
+                             inc->o.max_iters > 0 ? inc->o.max_iters : kTopkDefaultIters, s, &iters, &flops, start);
+        if (st) return st;
+        if (iters > 0) {
+            launch_inc_keep(e.d[0].W, e.d[0].npad, e.d[0].m2r, M, p, reinterpret_cast<double *>(inc->ws + L.o_keep), s);
+            inc->has_prev = true;
+        } else {
+            st = e.plan_rest();
+            if (st) return st;
+        }
+    }
+    if (iters == 0) {
+        st = e.eigensolve(false);
+        if (st) return st;
+    }
+    launch_select(e.ddesc(), 1, e.maxn, s);
+    launch_gather_u(e.ddesc(), e.dwp(kPhGather), e.nblk[kPhGather], 1, s);
+    HIP_TRY(hipGetLastError());
+    std::vector<int32_t> iv;
+    std::vector<double> fv;
+    st = e.collect(iv, fv);
+    if (st) return st;
+    const bool notconv = iters == 0 && n > 0 && e.notconv[0] != 0;
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->status = notconv ? RANKY_E_NOT_CONVERGED : RANKY_OK;
+        info->rank = iv[2];
+        info->n_nonempty = n;
+        info->empty_rows = M - n;
+        info->sweeps = iters == 0 && n > 0 ? e.sweeps[0] : 0;
+        info->n_blocks = (int32_t)std::min<int64_t>(inc->blocks, 0x7fffffff);
+        info->tau = fv[0];
+        info->sigma_max = fv[1];
+        info->eig_iters = iters;
+        info->eig_flops = flops;
+    }
+    if (notconv) return fail(RANKY_E_NOT_CONVERGED, "Jacobi did not converge in %d sweeps", inc->o.max_sweeps);
+    return RANKY_OK;
+}
+
+ranky_status ranky_inc_destroy(ranky_inc *inc) {
+    delete inc;
     return RANKY_OK;
 }
 

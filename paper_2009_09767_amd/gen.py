@@ -310,6 +310,15 @@ def powerlaw_200m(seed: int | None = None, M=4096, N=1 << 24, D=256, nnz=200_000
                dict(name="powerlaw_200m", D=D, k=k, tol=0.0, zeroed_blocks=dict(zip(blocks.tolist(), zero_sets))))
 
 
+def paper_standin(seed: int | None = None, M=539, N=170_897, nnz_per_col=5.0, s=1.1) -> CSC:
+    """Stand-in for the paper's job-candidate matrix (539 x 170897, 0/1 entries; the data set is not
+    available): power-law row degrees (Zipf(s)) summing to about nnz_per_col * N, uniform columns,
+    every value 1."""
+    rng = rng_for(6, seed)
+    rows, cols, vals = powerlaw_rows(rng, M, N, int(round(nnz_per_col * N)), s, "ones", np.float64)
+    return from_coo(M, N, rows, cols, vals, dict(name="paper_standin", k=10, tol=0.0))
+
+
 # ----------------------------------------------------------------------------
 # Closed-form inputs for the pins (their singular values are known exactly)
 # ----------------------------------------------------------------------------

@@ -89,6 +89,17 @@ class Info(ctypes.Structure):
         return d
 
 
+class PaperInfo(ctypes.Structure):
+    _fields_ = [("added", ctypes.c_int64), ("nnz_repaired", ctypes.c_int64), ("proxy_cols", ctypes.c_int64),
+                ("rank", ctypes.c_int32), ("n_nonempty", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("ms", ctypes.c_float * 4)]
+
+    def as_dict(self):
+        d = {n: getattr(self, n) for n, _ in self._fields_ if n != "ms"}
+        d["ms"] = list(self.ms)
+        return d
+
+
 class TuneReport(ctypes.Structure):
     _fields_ = [("bp_per_cu", ctypes.c_int32), ("jacobi_schedule", ctypes.c_int32),
                 ("bp_candidates", ctypes.c_int32 * 4), ("bp_ms", ctypes.c_float * 4),
@@ -141,6 +152,18 @@ def lib():
         "ranky_backproject": ([P(Csc), i32, i64, i32, vp, vp, vp, vp, i32, vp], i32),
         "ranky_transpose": ([P(Csc), i64, i64, vp, vp, vp, vp, sz, vp], i32),
         "ranky_svd_noalloc": ([vp, P(Csc), i32, i64, i32, dbl, P(Opts), vp, vp, vp, P(Info), vp], i32),
+        "ranky_inc_workspace_bytes": ([i32, i64, i64, i32, P(Opts)], sz),
+        "ranky_inc_create": ([vp, i32, i32, i64, i64, P(Opts), vp, sz, P(vp), vp], i32),
+        "ranky_inc_append": ([vp, P(Csc), i64, vp], i32),
+        "ranky_inc_solve": ([vp, dbl, vp, vp, P(Info), vp], i32),
+        "ranky_inc_destroy": ([vp], i32),
+        "ranky_checker_workspace_bytes": ([i32, i64, i64, i32], sz),
+        "ranky_checker": ([P(Csc), i32, i64, i32, i32, ctypes.c_uint64, vp, vp, vp, i64, P(i64), P(i64), vp, sz, vp],
+                          i32),
+        "ranky_paper_workspace_bytes": ([i32, i64, i64, i32, i32, i32], sz),
+        "ranky_svd_paper": ([vp, P(Csc), i32, i64, i32, i32, i32, ctypes.c_uint64, dbl, vp, sz, vp, vp, P(PaperInfo),
+                             vp], i32),
+        "ranky_paper_errors": ([i32, i32, vp, vp, vp, vp, P(dbl), P(dbl), vp, sz, vp], i32),
         "ranky_tall_workspace_bytes": ([i64, i32, i64, i32, P(Opts)], sz),
         "ranky_svd_tall": ([vp, P(Csc), i64, i32, i32, dbl, P(Opts), vp, sz, vp, vp, vp, P(Info), vp], i32),
     }
@@ -338,6 +361,101 @@ def svd_tall(A: DeviceCSC, k: int, tol: float = 0.0, ctx: Context | None = None,
                                 _stream(stream)))
     out.info = info.as_dict()
     return out
+
+
+class Incremental:
+    """ranky_inc_*: a resident Gram that column blocks of an M-row matrix are appended to; solve()
+    gives the leading sigma and U of everything appended so far."""
+
+    def __init__(self, M: int, k: int, max_cols: int, max_nnz: int, ctx: Context | None = None, device: int = 0,
+                 stream=None, **opt_kw):
+        self.ctx = ctx or context(device)
+        self.M, self.k = M, k
+        self.opts = make_opts(**opt_kw)
+        nbytes = int(lib().ranky_inc_workspace_bytes(M, max_cols, max_nnz, k, ctypes.byref(self.opts)))
+        if nbytes == 0:
+            raise RankyError(E_INVALID, "invalid sizes")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{self.ctx.device}")
+        h = ctypes.c_void_p()
+        _check(lib().ranky_inc_create(self.ctx.handle, M, k, max_cols, max_nnz, ctypes.byref(self.opts),
+                                      _ptr(self.ws), nbytes, ctypes.byref(h), _stream(stream)))
+        self.handle = h
+
+    def append(self, block: DeviceCSC, stream=None):
+        csc = block.struct()
+        _check(lib().ranky_inc_append(self.handle, ctypes.byref(csc), block.N, _stream(stream)))
+
+    def solve(self, tol: float = 0.0, stream=None):
+        dev = self.ws.device
+        sigma = torch.empty(self.k, dtype=torch.float64, device=dev)
+        U = torch.empty((self.M, self.k), dtype=torch.float64, device=dev)
+        info = Info()
+        _check(lib().ranky_inc_solve(self.handle, float(tol), _ptr(sigma), _ptr(U), ctypes.byref(info),
+                                     _stream(stream)))
+        return sigma, U, info.as_dict()
+
+    def close(self):
+        if self.handle:
+            lib().ranky_inc_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+CHECKERS = {"none": -1, "random": 0, "neighbor": 1, "neighbor_random": 2}
+
+
+def checker(A: DeviceCSC, D: int, kind: str, seed: int, stream=None):
+    """ranky_checker: (A' as a DeviceCSC with FP64 values, entries added)."""
+    dev = A.colptr.device
+    cap = A.nnz + 2 * D * A.M
+    colptr = torch.empty(A.N + 1, dtype=torch.int32, device=dev)
+    rowidx = torch.empty(cap, dtype=torch.int32, device=dev)
+    values = torch.empty(cap, dtype=torch.float64, device=dev)
+    nbytes = int(lib().ranky_checker_workspace_bytes(A.M, A.N, A.nnz, D))
+    if nbytes == 0:
+        raise RankyError(E_INVALID, "invalid sizes")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    nz, added = ctypes.c_int64(0), ctypes.c_int64(0)
+    csc = A.struct()
+    _check(lib().ranky_checker(ctypes.byref(csc), A.M, A.N, D, CHECKERS[kind], int(seed), _ptr(colptr), _ptr(rowidx),
+                               _ptr(values), cap, ctypes.byref(nz), ctypes.byref(added), _ptr(ws), nbytes,
+                               _stream(stream)))
+    n = nz.value
+    return DeviceCSC(A.M, A.N, colptr, rowidx[:n], values[:n]), added.value
+
+
+def svd_paper(A: DeviceCSC, k: int, D: int, kind: str = "none", seed: int = 0, tol: float = 0.0,
+              ctx: Context | None = None, stream=None):
+    """ranky_svd_paper: (sigma [k], U [M x k], info dict) by the paper's proxy route."""
+    ctx = ctx or context(A.colptr.device.index or 0)
+    dev = A.colptr.device
+    sigma = torch.empty(k, dtype=torch.float64, device=dev)
+    U = torch.empty((A.M, k), dtype=torch.float64, device=dev)
+    nbytes = int(lib().ranky_paper_workspace_bytes(A.M, A.N, A.nnz, k, D, CHECKERS[kind]))
+    if nbytes == 0:
+        raise RankyError(E_INVALID, "invalid sizes")
+    ws = ctx.workspace(nbytes)
+    info = PaperInfo()
+    csc = A.struct()
+    _check(lib().ranky_svd_paper(ctx.handle, ctypes.byref(csc), A.M, A.N, k, D, CHECKERS[kind], int(seed), float(tol),
+                                 _ptr(ws), ws.numel(), _ptr(sigma), _ptr(U), ctypes.byref(info), _stream(stream)))
+    return sigma, U, info.as_dict()
+
+
+def paper_errors(sigma_hat, U_hat, sigma, U, stream=None):
+    """ranky_paper_errors: (e_sigma, e_u) of Sec. IV over the k columns of U_hat."""
+    M, k = U_hat.shape
+    ws = torch.empty(k + 2, dtype=torch.float64, device=U_hat.device)
+    es, eu = ctypes.c_double(0), ctypes.c_double(0)
+    _check(lib().ranky_paper_errors(M, k, _ptr(sigma_hat.contiguous()), _ptr(U_hat.contiguous()),
+                                    _ptr(sigma.contiguous()), _ptr(U.contiguous()), ctypes.byref(es),
+                                    ctypes.byref(eu), _ptr(ws), 8 * (k + 2), _stream(stream)))
+    return es.value, eu.value
 
 
 NOALLOC_WORKSPACE_BYTES = 64 << 20

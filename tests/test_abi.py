@@ -106,7 +106,7 @@ def test_struct_layouts_match_the_binding(tmp_path):
     structs = {"ranky_csc": ranky.Csc, "ranky_opts": ranky.Opts, "ranky_info": ranky.Info,
                "ranky_batch_item": ranky.BatchItem, "ranky_serve_cfg": ranky.ServeCfg,
                "ranky_request": ranky.Request, "ranky_serve_summary": ranky.ServeStats,
-               "ranky_tune_report": ranky.TuneReport}
+               "ranky_tune_report": ranky.TuneReport, "ranky_paper_info": ranky.PaperInfo}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ranky.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
