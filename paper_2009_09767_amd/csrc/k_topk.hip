@@ -5,8 +5,10 @@
 // eigenpairs of G = P P^T.  A block of p > k vectors is
 //   - filtered by a Chebyshev polynomial of G that stays small on [0, theta_p] (the unwanted
 //     part of the spectrum, theta_p the smallest Ritz value of the block) and grows fast above;
-//   - orthonormalised twice by SVQB: S = Y^T Y, D = diag(S)^1/2, D^-1 S D^-1 = V L V^T,
-//     Y <- Y D^-1 V L^-1/2;
+//   - orthonormalised: blocks up to 192 wide by three Cholesky-QR passes in one workgroup
+//     each (S = Y^T Y, D = diag(S)^1/2, D^-1 S D^-1 (+ a small shift on the first pass)
+//     = L L^T, Y <- Y D^-1 L^-T), wider ones twice by SVQB (D^-1 S D^-1 = V L V^T,
+//     Y <- Y D^-1 V L^-1/2);
 //   - projected (Rayleigh-Ritz): H = Y^T G Y = Q Theta Q^T, X = Y Q, with the residuals
 //     ||G x_i - theta_i x_i|| of the Ritz pairs read back to decide convergence.
 // The p x p eigenproblems run on the blocked Jacobi of k_jacobi.hip; the products here are
@@ -235,6 +237,109 @@ __global__ __launch_bounds__(1024) void k_tk_svqb_w(const double *__restrict__ V
     }
 }
 
+// Cholesky-QR transform of one workgroup: for S = Y^T Y (p x p, ld p, p = 32 PB) with
+// d_i = S_ii^-1/2, S' = diag(d) S diag(d) + shift I = L L^T, write Wm = diag(d) L^-T (upper
+// triangular), so that Y Wm has the span of Y and, without shift, orthonormal columns.
+//
+// L and L^-T come out of one elimination: right-looking Cholesky of the stacked matrix
+// [S'; I] (2p x p) turns the lower block into I L^-T.  Column l of the stack has p + 1 live
+// entries, the rows 0..l of the lower block (L^-T is upper triangular) and the rows l..p-1
+// of the upper block, so it is kept as one virtual column of p + 1 rows: v <= l is row v
+// of the lower block, v > l row v - 1 of the upper.  Both blocks of column j then sit at the
+// same virtual rows as in any later column, and step j updates column l > j at v <= j and
+// v > l.  The (p + 1) x p virtual matrix lives in registers, 32 x 32 threads owning the
+// rows v = r (mod 32) and columns l = c (mod 32); step j's column is finished by the 32
+// lanes owning it and passed to all through LDS (two buffers, one barrier per step).
+// A non-positive or non-finite pivot (or diagonal of S) sets *fail and writes Wm = I.
+template <int PB>
+__global__ __launch_bounds__(1024) void k_tk_chol(const double *__restrict__ S_, double shift,
+                                                  double *__restrict__ Wm_, int32_t *fail) {
+    constexpr int p = 32 * PB, VB = PB + 1;
+    __shared__ double sc[p];
+    __shared__ double col[2][p + 1];
+    __shared__ int bad;
+    const auto S = gmem(S_);
+    const int t = threadIdx.x, c = t >> 5, r = t & 31;
+    if (t == 0) bad = 0;
+    if (t < p) {
+        const double d = S[(int64_t)t * p + t];
+        const bool ok = d > 0.0 && d < __builtin_huge_val();
+        sc[t] = ok ? 1.0 / sqrt(d) : 0.0;
+        if (!ok) bad = 1;
+    }
+    __syncthreads();
+    double a[VB][PB];
+#pragma unroll
+    for (int vb = 0; vb < VB; ++vb) {
+#pragma unroll
+        for (int lb = 0; lb < PB; ++lb) {
+            const int v = r + 32 * vb, l = c + 32 * lb;
+            double x = 0.0;
+            if (v <= l) {
+                x = v == l ? 1.0 : 0.0;
+            } else if (v <= p) {
+                const int i = v - 1;
+                x = 0.5 * (S[(int64_t)i * p + l] + S[(int64_t)l * p + i]) * sc[i] * sc[l];
+                if (i == l) x += shift;
+            }
+            a[vb][lb] = x;
+        }
+    }
+    const int half = (c & 1) * 32;   // this thread's half of its wave
+#pragma unroll
+    for (int lb = 0; lb < PB; ++lb) {
+        for (int jj = 0; jj < 32; ++jj) {
+            const int j = 32 * lb + jj, slot = j & 1;
+            if (c == jj) {
+                // the pivot sits at virtual row j + 1 of column j
+                double pv = jj == 31 ? a[lb + 1][lb] : a[lb][lb];
+                pv = __shfl(pv, half + ((jj + 1) & 31), 64);
+                if (!(pv > 0.0 && pv < __builtin_huge_val())) {
+                    bad = 1;
+                    pv = 1.0;
+                }
+                const double piv = sqrt(pv), inv = 1.0 / piv;
+#pragma unroll
+                for (int vb = 0; vb < VB; ++vb) {
+                    const int v = r + 32 * vb;
+                    const double x = v == j + 1 ? piv : a[vb][lb] * inv;
+                    a[vb][lb] = x;
+                    if (v <= p) col[slot][v] = x;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int lc = 0; lc < PB; ++lc) {
+                const int l = c + 32 * lc;
+                if (l > j) {
+                    const double llj = col[slot][l + 1];
+#pragma unroll
+                    for (int vb = 0; vb < VB; ++vb) {
+                        const int v = r + 32 * vb;
+                        if (v <= p && (v <= j || v > l)) a[vb][lc] = fma(-col[slot][v], llj, a[vb][lc]);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const bool failed = bad != 0;
+    const auto Wm = gmem(Wm_);
+#pragma unroll
+    for (int vb = 0; vb < VB; ++vb) {
+#pragma unroll
+        for (int lb = 0; lb < PB; ++lb) {
+            const int v = r + 32 * vb, l = c + 32 * lb;
+            if (v < p) {
+                double x = v <= l ? a[vb][lb] * sc[v] : 0.0;
+                if (failed) x = v == l ? 1.0 : 0.0;
+                Wm[(int64_t)v * p + l] = x;
+            }
+        }
+    }
+    if (t == 0 && failed) *fail = 1;
+}
+
 // Ritz rotation in descending order: Qs[:, j] = V[:, perm[j]], theta[j] = lam[perm[j]].
 __global__ __launch_bounds__(256) void k_tk_permute(const double *__restrict__ V_, const double *__restrict__ lam_,
                                                     const int32_t *__restrict__ perm_, int32_t p,
@@ -327,6 +432,15 @@ void launch_tk_symcopy(const double *src, int32_t p, double *dst, double *dvec, 
 
 void launch_tk_svqb_w(const double *V, const double *lam, const double *dvec, int32_t p, double *Wm, hipStream_t s) {
     hipLaunchKernelGGL(k_tk_svqb_w, dim3(1), dim3(1024), 0, s, V, lam, dvec, p, Wm);
+}
+
+void launch_tk_chol(const double *S, int32_t p, double shift, double *Wm, int32_t *fail, hipStream_t s) {
+    switch (p) {
+    case 64: hipLaunchKernelGGL(k_tk_chol<2>, dim3(1), dim3(1024), 0, s, S, shift, Wm, fail); break;
+    case 128: hipLaunchKernelGGL(k_tk_chol<4>, dim3(1), dim3(1024), 0, s, S, shift, Wm, fail); break;
+    case 192: hipLaunchKernelGGL(k_tk_chol<6>, dim3(1), dim3(1024), 0, s, S, shift, Wm, fail); break;
+    default: break;
+    }
 }
 
 void launch_tk_permute(const double *V, const double *lam, const int32_t *perm, int32_t p, double *Qs, double *theta,

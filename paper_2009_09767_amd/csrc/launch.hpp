@@ -44,7 +44,10 @@ int64_t gram_part_slots(int64_t nnz);   // partial Gram rows the workspace must 
 void launch_gram(const MatDesc *descs, const int32_t *wp, int64_t nblocks, const int32_t *wp_red, int64_t nblocks_red,
                  int count, int32_t max_waves, size_t lds_bytes, hipStream_t s);
 hipError_t gram_set_attributes(size_t lds_limit);
-int32_t gram_dense_wgs(int64_t N);   // workgroups of the split-bf16 dense-row tiles (a function of N)
+int32_t gram_dense_wgs(int64_t N);
+int32_t gram_heavy_wgs(int64_t N);   // workgroups of the heavy-row tiles (a function of N)
+void launch_gram_heavy_build(const MatDesc *descs, int32_t dtype, int64_t N, hipStream_t s);
+void launch_gram_heavy_tiles(const MatDesc *descs, int32_t dtype, int32_t hwg, hipStream_t s);   // workgroups of the split-bf16 dense-row tiles (a function of N)
 void launch_gram_dense(const MatDesc *descs, int32_t dwg, hipStream_t s);   // BF16X3 dense tiles
 void launch_gram_dense_reduce(const MatDesc *descs, int32_t dwg, hipStream_t s);
 
@@ -96,6 +99,7 @@ void launch_rr_apply(const double *U0, const double *Q, int64_t ldq, const int32
 // Leading eigenpairs by Chebyshev-filtered subspace iteration (k_topk.hip).  Block matrices are
 // rows x p row-major (ld p); rows and p are multiples of 64.
 constexpr int32_t kTopkTile = 64;
+constexpr int32_t kTopkCholMax = 192;   // widest block the one-workgroup Cholesky-QR takes
 // part[z] = op(A) B over the z-th k range of klen (k ranges past K empty); then
 // launch_tk_combine adds the splits in order: out = alpha sum + beta E + gamma F
 void launch_tk_gemm(bool trans_a, const double *A, int64_t lda, const double *B, int64_t ldb, double *part,
@@ -105,6 +109,8 @@ void launch_tk_combine(const double *part, int32_t splits, int64_t count, double
                        double gamma, const double *F, double *out, hipStream_t s);
 void launch_tk_start(const double *G, int64_t ldg, int32_t n, int32_t p, int32_t rows, double *X, hipStream_t s);
 void launch_tk_symcopy(const double *src, int32_t p, double *dst, double *dvec, hipStream_t s);
+// p in {64, 128, 192}; other p launch nothing (the caller checks kTopkCholMax).
+void launch_tk_chol(const double *S, int32_t p, double shift, double *Wm, int32_t *fail, hipStream_t s);
 void launch_tk_svqb_w(const double *V, const double *lam, const double *dvec, int32_t p, double *Wm, hipStream_t s);
 void launch_tk_permute(const double *V, const double *lam, const int32_t *perm, int32_t p, double *Qs, double *theta,
                        hipStream_t s);

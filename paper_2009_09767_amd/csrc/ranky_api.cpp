@@ -820,7 +820,7 @@ int32_t topk_plan_p(const ranky_opts &o, int count, int32_t M, int32_t k) {
 }
 
 // The subspace iteration on the main matrix of engine e (a batch of one): Chebyshev filter,
-// two SVQB passes, Rayleigh-Ritz, until the k leading Ritz pairs have residuals at most
+// orthonormalisation (Cholesky-QR, or SVQB for wide blocks), Rayleigh-Ritz, until the k leading Ritz pairs have residuals at most
 // tol_r theta_1 (or stop improving at the rounding level).  On success the Ritz values are in
 // lam[0, p) (descending), the Ritz vectors in W's first p columns, neig = p, and *iters
 // holds the iterations; *iters = 0 when it did not converge (the caller runs the Jacobi).
@@ -833,6 +833,7 @@ struct Topk {
     Engine es;                // the p x p Jacobi
     double *blk[5];
     double *part, *Sp, *Wm, *Qs, *theta, *dvec;
+    int32_t *cflag = nullptr;   // set by a failed Cholesky-QR (host-visible)
     int32_t n = 0;           // rows of G (the products' useful rows)
     double flops = 0.0;      // algorithmic flops of the products: 2 (useful rows) x cols x (useful k)
 
@@ -855,6 +856,32 @@ struct Topk {
         if (st) return st;
         if (es.notconv[0]) return fail(RANKY_E_NOT_CONVERGED, "Jacobi on a %d x %d block did not converge", L.p, L.p);
         return RANKY_OK;
+    }
+    // one Cholesky-QR pass: S = Y^T Y, out = Y diag(S)^-1/2 L^-T (a failed factorisation sets
+    // *cflag and leaves out = Y)
+    void cholqr(const double *Y, double *out, double shift) {
+        const int32_t p = L.p;
+        gemm(true, Y, p, Y, p, Sp, p, p, L.rows, L.rows, L.rows, 1.0);
+        launch_tk_chol(Sp, p, shift, Wm, cflag, s);
+        gemm(false, Y, p, Wm, p, out, L.rows, p, p, L.rows, p, 1.0);
+    }
+    // out = an orthonormal basis of span(Y) (tmp: scratch of the same shape).  Blocks up to
+    // kTopkCholMax wide: three Cholesky-QR passes, the first shifted so that it cannot break
+    // down on an ill-conditioned block (its triangular factor keeps every column's direction
+    // close to its own, so the Rayleigh-Ritz matrix that follows stays near diagonal); wider
+    // blocks: two SVQB passes.
+    ranky_status orth(const double *Y, double *out, double *tmp) {
+        const int32_t p = L.p;
+        if (p <= kTopkCholMax) {
+            const double shift = 11.0 * ((double)n * p + (double)p * (p + 1)) * std::ldexp(1.0, -53) * p;
+            cholqr(Y, out, shift);
+            cholqr(out, tmp, 0.0);
+            cholqr(tmp, out, 0.0);
+            return RANKY_OK;
+        }
+        const ranky_status st = svqb(Y, tmp);
+        if (st) return st;
+        return svqb(tmp, out);
     }
     // Y (orthonormal afterwards) <- Y D^-1 V L^-1/2, written to out
     ranky_status svqb(const double *Y, double *out) {
@@ -895,7 +922,7 @@ ranky_status topk_eigensolve(ranky_ctx *ctx, Engine &e, const Plan &plan, char *
     // staging is sized first, so that no later growth drops what the small engine stages there.
     const Header hs = make_header(1, 1, p / kJacobiBlock);
     const size_t rb_off = align_up(std::max(hs.total, e.h.total));
-    ranky_status st = ensure_pinned(ctx, rb_off + sizeof(double) * 2 * (size_t)p);
+    ranky_status st = ensure_pinned(ctx, rb_off + sizeof(double) * 2 * (size_t)p + sizeof(int32_t));
     if (st) return st;
     st = make_engine(ctx, s, hs, t.base + t.L.o_hdr, 1, t.es);
     if (st) return st;
@@ -923,6 +950,10 @@ ranky_status topk_eigensolve(ranky_ctx *ctx, Engine &e, const Plan &plan, char *
 
     double *rb_dev = reinterpret_cast<double *>(static_cast<char *>(ctx->pinned_dev) + rb_off);
     const double *rb_host = reinterpret_cast<const double *>(static_cast<const char *>(ctx->pinned) + rb_off);
+    const size_t flag_off = rb_off + sizeof(double) * 2 * (size_t)p;
+    t.cflag = reinterpret_cast<int32_t *>(static_cast<char *>(ctx->pinned_dev) + flag_off);
+    volatile int32_t *cflag_host = reinterpret_cast<volatile int32_t *>(static_cast<char *>(ctx->pinned) + flag_off);
+    *cflag_host = 0;
 
     // three rotating block buffers (the basis Y, the Ritz vectors X, the filter's third term)
     // plus T = G Y and G X
@@ -934,7 +965,7 @@ ranky_status topk_eigensolve(ranky_ctx *ctx, Engine &e, const Plan &plan, char *
     else
         launch_tk_start(G, npad, n, p, rows, R3[1], s);
     double *Y = R3[0];
-    st = t.svqb(R3[1], Y);
+    st = t.orth(R3[1], Y, R3[2]);
     if (st) return st;
     double prev_res = 1e300;
     bool done = false;
@@ -955,6 +986,7 @@ ranky_status topk_eigensolve(ranky_ctx *ctx, Engine &e, const Plan &plan, char *
         launch_tk_resid(GX, X, t.theta, n, p, rb_dev, s);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipStreamSynchronize(s));
+        if (*cflag_host) return RANKY_OK;   // a Cholesky-QR broke down: the full Jacobi takes over
         const double th0 = rb_host[0];
         double worst = 0.0;
         for (int32_t i = 0; i < k; ++i) worst = std::max(worst, rb_host[p + i]);
@@ -970,7 +1002,7 @@ ranky_status topk_eigensolve(ranky_ctx *ctx, Engine &e, const Plan &plan, char *
         prev_res = worst;
         // Chebyshev filter of X damping [0, b], b = the smallest Ritz value, scaled at theta_1;
         // the degree keeps the growth of the leading direction below 1e7 so that the block
-        // stays well conditioned for the SVQB
+        // stays well conditioned for the orthonormalisation
         const double b = std::max(rb_host[p - 1], th0 * 1e-12);
         const double c = 0.5 * b, ew = 0.5 * b;
         const double x0 = (th0 - c) / ew;
@@ -997,10 +1029,8 @@ ranky_status topk_eigensolve(ranky_ctx *ctx, Engine &e, const Plan &plan, char *
             spare = np_;
             sig = sig2;
         }
-        // two SVQB passes: the filtered block into spare, then back into a free buffer as Y
-        st = t.svqb(cur, spare);
-        if (st) return st;
-        st = t.svqb(spare, prev);
+        // orthonormalise the filtered block into a free buffer as the next Y
+        st = t.orth(cur, prev, spare);
         if (st) return st;
         Y = prev;
     }
