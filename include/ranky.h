@@ -109,6 +109,13 @@ typedef struct {
                            iteration that has not converged after max_iters falls back to the full
                            Jacobi; ranky_info.eig_iters tells which ran. */
     int32_t max_iters;  /* cap on the subspace iterations (0 = 60) */
+    int32_t gram_split; /* heavy-row split of the Gram (Eq. 2 summed in three parts: the densest
+                           rows' block on the FP64 matrix cores, their pairs with the other rows
+                           from one gathered row per nonzero, the other pairs in the sparse walk):
+                           0 = automatic (the default: a single matrix of at least 2^22 nonzeros
+                           with an FP64 or FP32 Gram), 1 = off, 2 = on for a single matrix with an
+                           FP64 or FP32 Gram.  Changes the order of the sums (not the result beyond
+                           rounding); costs N x 32 x 8 bytes of workspace. */
     const int64_t *block_start; /* host, optional: D + 1 column boundaries, block b = columns
                            [block_start[b], block_start[b+1]); block_start[0] = 0, non-decreasing,
                            block_start[D] = N, with n_blocks = D >= 1 given (E_INVALID otherwise).
@@ -146,6 +153,9 @@ typedef struct {
      * ranky_serve_destroy. */
     const int32_t *lonely_per_block;
     const int32_t *single_per_block;
+    int32_t topk_block;    /* block width p of the subspace iteration (0 when the full Jacobi ran) */
+    int32_t heavy_rows;    /* dense rows the Gram took out of the sparse walk (opts.gram_split;
+                              0 when the split was off or found no dense row) */
 } ranky_info;
 
 typedef struct ranky_ctx ranky_ctx;

@@ -43,6 +43,14 @@ struct MatDesc {
     double *gpart;            // [slots][npad] partial Gram rows of the cut rows
     double *dpart;            // [dwg][kDenseRows^2] partial dense-row Gram tiles
     int32_t *dense;           // [kDenseRows] the densest rows (original index, by degree), -1 when unused
+    // heavy-row split of the Gram (hwg > 0): the dense rows leave the sparse walk; their
+    // values per column go to aht (N x kDenseRows, the matrix's value type, zeros elsewhere),
+    // their block of G comes from FP64 matrix-core tiles over column ranges (hpart, one
+    // kDenseRows^2 tile per workgroup) and their pairs with the other rows from rows of aht
+    void *aht;
+    double *hpart;
+    int32_t hwg;              // heavy-tile workgroups (0: off)
+    int32_t hpad;
     // launch-shape knobs (results do not depend on them; set from the context's tuning cache)
     int32_t bp_per_cu;        // back-projection workgroups per compute unit
     int32_t jsched;           // Jacobi round launch: bit 0 update tiles grouped per XCD, bit 1 one round workgroup per CU

@@ -47,13 +47,14 @@ inline int32_t gram_seg_len(int64_t nnz) {
 constexpr int kDenseRows = 32;
 // Column entries each lane of the Gram walk loads ahead (one group of gathers in flight).
 constexpr int kGramStep = 4;
+constexpr int kHlUnroll = 8;   // heavy split: rows of aht gathered per lane before the sums
 // Column entries the occupancy scan loads per step.
 constexpr int kOccGroup = 8;
 // Free value of a Gram election tag (above every workgroup-wide lane id).
 constexpr int32_t kTagFree = 0x7fffffff;
 // Ints per matrix in the per-matrix read-back (status, M', rank, sweeps, not-converged,
 // lonely max, lonely blocks, active, Gram segments, Gram partial rows).
-constexpr int kColI = 10;
+constexpr int kColI = 11;
 enum : int32_t { kSdTau = 0, kSdSigmaMax = 1, kSdFloor = 2, kSdScale = 3, kSdCount = 8 };
 
 // Column range of chunk c: block b = c / cpb owns columns [floor(bN/D), floor((b+1)N/D)),

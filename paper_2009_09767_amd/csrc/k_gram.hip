@@ -65,8 +65,9 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const bool walker = wave < nw;
-    if (i >= n) {  // padding row and column of the Jacobi layout
-        for (int32_t j = i + threadIdx.x; j < npad; j += blockDim.x) {
+    if (i >= n) {  // padding row and column of the Jacobi layout (all of them: with the heavy
+                   // split no dense row's workgroup writes its part of them)
+        for (int32_t j = threadIdx.x; j < npad; j += blockDim.x) {
             G[(int64_t)i * ld + j] = 0.0;
             G[(int64_t)j * ld + i] = 0.0;
         }
@@ -89,8 +90,13 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
     __syncthreads();
 
     const int32_t p = r2m[i];
-    // with dense tiles on, a dense row's pairs with other dense rows are theirs
-    const bool skip_dense = dsc.dwg > 0 && dmap[p] >= 0;
+    // heavy split: a dense row's entries of G come from the heavy tiles and from the other
+    // rows' gathers, so its workgroups have nothing to do
+    const bool heavy = dsc.hwg > 0;
+    if (heavy && dmap[p] >= 0) return;
+    // with dense tiles on, a dense row's pairs with other dense rows are theirs; with the
+    // heavy split every pair with a dense row comes from the gathers below
+    const bool skip_dense = heavy || (dsc.dwg > 0 && dmap[p] >= 0);
     const int32_t r_begin = rowptr[p], r_end = rowptr[p + 1];
     const int32_t gs = dsc.gseg;
     const int32_t e_begin = r_begin + seg * gs;
@@ -161,10 +167,44 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
         kk = kk_next;
         kend = kend_next;
     }
+    if (heavy && walker) {
+        // pairs with the dense rows: sum_j a_pj aht[j][h] over this wave's run, the two halves
+        // of the wave taking alternate nonzeros (lane h + 32 half the sum of dense row h),
+        // kHlUnroll row gathers of aht in flight per lane
+        const auto aht = gmem(static_cast<const TV *>(dsc.aht));
+        const auto csr_col = gmem(dsc.csrcol);
+        const int half = lane >> 5, h = lane & 31;
+        double hs = 0.0;
+        for (int32_t base = wb; base < we; base += 64) {
+            const int32_t e = base + lane < we ? base + lane : we - 1;
+            const int32_t jl = csr_col[e];
+            const double al = base + lane < we ? static_cast<double>(vals[csr_k[e]]) : 0.0;
+            const int cnt = we - base < 64 ? we - base : 64;
+            for (int u = 0; u < cnt; u += 2 * kHlUnroll) {
+                double xs[kHlUnroll], as[kHlUnroll];
+#pragma unroll
+                for (int v = 0; v < kHlUnroll; ++v) {
+                    const int src = u + 2 * v + half;
+                    const int sl = src < 64 ? src : 63;
+                    const int32_t j = __shfl(jl, sl, 64);
+                    const double a = __shfl(al, sl, 64);
+                    as[v] = src < cnt ? a : 0.0;
+                    xs[v] = static_cast<double>(aht[(int64_t)j * kDenseRows + h]);
+                }
+#pragma unroll
+                for (int v = 0; v < kHlUnroll; ++v) hs = fma(as[v], xs[v], hs);
+            }
+        }
+        const double other = __shfl(hs, h + 32, 64);
+        if (lane < 32) {
+            const int32_t q = dense[h];
+            if (q >= 0) my[q] = static_cast<Acc>(hs + other);
+        }
+    }
     dg = wave_sum(dg);
     if (lane == 0) dsum[wave] = dg;
     // the dense rows: lane-private sums reduced over the lanes into the wave's row
-    for (int t = 0; walker && t < kDenseRows; ++t) {
+    for (int t = 0; walker && !heavy && t < kDenseRows; ++t) {
         const int32_t q = dense[t];
         if (q < 0) break;
         const Acc v = wave_sum(myslot[t * 64]);
@@ -188,6 +228,17 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
             for (int w = 0; w < nw; ++w) d += static_cast<double>(dsum[w]);
             G[(int64_t)i * ld + i] = d;
         }
+        // heavy split: the dense rows before row i (the loop above wrote those after it)
+        if (heavy && threadIdx.x < kDenseRows) {
+            const int32_t q = dense[threadIdx.x];
+            const int32_t jc = q >= 0 ? gmem(dsc.m2r)[q] : -1;
+            if (jc >= 0 && jc < i) {
+                double v = 0.0;
+                for (int w = 0; w < nw; ++w) v += static_cast<double>(acc[(size_t)w * M + q]);
+                G[(int64_t)i * ld + jc] = v;
+                G[(int64_t)jc * ld + i] = v;
+            }
+        }
         return;
     }
     // partial row of this segment: entry j >= i (the diagonal at j = i)
@@ -202,6 +253,15 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
         double d = 0.0;
         for (int w = 0; w < nw; ++w) d += static_cast<double>(dsum[w]);
         part[i] = d;
+    }
+    if (heavy && threadIdx.x < kDenseRows) {
+        const int32_t q = dense[threadIdx.x];
+        const int32_t jc = q >= 0 ? gmem(dsc.m2r)[q] : -1;
+        if (jc >= 0 && jc < i) {
+            double v = 0.0;
+            for (int w = 0; w < nw; ++w) v += static_cast<double>(acc[(size_t)w * M + q]);
+            part[jc] = v;
+        }
     }
 }
 
@@ -251,9 +311,25 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const MatDesc *__restrict__
     if (i >= d.n) return;
     const int32_t nseg = gmem(d.gsegp)[i + 1] - gmem(d.gsegp)[i];
     if (nseg <= 1) return;
+    const bool heavy = d.hwg > 0;
+    if (heavy) {   // a dense row's entries come from the heavy tiles and the other rows
+        const int32_t p = gmem(d.r2m)[i];
+        for (int t = 0; t < kDenseRows; ++t)
+            if (gmem(d.dense)[t] == p) return;
+    }
     const int64_t ld = d.npad;
     const auto part = gmem(d.gpart) + (int64_t)gmem(d.gslot)[i] * ld;
     const auto G = gmem(d.G);
+    if (heavy && threadIdx.x < kDenseRows) {   // the dense rows before row i
+        const int32_t q = gmem(d.dense)[threadIdx.x];
+        const int32_t jc = q >= 0 ? gmem(d.m2r)[q] : -1;
+        if (jc >= 0 && jc < i) {
+            double v = 0.0;
+            for (int32_t s = 0; s < nseg; ++s) v += part[(int64_t)s * ld + jc];
+            G[(int64_t)i * ld + jc] = v;
+            G[(int64_t)jc * ld + i] = v;
+        }
+    }
     for (int32_t j = i + threadIdx.x; j < d.n; j += blockDim.x) {
         double v = 0.0;
         for (int32_t s = 0; s < nseg; ++s) v += part[(int64_t)s * ld + j];
@@ -375,6 +451,148 @@ __global__ __launch_bounds__(1024) void k_gram_dense_reduce(const MatDesc *__res
     const auto G = gmem(d.G);
     G[i1 * d.npad + i2] = v;
     G[i2 * d.npad + i1] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Heavy-row split of the Gram (FP64 and FP32 accumulation, large single matrices).
+//
+// The densest rows H (the scan's dense list) hold most nonzeros of a power-law matrix and
+// meet in most columns: in the sparse walk they make most of the pairs and most of the
+// election collisions.  With the split they leave the walk:
+//   - k_gram_heavy_build writes aht[j][h] = a_{H[h], j} (zeros elsewhere), one row of
+//     kDenseRows values per column, in the matrix's value type (exact);
+//   - G_HH = sum_j aht[j] aht[j]^T on the FP64 matrix cores (k_gram_heavy_tiles): each
+//     workgroup owns a fixed column range (a function of N alone), its four waves a fixed
+//     quarter of it, summed in wave order into one partial tile per workgroup, which
+//     k_gram_heavy_reduce adds in workgroup order;
+//   - every other row p adds sum_j a_pj aht[j] (one coalesced row per nonzero) in the walk
+//     kernel, and its walk skips the dense rows.
+// Every sum keeps an order fixed by the matrix alone, so the result is bitwise
+// reproducible and independent of D.
+
+// Thread per column j (grid-stride): the row of aht is cleared, then the column's dense
+// entries are written into it (the same thread, so program order keeps the values).
+template <typename TV>
+__global__ __launch_bounds__(256) void k_gram_heavy_build(const MatDesc *__restrict__ descs) {
+    __shared__ int8_t dmap[kMaxM];
+    const MatDesc &d = descs[0];
+    const auto dense = gmem(d.dense);
+    if (dense[0] < 0) return;   // no dense row: aht is never read
+    for (int32_t m = threadIdx.x; m < d.M; m += blockDim.x) dmap[m] = -1;
+    __syncthreads();
+    if (threadIdx.x < kDenseRows && dense[threadIdx.x] >= 0) dmap[dense[threadIdx.x]] = (int8_t)threadIdx.x;
+    __syncthreads();
+    const auto colptr = gmem(d.colptr);
+    const auto rowidx = gmem(d.rowidx);
+    const auto vals = gmem(static_cast<const TV *>(d.values));
+    const auto aht = gmem(static_cast<TV *>(d.aht));
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < d.N; j += (int64_t)gridDim.x * blockDim.x) {
+        auto row = aht + j * kDenseRows;
+#pragma unroll
+        for (int h = 0; h < kDenseRows; ++h) row[h] = TV(0);
+        const int32_t e1 = colptr[j + 1];
+        for (int32_t e = colptr[j]; e < e1; ++e) {
+            const int h = dmap[rowidx[e]];
+            if (h >= 0) row[h] = vals[e];
+        }
+    }
+}
+
+// G_HH partial tile of workgroup b over columns [N b / hwg, N (b + 1) / hwg).  The 32 x 32
+// tile is the 16 x 16 blocks (0,0), (0,1), (1,1) (the upper triangle); every wave runs all
+// three with v_mfma_f64_16x16x4f64 over its quarter of the range, four columns per product
+// (lane l holds aht[j0 + l / 16][16 x + l % 16] as both operands' entry), kHhUnroll products
+// with their loads issued ahead.
+constexpr int kHhUnroll = 4;
+
+template <typename TV>
+__global__ __launch_bounds__(256) void k_gram_heavy_tiles(const MatDesc *__restrict__ descs) {
+    __shared__ double red[4][3][256];
+    const MatDesc &d = descs[0];
+    if (gmem(d.dense)[0] < 0) return;
+    const auto aht = gmem(static_cast<const TV *>(d.aht));
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t N = d.N, hwg = d.hwg;
+    const int64_t c0 = (N * blockIdx.x) / hwg, c1 = (N * (blockIdx.x + 1)) / hwg;
+    const int64_t q0 = c0 + ((c1 - c0) * wave) / 4, q1 = c0 + ((c1 - c0) * (wave + 1)) / 4;
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    d4 a00 = {0.0, 0.0, 0.0, 0.0}, a01 = a00, a11 = a00;
+    const int kr = lane >> 4, hc = lane & 15;
+    for (int64_t j0 = q0; j0 < q1; j0 += 4 * kHhUnroll) {
+        double x0[kHhUnroll], x1[kHhUnroll];
+#pragma unroll
+        for (int u = 0; u < kHhUnroll; ++u) {
+            const int64_t j = j0 + 4 * u + kr;
+            const bool ok = j < q1;
+            const int64_t jj = ok ? j : q0;
+            const double v0 = static_cast<double>(aht[jj * kDenseRows + hc]);
+            const double v1 = static_cast<double>(aht[jj * kDenseRows + 16 + hc]);
+            x0[u] = ok ? v0 : 0.0;
+            x1[u] = ok ? v1 : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kHhUnroll; ++u) {
+            a00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[u], x0[u], a00, 0, 0, 0);
+            a01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[u], x1[u], a01, 0, 0, 0);
+            a11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[u], x1[u], a11, 0, 0, 0);
+        }
+    }
+    // result layout: element i of lane l at row l / 16 + 4 i, column l % 16
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int e = (kr + 4 * i) * 16 + hc;
+        red[wave][0][e] = a00[i];
+        red[wave][1][e] = a01[i];
+        red[wave][2][e] = a11[i];
+    }
+    __syncthreads();
+    const auto out = gmem(d.hpart) + (int64_t)blockIdx.x * kDenseRows * kDenseRows;
+    for (int t = tid; t < 3 * 256; t += 256) {
+        const int blk = t >> 8, e = t & 255, r = e >> 4, c = e & 15;
+        const double v = ((red[0][blk][e] + red[1][blk][e]) + red[2][blk][e]) + red[3][blk][e];
+        const int ra = blk == 2 ? 16 : 0, cb = blk == 0 ? 0 : 16;
+        out[(ra + r) * kDenseRows + cb + c] = v;
+    }
+}
+
+// G entries of the dense rows among themselves (the diagonal included): the partial tiles
+// added in workgroup order.  Upper-triangle entries of the tile (h1 <= h2 by position in the
+// dense list) are read; both G entries are written.
+__global__ __launch_bounds__(1024) void k_gram_heavy_reduce(const MatDesc *__restrict__ descs) {
+    const MatDesc &d = descs[0];
+    const int t = threadIdx.x, h1 = t / kDenseRows, h2 = t % kDenseRows;
+    const auto dense = gmem(d.dense);
+    if (h1 > h2 || dense[h1] < 0 || dense[h2] < 0) return;
+    const auto part = gmem(d.hpart) + h1 * kDenseRows + h2;
+    double v = 0.0;
+    for (int32_t b = 0; b < d.hwg; ++b) v += part[(int64_t)b * kDenseRows * kDenseRows];
+    const int64_t i1 = gmem(d.m2r)[dense[h1]], i2 = gmem(d.m2r)[dense[h2]];
+    const auto G = gmem(d.G);
+    G[i1 * d.npad + i2] = v;
+    G[i2 * d.npad + i1] = v;
+}
+
+int32_t gram_heavy_wgs(int64_t N) {
+    const int64_t w = (N + 8191) / 8192;
+    return (int32_t)(w < 1 ? 1 : (w > 2048 ? 2048 : w));
+}
+
+void launch_gram_heavy_build(const MatDesc *descs, int32_t dtype, int64_t N, hipStream_t s) {
+    int64_t b = (N + 255) / 256;
+    if (b > 8192) b = 8192;
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_gram_heavy_build<double>, dim3((unsigned)b), dim3(256), 0, s, descs);
+    else
+        hipLaunchKernelGGL(k_gram_heavy_build<float>, dim3((unsigned)b), dim3(256), 0, s, descs);
+}
+
+void launch_gram_heavy_tiles(const MatDesc *descs, int32_t dtype, int32_t hwg, hipStream_t s) {
+    if (hwg <= 0) return;
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_gram_heavy_tiles<double>, dim3((unsigned)hwg), dim3(256), 0, s, descs);
+    else
+        hipLaunchKernelGGL(k_gram_heavy_tiles<float>, dim3((unsigned)hwg), dim3(256), 0, s, descs);
+    hipLaunchKernelGGL(k_gram_heavy_reduce, dim3(1), dim3(kDenseRows * kDenseRows), 0, s, descs);
 }
 
 int32_t gram_dense_wgs(int64_t N) {

@@ -475,6 +475,10 @@ __global__ __launch_bounds__(256) void k_batch_collect(const MatDesc *__restrict
         o[7] = d.jstate ? d.jstate[kJsActive] : 0;
         o[8] = d.scal[kScGramSegs];
         o[9] = d.scal[kScGramSlots];
+        int32_t heavy = 0;   // dense rows split out of the sparse Gram walk
+        if (d.hwg > 0 && d.dense)
+            for (int t = 0; t < kDenseRows; ++t) heavy += d.dense[t] >= 0;
+        o[10] = heavy;
         out_f64[2 * i + 0] = d.sdbl[kSdTau];
         out_f64[2 * i + 1] = d.sdbl[kSdSigmaMax];
     }

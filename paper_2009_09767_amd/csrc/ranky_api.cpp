@@ -110,6 +110,7 @@ hipError_t kernel_attributes(int device, size_t lds_limit) {
 constexpr int32_t kTopkMaxBlock = 256;    // widest block (the p x p problems run on the Jacobi)
 constexpr int32_t kTopkWgTarget = 512;    // workgroups a split product aims for
 constexpr int32_t kTopkDefaultIters = 60;
+constexpr int64_t kHeavyMinNnz = (int64_t)1 << 22;   // automatic heavy-row split of the Gram from here
 
 // Block width for k wanted pairs: k plus half again (at least 32) of oversampling, in 64s.
 int32_t topk_block(int32_t k) {
@@ -197,6 +198,8 @@ struct Plan {
     bool solver = false, refine = false, explicit_blocks = false, uf = false;
     size_t o_topk = 0;     // the subspace iteration's region (topk.p > 0)
     TopkLayout topk;
+    int32_t hwg = 0;       // heavy-row split of the Gram: tile workgroups (0: off)
+    size_t o_aht = 0, o_hpart = 0;
 };
 
 // bstart (host, may be NULL): the caller's D + 1 block boundaries; the widest block sets
@@ -204,8 +207,11 @@ struct Plan {
 // dense: room for the split-bf16 dense tiles (a single matrix; used with gram_prec BF16X3).
 // uf: room for an FP32 copy of U (solver plans with an FP32 V: the back-projection gathers it).
 // topk_p: block width of the subspace iteration (0: the full Jacobi only).
+// heavy: room for the heavy-row split of the Gram (needs dense): the dense rows' values per
+// column (N x kDenseRows, 8-byte slots) and one partial tile per tile workgroup.
 Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool solver, bool refine,
-               const int64_t *bstart = nullptr, bool dense = false, bool uf = false, int32_t topk_p = 0) {
+               const int64_t *bstart = nullptr, bool dense = false, bool uf = false, int32_t topk_p = 0,
+               bool heavy = false) {
     Plan p;
     p.M = M;
     p.N = N;
@@ -255,6 +261,11 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool sol
     p.o_dense = take(sizeof(int32_t) * kDenseRows);
     p.dwg = dense ? gram_dense_wgs(N) : 0;
     p.o_dpart = take(sizeof(double) * kDenseRows * kDenseRows * (size_t)p.dwg);
+    if (dense && heavy) {
+        p.hwg = gram_heavy_wgs(N);
+        p.o_aht = take(sizeof(double) * kDenseRows * (size_t)N);
+        p.o_hpart = take(sizeof(double) * kDenseRows * kDenseRows * (size_t)p.hwg);
+    }
     p.o_G = take(sizeof(double) * (size_t)p.npad * p.npad);
     if (solver) {
         p.solver = true;
@@ -325,6 +336,9 @@ MatDesc carve(const Plan &p, char *base, Refine *rf) {
     d.dense = i32(p.o_dense);
     d.dwg = p.dwg;
     d.dpart = f64(p.o_dpart);
+    d.hwg = p.hwg;
+    d.aht = p.hwg > 0 ? static_cast<void *>(base + p.o_aht) : nullptr;
+    d.hpart = p.hwg > 0 ? f64(p.o_hpart) : nullptr;
     d.bp_per_cu = 32;
     d.jsched = 0;
     d.G = f64(p.o_G);
@@ -424,6 +438,7 @@ ranky_status check_opts(const ranky_opts &o) {
     if (o.refine < 0 || o.refine > 1) return fail(RANKY_E_INVALID, "refine=%d (0, 1, or -1 = automatic)", o.refine);
     if (o.eigensolver < 0 || o.eigensolver > 2) return fail(RANKY_E_INVALID, "eigensolver=%d (0, 1 or 2)", o.eigensolver);
     if (o.max_iters < 0) return fail(RANKY_E_INVALID, "max_iters=%d", o.max_iters);
+    if (o.gram_split < 0 || o.gram_split > 2) return fail(RANKY_E_INVALID, "gram_split=%d", o.gram_split);
     return RANKY_OK;
 }
 
@@ -1045,6 +1060,14 @@ ranky_status topk_eigensolve(ranky_ctx *ctx, Engine &e, const Plan &plan, char *
     return e.upload_desc();
 }
 
+// The heavy-row split of the Gram: a single matrix with an FP64 or FP32 Gram, automatic from
+// kHeavyMinNnz nonzeros (below it the walk over every pair is cheap and the split's per-column
+// pass is not), or as opts.gram_split asks.
+bool heavy_split(const ranky_opts &o, int count, int64_t nnz) {
+    if (count != 1 || o.gram_prec == RANKY_PREC_BF16X3 || o.gram_split == 1) return false;
+    return o.gram_split == 2 || nnz >= kHeavyMinNnz;
+}
+
 size_t path_bytes(const std::vector<Job> &jobs, const ranky_opts &o) {
     const int count = (int)jobs.size();
     const bool refine = count == 1 && wants_refine(o, jobs[0].k);
@@ -1054,7 +1077,7 @@ size_t path_bytes(const std::vector<Job> &jobs, const ranky_opts &o) {
     const int32_t topk_p = topk_plan_p(o, count, jobs[0].M, jobs[0].k);
     for (const Job &j : jobs) {
         total += make_plan(j.M, j.N, j.A.nnz, j.k, j.D, true, refine, j.bstart, count == 1, o.v_dtype == RANKY_F32,
-                           topk_p)
+                           topk_p, heavy_split(o, count, j.A.nnz))
                      .total;
         maxM = std::max(maxM, j.M);
         sum_d += j.D;
@@ -1074,7 +1097,7 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
     const int32_t topk_p = topk_plan_p(o, count, jobs[0].M, jobs[0].k);
     for (int i = 0; i < count; ++i) {
         plans[i] = make_plan(jobs[i].M, jobs[i].N, jobs[i].A.nnz, jobs[i].k, jobs[i].D, true, refine, jobs[i].bstart,
-                             count == 1, o.v_dtype == RANKY_F32, topk_p);
+                             count == 1, o.v_dtype == RANKY_F32, topk_p, heavy_split(o, count, jobs[i].A.nnz));
         maxM = std::max(maxM, jobs[i].M);
         blk_off[i] = (int32_t)sum_d;
         sum_d += jobs[i].D;
@@ -1154,9 +1177,11 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
     size_t gram_lds = 0;
     gram_shape(e.d, ctx->lds_limit, gram_nw, gram_lds);
     if (count == 1) launch_gram_dense(e.ddesc(), e.d[0].dwg, s);
+    if (count == 1 && e.d[0].hwg > 0) launch_gram_heavy_build(e.ddesc(), e.d[0].dtype, e.d[0].N, s);
     launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], e.dwp(kPhGramRed), e.nblk[kPhGramRed], count, gram_nw,
                 gram_lds, s);
     if (count == 1) launch_gram_dense_reduce(e.ddesc(), e.d[0].dwg, s);
+    if (count == 1) launch_gram_heavy_tiles(e.ddesc(), e.d[0].dtype, e.d[0].hwg, s);
     HIP_TRY(hipGetLastError());
     if (timing) hipEventRecord(ctx->ev[3], s);
     // the k leading pairs by subspace iteration when the block is narrow next to M' (and the
@@ -1257,6 +1282,8 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
             in.rr_sweeps = refine_sweeps;
             in.eig_iters = i == 0 ? eig_iters : 0;
             in.eig_flops = i == 0 ? eig_flops : 0.0;
+            in.topk_block = (i == 0 && eig_iters > 0) ? plans[0].topk.p : 0;
+            in.heavy_rows = iv[kColI * i + 10];
             in.n_blocks = jobs[i].D;
             in.lonely_max = iv[kColI * i + 5];
             in.lonely_blocks = iv[kColI * i + 6];
@@ -1342,8 +1369,8 @@ ranky_status step_device(StepCtx &sc) {
 
 ranky_status step_scan(StepCtx &sc, const ranky_csc *A, int32_t M, int64_t N, int32_t D, void *workspace,
                        size_t ws_bytes, hipStream_t s, Engine &e, int32_t *cnt, int32_t *rownnz, int32_t *lonely,
-                       int32_t *single) {
-    const Plan p = make_plan(M, N, A->nnz, 1, D, false, false, nullptr, true);
+                       int32_t *single, bool heavy = false) {
+    const Plan p = make_plan(M, N, A->nnz, 1, D, false, false, nullptr, true, false, 0, heavy);
     const Header h = make_header(1, 1, 1);
     if (!workspace || ws_bytes < h.total + p.total)
         return fail(RANKY_E_NOMEM, "workspace %zu < %zu", ws_bytes, h.total + p.total);
@@ -1973,7 +2000,8 @@ ranky_status ranky_batch(ranky_ctx *ctx, int32_t count, const ranky_batch_item *
 
 size_t ranky_step_workspace_bytes(int32_t M, int64_t N, int64_t nnz, int32_t D) {
     if (M < 1 || N < 1 || M > kMaxM || nnz < 0 || D < 1 || D > N) return 0;
-    return make_header(1, 1, 1).total + make_plan(M, N, nnz, 1, D, false, false, nullptr, true).total;
+    return make_header(1, 1, 1).total +
+           make_plan(M, N, nnz, 1, D, false, false, nullptr, true, false, 0, nnz >= kHeavyMinNnz).total;
 }
 
 ranky_status ranky_occupancy(const ranky_csc *A, int32_t M, int64_t N, int32_t D, int32_t *cnt, int32_t *rownnz,
@@ -1999,7 +2027,10 @@ ranky_status ranky_gram(const ranky_csc *A, int32_t M, int64_t N, int32_t prec, 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     StepCtx sc;
     Engine e;
-    st = step_scan(sc, A, M, N, default_blocks(N), workspace, ws_bytes, s, e, nullptr, nullptr, nullptr, nullptr);
+    // the heavy-row split as the path takes it (FP64 / FP32 Grams of at least kHeavyMinNnz nonzeros)
+    const bool heavy = prec != RANKY_PREC_BF16X3 && A->nnz >= kHeavyMinNnz;
+    st = step_scan(sc, A, M, N, default_blocks(N), workspace, ws_bytes, s, e, nullptr, nullptr, nullptr, nullptr,
+                   heavy);
     if (st) return st;
     MatDesc &x = e.d[0];
     x.prec = prec;
@@ -2013,12 +2044,14 @@ ranky_status ranky_gram(const ranky_csc *A, int32_t M, int64_t N, int32_t prec, 
         if (st) return st;
         e.enqueue_transpose();
         launch_gram_dense(e.ddesc(), x.dwg, s);
+        if (x.hwg > 0) launch_gram_heavy_build(e.ddesc(), x.dtype, x.N, s);
         int32_t gram_nw = 1;
         size_t gram_lds = 0;
         gram_shape(e.d, sc.c.lds_limit, gram_nw, gram_lds);
         launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], e.dwp(kPhGramRed), e.nblk[kPhGramRed], 1, gram_nw,
                     gram_lds, s);
         launch_gram_dense_reduce(e.ddesc(), x.dwg, s);
+        launch_gram_heavy_tiles(e.ddesc(), x.dtype, x.hwg, s);
         launch_scatter_gram(x.G, x.npad, x.m2r, M, G, s);
     } else {
         launch_fill_f64(G, (int64_t)M * M, 0.0, s);

@@ -36,7 +36,7 @@ class Csc(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
                 ("n_blocks", "gram_prec", "refine", "max_sweeps", "validate", "v_dtype", "timing", "graph",
-                 "eigensolver", "max_iters")] + \
+                 "eigensolver", "max_iters", "gram_split")] + \
                [("block_start", ctypes.c_void_p)]
 
 
@@ -75,7 +75,8 @@ class Info(ctypes.Structure):
                  ("round_ms", ctypes.c_float), ("round_launches", ctypes.c_int32), ("rr_sweeps", ctypes.c_int32),
                  ("eig_iters", ctypes.c_int32), ("eig_flops", ctypes.c_double),
                  ("lonely_per_block", ctypes.POINTER(ctypes.c_int32)),
-                 ("single_per_block", ctypes.POINTER(ctypes.c_int32))]
+                 ("single_per_block", ctypes.POINTER(ctypes.c_int32)),
+                 ("topk_block", ctypes.c_int32), ("heavy_rows", ctypes.c_int32)]
 
     def as_dict(self):
         """Copies every field; the per-block counts (library memory) become lists."""
@@ -261,10 +262,15 @@ def context(device: int = 0) -> Context:
 EIGENSOLVER = {"auto": 0, "jacobi": 1, "subspace": 2}
 
 
+GRAM_SPLIT = {"auto": 0, "off": 1, "on": 2}
+
+
 def make_opts(n_blocks=0, gram_prec="fp64", refine=None, max_sweeps=0, validate=True, v_dtype=torch.float64,
-              timing=False, graph=False, block_start=None, eigensolver="auto", max_iters=0) -> Opts:
+              timing=False, graph=False, block_start=None, eigensolver="auto", max_iters=0,
+              gram_split="auto") -> Opts:
     """block_start: optional D + 1 column boundaries (host; kept alive by the Opts).
-    refine=None keeps the library's automatic choice (-1)."""
+    refine=None keeps the library's automatic choice (-1).  gram_split: "auto", "off" or "on"
+    (the heavy-row split of the Gram)."""
     o = Opts()
     _check(lib().ranky_default_opts(ctypes.byref(o)))
     o.n_blocks = n_blocks
@@ -278,6 +284,7 @@ def make_opts(n_blocks=0, gram_prec="fp64", refine=None, max_sweeps=0, validate=
     o.graph = int(graph)
     o.eigensolver = EIGENSOLVER[eigensolver]
     o.max_iters = int(max_iters)
+    o.gram_split = GRAM_SPLIT[gram_split]
     if block_start is not None:
         import numpy as np
 

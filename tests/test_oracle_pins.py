@@ -548,3 +548,27 @@ def test_neighbor_checker_hand_worked_example(orc):
         X2 = _dense(3, 4, cp, ri, va)
         seen.add(2 if X2[2, 2] == 1.0 else 3)
     assert seen == {2, 3}
+
+
+# SplitMix64's published reference outputs for seed 1234567 (Vigna's splitmix64.c, the generator of
+# Steele, Lea and Flood, OOPSLA 2014): outputs 0..3 of the stream.
+SPLITMIX64_1234567 = [6457827717110365317, 3203168211198807973, 9817491932198370423, 4593380528125082431]
+
+
+def test_checker_draws_follow_the_published_splitmix64():
+    """RandomChecker on a 3 x 1000 matrix with one block (D = 1) whose rows 0 and 1 are empty:
+    (block 0, row m) takes draw 2m, so row 0 lands in column out[0] mod 1000 and row 1 in
+    out[2] mod 1000, with out the published stream; NeighborChecker with no neighbour falls back
+    to the same columns (its own draws 2m + 1 then pick among no candidates)."""
+    from oracle import checker
+
+    M, N = 3, 1000
+    cols = np.array([5, 77, 640])
+    A = gen.from_coo(M, N, np.full(cols.size, 2), cols, np.ones(cols.size))
+    want = {0: SPLITMIX64_1234567[0] % N, 1: SPLITMIX64_1234567[2] % N}
+    for kind in ("random", "neighbor"):
+        cp, ri, va, ins = checker(M, N, A.colptr, A.rowidx, A.values, 1, kind, seed=1234567)
+        assert ins == 2
+        X = _dense(M, N, cp, ri, va)
+        for m, c in want.items():
+            assert np.flatnonzero(X[m]).tolist() == [c]
