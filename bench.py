@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--no-other", action="store_true", help="skip the other-precision legs and the second matrix")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper's D sweep (Tables I-III protocol)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a device-to-device copy of this many GiB (counter calibration) and exit")
     return ap.parse_args()
@@ -282,6 +283,41 @@ def time_serving(ranky, torch, gen, seconds, pool_size=48, slots=8):
     return res
 
 
+def paper_tables(ranky, torch, gen, np):
+    """The protocol of Tables I-III (Sec. IV) on the 539 x 170897 stand-in: for every checker and D,
+    the paper's route (checker on a copy A', per-block factors, proxy P, P P^T, its eigenpairs)
+    against the Gram-form path on the same A' (how exact the route is) and on the unmodified A (what
+    the checker's additions change), by the paper's sums e_sigma and e_u over the k = 10 leading
+    triplets."""
+    A = gen.paper_standin()
+    dA = ranky.to_device(A, "cuda:0")
+    k = 10
+    base = ranky.svd(dA, k, 0.0)
+    rows = []
+    t_route = 0.0
+    for D in (2, 3, 4, 8, 10, 16, 32, 64, 128):
+        for kind in ("random", "neighbor", "neighbor_random"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sg, Ug, info = ranky.svd_paper(dA, k, D, kind, seed=D)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            t_route += dt
+            rep, added = ranky.checker(dA, D, kind, seed=D)
+            ref = ranky.svd(rep, k, 0.0, n_blocks=D)
+            es, eu = ranky.paper_errors(sg, Ug, ref.sigma, ref.U)
+            es_a, eu_a = ranky.paper_errors(sg, Ug, base.sigma, base.U)
+            rows.append({"D": D, "checker": kind, "added": int(added), "rank": int(info["rank"]),
+                         "proxy_cols": int(info["proxy_cols"]), "e_sigma": es, "e_u": eu,
+                         "e_sigma_vs_A": es_a, "e_u_vs_A": eu_a, "ms": dt * 1e3})
+    del dA
+    return {"workload": f"paper stand-in {A.M} x {A.N}, {A.nnz} nnz (0/1 values, Zipf(1.1) rows), k = {k}",
+            "rule": "e_sigma = sum_i |s_route - s_ref|, e_u = sum_i sum_m |sign u_route - u_ref| (i < k); "
+                    "ref = the Gram-form FP64 path on the same A' (e_*) or on A (e_*_vs_A)",
+            "max_e_sigma": max(r["e_sigma"] for r in rows), "max_e_u": max(r["e_u"] for r in rows),
+            "route_s_total": t_route, "rows": rows}
+
+
 def cpu_sample_200m(np, A, rows=2560, blocks=16, D=256):
     """The bounded oracle sample of the 200M-nonzero matrix: rows [0, rows) (heavy rows sit at
     seeded positions, so the leading rows are a representative slice) and the columns of the
@@ -437,6 +473,8 @@ def main():
         line["powerlaw_1m"] = second
         del dA2
 
+    if not args.no_paper:
+        line["paper_tables"] = paper_tables(ranky, torch, gen, np)
     if not args.no_batch:
         line["batch"] = time_batch(ranky, torch, gen, max(2, args.steps // 3), 1)
     if not args.no_serve:

@@ -51,8 +51,8 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
     const int32_t M = dsc.M, n = dsc.n, npad = dsc.npad;
     const int64_t ld = npad;
     // global (not FLAT) accesses: FLAT ones would also hold up the LDS waits below
-    const auto vals = gmem(vals_);
-    const auto rowidx = gmem(dsc.rowidx);
+    const auto vals = gmem(vals_);   // the light CSC's values with the heavy split
+    const auto rowidx = gmem(dsc.hwg > 0 ? dsc.lrowidx : dsc.rowidx);
     const auto rowptr = gmem(dsc.rowptr);
     const auto r2m = gmem(dsc.r2m);
     const auto csr_k = gmem(dsc.csrk);
@@ -168,37 +168,57 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
         kend = kend_next;
     }
     if (heavy && walker) {
-        // pairs with the dense rows: sum_j a_pj aht[j][h] over this wave's run, the two halves
-        // of the wave taking alternate nonzeros (lane h + 32 half the sum of dense row h),
-        // kHlUnroll row gathers of aht in flight per lane
+        // pairs with the dense rows: sum_j a_pj aht[j][h] over this wave's run.  A row of aht
+        // (kDenseRows values) is read by kLpn lanes with 16-byte loads (kVec values each), so a
+        // step covers kNps nonzeros, one per lane group g; kHlBatch batches of 64 nonzeros are
+        // taken per round, all kHlSteps row loads of a lane issued before the first sum.  Group
+        // g sums the nonzeros u = g (mod kNps) in order; the groups are added in order at the end.
+        constexpr int kVec = 16 / (int)sizeof(TV), kLpn = kDenseRows / kVec, kNps = 64 / kLpn;
+        constexpr int kHlSteps = kHlBatch * 64 / kNps;
+        typedef TV tv_vec __attribute__((ext_vector_type(kVec)));
         const auto aht = gmem(static_cast<const TV *>(dsc.aht));
         const auto csr_col = gmem(dsc.csrcol);
-        const int half = lane >> 5, h = lane & 31;
-        double hs = 0.0;
-        for (int32_t base = wb; base < we; base += 64) {
-            const int32_t e = base + lane < we ? base + lane : we - 1;
-            const int32_t jl = csr_col[e];
-            const double al = base + lane < we ? static_cast<double>(vals[csr_k[e]]) : 0.0;
-            const int cnt = we - base < 64 ? we - base : 64;
-            for (int u = 0; u < cnt; u += 2 * kHlUnroll) {
-                double xs[kHlUnroll], as[kHlUnroll];
+        const int g = lane / kLpn, hq = lane % kLpn;
+        double hs[kVec];
 #pragma unroll
-                for (int v = 0; v < kHlUnroll; ++v) {
-                    const int src = u + 2 * v + half;
-                    const int sl = src < 64 ? src : 63;
-                    const int32_t j = __shfl(jl, sl, 64);
-                    const double a = __shfl(al, sl, 64);
-                    as[v] = src < cnt ? a : 0.0;
-                    xs[v] = static_cast<double>(aht[(int64_t)j * kDenseRows + h]);
-                }
+        for (int c = 0; c < kVec; ++c) hs[c] = 0.0;
+        for (int32_t base = wb; base < we; base += 64 * kHlBatch) {
+            int32_t jl[kHlBatch];
+            double al[kHlBatch];
 #pragma unroll
-                for (int v = 0; v < kHlUnroll; ++v) hs = fma(as[v], xs[v], hs);
+            for (int t = 0; t < kHlBatch; ++t) {
+                const int32_t x = base + 64 * t + lane;
+                const int32_t e = x < we ? x : we - 1;
+                jl[t] = csr_col[e];
+                const double v = static_cast<double>(vals[csr_k[e]]);
+                al[t] = x < we ? v : 0.0;
             }
+            tv_vec xs[kHlSteps];
+            double as[kHlSteps];
+#pragma unroll
+            for (int v = 0; v < kHlSteps; ++v) {
+                // nonzero v kNps + g of this round: batch t (a compile-time index), lane sl
+                const int t = (v * kNps) / 64, sl = (v * kNps) % 64 + g;
+                const int32_t j = __shfl(jl[t], sl, 64);
+                as[v] = __shfl(al[t], sl, 64);
+                xs[v] = *reinterpret_cast<__attribute__((address_space(1))) const tv_vec *>(
+                    aht + (int64_t)j * kDenseRows + kVec * hq);
+            }
+#pragma unroll
+            for (int v = 0; v < kHlSteps; ++v)
+#pragma unroll
+                for (int c = 0; c < kVec; ++c) hs[c] = fma(as[v], static_cast<double>(xs[v][c]), hs[c]);
         }
-        const double other = __shfl(hs, h + 32, 64);
-        if (lane < 32) {
-            const int32_t q = dense[h];
-            if (q >= 0) my[q] = static_cast<Acc>(hs + other);
+        // lane hq of group 0 adds the groups' sums in group order and writes dense rows kVec hq + c
+#pragma unroll
+        for (int c = 0; c < kVec; ++c) {
+            double tot = 0.0;
+#pragma unroll
+            for (int gg = 0; gg < kNps; ++gg) tot += __shfl(hs[c], gg * kLpn + hq, 64);
+            if (lane < kLpn) {
+                const int32_t q = dense[kVec * hq + c];
+                if (q >= 0) my[q] = static_cast<Acc>(tot);
+            }
         }
     }
     dg = wave_sum(dg);
@@ -290,12 +310,13 @@ __global__ __launch_bounds__(512) void k_gram_rows(const MatDesc *__restrict__ d
         seg = b - gsegp[i];
         nseg = gsegp[i + 1] - gsegp[i];
     }
+    const void *vp = d.hwg > 0 ? d.lvals : d.values;   // the walk's columns
     if (d.dtype == 1) {
-        const double *v = static_cast<const double *>(d.values);
+        const double *v = static_cast<const double *>(vp);
         if (d.prec == 0) gram_row<double, double>(d, v, i, seg, nseg, lds_raw);
         else gram_row<double, float>(d, v, i, seg, nseg, lds_raw);
     } else {
-        const float *v = static_cast<const float *>(d.values);
+        const float *v = static_cast<const float *>(vp);
         if (d.prec == 0) gram_row<float, double>(d, v, i, seg, nseg, lds_raw);
         else gram_row<float, float>(d, v, i, seg, nseg, lds_raw);
     }
@@ -464,20 +485,27 @@ __global__ __launch_bounds__(1024) void k_gram_dense_reduce(const MatDesc *__res
 //   - G_HH = sum_j aht[j] aht[j]^T on the FP64 matrix cores (k_gram_heavy_tiles): each
 //     workgroup owns a fixed column range (a function of N alone), its four waves a fixed
 //     quarter of it, summed in wave order into one partial tile per workgroup, which
-//     k_gram_heavy_reduce adds in workgroup order;
-//   - every other row p adds sum_j a_pj aht[j] (one coalesced row per nonzero) in the walk
-//     kernel, and its walk skips the dense rows.
+//     k_gram_heavy_reduce adds in a fixed tree over the workgroups;
+//   - the other ("light") rows' entries of every column are copied in row order to a light
+//     CSC (k_gram_light_scatter, after a scan of the per-column counts), and the row-major
+//     copy's positions of the light rows are rewritten to point into it (k_gram_light_slots):
+//     the walk then steps over light entries only;
+//   - every light row p adds sum_j a_pj aht[j] (one coalesced row per nonzero) in the walk
+//     kernel.
 // Every sum keeps an order fixed by the matrix alone, so the result is bitwise
 // reproducible and independent of D.
 
 // Thread per column j (grid-stride): the row of aht is cleared, then the column's dense
-// entries are written into it (the same thread, so program order keeps the values).
+// entries are written into it (the same thread, so program order keeps the values), and the
+// column's other ("light") entries are counted.  The column is read kHbBatch entries at a time
+// with every load issued before the first use.
+constexpr int kHbBatch = 8;
+
 template <typename TV>
 __global__ __launch_bounds__(256) void k_gram_heavy_build(const MatDesc *__restrict__ descs) {
     __shared__ int8_t dmap[kMaxM];
     const MatDesc &d = descs[0];
     const auto dense = gmem(d.dense);
-    if (dense[0] < 0) return;   // no dense row: aht is never read
     for (int32_t m = threadIdx.x; m < d.M; m += blockDim.x) dmap[m] = -1;
     __syncthreads();
     if (threadIdx.x < kDenseRows && dense[threadIdx.x] >= 0) dmap[dense[threadIdx.x]] = (int8_t)threadIdx.x;
@@ -486,14 +514,96 @@ __global__ __launch_bounds__(256) void k_gram_heavy_build(const MatDesc *__restr
     const auto rowidx = gmem(d.rowidx);
     const auto vals = gmem(static_cast<const TV *>(d.values));
     const auto aht = gmem(static_cast<TV *>(d.aht));
+    const auto lcnt = gmem(d.lcnt);
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < d.N; j += (int64_t)gridDim.x * blockDim.x) {
         auto row = aht + j * kDenseRows;
 #pragma unroll
         for (int h = 0; h < kDenseRows; ++h) row[h] = TV(0);
-        const int32_t e1 = colptr[j + 1];
-        for (int32_t e = colptr[j]; e < e1; ++e) {
-            const int h = dmap[rowidx[e]];
-            if (h >= 0) row[h] = vals[e];
+        const int32_t e0 = colptr[j], e1 = colptr[j + 1];
+        int32_t light = 0;
+        for (int32_t base = e0; base < e1; base += kHbBatch) {
+            int32_t rr[kHbBatch];
+            TV vv[kHbBatch];
+#pragma unroll
+            for (int u = 0; u < kHbBatch; ++u) {
+                const int32_t at = base + u < e1 ? base + u : e1 - 1;
+                rr[u] = rowidx[at];
+                vv[u] = vals[at];
+            }
+#pragma unroll
+            for (int u = 0; u < kHbBatch; ++u) {
+                if (base + u < e1) {
+                    const int h = dmap[rr[u]];
+                    if (h >= 0) row[h] = vv[u];
+                    else ++light;
+                }
+            }
+        }
+        lcnt[j] = light;
+    }
+}
+
+// Thread per column j: the light entries, in row order, to the light CSC at lptr[j], and every
+// entry's light position (-1 for a dense row's) to lpos.
+template <typename TV>
+__global__ __launch_bounds__(256) void k_gram_light_scatter(const MatDesc *__restrict__ descs) {
+    __shared__ int8_t dmap[kMaxM];
+    const MatDesc &d = descs[0];
+    const auto dense = gmem(d.dense);
+    for (int32_t m = threadIdx.x; m < d.M; m += blockDim.x) dmap[m] = -1;
+    __syncthreads();
+    if (threadIdx.x < kDenseRows && dense[threadIdx.x] >= 0) dmap[dense[threadIdx.x]] = (int8_t)threadIdx.x;
+    __syncthreads();
+    const auto colptr = gmem(d.colptr);
+    const auto rowidx = gmem(d.rowidx);
+    const auto vals = gmem(static_cast<const TV *>(d.values));
+    const auto lptr = gmem(d.lptr);
+    const auto lrow = gmem(d.lrowidx);
+    const auto lval = gmem(static_cast<TV *>(d.lvals));
+    const auto lpos = gmem(d.lpos);
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < d.N; j += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t e0 = colptr[j], e1 = colptr[j + 1];
+        int32_t out = lptr[j];
+        for (int32_t base = e0; base < e1; base += kHbBatch) {
+            int32_t rr[kHbBatch];
+            TV vv[kHbBatch];
+#pragma unroll
+            for (int u = 0; u < kHbBatch; ++u) {
+                const int32_t at = base + u < e1 ? base + u : e1 - 1;
+                rr[u] = rowidx[at];
+                vv[u] = vals[at];
+            }
+#pragma unroll
+            for (int u = 0; u < kHbBatch; ++u) {
+                if (base + u < e1) {
+                    if (dmap[rr[u]] < 0) {
+                        lrow[out] = rr[u];
+                        lval[out] = vv[u];
+                        lpos[base + u] = out;
+                        ++out;
+                    } else {
+                        lpos[base + u] = -1;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Row-major slot e of a light row: its CSC position and column end become the light CSC's.
+// The dense rows' slots keep theirs (their workgroups do not walk).
+__global__ __launch_bounds__(256) void k_gram_light_slots(const MatDesc *__restrict__ descs) {
+    const MatDesc &d = descs[0];
+    const auto csr_k = gmem(d.csrk);
+    const auto csr_end = gmem(d.csrend);
+    const auto csr_col = gmem(d.csrcol);
+    const auto lpos = gmem(d.lpos);
+    const auto lptr = gmem(d.lptr);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < d.nnz; e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t kl = lpos[csr_k[e]];
+        if (kl >= 0) {
+            csr_k[e] = kl;
+            csr_end[e] = lptr[csr_col[e] + 1];
         }
     }
 }
@@ -555,21 +665,36 @@ __global__ __launch_bounds__(256) void k_gram_heavy_tiles(const MatDesc *__restr
     }
 }
 
-// G entries of the dense rows among themselves (the diagonal included): the partial tiles
-// added in workgroup order.  Upper-triangle entries of the tile (h1 <= h2 by position in the
-// dense list) are read; both G entries are written.
-__global__ __launch_bounds__(1024) void k_gram_heavy_reduce(const MatDesc *__restrict__ descs) {
+// G entries of the dense rows among themselves (the diagonal included): one workgroup per
+// upper-triangle entry (h1 <= h2 by position in the dense list) adds the hwg partial tiles,
+// thread t the tiles t, t + 256, ... in order, then a fixed tree over the threads; both G
+// entries are written.
+__global__ __launch_bounds__(256) void k_gram_heavy_reduce(const MatDesc *__restrict__ descs) {
+    __shared__ double red[256];
     const MatDesc &d = descs[0];
-    const int t = threadIdx.x, h1 = t / kDenseRows, h2 = t % kDenseRows;
+    int h1 = 0, rem = blockIdx.x;
+    while (rem >= kDenseRows - h1) {
+        rem -= kDenseRows - h1;
+        ++h1;
+    }
+    const int h2 = h1 + rem;
     const auto dense = gmem(d.dense);
-    if (h1 > h2 || dense[h1] < 0 || dense[h2] < 0) return;
+    if (dense[h1] < 0 || dense[h2] < 0) return;
     const auto part = gmem(d.hpart) + h1 * kDenseRows + h2;
     double v = 0.0;
-    for (int32_t b = 0; b < d.hwg; ++b) v += part[(int64_t)b * kDenseRows * kDenseRows];
-    const int64_t i1 = gmem(d.m2r)[dense[h1]], i2 = gmem(d.m2r)[dense[h2]];
-    const auto G = gmem(d.G);
-    G[i1 * d.npad + i2] = v;
-    G[i2 * d.npad + i1] = v;
+    for (int32_t b = threadIdx.x; b < d.hwg; b += blockDim.x) v += part[(int64_t)b * kDenseRows * kDenseRows];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t i1 = gmem(d.m2r)[dense[h1]], i2 = gmem(d.m2r)[dense[h2]];
+        const auto G = gmem(d.G);
+        G[i1 * d.npad + i2] = red[0];
+        G[i2 * d.npad + i1] = red[0];
+    }
 }
 
 int32_t gram_heavy_wgs(int64_t N) {
@@ -577,13 +702,21 @@ int32_t gram_heavy_wgs(int64_t N) {
     return (int32_t)(w < 1 ? 1 : (w > 2048 ? 2048 : w));
 }
 
-void launch_gram_heavy_build(const MatDesc *descs, int32_t dtype, int64_t N, hipStream_t s) {
-    int64_t b = (N + 255) / 256;
+static unsigned heavy_cols_grid(int64_t n) {
+    int64_t b = (n + 255) / 256;
     if (b > 8192) b = 8192;
-    if (dtype == 1)
-        hipLaunchKernelGGL(k_gram_heavy_build<double>, dim3((unsigned)b), dim3(256), 0, s, descs);
-    else
-        hipLaunchKernelGGL(k_gram_heavy_build<float>, dim3((unsigned)b), dim3(256), 0, s, descs);
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+void launch_gram_heavy_prep(const MatDesc *descs, const MatDesc &host, hipStream_t s) {
+    if (host.hwg <= 0) return;
+    const unsigned g = heavy_cols_grid(host.N);
+    if (host.dtype == 1) hipLaunchKernelGGL(k_gram_heavy_build<double>, dim3(g), dim3(256), 0, s, descs);
+    else hipLaunchKernelGGL(k_gram_heavy_build<float>, dim3(g), dim3(256), 0, s, descs);
+    launch_exclusive_scan(host.lcnt, host.N, host.lbtot, host.lptr, s);
+    if (host.dtype == 1) hipLaunchKernelGGL(k_gram_light_scatter<double>, dim3(g), dim3(256), 0, s, descs);
+    else hipLaunchKernelGGL(k_gram_light_scatter<float>, dim3(g), dim3(256), 0, s, descs);
+    if (host.nnz > 0) hipLaunchKernelGGL(k_gram_light_slots, dim3(heavy_cols_grid(host.nnz)), dim3(256), 0, s, descs);
 }
 
 void launch_gram_heavy_tiles(const MatDesc *descs, int32_t dtype, int32_t hwg, hipStream_t s) {
@@ -592,7 +725,7 @@ void launch_gram_heavy_tiles(const MatDesc *descs, int32_t dtype, int32_t hwg, h
         hipLaunchKernelGGL(k_gram_heavy_tiles<double>, dim3((unsigned)hwg), dim3(256), 0, s, descs);
     else
         hipLaunchKernelGGL(k_gram_heavy_tiles<float>, dim3((unsigned)hwg), dim3(256), 0, s, descs);
-    hipLaunchKernelGGL(k_gram_heavy_reduce, dim3(1), dim3(kDenseRows * kDenseRows), 0, s, descs);
+    hipLaunchKernelGGL(k_gram_heavy_reduce, dim3(kDenseRows * (kDenseRows + 1) / 2), dim3(256), 0, s, descs);
 }
 
 int32_t gram_dense_wgs(int64_t N) {

@@ -308,15 +308,23 @@ __global__ __launch_bounds__(1024) void k_tk_chol(const double *__restrict__ S_,
                 }
             }
             __syncthreads();
+            // this thread's rows of column j and its columns' entries L(l, j), read once
+            double cv[VB], cl[PB];
+#pragma unroll
+            for (int vb = 0; vb < VB; ++vb) {
+                const int v = r + 32 * vb;
+                cv[vb] = v <= p ? col[slot][v] : 0.0;
+            }
+#pragma unroll
+            for (int lc = 0; lc < PB; ++lc) cl[lc] = col[slot][c + 32 * lc + 1];
 #pragma unroll
             for (int lc = 0; lc < PB; ++lc) {
                 const int l = c + 32 * lc;
                 if (l > j) {
-                    const double llj = col[slot][l + 1];
 #pragma unroll
                     for (int vb = 0; vb < VB; ++vb) {
                         const int v = r + 32 * vb;
-                        if (v <= p && (v <= j || v > l)) a[vb][lc] = fma(-col[slot][v], llj, a[vb][lc]);
+                        if (v <= j || v > l) a[vb][lc] = fma(-cv[vb], cl[lc], a[vb][lc]);
                     }
                 }
             }

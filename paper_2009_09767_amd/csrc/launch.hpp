@@ -46,7 +46,10 @@ void launch_gram(const MatDesc *descs, const int32_t *wp, int64_t nblocks, const
 hipError_t gram_set_attributes(size_t lds_limit);
 int32_t gram_dense_wgs(int64_t N);
 int32_t gram_heavy_wgs(int64_t N);   // workgroups of the heavy-row tiles (a function of N)
-void launch_gram_heavy_build(const MatDesc *descs, int32_t dtype, int64_t N, hipStream_t s);
+// The heavy split's preparation, after the transpose: aht and the light CSC (the walk's columns),
+// and the row-major copy's positions of the light rows rewritten to point into it.  host: the
+// matrix's descriptor as the host holds it (its workspace pointers).
+void launch_gram_heavy_prep(const MatDesc *descs, const MatDesc &host, hipStream_t s);
 void launch_gram_heavy_tiles(const MatDesc *descs, int32_t dtype, int32_t hwg, hipStream_t s);   // workgroups of the split-bf16 dense-row tiles (a function of N)
 void launch_gram_dense(const MatDesc *descs, int32_t dwg, hipStream_t s);   // BF16X3 dense tiles
 void launch_gram_dense_reduce(const MatDesc *descs, int32_t dwg, hipStream_t s);

@@ -199,7 +199,7 @@ struct Plan {
     size_t o_topk = 0;     // the subspace iteration's region (topk.p > 0)
     TopkLayout topk;
     int32_t hwg = 0;       // heavy-row split of the Gram: tile workgroups (0: off)
-    size_t o_aht = 0, o_hpart = 0;
+    size_t o_aht = 0, o_hpart = 0, o_lcnt = 0, o_lptr = 0, o_lbtot = 0, o_lrow = 0, o_lval = 0, o_lpos = 0;
 };
 
 // bstart (host, may be NULL): the caller's D + 1 block boundaries; the widest block sets
@@ -265,6 +265,12 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool sol
         p.hwg = gram_heavy_wgs(N);
         p.o_aht = take(sizeof(double) * kDenseRows * (size_t)N);
         p.o_hpart = take(sizeof(double) * kDenseRows * kDenseRows * (size_t)p.hwg);
+        p.o_lcnt = take(sizeof(int32_t) * (size_t)N);
+        p.o_lptr = take(sizeof(int32_t) * ((size_t)N + 1));
+        p.o_lbtot = take(sizeof(int32_t) * (size_t)tall_scan_blocks(N));
+        p.o_lrow = take(sizeof(int32_t) * nz);
+        p.o_lval = take(sizeof(double) * nz);
+        p.o_lpos = take(sizeof(int32_t) * nz);
     }
     p.o_G = take(sizeof(double) * (size_t)p.npad * p.npad);
     if (solver) {
@@ -339,6 +345,12 @@ MatDesc carve(const Plan &p, char *base, Refine *rf) {
     d.hwg = p.hwg;
     d.aht = p.hwg > 0 ? static_cast<void *>(base + p.o_aht) : nullptr;
     d.hpart = p.hwg > 0 ? f64(p.o_hpart) : nullptr;
+    d.lcnt = p.hwg > 0 ? i32(p.o_lcnt) : nullptr;
+    d.lptr = p.hwg > 0 ? i32(p.o_lptr) : nullptr;
+    d.lbtot = p.hwg > 0 ? i32(p.o_lbtot) : nullptr;
+    d.lrowidx = p.hwg > 0 ? i32(p.o_lrow) : nullptr;
+    d.lpos = p.hwg > 0 ? i32(p.o_lpos) : nullptr;
+    d.lvals = p.hwg > 0 ? static_cast<void *>(base + p.o_lval) : nullptr;
     d.bp_per_cu = 32;
     d.jsched = 0;
     d.G = f64(p.o_G);
@@ -1177,7 +1189,7 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
     size_t gram_lds = 0;
     gram_shape(e.d, ctx->lds_limit, gram_nw, gram_lds);
     if (count == 1) launch_gram_dense(e.ddesc(), e.d[0].dwg, s);
-    if (count == 1 && e.d[0].hwg > 0) launch_gram_heavy_build(e.ddesc(), e.d[0].dtype, e.d[0].N, s);
+    if (count == 1 && e.d[0].hwg > 0) launch_gram_heavy_prep(e.ddesc(), e.d[0], s);
     launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], e.dwp(kPhGramRed), e.nblk[kPhGramRed], count, gram_nw,
                 gram_lds, s);
     if (count == 1) launch_gram_dense_reduce(e.ddesc(), e.d[0].dwg, s);
@@ -1542,7 +1554,9 @@ PaperPlan paper_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bo
     pp.o_bU = take(sizeof(double) * (size_t)D * M * M);
     pp.o_rank = take(sizeof(int32_t) * (size_t)D);
     const size_t np = pp.np;
-    pp.o_Pt = take(sizeof(double) * (size_t)D * M * np);   // at most M retained triplets per block
+    // at most M retained triplets per block; the product reads the rows padded to a multiple of 16
+    const size_t pt_rows = std::max<size_t>(16, (((size_t)D * M + 15) / 16) * 16);
+    pp.o_Pt = take(sizeof(double) * pt_rows * np);
     int32_t klen = 0;
     topk_split((int64_t)(np / kTopkTile) * (np / kTopkTile), (int32_t)std::min<int64_t>((int64_t)D * M, 0x7fffffff),
                pp.part_splits, klen);
@@ -2044,7 +2058,7 @@ ranky_status ranky_gram(const ranky_csc *A, int32_t M, int64_t N, int32_t prec, 
         if (st) return st;
         e.enqueue_transpose();
         launch_gram_dense(e.ddesc(), x.dwg, s);
-        if (x.hwg > 0) launch_gram_heavy_build(e.ddesc(), x.dtype, x.N, s);
+        if (x.hwg > 0) launch_gram_heavy_prep(e.ddesc(), x, s);
         int32_t gram_nw = 1;
         size_t gram_lds = 0;
         gram_shape(e.d, sc.c.lds_limit, gram_nw, gram_lds);
@@ -2461,7 +2475,7 @@ ranky_status ranky_svd_paper(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int6
     const int32_t np = pp.np;
     int64_t R = 0;
     for (int32_t b = 0; b < D; ++b) R += binfo[b].rank;
-    const int64_t Rpad = std::max<int64_t>(16, ((R + 15) / 16) * 16);
+    const int64_t Rpad = std::max<int64_t>(16, ((R + 15) / 16) * 16);   // R <= D M: within the Pt rows
     launch_fill_f64(f64(pp.o_Pt), Rpad * np, 0.0, s);
     for (int32_t b = 0, off = 0; b < D; off += binfo[b].rank, ++b)
         launch_proxy_rows(f64(pp.o_bU) + (size_t)b * M * M, f64(pp.o_bsig) + (size_t)b * M, M, binfo[b].rank, xs.m2r,

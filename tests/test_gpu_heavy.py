@@ -101,6 +101,12 @@ def test_split_forced_whole_path_against_oracle(R, orc, dtype):
     S = sp.csc_matrix((A.values.astype(np.float64), A.rowidx, A.colptr), shape=(A.M, A.N))
     X = (S.T @ U_on[:, :r]) / s_on[:r]
     assert np.max(np.abs(Vd[:, :r] - X)) <= 1e-10 * max(1.0, np.max(np.abs(X)))
+    # an FP32 V from the same split (the heavy back-projection writes either type)
+    o32 = R.svd(dA, k, 0.0, gram_split="on", eigensolver="jacobi", v_dtype=torch.float32)
+    V32 = o32.V.cpu().numpy().astype(np.float64)
+    X32 = (S.T @ o32.U.cpu().numpy()[:, :r]) / o32.sigma.cpu().numpy()[:r]
+    assert np.max(np.abs(V32[:, :r] - X32)) <= 2.0 ** -22 * max(1.0, np.max(np.abs(X32)))
+    assert np.all(V32[:, r:] == 0.0)
     # bitwise: repeated and for any D (the sums' order is a function of the matrix alone)
     again = R.svd(dA, k, 0.0, gram_split="on", eigensolver="jacobi", n_blocks=7)
     assert torch.equal(again.sigma, on.sigma) and torch.equal(again.U, on.U)

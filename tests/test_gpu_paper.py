@@ -110,3 +110,35 @@ def test_tables_sweep_small(R):
             assert info["added"] == added
             assert info["rank"] == ref.info["rank"]
             assert es <= 1e-10 * float(ref.sigma.sum())
+
+
+@pytest.mark.parametrize("D", [2, 3, 5])
+def test_proxy_route_full_rank_blocks(R, orc, D):
+    """Every block of full rank M with D M not a multiple of 16: P^T has D M rows, and the P P^T
+    product reads them padded to a multiple of 16.  The route equals the oracle's block merge and
+    does not depend on the workspace's prior contents."""
+    import ctypes
+    import torch
+
+    A = gen.random_sparse(37, 6000, 0.05, seed=43)
+    dA = R.to_device(A)
+    k = 12
+    ref = orc.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=k, method="merge", D=D)
+    nb = int(R.lib().ranky_paper_workspace_bytes(A.M, A.N, A.nnz, k, D, -1))
+    outs = []
+    for fill in (0.0, 0.5, 1e30):
+        ws = torch.full(((nb + 7) // 8,), fill, dtype=torch.float64, device="cuda")
+        sigma = torch.empty(k, dtype=torch.float64, device="cuda")
+        U = torch.empty((A.M, k), dtype=torch.float64, device="cuda")
+        info = R.PaperInfo()
+        csc = dA.struct()
+        R._check(R.lib().ranky_svd_paper(R.context(0).handle, ctypes.byref(csc), A.M, A.N, k, D, -1, 0, 0.0,
+                                         R._ptr(ws), nb, R._ptr(sigma), R._ptr(U), ctypes.byref(info), None))
+        assert info.proxy_cols == D * A.M
+        outs.append((sigma.cpu().numpy(), U.cpu().numpy()))
+    r = ref.rank
+    for s, U in outs:
+        assert H.rel_sigma_err(s, ref.sigma, r) <= 1e-10
+        scaled, _ = H.vector_errors(U[:, :r], ref.U[:, :r], ref.sigma, r)
+        assert scaled <= 1e-10
+        assert np.array_equal(s, outs[0][0]) and np.array_equal(U, outs[0][1])
