@@ -111,33 +111,51 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
     Acc dg = Acc(0);
 
     // Each lane walks the later entries of its column kGramStep steps at a time: the
-    // loads of a group are all issued before the first product is added, and the next
-    // batch's CSR positions are fetched during the walk.  The additions still run step
-    // by step in lane order, so the sums are those of a one-step walk.
-    // Lanes past the end of the run load the run's last entry (a valid address) and
-    // discard it: with no conditional loads, all of a group's loads stay in flight.
-    int32_t kk = 0, kend = 0;
+    // loads of a group are all issued before the first product is added.  Batches of 64
+    // nonzeros are pipelined: while a batch's additions run, the next batch's value and
+    // first group of column entries and the positions of the batch after it are in
+    // flight.  The additions still run step by step in lane order, so the sums are those of
+    // a one-step walk.  Lanes past the end of the run load the run's last entry (a valid
+    // address) and discard it: with no conditional loads, all of a group's loads stay in
+    // flight.
+    auto clampe = [&](int32_t x) { return x < we ? x : we - 1; };
+    auto load_group = [&](int32_t k0, int32_t k1, int32_t s, int32_t(&qs)[kGramStep], Acc(&vs)[kGramStep]) {
+#pragma unroll
+        for (int u = 0; u < kGramStep; ++u) {
+            const int32_t at = k0 + s + u < k1 ? k0 + s + u : k0;
+            qs[u] = rowidx[at];
+            vs[u] = static_cast<Acc>(vals[at]);
+        }
+    };
+    int32_t kk = 0, kend = 0, kk1 = 0, kend1 = 0;
+    Acc a = Acc(0);
+    int32_t q0[kGramStep];
+    Acc v0[kGramStep];
+#pragma unroll
+    for (int u = 0; u < kGramStep; ++u) {
+        q0[u] = 0;
+        v0[u] = Acc(0);
+    }
     if (walker && wb < we) {
-        const int32_t e0 = wb + lane < we ? wb + lane : we - 1;
+        const int32_t e0 = clampe(wb + lane), e1 = clampe(wb + 64 + lane);
         kk = csr_k[e0];
         kend = csr_end[e0];
+        kk1 = csr_k[e1];
+        kend1 = csr_end[e1];
+        a = static_cast<Acc>(vals[kk]);
+        load_group(kk, kend, 1, q0, v0);
     }
     for (int32_t base = wb; walker && base < we; base += 64) {
         const bool has = base + lane < we;
-        const int32_t nb = base + 64 + lane < we ? base + 64 + lane : we - 1;
-        const int32_t kk_next = csr_k[nb], kend_next = csr_end[nb];
-        const Acc a = static_cast<Acc>(vals[kk]);   // used only where has holds
-        for (int32_t s = 1;; s += kGramStep) {
-            if (__ballot(has && kk + s < kend) == 0) break;
-            int32_t qs[kGramStep];
-            Acc vs[kGramStep];
-#pragma unroll
-            for (int u = 0; u < kGramStep; ++u) {
-                const int32_t at = kk + s + u < kend ? kk + s + u : kk;
-                qs[u] = rowidx[at];
-                vs[u] = static_cast<Acc>(vals[at]);
-            }
-            __builtin_amdgcn_sched_barrier(0);   // keep every load of the group ahead of its uses
+        // ahead: the positions of the batch after next, the next batch's value and first group
+        const int32_t e2 = clampe(base + 128 + lane);
+        const int32_t kk2 = csr_k[e2], kend2 = csr_end[e2];
+        const Acc a1 = static_cast<Acc>(vals[kk1]);
+        int32_t q1[kGramStep];
+        Acc v1[kGramStep];
+        load_group(kk1, kend1, 1, q1, v1);
+        __builtin_amdgcn_sched_barrier(0);
+        auto add_group = [&](const int32_t(&qs)[kGramStep], const Acc(&vs)[kGramStep], int32_t s) {
 #pragma unroll
             for (int u = 0; u < kGramStep; ++u) {
                 const bool act = has && (kk + s + u < kend);
@@ -162,10 +180,29 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
                     pend = pend && !win;
                 }
             }
+        };
+        if (__ballot(has && kk + 1 < kend) != 0) {
+            add_group(q0, v0, 1);   // loaded a batch ago
+            for (int32_t s = 1 + kGramStep;; s += kGramStep) {
+                if (__ballot(has && kk + s < kend) == 0) break;
+                int32_t qs[kGramStep];
+                Acc vs[kGramStep];
+                load_group(kk, kend, s, qs, vs);
+                __builtin_amdgcn_sched_barrier(0);   // keep every load of the group ahead of its uses
+                add_group(qs, vs, s);
+            }
         }
         if (has) dg += a * a;
-        kk = kk_next;
-        kend = kend_next;
+        kk = kk1;
+        kend = kend1;
+        kk1 = kk2;
+        kend1 = kend2;
+        a = a1;
+#pragma unroll
+        for (int u = 0; u < kGramStep; ++u) {
+            q0[u] = q1[u];
+            v0[u] = v1[u];
+        }
     }
     if (heavy && walker) {
         // pairs with the dense rows: sum_j a_pj aht[j][h] over this wave's run.  A row of aht
