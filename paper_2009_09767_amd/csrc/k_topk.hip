@@ -169,16 +169,19 @@ __device__ __forceinline__ double tk_noise(uint64_t c) {
 // per row i: its rank among the n diagonal entries decides which column gets the one.
 __global__ __launch_bounds__(256) void k_tk_start(const double *__restrict__ G_, int64_t ldg, int32_t n, int32_t p,
                                                   int32_t rows, double *__restrict__ X_) {
+    extern __shared__ double diag[];   // the n diagonal entries, staged once per workgroup
     const auto G = gmem(G_);
     const auto X = gmem(X_);
+    for (int32_t j = threadIdx.x; j < n; j += blockDim.x) diag[j] = G[(int64_t)j * ldg + j];
+    __syncthreads();
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= rows) return;
     int32_t rank = n;
     if (i < n) {
-        const double gi = G[(int64_t)i * ldg + i];
+        const double gi = diag[i];
         rank = 0;
         for (int32_t j = 0; j < n; ++j) {
-            const double gj = G[(int64_t)j * ldg + j];
+            const double gj = diag[j];
             rank += (gj > gi) || (gj == gi && j < i);
         }
     }
@@ -431,7 +434,8 @@ void launch_tk_combine(const double *part, int32_t splits, int64_t count, double
 }
 
 void launch_tk_start(const double *G, int64_t ldg, int32_t n, int32_t p, int32_t rows, double *X, hipStream_t s) {
-    hipLaunchKernelGGL(k_tk_start, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, G, ldg, n, p, rows, X);
+    hipLaunchKernelGGL(k_tk_start, dim3((unsigned)((rows + 255) / 256)), dim3(256), sizeof(double) * (size_t)(n > 0 ? n : 1),
+                       s, G, ldg, n, p, rows, X);
 }
 
 void launch_tk_symcopy(const double *src, int32_t p, double *dst, double *dvec, hipStream_t s) {

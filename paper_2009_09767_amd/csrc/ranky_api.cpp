@@ -1028,15 +1028,19 @@ ranky_status topk_eigensolve(ranky_ctx *ctx, Engine &e, const Plan &plan, char *
         }
         prev_res = worst;
         // Chebyshev filter of X damping [0, b], b = the smallest Ritz value, scaled at theta_1;
-        // the degree keeps the growth of the leading direction below 1e7 so that the block
-        // stays well conditioned for the orthonormalisation
+        // the degree keeps the growth of the leading direction within what the
+        // orthonormalisation takes: the shifted Cholesky-QR pass any condition number below
+        // about 1/u (growth 1e10, degree up to 16), SVQB about 1/sqrt(u) (1e7, degree 8)
+        const bool chol = p <= kTopkCholMax;
+        const double growth = chol ? 1e10 : 1e7;
+        const int32_t max_deg = chol ? 16 : 8;
         const double b = std::max(rb_host[p - 1], th0 * 1e-12);
         const double c = 0.5 * b, ew = 0.5 * b;
         const double x0 = (th0 - c) / ew;
         int32_t m = 1;
         if (x0 > 1.0) {
             const double ac = std::acosh(x0);
-            while (m < 8 && std::cosh((m + 1) * ac) <= 1e7) ++m;
+            while (m < max_deg && std::cosh((m + 1) * ac) <= growth) ++m;
         }
         const double sigma1 = ew / (th0 - c);
         const double tau = 2.0 / sigma1;
