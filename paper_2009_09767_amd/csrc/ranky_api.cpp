@@ -528,7 +528,10 @@ struct Engine {
     int32_t round_launches = 0;
     size_t jround_lds = 0;           // dynamic LDS of the round launches (one workgroup per CU when set)
 
-    char *stage() { return static_cast<char *>(ctx->pinned); }
+    // this engine's part of the context's pinned staging: an engine made while another one's
+    // uploads may still be pending (the subspace iteration's p x p Jacobi) stages past it
+    size_t stage_off = 0;
+    char *stage() { return static_cast<char *>(ctx->pinned) + stage_off; }
     MatDesc *ddesc() { return reinterpret_cast<MatDesc *>(hdr + h.o_desc); }
     int32_t *dwp(int ph) { return reinterpret_cast<int32_t *>(hdr + h.o_wp) + (size_t)ph * (h.slots + 1); }
     int32_t *drwp(int r) { return reinterpret_cast<int32_t *>(hdr + h.o_rwp) + (size_t)r * (h.slots + 1); }
@@ -688,7 +691,7 @@ struct Engine {
     }
 
     // sweep state per matrix (active, sweeps, not converged), written by the device
-    int32_t *js_dev() { return reinterpret_cast<int32_t *>(static_cast<char *>(ctx->pinned_dev) + h.o_js); }
+    int32_t *js_dev() { return reinterpret_cast<int32_t *>(static_cast<char *>(ctx->pinned_dev) + stage_off + h.o_js); }
     const int32_t *js_host() { return reinterpret_cast<const int32_t *>(stage() + h.o_js); }
     int32_t *epoch_dev() { return reinterpret_cast<int32_t *>(hdr + h.o_js); }
     volatile int32_t *epoch_host() { return reinterpret_cast<volatile int32_t *>(stage() + h.o_js) + 3 * count; }
@@ -821,9 +824,11 @@ struct Engine {
     }
 };
 
-ranky_status make_engine(ranky_ctx *ctx, hipStream_t s, const Header &h, char *hdr, int count, Engine &e) {
-    ranky_status st = ensure_pinned(ctx, h.total);
+ranky_status make_engine(ranky_ctx *ctx, hipStream_t s, const Header &h, char *hdr, int count, Engine &e,
+                         size_t stage_off = 0) {
+    ranky_status st = ensure_pinned(ctx, stage_off + h.total);
     if (st) return st;
+    e.stage_off = stage_off;
     e.ctx = ctx;
     e.s = s;
     e.count = count;
@@ -948,10 +953,11 @@ ranky_status topk_eigensolve(ranky_ctx *ctx, Engine &e, const Plan &plan, char *
     // values and residuals (2p doubles) goes through the pinned staging past both headers.  The
     // staging is sized first, so that no later growth drops what the small engine stages there.
     const Header hs = make_header(1, 1, p / kJacobiBlock);
-    const size_t rb_off = align_up(std::max(hs.total, e.h.total));
+    const size_t small_off = align_up(e.stage_off + e.h.total);   // the main engine's uploads may be pending
+    const size_t rb_off = align_up(small_off + hs.total);
     ranky_status st = ensure_pinned(ctx, rb_off + sizeof(double) * 2 * (size_t)p + sizeof(int32_t));
     if (st) return st;
-    st = make_engine(ctx, s, hs, t.base + t.L.o_hdr, 1, t.es);
+    st = make_engine(ctx, s, hs, t.base + t.L.o_hdr, 1, t.es, small_off);
     if (st) return st;
     MatDesc jd;
     std::memset(&jd, 0, sizeof(jd));
@@ -1241,9 +1247,10 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
         if (x.n > 0) launch_rr_h(Av, j.N, k, rf.U0, rf.part, kpad, x.G, s);
         else launch_fill_f64(x.G, (int64_t)kpad * kpad, 0.0, s);
         HIP_TRY(hipGetLastError());
-        // the main matrix's header entries are no longer read: reuse them for H
+        // the main matrix's header entries are no longer read: reuse them for H (staged past
+        // the main engine's staging, whose last upload may still be pending)
         Engine eh;
-        st = make_engine(ctx, s, h, ws, 1, eh);
+        st = make_engine(ctx, s, h, ws, 1, eh, align_up(e.stage_off + e.h.total));
         if (st) return st;
         eh.sweeps_cap = o.max_sweeps;
         eh.d.assign(1, x);

@@ -161,3 +161,25 @@ def test_result_independent_of_workspace_contents(R, split):
         outs.append((o.sigma.clone(), o.U.clone(), o.V.clone()))
     for s, U, V in outs[1:]:
         assert torch.equal(s, outs[0][0]) and torch.equal(U, outs[0][1]) and torch.equal(V, outs[0][2])
+
+
+def test_split_with_long_light_columns(R, orc):
+    """A few columns with an entry in every row (long columns of the light CSC, walked by many
+    rows at once): the split's result equals the oracle's."""
+    rng = np.random.default_rng(106)
+    M, N = 400, 1 << 14
+    A0 = powerlaw(M, N, 300_000, 1.2, 107, np.float64, "normal")
+    full = np.array([5, 777, 9000])
+    rows = np.concatenate([A0.rowidx, np.tile(np.arange(M), full.size)])
+    cols = np.concatenate([np.repeat(np.arange(A0.N), np.diff(A0.colptr)), np.repeat(full, M)])
+    flat = np.unique(cols.astype(np.int64) * M + rows)
+    cols, rows = flat // M, flat % M
+    A = gen.from_coo(M, N, rows, cols, rng.standard_normal(rows.size), dict(name="long_light_cols"))
+    k = 24
+    got = R.svd(R.to_device(A), k, 0.0, gram_split="on", eigensolver="jacobi")
+    ref = orc.svd(A.M, A.N, A.colptr, A.rowidx, A.values, k=k, method="whole_qr")
+    assert got.info["heavy_rows"] > 0
+    assert got.info["rank"] == ref.rank
+    err = H.rel_sigma_err(got.sigma.cpu().numpy(), ref.sigma, ref.rank)
+    scaled, _ = H.vector_errors(got.U.cpu().numpy()[:, :ref.rank], ref.U[:, :ref.rank], ref.sigma, ref.rank)
+    assert err <= 1e-10 and scaled <= 1e-10
