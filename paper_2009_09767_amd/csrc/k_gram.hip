@@ -74,16 +74,18 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
         return;
     }
     Acc *acc = reinterpret_cast<Acc *>(lds_raw);                  // nw x M
-    // nw x kDenseRows x 64 lane-private slots, 16-byte aligned (M may be odd)
+    // nw x kDenseRows x 64 lane-private slots, 16-byte aligned (M may be odd); none with the
+    // heavy-row split, whose dense rows' pairs come from the gathers
+    const int nslot = dsc.hwg > 0 ? 0 : kDenseRows * 64;
     Acc *dslot = reinterpret_cast<Acc *>(reinterpret_cast<char *>(lds_raw) +
                                          ((((size_t)nw * M * sizeof(Acc)) + 15) & ~(size_t)15));
-    int32_t *tag = reinterpret_cast<int32_t *>(dslot + (size_t)nw * kDenseRows * 64);  // M, shared
+    int32_t *tag = reinterpret_cast<int32_t *>(dslot + (size_t)nw * nslot);  // M, shared
     int8_t *dmap = reinterpret_cast<int8_t *>(tag + M);  // M: dense index or -1
     __shared__ Acc dsum[16];
     __syncthreads();
     for (int32_t t = threadIdx.x; t < nw * M; t += blockDim.x) acc[t] = Acc(0);
     for (int32_t t = threadIdx.x; t < M; t += blockDim.x) tag[t] = kTagFree;
-    for (int32_t t = threadIdx.x; t < nw * kDenseRows * 64; t += blockDim.x) dslot[t] = Acc(0);
+    for (int32_t t = threadIdx.x; t < nw * nslot; t += blockDim.x) dslot[t] = Acc(0);
     for (int32_t t = threadIdx.x; t < M; t += blockDim.x) dmap[t] = -1;
     __syncthreads();
     if (threadIdx.x < kDenseRows && dense[threadIdx.x] >= 0) dmap[dense[threadIdx.x]] = (int8_t)threadIdx.x;
@@ -107,7 +109,7 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
     const int32_t we = (wb + run < e_end) ? wb + run : e_end;
     Acc *my = acc + (size_t)wave * M;
     const int32_t gid = threadIdx.x;   // workgroup-wide id in the election
-    Acc *myslot = dslot + (size_t)wave * kDenseRows * 64 + lane;
+    Acc *myslot = dslot + (size_t)wave * nslot + lane;   // not used with the heavy split
     Acc dg = Acc(0);
 
     // Each lane walks the later entries of its column kGramStep steps at a time: the
@@ -814,26 +816,27 @@ void launch_gram_dense_reduce(const MatDesc *descs, int32_t dwg, hipStream_t s) 
     hipLaunchKernelGGL(k_gram_dense_reduce, dim3(1), dim3(kDenseRows * kDenseRows), 0, s, descs);
 }
 
-// LDS per wave: one accumulator row and the lane-private dense slots; per workgroup:
-// the shared tag row, one dense-index byte per row and the alignment pad.
-static size_t gram_wave_bytes(int32_t M, int32_t acc_bytes) {
-    return (size_t)M * acc_bytes + (size_t)kDenseRows * 64 * acc_bytes;
+// LDS per wave: one accumulator row and the lane-private dense slots (none with the heavy-row
+// split, whose dense rows' pairs come from the gathers); per workgroup: the shared tag row, one
+// dense-index byte per row and the alignment pad.
+static size_t gram_wave_bytes(int32_t M, int32_t acc_bytes, bool slots) {
+    return (size_t)M * acc_bytes + (slots ? (size_t)kDenseRows * 64 * acc_bytes : 0);
 }
 
 static size_t gram_fixed_bytes(int32_t M) {
     return (size_t)M * sizeof(int32_t) + (((size_t)M + 15) & ~(size_t)15) + 16;
 }
 
-int gram_waves(int32_t M, int32_t acc_bytes, size_t lds_limit) {
+int gram_waves(int32_t M, int32_t acc_bytes, size_t lds_limit, bool slots) {
     const size_t fixed = gram_fixed_bytes(M);
-    int w = lds_limit > fixed ? (int)((lds_limit - fixed) / gram_wave_bytes(M, acc_bytes)) : 1;
+    int w = lds_limit > fixed ? (int)((lds_limit - fixed) / gram_wave_bytes(M, acc_bytes, slots)) : 1;
     if (w > 8) w = 8;
     if (w < 1) w = 1;
     return w;
 }
 
-size_t gram_lds_bytes(int32_t M, int32_t acc_bytes, int32_t nw) {
-    return (size_t)nw * gram_wave_bytes(M, acc_bytes) + gram_fixed_bytes(M);
+size_t gram_lds_bytes(int32_t M, int32_t acc_bytes, int32_t nw, bool slots) {
+    return (size_t)nw * gram_wave_bytes(M, acc_bytes, slots) + gram_fixed_bytes(M);
 }
 
 void launch_gram(const MatDesc *descs, const int32_t *wp, int64_t nblocks, const int32_t *wp_red, int64_t nblocks_red,

@@ -37,8 +37,9 @@ hipError_t occupancy_set_attributes(int32_t maxM);
 // Gram (k_gram.hip)
 // waves per Gram workgroup of an M-row matrix (a function of the matrix alone: it fixes the
 // order of the sums) and the LDS that matrix's workgroups use with nw waves
-int gram_waves(int32_t M, int32_t acc_bytes, size_t lds_limit);
-size_t gram_lds_bytes(int32_t M, int32_t acc_bytes, int32_t nw);
+// slots: the walk keeps lane-private slots for the dense rows (not with the heavy-row split)
+int gram_waves(int32_t M, int32_t acc_bytes, size_t lds_limit, bool slots = true);
+size_t gram_lds_bytes(int32_t M, int32_t acc_bytes, int32_t nw, bool slots = true);
 int64_t gram_part_slots(int64_t nnz);   // partial Gram rows the workspace must hold
 // max_waves, lds_bytes: the largest MatDesc::gwaves and LDS over the launch's matrices
 void launch_gram(const MatDesc *descs, const int32_t *wp, int64_t nblocks, const int32_t *wp_red, int64_t nblocks_red,

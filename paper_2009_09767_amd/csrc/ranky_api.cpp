@@ -493,7 +493,7 @@ void gram_shape(const std::vector<MatDesc> &d, size_t lds_limit, int32_t &max_wa
     for (const MatDesc &x : d) {
         const int32_t acc = x.prec == RANKY_PREC_FP64 ? 8 : 4;
         max_waves = std::max(max_waves, x.gwaves);
-        lds_bytes = std::max(lds_bytes, gram_lds_bytes(x.M, acc, x.gwaves));   // <= lds_limit by gram_waves
+        lds_bytes = std::max(lds_bytes, gram_lds_bytes(x.M, acc, x.gwaves, x.hwg == 0));   // <= lds_limit by gram_waves
     }
     (void)lds_limit;
 }
@@ -1163,7 +1163,7 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
             x.bp_per_cu = tc->second.bp_per_cu;
             x.jsched = tc->second.jsched;
         }
-        x.gwaves = gram_waves(x.M, x.prec == RANKY_PREC_FP64 ? 8 : 4, ctx->lds_limit);
+        x.gwaves = gram_waves(x.M, x.prec == RANKY_PREC_FP64 ? 8 : 4, ctx->lds_limit, x.hwg == 0);
         // unit roundoff of the Gram entries as they are computed: FP64, FP32, or the bf16x3
         // products (2^-16) when the split-bf16 tiles run (a single matrix; the selection
         // falls back to 2^-24 when the scan found fewer than two dense rows, since then no tile
@@ -2060,7 +2060,7 @@ ranky_status ranky_gram(const ranky_csc *A, int32_t M, int64_t N, int32_t prec, 
     MatDesc &x = e.d[0];
     x.prec = prec;
     if (x.prec != RANKY_PREC_BF16X3) x.dwg = 0;
-    x.gwaves = gram_waves(M, prec == RANKY_PREC_FP64 ? 8 : 4, sc.c.lds_limit);
+    x.gwaves = gram_waves(M, prec == RANKY_PREC_FP64 ? 8 : 4, sc.c.lds_limit, x.hwg == 0);
     if (x.n > 0) {
         e.nblk[kPhGram] = fill_wp(e.hwp(kPhGram), 1, [&](int) { return (int64_t)e.gsegs[0] + (x.npad - x.n); });
         e.nblk[kPhGramRed] = fill_wp(e.hwp(kPhGramRed), 1, [&](int) { return (int64_t)x.n; });
