@@ -139,15 +139,30 @@ __global__ __launch_bounds__(256) void k_gather_u(const MatDesc *__restrict__ de
     }
 }
 
+// Lane q's copy of v, a wave-uniform lane index q (an FP64 value as its two halves).
+template <typename T>
+__device__ inline double readlane_val(T v, int32_t q) {
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t b = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)b, q);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)(b >> 32), q);
+        return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+    } else {
+        return static_cast<double>(__builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int32_t, v), q)));
+    }
+}
+
 // V[j][i] = (sum over the nonzeros a_mj of column j of a_mj U[m][i]) / sigma[i] for
 // i < rank, else 0.  A wave handles one column at a time, over a contiguous run of
 // columns whose bounds it loads 64 at a time; a lane owns P pairs of outputs, i = i0 + 128 p + 2 lane (P = 1 for k <= 128,
 // 2 for k <= 256, 4 above: one pass over the columns covers k <= 512), so every load of
-// a U row and every store of a V row is one contiguous 1 KB per wave, and the column's
-// dependent chain (bounds -> row index -> U row) is walked once per pass.  The column's
-// nonzeros are taken four (P = 1) or two at a time with independent loads; each output
-// adds them in order.  U rows come from L2, and V goes out with non-temporal stores so
-// it does not evict them.
+// a U row and every store of a V row is one contiguous 1 KB per wave.  The run's nonzeros
+// are contiguous in the CSC arrays: their row indices and values stream through a window
+// of 128 entries in registers (lane t holding entries w + t and w + 64 + t), refilled 64 at a
+// time one refill ahead, so a column's only wait is on its U rows.  The column's nonzeros
+// are taken four (P = 1) or two at a time with independent loads (a shorter tail as one
+// step); each output adds them in order.  U rows come from L2, and V goes out with
+// non-temporal stores so it does not evict them.
 template <typename TV, typename TO, typename TU, int P>
 __device__ void backproject_cols(const int32_t *__restrict__ colptr_, const int32_t *__restrict__ rowidx_,
                                  const TV *__restrict__ vals_, int64_t N, int32_t k, const TU *__restrict__ U_,
@@ -161,6 +176,12 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr_, const int3
     const auto V = gmem(V_);
     constexpr int kNz = P == 1 ? 4 : 2;
     const int lane = threadIdx.x & 63;
+    // a contiguous run of columns per wave: each line of colptr / rowidx / values is
+    // then read by one wave, hence one XCD's L2 (a stride would pull it into all of them)
+    const int64_t per = (N + nwaves - 1) / nwaves;
+    const int64_t jb = wave * per, je = jb + per < N ? jb + per : N;
+    if (jb >= je) return;
+    const int32_t eend = colptr[je];
     for (int32_t i0 = 0; i0 < k; i0 += 128 * P) {
         int32_t i[P];
         bool ok0[P], ok1[P], live0[P], live1[P];
@@ -175,10 +196,63 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr_, const int3
             s0[p] = live0[p] ? sigma[i[p]] : 0.0;
             s1[p] = live1[p] ? sigma[i[p] + 1] : 0.0;
         }
-        // a contiguous run of columns per wave: each line of colptr / rowidx / values is
-        // then read by one wave, hence one XCD's L2 (a stride would pull it into all of them)
-        const int64_t per = (N + nwaves - 1) / nwaves;
-        const int64_t jb = wave * per, je = jb + per < N ? jb + per : N;
+        // the entry window [w, w + 128)
+        int32_t w = colptr[jb];
+        int32_t r_lo, r_hi;
+        TV v_lo, v_hi;
+        auto fill = [&](int32_t at, int32_t &r, TV &v) {
+            const int32_t q = at + lane;
+            r = q < eend ? rowidx[q] : 0;
+            v = q < eend ? vals[q] : TV(0);
+        };
+        fill(w, r_lo, v_lo);
+        fill(w + 64, r_hi, v_hi);
+        // entry e (w <= e < w + 128): its U row and value
+        auto take = [&](int32_t e, __attribute__((address_space(1))) const TU *&Um, double &a) {
+            const int32_t q = e - w;
+            const int32_t m = q < 64 ? __builtin_amdgcn_readlane(r_lo, q) : __builtin_amdgcn_readlane(r_hi, q - 64);
+            a = q < 64 ? readlane_val(v_lo, q) : readlane_val(v_hi, q - 64);
+            Um = U + (int64_t)m * k;
+        };
+        // the step's n <= kNz nonzeros: every U load issued before the first addition
+        auto add = [&](double *a0, double *a1, const double *av,
+                       __attribute__((address_space(1))) const TU *const *Um, int n) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                double ux[kNz], uy[kNz];
+                if (ok1[p]) {
+#pragma unroll
+                    for (int t = 0; t < kNz; ++t) {
+                        ux[t] = uy[t] = 0.0;
+                        if (t < n) {
+                            ux[t] = static_cast<double>(Um[t][i[p]]);
+                            uy[t] = static_cast<double>(Um[t][i[p] + 1]);
+                        }
+                    }
+                    double x = a0[p], y = a1[p];
+#pragma unroll
+                    for (int t = 0; t < kNz; ++t) {
+                        if (t < n) {
+                            x = fma(av[t], ux[t], x);
+                            y = fma(av[t], uy[t], y);
+                        }
+                    }
+                    a0[p] = x;
+                    a1[p] = y;
+                } else if (ok0[p]) {
+#pragma unroll
+                    for (int t = 0; t < kNz; ++t) {
+                        ux[t] = 0.0;
+                        if (t < n) ux[t] = static_cast<double>(Um[t][i[p]]);
+                    }
+                    double x = a0[p];
+#pragma unroll
+                    for (int t = 0; t < kNz; ++t)
+                        if (t < n) x = fma(av[t], ux[t], x);
+                    a0[p] = x;
+                }
+            }
+        };
         for (int64_t jc = jb; jc < je; jc += 64) {
             // the bounds of the next 64 columns in one load, lane t holding column jc + t's
             // (clamped to the run's last column, so jl + 1 <= N); each column reads its pair
@@ -193,46 +267,30 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr_, const int3
                 double a0[P], a1[P];
 #pragma unroll
                 for (int p = 0; p < P; ++p) a0[p] = a1[p] = 0.0;
-                int32_t e = e0;
-                // kNz nonzeros per step with independent loads (their U rows in flight together)
-                for (; e + kNz <= e1; e += kNz) {
+                for (int32_t e = e0; e < e1; e += kNz) {
+                    // e < w + 64 on entry to every step (steps advance by kNz <= 64), so the
+                    // step's entries lie in the window
+                    if (e >= w + 64) {
+                        w += 64;
+                        r_lo = r_hi;
+                        v_lo = v_hi;
+                        fill(w + 64, r_hi, v_hi);
+                    }
                     double av[kNz];
                     __attribute__((address_space(1))) const TU *Um[kNz];
+                    if (e + kNz <= e1) {
 #pragma unroll
-                    for (int t = 0; t < kNz; ++t) {
-                        av[t] = static_cast<double>(vals[e + t]);
-                        Um[t] = U + (int64_t)rowidx[e + t] * k;
-                    }
+                        for (int t = 0; t < kNz; ++t) take(e + t, Um[t], av[t]);
+                        add(a0, a1, av, Um, kNz);
+                    } else {
+                        const int n = e1 - e;
 #pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        if (ok1[p]) {
-                            double x = a0[p], y = a1[p];
-#pragma unroll
-                            for (int t = 0; t < kNz; ++t) {
-                                x = fma(av[t], static_cast<double>(Um[t][i[p]]), x);
-                                y = fma(av[t], static_cast<double>(Um[t][i[p] + 1]), y);
-                            }
-                            a0[p] = x;
-                            a1[p] = y;
-                        } else if (ok0[p]) {
-                            double x = a0[p];
-#pragma unroll
-                            for (int t = 0; t < kNz; ++t) x = fma(av[t], static_cast<double>(Um[t][i[p]]), x);
-                            a0[p] = x;
+                        for (int t = 0; t < kNz; ++t) {
+                            Um[t] = U;
+                            av[t] = 0.0;
+                            if (t < n) take(e + t, Um[t], av[t]);
                         }
-                    }
-                }
-                for (; e < e1; ++e) {
-                    const double a = static_cast<double>(vals[e]);
-                    const auto Um = U + (int64_t)rowidx[e] * k;
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        if (ok1[p]) {
-                            a0[p] = fma(a, static_cast<double>(Um[i[p]]), a0[p]);
-                            a1[p] = fma(a, static_cast<double>(Um[i[p] + 1]), a1[p]);
-                        } else if (ok0[p]) {
-                            a0[p] = fma(a, static_cast<double>(Um[i[p]]), a0[p]);
-                        }
+                        add(a0, a1, av, Um, n);
                     }
                 }
 #pragma unroll
@@ -243,9 +301,9 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr_, const int3
                     if (ok1[p] && (k & 1) == 0) {
                         // one 2-wide store (i and k are even, so it is aligned)
                         typedef TO TO2 __attribute__((ext_vector_type(2)));
-                        const TO2 w = {static_cast<TO>(v0), static_cast<TO>(v1)};
+                        const TO2 w2 = {static_cast<TO>(v0), static_cast<TO>(v1)};
                         __builtin_nontemporal_store(
-                            w, reinterpret_cast<__attribute__((address_space(1))) TO2 *>(out));
+                            w2, reinterpret_cast<__attribute__((address_space(1))) TO2 *>(out));
                     } else if (ok1[p]) {
                         __builtin_nontemporal_store(static_cast<TO>(v0), out);
                         __builtin_nontemporal_store(static_cast<TO>(v1), out + 1);
@@ -266,7 +324,9 @@ __global__ __launch_bounds__(256) void k_backproject(const MatDesc *__restrict__
                                                      int count) {
     const int mat = find_mat(wp, count, blockIdx.x);
     const MatDesc &d = descs[mat];
-    const int64_t wave = (((int64_t)blockIdx.x - wp[mat]) * blockDim.x + threadIdx.x) >> 6;
+    // the wave index is wave-uniform: readfirstlane lets the compiler keep the run in scalars
+    const int64_t wave = (((int64_t)blockIdx.x - wp[mat]) * blockDim.x +
+                          __builtin_amdgcn_readfirstlane((int32_t)threadIdx.x)) >> 6;
     const int64_t nwaves = ((int64_t)(wp[mat + 1] - wp[mat]) * blockDim.x) >> 6;
     const int32_t rank = d.scal[kScRank];
     // an FP32 V reads the FP32 copy of U (half the bytes per gathered row)
@@ -304,7 +364,7 @@ __global__ __launch_bounds__(256) void k_backproject_one(const int32_t *__restri
                                                          const TU *__restrict__ U,
                                                          const double *__restrict__ sigma,
                                                          const int32_t *__restrict__ rank_ptr, TO *__restrict__ V) {
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + __builtin_amdgcn_readfirstlane((int32_t)threadIdx.x)) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     backproject_cols<TV, TO, TU, P>(colptr, rowidx, vals, N, k, U, sigma, *rank_ptr, V, wave, nwaves);
 }
