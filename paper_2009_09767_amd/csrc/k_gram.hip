@@ -526,9 +526,9 @@ __global__ __launch_bounds__(1024) void k_gram_dense_reduce(const MatDesc *__res
 //     quarter of it, summed in wave order into one partial tile per workgroup, which
 //     k_gram_heavy_reduce adds in a fixed tree over the workgroups;
 //   - the other ("light") rows' entries of every column are copied in row order to a light
-//     CSC (k_gram_light_scatter, after a scan of the per-column counts), and the row-major
-//     copy's positions of the light rows are rewritten to point into it (k_gram_light_slots):
-//     the walk then steps over light entries only;
+//     CSC (k_gram_light_scatter, after a scan of the per-column counts), before the transpose,
+//     which gives the light rows' row-major slots their positions in it: the walk then steps
+//     over light entries only;
 //   - every light row p adds sum_j a_pj aht[j] (one coalesced row per nonzero) in the walk
 //     kernel.
 // Every sum keeps an order fixed by the matrix alone, so the result is bitwise
@@ -626,58 +626,6 @@ __global__ __launch_bounds__(256) void k_gram_light_scatter(const MatDesc *__res
                 }
             }
         }
-    }
-}
-
-// Row-major slot e of a light row: its CSC position and column end become the light CSC's.
-// The dense rows' slots keep theirs (their workgroups do not walk) and are not visited: the
-// light slots are the gaps between the dense rows' runs, numbered flat in row order.
-__global__ __launch_bounds__(256) void k_gram_light_slots(const MatDesc *__restrict__ descs) {
-    __shared__ int64_t gap_lo[kDenseRows + 1], gap_at[kDenseRows + 2];   // gap g: slots from gap_lo[g], flat index gap_at[g]
-    __shared__ int ngap;
-    const MatDesc &d = descs[0];
-    const auto rowptr = gmem(d.rowptr);
-    const auto dense = gmem(d.dense);
-    if (threadIdx.x == 0) {
-        // the dense rows' runs in row order (insertion sort of at most kDenseRows rows)
-        int32_t rows[kDenseRows];
-        int n = 0;
-        for (int t = 0; t < kDenseRows; ++t) {
-            const int32_t q = dense[t];
-            if (q < 0) break;
-            int u = n++;
-            while (u > 0 && rows[u - 1] > q) {
-                rows[u] = rows[u - 1];
-                --u;
-            }
-            rows[u] = q;
-        }
-        int64_t lo = 0, at = 0;
-        for (int t = 0; t < n; ++t) {
-            gap_lo[t] = lo;
-            gap_at[t] = at;
-            at += rowptr[rows[t]] - lo;
-            lo = rowptr[rows[t] + 1];
-        }
-        gap_lo[n] = lo;
-        gap_at[n] = at;
-        gap_at[n + 1] = at + (d.nnz - lo);
-        ngap = n + 1;
-    }
-    __syncthreads();
-    const int ng = ngap;
-    const int64_t total = gap_at[ng];
-    const auto csr_k = gmem(d.csrk);
-    const auto csr_end = gmem(d.csrend);
-    const auto csr_col = gmem(d.csrcol);
-    const auto lpos = gmem(d.lpos);
-    const auto lptr = gmem(d.lptr);
-    int g = 0;   // this thread's flat indices only grow: its gap is found by moving forward
-    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < total; f += (int64_t)gridDim.x * blockDim.x) {
-        while (g + 1 < ng && gap_at[g + 1] <= f) ++g;
-        const int64_t e = gap_lo[g] + (f - gap_at[g]);
-        csr_k[e] = lpos[csr_k[e]];
-        csr_end[e] = lptr[csr_col[e] + 1];
     }
 }
 
@@ -789,7 +737,6 @@ void launch_gram_heavy_prep(const MatDesc *descs, const MatDesc &host, hipStream
     launch_exclusive_scan(host.lcnt, host.N, host.lbtot, host.lptr, s);
     if (host.dtype == 1) hipLaunchKernelGGL(k_gram_light_scatter<double>, dim3(g), dim3(256), 0, s, descs);
     else hipLaunchKernelGGL(k_gram_light_scatter<float>, dim3(g), dim3(256), 0, s, descs);
-    if (host.nnz > 0) hipLaunchKernelGGL(k_gram_light_slots, dim3(heavy_cols_grid(host.nnz)), dim3(256), 0, s, descs);
 }
 
 void launch_gram_heavy_tiles(const MatDesc *descs, int32_t dtype, int32_t hwg, hipStream_t s) {

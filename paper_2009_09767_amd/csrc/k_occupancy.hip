@@ -310,7 +310,9 @@ __global__ __launch_bounds__(1024) void k_occ_offsets(const MatDesc *__restrict_
 // mask does not depend on timing), read it back and count.  The entry's slot is
 // the row's running offset plus that rank; the lowest lane then advances the offset.
 // csr_k[slot] = CSC position of the entry, csr_end[slot] = end of its column,
-// csr_col[slot] = its column.
+// csr_col[slot] = its column.  With light = 1 (the heavy-row split, whose light CSC is built
+// first) an entry of a light row gets its position in the light CSC (lpos) and the end of its
+// column there (lptr) instead, so the Gram walk steps over light entries only.
 // The first kTrRegs row indices of each lane's column are held in registers for the
 // four passes, loaded (with the next group's column bounds) while the previous group's
 // passes run; entries past kTrRegs are read from memory in each pass.
@@ -327,8 +329,19 @@ __device__ __forceinline__ void tr_load_rows(__attribute__((address_space(1))) c
     }
 }
 
+// Slot values of entry e (row-major slot written by the second pass): the CSC position and
+// column end, or, for a light row under the split (lp = lpos[e] >= 0), the light CSC's.
+__device__ __forceinline__ void tr_slot(__attribute__((address_space(1))) int32_t *csr_k,
+                                        __attribute__((address_space(1))) int32_t *csr_end,
+                                        __attribute__((address_space(1))) int32_t *csr_col, int32_t slot, int32_t e,
+                                        int32_t e1, int32_t lp, int32_t lend, int32_t j) {
+    csr_k[slot] = lp >= 0 ? lp : e;
+    csr_end[slot] = lp >= 0 ? lend : e1;
+    csr_col[slot] = j;
+}
+
 __global__ __launch_bounds__(64) void k_transpose(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
-                                                  int count) {
+                                                  int count, int light_) {
     const int mat = find_mat(wp, count, blockIdx.x);
     const MatDesc &d = descs[mat];
     if (d.nnz == 0) return;
@@ -338,6 +351,9 @@ __global__ __launch_bounds__(64) void k_transpose(const MatDesc *__restrict__ de
     const auto csr_k = gmem(d.csrk);
     const auto csr_end = gmem(d.csrend);
     const auto csr_col = gmem(d.csrcol);
+    const bool light = light_ != 0 && d.hwg > 0;
+    const auto lpos = gmem(d.lpos);
+    const auto lptr = gmem(d.lptr);
     extern __shared__ uint64_t lds_mask[];
     int32_t *ctr = reinterpret_cast<int32_t *>(lds_mask + M);
     const int64_t c = blockIdx.x - wp[mat];
@@ -351,46 +367,50 @@ __global__ __launch_bounds__(64) void k_transpose(const MatDesc *__restrict__ de
     const int lane = threadIdx.x;
     const uint64_t bit = 1ull << lane;
     const uint64_t lower = bit - 1;
-    int32_t e0 = 0, e1 = 0;
+    int32_t e0 = 0, e1 = 0, lend = 0;
     if (c0 + lane < c1) {
         e0 = colptr[c0 + lane];
         e1 = colptr[c0 + lane + 1];
+        if (light) lend = lptr[c0 + lane + 1];
     }
-    int32_t rows[kTrRegs];
+    int32_t rows[kTrRegs], lps[kTrRegs];
     tr_load_rows(rowidx, e0, e1, rows);
+#pragma unroll
+    for (int t = 0; t < kTrRegs; ++t) lps[t] = -1;
+    if (light) tr_load_rows(lpos, e0, e1, lps);
     __syncthreads();
     for (int64_t g = c0; g < c1; g += 64) {
         const int64_t j = g + lane;
         const int32_t n = e1 - e0;
         // next group: bounds now, its rows after pass 1 (they are in flight during passes 2-4)
-        int32_t f0 = 0, f1 = 0;
+        int32_t f0 = 0, f1 = 0, fend = 0;
         if (j + 64 < c1) {
             f0 = colptr[j + 64];
             f1 = colptr[j + 65];
+            if (light) fend = lptr[j + 65];
         }
 #pragma unroll
         for (int t = 0; t < kTrRegs; ++t)
             if (t < n) atomicOr(reinterpret_cast<unsigned long long *>(&lds_mask[rows[t]]), bit);
         for (int32_t t = kTrRegs; t < n; ++t)
             atomicOr(reinterpret_cast<unsigned long long *>(&lds_mask[rowidx[e0 + t]]), bit);
-        int32_t next[kTrRegs];
+        int32_t next[kTrRegs], nlps[kTrRegs];
         tr_load_rows(rowidx, f0, f1, next);
+#pragma unroll
+        for (int t = 0; t < kTrRegs; ++t) nlps[t] = -1;
+        if (light) tr_load_rows(lpos, f0, f1, nlps);
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < kTrRegs; ++t)
             if (t < n) {
                 const int32_t r = rows[t];
                 const int32_t slot = ctr[r] + __popcll(lds_mask[r] & lower);
-                csr_k[slot] = e0 + t;
-                csr_end[slot] = e1;
-                csr_col[slot] = (int32_t)j;
+                tr_slot(csr_k, csr_end, csr_col, slot, e0 + t, e1, lps[t], lend, (int32_t)j);
             }
         for (int32_t t = kTrRegs; t < n; ++t) {
             const int32_t r = rowidx[e0 + t];
             const int32_t slot = ctr[r] + __popcll(lds_mask[r] & lower);
-            csr_k[slot] = e0 + t;
-            csr_end[slot] = e1;
-            csr_col[slot] = (int32_t)j;
+            tr_slot(csr_k, csr_end, csr_col, slot, e0 + t, e1, light ? lpos[e0 + t] : -1, lend, (int32_t)j);
         }
         __syncthreads();
 #pragma unroll
@@ -413,8 +433,12 @@ __global__ __launch_bounds__(64) void k_transpose(const MatDesc *__restrict__ de
         __syncthreads();
         e0 = f0;
         e1 = f1;
+        lend = fend;
 #pragma unroll
-        for (int t = 0; t < kTrRegs; ++t) rows[t] = next[t];
+        for (int t = 0; t < kTrRegs; ++t) {
+            rows[t] = next[t];
+            lps[t] = nlps[t];
+        }
     }
 }
 
@@ -528,10 +552,10 @@ void launch_row_offsets(const MatDesc *descs, const int32_t *wp_rows, int64_t n_
 }
 
 void launch_transpose(const MatDesc *descs, const int32_t *wp_chunks, int64_t n_chunk_blocks, int count, int32_t maxM,
-                      hipStream_t s) {
+                      bool light, hipStream_t s) {
     if (n_chunk_blocks <= 0) return;
     hipLaunchKernelGGL(k_transpose, dim3((unsigned)n_chunk_blocks), dim3(64), transpose_lds_bytes(maxM), s, descs,
-                       wp_chunks, count);
+                       wp_chunks, count, light ? 1 : 0);
 }
 
 size_t transpose_lds_bytes(int32_t M) { return (sizeof(uint64_t) + sizeof(int32_t)) * (size_t)M; }

@@ -685,9 +685,10 @@ struct Engine {
         return st;
     }
 
-    void enqueue_transpose() {
+    // light: the heavy-row split's light CSC is built (the Gram walk then steps over it)
+    void enqueue_transpose(bool light = false) {
         launch_row_offsets(ddesc(), dwp(kPhRows), nblk[kPhRows], count, s);
-        launch_transpose(ddesc(), dwp(kPhChunks), nblk[kPhChunks], count, maxM, s);
+        launch_transpose(ddesc(), dwp(kPhChunks), nblk[kPhChunks], count, maxM, light, s);
     }
 
     // sweep state per matrix (active, sweeps, not converged), written by the device
@@ -1193,13 +1194,14 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
     if (timing) hipEventRecord(ctx->ev[1], s);
     st = e.plan_rest();
     if (st) return st;
-    e.enqueue_transpose();
+    const bool heavy = count == 1 && e.d[0].hwg > 0;
+    if (heavy) launch_gram_heavy_prep(e.ddesc(), e.d[0], s);
+    e.enqueue_transpose(heavy);
     if (timing) hipEventRecord(ctx->ev[2], s);
     int32_t gram_nw = 1;
     size_t gram_lds = 0;
     gram_shape(e.d, ctx->lds_limit, gram_nw, gram_lds);
     if (count == 1) launch_gram_dense(e.ddesc(), e.d[0].dwg, s);
-    if (count == 1 && e.d[0].hwg > 0) launch_gram_heavy_prep(e.ddesc(), e.d[0], s);
     launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], e.dwp(kPhGramRed), e.nblk[kPhGramRed], count, gram_nw,
                 gram_lds, s);
     if (count == 1) launch_gram_dense_reduce(e.ddesc(), e.d[0].dwg, s);
@@ -2067,9 +2069,9 @@ ranky_status ranky_gram(const ranky_csc *A, int32_t M, int64_t N, int32_t prec, 
         st = e.upload_desc();
         if (!st) st = e.upload(e.h.o_wp, sizeof(int32_t) * (size_t)kPhCount * (e.h.slots + 1));
         if (st) return st;
-        e.enqueue_transpose();
-        launch_gram_dense(e.ddesc(), x.dwg, s);
         if (x.hwg > 0) launch_gram_heavy_prep(e.ddesc(), x, s);
+        e.enqueue_transpose(x.hwg > 0);
+        launch_gram_dense(e.ddesc(), x.dwg, s);
         int32_t gram_nw = 1;
         size_t gram_lds = 0;
         gram_shape(e.d, sc.c.lds_limit, gram_nw, gram_lds);
