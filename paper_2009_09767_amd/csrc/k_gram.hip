@@ -534,65 +534,85 @@ __global__ __launch_bounds__(1024) void k_gram_dense_reduce(const MatDesc *__res
 // Every sum keeps an order fixed by the matrix alone, so the result is bitwise
 // reproducible and independent of D.
 
-// Thread per column j (grid-stride): the row of aht is cleared, then the column's dense
-// entries are written into it (the same thread, so program order keeps the values), and the
-// column's other ("light") entries are counted.  The column is read kHbBatch entries at a time
-// with every load issued before the first use.
-constexpr int kHbBatch = 8;
+// Both kernels below take ranges of kHpCols consecutive columns, one workgroup (256 threads)
+// per range in turn: the range's entries are contiguous in the CSC, so they are read in
+// coalesced passes of 256 (thread t: entry base + t), an entry's column found by a binary search
+// over the range's column starts in LDS, its row's dense slot h from a byte map in LDS.
+constexpr int kHpCols = 256;
 
-template <typename TV>
-__global__ __launch_bounds__(256) void k_gram_heavy_build(const MatDesc *__restrict__ descs) {
-    __shared__ int8_t dmap[kMaxM];
-    const MatDesc &d = descs[0];
+// the range's dense-row map and column starts (cs[c] = colptr[c0 + c], c = 0 .. nc)
+__device__ __forceinline__ void hp_map(const MatDesc &d, int8_t *dmap) {
     const auto dense = gmem(d.dense);
     for (int32_t m = threadIdx.x; m < d.M; m += blockDim.x) dmap[m] = -1;
     __syncthreads();
     if (threadIdx.x < kDenseRows && dense[threadIdx.x] >= 0) dmap[dense[threadIdx.x]] = (int8_t)threadIdx.x;
     __syncthreads();
+}
+
+// the column (range-relative) of entry e: the largest c with cs[c] <= e (empty columns share
+// their start with the next column, so the column that holds e wins)
+__device__ __forceinline__ int32_t hp_col(const int32_t *cs, int32_t nc, int32_t e) {
+    int32_t lo = 0, hi = nc - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (cs[mid] <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// aht rows of the range cleared, then every dense entry a_{H[h], j} written to aht[j][h]; the
+// light entries counted per column (LDS counters, written to lcnt).  The clearing stores are
+// complete before the value stores start (the barrier between them).
+template <typename TV>
+__global__ __launch_bounds__(256) void k_gram_heavy_build(const MatDesc *__restrict__ descs) {
+    __shared__ int8_t dmap[kMaxM];
+    __shared__ int32_t cs[kHpCols + 1], cnt[kHpCols];
+    const MatDesc &d = descs[0];
+    hp_map(d, dmap);
     const auto colptr = gmem(d.colptr);
     const auto rowidx = gmem(d.rowidx);
     const auto vals = gmem(static_cast<const TV *>(d.values));
     const auto aht = gmem(static_cast<TV *>(d.aht));
     const auto lcnt = gmem(d.lcnt);
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < d.N; j += (int64_t)gridDim.x * blockDim.x) {
-        auto row = aht + j * kDenseRows;
-#pragma unroll
-        for (int h = 0; h < kDenseRows; ++h) row[h] = TV(0);
-        const int32_t e0 = colptr[j], e1 = colptr[j + 1];
-        int32_t light = 0;
-        for (int32_t base = e0; base < e1; base += kHbBatch) {
-            int32_t rr[kHbBatch];
-            TV vv[kHbBatch];
-#pragma unroll
-            for (int u = 0; u < kHbBatch; ++u) {
-                const int32_t at = base + u < e1 ? base + u : e1 - 1;
-                rr[u] = rowidx[at];
-                vv[u] = vals[at];
-            }
-#pragma unroll
-            for (int u = 0; u < kHbBatch; ++u) {
-                if (base + u < e1) {
-                    const int h = dmap[rr[u]];
-                    if (h >= 0) row[h] = vv[u];
-                    else ++light;
-                }
+    const int64_t N = d.N, ranges = (N + kHpCols - 1) / kHpCols;
+    for (int64_t r = blockIdx.x; r < ranges; r += gridDim.x) {
+        const int64_t c0 = r * kHpCols;
+        const int32_t nc = (int32_t)(N - c0 < kHpCols ? N - c0 : kHpCols);
+        for (int32_t c = threadIdx.x; c <= nc; c += blockDim.x) cs[c] = colptr[c0 + c];
+        for (int32_t c = threadIdx.x; c < nc; c += blockDim.x) cnt[c] = 0;
+        // clear the range's rows of aht (contiguous: nc * kDenseRows values)
+        const int64_t nv = (int64_t)nc * kDenseRows;
+        for (int64_t t = threadIdx.x; t < nv; t += blockDim.x) aht[c0 * kDenseRows + t] = TV(0);
+        __syncthreads();
+        const int64_t e0 = cs[0], e1 = cs[nc];
+        for (int64_t base = e0; base < e1; base += blockDim.x) {
+            const int64_t e = base + threadIdx.x;
+            if (e < e1) {
+                const int32_t m = rowidx[e];
+                const TV v = vals[e];
+                const int32_t c = hp_col(cs, nc, (int32_t)e);
+                const int h = dmap[m];
+                if (h >= 0) aht[(c0 + c) * kDenseRows + h] = v;
+                else atomicAdd(&cnt[c], 1);
             }
         }
-        lcnt[j] = light;
+        __syncthreads();
+        for (int32_t c = threadIdx.x; c < nc; c += blockDim.x) lcnt[c0 + c] = cnt[c];
+        __syncthreads();
     }
 }
 
-// Thread per column j: the light entries, in row order, to the light CSC at lptr[j], and every
-// entry's light position (-1 for a dense row's) to lpos.
+// The light entries in CSC order to the light CSC: a range's light entries start at lptr[c0]
+// and keep their order, so entry e's position is that start plus the number of light entries
+// before it in the range (a prefix count over the 256-entry passes: ballots within a wave,
+// the waves' totals through LDS).  lpos[e] = that position, -1 for a dense row's entry.
 template <typename TV>
 __global__ __launch_bounds__(256) void k_gram_light_scatter(const MatDesc *__restrict__ descs) {
     __shared__ int8_t dmap[kMaxM];
+    __shared__ int32_t wtot[4];
     const MatDesc &d = descs[0];
-    const auto dense = gmem(d.dense);
-    for (int32_t m = threadIdx.x; m < d.M; m += blockDim.x) dmap[m] = -1;
-    __syncthreads();
-    if (threadIdx.x < kDenseRows && dense[threadIdx.x] >= 0) dmap[dense[threadIdx.x]] = (int8_t)threadIdx.x;
-    __syncthreads();
+    hp_map(d, dmap);
     const auto colptr = gmem(d.colptr);
     const auto rowidx = gmem(d.rowidx);
     const auto vals = gmem(static_cast<const TV *>(d.values));
@@ -600,31 +620,38 @@ __global__ __launch_bounds__(256) void k_gram_light_scatter(const MatDesc *__res
     const auto lrow = gmem(d.lrowidx);
     const auto lval = gmem(static_cast<TV *>(d.lvals));
     const auto lpos = gmem(d.lpos);
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < d.N; j += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t e0 = colptr[j], e1 = colptr[j + 1];
-        int32_t out = lptr[j];
-        for (int32_t base = e0; base < e1; base += kHbBatch) {
-            int32_t rr[kHbBatch];
-            TV vv[kHbBatch];
-#pragma unroll
-            for (int u = 0; u < kHbBatch; ++u) {
-                const int32_t at = base + u < e1 ? base + u : e1 - 1;
-                rr[u] = rowidx[at];
-                vv[u] = vals[at];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t N = d.N, ranges = (N + kHpCols - 1) / kHpCols;
+    for (int64_t r = blockIdx.x; r < ranges; r += gridDim.x) {
+        const int64_t c0 = r * kHpCols;
+        const int64_t c1 = c0 + kHpCols < N ? c0 + kHpCols : N;
+        const int64_t e0 = colptr[c0], e1 = colptr[c1];
+        int32_t out = lptr[c0];
+        for (int64_t base = e0; base < e1; base += blockDim.x) {
+            const int64_t e = base + threadIdx.x;
+            int32_t m = 0;
+            TV v = TV(0);
+            bool light = false;
+            if (e < e1) {
+                m = rowidx[e];
+                v = vals[e];
+                light = dmap[m] < 0;
             }
-#pragma unroll
-            for (int u = 0; u < kHbBatch; ++u) {
-                if (base + u < e1) {
-                    if (dmap[rr[u]] < 0) {
-                        lrow[out] = rr[u];
-                        lval[out] = vv[u];
-                        lpos[base + u] = out;
-                        ++out;
-                    } else {
-                        lpos[base + u] = -1;
-                    }
+            const uint64_t bal = __builtin_amdgcn_ballot_w64(light);
+            if (lane == 0) wtot[wave] = __popcll(bal);
+            __syncthreads();
+            int32_t before = out;
+            for (int w = 0; w < wave; ++w) before += wtot[w];
+            const int32_t pos = before + __popcll(bal & ((1ull << lane) - 1));
+            if (e < e1) {
+                if (light) {
+                    lrow[pos] = m;
+                    lval[pos] = v;
                 }
+                lpos[e] = light ? pos : -1;
             }
+            out += wtot[0] + wtot[1] + wtot[2] + wtot[3];
+            __syncthreads();
         }
     }
 }
@@ -724,7 +751,7 @@ int32_t gram_heavy_wgs(int64_t N) {
 }
 
 static unsigned heavy_cols_grid(int64_t n) {
-    int64_t b = (n + 255) / 256;
+    int64_t b = (n + kHpCols - 1) / kHpCols;
     if (b > 8192) b = 8192;
     return (unsigned)(b < 1 ? 1 : b);
 }
