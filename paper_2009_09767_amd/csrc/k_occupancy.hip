@@ -312,7 +312,8 @@ __global__ __launch_bounds__(1024) void k_occ_offsets(const MatDesc *__restrict_
 // csr_k[slot] = CSC position of the entry, csr_end[slot] = end of its column,
 // csr_col[slot] = its column.  With light = 1 (the heavy-row split, whose light CSC is built
 // first) an entry of a light row gets its position in the light CSC (lpos) and the end of its
-// column there (lptr) instead, so the Gram walk steps over light entries only.
+// column there (lptr) instead, so the Gram walk steps over light entries only; the dense rows'
+// entries are then skipped altogether (their slots are never read).
 // The first kTrRegs row indices of each lane's column are held in registers for the
 // four passes, loaded (with the next group's column bounds) while the previous group's
 // passes run; entries past kTrRegs are read from memory in each pass.
@@ -379,6 +380,10 @@ __global__ __launch_bounds__(64) void k_transpose(const MatDesc *__restrict__ de
     for (int t = 0; t < kTrRegs; ++t) lps[t] = -1;
     if (light) tr_load_rows(lpos, e0, e1, lps);
     __syncthreads();
+    // with the split, only the light rows' entries take part (the dense rows' slots are never
+    // read: their workgroups do not walk)
+    auto on_reg = [&](int t) { return t < (e1 - e0) && (!light || lps[t] >= 0); };
+    auto on_mem = [&](int32_t e) { return !light || lpos[e] >= 0; };
     for (int64_t g = c0; g < c1; g += 64) {
         const int64_t j = g + lane;
         const int32_t n = e1 - e0;
@@ -391,9 +396,9 @@ __global__ __launch_bounds__(64) void k_transpose(const MatDesc *__restrict__ de
         }
 #pragma unroll
         for (int t = 0; t < kTrRegs; ++t)
-            if (t < n) atomicOr(reinterpret_cast<unsigned long long *>(&lds_mask[rows[t]]), bit);
+            if (on_reg(t)) atomicOr(reinterpret_cast<unsigned long long *>(&lds_mask[rows[t]]), bit);
         for (int32_t t = kTrRegs; t < n; ++t)
-            atomicOr(reinterpret_cast<unsigned long long *>(&lds_mask[rowidx[e0 + t]]), bit);
+            if (on_mem(e0 + t)) atomicOr(reinterpret_cast<unsigned long long *>(&lds_mask[rowidx[e0 + t]]), bit);
         int32_t next[kTrRegs], nlps[kTrRegs];
         tr_load_rows(rowidx, f0, f1, next);
 #pragma unroll
@@ -402,25 +407,28 @@ __global__ __launch_bounds__(64) void k_transpose(const MatDesc *__restrict__ de
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < kTrRegs; ++t)
-            if (t < n) {
+            if (on_reg(t)) {
                 const int32_t r = rows[t];
                 const int32_t slot = ctr[r] + __popcll(lds_mask[r] & lower);
                 tr_slot(csr_k, csr_end, csr_col, slot, e0 + t, e1, lps[t], lend, (int32_t)j);
             }
         for (int32_t t = kTrRegs; t < n; ++t) {
+            const int32_t lp = light ? lpos[e0 + t] : -1;
+            if (light && lp < 0) continue;
             const int32_t r = rowidx[e0 + t];
             const int32_t slot = ctr[r] + __popcll(lds_mask[r] & lower);
-            tr_slot(csr_k, csr_end, csr_col, slot, e0 + t, e1, light ? lpos[e0 + t] : -1, lend, (int32_t)j);
+            tr_slot(csr_k, csr_end, csr_col, slot, e0 + t, e1, lp, lend, (int32_t)j);
         }
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < kTrRegs; ++t)
-            if (t < n) {
+            if (on_reg(t)) {
                 const int32_t r = rows[t];
                 const uint64_t mk = lds_mask[r];
                 if ((mk & lower) == 0) ctr[r] += __popcll(mk);
             }
         for (int32_t t = kTrRegs; t < n; ++t) {
+            if (!on_mem(e0 + t)) continue;
             const int32_t r = rowidx[e0 + t];
             const uint64_t mk = lds_mask[r];
             if ((mk & lower) == 0) ctr[r] += __popcll(mk);
@@ -428,8 +436,9 @@ __global__ __launch_bounds__(64) void k_transpose(const MatDesc *__restrict__ de
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < kTrRegs; ++t)
-            if (t < n) lds_mask[rows[t]] = 0;
-        for (int32_t t = kTrRegs; t < n; ++t) lds_mask[rowidx[e0 + t]] = 0;
+            if (on_reg(t)) lds_mask[rows[t]] = 0;
+        for (int32_t t = kTrRegs; t < n; ++t)
+            if (on_mem(e0 + t)) lds_mask[rowidx[e0 + t]] = 0;
         __syncthreads();
         e0 = f0;
         e1 = f1;
