@@ -53,8 +53,8 @@ struct MatDesc {
     int32_t hpad;
     // with the split, the walk runs on a copy of the columns without the dense rows (the light
     // CSC): per-column light counts, their exclusive scan (N + 1), its block totals, the light
-    // rows and values, and for every entry of A its light position (-1 for a dense row's)
-    int32_t *lcnt, *lptr, *lbtot, *lrowidx, *lpos;
+    // rows and values
+    int32_t *lcnt, *lptr, *lbtot, *lrowidx;
     void *lvals;
     // launch-shape knobs (results do not depend on them; set from the context's tuning cache)
     int32_t bp_per_cu;        // back-projection workgroups per compute unit

@@ -527,8 +527,8 @@ __global__ __launch_bounds__(1024) void k_gram_dense_reduce(const MatDesc *__res
 //     k_gram_heavy_reduce adds in a fixed tree over the workgroups;
 //   - the other ("light") rows' entries of every column are copied in row order to a light
 //     CSC (k_gram_light_scatter, after a scan of the per-column counts), before the transpose,
-//     which gives the light rows' row-major slots their positions in it: the walk then steps
-//     over light entries only;
+//     which then transposes the light CSC, so the light rows' row-major slots hold positions in
+//     it: the walk steps over light entries only;
 //   - every light row p adds sum_j a_pj aht[j] (one coalesced row per nonzero) in the walk
 //     kernel.
 // Every sum keeps an order fixed by the matrix alone, so the result is bitwise
@@ -606,7 +606,7 @@ __global__ __launch_bounds__(256) void k_gram_heavy_build(const MatDesc *__restr
 // The light entries in CSC order to the light CSC: a range's light entries start at lptr[c0]
 // and keep their order, so entry e's position is that start plus the number of light entries
 // before it in the range (a prefix count over the 256-entry passes: ballots within a wave,
-// the waves' totals through LDS).  lpos[e] = that position, -1 for a dense row's entry.
+// the waves' totals through LDS).
 template <typename TV>
 __global__ __launch_bounds__(256) void k_gram_light_scatter(const MatDesc *__restrict__ descs) {
     __shared__ int8_t dmap[kMaxM];
@@ -619,7 +619,6 @@ __global__ __launch_bounds__(256) void k_gram_light_scatter(const MatDesc *__res
     const auto lptr = gmem(d.lptr);
     const auto lrow = gmem(d.lrowidx);
     const auto lval = gmem(static_cast<TV *>(d.lvals));
-    const auto lpos = gmem(d.lpos);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t N = d.N, ranges = (N + kHpCols - 1) / kHpCols;
     for (int64_t r = blockIdx.x; r < ranges; r += gridDim.x) {
@@ -643,12 +642,9 @@ __global__ __launch_bounds__(256) void k_gram_light_scatter(const MatDesc *__res
             int32_t before = out;
             for (int w = 0; w < wave; ++w) before += wtot[w];
             const int32_t pos = before + __popcll(bal & ((1ull << lane) - 1));
-            if (e < e1) {
-                if (light) {
-                    lrow[pos] = m;
-                    lval[pos] = v;
-                }
-                lpos[e] = light ? pos : -1;
+            if (e < e1 && light) {
+                lrow[pos] = m;
+                lval[pos] = v;
             }
             out += wtot[0] + wtot[1] + wtot[2] + wtot[3];
             __syncthreads();

@@ -311,9 +311,10 @@ __global__ __launch_bounds__(1024) void k_occ_offsets(const MatDesc *__restrict_
 // the row's running offset plus that rank; the lowest lane then advances the offset.
 // csr_k[slot] = CSC position of the entry, csr_end[slot] = end of its column,
 // csr_col[slot] = its column.  With light = 1 (the heavy-row split, whose light CSC is built
-// first) an entry of a light row gets its position in the light CSC (lpos) and the end of its
-// column there (lptr) instead, so the Gram walk steps over light entries only; the dense rows'
-// entries are then skipped altogether (their slots are never read).
+// first) the light CSC is transposed instead of the CSC: the light rows' slots then hold their
+// positions and column ends in it, so the Gram walk steps over light entries only, and the
+// dense rows' slots are never written (nor read: their workgroups do not walk).  The per-chunk
+// row offsets hold for both, a light row having all its entries in the light CSC.
 // The first kTrRegs row indices of each lane's column are held in registers for the
 // four passes, loaded (with the next group's column bounds) while the previous group's
 // passes run; entries past kTrRegs are read from memory in each pass.
@@ -330,31 +331,18 @@ __device__ __forceinline__ void tr_load_rows(__attribute__((address_space(1))) c
     }
 }
 
-// Slot values of entry e (row-major slot written by the second pass): the CSC position and
-// column end, or, for a light row under the split (lp = lpos[e] >= 0), the light CSC's.
-__device__ __forceinline__ void tr_slot(__attribute__((address_space(1))) int32_t *csr_k,
-                                        __attribute__((address_space(1))) int32_t *csr_end,
-                                        __attribute__((address_space(1))) int32_t *csr_col, int32_t slot, int32_t e,
-                                        int32_t e1, int32_t lp, int32_t lend, int32_t j) {
-    csr_k[slot] = lp >= 0 ? lp : e;
-    csr_end[slot] = lp >= 0 ? lend : e1;
-    csr_col[slot] = j;
-}
-
 __global__ __launch_bounds__(64) void k_transpose(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
                                                   int count, int light_) {
     const int mat = find_mat(wp, count, blockIdx.x);
     const MatDesc &d = descs[mat];
     if (d.nnz == 0) return;
     const int32_t M = d.M;
-    const auto colptr = gmem(d.colptr);
-    const auto rowidx = gmem(d.rowidx);
+    const bool light = light_ != 0 && d.hwg > 0;
+    const auto colptr = gmem(light ? d.lptr : d.colptr);
+    const auto rowidx = gmem(light ? d.lrowidx : d.rowidx);
     const auto csr_k = gmem(d.csrk);
     const auto csr_end = gmem(d.csrend);
     const auto csr_col = gmem(d.csrcol);
-    const bool light = light_ != 0 && d.hwg > 0;
-    const auto lpos = gmem(d.lpos);
-    const auto lptr = gmem(d.lptr);
     extern __shared__ uint64_t lds_mask[];
     int32_t *ctr = reinterpret_cast<int32_t *>(lds_mask + M);
     const int64_t c = blockIdx.x - wp[mat];
@@ -368,67 +356,56 @@ __global__ __launch_bounds__(64) void k_transpose(const MatDesc *__restrict__ de
     const int lane = threadIdx.x;
     const uint64_t bit = 1ull << lane;
     const uint64_t lower = bit - 1;
-    int32_t e0 = 0, e1 = 0, lend = 0;
+    int32_t e0 = 0, e1 = 0;
     if (c0 + lane < c1) {
         e0 = colptr[c0 + lane];
         e1 = colptr[c0 + lane + 1];
-        if (light) lend = lptr[c0 + lane + 1];
     }
-    int32_t rows[kTrRegs], lps[kTrRegs];
+    int32_t rows[kTrRegs];
     tr_load_rows(rowidx, e0, e1, rows);
-#pragma unroll
-    for (int t = 0; t < kTrRegs; ++t) lps[t] = -1;
-    if (light) tr_load_rows(lpos, e0, e1, lps);
     __syncthreads();
-    // with the split, only the light rows' entries take part (the dense rows' slots are never
-    // read: their workgroups do not walk)
-    auto on_reg = [&](int t) { return t < (e1 - e0) && (!light || lps[t] >= 0); };
-    auto on_mem = [&](int32_t e) { return !light || lpos[e] >= 0; };
     for (int64_t g = c0; g < c1; g += 64) {
         const int64_t j = g + lane;
         const int32_t n = e1 - e0;
         // next group: bounds now, its rows after pass 1 (they are in flight during passes 2-4)
-        int32_t f0 = 0, f1 = 0, fend = 0;
+        int32_t f0 = 0, f1 = 0;
         if (j + 64 < c1) {
             f0 = colptr[j + 64];
             f1 = colptr[j + 65];
-            if (light) fend = lptr[j + 65];
         }
 #pragma unroll
         for (int t = 0; t < kTrRegs; ++t)
-            if (on_reg(t)) atomicOr(reinterpret_cast<unsigned long long *>(&lds_mask[rows[t]]), bit);
+            if (t < n) atomicOr(reinterpret_cast<unsigned long long *>(&lds_mask[rows[t]]), bit);
         for (int32_t t = kTrRegs; t < n; ++t)
-            if (on_mem(e0 + t)) atomicOr(reinterpret_cast<unsigned long long *>(&lds_mask[rowidx[e0 + t]]), bit);
-        int32_t next[kTrRegs], nlps[kTrRegs];
+            atomicOr(reinterpret_cast<unsigned long long *>(&lds_mask[rowidx[e0 + t]]), bit);
+        int32_t next[kTrRegs];
         tr_load_rows(rowidx, f0, f1, next);
-#pragma unroll
-        for (int t = 0; t < kTrRegs; ++t) nlps[t] = -1;
-        if (light) tr_load_rows(lpos, f0, f1, nlps);
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < kTrRegs; ++t)
-            if (on_reg(t)) {
+            if (t < n) {
                 const int32_t r = rows[t];
                 const int32_t slot = ctr[r] + __popcll(lds_mask[r] & lower);
-                tr_slot(csr_k, csr_end, csr_col, slot, e0 + t, e1, lps[t], lend, (int32_t)j);
+                csr_k[slot] = e0 + t;
+                csr_end[slot] = e1;
+                csr_col[slot] = (int32_t)j;
             }
         for (int32_t t = kTrRegs; t < n; ++t) {
-            const int32_t lp = light ? lpos[e0 + t] : -1;
-            if (light && lp < 0) continue;
             const int32_t r = rowidx[e0 + t];
             const int32_t slot = ctr[r] + __popcll(lds_mask[r] & lower);
-            tr_slot(csr_k, csr_end, csr_col, slot, e0 + t, e1, lp, lend, (int32_t)j);
+            csr_k[slot] = e0 + t;
+            csr_end[slot] = e1;
+            csr_col[slot] = (int32_t)j;
         }
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < kTrRegs; ++t)
-            if (on_reg(t)) {
+            if (t < n) {
                 const int32_t r = rows[t];
                 const uint64_t mk = lds_mask[r];
                 if ((mk & lower) == 0) ctr[r] += __popcll(mk);
             }
         for (int32_t t = kTrRegs; t < n; ++t) {
-            if (!on_mem(e0 + t)) continue;
             const int32_t r = rowidx[e0 + t];
             const uint64_t mk = lds_mask[r];
             if ((mk & lower) == 0) ctr[r] += __popcll(mk);
@@ -436,18 +413,13 @@ __global__ __launch_bounds__(64) void k_transpose(const MatDesc *__restrict__ de
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < kTrRegs; ++t)
-            if (on_reg(t)) lds_mask[rows[t]] = 0;
-        for (int32_t t = kTrRegs; t < n; ++t)
-            if (on_mem(e0 + t)) lds_mask[rowidx[e0 + t]] = 0;
+            if (t < n) lds_mask[rows[t]] = 0;
+        for (int32_t t = kTrRegs; t < n; ++t) lds_mask[rowidx[e0 + t]] = 0;
         __syncthreads();
         e0 = f0;
         e1 = f1;
-        lend = fend;
 #pragma unroll
-        for (int t = 0; t < kTrRegs; ++t) {
-            rows[t] = next[t];
-            lps[t] = nlps[t];
-        }
+        for (int t = 0; t < kTrRegs; ++t) rows[t] = next[t];
     }
 }
 

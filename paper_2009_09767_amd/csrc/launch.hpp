@@ -29,8 +29,8 @@ void launch_occupancy(const MatDesc *descs, const int32_t *wp_chunks, int64_t n_
                       const int32_t *wp_rows, int64_t n_row_blocks, int count, int32_t maxM, int32_t maxD,
                       hipStream_t s);
 void launch_row_offsets(const MatDesc *descs, const int32_t *wp_rows, int64_t n_row_blocks, int count, hipStream_t s);
-// light: a single matrix whose light CSC (heavy-row split) is built: its light rows' slots point
-// into the light CSC
+// light: a single matrix whose light CSC (heavy-row split) is built: that is transposed instead,
+// so the light rows' slots point into it
 void launch_transpose(const MatDesc *descs, const int32_t *wp_chunks, int64_t n_chunk_blocks, int count, int32_t maxM,
                       bool light, hipStream_t s);
 size_t transpose_lds_bytes(int32_t M);
@@ -49,10 +49,9 @@ void launch_gram(const MatDesc *descs, const int32_t *wp, int64_t nblocks, const
 hipError_t gram_set_attributes(size_t lds_limit);
 int32_t gram_dense_wgs(int64_t N);
 int32_t gram_heavy_wgs(int64_t N);   // workgroups of the heavy-row tiles (a function of N)
-// The heavy split's preparation, before the transpose (which then points the light rows' slots
-// into the light CSC): aht and the light CSC (the walk's columns) with each CSC entry's position
-// in it (lpos, -1 for the dense rows).  host: the matrix's descriptor as the host holds it (its
-// workspace pointers).
+// The heavy split's preparation, before the transpose (which then transposes the light CSC,
+// so that the light rows' slots point into it): aht and the light CSC (the walk's columns).
+// host: the matrix's descriptor as the host holds it (its workspace pointers).
 void launch_gram_heavy_prep(const MatDesc *descs, const MatDesc &host, hipStream_t s);
 void launch_gram_heavy_tiles(const MatDesc *descs, int32_t dtype, int32_t hwg, hipStream_t s);   // workgroups of the split-bf16 dense-row tiles (a function of N)
 void launch_gram_dense(const MatDesc *descs, int32_t dwg, hipStream_t s);   // BF16X3 dense tiles

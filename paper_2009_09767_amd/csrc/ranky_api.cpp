@@ -199,7 +199,7 @@ struct Plan {
     size_t o_topk = 0;     // the subspace iteration's region (topk.p > 0)
     TopkLayout topk;
     int32_t hwg = 0;       // heavy-row split of the Gram: tile workgroups (0: off)
-    size_t o_aht = 0, o_hpart = 0, o_lcnt = 0, o_lptr = 0, o_lbtot = 0, o_lrow = 0, o_lval = 0, o_lpos = 0;
+    size_t o_aht = 0, o_hpart = 0, o_lcnt = 0, o_lptr = 0, o_lbtot = 0, o_lrow = 0, o_lval = 0;
 };
 
 // bstart (host, may be NULL): the caller's D + 1 block boundaries; the widest block sets
@@ -270,7 +270,6 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool sol
         p.o_lbtot = take(sizeof(int32_t) * (size_t)tall_scan_blocks(N));
         p.o_lrow = take(sizeof(int32_t) * nz);
         p.o_lval = take(sizeof(double) * nz);
-        p.o_lpos = take(sizeof(int32_t) * nz);
     }
     p.o_G = take(sizeof(double) * (size_t)p.npad * p.npad);
     if (solver) {
@@ -349,7 +348,6 @@ MatDesc carve(const Plan &p, char *base, Refine *rf) {
     d.lptr = p.hwg > 0 ? i32(p.o_lptr) : nullptr;
     d.lbtot = p.hwg > 0 ? i32(p.o_lbtot) : nullptr;
     d.lrowidx = p.hwg > 0 ? i32(p.o_lrow) : nullptr;
-    d.lpos = p.hwg > 0 ? i32(p.o_lpos) : nullptr;
     d.lvals = p.hwg > 0 ? static_cast<void *>(base + p.o_lval) : nullptr;
     d.bp_per_cu = 32;
     d.jsched = 0;
