@@ -9,6 +9,21 @@
 
 namespace ranky {
 
+// A light-CSC entry of the heavy-row split: its row and value side by side, so that the Gram
+// walk reads both with one load (8 bytes for FP32 values, 16 for FP64).
+template <typename TV>
+struct LightRec;
+template <>
+struct alignas(8) LightRec<float> {
+    int32_t row;
+    float val;
+};
+template <>
+struct alignas(16) LightRec<double> {
+    int32_t row, pad;
+    double val;
+};
+
 struct MatDesc {
     // input (caller-owned)
     const int32_t *colptr;
@@ -53,7 +68,7 @@ struct MatDesc {
     int32_t hpad;
     // with the split, the walk runs on a copy of the columns without the dense rows (the light
     // CSC): per-column light counts, their exclusive scan (N + 1), its block totals, the light
-    // rows and values
+    // rows, and the light entries as (row, value) records (LightRec: one load per entry)
     int32_t *lcnt, *lptr, *lbtot, *lrowidx;
     void *lvals;
     // launch-shape knobs (results do not depend on them; set from the context's tuning cache)

@@ -45,14 +45,59 @@ __device__ __forceinline__ Acc wave_sum(Acc v) {
     return v;
 }
 
-template <typename TV, typename Acc>
-__device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32_t i, int32_t seg, int32_t nseg,
+// One light-CSC record, loaded (returns the row, the value in x) or stored as one vector access.
+// The vector's elements are copied to scalars before any bit cast (a bit cast applied to a
+// vector element expression has been compiled as a cast of element 0).
+template <typename TV>
+__device__ __forceinline__ int32_t light_rec_load(__attribute__((address_space(1))) const LightRec<TV> *p, TV &x) {
+    if constexpr (sizeof(TV) == 4) {
+        typedef int32_t i2 __attribute__((ext_vector_type(2)));
+        const i2 w = *reinterpret_cast<__attribute__((address_space(1))) const i2 *>(p);
+        const int32_t row = w[0], bits = w[1];
+        x = __builtin_bit_cast(TV, bits);
+        return row;
+    } else {
+        typedef int32_t i4 __attribute__((ext_vector_type(4)));
+        const i4 w = *reinterpret_cast<__attribute__((address_space(1))) const i4 *>(p);
+        const int32_t row = w[0], lo = w[2], hi = w[3];
+        x = __builtin_bit_cast(TV, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+        return row;
+    }
+}
+
+template <typename TV>
+__device__ __forceinline__ void light_rec_store(__attribute__((address_space(1))) LightRec<TV> *p, int32_t row, TV x) {
+    if constexpr (sizeof(TV) == 4) {
+        typedef int32_t i2 __attribute__((ext_vector_type(2)));
+        const i2 w = {row, __builtin_bit_cast(int32_t, x)};
+        *reinterpret_cast<__attribute__((address_space(1))) i2 *>(p) = w;
+    } else {
+        typedef int32_t i4 __attribute__((ext_vector_type(4)));
+        const uint64_t b = __builtin_bit_cast(uint64_t, x);
+        const i4 w = {row, 0, (int32_t)(uint32_t)b, (int32_t)(uint32_t)(b >> 32)};
+        *reinterpret_cast<__attribute__((address_space(1))) i4 *>(p) = w;
+    }
+}
+
+// kRec: the heavy split's walk over the light CSC, read as (row, value) records
+template <typename TV, typename Acc, bool kRec>
+__device__ __forceinline__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32_t i, int32_t seg, int32_t nseg,
                          double *lds_raw) {
     const int32_t M = dsc.M, n = dsc.n, npad = dsc.npad;
     const int64_t ld = npad;
     // global (not FLAT) accesses: FLAT ones would also hold up the LDS waits below
-    const auto vals = gmem(vals_);   // the light CSC's values with the heavy split
-    const auto rowidx = gmem(dsc.hwg > 0 ? dsc.lrowidx : dsc.rowidx);
+    const auto vals = gmem(vals_);
+    const auto rowidx = gmem(dsc.rowidx);
+    const auto rec = gmem(static_cast<const LightRec<TV> *>(dsc.lvals));
+    auto value_at = [&](int32_t at) -> TV {
+        if constexpr (kRec) {
+            TV x;
+            light_rec_load(rec + at, x);
+            return x;
+        } else {
+            return vals[at];
+        }
+    };
     const auto rowptr = gmem(dsc.rowptr);
     const auto r2m = gmem(dsc.r2m);
     const auto csr_k = gmem(dsc.csrk);
@@ -125,8 +170,14 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
 #pragma unroll
         for (int u = 0; u < kGramStep; ++u) {
             const int32_t at = k0 + s + u < k1 ? k0 + s + u : k0;
-            qs[u] = rowidx[at];
-            vs[u] = static_cast<Acc>(vals[at]);
+            if constexpr (kRec) {
+                TV x;
+                qs[u] = light_rec_load(rec + at, x);
+                vs[u] = static_cast<Acc>(x);
+            } else {
+                qs[u] = rowidx[at];
+                vs[u] = static_cast<Acc>(vals[at]);
+            }
         }
     };
     int32_t kk = 0, kend = 0, kk1 = 0, kend1 = 0;
@@ -144,7 +195,7 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
         kend = csr_end[e0];
         kk1 = csr_k[e1];
         kend1 = csr_end[e1];
-        a = static_cast<Acc>(vals[kk]);
+        a = static_cast<Acc>(value_at(kk));
         load_group(kk, kend, 1, q0, v0);
     }
     for (int32_t base = wb; walker && base < we; base += 64) {
@@ -152,7 +203,7 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
         // ahead: the positions of the batch after next, the next batch's value and first group
         const int32_t e2 = clampe(base + 128 + lane);
         const int32_t kk2 = csr_k[e2], kend2 = csr_end[e2];
-        const Acc a1 = static_cast<Acc>(vals[kk1]);
+        const Acc a1 = static_cast<Acc>(value_at(kk1));
         int32_t q1[kGramStep];
         Acc v1[kGramStep];
         load_group(kk1, kend1, 1, q1, v1);
@@ -229,7 +280,7 @@ __device__ void gram_row(const MatDesc &dsc, const TV *__restrict__ vals_, int32
                 const int32_t x = base + 64 * t + lane;
                 const int32_t e = x < we ? x : we - 1;
                 jl[t] = csr_col[e];
-                const double v = static_cast<double>(vals[csr_k[e]]);
+                const double v = static_cast<double>(value_at(csr_k[e]));
                 al[t] = x < we ? v : 0.0;
             }
             tv_vec xs[kHlSteps];
@@ -349,15 +400,26 @@ __global__ __launch_bounds__(512) void k_gram_rows(const MatDesc *__restrict__ d
         seg = b - gsegp[i];
         nseg = gsegp[i + 1] - gsegp[i];
     }
-    const void *vp = d.hwg > 0 ? d.lvals : d.values;   // the walk's columns
+    // the walk's columns: the light CSC's records with the heavy split (FP64 or FP32 Gram only),
+    // else the CSC
     if (d.dtype == 1) {
-        const double *v = static_cast<const double *>(vp);
-        if (d.prec == 0) gram_row<double, double>(d, v, i, seg, nseg, lds_raw);
-        else gram_row<double, float>(d, v, i, seg, nseg, lds_raw);
+        const double *v = static_cast<const double *>(d.values);
+        if (d.hwg > 0) {
+            if (d.prec == 0) gram_row<double, double, true>(d, v, i, seg, nseg, lds_raw);
+            else gram_row<double, float, true>(d, v, i, seg, nseg, lds_raw);
+        } else {
+            if (d.prec == 0) gram_row<double, double, false>(d, v, i, seg, nseg, lds_raw);
+            else gram_row<double, float, false>(d, v, i, seg, nseg, lds_raw);
+        }
     } else {
-        const float *v = static_cast<const float *>(vp);
-        if (d.prec == 0) gram_row<float, double>(d, v, i, seg, nseg, lds_raw);
-        else gram_row<float, float>(d, v, i, seg, nseg, lds_raw);
+        const float *v = static_cast<const float *>(d.values);
+        if (d.hwg > 0) {
+            if (d.prec == 0) gram_row<float, double, true>(d, v, i, seg, nseg, lds_raw);
+            else gram_row<float, float, true>(d, v, i, seg, nseg, lds_raw);
+        } else {
+            if (d.prec == 0) gram_row<float, double, false>(d, v, i, seg, nseg, lds_raw);
+            else gram_row<float, float, false>(d, v, i, seg, nseg, lds_raw);
+        }
     }
 }
 
@@ -618,7 +680,7 @@ __global__ __launch_bounds__(256) void k_gram_light_scatter(const MatDesc *__res
     const auto vals = gmem(static_cast<const TV *>(d.values));
     const auto lptr = gmem(d.lptr);
     const auto lrow = gmem(d.lrowidx);
-    const auto lval = gmem(static_cast<TV *>(d.lvals));
+    const auto lrec = gmem(static_cast<LightRec<TV> *>(d.lvals));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t N = d.N, ranges = (N + kHpCols - 1) / kHpCols;
     for (int64_t r = blockIdx.x; r < ranges; r += gridDim.x) {
@@ -644,7 +706,7 @@ __global__ __launch_bounds__(256) void k_gram_light_scatter(const MatDesc *__res
             const int32_t pos = before + __popcll(bal & ((1ull << lane) - 1));
             if (e < e1 && light) {
                 lrow[pos] = m;
-                lval[pos] = v;
+                light_rec_store(lrec + pos, m, v);
             }
             out += wtot[0] + wtot[1] + wtot[2] + wtot[3];
             __syncthreads();

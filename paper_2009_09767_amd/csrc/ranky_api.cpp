@@ -269,7 +269,7 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool sol
         p.o_lptr = take(sizeof(int32_t) * ((size_t)N + 1));
         p.o_lbtot = take(sizeof(int32_t) * (size_t)tall_scan_blocks(N));
         p.o_lrow = take(sizeof(int32_t) * nz);
-        p.o_lval = take(sizeof(double) * nz);
+        p.o_lval = take(sizeof(LightRec<double>) * nz);
     }
     p.o_G = take(sizeof(double) * (size_t)p.npad * p.npad);
     if (solver) {
