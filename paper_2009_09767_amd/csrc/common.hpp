@@ -47,7 +47,6 @@ inline int32_t gram_seg_len(int64_t nnz) {
 constexpr int kDenseRows = 32;
 // Column entries each lane of the Gram walk loads ahead (one group of gathers in flight).
 constexpr int kGramStep = 4;
-constexpr int kHlBatch = 2;    // heavy split: batches of 64 nonzeros whose rows of aht are gathered at once
 // Column entries the occupancy scan loads per step.
 constexpr int kOccGroup = 8;
 // Free value of a Gram election tag (above every workgroup-wide lane id).

@@ -139,7 +139,7 @@ __device__ __forceinline__ void gram_row(const MatDesc &dsc, const TV *__restric
     const int32_t p = r2m[i];
     // heavy split: a dense row's entries of G come from the heavy tiles and from the other
     // rows' gathers, so its workgroups have nothing to do
-    const bool heavy = dsc.hwg > 0;
+    constexpr bool heavy = kRec;   // launched for a matrix with the split (dsc.hwg > 0)
     if (heavy && dmap[p] >= 0) return;
     // with dense tiles on, a dense row's pairs with other dense rows are theirs; with the
     // heavy split every pair with a dense row comes from the gathers below
@@ -181,6 +181,7 @@ __device__ __forceinline__ void gram_row(const MatDesc &dsc, const TV *__restric
         }
     };
     int32_t kk = 0, kend = 0, kk1 = 0, kend1 = 0;
+    TV ta = TV(0);   // the value of this lane's nonzero (a in the walk's precision)
     Acc a = Acc(0);
     int32_t q0[kGramStep];
     Acc v0[kGramStep];
@@ -189,13 +190,35 @@ __device__ __forceinline__ void gram_row(const MatDesc &dsc, const TV *__restric
         q0[u] = 0;
         v0[u] = Acc(0);
     }
+    // heavy split: the pairs with the dense rows, sum_j a_pj aht[j][h] over this wave's run, are
+    // gathered batch by batch inside the walk (the batch's values are at hand).  A row of aht
+    // (kDenseRows values) is read by kLpn lanes with 16-byte loads (kVec values each), so a step
+    // covers kNps nonzeros, one per lane group g, and a batch of 64 nonzeros takes kHlSteps
+    // steps, all of its row loads issued before the walk's additions and summed after them.
+    // Group g sums the nonzeros u = g (mod kNps) in order; the groups are added in order at the
+    // end.
+    constexpr int kVec = 16 / (int)sizeof(TV), kLpn = kDenseRows / kVec, kNps = 64 / kLpn;
+    constexpr int kHlSteps = 64 / kNps;
+    typedef TV tv_vec __attribute__((ext_vector_type(kVec)));
+    const auto aht = gmem(static_cast<const TV *>(dsc.aht));
+    const auto csr_col = gmem(dsc.csrcol);
+    const int g = lane / kLpn, hq = lane % kLpn;
+    double hs[kVec];
+#pragma unroll
+    for (int c = 0; c < kVec; ++c) hs[c] = 0.0;
+    int32_t jl0 = 0, jl1 = 0;   // the columns of this batch's and the next batch's nonzeros
     if (walker && wb < we) {
         const int32_t e0 = clampe(wb + lane), e1 = clampe(wb + 64 + lane);
         kk = csr_k[e0];
         kend = csr_end[e0];
         kk1 = csr_k[e1];
         kend1 = csr_end[e1];
-        a = static_cast<Acc>(value_at(kk));
+        if (heavy) {
+            jl0 = csr_col[e0];
+            jl1 = csr_col[e1];
+        }
+        ta = value_at(kk);
+        a = static_cast<Acc>(ta);
         load_group(kk, kend, 1, q0, v0);
     }
     for (int32_t base = wb; walker && base < we; base += 64) {
@@ -203,10 +226,27 @@ __device__ __forceinline__ void gram_row(const MatDesc &dsc, const TV *__restric
         // ahead: the positions of the batch after next, the next batch's value and first group
         const int32_t e2 = clampe(base + 128 + lane);
         const int32_t kk2 = csr_k[e2], kend2 = csr_end[e2];
-        const Acc a1 = static_cast<Acc>(value_at(kk1));
+        const TV ta1 = value_at(kk1);
+        const Acc a1 = static_cast<Acc>(ta1);
         int32_t q1[kGramStep];
         Acc v1[kGramStep];
         load_group(kk1, kend1, 1, q1, v1);
+        // this batch's rows of aht
+        tv_vec xs[kHlSteps];
+        double as[kHlSteps];
+        int32_t jl2 = 0;
+        if (heavy) {
+            const double am = has ? static_cast<double>(ta) : 0.0;
+#pragma unroll
+            for (int v = 0; v < kHlSteps; ++v) {
+                const int sl = v * kNps + g;   // nonzero v kNps + g of the batch
+                const int32_t j = __shfl(jl0, sl, 64);
+                as[v] = __shfl(am, sl, 64);
+                xs[v] = *reinterpret_cast<__attribute__((address_space(1))) const tv_vec *>(
+                    aht + (int64_t)j * kDenseRows + kVec * hq);
+            }
+            jl2 = csr_col[e2];
+        }
         __builtin_amdgcn_sched_barrier(0);
         auto add_group = [&](const int32_t(&qs)[kGramStep], const Acc(&vs)[kGramStep], int32_t s) {
 #pragma unroll
@@ -246,10 +286,19 @@ __device__ __forceinline__ void gram_row(const MatDesc &dsc, const TV *__restric
             }
         }
         if (has) dg += a * a;
+        if (heavy) {
+#pragma unroll
+            for (int v = 0; v < kHlSteps; ++v)
+#pragma unroll
+                for (int c = 0; c < kVec; ++c) hs[c] = fma(as[v], static_cast<double>(xs[v][c]), hs[c]);
+            jl0 = jl1;
+            jl1 = jl2;
+        }
         kk = kk1;
         kend = kend1;
         kk1 = kk2;
         kend1 = kend2;
+        ta = ta1;
         a = a1;
 #pragma unroll
         for (int u = 0; u < kGramStep; ++u) {
@@ -258,47 +307,6 @@ __device__ __forceinline__ void gram_row(const MatDesc &dsc, const TV *__restric
         }
     }
     if (heavy && walker) {
-        // pairs with the dense rows: sum_j a_pj aht[j][h] over this wave's run.  A row of aht
-        // (kDenseRows values) is read by kLpn lanes with 16-byte loads (kVec values each), so a
-        // step covers kNps nonzeros, one per lane group g; kHlBatch batches of 64 nonzeros are
-        // taken per round, all kHlSteps row loads of a lane issued before the first sum.  Group
-        // g sums the nonzeros u = g (mod kNps) in order; the groups are added in order at the end.
-        constexpr int kVec = 16 / (int)sizeof(TV), kLpn = kDenseRows / kVec, kNps = 64 / kLpn;
-        constexpr int kHlSteps = kHlBatch * 64 / kNps;
-        typedef TV tv_vec __attribute__((ext_vector_type(kVec)));
-        const auto aht = gmem(static_cast<const TV *>(dsc.aht));
-        const auto csr_col = gmem(dsc.csrcol);
-        const int g = lane / kLpn, hq = lane % kLpn;
-        double hs[kVec];
-#pragma unroll
-        for (int c = 0; c < kVec; ++c) hs[c] = 0.0;
-        for (int32_t base = wb; base < we; base += 64 * kHlBatch) {
-            int32_t jl[kHlBatch];
-            double al[kHlBatch];
-#pragma unroll
-            for (int t = 0; t < kHlBatch; ++t) {
-                const int32_t x = base + 64 * t + lane;
-                const int32_t e = x < we ? x : we - 1;
-                jl[t] = csr_col[e];
-                const double v = static_cast<double>(value_at(csr_k[e]));
-                al[t] = x < we ? v : 0.0;
-            }
-            tv_vec xs[kHlSteps];
-            double as[kHlSteps];
-#pragma unroll
-            for (int v = 0; v < kHlSteps; ++v) {
-                // nonzero v kNps + g of this round: batch t (a compile-time index), lane sl
-                const int t = (v * kNps) / 64, sl = (v * kNps) % 64 + g;
-                const int32_t j = __shfl(jl[t], sl, 64);
-                as[v] = __shfl(al[t], sl, 64);
-                xs[v] = *reinterpret_cast<__attribute__((address_space(1))) const tv_vec *>(
-                    aht + (int64_t)j * kDenseRows + kVec * hq);
-            }
-#pragma unroll
-            for (int v = 0; v < kHlSteps; ++v)
-#pragma unroll
-                for (int c = 0; c < kVec; ++c) hs[c] = fma(as[v], static_cast<double>(xs[v][c]), hs[c]);
-        }
         // lane hq of group 0 adds the groups' sums in group order and writes dense rows kVec hq + c
 #pragma unroll
         for (int c = 0; c < kVec; ++c) {
@@ -378,6 +386,7 @@ __device__ __forceinline__ void gram_row(const MatDesc &dsc, const TV *__restric
 
 // Workgroup b of a matrix: segment b of the nonempty rows' segments (gsegp maps it to
 // compacted row i and segment seg), then one workgroup per padding row n..npad-1.
+template <bool kHeavy>
 __global__ __launch_bounds__(512) void k_gram_rows(const MatDesc *__restrict__ descs, const int32_t *__restrict__ wp,
                                                    int count) {
     extern __shared__ double lds_raw[];
@@ -404,22 +413,12 @@ __global__ __launch_bounds__(512) void k_gram_rows(const MatDesc *__restrict__ d
     // else the CSC
     if (d.dtype == 1) {
         const double *v = static_cast<const double *>(d.values);
-        if (d.hwg > 0) {
-            if (d.prec == 0) gram_row<double, double, true>(d, v, i, seg, nseg, lds_raw);
-            else gram_row<double, float, true>(d, v, i, seg, nseg, lds_raw);
-        } else {
-            if (d.prec == 0) gram_row<double, double, false>(d, v, i, seg, nseg, lds_raw);
-            else gram_row<double, float, false>(d, v, i, seg, nseg, lds_raw);
-        }
+        if (d.prec == 0) gram_row<double, double, kHeavy>(d, v, i, seg, nseg, lds_raw);
+        else gram_row<double, float, kHeavy>(d, v, i, seg, nseg, lds_raw);
     } else {
         const float *v = static_cast<const float *>(d.values);
-        if (d.hwg > 0) {
-            if (d.prec == 0) gram_row<float, double, true>(d, v, i, seg, nseg, lds_raw);
-            else gram_row<float, float, true>(d, v, i, seg, nseg, lds_raw);
-        } else {
-            if (d.prec == 0) gram_row<float, double, false>(d, v, i, seg, nseg, lds_raw);
-            else gram_row<float, float, false>(d, v, i, seg, nseg, lds_raw);
-        }
+        if (d.prec == 0) gram_row<float, double, kHeavy>(d, v, i, seg, nseg, lds_raw);
+        else gram_row<float, float, kHeavy>(d, v, i, seg, nseg, lds_raw);
     }
 }
 
@@ -872,10 +871,14 @@ size_t gram_lds_bytes(int32_t M, int32_t acc_bytes, int32_t nw, bool slots) {
 }
 
 void launch_gram(const MatDesc *descs, const int32_t *wp, int64_t nblocks, const int32_t *wp_red, int64_t nblocks_red,
-                 int count, int32_t max_waves, size_t lds_bytes, hipStream_t s) {
+                 int count, int32_t max_waves, size_t lds_bytes, bool heavy, hipStream_t s) {
     if (nblocks <= 0) return;
-    hipLaunchKernelGGL(k_gram_rows, dim3((unsigned)nblocks), dim3((unsigned)(64 * max_waves)), lds_bytes, s, descs, wp,
-                       count);
+    if (heavy)
+        hipLaunchKernelGGL(k_gram_rows<true>, dim3((unsigned)nblocks), dim3((unsigned)(64 * max_waves)), lds_bytes, s,
+                           descs, wp, count);
+    else
+        hipLaunchKernelGGL(k_gram_rows<false>, dim3((unsigned)nblocks), dim3((unsigned)(64 * max_waves)), lds_bytes,
+                           s, descs, wp, count);
     if (nblocks_red > 0)
         hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)nblocks_red), dim3(256), 0, s, descs, wp_red, count);
 }
@@ -888,8 +891,12 @@ int64_t gram_part_slots(int64_t nnz) {
 }
 
 hipError_t gram_set_attributes(size_t lds_limit) {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_gram_rows), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds_limit);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_gram_rows<false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_gram_rows<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit);
+    return e;
 }
 
 }  // namespace ranky

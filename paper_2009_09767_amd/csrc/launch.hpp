@@ -45,7 +45,7 @@ size_t gram_lds_bytes(int32_t M, int32_t acc_bytes, int32_t nw, bool slots = tru
 int64_t gram_part_slots(int64_t nnz);   // partial Gram rows the workspace must hold
 // max_waves, lds_bytes: the largest MatDesc::gwaves and LDS over the launch's matrices
 void launch_gram(const MatDesc *descs, const int32_t *wp, int64_t nblocks, const int32_t *wp_red, int64_t nblocks_red,
-                 int count, int32_t max_waves, size_t lds_bytes, hipStream_t s);
+                 int count, int32_t max_waves, size_t lds_bytes, bool heavy, hipStream_t s);
 hipError_t gram_set_attributes(size_t lds_limit);
 int32_t gram_dense_wgs(int64_t N);
 int32_t gram_heavy_wgs(int64_t N);   // workgroups of the heavy-row tiles (a function of N)

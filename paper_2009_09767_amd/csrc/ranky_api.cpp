@@ -1201,7 +1201,7 @@ ranky_status run_path(ranky_ctx *ctx, const std::vector<Job> &jobs, double tol, 
     gram_shape(e.d, ctx->lds_limit, gram_nw, gram_lds);
     if (count == 1) launch_gram_dense(e.ddesc(), e.d[0].dwg, s);
     launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], e.dwp(kPhGramRed), e.nblk[kPhGramRed], count, gram_nw,
-                gram_lds, s);
+                gram_lds, heavy, s);
     if (count == 1) launch_gram_dense_reduce(e.ddesc(), e.d[0].dwg, s);
     if (count == 1) launch_gram_heavy_tiles(e.ddesc(), e.d[0].dtype, e.d[0].hwg, s);
     HIP_TRY(hipGetLastError());
@@ -2074,7 +2074,7 @@ ranky_status ranky_gram(const ranky_csc *A, int32_t M, int64_t N, int32_t prec, 
         size_t gram_lds = 0;
         gram_shape(e.d, sc.c.lds_limit, gram_nw, gram_lds);
         launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], e.dwp(kPhGramRed), e.nblk[kPhGramRed], 1, gram_nw,
-                    gram_lds, s);
+                    gram_lds, x.hwg > 0, s);
         launch_gram_dense_reduce(e.ddesc(), x.dwg, s);
         launch_gram_heavy_tiles(e.ddesc(), x.dtype, x.hwg, s);
         launch_scatter_gram(x.G, x.npad, x.m2r, M, G, s);
@@ -2292,7 +2292,7 @@ ranky_status ranky_inc_append(ranky_inc *inc, const ranky_csc *block, int64_t co
         size_t gram_lds = 0;
         gram_shape(e.d, sc.c.lds_limit, gram_nw, gram_lds);
         launch_gram(e.ddesc(), e.dwp(kPhGram), e.nblk[kPhGram], e.dwp(kPhGramRed), e.nblk[kPhGramRed], 1, gram_nw,
-                    gram_lds, s);
+                    gram_lds, x.hwg > 0, s);
         launch_scatter_add_gram(x.G, x.npad, x.m2r, inc->M, reinterpret_cast<double *>(inc->ws + L.o_G), s);
     }
     HIP_TRY(hipGetLastError());
