@@ -52,10 +52,10 @@ def parse():
 TRAFFIC = {
     ("k_backproject", "powerlaw_1m/fp64"): {"bytes": (13605.64 * 2.0 + 1048841.05) * 1024, "source": "k_select.hip",
                                            "source_sha256": "10ec62b8b56e6f7f358da962eb913eaae2dca55ea1235111e7c3b02a437fe775"},
-    ("k_backproject", "powerlaw_200m/fp64"): {"bytes": (1589652.51 * 2.0 + 13184244.41) * 1024, "source": "k_select.hip",
-                                             "source_sha256": "27f7d8d0db7be10c881843cbfaeb55738bded1dd78f4d4e1341ea186e4414462"},
-    ("k_gram_rows", "powerlaw_200m/fp64"): {"bytes": (22026016.82 * 2.0 + 324392.76) * 1024, "source": "k_gram.hip",
-                                           "source_sha256": "e3d07d36c1adeaabfea789710831b08c55cc34e41faf1e51cc4364512566d025"},
+    ("k_backproject", "powerlaw_200m/fp64"): {"bytes": (1625946.40 * 2.0 + 13219728.08) * 1024, "source": "k_select.hip",
+                                             "source_sha256": "bbe1f92a509f24ebd64ce446ec944c0c0f29d1cb692094a71cc0242b0e9bead0"},
+    ("k_gram_rows", "powerlaw_200m/fp64"): {"bytes": (13309329.70 * 2.0 + 325119.49) * 1024, "source": "k_gram.hip",
+                                           "source_sha256": "116ffd479d8d0cec73078faf37c826c6d84f59ab9f4653d6fae7a560387d0265"},
 }
 
 

@@ -108,7 +108,7 @@ hipError_t kernel_attributes(int device, size_t lds_limit) {
 // ---------------------------------------------------------------------------
 
 constexpr int32_t kTopkMaxBlock = 256;    // widest block (the p x p problems run on the Jacobi)
-constexpr int32_t kTopkWgTarget = 512;    // workgroups a split product aims for
+constexpr int32_t kTopkWgTarget = 768;    // workgroups a split product aims for (three per CU)
 constexpr int32_t kTopkDefaultIters = 60;
 constexpr int64_t kHeavyMinNnz = (int64_t)1 << 22;   // automatic heavy-row split of the Gram from here
 
