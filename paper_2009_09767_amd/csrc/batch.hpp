@@ -50,7 +50,9 @@ struct MatDesc {
     double jtol;              // Jacobi rotation test tolerance (0: max(1e-15, sqrt(n) eps))
     // workspace (library-carved from caller memory)
     int32_t *scal, *hist, *rownnz, *rowptr, *m2r, *r2m, *empty, *lonely, *single;
-    int32_t *csrk, *csrend, *csrcol, *jflag, *perm;
+    // row-major copy of the nonzeros: csrk holds a (CSC position, column end) pair per slot (one
+    // 8-byte access each), csrcol the column
+    int32_t *csrk, *csrcol, *jflag, *perm;
     int32_t *cnt;             // optional [D x M] occupancy output (step call only)
     int32_t *jstate;          // Jacobi state: [0] sweeps done, [1] active this sweep, [2] not converged
     int32_t *gsegp;           // [n + 1] first Gram segment of compacted row i (set by the scan)

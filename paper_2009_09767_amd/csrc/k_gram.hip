@@ -100,8 +100,8 @@ __device__ __forceinline__ void gram_row(const MatDesc &dsc, const TV *__restric
     };
     const auto rowptr = gmem(dsc.rowptr);
     const auto r2m = gmem(dsc.r2m);
-    const auto csr_k = gmem(dsc.csrk);
-    const auto csr_end = gmem(dsc.csrend);
+    typedef int32_t i2 __attribute__((ext_vector_type(2)));
+    const auto csr_ke = gmem(reinterpret_cast<const i2 *>(dsc.csrk));   // (position, column end) per slot
     const auto dense = gmem(dsc.dense);
     const auto G = gmem(dsc.G);
     // the matrix's own wave count (a function of its M alone, so a batch sums in the order a
@@ -209,10 +209,11 @@ __device__ __forceinline__ void gram_row(const MatDesc &dsc, const TV *__restric
     int32_t jl0 = 0, jl1 = 0;   // the columns of this batch's and the next batch's nonzeros
     if (walker && wb < we) {
         const int32_t e0 = clampe(wb + lane), e1 = clampe(wb + 64 + lane);
-        kk = csr_k[e0];
-        kend = csr_end[e0];
-        kk1 = csr_k[e1];
-        kend1 = csr_end[e1];
+        const i2 w0 = csr_ke[e0], w1 = csr_ke[e1];
+        kk = w0[0];
+        kend = w0[1];
+        kk1 = w1[0];
+        kend1 = w1[1];
         if (heavy) {
             jl0 = csr_col[e0];
             jl1 = csr_col[e1];
@@ -225,7 +226,8 @@ __device__ __forceinline__ void gram_row(const MatDesc &dsc, const TV *__restric
         const bool has = base + lane < we;
         // ahead: the positions of the batch after next, the next batch's value and first group
         const int32_t e2 = clampe(base + 128 + lane);
-        const int32_t kk2 = csr_k[e2], kend2 = csr_end[e2];
+        const i2 w2 = csr_ke[e2];
+        const int32_t kk2 = w2[0], kend2 = w2[1];
         const TV ta1 = value_at(kk1);
         const Acc a1 = static_cast<Acc>(ta1);
         int32_t q1[kGramStep];

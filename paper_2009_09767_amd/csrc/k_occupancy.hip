@@ -309,7 +309,7 @@ __global__ __launch_bounds__(1024) void k_occ_offsets(const MatDesc *__restrict_
 // lanes publish themselves in a per-row 64-bit mask (bitwise OR commutes, so the
 // mask does not depend on timing), read it back and count.  The entry's slot is
 // the row's running offset plus that rank; the lowest lane then advances the offset.
-// csr_k[slot] = CSC position of the entry, csr_end[slot] = end of its column,
+// csr_ke[slot] = (CSC position of the entry, end of its column) as one 8-byte store,
 // csr_col[slot] = its column.  With light = 1 (the heavy-row split, whose light CSC is built
 // first) the light CSC is transposed instead of the CSC: the light rows' slots then hold their
 // positions and column ends in it, so the Gram walk steps over light entries only, and the
@@ -340,8 +340,8 @@ __global__ __launch_bounds__(64) void k_transpose(const MatDesc *__restrict__ de
     const bool light = light_ != 0 && d.hwg > 0;
     const auto colptr = gmem(light ? d.lptr : d.colptr);
     const auto rowidx = gmem(light ? d.lrowidx : d.rowidx);
-    const auto csr_k = gmem(d.csrk);
-    const auto csr_end = gmem(d.csrend);
+    typedef int32_t i2 __attribute__((ext_vector_type(2)));
+    const auto csr_ke = gmem(reinterpret_cast<i2 *>(d.csrk));
     const auto csr_col = gmem(d.csrcol);
     extern __shared__ uint64_t lds_mask[];
     int32_t *ctr = reinterpret_cast<int32_t *>(lds_mask + M);
@@ -386,15 +386,13 @@ __global__ __launch_bounds__(64) void k_transpose(const MatDesc *__restrict__ de
             if (t < n) {
                 const int32_t r = rows[t];
                 const int32_t slot = ctr[r] + __popcll(lds_mask[r] & lower);
-                csr_k[slot] = e0 + t;
-                csr_end[slot] = e1;
+                csr_ke[slot] = i2{e0 + t, e1};
                 csr_col[slot] = (int32_t)j;
             }
         for (int32_t t = kTrRegs; t < n; ++t) {
             const int32_t r = rowidx[e0 + t];
             const int32_t slot = ctr[r] + __popcll(lds_mask[r] & lower);
-            csr_k[slot] = e0 + t;
-            csr_end[slot] = e1;
+            csr_ke[slot] = i2{e0 + t, e1};
             csr_col[slot] = (int32_t)j;
         }
         __syncthreads();

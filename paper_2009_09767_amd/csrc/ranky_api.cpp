@@ -189,7 +189,7 @@ struct Plan {
     int32_t M = 0, k = 0, D = 0, cpb = 0, ccols = 0, npad = 0;
     int64_t N = 0, nnz = 0, nchunks = 0;
     size_t o_scal = 0, o_sdbl = 0, o_jstate = 0, o_hist = 0, o_rownnz = 0, o_rowptr = 0, o_m2r = 0, o_r2m = 0;
-    size_t o_empty = 0, o_lonely = 0, o_single = 0, o_csrk = 0, o_csrend = 0, o_csrcol = 0;
+    size_t o_empty = 0, o_lonely = 0, o_single = 0, o_csrk = 0, o_csrcol = 0;
     size_t o_gsegp = 0, o_gslot = 0, o_gpart = 0, o_dense = 0, o_dpart = 0;
     int32_t dwg = 0;
     size_t o_G = 0, o_G2 = 0, o_W = 0, o_J = 0, o_S = 0, o_jflag = 0, o_lam = 0, o_perm = 0;
@@ -252,8 +252,7 @@ Plan make_plan(int32_t M, int64_t N, int64_t nnz, int32_t k, int32_t D, bool sol
     p.o_empty = take(sizeof(int32_t) * M);
     p.o_lonely = take(sizeof(int32_t) * D);
     p.o_single = take(sizeof(int32_t) * D);
-    p.o_csrk = take(sizeof(int32_t) * nz);
-    p.o_csrend = take(sizeof(int32_t) * nz);
+    p.o_csrk = take(2 * sizeof(int32_t) * nz);
     p.o_csrcol = take(sizeof(int32_t) * nz);
     p.o_gsegp = take(sizeof(int32_t) * (M + 1));
     p.o_gslot = take(sizeof(int32_t) * (M + 1));
@@ -333,7 +332,6 @@ MatDesc carve(const Plan &p, char *base, Refine *rf) {
     d.lonely = i32(p.o_lonely);
     d.single = i32(p.o_single);
     d.csrk = i32(p.o_csrk);
-    d.csrend = i32(p.o_csrend);
     d.csrcol = i32(p.o_csrcol);
     d.gsegp = i32(p.o_gsegp);
     d.gslot = i32(p.o_gslot);
