@@ -136,6 +136,110 @@ __global__ __launch_bounds__(256) void k_tk_gemm(const double *__restrict__ A_, 
             }
 }
 
+// The block products G Y (A = G, plain, rows x K; B = Y, K x P with P = 64 CB the whole block
+// width): a workgroup owns 64 rows and all P columns, so each split reads its rows of G once
+// (the 64-column tiles above read G once per column tile).  Wave w owns the CB 16-column blocks
+// 16 CB w .. of every one of the four 16-row blocks; per k step of 16 it makes 16 CB products
+// from 4 + CB operands read from LDS.  Same zero padding (a_valid, k_valid) and split partials
+// as k_tk_gemm.
+template <int CB>
+__global__ __launch_bounds__(256) void k_tk_gemm_wide(const double *__restrict__ A_, int64_t lda,
+                                                      const double *__restrict__ B_, int64_t ldb,
+                                                      double *__restrict__ part_, int32_t rows, int32_t K,
+                                                      int32_t klen, int32_t a_valid, int32_t k_valid) {
+    constexpr int P = 64 * CB, BLd = P + 2;
+    __shared__ double As[2][kTkK][kTkLd];   // [k][m]
+    __shared__ double Bs[2][kTkK][BLd];     // [k][n]
+    const auto A = gmem(A_);
+    const auto B = gmem(B_);
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6, lr = l & 15, lg = l >> 4;
+    const int64_t m0 = (int64_t)blockIdx.x * kTkTile;
+    const int32_t kb = blockIdx.y * klen;
+    const int32_t ke = kb + klen < K ? kb + klen : K;
+    const int32_t kv = ke < k_valid ? ke : k_valid;   // k past it reads as zero
+    double ra[4], rb[CB][4];
+    auto load = [&](int32_t k0) {
+        {
+            const int64_t m = m0 + (tid >> 2);
+            const int32_t k = k0 + 4 * (tid & 3);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool ok = m < a_valid && k + q < kv;
+                const double v = A[(ok ? m : 0) * lda + (ok ? k + q : 0)];
+                ra[q] = ok ? v : 0.0;
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < CB; ++g) {
+            const int idx = tid + 256 * g;
+            const int32_t k = k0 + idx / (P / 4);
+            const int n = 4 * (idx % (P / 4));
+            const bool ok = k < kv;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double v = B[(int64_t)(ok ? k : 0) * ldb + n + q];
+                rb[g][q] = ok ? v : 0.0;
+            }
+        }
+    };
+    auto store = [&](int buf) {
+        {
+            const int m = tid >> 2, k = 4 * (tid & 3);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) As[buf][k + q][m] = ra[q];
+        }
+#pragma unroll
+        for (int g = 0; g < CB; ++g) {
+            const int idx = tid + 256 * g;
+            const int k = idx / (P / 4), n = 4 * (idx % (P / 4));
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Bs[buf][k][n + q] = rb[g][q];
+        }
+    };
+    tk_d4 acc[4][CB];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < CB; ++y) acc[x][y] = tk_d4{0.0, 0.0, 0.0, 0.0};
+    const int32_t nsteps = ke > kb ? (ke - kb + kTkK - 1) / kTkK : 0;
+    if (nsteps > 0) {
+        load(kb);
+        store(0);
+    }
+    __syncthreads();
+    const int c0 = 16 * CB * w;
+    for (int32_t st = 0; st < nsteps; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nsteps) load(kb + (st + 1) * kTkK);
+#pragma unroll
+        for (int kk = 0; kk < kTkK / 4; ++kk) {
+            const int k = 4 * kk + lg;
+            double a[4], b[CB];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) a[x] = As[buf][k][16 * x + lr];
+#pragma unroll
+            for (int y = 0; y < CB; ++y) b[y] = Bs[buf][k][c0 + 16 * y + lr];
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < CB; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+        }
+        if (st + 1 < nsteps) store(buf ^ 1);
+        __syncthreads();
+    }
+    // result layout: element i of lane l at row l / 16 + 4 i, column l % 16 of a 16 x 16 block
+    const auto part = gmem(part_) + (int64_t)blockIdx.y * rows * P;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < CB; ++y)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t r = m0 + 16 * x + lg + 4 * i;
+                part[r * P + c0 + 16 * y + lr] = acc[x][y][i];
+            }
+}
+
 // out = alpha (sum over the splits, in split order, of part) + beta E + gamma F, elementwise
 // over count entries (E, F may be NULL).  out may not alias part.
 __global__ __launch_bounds__(256) void k_tk_combine(const double *__restrict__ part_, int32_t splits, int64_t count,
@@ -425,6 +529,18 @@ void launch_tk_gemm(bool trans_a, const double *A, int64_t lda, const double *B,
     else
         hipLaunchKernelGGL(k_tk_gemm<false>, grid, dim3(256), 0, s, A, lda, B, ldb, part, rows, cols, K, klen, a_valid,
                            k_valid);
+}
+
+bool launch_tk_gemm_wide(const double *A, int64_t lda, const double *B, int64_t ldb, double *part, int32_t rows,
+                         int32_t cols, int32_t K, int32_t splits, int32_t klen, int32_t a_valid, int32_t k_valid,
+                         hipStream_t s) {
+    const dim3 grid((unsigned)(rows / kTkTile), (unsigned)splits);
+    switch (cols) {
+    case 64: hipLaunchKernelGGL(k_tk_gemm_wide<1>, grid, dim3(256), 0, s, A, lda, B, ldb, part, rows, K, klen, a_valid, k_valid); return true;
+    case 128: hipLaunchKernelGGL(k_tk_gemm_wide<2>, grid, dim3(256), 0, s, A, lda, B, ldb, part, rows, K, klen, a_valid, k_valid); return true;
+    case 192: hipLaunchKernelGGL(k_tk_gemm_wide<3>, grid, dim3(256), 0, s, A, lda, B, ldb, part, rows, K, klen, a_valid, k_valid); return true;
+    default: return false;
+    }
 }
 
 void launch_tk_combine(const double *part, int32_t splits, int64_t count, double alpha, double beta, const double *E,

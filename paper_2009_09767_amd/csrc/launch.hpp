@@ -111,6 +111,11 @@ constexpr int32_t kTopkCholMax = 192;   // widest block the one-workgroup Choles
 void launch_tk_gemm(bool trans_a, const double *A, int64_t lda, const double *B, int64_t ldb, double *part,
                     int32_t rows, int32_t cols, int32_t K, int32_t splits, int32_t klen, int32_t a_valid,
                     int32_t k_valid, hipStream_t s);
+// G Y with the whole block width in one workgroup (cols = 64, 128 or 192; false otherwise, nothing
+// launched): grid rows / 64 x splits, partials as launch_tk_gemm's
+bool launch_tk_gemm_wide(const double *A, int64_t lda, const double *B, int64_t ldb, double *part, int32_t rows,
+                         int32_t cols, int32_t K, int32_t splits, int32_t klen, int32_t a_valid, int32_t k_valid,
+                         hipStream_t s);
 void launch_tk_combine(const double *part, int32_t splits, int64_t count, double alpha, double beta, const double *E,
                        double gamma, const double *F, double *out, hipStream_t s);
 void launch_tk_start(const double *G, int64_t ldg, int32_t n, int32_t p, int32_t rows, double *X, hipStream_t s);

@@ -109,6 +109,9 @@ hipError_t kernel_attributes(int device, size_t lds_limit) {
 
 constexpr int32_t kTopkMaxBlock = 256;    // widest block (the p x p problems run on the Jacobi)
 constexpr int32_t kTopkWgTarget = 768;    // workgroups a split product aims for (three per CU)
+constexpr int32_t kTopkWideTarget = 512;  // the same for the whole-width G Y products (two per CU: LDS)
+constexpr int32_t kTopkWideMaxP = 192;    // block widths the whole-width product takes
+constexpr int32_t kTopkWideMinK = 1024;   // and inner sizes (shorter ones stay on the 64 x 64 tiles)
 constexpr int32_t kTopkDefaultIters = 60;
 constexpr int64_t kHeavyMinNnz = (int64_t)1 << 22;   // automatic heavy-row split of the Gram from here
 
@@ -119,8 +122,8 @@ int32_t topk_block(int32_t k) {
 }
 
 // k split of a product with `tiles` output tiles over K: (splits, klen), klen a multiple of 16.
-void topk_split(int64_t tiles, int32_t K, int32_t &splits, int32_t &klen) {
-    int64_t sp = (kTopkWgTarget + tiles - 1) / tiles;
+void topk_split(int64_t tiles, int32_t K, int32_t &splits, int32_t &klen, int64_t target = kTopkWgTarget) {
+    int64_t sp = (target + tiles - 1) / tiles;
     if (sp > K / 64) sp = K / 64;
     if (sp < 1) sp = 1;
     klen = (int32_t)((((K + sp - 1) / sp) + 15) / 16 * 16);
@@ -155,7 +158,10 @@ TopkLayout topk_layout(int32_t M, int32_t p) {
     topk_split((int64_t)(p / kTopkTile) * (p / kTopkTile), t.rows, sp2, kl2);        // Y^T Y, Y^T T
     int32_t sp3, kl3;
     topk_split((int64_t)(t.rows / kTopkTile) * (p / kTopkTile), p, sp3, kl3);        // Y W
-    t.part_doubles = std::max({(size_t)sp1 * t.rows * p, (size_t)sp2 * p * p, (size_t)sp3 * t.rows * p});
+    int32_t sp4, kl4;
+    topk_split(t.rows / kTopkTile, npad, sp4, kl4, kTopkWideTarget);                // G Y, whole width
+    t.part_doubles = std::max({(size_t)sp1 * t.rows * p, (size_t)sp2 * p * p, (size_t)sp3 * t.rows * p,
+                               (size_t)sp4 * t.rows * p});
     t.o_part = take(sizeof(double) * t.part_doubles);
     t.o_Sp = take(sq);
     t.o_Wm = take(sq);
@@ -873,9 +879,16 @@ struct Topk {
               int32_t cols, int32_t K, int32_t a_valid, int32_t k_valid, double alpha, double beta = 0.0,
               const double *E = nullptr, double gamma = 0.0, const double *F = nullptr) {
         int32_t splits, klen;
-        topk_split((int64_t)(rows / kTopkTile) * (cols / kTopkTile), K, splits, klen);
         flops += 2.0 * (ta ? rows : std::min(rows, n)) * cols * std::min(K, std::min(k_valid, n));
-        launch_tk_gemm(ta, A, lda, B, ldb, part, rows, cols, K, splits, klen, a_valid, k_valid, s);
+        bool done = false;
+        if (!ta && cols <= kTopkWideMaxP && K >= kTopkWideMinK) {
+            topk_split(rows / kTopkTile, K, splits, klen, kTopkWideTarget);
+            done = launch_tk_gemm_wide(A, lda, B, ldb, part, rows, cols, K, splits, klen, a_valid, k_valid, s);
+        }
+        if (!done) {
+            topk_split((int64_t)(rows / kTopkTile) * (cols / kTopkTile), K, splits, klen);
+            launch_tk_gemm(ta, A, lda, B, ldb, part, rows, cols, K, splits, klen, a_valid, k_valid, s);
+        }
         launch_tk_combine(part, splits, (int64_t)rows * cols, alpha, beta, E, gamma, F, out, s);
     }
     // the p x p Jacobi on the matrix already in es's G; eigenvectors in its W, values in lam
