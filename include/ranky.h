@@ -256,7 +256,7 @@ typedef struct {
 /* Picks the launch shapes of this problem shape by measurement and stores them in the
  * context: later ranky_svd / ranky_batch calls on the same context with the same
  * (M, N, nnz, k, value dtype, opts->v_dtype, opts->gram_prec) use them.  Candidates:
- * back-projection workgroups per CU {8, 16, 32, 64} and the Jacobi round launch shape
+ * back-projection workgroups per CU {16, 32, 64, 128} and the Jacobi round launch shape
  * {0..3}: bit 0 groups the update tiles per XCD (the tiles that share a rotation J run on
  * one XCD's L2), bit 1 gives every round workgroup a CU of its own (extra LDS), so no update
  * workgroup shares a CU with a subproblem sweep, the round's critical path.

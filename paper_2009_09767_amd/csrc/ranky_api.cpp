@@ -1921,7 +1921,7 @@ ranky_status ranky_autotune(ranky_ctx *ctx, const ranky_csc *A, int32_t M, int64
     o.graph = 0;       // direct launches while timing
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const TuneKey key{M, N, j.A.nnz, k, j.A.dtype, o.v_dtype, o.gram_prec};
-    const int32_t bp_cands[4] = {8, 16, 32, 64};
+    const int32_t bp_cands[4] = {16, 32, 64, 128};
     const int32_t sched_cands[4] = {0, 1, 2, 3};
     const int reps = 2;
     TuneCfg best;

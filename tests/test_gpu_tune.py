@@ -32,7 +32,7 @@ def test_every_candidate_gives_the_default_result(R):
     dA = R.to_device(A)
     k = 32
     base = R.svd(dA, k, 0.0, ctx=R.Context(0), n_blocks=8)
-    for bp in (8, 16, 32, 64):
+    for bp in (8, 16, 32, 64, 128):
         for sched in (0, 1, 2, 3):
             ctx = R.Context(0)
             R.tune_set(dA, k, bp, sched, ctx=ctx, n_blocks=8)
@@ -51,7 +51,7 @@ def test_autotune_report_and_reuse(R):
     stream = torch.cuda.Stream()
     rep = R.autotune(dA, k, ctx=ctx, stream=stream, n_blocks=8)
     torch.cuda.synchronize()
-    assert rep["bp_per_cu"] in (8, 16, 32, 64)
+    assert rep["bp_per_cu"] in (16, 32, 64, 128)
     assert rep["jacobi_schedule"] in (0, 1, 2, 3) and len(rep["eig_ms"]) == 4
     assert all(v > 0 for v in rep["bp_ms"].values()) and all(v > 0 for v in rep["eig_ms"].values())
     assert min(rep["bp_ms"], key=rep["bp_ms"].get) == rep["bp_per_cu"]
