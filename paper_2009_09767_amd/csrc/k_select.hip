@@ -154,15 +154,19 @@ __device__ inline double readlane_val(T v, int32_t q) {
 
 // V[j][i] = (sum over the nonzeros a_mj of column j of a_mj U[m][i]) / sigma[i] for
 // i < rank, else 0.  A wave handles one column at a time, over a contiguous run of
-// columns whose bounds it loads 64 at a time; a lane owns P pairs of outputs, i = i0 + 128 p + 2 lane (P = 1 for k <= 128,
-// 2 for k <= 256, 4 above: one pass over the columns covers k <= 512), so every load of
-// a U row and every store of a V row is one contiguous 1 KB per wave.  The run's nonzeros
-// are contiguous in the CSC arrays: their row indices and values stream through a window
-// of 128 entries in registers (lane t holding entries w + t and w + 64 + t), refilled 64 at a
-// time one refill ahead, so a column's only wait is on its U rows.  The column's nonzeros
-// are taken four (P = 1) or two at a time with independent loads (a shorter tail as one
-// step); each output adds them in order.  U rows come from L2, and V goes out with
-// non-temporal stores so it does not evict them.
+// columns whose bounds it loads 64 at a time; a lane owns P pairs of outputs,
+// i = i0 + 128 p + 2 lane (P = 1 for k <= 128, 2 for k <= 256, 4 above: one pass over the
+// columns covers k <= 512), so every load of a U row and every store of a V row is one
+// contiguous 1 KB per wave.  The run's nonzeros are contiguous in the CSC arrays: their row
+// indices and values stream through a window of 128 entries in registers (lane t holding
+// entries w + t and w + 64 + t), refilled 64 at a time one refill ahead, so a column's only
+// wait is on its U rows.  The column's nonzeros are taken four (P = 1) or two at a time with
+// independent loads, a step stopping early at the column's end or at the window's 64-entry
+// boundary; each output adds them in order, so the sums do not depend on where the steps
+// stop.  A nonzero costs three lane reads (row, value), one scalar multiply and one vector
+// add before its load, with no branch: the kernel is bound by its instruction issue about as
+// much as by its loads.  U rows come from L2, and V goes out with non-temporal stores so it
+// does not evict them.
 template <typename TV, typename TO, typename TU, int P>
 __device__ void backproject_cols(const int32_t *__restrict__ colptr_, const int32_t *__restrict__ rowidx_,
                                  const TV *__restrict__ vals_, int64_t N, int32_t k, const TU *__restrict__ U_,
@@ -171,7 +175,6 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr_, const int3
     const auto colptr = gmem(colptr_);
     const auto rowidx = gmem(rowidx_);
     const auto vals = gmem(vals_);
-    const auto U = gmem(U_);
     const auto sigma = gmem(sigma_);
     const auto V = gmem(V_);
     constexpr int kNz = P == 1 ? 4 : 2;
@@ -207,16 +210,24 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr_, const int3
         };
         fill(w, r_lo, v_lo);
         fill(w + 64, r_hi, v_hi);
-        // entry e (w <= e < w + 128): its U row and value
-        auto take = [&](int32_t e, __attribute__((address_space(1))) const TU *&Um, double &a) {
+        // entry e (w <= e < w + 64): its value and its U row as a byte offset (M k sizeof(TU) <
+        // 2^32 for M <= 8192), so that a load is the 64-bit base in scalars plus a 32-bit offset
+        // in a vector register: one scalar multiply per nonzero
+        const auto Ub = reinterpret_cast<__attribute__((address_space(1))) const char *>(gmem(U_));
+        const uint32_t kb = (uint32_t)k * (uint32_t)sizeof(TU);
+        uint32_t ib[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) ib[p] = (uint32_t)i[p] * (uint32_t)sizeof(TU);
+        auto take = [&](int32_t e, uint32_t &off, double &a) {
             const int32_t q = e - w;
-            const int32_t m = q < 64 ? __builtin_amdgcn_readlane(r_lo, q) : __builtin_amdgcn_readlane(r_hi, q - 64);
-            a = q < 64 ? readlane_val(v_lo, q) : readlane_val(v_hi, q - 64);
-            Um = U + (int64_t)m * k;
+            off = (uint32_t)__builtin_amdgcn_readlane(r_lo, q) * kb;
+            a = readlane_val(v_lo, q);
+        };
+        auto urow = [&](uint32_t off, int p) {
+            return reinterpret_cast<__attribute__((address_space(1))) const TU *>(Ub + (off + ib[p]));
         };
         // the step's n <= kNz nonzeros: every U load issued before the first addition
-        auto add = [&](double *a0, double *a1, const double *av,
-                       __attribute__((address_space(1))) const TU *const *Um, int n) {
+        auto add = [&](double *a0, double *a1, const double *av, const uint32_t *off, int n) {
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 double ux[kNz], uy[kNz];
@@ -225,8 +236,9 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr_, const int3
                     for (int t = 0; t < kNz; ++t) {
                         ux[t] = uy[t] = 0.0;
                         if (t < n) {
-                            ux[t] = static_cast<double>(Um[t][i[p]]);
-                            uy[t] = static_cast<double>(Um[t][i[p] + 1]);
+                            const auto u = urow(off[t], p);
+                            ux[t] = static_cast<double>(u[0]);
+                            uy[t] = static_cast<double>(u[1]);
                         }
                     }
                     double x = a0[p], y = a1[p];
@@ -243,7 +255,7 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr_, const int3
 #pragma unroll
                     for (int t = 0; t < kNz; ++t) {
                         ux[t] = 0.0;
-                        if (t < n) ux[t] = static_cast<double>(Um[t][i[p]]);
+                        if (t < n) ux[t] = static_cast<double>(urow(off[t], p)[0]);
                     }
                     double x = a0[p];
 #pragma unroll
@@ -267,30 +279,34 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr_, const int3
                 double a0[P], a1[P];
 #pragma unroll
                 for (int p = 0; p < P; ++p) a0[p] = a1[p] = 0.0;
-                for (int32_t e = e0; e < e1; e += kNz) {
-                    // e < w + 64 on entry to every step (steps advance by kNz <= 64), so the
-                    // step's entries lie in the window
+                for (int32_t e = e0; e < e1;) {
+                    // every step ends at w + 64 at the latest, so e <= w + 64 here and one
+                    // slide brings e into the low half; a step then takes its entries from the
+                    // low half alone (lane q = e - w), which keeps the takes free of branches
                     if (e >= w + 64) {
                         w += 64;
                         r_lo = r_hi;
                         v_lo = v_hi;
                         fill(w + 64, r_hi, v_hi);
                     }
+                    const int32_t lim = e1 < w + 64 ? e1 : w + 64;
                     double av[kNz];
-                    __attribute__((address_space(1))) const TU *Um[kNz];
-                    if (e + kNz <= e1) {
+                    uint32_t off[kNz];
+                    if (e + kNz <= lim) {
 #pragma unroll
-                        for (int t = 0; t < kNz; ++t) take(e + t, Um[t], av[t]);
-                        add(a0, a1, av, Um, kNz);
+                        for (int t = 0; t < kNz; ++t) take(e + t, off[t], av[t]);
+                        add(a0, a1, av, off, kNz);
+                        e += kNz;
                     } else {
-                        const int n = e1 - e;
+                        const int n = lim - e;
 #pragma unroll
                         for (int t = 0; t < kNz; ++t) {
-                            Um[t] = U;
+                            off[t] = 0;
                             av[t] = 0.0;
-                            if (t < n) take(e + t, Um[t], av[t]);
+                            if (t < n) take(e + t, off[t], av[t]);
                         }
-                        add(a0, a1, av, Um, n);
+                        add(a0, a1, av, off, n);
+                        e = lim;
                     }
                 }
 #pragma unroll

@@ -54,7 +54,9 @@ def test_autotune_report_and_reuse(R):
     assert rep["bp_per_cu"] in (16, 32, 64, 128)
     assert rep["jacobi_schedule"] in (0, 1, 2, 3) and len(rep["eig_ms"]) == 4
     assert all(v > 0 for v in rep["bp_ms"].values()) and all(v > 0 for v in rep["eig_ms"].values())
-    assert min(rep["bp_ms"], key=rep["bp_ms"].get) == rep["bp_per_cu"]
+    # the report rounds the times to 0.1 us (ties on a small matrix); rounding keeps the order,
+    # so the chosen candidate's time is the smallest of the reported ones
+    assert rep["bp_ms"][rep["bp_per_cu"]] == min(rep["bp_ms"].values())
     out = R.svd(dA, k, 0.0, ctx=ctx, n_blocks=8)
     assert same(out, base)
     # the mixed path has no back-projection launch to time (V comes from the refinement)
