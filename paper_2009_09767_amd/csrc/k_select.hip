@@ -6,6 +6,8 @@
 // halves the exponent, so below sqrt(M' u_G) sigma_1 a singular value cannot be told
 // from zero).  Returned sigma_i for i >= r are exactly 0, and the back-projection
 // V = A^T U Sigma^{-1} (Sec. V) fills those columns with zeros instead of dividing.
+#include <type_traits>
+
 #include "batch.hpp"
 #include "common.hpp"
 #include "launch.hpp"
@@ -290,15 +292,12 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr_, const int3
                         fill(w + 64, r_hi, v_hi);
                     }
                     const int32_t lim = e1 < w + 64 ? e1 : w + 64;
-                    double av[kNz];
-                    uint32_t off[kNz];
-                    if (e + kNz <= lim) {
-#pragma unroll
-                        for (int t = 0; t < kNz; ++t) take(e + t, off[t], av[t]);
-                        add(a0, a1, av, off, kNz);
-                        e += kNz;
-                    } else {
-                        const int n = lim - e;
+                    // a step of n nonzeros, n a compile-time constant, so a short step is as
+                    // free of branches as a full one
+                    auto step = [&](auto nn) {
+                        constexpr int n = decltype(nn)::value;
+                        double av[kNz];
+                        uint32_t off[kNz];
 #pragma unroll
                         for (int t = 0; t < kNz; ++t) {
                             off[t] = 0;
@@ -306,6 +305,15 @@ __device__ void backproject_cols(const int32_t *__restrict__ colptr_, const int3
                             if (t < n) take(e + t, off[t], av[t]);
                         }
                         add(a0, a1, av, off, n);
+                    };
+                    if (e + kNz <= lim) {
+                        step(std::integral_constant<int, kNz>{});
+                        e += kNz;
+                    } else {
+                        const int n = lim - e;   // 1 <= n < kNz
+                        if (n == 1) step(std::integral_constant<int, 1>{});
+                        else if (kNz > 2 && n == 2) step(std::integral_constant<int, (kNz > 2 ? 2 : 1)>{});
+                        else if (kNz > 3) step(std::integral_constant<int, (kNz > 3 ? 3 : 1)>{});
                         e = lim;
                     }
                 }
