@@ -52,8 +52,8 @@ def parse():
 TRAFFIC = {
     ("k_backproject", "powerlaw_1m/fp64"): {"bytes": (13605.64 * 2.0 + 1048841.05) * 1024, "source": "k_select.hip",
                                            "source_sha256": "10ec62b8b56e6f7f358da962eb913eaae2dca55ea1235111e7c3b02a437fe775"},
-    ("k_backproject", "powerlaw_200m/fp64"): {"bytes": (1637024.31 * 2.0 + 13217307.81) * 1024, "source": "k_select.hip",
-                                             "source_sha256": "bbe1f92a509f24ebd64ce446ec944c0c0f29d1cb692094a71cc0242b0e9bead0"},
+    ("k_backproject", "powerlaw_200m/fp64"): {"bytes": (1648284.70 * 2.0 + 13206772.57) * 1024, "source": "k_select.hip",
+                                             "source_sha256": "ce2bdb50161630554942264f735b4105ce3290352cf07fc05f8a3241fbff21d8"},
     ("k_gram_rows", "powerlaw_200m/fp64"): {"bytes": (13301123.78 * 2.0 + 325176.79) * 1024, "source": "k_gram.hip",
                                            "source_sha256": "2291a50c0948b77d11de8872f7134d24b3bc7e68269df468f2c92c50e35853ff"},
 }
