@@ -165,7 +165,8 @@ def test_result_independent_of_workspace_contents(R, split):
 
 def test_split_with_long_light_columns(R, orc):
     """A few columns with an entry in every row (long columns of the light CSC, walked by many
-    rows at once): the split's result equals the oracle's."""
+    rows at once): the split's result equals the oracle's, V included on the long columns (400
+    entries each, whose back-projection steps cross its 64-entry window several times)."""
     rng = np.random.default_rng(106)
     M, N = 400, 1 << 14
     A0 = powerlaw(M, N, 300_000, 1.2, 107, np.float64, "normal")
@@ -183,3 +184,12 @@ def test_split_with_long_light_columns(R, orc):
     err = H.rel_sigma_err(got.sigma.cpu().numpy(), ref.sigma, ref.rank)
     scaled, _ = H.vector_errors(got.U.cpu().numpy()[:, :ref.rank], ref.U[:, :ref.rank], ref.sigma, ref.rank)
     assert err <= 1e-10 and scaled <= 1e-10
+    r = ref.rank
+    cols = np.concatenate([full, [0, 1, N - 1]])
+    Vs = got.V.cpu().numpy()[cols]
+    Vr = ref.V[cols]
+    sgn = np.sign(np.sum(Vs[:, :r] * Vr[:, :r], axis=0))
+    sgn[sgn == 0] = 1
+    vb = np.minimum(1.0, 1e-12 / H.relgaps(ref.sigma, r)) * 4 + 1e-13
+    verr = np.max(np.abs(Vs[:, :r] * sgn - Vr[:, :r]), axis=0)
+    assert np.all(verr <= vb * np.maximum(np.abs(ref.V[:, :r]).max(axis=0), 1e-300))
